@@ -1,0 +1,399 @@
+"""FP64 CPU oracle of shape-constrained gravitational registration.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library may import or call this
+module: only the tests, the smoke check and the bench's CPU-baseline leg do.
+It shares no code with the HIP path.
+
+It follows the paper (Agarwal & Bhowmick, "3D Point Cloud Registration with
+Shape Constraint", arXiv 1902.01061) step by step, in float64, literally
+updating the template point array as eq. (9) does, with these readings of
+passages the paper leaves open (each is repeated where it is used):
+
+* X is the reference (N points), Y the template (M points); the mass and
+  velocity "of X" in eq. (5.5) are the template's (Sec. III-B calls the
+  template X there).
+* n_ij = (y_i - x_j)/|y_i - x_j|, so -G n_ij pulls the template point toward
+  the reference point (eq. 5; attraction, Sec. II/III).
+* Distance law (eqs. 4, 11): h(d) n = d^(p-1) r with r = y_i - x_j, i.e.
+  |f| grows like d^p; p = 1 by default (larger p overshoots, as Sec. IV
+  warns: with p = 2 the update flips the template by 180 degrees once
+  G dt^2 nears 1).  Softening eps and the length scale L = sqrt(lambda_max
+  of the reference covariance) are added for dimensional consistency:
+  h = ((d^2 + eps^2)/L^2)^((p-1)/2); eps = 0 reproduces the paper exactly.
+* g(s) = s (Sec. IV, equal weightage) or g = (a_i/abar)(a_j/abar) s (eq. 10),
+  with abar the mean reference descriptor.
+* The similarity spread sigma defaults to the population std of the
+  reference descriptors (the paper gives no value, eq. 3).
+* Curvature (Sec. III-A): PCA surface variation lambda_0/(lambda_0 +
+  lambda_1 + lambda_2) of the k nearest neighbours, self included, ties in
+  float32 squared distance broken by index, covariance normalised by 1/k.
+* The force is normalised by Z = sum_j w_j and only G dt^2 is identifiable;
+  dt2 = 1/G1 by default, so G_t dt2 runs over [0.1, 1].
+* Per-point displacement delta_i = dt2 f_i (Newton, v = 0); the translation
+  is d = dt2 F / sum_i m_i with F = sum_i m_i f_i (eq. 5.5).
+* Kabsch (eq. 6): "after" is Y + delta; C = Y_D^T Y with both centred.
+* Scale (eq. 8): c = sqrt(lambda_max(Sigma_X) / lambda_max(Sigma_Y(t))),
+  covariances normalised by point count, V diag(c) V^T = c I.
+* Update (eq. 9): Y(t+1) = c (Y - ybar) R + ybar + d (row vectors).
+* G schedule (eq. 12): iteration t (0-based) uses
+  G_t = 0.1 G1 + 0.9 G1 / (1 + exp(-(t - 1 - E/2))).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+G1_DEFAULT = 10000.0
+
+
+# ------------------------------------------------------------------ params
+@dataclasses.dataclass
+class Params:
+    p: float = 1.0           # distance exponent, p >= 1 (eq. 11); 1 is the stable choice
+    g_mode: int = 0          # 0: g = s ; 1: g = (a_i/abar)(a_j/abar) s   (eq. 10)
+    k: int = 16
+    sigma: float = 0.0       # <= 0: population std of the reference descriptors
+    eps: float = 0.0         # softening (0 = the paper's law)
+    G1: float = G1_DEFAULT   # eq. 12
+    E: int = 100             # number of iterations
+    dt2: float = 0.0         # <= 0: 1 / G1
+
+
+# -------------------------------------------------------------- kNN (fp32)
+def sqdist32(P: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """Squared distances from float32 point q to rows of float32 P, each
+    operation rounded to float32 in the order ((dx*dx + dy*dy) + dz*dz).
+    The neighbour choice is an integer decision taken in float32; this
+    fixes the exact float32 arithmetic that decides it."""
+    P = P.astype(np.float32, copy=False)
+    q = np.asarray(q, dtype=np.float32)
+    d = P - q                                  # float32, exactly rounded
+    return (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+
+
+def knn_bruteforce(P: np.ndarray, k: int, queries=None) -> np.ndarray:
+    """Exact k nearest neighbours (self included) of each query row of P,
+    ordered by (float32 squared distance, index).  Returns int64 (nq, k)."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    n = P.shape[0]
+    if queries is None:
+        queries = np.arange(n)
+    out = np.empty((len(queries), k), dtype=np.int64)
+    idx = np.arange(n)
+    for r, i in enumerate(queries):
+        d = sqdist32(P, P[i])
+        order = np.lexsort((idx, d))          # primary d, ties by index
+        out[r] = order[:k]
+    return out
+
+
+def knn(P: np.ndarray, k: int, queries=None) -> np.ndarray:
+    """Same result as knn_bruteforce.  For large clouds a k-d tree (float64)
+    proposes k + 8 candidates which are then ranked by the float32 key; a
+    query whose float32 k-th distance is not clearly inside the candidate
+    radius is redone by brute force, so the result is always exact."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    n = P.shape[0]
+    if queries is None:
+        queries = np.arange(n)
+    queries = np.asarray(queries)
+    if n <= 4096 or k + 8 >= n:
+        return knn_bruteforce(P, k, queries)
+    from scipy.spatial import cKDTree
+
+    tree = cKDTree(P.astype(np.float64))
+    kk = k + 8
+    dd, cand = tree.query(P[queries].astype(np.float64), k=kk)
+    out = np.empty((len(queries), k), dtype=np.int64)
+    for r, i in enumerate(queries):
+        c = cand[r]
+        d32 = sqdist32(P[c], P[i])
+        order = np.lexsort((c, d32))
+        kth = float(d32[order[k - 1]])
+        # every point outside the candidate set lies at float64 distance
+        # >= dd[r, -1]; float32 rounding moves squared distances by far less
+        # than this margin unless the radii nearly coincide.
+        if kth * (1 + 1e-5) + 1e-30 < dd[r, -1] ** 2:
+            out[r] = c[order[:k]]
+        else:
+            out[r] = knn_bruteforce(P, k, [i])[0]
+    return out
+
+
+# -------------------------------------------------------------- descriptors
+def surface_variation(P: np.ndarray, nbr: np.ndarray) -> np.ndarray:
+    """Curvature a_i = lambda_0 / (lambda_0 + lambda_1 + lambda_2) of the
+    neighbourhood covariance (1/k, centred at the neighbourhood mean); 0
+    when the trace is 0.  Sec. III-A (curvature as the local shape)."""
+    Q = P.astype(np.float64)[nbr]                     # (n, k, 3)
+    Qc = Q - Q.mean(axis=1, keepdims=True)
+    C = np.einsum("nki,nkj->nij", Qc, Qc) / nbr.shape[1]
+    lam = np.linalg.eigvalsh(C)                       # ascending
+    tr = lam.sum(axis=1)
+    a = np.zeros(len(nbr))
+    nz = tr > 0
+    a[nz] = lam[nz, 0] / tr[nz]
+    return a
+
+
+def descriptors(P: np.ndarray, k: int, queries=None) -> np.ndarray:
+    """Curvature of every point (or of the ``queries`` rows) of cloud P."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    return surface_variation(P, knn(P, k, queries))
+
+
+def moments(P: np.ndarray):
+    """Centroid, 1/n covariance and its largest eigenvalue (Sec. III-B,
+    scale model)."""
+    Q = P.astype(np.float64)
+    c = Q.mean(axis=0)
+    Qc = Q - c
+    S = Qc.T @ Qc / len(Q)
+    return c, S, float(np.linalg.eigvalsh(S)[-1])
+
+
+# ------------------------------------------------------------ G schedule
+def G_schedule(t: int, E: int, G1: float = G1_DEFAULT) -> float:
+    """eq. 12, with iteration t (0-based) using G(t) = formula at t - 1."""
+    return 0.1 * G1 + 0.9 * G1 / (1.0 + math.exp(-((t - 1) - E / 2.0)))
+
+
+# ---------------------------------------------------------------- setup
+@dataclasses.dataclass
+class Setup:
+    X: np.ndarray          # (N,3) float64 reference
+    aX: np.ndarray         # (N,)
+    aY: np.ndarray         # (M,)
+    wX: np.ndarray         # (N,) reference masses
+    mY: np.ndarray         # (M,) template masses
+    lamX: float
+    L: float
+    abar: float
+    sigma: float
+    Z: float
+    prm: Params
+
+
+def make_setup(X, Y0, prm: Params, aX=None, aY=None, wX=None, mY=None) -> Setup:
+    X = np.asarray(X, dtype=np.float64)
+    if aX is None:
+        aX = descriptors(np.asarray(X, dtype=np.float32), prm.k)
+    if aY is None:
+        aY = descriptors(np.asarray(Y0, dtype=np.float32), prm.k)
+    N, M = len(X), len(Y0)
+    wX = np.ones(N) if wX is None else np.asarray(wX, dtype=np.float64)
+    mY = np.ones(M) if mY is None else np.asarray(mY, dtype=np.float64)
+    _, _, lamX = moments(X)
+    sigma = prm.sigma if prm.sigma > 0 else float(np.std(np.asarray(aX, dtype=np.float64)))
+    return Setup(X=X, aX=np.asarray(aX, np.float64), aY=np.asarray(aY, np.float64), wX=wX, mY=mY,
+                 lamX=lamX, L=math.sqrt(lamX), abar=float(np.mean(aX)), sigma=sigma,
+                 Z=float(wX.sum()), prm=prm)
+
+
+# ---------------------------------------------------------------- forces
+def pair_weights(Yi, aYi, S: Setup):
+    """Per-pair factors for a block of template points: r (b,N,3),
+    q = |r|^2 + eps^2 (b,N), and w_j g_ij h_ij (b,N).  eqs. 3, 5, 10, 11."""
+    prm = S.prm
+    r = Yi[:, None, :] - S.X[None, :, :]
+    q = np.einsum("bnk,bnk->bn", r, r) + prm.eps ** 2
+    s = np.exp(-((aYi[:, None] - S.aX[None, :]) ** 2) / S.sigma ** 2)        # eq. 3
+    if prm.g_mode == 1:                                                       # eq. 10
+        g = (aYi[:, None] / S.abar) * (S.aX[None, :] / S.abar) * s
+    else:
+        g = s
+    h = (q / S.L ** 2) ** ((prm.p - 1) / 2.0)                                 # eqs. 4, 11
+    return r, q, S.wX[None, :] * g * h
+
+
+def forces(Y: np.ndarray, S: Setup, G: float, rows=None, block: int = 256):
+    """f_i = -(G/Z) sum_j w_j g_ij h_ij (y_i - x_j)  (eq. 5) and the energy
+    U = (G/Z) sum_ij w_j g_ij L^(1-p) q^((p+1)/2)/(p+1), whose negative
+    gradient is f.  Returns (f (b,3), U)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    rows = np.arange(len(Y)) if rows is None else np.asarray(rows)
+    f = np.empty((len(rows), 3))
+    U = 0.0
+    p = S.prm.p
+    for b0 in range(0, len(rows), block):
+        rr = rows[b0:b0 + block]
+        r, q, c = pair_weights(Y[rr], S.aY[rr], S)
+        f[b0:b0 + block] = -(G / S.Z) * np.einsum("bn,bnk->bk", c, r)
+        U += (G / S.Z) * float(np.sum(c * q)) / (p + 1)
+    return f, U
+
+
+# ------------------------------------------------------------ rigid update
+def kabsch(Yc: np.ndarray, YD: np.ndarray):
+    """eq. 6: C = Y_D^T Y = U S V^T, d = sign det(V U^T), R = V diag(1,1,d) U^T.
+    A zero determinant counts as positive."""
+    C = YD.T @ Yc
+    U, _, Vt = np.linalg.svd(C)
+    V = Vt.T
+    d = 1.0 if np.linalg.det(V @ U.T) >= 0 else -1.0
+    return V @ np.diag([1.0, 1.0, d]) @ U.T, C
+
+
+@dataclasses.dataclass
+class StepOut:
+    Y: np.ndarray       # Y(t+1)
+    f: np.ndarray       # per-point force at Y(t)
+    F: np.ndarray       # sum_i m_i f_i
+    K: np.ndarray       # sum_i f_i (y_i - ybar)^T
+    U: float
+    G: float
+    R: np.ndarray       # Kabsch rotation (row convention)
+    c: float            # scale factor
+    d: np.ndarray       # translation
+    C: np.ndarray       # cross-covariance
+
+
+def step(Y: np.ndarray, S: Setup, t: int) -> StepOut:
+    """One iteration of Sec. III: forces (eq. 5), Newtonian translation
+    (eq. 5.5), Kabsch rotation (eq. 6), eigenvalue scale (eq. 8), update
+    (eq. 9), with G from eq. 12."""
+    prm = S.prm
+    G = G_schedule(t, prm.E, prm.G1)
+    dt2 = prm.dt2 if prm.dt2 > 0 else 1.0 / prm.G1
+    f, U = forces(Y, S, G)
+    delta = dt2 * f                                   # per-point displacement, v = 0
+    F = (S.mY[:, None] * f).sum(axis=0)
+    d = dt2 * F / S.mY.sum()                          # eq. 5.5
+    ybar = Y.mean(axis=0)
+    Yc = Y - ybar
+    YD = (Y + delta) - (Y + delta).mean(axis=0)
+    R, C = kabsch(Yc, YD)                             # eq. 6
+    lamY = float(np.linalg.eigvalsh(Yc.T @ Yc / len(Y))[-1])
+    c = math.sqrt(S.lamX / lamY)                      # eq. 8
+    Ynew = c * Yc @ R + ybar + d                      # eq. 9
+    K = f.T @ Yc                                      # sum_i f_i (y_i - ybar)^T
+    return StepOut(Y=Ynew, f=f, F=F, K=K, U=U, G=G, R=R, c=c, d=d, C=C)
+
+
+@dataclasses.dataclass
+class Pose:
+    """T(y) = s R y + t (column vectors)."""
+    s: float
+    R: np.ndarray
+    t: np.ndarray
+
+    @staticmethod
+    def identity():
+        return Pose(1.0, np.eye(3), np.zeros(3))
+
+    def apply(self, P):
+        return self.s * np.asarray(P, np.float64) @ self.R.T + self.t
+
+    def as_array(self):
+        return np.concatenate([[self.s], self.R.reshape(-1), self.t])
+
+
+def compose(pose: Pose, so: StepOut, ybar: np.ndarray) -> Pose:
+    """Fold one update y' = c R^T (y - ybar) + ybar + d into the pose."""
+    Rt = so.R.T
+    return Pose(so.c * pose.s, Rt @ pose.R, so.c * Rt @ (pose.t - ybar) + ybar + so.d)
+
+
+def register(Y0, S: Setup, E=None, pose0: Pose | None = None, t0: int = 0, keep=False):
+    """E iterations from Y0 (optionally pre-posed).  Returns the final pose
+    (mapping the input template onto the registered one), the final points,
+    and (if keep) the per-iteration StepOut list."""
+    E = S.prm.E if E is None else E
+    pose = Pose.identity() if pose0 is None else pose0
+    Y = pose.apply(Y0)
+    hist = []
+    for t in range(t0, t0 + E):
+        ybar = Y.mean(axis=0)
+        so = step(Y, S, t)
+        pose = compose(pose, so, ybar)
+        Y = so.Y
+        if keep:
+            hist.append(so)
+    return pose, Y, hist
+
+
+# ---------------------------------------------------------------- metrics
+def pose_rmse(pose: Pose, Y0, gt_s, gt_R, gt_t, corr=None) -> float:
+    """sqrt(mean |T_est(y) - T_gt^{-1}(y)|^2) over inlier template points."""
+    Y0 = np.asarray(Y0, np.float64)
+    if corr is not None:
+        Y0 = Y0[np.asarray(corr) >= 0]
+    inv = (Y0 - gt_t) @ gt_R / gt_s
+    return float(np.sqrt(np.mean(np.sum((pose.apply(Y0) - inv) ** 2, axis=1))))
+
+
+def residual_corr(pose: Pose, Y0, X, corr) -> float:
+    """sqrt(mean |T(y_i) - x_corr(i)|^2) over i with corr >= 0."""
+    corr = np.asarray(corr)
+    sel = corr >= 0
+    D = pose.apply(np.asarray(Y0, np.float64)[sel]) - np.asarray(X, np.float64)[corr[sel]]
+    return float(np.sqrt(np.mean(np.sum(D * D, axis=1))))
+
+
+def residual_nn(pose: Pose, Y0, X) -> float:
+    """One-sided nearest-neighbour RMSE, template -> reference, in float64."""
+    from scipy.spatial import cKDTree
+
+    d, _ = cKDTree(np.asarray(X, np.float64)).query(pose.apply(Y0))
+    return float(np.sqrt(np.mean(d * d)))
+
+
+def diameter(X) -> float:
+    """Bounding-box diagonal of a cloud."""
+    X = np.asarray(X, np.float64)
+    return float(np.linalg.norm(X.max(axis=0) - X.min(axis=0)))
+
+
+# ----------------------------------------------------- C loops (same maths)
+_LIB = None
+
+
+def _clib():
+    global _LIB
+    if _LIB is None:
+        import ctypes
+
+        from .build import build
+
+        _LIB = ctypes.CDLL(build(force=False))
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        _LIB.ora_forces.argtypes = [I64, I64, P, P, P, P, P, D, ctypes.c_int, D, D, D, D, D, D, P, P]
+        _LIB.ora_knn.argtypes = [I64, P, ctypes.c_int, I64, P, P]
+    return _LIB
+
+
+def _ptr(a):
+    import ctypes
+
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def forces_c(Y: np.ndarray, S: Setup, G: float, rows=None):
+    """forces() evaluated by the plain C loops (OpenMP); same definition."""
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    aY = np.ascontiguousarray(S.aY)
+    if rows is not None:
+        rows = np.asarray(rows)
+        Y = np.ascontiguousarray(Y[rows])
+        aY = np.ascontiguousarray(aY[rows])
+    X = np.ascontiguousarray(S.X)
+    f = np.empty((len(Y), 3))
+    U = np.zeros(1)
+    prm = S.prm
+    _clib().ora_forces(len(Y), len(X), _ptr(Y), _ptr(aY), _ptr(X), _ptr(np.ascontiguousarray(S.aX)),
+                       _ptr(np.ascontiguousarray(S.wX)), float(prm.p), int(prm.g_mode), S.sigma,
+                       float(prm.eps), S.L, S.abar, float(G), S.Z, _ptr(f), _ptr(U))
+    return f, float(U[0])
+
+
+def knn_c(P: np.ndarray, k: int, queries=None) -> np.ndarray:
+    """knn_bruteforce() evaluated by the plain C loops; same definition."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    q = np.arange(len(P), dtype=np.int64) if queries is None else np.ascontiguousarray(queries, dtype=np.int64)
+    out = np.empty((len(q), k), dtype=np.int64)
+    _clib().ora_knn(len(P), _ptr(P), int(k), len(q), _ptr(q), _ptr(out))
+    return out

@@ -1,0 +1,270 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by the
+mathematics (not by the oracle itself): a hand-worked force, closed forms,
+Newton's third law, the energy gradient, equivariance, descriptor
+invariance and closed-form descriptors, Kabsch special cases and an
+independent solver, scale idempotence, the G schedule, the fixed point and
+exact recovery."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ref as O
+from synth import config1, random_pair, rot_axis_angle
+from synth.clouds import ellipsoid_patch
+
+HERE = os.path.dirname(__file__)
+
+
+def _setup(X, aX, aY, p=1.0, g_mode=0, sigma=0.2, eps=0.0, L=None, wX=None, mY=None):
+    prm = O.Params(p=p, g_mode=g_mode, sigma=sigma, eps=eps)
+    S = O.make_setup(X, np.zeros((len(aY), 3)), prm, aX=aX, aY=aY, wX=wX, mY=mY)
+    if L is not None:
+        S.L = L
+    return S
+
+
+# ------------------------------------------------------------ eqs. 3, 5, 10, 11
+def test_hand_worked_force():
+    gold = json.load(open(os.path.join(HERE, "golden", "hand_force.json")))
+    X = np.array(gold["reference"])
+    Y = np.array(gold["template"])
+    for case in gold["cases"]:
+        S = _setup(X, np.array(gold["a_reference"]), np.array(gold["a_template"]), p=case["p"],
+                   g_mode=case["g_mode"], sigma=gold["sigma"], L=gold["L"])
+        for fn in (O.forces, O.forces_c):
+            f, U = fn(Y, S, gold["G"])
+            np.testing.assert_allclose(f[0], case["f"], rtol=1e-14, atol=1e-14)
+            assert U == pytest.approx(case["U"], rel=1e-14)
+
+
+def test_closed_form_uniform_similarity_p1():
+    """p = 1, s = 1 (sigma -> inf), unit masses: f_i = -G (y_i - xbar),
+    F = -G M (ybar - xbar), K = -G M Sigma_Y."""
+    pr = random_pair(40, 60, seed=3)
+    X, Y = pr.ref.astype(np.float64), pr.tmpl.astype(np.float64)
+    rng = np.random.default_rng(0)
+    S = _setup(X, rng.uniform(0, 0.3, 60), rng.uniform(0, 0.3, 40), p=1.0, sigma=1e30)
+    G = 7.5
+    f, _ = O.forces(Y, S, G)
+    np.testing.assert_allclose(f, -G * (Y - X.mean(axis=0)), rtol=1e-12, atol=1e-12)
+    so = O.step(Y, S, t=3)
+    Gt = so.G
+    M = len(Y)
+    np.testing.assert_allclose(so.F, -Gt * M * (Y.mean(0) - X.mean(0)), rtol=1e-11)
+    Yc = Y - Y.mean(0)
+    np.testing.assert_allclose(so.K, -Gt * Yc.T @ Yc, rtol=1e-11, atol=1e-9)
+
+
+@pytest.mark.parametrize("p", [1.0, 2.0, 3.0, 1.5])
+@pytest.mark.parametrize("g_mode", [0, 1])
+@pytest.mark.parametrize("eps", [0.0, 0.1])
+def test_newton_third_law_self_registration(p, g_mode, eps):
+    """Y = X with equal descriptors: the pair weights are symmetric and h r
+    antisymmetric, so F = 0 and K = K^T exactly."""
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(50, 3))
+    a = rng.uniform(0.0, 0.3, 50)
+    S = _setup(X, a, a, p=p, g_mode=g_mode, sigma=0.07, eps=eps, L=0.8)
+    f, _ = O.forces(X, S, 100.0)
+    scale = np.abs(f).sum()
+    F = f.sum(axis=0)
+    K = f.T @ (X - X.mean(0))
+    assert np.abs(F).max() <= 1e-13 * scale
+    assert np.abs(K - K.T).max() <= 1e-13 * scale * np.abs(X).max()
+
+
+def test_force_is_negative_energy_gradient():
+    pr = random_pair(6, 30, seed=5)
+    X = pr.ref.astype(np.float64)
+    Y = pr.tmpl.astype(np.float64)
+    rng = np.random.default_rng(1)
+    for p, g_mode in ((2.0, 0), (1.0, 1), (3.0, 0)):
+        S = _setup(X, rng.uniform(0.01, 0.3, 30), rng.uniform(0.01, 0.3, 6), p=p, g_mode=g_mode,
+                   sigma=0.1, eps=0.05, L=0.9)
+        f, _ = O.forces(Y, S, 3.0)
+        h = 1e-6
+        for i in range(6):
+            for c in range(3):
+                Yp, Ym = Y.copy(), Y.copy()
+                Yp[i, c] += h
+                Ym[i, c] -= h
+                dU = (O.forces(Yp, S, 3.0)[1] - O.forces(Ym, S, 3.0)[1]) / (2 * h)
+                assert -dU == pytest.approx(f[i, c], rel=1e-6, abs=1e-8)
+
+
+def test_force_equivariance():
+    pr = random_pair(20, 35, seed=8)
+    X = pr.ref.astype(np.float64)
+    Y = pr.tmpl.astype(np.float64)
+    rng = np.random.default_rng(2)
+    aX, aY = rng.uniform(0, 0.3, 35), rng.uniform(0, 0.3, 20)
+    S = _setup(X, aX, aY, p=2.0, sigma=0.1, eps=0.02, L=1.0)
+    f, U = O.forces(Y, S, 5.0)
+    t = np.array([3.0, -1.0, 2.5])
+    Q = rot_axis_angle([0.2, -0.5, 1.0], 73.0)
+    St = _setup(X + t, aX, aY, p=2.0, sigma=0.1, eps=0.02, L=1.0)
+    ft, Ut = O.forces(Y + t, St, 5.0)
+    np.testing.assert_allclose(ft, f, rtol=1e-10, atol=1e-10)
+    Sq = _setup(X @ Q.T, aX, aY, p=2.0, sigma=0.1, eps=0.02, L=1.0)
+    fq, Uq = O.forces(Y @ Q.T, Sq, 5.0)
+    np.testing.assert_allclose(fq, f @ Q.T, rtol=1e-10, atol=1e-10)
+    assert Ut == pytest.approx(U, rel=1e-12) and Uq == pytest.approx(U, rel=1e-12)
+
+
+# ------------------------------------------------------------ descriptors
+def test_knn_matches_bruteforce_and_c():
+    P = ellipsoid_patch(5000, 4).astype(np.float32)
+    q = np.arange(0, 5000, 7)
+    a = O.knn_bruteforce(P, 16, q)
+    b = O.knn(P, 16, q)
+    c = O.knn_c(P, 16, q)
+    assert (a == b).all() and (a == c).all()
+    assert (a[:, 0] == q).all()                      # self first (distance 0)
+
+
+def test_knn_tie_break_by_index():
+    # a square lattice: many exactly equal float32 distances
+    g = np.stack(np.meshgrid(np.arange(6), np.arange(6), [0.0]), -1).reshape(-1, 3).astype(np.float32)
+    nb = O.knn_bruteforce(g, 5)
+    # the centre-ish point 14 = (2,2): neighbours at distance 1 are 8, 13, 15, 20
+    i = 2 * 6 + 2
+    assert list(nb[i]) == [i, i - 6, i - 1, i + 1, i + 6]
+    assert (O.knn_c(g, 5) == nb).all()
+
+
+def test_descriptor_closed_form_box_corners():
+    """k = n = 8 box corners with half-sides (1, 2, 3): every neighbourhood
+    is the whole cloud, covariance diag(1, 4, 9), so a = 1/14."""
+    c = np.array([[x, y, z] for x in (-1, 1) for y in (-2, 2) for z in (-3, 3)], dtype=np.float32)
+    a = O.descriptors(c, 8)
+    np.testing.assert_allclose(a, 1.0 / 14.0, rtol=1e-14)
+
+
+def test_descriptor_plane_is_zero():
+    rng = np.random.default_rng(3)
+    P = np.stack([rng.uniform(-1, 1, 300), rng.uniform(-1, 1, 300), np.full(300, -0.4)], 1).astype(np.float32)
+    assert np.abs(O.descriptors(P, 16)).max() == 0.0
+
+
+def test_descriptor_invariance():
+    """a is invariant under rotation, translation and uniform scale; checked
+    where the float32 neighbour sets agree (they may differ at near-ties)."""
+    P = ellipsoid_patch(1500, 9).astype(np.float32)
+    Q = rot_axis_angle([1.0, 2.0, -0.5], 37.0)
+    P2 = (1.7 * P.astype(np.float64) @ Q.T + np.array([0.3, -2.0, 5.0])).astype(np.float32)
+    n1, n2 = O.knn(P, 16), O.knn(P2, 16)
+    same = np.array([set(a) == set(b) for a, b in zip(n1, n2)])
+    assert same.mean() > 0.95
+    a1 = O.surface_variation(P, n1)
+    a2 = O.surface_variation(P2, n2)
+    np.testing.assert_allclose(a1[same], a2[same], rtol=0, atol=2e-6)
+
+
+# ------------------------------------------------------------ Kabsch, scale
+def _horn_rotation(A, B):
+    """Rotation R (row convention) minimising |A R - B| by Horn's unit
+    quaternion method (an independent closed-form solver)."""
+    S = A.T @ B
+    Sxx, Sxy, Sxz = S[0]
+    Syx, Syy, Syz = S[1]
+    Szx, Szy, Szz = S[2]
+    N = np.array([
+        [Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx],
+        [Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz],
+        [Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy],
+        [Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz]])
+    w, v = np.linalg.eigh(N)
+    q = v[:, -1]
+    from synth.clouds import quat_to_R
+    return quat_to_R(q).T        # column rotation of B ~ R_col A -> row form R_col^T
+
+
+def test_kabsch_pure_rotation_and_spd():
+    rng = np.random.default_rng(4)
+    Y = rng.normal(size=(30, 3)) * [1.0, 0.5, 0.2]
+    Y -= Y.mean(0)
+    Q = rot_axis_angle([0.3, -1.0, 0.4], 63.0)       # column rotation
+    R, _ = O.kabsch(Y, Y @ Q.T)                      # Y_D = Y Q^T, rows rotated by Q
+    np.testing.assert_allclose(R, Q.T, atol=1e-12)  # Y R = Y_D
+    R2, _ = O.kabsch(Y, 0.5 * Y)                      # C symmetric positive definite
+    np.testing.assert_allclose(R2, np.eye(3), atol=1e-12)
+
+
+def test_kabsch_matches_horn():
+    rng = np.random.default_rng(6)
+    for _ in range(5):
+        A = rng.normal(size=(40, 3))
+        A -= A.mean(0)
+        B = A @ rot_axis_angle(rng.normal(size=3), rng.uniform(0, 170)) + 0.1 * rng.normal(size=(40, 3))
+        B -= B.mean(0)
+        R, _ = O.kabsch(A, B)
+        np.testing.assert_allclose(R, _horn_rotation(A, B), atol=1e-10)
+        assert np.linalg.det(R) == pytest.approx(1.0, abs=1e-12)
+
+
+def test_scale_is_idempotent():
+    pr = config1(n=400)
+    S = O.make_setup(pr.ref, pr.tmpl, O.Params(k=16, E=10))
+    so = O.step(pr.tmpl.astype(np.float64), S, 0)
+    assert so.c == pytest.approx(1 / 1.2, rel=2e-3)
+    assert O.moments(so.Y)[2] == pytest.approx(S.lamX, rel=1e-12)
+    so2 = O.step(so.Y, S, 1)
+    assert so2.c == pytest.approx(1.0, abs=1e-12)
+
+
+# ------------------------------------------------------------ eq. 12
+def test_G_schedule_closed_form():
+    G1, E = 10000.0, 100
+    assert O.G_schedule(0, E, G1) == pytest.approx(1000.0 + 9000.0 / (1 + math.exp(51)), rel=1e-15)
+    assert O.G_schedule(51, E, G1) == 5500.0
+    assert O.G_schedule(100, E, G1) == pytest.approx(10000.0, rel=1e-10)
+    g = [O.G_schedule(t, E, G1) for t in range(E)]
+    assert all(b >= a for a, b in zip(g, g[1:])) and g[60] > g[40]
+
+
+# ------------------------------------------------------------ whole iteration
+def test_true_alignment_is_fixed_point():
+    pr = config1(n=600, noise=0.0)
+    X = pr.ref
+    for p in (1.0, 2.0):
+        S = O.make_setup(X, X, O.Params(p=p, k=16, E=20))
+        so = O.step(X.astype(np.float64), S, 5)
+        np.testing.assert_allclose(so.Y, X.astype(np.float64), atol=1e-12)
+        np.testing.assert_allclose(so.R, np.eye(3), atol=1e-13)
+        assert so.c == pytest.approx(1.0, abs=1e-13)
+
+
+def test_exact_recovery_translation_scale_symmetric_cloud():
+    """Noise-free, centrally symmetric cloud, template = 1.3 x + t: the
+    torque vanishes by symmetry and the translation/scale are recovered."""
+    P = ellipsoid_patch(256, 77)
+    X = np.concatenate([P, -P]).astype(np.float32)
+    s, t = 1.3, np.array([0.4, -0.3, 0.2])
+    Y0 = (s * X.astype(np.float64) + t).astype(np.float32)
+    S = O.make_setup(X, Y0, O.Params(p=1.0, k=16, E=100))
+    S.aY = S.aX.copy()                              # pose-invariant descriptors
+    pose, Y, _ = O.register(Y0, S)
+    assert O.pose_rmse(pose, Y0, s, np.eye(3), t) <= 1e-9 * O.diameter(X)
+
+
+def test_pose_composition_matches_point_update():
+    pr = config1(n=300)
+    S = O.make_setup(pr.ref, pr.tmpl, O.Params(k=16, E=15))
+    pose, Y, _ = O.register(pr.tmpl, S)
+    np.testing.assert_allclose(pose.apply(pr.tmpl), Y, atol=1e-11)
+    assert np.allclose(pose.R @ pose.R.T, np.eye(3), atol=1e-12)
+
+
+def test_c_oracle_matches_numpy():
+    pr = random_pair(70, 90, seed=12)
+    rng = np.random.default_rng(9)
+    for p, g_mode, eps in ((1.0, 0, 0.0), (2.0, 1, 0.03), (3.0, 0, 0.0), (2.5, 0, 0.1)):
+        S = _setup(pr.ref.astype(np.float64), rng.uniform(0.01, 0.3, 90), rng.uniform(0.01, 0.3, 70),
+                   p=p, g_mode=g_mode, sigma=0.08, eps=eps, L=0.7, wX=rng.uniform(0.5, 2, 90))
+        f1, U1 = O.forces(pr.tmpl, S, 42.0)
+        f2, U2 = O.forces_c(pr.tmpl, S, 42.0)
+        np.testing.assert_allclose(f2, f1, rtol=1e-12, atol=1e-12 * np.abs(f1).max())
+        assert U2 == pytest.approx(U1, rel=1e-12)
