@@ -1,0 +1,171 @@
+/*
+ * sgreg — shape-constrained gravitational point-cloud registration on
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: Agarwal & Bhowmick, "3D Point Cloud Registration with Shape
+ * Constraint" (arXiv 1902.01061).  Given a template cloud Y (M points) and a
+ * reference cloud X (N points) with nothing but xyz coordinates (no colour,
+ * texture, correspondences or topology; Sec. I), find the translation,
+ * rotation and isotropic scale that align the template to the reference.
+ * Each template point is attracted by every reference point with a force
+ * weighted by the similarity of the two points' local curvature (eqs. 2-5,
+ * 10, 11); the net force and moment drive a Newtonian translation (eq. 5.5),
+ * a Kabsch rotation (eq. 6) and an eigenvalue-ratio scale (eq. 8), iterated
+ * with the G schedule of eq. (12).
+ *
+ * Conventions used by every call:
+ *  - All array pointers are DEVICE pointers on the context's GPU, owned by
+ *    the caller; the library never frees them and never keeps them past the
+ *    call (except inside a graph it captured for an identical later call).
+ *  - Clouds are structure-of-arrays float32 (x[n], y[n], z[n]); `m` is an
+ *    optional float32 mass per point (NULL = unit masses, Sec. IV).
+ *  - A pose maps template coordinates into the reference frame:
+ *    T(y) = s R y + t with R row-major (13 doubles: s, R[9], t[3]).
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the
+ *    default stream) unless stated otherwise.
+ *  - Return value: SGR_OK (0) or a negative error code; sgr_last_error()
+ *    gives a message for the calling thread.
+ *  - There is no CPU code path: every step runs in HIP kernels.
+ */
+#ifndef SGREG_H
+#define SGREG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SGR_OK 0
+#define SGR_EINVAL (-1)      /* bad argument: NULL pointer, n < k+1, sigma/eps/p out of range */
+#define SGR_EDEGENERATE (-2) /* a cloud with zero variance (no length scale / scale ratio) */
+#define SGR_EHIP (-3)        /* a HIP runtime call failed; message has hipGetErrorString */
+#define SGR_ENOMEM (-4)      /* workspace allocation failed */
+#define SGR_ENUMERIC (-5)    /* device status word: non-finite or rank-deficient update */
+
+typedef struct sgr_ctx sgr_ctx;
+typedef void* sgr_stream_t; /* hipStream_t */
+
+typedef struct {
+  const float* x;
+  const float* y;
+  const float* z;
+  const float* m; /* per-point mass or NULL (unit masses) */
+  int64_t n;
+} sgr_cloud;
+
+typedef struct {
+  double s;
+  double R[9];
+  double t[3];
+} sgr_pose;
+
+/* Parameters of the method.  Readings of passages the paper leaves open:
+ *  p      distance exponent of eq. (11), h(d) n = d^(p-1) r, p >= 1
+ *         (p < 1 only with eps > 0).  1 is the default: larger p overshoots
+ *         (Sec. IV warns of oscillation), p = 2 flips the template once
+ *         G dt2 nears 1.
+ *  g_mode 0: g = s (Sec. IV, equal weightage); 1: g = (a_i/abar)(a_j/abar) s
+ *         (eq. 10), abar = mean reference curvature.
+ *  k      neighbours (self included) for the curvature descriptor.
+ *  sigma  RBF spread of eq. (3); <= 0 selects the population std of the
+ *         reference curvatures.
+ *  eps    softening added to the distance law: h = ((d^2+eps^2)/L^2)^((p-1)/2),
+ *         L = sqrt(largest eigenvalue of the reference covariance); 0 is the
+ *         paper's law.
+ *  G1, E  eq. (12): iteration t (0-based) uses
+ *         G_t = 0.1 G1 + 0.9 G1 / (1 + exp(-(t - 1 - E/2))); E iterations.
+ *  dt2    the squared time step of eq. (5.5); only G dt2 matters; <= 0
+ *         selects 1/G1 so G_t dt2 runs over [0.1, 1].
+ *  The force is normalised by Z = sum of reference masses. */
+typedef struct {
+  double p;
+  int32_t g_mode;
+  int32_t k;
+  double sigma;
+  double eps;
+  double G1;
+  int32_t E;
+  int32_t flags; /* bit 0: disable graph capture in sgr_register */
+  double dt2;
+} sgr_params;
+
+/* Context on HIP device `device`: owns the workspace, captured graphs and the
+ * tile table.  The only memory the library allocates. */
+int sgr_create(sgr_ctx** ctx, int device);
+int sgr_destroy(sgr_ctx* ctx);
+const char* sgr_last_error(void);
+
+/* "descriptors(cloud)" (Sec. III-A, curvature; Sec. III-B, moments).
+ * a_out[n] (float32): PCA surface variation lambda_0/(lambda_0+lambda_1+lambda_2)
+ *   of the covariance (1/k, centred) of the k nearest neighbours, self
+ *   included; neighbours ranked by float32 squared distance
+ *   ((dx*dx + dy*dy) + dz*dz, each operation rounded) then by index.
+ * moments_out[10] (float64, nullable): centroid[3], covariance (1/n)
+ *   xx yy zz xy xz yz, largest eigenvalue.
+ * Errors: SGR_EINVAL if k < 1, k > 32 or n < k. */
+int sgr_descriptors(sgr_ctx* ctx, const sgr_cloud* c, int k, float* a_out, double* moments_out,
+                    sgr_stream_t stream);
+
+/* The k-nearest-neighbour lists behind sgr_descriptors: idx_out[n][k]
+ * (int32), row i sorted by (float32 squared distance, index). */
+int sgr_knn(sgr_ctx* ctx, const sgr_cloud* c, int k, int32_t* idx_out, sgr_stream_t stream);
+
+/* "step(template, reference, pose)": exactly one iteration t of Sec. III
+ * from pose `in`, writing `out` (device; may alias `in`).
+ * a_t[M], a_r[N]: curvatures (e.g. from sgr_descriptors); mom_t, mom_r: the
+ * moments_out of the INPUT template and of the reference.
+ * wrench_out[13] (nullable): F[3] = sum_i m_i f_i, K[9] = sum_i f_i
+ *   (y_i - ybar)^T row-major, U (energy whose negative gradient is f).
+ * f_out[M][3] (nullable, float32): per-point force f_i at pose `in`. */
+int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref,
+             const float* a_r, const double* mom_t, const double* mom_r, const sgr_params* prm,
+             int t, const sgr_pose* in, sgr_pose* out, double* wrench_out, float* f_out,
+             sgr_stream_t stream);
+
+/* "register(template, reference, params) -> pose": descriptors of both
+ * clouds, then E iterations from the pose in `inout` (device), written back
+ * in place.  stats (nullable, device float64 [E][32]): per iteration G_t,
+ * F[3], K[9], U, the pose after the update (13), the scale factor c and the
+ * status word.  Synchronises the stream at the end to read the device
+ * status word; SGR_ENUMERIC if an update went non-finite or rank deficient
+ * (the pose is then frozen at the last good value). */
+int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm,
+                 sgr_pose* inout, double* stats, sgr_stream_t stream);
+
+/* "residual": with corr (int32[M], -1 = none): sqrt(mean |T(y_i) - x_corr(i)|^2)
+ * over i with corr >= 0; with corr == NULL: one-sided nearest-neighbour RMSE
+ * template -> reference (nearest by float32 distance of the float32-rounded
+ * transformed point, the distance itself in float64).  rmse_out: device
+ * float64 [1]. */
+int sgr_residual(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_pose* pose,
+                 const int32_t* corr, double* rmse_out, sgr_stream_t stream);
+
+/* A prepared (template, reference) pair for repeated force evaluation:
+ * the per-registration constants (curvature statistics, length scale,
+ * masses) and the reference packed for the pair loop are computed once, on
+ * `stream`, into plan-owned device memory.  The cloud, curvature and moment
+ * arrays must stay valid and unchanged while the plan is used. */
+typedef struct sgr_plan sgr_plan;
+int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                    const double* mom_t, const double* mom_r, const sgr_params* prm, sgr_plan** plan,
+                    sgr_stream_t stream);
+int sgr_plan_destroy(sgr_plan* plan);
+
+/* The shape-weighted all-pairs force of eq. (5) (with eqs. 3, 10, 11) at
+ * pose `pose`, reduced to the wrench: wrench_out[13] = F[3], K[9], U as in
+ * sgr_step; f_out[M][3] the per-point forces.  G <= 0 takes G_t of eq. (12)
+ * at iteration t.  With both outputs NULL only the force kernel runs (its
+ * partial sums stay in plan memory); used for timing. */
+int sgr_plan_force(sgr_plan* plan, int t, double G, const sgr_pose* pose, double* wrench_out, float* f_out,
+                   sgr_stream_t stream);
+
+/* One iteration (as sgr_step) on a plan: pose_out may alias pose_in. */
+int sgr_plan_step(sgr_plan* plan, int t, const sgr_pose* pose_in, sgr_pose* pose_out, double* wrench_out,
+                  sgr_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGREG_H */

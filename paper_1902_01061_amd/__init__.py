@@ -1,0 +1,206 @@
+"""Shape-constrained gravitational point-cloud registration on MI355X.
+
+Thin Python binding over the C ABI of ``include/sgreg.h``: it only moves
+arguments (torch tensors for device memory, torch's current stream).  Every
+step of the computation runs in the HIP kernels of ``libsgreg.so``; there is
+no CPU fallback, and importing fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _ffi
+from ._ffi import SgrCloud, SgrError, SgrParams, check, lib
+
+__all__ = ["Params", "Cloud", "Context", "Plan", "SgrError", "pose_identity", "pose_to_srt", "pose_from_srt"]
+
+lib()  # fail at import when the native library is absent
+
+
+@dataclasses.dataclass
+class Params:
+    """Method parameters (see include/sgreg.h for the reading of each)."""
+    p: float = 1.0
+    g_mode: int = 0
+    k: int = 16
+    sigma: float = 0.0
+    eps: float = 0.0
+    G1: float = 10000.0
+    E: int = 100
+    flags: int = 0
+    dt2: float = 0.0
+
+    def c(self) -> SgrParams:
+        return SgrParams(float(self.p), int(self.g_mode), int(self.k), float(self.sigma), float(self.eps),
+                         float(self.G1), int(self.E), int(self.flags), float(self.dt2))
+
+
+def _dev(device) -> torch.device:
+    d = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    if d.type != "cuda":
+        raise ValueError("sgreg runs on a HIP device only")
+    if d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Cloud:
+    """A point cloud in device memory as structure-of-arrays float32
+    (``soa`` has shape (3, n)), with optional per-point masses."""
+
+    def __init__(self, points, masses=None, device=None):
+        dev = _dev(device)
+        p = torch.as_tensor(np.asarray(points) if not torch.is_tensor(points) else points)
+        if p.ndim != 2 or p.shape[1] != 3:
+            raise ValueError("points must have shape (n, 3)")
+        self.soa = p.to(device=dev, dtype=torch.float32).t().contiguous()
+        self.m = None
+        if masses is not None:
+            m = torch.as_tensor(masses).to(device=dev, dtype=torch.float32).contiguous()
+            if m.shape != (p.shape[0],):
+                raise ValueError("masses must have shape (n,)")
+            self.m = m
+        self.device = dev
+
+    @property
+    def n(self) -> int:
+        return int(self.soa.shape[1])
+
+    def c(self) -> SgrCloud:
+        s = self.soa
+        return SgrCloud(s[0].data_ptr(), s[1].data_ptr(), s[2].data_ptr(),
+                        self.m.data_ptr() if self.m is not None else None, self.n)
+
+
+def pose_identity(device=None) -> torch.Tensor:
+    p = torch.zeros(13, dtype=torch.float64, device=_dev(device))
+    p[0] = 1.0
+    p[1] = p[5] = p[9] = 1.0
+    return p
+
+
+def pose_from_srt(s, R, t, device=None) -> torch.Tensor:
+    v = np.concatenate([[float(s)], np.asarray(R, np.float64).reshape(-1), np.asarray(t, np.float64).reshape(-1)])
+    return torch.tensor(v, dtype=torch.float64, device=_dev(device))
+
+
+def pose_to_srt(pose: torch.Tensor):
+    v = pose.detach().double().cpu().numpy()
+    return float(v[0]), v[1:10].reshape(3, 3), v[10:13].copy()
+
+
+class Context:
+    """A library context on one HIP device (owns workspace, graphs, tiles)."""
+
+    def __init__(self, device=0):
+        self.device = _dev(device)
+        h = ctypes.c_void_p()
+        check(lib().sgr_create(ctypes.byref(h), self.device.index))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().sgr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- calls
+    def descriptors(self, cloud: Cloud, k: int):
+        a = torch.empty(cloud.n, dtype=torch.float32, device=self.device)
+        mom = torch.empty(10, dtype=torch.float64, device=self.device)
+        c = cloud.c()
+        check(lib().sgr_descriptors(self._h, ctypes.byref(c), int(k), _ptr(a), _ptr(mom), _stream(self.device)))
+        return a, mom
+
+    def knn(self, cloud: Cloud, k: int) -> torch.Tensor:
+        idx = torch.empty((cloud.n, k), dtype=torch.int32, device=self.device)
+        c = cloud.c()
+        check(lib().sgr_knn(self._h, ctypes.byref(c), int(k), _ptr(idx), _stream(self.device)))
+        return idx
+
+    def step(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params, t: int, pose_in,
+             pose_out=None, want_wrench=True, want_f=False):
+        pose_out = torch.empty(13, dtype=torch.float64, device=self.device) if pose_out is None else pose_out
+        wrench = torch.empty(13, dtype=torch.float64, device=self.device) if want_wrench else None
+        f = torch.empty((tmpl.n, 3), dtype=torch.float32, device=self.device) if want_f else None
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_step(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_t),
+                             _ptr(mom_r), ctypes.byref(pr), int(t), _ptr(pose_in), _ptr(pose_out), _ptr(wrench),
+                             _ptr(f), _stream(self.device)))
+        return pose_out, wrench, f
+
+    def register(self, tmpl: Cloud, ref: Cloud, params: Params, pose=None, stats=False):
+        pose = pose_identity(self.device) if pose is None else pose
+        st = torch.empty((params.E, 32), dtype=torch.float64, device=self.device) if stats else None
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_register(self._h, ctypes.byref(ct), ctypes.byref(cr), ctypes.byref(pr), _ptr(pose),
+                                 _ptr(st), _stream(self.device)))
+        return pose, st
+
+    def residual(self, tmpl: Cloud, ref: Cloud, pose, corr=None) -> torch.Tensor:
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        if corr is not None:
+            corr = torch.as_tensor(corr).to(device=self.device, dtype=torch.int32).contiguous()
+        ct, cr = tmpl.c(), ref.c()
+        check(lib().sgr_residual(self._h, ctypes.byref(ct), ctypes.byref(cr), _ptr(pose), _ptr(corr), _ptr(out),
+                                 _stream(self.device)))
+        return out
+
+
+class Plan:
+    """A prepared (template, reference) pair (sgr_plan_*): constants and the
+    packed reference are built once; force evaluations and steps reuse them.
+    Keeps references to every tensor the plan reads."""
+
+    def __init__(self, ctx: Context, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params):
+        self.ctx = ctx
+        self._keep = (tmpl, a_t, ref, a_r, mom_t, mom_r)
+        self.M, self.N = tmpl.n, ref.n
+        h = ctypes.c_void_p()
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_plan_create(ctx._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_t),
+                                    _ptr(mom_r), ctypes.byref(pr), ctypes.byref(h), _stream(ctx.device)))
+        self._h = h
+
+    def force(self, pose, t=0, G=0.0, want_wrench=True, want_f=False):
+        dev = self.ctx.device
+        wrench = torch.empty(13, dtype=torch.float64, device=dev) if want_wrench else None
+        f = torch.empty((self.M, 3), dtype=torch.float32, device=dev) if want_f else None
+        check(lib().sgr_plan_force(self._h, int(t), float(G), _ptr(pose), _ptr(wrench), _ptr(f), _stream(dev)))
+        return wrench, f
+
+    def step(self, pose_in, t, pose_out=None, want_wrench=False):
+        dev = self.ctx.device
+        pose_out = torch.empty(13, dtype=torch.float64, device=dev) if pose_out is None else pose_out
+        wrench = torch.empty(13, dtype=torch.float64, device=dev) if want_wrench else None
+        check(lib().sgr_plan_step(self._h, int(t), _ptr(pose_in), _ptr(pose_out), _ptr(wrench), _stream(dev)))
+        return pose_out, wrench
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sgr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,189 @@
+// Shared device helpers for the gfx950 kernels: FP64 3x3 linear algebra
+// (one-sided Jacobi SVD), wave/block FP64 reductions, the per-registration
+// constant block, and launch helpers.  Host-callable where marked so the
+// 3x3 routines can be unit-checked on the CPU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SGR_HD __host__ __device__ inline
+
+namespace sgr {
+
+// Per-registration constants, computed on the device once per call from the
+// clouds, their descriptors and the parameters (kept in device memory so a
+// captured graph can replay without host involvement).
+struct Derived {
+  double xbar[3];    // reference centroid
+  double lamX;       // largest eigenvalue of the reference covariance (1/N)
+  double L;          // sqrt(lamX): length scale of the distance law
+  double ybar0[3];   // centroid of the input template (unweighted)
+  double SigY0[6];   // template covariance (1/M): xx yy zz xy xz yz
+  double lamY0;      // its largest eigenvalue
+  double abar;       // mean reference curvature
+  double sigma;      // similarity spread actually used
+  double Z;          // sum of reference masses
+  double Mtot;       // sum of template masses
+  double Mcount;     // number of template points
+  double bscale;     // sqrt(log2 e) / sigma: a -> b so that s = exp2(-(b_i - b_j)^2)
+  double coefL;      // L^(1 - p)
+  double hp;         // (p - 1) / 2
+  double eps2;       // eps^2
+  double dt2;        // G dt^2 / G
+  double G1;
+  double E;
+  double p;
+  double g_mode;
+  double expand_ok;  // 1: the expanded similarity exponent 2 b_i b_j - b_j^2 + lw_j stays
+                     //    below 2^64 for every pair (b centred at the mean curvature)
+  int32_t status;    // 0 ok; bit flags set by the update kernel
+  int32_t pad;
+};
+
+enum : int32_t {
+  ST_NONFINITE = 1,   // non-finite wrench or cross-covariance
+  ST_SINGULAR = 2,    // cross-covariance of rank < 2
+  ST_SCALE = 4,       // pose scale outside [1e-6, 1e6]
+  ST_DEGENERATE = 8,  // a cloud with zero variance
+};
+
+// Row slot layout of the per-block wrench partials.
+constexpr int WR_F = 0;    // 3
+constexpr int WR_K = 3;    // 9, row-major K[a][b] = sum_i f_ia (y_i - ybar)_b
+constexpr int WR_U = 12;   // 1
+constexpr int WR_STRIDE = 16;
+
+// Per-iteration stats row written by the update kernel.
+constexpr int ST_G = 0, ST_F = 1, ST_K = 4, ST_U = 13, ST_POSE = 14, ST_C = 27, ST_STATUS = 28;
+constexpr int STATS_STRIDE = 32;
+
+// ------------------------------------------------------------- 3x3 FP64
+SGR_HD void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// One-sided (Hestenes) Jacobi SVD of a 3x3 matrix A (row-major):
+// A = U diag(sv) V^T with sv sorted descending.  U and V are returned
+// column-major in the sense u[k][*] = k-th left singular vector.  A column of
+// A that collapses to zero leaves its u[k] undefined (set to 0); callers
+// only use the vectors of non-zero singular values.
+SGR_HD void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3][3]) {
+  double a[3][3];  // a[col][row]
+  double vv[3][3]; // vv[col][row]
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r) {
+      a[c][r] = A_in[r * 3 + c];
+      vv[c][r] = (r == c) ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = (pq == 2) ? 1 : 0;
+      const int q = (pq == 0) ? 1 : 2;
+      double al = 0, be = 0, ga = 0;
+      for (int r = 0; r < 3; ++r) {
+        al += a[p][r] * a[p][r];
+        be += a[q][r] * a[q][r];
+        ga += a[p][r] * a[q][r];
+      }
+      if (ga == 0.0) continue;
+      const double rel = fabs(ga) / sqrt(al * be);
+      if (!(rel > 1e-17)) continue;
+      off = fmax(off, rel);
+      const double zeta = (be - al) / (2.0 * ga);
+      const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + t * t);
+      const double s = c * t;
+      for (int r = 0; r < 3; ++r) {
+        const double ap = a[p][r], aq = a[q][r];
+        a[p][r] = c * ap - s * aq;
+        a[q][r] = s * ap + c * aq;
+        const double vp = vv[p][r], vq = vv[q][r];
+        vv[p][r] = c * vp - s * vq;
+        vv[q][r] = s * vp + c * vq;
+      }
+    }
+    if (off < 1e-15) break;
+  }
+  double n[3];
+  for (int c = 0; c < 3; ++c) n[c] = sqrt(a[c][0] * a[c][0] + a[c][1] * a[c][1] + a[c][2] * a[c][2]);
+  int o[3] = {0, 1, 2};
+  // sort descending (3 elements)
+  if (n[o[0]] < n[o[1]]) { int t = o[0]; o[0] = o[1]; o[1] = t; }
+  if (n[o[1]] < n[o[2]]) { int t = o[1]; o[1] = o[2]; o[2] = t; }
+  if (n[o[0]] < n[o[1]]) { int t = o[0]; o[0] = o[1]; o[1] = t; }
+  for (int k = 0; k < 3; ++k) {
+    const int c = o[k];
+    sv[k] = n[c];
+    for (int r = 0; r < 3; ++r) {
+      u[k][r] = n[c] > 0 ? a[c][r] / n[c] : 0.0;
+      v[k][r] = vv[c][r];
+    }
+  }
+}
+
+// Eigenvalues of a symmetric positive semi-definite 3x3 matrix given as
+// (xx, yy, zz, xy, xz, yz): for such matrices the singular values are the
+// eigenvalues.  Returns them descending.
+SGR_HD void eig_psd3(const double S6[6], double lam[3]) {
+  const double A[9] = {S6[0], S6[3], S6[4], S6[3], S6[1], S6[5], S6[4], S6[5], S6[2]};
+  double u[3][3], v[3][3];
+  svd3(A, lam, u, v);
+}
+
+// Kabsch rotation of eq. (6): with C = U S V^T (paper's hats), R =
+// V diag(1, 1, sign det(V U^T)) U^T.  Written through the two leading
+// singular pairs: R = v1 u1^T + v2 u2^T + (v1 x v2)(u1 x u2)^T, which is
+// the same matrix and needs no sign bookkeeping.  Returns false if C has
+// rank < 2 (the rotation is then not determined).
+SGR_HD bool kabsch_rot(const double C[9], double R[9]) {
+  double sv[3], u[3][3], v[3][3];
+  svd3(C, sv, u, v);
+  if (!(sv[1] > 0.0) || !(sv[1] > sv[0] * 1e-14)) return false;
+  double u3[3], v3[3];
+  cross3(u[0], u[1], u3);
+  cross3(v[0], v[1], v3);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) R[r * 3 + c] = v[0][r] * u[0][c] + v[1][r] * u[1][c] + v3[r] * u3[c];
+  return true;
+}
+
+// ------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+__device__ inline float wave_sum_f(float x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// Sum NV doubles over a block of BT threads (BT a multiple of 64) in a fixed
+// order; the result is valid in thread 0.  `lds` needs NV * BT/64 doubles.
+template <int NV, int BT>
+__device__ inline void block_sum(double (&v)[NV], double* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[w * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int ww = 0; ww < BT / 64; ++ww) s += lds[ww * NV + k];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace sgr

@@ -1,0 +1,58 @@
+// Host-side launchers shared between the kernel translation units and the
+// C-ABI layer (internal; not part of the public interface).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace sgr {
+
+struct PrepParams {
+  double p;
+  double sigma;
+  double eps;
+  double G1;
+  double dt2;
+  int32_t E;
+  int32_t g_mode;
+};
+
+struct ForceArgs {
+  const float* y0x;
+  const float* y0y;
+  const float* y0z;
+  const float* aY;
+  const float* mY;      // template masses or nullptr
+  const float4* ref4;   // packed reference (x - xbar, b)
+  const float* reflw;   // log2 weights
+  const double* pose;   // 13 doubles
+  const Derived* dv;
+  int M, N;
+  int chunk_len;        // reference points per block (multiple of the LDS tile)
+  int n_chunks;
+  int t;                // iteration index (G from eq. 12 when G <= 0)
+  double G;             // explicit force constant, or <= 0
+  double* wpart;        // [n_blocks][WR_STRIDE]
+  double* fpart;        // [n_chunks][M][3] or nullptr
+};
+
+hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
+                           int32_t* idx_out, hipStream_t st);
+hipError_t launch_moments(const float* x, const float* y, const float* z, int64_t n, double* out, hipStream_t st);
+hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const float* aY, const float* mY, int64_t M,
+                          const double* mom_t, const double* mom_r, const PrepParams& P, Derived* out, hipStream_t st);
+hipError_t launch_pack_ref(const float* x, const float* y, const float* z, const float* aX, const float* wX, int64_t N,
+                           const Derived* dv, float4* ref4, float* lw, hipStream_t st);
+hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st);
+hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, float* f_out, hipStream_t st);
+int force_points_per_block(int R);
+int force_tile_j();
+hipError_t launch_update(const double* wpart, int nblk, const double* pose_in, double* pose_out, Derived* dv, int t,
+                         double G_fixed, int do_update, double* wrench_out, double* stats_row, hipStream_t st);
+hipError_t launch_residual(const float* yx, const float* yy, const float* yz, int M, const float* xx, const float* xy,
+                           const float* xz, int N, const double* pose, const int32_t* corr, double* part, int nblk,
+                           double* rmse_out, hipStream_t st);
+int residual_blocks(int M);
+
+}  // namespace sgr

@@ -1,0 +1,61 @@
+// Launch shape of the pair-force kernel: template points per lane (R),
+// template blocks, reference chunks.  A default heuristic fills the chip
+// (about 8 blocks of 4 waves per CU); the autotuner can override it per
+// (M, N, p-mode) bucket.
+#pragma once
+#include <stdint.h>
+
+#include <map>
+#include <tuple>
+
+namespace sgr {
+
+struct Tiles {
+  int R;
+  int n_iblk;
+  int n_chunks;
+  int chunk_len;
+  int nblk;
+};
+
+inline int log2_bucket(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << (b + 1)) <= n) ++b;
+  return b;
+}
+
+struct TileTable {
+  int n_cu = 256;
+  // (M bucket, N bucket, p mode) -> (R, blocks per CU target)
+  std::map<std::tuple<int, int, int>, std::pair<int, int>> over;
+
+  void init(int cus) { n_cu = cus; }
+
+  static Tiles make(int M, int N, int R, int target_blocks) {
+    const int bt = 256, tj = 256;
+    Tiles T;
+    T.R = R;
+    T.n_iblk = (M + bt * R - 1) / (bt * R);
+    int nc = (target_blocks + T.n_iblk - 1) / T.n_iblk;
+    const int max_nc = (N + tj - 1) / tj;
+    if (nc > max_nc) nc = max_nc;
+    if (nc < 1) nc = 1;
+    int cl = (N + nc - 1) / nc;
+    cl = ((cl + tj - 1) / tj) * tj;
+    T.chunk_len = cl;
+    T.n_chunks = (N + cl - 1) / cl;
+    T.nblk = T.n_iblk * T.n_chunks;
+    return T;
+  }
+
+  Tiles pick(int M, int N, int pm) const {
+    auto it = over.find(std::make_tuple(log2_bucket(M), log2_bucket(N), pm));
+    if (it != over.end()) return make(M, N, it->second.first, it->second.second * n_cu);
+    int R = 4;
+    if (M <= 256 * 4 * 16) R = 2;
+    if (M <= 256 * 2 * 4) R = 1;
+    return make(M, N, R, 8 * n_cu);
+  }
+};
+
+}  // namespace sgr

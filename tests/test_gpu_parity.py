@@ -1,0 +1,228 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle, through
+the C ABI.  Floating-point tolerances follow the one-step force bar
+(relative error 1e-4, F and K normalised by their absolute-sum scale) and
+the final-pose bar (pose RMSE between the two paths <= 1e-4 of the cloud
+diameter); neighbour indices are compared bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref as O
+from synth import config1, config2, random_pair, rot_axis_angle
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_01061_amd as sg
+    return sg
+
+
+@pytest.fixture(scope="module")
+def ctx(sg):
+    c = sg.Context(0)
+    yield c
+    c.close()
+
+
+def _mom(P):
+    c, S, lam = O.moments(P)
+    return np.array([c[0], c[1], c[2], S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2], lam])
+
+
+def _dt(x, dtype=torch.float32):
+    return torch.as_tensor(np.asarray(x)).to(device="cuda", dtype=dtype).contiguous()
+
+
+# ------------------------------------------------------------ descriptors
+@pytest.mark.parametrize("n,k", [(1000, 16), (3001, 24), (257, 8), (600, 32)])
+def test_knn_and_descriptors_match_oracle(sg, ctx, n, k):
+    pr = config1(n=n)
+    for P in (pr.ref, pr.tmpl):
+        cl = sg.Cloud(P)
+        idx = ctx.knn(cl, k).cpu().numpy()
+        ref_idx = O.knn(P, k)
+        assert (idx == ref_idx).all(), "neighbour lists differ"
+        a, mom = ctx.descriptors(cl, k)
+        a_ora = O.surface_variation(P, ref_idx)
+        np.testing.assert_allclose(a.cpu().numpy(), a_ora.astype(np.float32), rtol=2e-6, atol=1e-9)
+        np.testing.assert_allclose(mom.cpu().numpy(), _mom(P), rtol=1e-11, atol=1e-13)
+
+
+def test_descriptors_full_size_sampled(sg, ctx):
+    pr = config2()
+    cl = sg.Cloud(pr.ref)
+    idx = ctx.knn(cl, 24).cpu().numpy()
+    a, _ = ctx.descriptors(cl, 24)
+    q = np.random.default_rng(0).choice(pr.N, 200, replace=False)
+    ref_idx = O.knn_c(pr.ref, 24, q)
+    assert (idx[q] == ref_idx).all()
+    np.testing.assert_allclose(a.cpu().numpy()[q], O.surface_variation(pr.ref, ref_idx).astype(np.float32),
+                               rtol=2e-6, atol=1e-9)
+
+
+# ------------------------------------------------------------ one step
+def _one_step(sg, ctx, pr, prm, pose, t, aX32, aY32, wX=None, mY=None):
+    """Run one GPU step and the oracle step from the same state."""
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX32.astype(np.float64), aY=aY32.astype(np.float64), wX=wX, mY=mY)
+    Y = pose.apply(pr.tmpl)
+    so = O.step(Y, S, t)
+    ora_pose = O.compose(pose, so, Y.mean(axis=0))
+    tm = sg.Cloud(pr.tmpl, masses=mY)
+    rf = sg.Cloud(pr.ref, masses=wX)
+    gp = sg.Params(p=prm.p, g_mode=prm.g_mode, k=prm.k, sigma=prm.sigma, eps=prm.eps, E=prm.E)
+    pin = sg.pose_from_srt(pose.s, pose.R, pose.t)
+    pout, wr, f = ctx.step(tm, _dt(aY32), rf, _dt(aX32), _dt(_mom(pr.tmpl), torch.float64),
+                           _dt(_mom(pr.ref), torch.float64), gp, t, pin, want_wrench=True, want_f=True)
+    return so, ora_pose, pout.cpu().numpy(), wr.cpu().numpy(), f.cpu().numpy().astype(np.float64)
+
+
+def _check_wrench(so, wr, f, Y, mY=None):
+    m = np.ones(len(f)) if mY is None else np.asarray(mY, np.float64)
+    e_f = np.linalg.norm(f - so.f) / np.linalg.norm(so.f)
+    scaleF = np.sum(m * np.linalg.norm(so.f, axis=1))
+    e_F = np.linalg.norm(wr[0:3] - so.F) / scaleF
+    Yc = Y - Y.mean(axis=0)
+    scaleK = np.sum(np.linalg.norm(so.f, axis=1) * np.linalg.norm(Yc, axis=1))
+    e_K = np.linalg.norm(wr[3:12].reshape(3, 3) - so.K) / scaleK
+    e_U = abs(wr[12] - so.U) / abs(so.U)
+    assert e_f <= F_TOL and e_F <= F_TOL and e_K <= F_TOL and e_U <= F_TOL, (e_f, e_F, e_K, e_U)
+    return e_f, e_F, e_K
+
+
+@pytest.mark.parametrize("p,g_mode,eps,masses", [
+    (1.0, 0, 0.0, False), (2.0, 0, 0.0, False), (3.0, 1, 0.0, False), (1.5, 0, 0.05, True),
+    (2.0, 1, 0.02, True)])
+def test_step_matches_oracle(sg, ctx, p, g_mode, eps, masses):
+    pr = random_pair(1300, 2900, seed=21)          # several tiles, ragged tails
+    rng = np.random.default_rng(4)
+    aX32 = rng.uniform(0.0, 0.3, pr.N).astype(np.float32)
+    aY32 = rng.uniform(0.0, 0.3, pr.M).astype(np.float32)
+    wX = rng.uniform(0.5, 2.0, pr.N) if masses else None
+    mY = rng.uniform(0.5, 2.0, pr.M) if masses else None
+    wX32 = None if wX is None else wX.astype(np.float32)
+    mY32 = None if mY is None else mY.astype(np.float32)
+    prm = O.Params(p=p, g_mode=g_mode, k=16, eps=eps, E=40)
+    pose = O.Pose(1.1, rot_axis_angle([1, 2, 3], 20.0), np.array([0.1, -0.2, 0.05]))
+    for t in (0, 21, 39):
+        so, ora_pose, pout, wr, f = _one_step(sg, ctx, pr, prm, pose, t, aX32, aY32,
+                                              None if wX32 is None else wX32.astype(np.float64),
+                                              None if mY32 is None else mY32.astype(np.float64))
+        _check_wrench(so, wr, f, pose.apply(pr.tmpl), mY32)
+        D = O.diameter(pr.ref)
+        gp = O.Pose(pout[0], pout[1:10].reshape(3, 3), pout[10:13])
+        d = gp.apply(pr.tmpl) - ora_pose.apply(pr.tmpl)
+        assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * D
+
+
+def test_step_full_size_config2(sg, ctx):
+    """Bench-size one-step parity: f on sampled rows, F and K in full."""
+    pr = config2()
+    aX = O.descriptors(pr.ref, 24).astype(np.float32)
+    aY = O.descriptors(pr.tmpl, 24).astype(np.float32)
+    prm = O.Params(p=1.0, k=24, E=300)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64))
+    Y = pr.tmpl.astype(np.float64)
+    G = O.G_schedule(0, 300)
+    f_ora, U = O.forces_c(Y, S, G)
+    F = f_ora.sum(axis=0)
+    Yc = Y - Y.mean(axis=0)
+    K = f_ora.T @ Yc
+    gp = sg.Params(p=1.0, k=24, E=300)
+    pin = sg.pose_identity()
+    _, wr, f = ctx.step(sg.Cloud(pr.tmpl), _dt(aY), sg.Cloud(pr.ref), _dt(aX), _dt(_mom(pr.tmpl), torch.float64),
+                        _dt(_mom(pr.ref), torch.float64), gp, 0, pin, want_wrench=True, want_f=True)
+    wr = wr.cpu().numpy()
+    f = f.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(f - f_ora) / np.linalg.norm(f_ora) <= F_TOL
+    assert np.linalg.norm(wr[0:3] - F) / np.linalg.norm(f_ora, axis=1).sum() <= F_TOL
+    scaleK = np.sum(np.linalg.norm(f_ora, axis=1) * np.linalg.norm(Yc, axis=1))
+    assert np.linalg.norm(wr[3:12].reshape(3, 3) - K) / scaleK <= F_TOL
+    assert abs(wr[12] - U) / abs(U) <= F_TOL
+
+
+# ------------------------------------------------------------ registration
+def _register_both(sg, ctx, pr, prm):
+    S = O.make_setup(pr.ref, pr.tmpl, prm)
+    pose_o, _, _ = O.register(pr.tmpl, S)
+    gp = sg.Params(p=prm.p, g_mode=prm.g_mode, k=prm.k, sigma=prm.sigma, eps=prm.eps, E=prm.E)
+    pose_g, _ = ctx.register(sg.Cloud(pr.tmpl), sg.Cloud(pr.ref), gp)
+    s, R, t = sg.pose_to_srt(pose_g)
+    return pose_o, O.Pose(s, R, t)
+
+
+def test_register_config1_matches_oracle(sg, ctx):
+    pr = config1()
+    prm = O.Params(p=1.0, k=16, E=100)
+    po, pg = _register_both(sg, ctx, pr, prm)
+    D = O.diameter(pr.ref)
+    d = pg.apply(pr.tmpl) - po.apply(pr.tmpl)
+    assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * D
+    # and the registration itself improved the alignment
+    assert O.pose_rmse(pg, pr.tmpl, pr.gt_s, pr.gt_R, pr.gt_t) < 0.2 * O.pose_rmse(
+        O.Pose.identity(), pr.tmpl, pr.gt_s, pr.gt_R, pr.gt_t)
+
+
+def test_register_graph_replay_and_determinism(sg, ctx):
+    pr = config1(n=2000)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    outs = []
+    for flags in (0, 0, 1):
+        gp = sg.Params(p=1.0, k=16, E=30, flags=flags)
+        pose, st = ctx.register(tm, rf, gp, stats=True)
+        torch.cuda.synchronize()
+        outs.append((pose.cpu().numpy(), st.cpu().numpy()))
+    for p, s in outs[1:]:
+        assert np.array_equal(p, outs[0][0])
+        assert np.array_equal(s, outs[0][1])
+
+
+def test_register_stats_follow_oracle_iterates(sg, ctx):
+    pr = config1(n=900)
+    prm = O.Params(p=1.0, k=16, E=8)
+    S = O.make_setup(pr.ref, pr.tmpl, prm)
+    _, _, hist = O.register(pr.tmpl, S, keep=True)
+    gp = sg.Params(p=1.0, k=16, E=8)
+    _, st = ctx.register(sg.Cloud(pr.tmpl), sg.Cloud(pr.ref), gp, stats=True)
+    st = st.cpu().numpy()
+    for t, so in enumerate(hist):
+        assert st[t, 0] == pytest.approx(so.G, rel=1e-14)
+        scale = np.abs(so.f).sum()
+        assert np.linalg.norm(st[t, 1:4] - so.F) <= 1e-4 * scale
+
+
+# ------------------------------------------------------------ residual
+def test_residual_matches_oracle(sg, ctx):
+    pr = config1(n=1500)
+    pose = O.Pose(1 / 1.2, pr.gt_R.T, -(pr.gt_R.T @ pr.gt_t) / 1.2)
+    pt = sg.pose_from_srt(pose.s, pose.R, pose.t)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    r_corr = ctx.residual(tm, rf, pt, corr=pr.corr).item()
+    assert r_corr == pytest.approx(O.residual_corr(pose, pr.tmpl, pr.ref, pr.corr), rel=1e-12)
+    r_nn = ctx.residual(tm, rf, pt).item()
+    assert r_nn == pytest.approx(O.residual_nn(pose, pr.tmpl, pr.ref), rel=1e-6)
+
+
+# ------------------------------------------------------------ error paths
+def test_error_codes(sg, ctx):
+    pr = random_pair(10, 20, seed=1)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    with pytest.raises(sg.SgrError) as e:
+        ctx.descriptors(tm, 33)
+    assert e.value.code == -1
+    with pytest.raises(sg.SgrError) as e:
+        ctx.descriptors(tm, 11)
+    assert e.value.code == -1
+    with pytest.raises(sg.SgrError) as e:
+        ctx.register(tm, rf, sg.Params(p=0.5, eps=0.0, k=4, E=3))
+    assert e.value.code == -1
+    flat = np.zeros((40, 3), np.float32)
+    flat[:, 0] = np.arange(40)
+    with pytest.raises(sg.SgrError) as e:   # all curvatures 0: no similarity spread
+        ctx.register(sg.Cloud(flat), sg.Cloud(flat), sg.Params(k=4, E=3))
+    assert e.value.code == -2
