@@ -160,6 +160,34 @@ int sgr_plan_destroy(sgr_plan* plan);
 int sgr_plan_force(sgr_plan* plan, int t, double G, const sgr_pose* pose, double* wrench_out, float* f_out,
                    sgr_stream_t stream);
 
+/* Launch shape of the pair-force kernel for the size bucket of (M, N) and
+ * the distance-law mode of p (1, 3 or other): R template points per lane
+ * (1, 2, 4 or 8), a target of blocks_per_cu blocks of 256 threads per
+ * compute unit (the reference is split into chunks to reach it) and the
+ * variant (0: reference tiles staged in LDS; 1: read through scalar
+ * loads).  Affects plans and calls created afterwards.  R = 0 removes the
+ * entry. */
+int sgr_set_tiles(sgr_ctx* ctx, int64_t M, int64_t N, double p, int R, int blocks_per_cu, int variant);
+
+/* The force field at template positions `tmpl` (used as they are, identity
+ * pose): f_out[M][3] (float32) and wrench_out[13] (F, K, U as in sgr_step),
+ * with force constant G > 0.  mom_r: reference moments.  The forward pass
+ * of the differentiable force field. */
+int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                  const double* mom_r, const sgr_params* prm, double G, float* f_out, double* wrench_out,
+                  sgr_stream_t stream);
+
+/* Adjoint of sgr_force_fwd.  Inputs: f[M][3] from the forward pass, the
+ * upstream gradients grad_f[M][3] (float32, nullable = 0) and
+ * grad_wrench[12] (F then K row-major, float64, nullable = 0).  Outputs:
+ * grad_y[M][3] (float32) w.r.t. template positions, grad_m[M] (nullable)
+ * w.r.t. template masses, grad_se[2] (nullable, float64) w.r.t. the
+ * similarity spread sigma (which must be given, > 0) and the softening eps.
+ * The curvatures are held constant (they do not depend on the pose). */
+int sgr_force_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                  const double* mom_r, const sgr_params* prm, double G, const float* f, const float* grad_f,
+                  const double* grad_wrench, float* grad_y, float* grad_m, double* grad_se, sgr_stream_t stream);
+
 /* One iteration (as sgr_step) on a plan: pose_out may alias pose_in. */
 int sgr_plan_step(sgr_plan* plan, int t, const sgr_pose* pose_in, sgr_pose* pose_out, double* wrench_out,
                   sgr_stream_t stream);

@@ -16,7 +16,8 @@ import torch
 from . import _ffi
 from ._ffi import SgrCloud, SgrError, SgrParams, check, lib
 
-__all__ = ["Params", "Cloud", "Context", "Plan", "SgrError", "pose_identity", "pose_to_srt", "pose_from_srt"]
+__all__ = ["Params", "Cloud", "Context", "Plan", "ForceField", "SgrError", "pose_identity", "pose_to_srt",
+           "pose_from_srt"]
 
 lib()  # fail at import when the native library is absent
 
@@ -122,6 +123,9 @@ class Context:
         except Exception:
             pass
 
+    def set_tiles(self, M: int, N: int, p: float, R: int, blocks_per_cu: int, variant: int = 0):
+        check(lib().sgr_set_tiles(self._h, int(M), int(N), float(p), int(R), int(blocks_per_cu), int(variant)))
+
     # -------------------------------------------------------------- calls
     def descriptors(self, cloud: Cloud, k: int):
         a = torch.empty(cloud.n, dtype=torch.float32, device=self.device)
@@ -154,6 +158,27 @@ class Context:
         check(lib().sgr_register(self._h, ctypes.byref(ct), ctypes.byref(cr), ctypes.byref(pr), _ptr(pose),
                                  _ptr(st), _stream(self.device)))
         return pose, st
+
+    def force_fwd(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_r, params: Params, G: float):
+        f = torch.empty((tmpl.n, 3), dtype=torch.float32, device=self.device)
+        wrench = torch.empty(13, dtype=torch.float64, device=self.device)
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_force_fwd(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_r),
+                                  ctypes.byref(pr), float(G), _ptr(f), _ptr(wrench), _stream(self.device)))
+        return f, wrench
+
+    def force_bwd(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_r, params: Params, G: float, f, grad_f=None,
+                  grad_wrench=None, want_m=True, want_se=True):
+        gy = torch.empty((tmpl.n, 3), dtype=torch.float32, device=self.device)
+        gm = torch.empty(tmpl.n, dtype=torch.float32, device=self.device) if want_m else None
+        gse = torch.empty(2, dtype=torch.float64, device=self.device) if want_se else None
+        gf = None if grad_f is None else grad_f.to(torch.float32).contiguous()
+        gw = None if grad_wrench is None else grad_wrench.to(torch.float64).contiguous()
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_force_bwd(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_r),
+                                  ctypes.byref(pr), float(G), _ptr(f.contiguous()), _ptr(gf), _ptr(gw), _ptr(gy),
+                                  _ptr(gm), _ptr(gse), _stream(self.device)))
+        return gy, gm, gse
 
     def residual(self, tmpl: Cloud, ref: Cloud, pose, corr=None) -> torch.Tensor:
         out = torch.empty(1, dtype=torch.float64, device=self.device)
@@ -204,3 +229,28 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class ForceField(torch.autograd.Function):
+    """Differentiable shape-weighted force field (forward and adjoint are the
+    library's kernels).  apply(ctx, Y, m, sigma, eps, a_t, ref, a_r, mom_r,
+    params, G) -> (f [M, 3] float32, wrench [12] float64: F then K).
+    Gradients flow to Y (template positions), m (template masses), sigma
+    and eps (0-dim float64 tensors); the curvatures are constants."""
+
+    @staticmethod
+    def forward(fctx, sctx, Y, m, sigma, eps, a_t, ref, a_r, mom_r, params, G):
+        prm = dataclasses.replace(params, sigma=float(sigma), eps=float(eps))
+        tm = Cloud(Y.detach(), masses=None if m is None else m.detach(), device=sctx.device)
+        f, wrench = sctx.force_fwd(tm, a_t, ref, a_r, mom_r, prm, G)
+        fctx.save_for_backward(f)
+        fctx.stuff = (sctx, tm, a_t, ref, a_r, mom_r, prm, G, m is not None)
+        return f, wrench[:12]
+
+    @staticmethod
+    def backward(fctx, grad_f, grad_w):
+        (f,) = fctx.saved_tensors
+        sctx, tm, a_t, ref, a_r, mom_r, prm, G, has_m = fctx.stuff
+        gy, gm, gse = sctx.force_bwd(tm, a_t, ref, a_r, mom_r, prm, G, f, grad_f, grad_w, want_m=has_m,
+                                     want_se=True)
+        return (None, gy, gm if has_m else None, gse[0], gse[1], None, None, None, None, None, None)

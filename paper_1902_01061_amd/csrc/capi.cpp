@@ -107,6 +107,9 @@ PrepParams prep_of(const sgr_params* p) {
 
 int pmode_of(double p) { return p == 1.0 ? 1 : (p == 3.0 ? 3 : 0); }
 
+// The packed reference is padded to whole tiles with zero-weight points.
+size_t pad_n(int64_t N) { return (size_t)((N + 255) / 256) * 256; }
+
 }  // namespace
 
 extern "C" {
@@ -181,15 +184,15 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   const Tiles T = ctx->tiles.pick(M, N, pmode_of(prm->p));
   Carve cv{nullptr};
   cv.take<Derived>(1);
-  cv.take<float4>(N);
-  cv.take<float>(N);
+  cv.take<float4>(pad_n(N));
+  cv.take<float>(pad_n(N));
   cv.take<double>((size_t)T.nblk * WR_STRIDE);
   if (f_out) cv.take<double>((size_t)T.n_chunks * M * 3);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   Derived* dv = w.take<Derived>(1);
-  float4* ref4 = w.take<float4>(N);
-  float* lw = w.take<float>(N);
+  float4* ref4 = w.take<float4>(pad_n(N));
+  float* lw = w.take<float>(pad_n(N));
   double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
   double* fpart = f_out ? w.take<double>((size_t)T.n_chunks * M * 3) : nullptr;
 
@@ -197,7 +200,7 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
   ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, (const double*)in, dv, M, N,
               T.chunk_len, T.n_chunks, t, 0.0, wpart, fpart};
-  HIPCHK(launch_force(A, T.R, pmode_of(prm->p), wrench_out != nullptr, f_out != nullptr, st));
+  HIPCHK(launch_force(A, T.R, pmode_of(prm->p), wrench_out != nullptr, f_out != nullptr, st, T.sm));
   if (f_out) HIPCHK(launch_reduce_f(fpart, T.n_chunks, M, f_out, st));
   HIPCHK(launch_update(wpart, T.nblk, (const double*)in, (double*)out, dv, t, 0.0, 1, wrench_out, nullptr, st));
   return SGR_OK;
@@ -222,8 +225,8 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   cv.take<float>(M);
   cv.take<double>(20);
   cv.take<Derived>(1);
-  cv.take<float4>(N);
-  cv.take<float>(N);
+  cv.take<float4>(pad_n(N));
+  cv.take<float>(pad_n(N));
   cv.take<double>((size_t)T.nblk * WR_STRIDE);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
@@ -231,8 +234,8 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   float* aY = w.take<float>(M);
   double* mom = w.take<double>(20);
   Derived* dv = w.take<Derived>(1);
-  float4* ref4 = w.take<float4>(N);
-  float* lw = w.take<float>(N);
+  float4* ref4 = w.take<float4>(pad_n(N));
+  float* lw = w.take<float>(pad_n(N));
   double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
 
   HIPCHK(launch_knn_desc(ref->x, ref->y, ref->z, N, prm->k, aX, nullptr, st));
@@ -247,7 +250,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
       const bool wu = stats != nullptr || t == prm->E - 1;
       ForceArgs A{tmpl->x, tmpl->y, tmpl->z, aY, tmpl->m, ref4, lw, (const double*)inout, dv, M, N,
                   T.chunk_len, T.n_chunks, t, 0.0, wpart, nullptr};
-      HIPCHK(launch_force(A, T.R, pm, wu, false, s));
+      HIPCHK(launch_force(A, T.R, pm, wu, false, s, T.sm));
       HIPCHK(launch_update(wpart, T.nblk, (const double*)inout, (double*)inout, dv, t, 0.0, 1, nullptr,
                            stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
     }
@@ -326,6 +329,114 @@ int sgr_residual(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   return SGR_OK;
 }
 
+int sgr_set_tiles(sgr_ctx* ctx, int64_t M, int64_t N, double p, int R, int blocks_per_cu, int variant) {
+  if (!ctx) return fail(SGR_EINVAL, "NULL ctx");
+  if (M < 1 || N < 1) return fail(SGR_EINVAL, "bad sizes");
+  const auto key = std::make_tuple(log2_bucket(M), log2_bucket(N), pmode_of(p));
+  if (R == 0) {
+    ctx->tiles.over.erase(key);
+    return SGR_OK;
+  }
+  if (R != 1 && R != 2 && R != 4 && R != 8) return fail(SGR_EINVAL, "R must be 1, 2, 4 or 8");
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(SGR_EINVAL, "blocks_per_cu must be in [1, 64]");
+  if (variant != 0 && variant != 1) return fail(SGR_EINVAL, "variant must be 0 (LDS) or 1 (scalar loads)");
+  ctx->tiles.over[key] = std::make_tuple(R, blocks_per_cu, variant);
+  return SGR_OK;
+}
+
+int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                  const double* mom_r, const sgr_params* prm, double G, float* f_out, double* wrench_out,
+                  sgr_stream_t stream) {
+  if (!ctx || !a_t || !a_r || !mom_r) return fail(SGR_EINVAL, "NULL argument");
+  if (!f_out && !wrench_out) return fail(SGR_EINVAL, "nothing to compute");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (!(G > 0)) return fail(SGR_EINVAL, "G must be positive");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  const int pm = pmode_of(prm->p);
+  const Tiles T = ctx->tiles.pick(M, N, pm);
+  Carve cv{nullptr};
+  cv.take<double>(16);
+  cv.take<double>(16);
+  cv.take<Derived>(1);
+  cv.take<float4>(pad_n(N));
+  cv.take<float>(pad_n(N));
+  cv.take<double>((size_t)T.nblk * WR_STRIDE);
+  cv.take<double>((size_t)T.n_chunks * M * 3);
+  if (int e = ensure_ws(ctx, cv.off)) return e;
+  Carve w{ctx->ws};
+  double* mom_t = w.take<double>(16);
+  double* pose = w.take<double>(16);
+  Derived* dv = w.take<Derived>(1);
+  float4* ref4 = w.take<float4>(pad_n(N));
+  float* lw = w.take<float>(pad_n(N));
+  double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
+  double* fpart = w.take<double>((size_t)T.n_chunks * M * 3);
+  HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom_t, st));
+  HIPCHK(launch_identity_pose(pose, st));
+  HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
+  HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
+  ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, pose, dv, M, N,
+              T.chunk_len, T.n_chunks, 0, G, wpart, f_out ? fpart : nullptr};
+  HIPCHK(launch_force(A, T.R, pm, wrench_out != nullptr, f_out != nullptr, st, T.sm));
+  if (f_out) HIPCHK(launch_reduce_f(fpart, T.n_chunks, M, f_out, st));
+  if (wrench_out) HIPCHK(launch_update(wpart, T.nblk, pose, nullptr, dv, 0, G, 0, wrench_out, nullptr, st));
+  return SGR_OK;
+}
+
+int sgr_force_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                  const double* mom_r, const sgr_params* prm, double G, const float* f, const float* grad_f,
+                  const double* grad_wrench, float* grad_y, float* grad_m, double* grad_se, sgr_stream_t stream) {
+  if (!ctx || !a_t || !a_r || !mom_r || !f || !grad_y) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (!(G > 0)) return fail(SGR_EINVAL, "G must be positive");
+  if (grad_se && !(prm->sigma > 0)) return fail(SGR_EINVAL, "the sigma gradient needs an explicit sigma > 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  const int pm = pmode_of(prm->p);
+  Tiles T = ctx->tiles.pick(M, N, pm);
+  if (T.R > 4) T = TileTable::make(M, N, 4, 8 * ctx->n_cu);
+  Carve cv{nullptr};
+  cv.take<double>(16);
+  cv.take<double>(16);
+  cv.take<Derived>(1);
+  cv.take<float4>(pad_n(N));
+  cv.take<float>(pad_n(N));
+  cv.take<float>((size_t)M * 3);
+  cv.take<double>((size_t)T.n_chunks * M * 4);
+  cv.take<double>((size_t)T.nblk * 2);
+  cv.take<float>((size_t)M * 3);
+  cv.take<double>(16);
+  if (int e = ensure_ws(ctx, cv.off)) return e;
+  Carve w{ctx->ws};
+  double* mom_t = w.take<double>(16);
+  double* fsum = w.take<double>(16);
+  Derived* dv = w.take<Derived>(1);
+  float4* ref4 = w.take<float4>(pad_n(N));
+  float* lw = w.take<float>(pad_n(N));
+  float* lam = w.take<float>((size_t)M * 3);
+  double* ypart = w.take<double>((size_t)T.n_chunks * M * 4);
+  double* spart = w.take<double>((size_t)T.nblk * 2);
+  float* gf0 = w.take<float>((size_t)M * 3);
+  double* gw0 = w.take<double>(16);
+  if (!grad_f) HIPCHK(launch_fill_f(gf0, (int64_t)M * 3, 0.f, st));
+  if (!grad_wrench) HIPCHK(launch_fill(gw0, 16, 0.0, st));
+  HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom_t, st));
+  HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
+  HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
+  AdjArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, dv, M, N, T.chunk_len, T.n_chunks, T.nblk,
+            pm == 1, G, f, grad_f ? grad_f : gf0, grad_wrench ? grad_wrench : gw0, lam, ypart, spart,
+            grad_y, grad_m, grad_se};
+  HIPCHK(launch_adjoint(A, T.R, fsum, st));
+  return SGR_OK;
+}
+
 struct sgr_plan {
   sgr_ctx* ctx = nullptr;
   sgr_cloud tmpl{}, ref{};
@@ -360,8 +471,8 @@ int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const
   pl->T = ctx->tiles.pick(M, N, pl->pm);
   Carve cv{nullptr};
   cv.take<Derived>(1);
-  cv.take<float4>(N);
-  cv.take<float>(N);
+  cv.take<float4>(pad_n(N));
+  cv.take<float>(pad_n(N));
   cv.take<double>((size_t)pl->T.nblk * WR_STRIDE);
   cv.take<double>((size_t)pl->T.n_chunks * M * 3);
   if (hipMalloc(&pl->mem, cv.off) != hipSuccess) {
@@ -371,8 +482,8 @@ int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const
   }
   Carve w{pl->mem};
   pl->dv = w.take<Derived>(1);
-  pl->ref4 = w.take<float4>(N);
-  pl->lw = w.take<float>(N);
+  pl->ref4 = w.take<float4>(pad_n(N));
+  pl->lw = w.take<float>(pad_n(N));
   pl->wpart = w.take<double>((size_t)pl->T.nblk * WR_STRIDE);
   pl->fpart = w.take<double>((size_t)pl->T.n_chunks * M * 3);
   hipStream_t st = (hipStream_t)stream;
@@ -409,7 +520,7 @@ int sgr_plan_force(sgr_plan* pl, int t, double G, const sgr_pose* pose, double* 
   HIPCHK(hipSetDevice(pl->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ForceArgs A = plan_args(pl, t, G, pose, f_out != nullptr);
-  HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, f_out != nullptr, st));
+  HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, f_out != nullptr, st, pl->T.sm));
   if (f_out) HIPCHK(launch_reduce_f(pl->fpart, pl->T.n_chunks, (int)pl->tmpl.n, f_out, st));
   if (wrench_out)
     HIPCHK(launch_update(pl->wpart, pl->T.nblk, (const double*)pose, nullptr, pl->dv, t, G, 0, wrench_out, nullptr,
@@ -423,7 +534,7 @@ int sgr_plan_step(sgr_plan* pl, int t, const sgr_pose* pose_in, sgr_pose* pose_o
   HIPCHK(hipSetDevice(pl->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ForceArgs A = plan_args(pl, t, 0.0, pose_in, false);
-  HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, false, st));
+  HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, false, st, pl->T.sm));
   HIPCHK(launch_update(pl->wpart, pl->T.nblk, (const double*)pose_in, (double*)pose_out, pl->dv, t, 0.0, 1,
                        wrench_out, nullptr, st));
   return SGR_OK;

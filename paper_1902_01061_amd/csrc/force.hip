@@ -121,8 +121,14 @@ __global__ __launch_bounds__(256) void pack_ref_kernel(const float* __restrict__
                                                        const float* __restrict__ wX, int64_t N,
                                                        const Derived* __restrict__ dv, float4* __restrict__ ref4,
                                                        float* __restrict__ lw) {
+  // grid covers N rounded up to whole tiles of 256: the tail gets
+  // zero-weight padding (lw = -inf, so exp2 gives exactly 0)
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
+  if (j >= N) {
+    ref4[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+    lw[j] = -INFINITY;
+    return;
+  }
   const Derived& D = *dv;
   ref4[j] = make_float4((float)((double)X[j] - D.xbar[0]), (float)((double)Y[j] - D.xbar[1]),
                         (float)((double)Zc[j] - D.xbar[2]), (float)(((double)aX[j] - D.abar) * D.bscale));
@@ -145,10 +151,13 @@ __device__ inline float pair_coef(float rx, float ry, float rz, float db, float 
   }
 }
 
-template <int R, int PM, bool WU, bool WF>
+// SM = false: the reference tile is staged in LDS and read by broadcast.
+// SM = true: every lane of a wave reads the same reference point, so the
+// loads go through the scalar unit into SGPRs (no LDS, no barriers).
+template <int R, int PM, bool WU, bool WF, bool SM>
 __global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
-  __shared__ float4 s_ref[F_TJ];
-  __shared__ float s_lw[F_TJ];
+  __shared__ float4 s_ref[SM ? 1 : F_TJ];
+  __shared__ float s_lw[SM ? 1 : F_TJ];
   __shared__ double s_red[(F_BT / 64) * 13];
 
   const int n_iblk = (A.M + F_BT * R - 1) / (F_BT * R);
@@ -208,18 +217,24 @@ __global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
   const int j0 = chunk * A.chunk_len;
   const int j1 = min(A.N, j0 + A.chunk_len);
   for (int base = j0; base < j1; base += F_TJ) {
-    __syncthreads();
-    {
-      const int j = base + threadIdx.x;
-      if (j < j1) {
-        s_ref[threadIdx.x] = A.ref4[j];
-        s_lw[threadIdx.x] = A.reflw[j];
-      } else {  // padding: zero weight (exp2(-inf) = 0), finite coordinates
-        s_ref[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_lw[threadIdx.x] = -INFINITY;
+    // reference point jj of this tile (the packed arrays are padded to whole
+    // tiles with zero-weight points, so no bounds test is needed)
+    const float4* __restrict__ gref = A.ref4 + base;
+    const float* __restrict__ glw = A.reflw + base;
+    if constexpr (!SM) {
+      __syncthreads();
+      {
+        const int j = base + threadIdx.x;
+        if (j < j1) {
+          s_ref[threadIdx.x] = gref[threadIdx.x];
+          s_lw[threadIdx.x] = glw[threadIdx.x];
+        } else {  // beyond this chunk: zero weight (exp2(-inf) = 0), finite coordinates
+          s_ref[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+          s_lw[threadIdx.x] = -INFINITY;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
     if constexpr (MOM_CAPABLE) {
       if (mom) {
         float a0[R], ax[R], ay[R], az[R];
@@ -227,8 +242,8 @@ __global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
         for (int r = 0; r < R; ++r) a0[r] = ax[r] = ay[r] = az[r] = 0.f;
 #pragma unroll 2
         for (int jj = 0; jj < F_TJ; ++jj) {
-          const float4 X = s_ref[jj];
-          const float beta = __builtin_fmaf(-X.w, X.w, s_lw[jj]);
+          const float4 X = SM ? gref[jj] : s_ref[jj];
+          const float beta = __builtin_fmaf(-X.w, X.w, SM ? glw[jj] : s_lw[jj]);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const float c = __builtin_amdgcn_exp2f(__builtin_fmaf(al[r], X.w, beta));
@@ -253,8 +268,8 @@ __global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
     for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = au[r] = 0.f;
 #pragma unroll 2
     for (int jj = 0; jj < F_TJ; ++jj) {
-      const float4 X = s_ref[jj];
-      const float lw = s_lw[jj];
+      const float4 X = SM ? gref[jj] : s_ref[jj];
+      const float lw = SM ? glw[jj] : s_lw[jj];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const float rx = yx[r] - X.x, ry = yy[r] - X.y, rz = yz[r] - X.z;
@@ -355,39 +370,48 @@ hipError_t launch_pack_ref(const float* x, const float* y, const float* z, const
   return hipGetLastError();
 }
 
-template <int R, int PM>
-static void launch_force_rp(const ForceArgs& A, int nblk, bool wu, bool wf, hipStream_t st) {
+template <int R, int PM, bool SM>
+static void launch_force_rps(const ForceArgs& A, int nblk, bool wu, bool wf, hipStream_t st) {
   if (wu && wf)
-    hipLaunchKernelGGL((force_kernel<R, PM, true, true>), dim3(nblk), dim3(F_BT), 0, st, A);
+    hipLaunchKernelGGL((force_kernel<R, PM, true, true, SM>), dim3(nblk), dim3(F_BT), 0, st, A);
   else if (wu)
-    hipLaunchKernelGGL((force_kernel<R, PM, true, false>), dim3(nblk), dim3(F_BT), 0, st, A);
+    hipLaunchKernelGGL((force_kernel<R, PM, true, false, SM>), dim3(nblk), dim3(F_BT), 0, st, A);
   else if (wf)
-    hipLaunchKernelGGL((force_kernel<R, PM, false, true>), dim3(nblk), dim3(F_BT), 0, st, A);
+    hipLaunchKernelGGL((force_kernel<R, PM, false, true, SM>), dim3(nblk), dim3(F_BT), 0, st, A);
   else
-    hipLaunchKernelGGL((force_kernel<R, PM, false, false>), dim3(nblk), dim3(F_BT), 0, st, A);
+    hipLaunchKernelGGL((force_kernel<R, PM, false, false, SM>), dim3(nblk), dim3(F_BT), 0, st, A);
 }
 
 template <int R>
-static void launch_force_r(const ForceArgs& A, int pm, int nblk, bool wu, bool wf, hipStream_t st) {
-  if (pm == 1)
-    launch_force_rp<R, 1>(A, nblk, wu, wf, st);
-  else if (pm == 3)
-    launch_force_rp<R, 3>(A, nblk, wu, wf, st);
-  else
-    launch_force_rp<R, 0>(A, nblk, wu, wf, st);
+static void launch_force_r(const ForceArgs& A, int pm, bool sm, int nblk, bool wu, bool wf, hipStream_t st) {
+  if (sm) {
+    if (pm == 1)
+      launch_force_rps<R, 1, true>(A, nblk, wu, wf, st);
+    else if (pm == 3)
+      launch_force_rps<R, 3, true>(A, nblk, wu, wf, st);
+    else
+      launch_force_rps<R, 0, true>(A, nblk, wu, wf, st);
+  } else {
+    if (pm == 1)
+      launch_force_rps<R, 1, false>(A, nblk, wu, wf, st);
+    else if (pm == 3)
+      launch_force_rps<R, 3, false>(A, nblk, wu, wf, st);
+    else
+      launch_force_rps<R, 0, false>(A, nblk, wu, wf, st);
+  }
 }
 
 int force_points_per_block(int R) { return F_BT * R; }
 int force_tile_j() { return F_TJ; }
 
-hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st) {
+hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st, bool sm) {
   const int n_iblk = (A.M + F_BT * R - 1) / (F_BT * R);
   const int nblk = n_iblk * A.n_chunks;
   switch (R) {
-    case 1: launch_force_r<1>(A, pm, nblk, want_u, want_f, st); break;
-    case 2: launch_force_r<2>(A, pm, nblk, want_u, want_f, st); break;
-    case 4: launch_force_r<4>(A, pm, nblk, want_u, want_f, st); break;
-    case 8: launch_force_r<8>(A, pm, nblk, want_u, want_f, st); break;
+    case 1: launch_force_r<1>(A, pm, sm, nblk, want_u, want_f, st); break;
+    case 2: launch_force_r<2>(A, pm, sm, nblk, want_u, want_f, st); break;
+    case 4: launch_force_r<4>(A, pm, sm, nblk, want_u, want_f, st); break;
+    case 8: launch_force_r<8>(A, pm, sm, nblk, want_u, want_f, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -37,6 +37,35 @@ struct ForceArgs {
   double* fpart;        // [n_chunks][M][3] or nullptr
 };
 
+struct AdjArgs {
+  const float* y0x;
+  const float* y0y;
+  const float* y0z;
+  const float* aY;
+  const float* mY;
+  const float4* ref4;
+  const float* reflw;
+  const Derived* dv;
+  int M, N;
+  int chunk_len, n_chunks, nblk;
+  bool p1;              // p == 1: no distance-law derivative terms
+  double G;             // force constant
+  const float* f;       // forces of the forward pass [M][3]
+  const float* gf;      // upstream gradient of f [M][3]
+  const double* gw;     // upstream gradient of the wrench (F[3], K[9])
+  float* lam;           // [M][3] workspace
+  double* ypart;        // [n_chunks][M][4] workspace
+  double* spart;        // [nblk][2] workspace
+  float* grad_y;        // [M][3]
+  float* grad_m;        // [M] or nullptr
+  double* grad_se;      // [2] (sigma, eps) or nullptr
+};
+
+hipError_t launch_adjoint(const AdjArgs& A, int R, double* fsum_tmp, hipStream_t st);
+hipError_t launch_fill(double* p, int n, double v, hipStream_t st);
+hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_identity_pose(double* pose, hipStream_t st);
+
 hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, hipStream_t st);
 hipError_t launch_moments(const float* x, const float* y, const float* z, int64_t n, double* out, hipStream_t st);
@@ -44,7 +73,7 @@ hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const flo
                           const double* mom_t, const double* mom_r, const PrepParams& P, Derived* out, hipStream_t st);
 hipError_t launch_pack_ref(const float* x, const float* y, const float* z, const float* aX, const float* wX, int64_t N,
                            const Derived* dv, float4* ref4, float* lw, hipStream_t st);
-hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st);
+hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st, bool sm);
 hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, float* f_out, hipStream_t st);
 int force_points_per_block(int R);
 int force_tile_j();

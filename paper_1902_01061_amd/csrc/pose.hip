@@ -135,6 +135,36 @@ __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ 
   }
 }
 
+__global__ void fill_kernel(double* __restrict__ p, int n, double v) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void fill_f_kernel(float* __restrict__ p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void identity_pose_kernel(double* __restrict__ pose) {
+  const int e = threadIdx.x;
+  if (e < 13) pose[e] = (e == 0 || e == 1 || e == 5 || e == 9) ? 1.0 : 0.0;
+}
+
+hipError_t launch_fill(double* p, int n, double v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_f_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity_pose(double* pose, hipStream_t st) {
+  hipLaunchKernelGGL(identity_pose_kernel, dim3(1), dim3(64), 0, st, pose);
+  return hipGetLastError();
+}
+
 hipError_t launch_update(const double* wpart, int nblk, const double* pose_in, double* pose_out, Derived* dv, int t,
                          double G_fixed, int do_update, double* wrench_out, double* stats_row, hipStream_t st) {
   hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, st, wpart, nblk, pose_in, pose_out, dv, t, G_fixed,

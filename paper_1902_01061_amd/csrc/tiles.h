@@ -12,6 +12,7 @@ namespace sgr {
 
 struct Tiles {
   int R;
+  int sm;  // 1: reference read through scalar loads instead of LDS
   int n_iblk;
   int n_chunks;
   int chunk_len;
@@ -26,15 +27,16 @@ inline int log2_bucket(int64_t n) {
 
 struct TileTable {
   int n_cu = 256;
-  // (M bucket, N bucket, p mode) -> (R, blocks per CU target)
-  std::map<std::tuple<int, int, int>, std::pair<int, int>> over;
+  // (M bucket, N bucket, p mode) -> (R, blocks per CU target, variant)
+  std::map<std::tuple<int, int, int>, std::tuple<int, int, int>> over;
 
   void init(int cus) { n_cu = cus; }
 
-  static Tiles make(int M, int N, int R, int target_blocks) {
+  static Tiles make(int M, int N, int R, int target_blocks, int sm = 0) {
     const int bt = 256, tj = 256;
     Tiles T;
     T.R = R;
+    T.sm = sm;
     T.n_iblk = (M + bt * R - 1) / (bt * R);
     int nc = (target_blocks + T.n_iblk - 1) / T.n_iblk;
     const int max_nc = (N + tj - 1) / tj;
@@ -50,7 +52,8 @@ struct TileTable {
 
   Tiles pick(int M, int N, int pm) const {
     auto it = over.find(std::make_tuple(log2_bucket(M), log2_bucket(N), pm));
-    if (it != over.end()) return make(M, N, it->second.first, it->second.second * n_cu);
+    if (it != over.end())
+      return make(M, N, std::get<0>(it->second), std::get<1>(it->second) * n_cu, std::get<2>(it->second));
     int R = 4;
     if (M <= 256 * 4 * 16) R = 2;
     if (M <= 256 * 2 * 4) R = 1;
