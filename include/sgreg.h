@@ -188,6 +188,27 @@ int sgr_force_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
                   const double* mom_r, const sgr_params* prm, double G, const float* f, const float* grad_f,
                   const double* grad_wrench, float* grad_y, float* grad_m, double* grad_se, sgr_stream_t stream);
 
+/* B independent registrations of uneven sizes with shared parameters
+ * (tmpls, refs: HOST arrays of B cloud views).  Descriptors of all 2B
+ * clouds run in one launch; each iteration is one persistent launch over a
+ * work list of (registration, template block, reference chunk) items plus
+ * one update launch, captured in a HIP graph.  poses: device [B] (initial
+ * poses in, final out).  energy_out (device [B], nullable): final energy U
+ * of each.  stats (device [B][E][32], nullable) as in sgr_register.
+ * Synchronises the stream; SGR_ENUMERIC / SGR_EDEGENERATE if any
+ * registration failed (the others are still valid). */
+int sgr_register_batch(sgr_ctx* ctx, int B, const sgr_cloud* tmpls, const sgr_cloud* refs, const sgr_params* prm,
+                       sgr_pose* poses, double* energy_out, double* stats, sgr_stream_t stream);
+
+/* Multi-start registration of one pair: S starts, start s pre-rotates the
+ * template about its centroid by R0[s] (device float64 [S][9], row-major);
+ * all starts run as one batch sharing the descriptors and the packed
+ * reference.  poses (device [S]) receive the final poses, energy_out
+ * (device [S], nullable) the final energy U, best_out (device int32 [1],
+ * nullable) the start with the lowest energy (ties: lowest index). */
+int sgr_multistart(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm, int S,
+                   const double* R0, sgr_pose* poses, double* energy_out, int32_t* best_out, sgr_stream_t stream);
+
 /* One iteration (as sgr_step) on a plan: pose_out may alias pose_in. */
 int sgr_plan_step(sgr_plan* plan, int t, const sgr_pose* pose_in, sgr_pose* pose_out, double* wrench_out,
                   sgr_stream_t stream);

@@ -180,6 +180,35 @@ class Context:
                                   _ptr(gm), _ptr(gse), _stream(self.device)))
         return gy, gm, gse
 
+    def register_batch(self, tmpls, refs, params: Params, poses=None, want_energy=True, stats=False):
+        """B registrations in one batched call; returns (poses [B, 13], energy [B] or None, stats)."""
+        B = len(tmpls)
+        if len(refs) != B:
+            raise ValueError("tmpls and refs differ in length")
+        if poses is None:
+            poses = pose_identity(self.device).repeat(B, 1).contiguous()
+        energy = torch.empty(B, dtype=torch.float64, device=self.device) if want_energy else None
+        st = torch.empty((B, params.E, 32), dtype=torch.float64, device=self.device) if stats else None
+        ct = (SgrCloud * B)(*[c.c() for c in tmpls])
+        cr = (SgrCloud * B)(*[c.c() for c in refs])
+        pr = params.c()
+        check(lib().sgr_register_batch(self._h, B, ct, cr, ctypes.byref(pr), _ptr(poses), _ptr(energy), _ptr(st),
+                                       _stream(self.device)))
+        return poses, energy, st
+
+    def multistart(self, tmpl: Cloud, ref: Cloud, params: Params, R0):
+        """Multi-start registration; R0 (S, 3, 3) initial rotations about the
+        template centroid.  Returns (poses [S, 13], energy [S], best index)."""
+        R0 = torch.as_tensor(np.asarray(R0, np.float64)).reshape(-1, 9).to(self.device).contiguous()
+        S = int(R0.shape[0])
+        poses = torch.empty((S, 13), dtype=torch.float64, device=self.device)
+        energy = torch.empty(S, dtype=torch.float64, device=self.device)
+        best = torch.empty(1, dtype=torch.int32, device=self.device)
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_multistart(self._h, ctypes.byref(ct), ctypes.byref(cr), ctypes.byref(pr), S, _ptr(R0),
+                                   _ptr(poses), _ptr(energy), _ptr(best), _stream(self.device)))
+        return poses, energy, int(best.item())
+
     def residual(self, tmpl: Cloud, ref: Cloud, pose, corr=None) -> torch.Tensor:
         out = torch.empty(1, dtype=torch.float64, device=self.device)
         if corr is not None:

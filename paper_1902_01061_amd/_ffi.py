@@ -55,6 +55,8 @@ SIGNATURES = {
     "sgr_plan_step": [P, I, P, P, P, P],
     "sgr_set_tiles": [P, I64, I64, D, I, I, I],
     "sgr_force_fwd": [P, CP, P, CP, P, P, PP, D, P, P, P],
+    "sgr_register_batch": [P, I, CP, CP, PP, P, P, P, P],
+    "sgr_multistart": [P, CP, CP, PP, I, P, P, P, P, P],
     "sgr_force_bwd": [P, CP, P, CP, P, P, PP, D, P, P, P, P, P, P, P],
 }
 

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -40,7 +41,8 @@ struct sgr_ctx {
   hipStream_t cap = nullptr;
   char* ws = nullptr;
   size_t ws_size = 0;
-  GraphCache gc;
+  GraphCache gc;   // single registration
+  GraphCache gcb;  // batch / multi-start
   TileTable tiles;
 };
 
@@ -110,6 +112,211 @@ int pmode_of(double p) { return p == 1.0 ? 1 : (p == 3.0 ? 3 : 0); }
 // The packed reference is padded to whole tiles with zero-weight points.
 size_t pad_n(int64_t N) { return (size_t)((N + 255) / 256) * 256; }
 
+// Capture `loop` (which launches on the given stream) into the cache unless
+// the cached graph was made for the same key, then launch it on `st`.
+template <class F>
+int run_graph(sgr_ctx* ctx, GraphCache& gc, const std::vector<uint8_t>& key, F&& loop, hipStream_t st) {
+  if (!gc.exec || key != gc.key) {
+    if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+    if (gc.graph) (void)hipGraphDestroy(gc.graph);
+    gc.exec = nullptr;
+    gc.graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    int e = loop(ctx->cap);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(ctx->cap, &g);
+    if (e) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    if (ce != hipSuccess) return fail(SGR_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(SGR_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    gc.graph = g;
+    gc.exec = ex;
+    gc.key = key;
+  }
+  HIPCHK(hipGraphLaunch(gc.exec, st));
+  return SGR_OK;
+}
+
+template <class T>
+void key_add(std::vector<uint8_t>& k, const T* p, size_t n) {
+  const uint8_t* b = reinterpret_cast<const uint8_t*>(p);
+  k.insert(k.end(), b, b + n * sizeof(T));
+}
+
+// Batch of registrations sharing parameters: host tables, device copies,
+// descriptors, set-up, then E iterations of (persistent force, update).
+struct BatchIn {
+  int B;
+  std::vector<const sgr_cloud*> tm, rf;  // per registration
+  std::vector<int> tm_cloud, rf_cloud;   // index of each registration's clouds in `clouds`
+  std::vector<const sgr_cloud*> clouds;  // distinct clouds (descriptors computed once each)
+  std::vector<int> pack_of;              // registration whose reference packing it uses (itself, or shared)
+};
+
+int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* poses, const double* R0_multistart,
+              double* energy_out, double* stats, int32_t* best_out, hipStream_t st) {
+  const int B = in.B;
+  const int pm = pmode_of(prm->p);
+  const int ncl = (int)in.clouds.size();
+  // launch shape: R from the tile table at the median registration size
+  std::vector<int64_t> Ms(B), Ns(B);
+  for (int r = 0; r < B; ++r) {
+    Ms[r] = in.tm[r]->n;
+    Ns[r] = in.rf[r]->n;
+  }
+  std::vector<int64_t> sm = Ms, sn = Ns;
+  std::nth_element(sm.begin(), sm.begin() + B / 2, sm.end());
+  std::nth_element(sn.begin(), sn.begin() + B / 2, sn.end());
+  int R = ctx->tiles.pick((int)sm[B / 2], (int)sn[B / 2], pm).R;
+  if (R > 4) R = 4;
+  const int chunk_len = 2048;
+  const int ipb = 256 * R;
+
+  // host tables
+  std::vector<CloudDesc> cds(ncl);
+  std::vector<int64_t> a_off(ncl + 1, 0);
+  std::vector<int2> kblocks;
+  for (int c = 0; c < ncl; ++c) {
+    a_off[c + 1] = a_off[c] + (int64_t)pad_n(in.clouds[c]->n);
+    for (int b = 0; b < (int)((in.clouds[c]->n + 255) / 256); ++b) kblocks.push_back(make_int2(c, b));
+  }
+  std::vector<int64_t> ref_off(B, 0);
+  std::vector<int> blk2reg;
+  std::vector<int> blk0(B, 0);
+  int64_t ref_total = 0;
+  for (int r = 0; r < B; ++r) {
+    if (in.pack_of[r] != r) continue;
+    ref_off[r] = ref_total;
+    blk0[r] = (int)blk2reg.size();
+    const int nb = (int)((Ns[r] + 255) / 256);
+    for (int b = 0; b < nb; ++b) blk2reg.push_back(r);
+    ref_total += (int64_t)nb * 256;
+  }
+  for (int r = 0; r < B; ++r) ref_off[r] = ref_off[in.pack_of[r]];
+  std::vector<RegDesc> regs(B);
+  std::vector<int4> items;
+  int slot = 0;
+  for (int r = 0; r < B; ++r) {
+    const int nib = (int)((Ms[r] + ipb - 1) / ipb), nch = (int)((Ns[r] + chunk_len - 1) / chunk_len);
+    regs[r].wslot0 = slot;
+    regs[r].n_items = nib * nch;
+    for (int ib = 0; ib < nib; ++ib)
+      for (int ch = 0; ch < nch; ++ch) items.push_back(make_int4(r, ib, ch, slot + ib * nch + ch));
+    slot += nib * nch;
+  }
+  auto cost = [&](const int4& it) {
+    const int64_t mi = std::min<int64_t>(ipb, Ms[it.x] - (int64_t)it.y * ipb);
+    const int64_t nj = std::min<int64_t>(chunk_len, Ns[it.x] - (int64_t)it.z * chunk_len);
+    return mi * nj;
+  };
+  std::stable_sort(items.begin(), items.end(), [&](const int4& a, const int4& b) { return cost(a) > cost(b); });
+  const int n_items = (int)items.size();
+
+  // workspace
+  Carve cv{nullptr};
+  cv.take<CloudDesc>(ncl);
+  cv.take<int2>(kblocks.size());
+  cv.take<PrepDesc>(B);
+  cv.take<int>(blk2reg.size());
+  cv.take<RegDesc>(B);
+  cv.take<int4>(n_items);
+  cv.take<float>(a_off[ncl]);
+  cv.take<double>((size_t)ncl * 10);
+  cv.take<Derived>(B);
+  cv.take<float4>(ref_total);
+  cv.take<float>(ref_total);
+  cv.take<double>((size_t)n_items * WR_STRIDE);
+  cv.take<double>(B);
+  if (int e = ensure_ws(ctx, cv.off)) return e;
+  Carve w{ctx->ws};
+  CloudDesc* d_cds = w.take<CloudDesc>(ncl);
+  int2* d_kb = w.take<int2>(kblocks.size());
+  PrepDesc* d_prep = w.take<PrepDesc>(B);
+  int* d_b2r = w.take<int>(blk2reg.size());
+  RegDesc* d_regs = w.take<RegDesc>(B);
+  int4* d_items = w.take<int4>(n_items);
+  float* d_a = w.take<float>(a_off[ncl]);
+  double* d_mom = w.take<double>((size_t)ncl * 10);
+  Derived* d_dv = w.take<Derived>(B);
+  float4* d_ref4 = w.take<float4>(ref_total);
+  float* d_lw = w.take<float>(ref_total);
+  double* d_wpart = w.take<double>((size_t)n_items * WR_STRIDE);
+  double* d_energy = w.take<double>(B);
+
+  for (int c = 0; c < ncl; ++c)
+    cds[c] = CloudDesc{in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, d_a + a_off[c], (int)in.clouds[c]->n, 0};
+  std::vector<PrepDesc> preps(B);
+  for (int r = 0; r < B; ++r) {
+    const int ct = in.tm_cloud[r], cr = in.rf_cloud[r];
+    preps[r] = PrepDesc{in.rf[r]->x, in.rf[r]->y, in.rf[r]->z, d_a + a_off[cr], in.rf[r]->m, d_a + a_off[ct],
+                        in.tm[r]->m, d_mom + 10 * ct, d_mom + 10 * cr, ref_off[r], (int)Ns[r], (int)Ms[r], blk0[r], 0};
+    regs[r].y0x = in.tm[r]->x;
+    regs[r].y0y = in.tm[r]->y;
+    regs[r].y0z = in.tm[r]->z;
+    regs[r].aY = d_a + a_off[ct];
+    regs[r].mY = in.tm[r]->m;
+    regs[r].ref_off = ref_off[r];
+    regs[r].M = (int)Ms[r];
+    regs[r].N = (int)Ns[r];
+  }
+  HIPCHK(hipMemcpyAsync(d_cds, cds.data(), sizeof(CloudDesc) * ncl, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_kb, kblocks.data(), sizeof(int2) * kblocks.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_prep, preps.data(), sizeof(PrepDesc) * B, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_b2r, blk2reg.data(), sizeof(int) * blk2reg.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_regs, regs.data(), sizeof(RegDesc) * B, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_items, items.data(), sizeof(int4) * n_items, hipMemcpyHostToDevice, st));
+
+  HIPCHK(launch_knn_desc_batch(d_cds, d_kb, (int)kblocks.size(), prm->k, st));
+  HIPCHK(launch_moments_batch(d_cds, ncl, d_mom, st));
+  HIPCHK(launch_prepare_batch(d_prep, B, prep_of(prm), d_dv, st));
+  HIPCHK(launch_pack_batch(d_prep, d_b2r, (int)blk2reg.size(), d_dv, d_ref4, d_lw, st));
+  if (R0_multistart) HIPCHK(launch_init_multistart(R0_multistart, B, d_mom + 10 * in.tm_cloud[0], poses, st));
+
+  const int grid = std::min(n_items, 8 * ctx->n_cu);
+  auto loop = [&](hipStream_t s) -> int {
+    for (int t = 0; t < prm->E; ++t) {
+      const bool wu = stats != nullptr || t == prm->E - 1;
+      BatchArgs A{d_regs, d_items, n_items, d_ref4, d_lw, poses, d_dv, chunk_len, t, d_wpart};
+      HIPCHK(launch_force_batch(A, R, pm, wu, grid, s));
+      HIPCHK(launch_update_batch(d_wpart, d_regs, B, poses, d_dv, t, 1, t == prm->E - 1 ? d_energy : nullptr, stats,
+                                 prm->E, s));
+    }
+    return SGR_OK;
+  };
+  if ((prm->flags & 1) || prm->E < 2) {
+    if (int e = loop(st)) return e;
+  } else {
+    std::vector<uint8_t> key;
+    key_add(key, &B, 1);
+    key_add(key, prm, 1);
+    key_add(key, items.data(), items.size());
+    key_add(key, regs.data(), regs.size());
+    const void* ptrs[4] = {ctx->ws, poses, stats, R0_multistart};
+    key_add(key, ptrs, 4);
+    if (int e = run_graph(ctx, ctx->gcb, key, loop, st)) return e;
+  }
+  if (energy_out) HIPCHK(hipMemcpyAsync(energy_out, d_energy, sizeof(double) * B, hipMemcpyDeviceToDevice, st));
+  if (best_out) HIPCHK(launch_argmin(d_energy, B, best_out, st));
+  std::vector<Derived> dh(B);
+  HIPCHK(hipMemcpyAsync(dh.data(), d_dv, sizeof(Derived) * B, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int bad = 0, degen = 0;
+  for (int r = 0; r < B; ++r) {
+    bad += dh[r].status != 0;
+    degen += (dh[r].status & ST_DEGENERATE) != 0;
+  }
+  if (degen) return fail(SGR_EDEGENERATE, std::to_string(degen) + " registration(s) with degenerate input");
+  if (bad) return fail(SGR_ENUMERIC, std::to_string(bad) + " registration(s) hit a numeric failure");
+  return SGR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -139,8 +346,10 @@ int sgr_destroy(sgr_ctx* ctx) {
   if (!ctx) return SGR_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  if (ctx->gc.exec) (void)hipGraphExecDestroy(ctx->gc.exec);
-  if (ctx->gc.graph) (void)hipGraphDestroy(ctx->gc.graph);
+  for (GraphCache* g : {&ctx->gc, &ctx->gcb}) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+  }
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   delete ctx;
@@ -538,6 +747,55 @@ int sgr_plan_step(sgr_plan* pl, int t, const sgr_pose* pose_in, sgr_pose* pose_o
   HIPCHK(launch_update(pl->wpart, pl->T.nblk, (const double*)pose_in, (double*)pose_out, pl->dv, t, 0.0, 1,
                        wrench_out, nullptr, st));
   return SGR_OK;
+}
+
+int sgr_register_batch(sgr_ctx* ctx, int B, const sgr_cloud* tmpls, const sgr_cloud* refs, const sgr_params* prm,
+                       sgr_pose* poses, double* energy_out, double* stats, sgr_stream_t stream) {
+  if (!ctx || !tmpls || !refs || !poses) return fail(SGR_EINVAL, "NULL argument");
+  if (B < 1) return fail(SGR_EINVAL, "empty batch");
+  if (int e = check_params(prm)) return e;
+  if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
+  if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
+  BatchIn in;
+  in.B = B;
+  for (int r = 0; r < B; ++r) {
+    if (int e = check_cloud(&tmpls[r], "template")) return e;
+    if (int e = check_cloud(&refs[r], "reference")) return e;
+    if (tmpls[r].n < prm->k || refs[r].n < prm->k) return fail(SGR_EINVAL, "a cloud has fewer points than k");
+    in.tm.push_back(&tmpls[r]);
+    in.rf.push_back(&refs[r]);
+    in.tm_cloud.push_back((int)in.clouds.size());
+    in.clouds.push_back(&tmpls[r]);
+    in.rf_cloud.push_back((int)in.clouds.size());
+    in.clouds.push_back(&refs[r]);
+    in.pack_of.push_back(r);
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  return run_batch(ctx, in, prm, (double*)poses, nullptr, energy_out, stats, nullptr, (hipStream_t)stream);
+}
+
+int sgr_multistart(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm, int S,
+                   const double* R0, sgr_pose* poses, double* energy_out, int32_t* best_out, sgr_stream_t stream) {
+  if (!ctx || !R0 || !poses) return fail(SGR_EINVAL, "NULL argument");
+  if (S < 1) return fail(SGR_EINVAL, "no starts");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
+  if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
+  if (tmpl->n < prm->k || ref->n < prm->k) return fail(SGR_EINVAL, "a cloud has fewer points than k");
+  BatchIn in;
+  in.B = S;
+  in.clouds = {tmpl, ref};
+  for (int s = 0; s < S; ++s) {
+    in.tm.push_back(tmpl);
+    in.rf.push_back(ref);
+    in.tm_cloud.push_back(0);
+    in.rf_cloud.push_back(1);
+    in.pack_of.push_back(0);
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  return run_batch(ctx, in, prm, (double*)poses, R0, energy_out, nullptr, best_out, (hipStream_t)stream);
 }
 
 }  // extern "C"

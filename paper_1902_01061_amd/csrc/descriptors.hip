@@ -19,11 +19,10 @@ namespace sgr {
 constexpr int KNN_BT = 256;
 
 template <int KC>
-__global__ __launch_bounds__(KNN_BT) void knn_desc_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                          const float* __restrict__ Zc, int n, int k,
-                                                          float* __restrict__ a_out, int32_t* __restrict__ idx_out) {
-  __shared__ float4 tile[KNN_BT];
-  const int q = blockIdx.x * KNN_BT + threadIdx.x;
+__device__ inline void knn_desc_body(const float* __restrict__ X, const float* __restrict__ Y,
+                                     const float* __restrict__ Zc, int n, int k, float* __restrict__ a_out,
+                                     int32_t* __restrict__ idx_out, int qblock, float4* tile) {
+  const int q = qblock * KNN_BT + threadIdx.x;
   const bool valid = q < n;
   const float qx = valid ? X[q] : 0.f;
   const float qy = valid ? Y[q] : 0.f;
@@ -106,12 +105,30 @@ __global__ __launch_bounds__(KNN_BT) void knn_desc_kernel(const float* __restric
   if (a_out) a_out[q] = a;
 }
 
+template <int KC>
+__global__ __launch_bounds__(KNN_BT) void knn_desc_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                          const float* __restrict__ Zc, int n, int k,
+                                                          float* __restrict__ a_out, int32_t* __restrict__ idx_out) {
+  __shared__ float4 tile[KNN_BT];
+  knn_desc_body<KC>(X, Y, Zc, n, k, a_out, idx_out, blockIdx.x, tile);
+}
+
+// Many clouds in one launch: block b works on query block blocks[b].y of
+// cloud blocks[b].x.
+template <int KC>
+__global__ __launch_bounds__(KNN_BT) void knn_desc_batch_kernel(const CloudDesc* __restrict__ clouds,
+                                                                const int2* __restrict__ blocks, int k) {
+  __shared__ float4 tile[KNN_BT];
+  const int2 b = blocks[blockIdx.x];
+  const CloudDesc& c = clouds[b.x];
+  knn_desc_body<KC>(c.x, c.y, c.z, c.n, k, c.a_out, nullptr, b.y, tile);
+}
+
 // Centroid, covariance (1/n) and its largest eigenvalue; two passes over
 // the cloud in one block with a fixed-order FP64 reduction (deterministic).
-__global__ __launch_bounds__(1024) void moments_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                       const float* __restrict__ Zc, int64_t n, double* __restrict__ out) {
-  __shared__ double lds[16 * 6];
-  __shared__ double cen[3];
+__device__ inline void moments_body(const float* __restrict__ X, const float* __restrict__ Y,
+                                    const float* __restrict__ Zc, int64_t n, double* __restrict__ out, double* lds,
+                                    double* cen) {
   double s[3] = {0, 0, 0};
   for (int64_t i = threadIdx.x; i < n; i += 1024) {
     s[0] += X[i];
@@ -148,6 +165,22 @@ __global__ __launch_bounds__(1024) void moments_kernel(const float* __restrict__
   }
 }
 
+__global__ __launch_bounds__(1024) void moments_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                       const float* __restrict__ Zc, int64_t n, double* __restrict__ out) {
+  __shared__ double lds[16 * 6];
+  __shared__ double cen[3];
+  moments_body(X, Y, Zc, n, out, lds, cen);
+}
+
+// One block per cloud; cloud c writes out[10 c .. 10 c + 9].
+__global__ __launch_bounds__(1024) void moments_batch_kernel(const CloudDesc* __restrict__ clouds,
+                                                             double* __restrict__ out) {
+  __shared__ double lds[16 * 6];
+  __shared__ double cen[3];
+  const CloudDesc& c = clouds[blockIdx.x];
+  moments_body(c.x, c.y, c.z, c.n, out + 10 * (int64_t)blockIdx.x, lds, cen);
+}
+
 hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, hipStream_t st) {
   const dim3 grid((n + KNN_BT - 1) / KNN_BT), block(KNN_BT);
@@ -159,6 +192,24 @@ hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n
     hipLaunchKernelGGL(knn_desc_kernel<24>, grid, block, 0, st, x, y, z, n, k, a_out, idx_out);
   else
     hipLaunchKernelGGL(knn_desc_kernel<32>, grid, block, 0, st, x, y, z, n, k, a_out, idx_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_knn_desc_batch(const CloudDesc* clouds, const int2* blocks, int n_blocks, int k, hipStream_t st) {
+  const dim3 grid(n_blocks), block(KNN_BT);
+  if (k <= 8)
+    hipLaunchKernelGGL(knn_desc_batch_kernel<8>, grid, block, 0, st, clouds, blocks, k);
+  else if (k <= 16)
+    hipLaunchKernelGGL(knn_desc_batch_kernel<16>, grid, block, 0, st, clouds, blocks, k);
+  else if (k <= 24)
+    hipLaunchKernelGGL(knn_desc_batch_kernel<24>, grid, block, 0, st, clouds, blocks, k);
+  else
+    hipLaunchKernelGGL(knn_desc_batch_kernel<32>, grid, block, 0, st, clouds, blocks, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_batch(const CloudDesc* clouds, int n_clouds, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(moments_batch_kernel, dim3(n_clouds), dim3(1024), 0, st, clouds, out);
   return hipGetLastError();
 }
 

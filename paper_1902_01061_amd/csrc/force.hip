@@ -33,14 +33,12 @@ __device__ inline double G_at(const Derived& D, int t) {
 
 // Per-registration set-up: statistics of the reference curvatures, masses
 // and the constants of the force law.  One block, fixed-order reductions.
-__global__ __launch_bounds__(1024) void prepare_kernel(const float* __restrict__ aX, const float* __restrict__ wX,
-                                                       int64_t N, const float* __restrict__ aY,
-                                                       const float* __restrict__ mY, int64_t M,
-                                                       const double* __restrict__ mom_t, const double* __restrict__ mom_r,
-                                                       PrepParams P, Derived* __restrict__ out) {
-  __shared__ double lds[16 * 3];
-  __shared__ double red_max[16];
-  __shared__ double abar_s;
+__device__ inline void prepare_body(const float* __restrict__ aX, const float* __restrict__ wX, int64_t N,
+                                    const float* __restrict__ aY, const float* __restrict__ mY, int64_t M,
+                                    const double* __restrict__ mom_t, const double* __restrict__ mom_r,
+                                    const PrepParams& P, Derived* __restrict__ out, double* lds, double* red_max,
+                                    double* abar_p) {
+  double& abar_s = *abar_p;
   double s[3] = {0, 0, 0};
   for (int64_t j = threadIdx.x; j < N; j += 1024) {
     s[0] += (double)aX[j];
@@ -114,16 +112,33 @@ __global__ __launch_bounds__(1024) void prepare_kernel(const float* __restrict__
   *out = D;
 }
 
+__global__ __launch_bounds__(1024) void prepare_kernel(const float* __restrict__ aX, const float* __restrict__ wX,
+                                                       int64_t N, const float* __restrict__ aY,
+                                                       const float* __restrict__ mY, int64_t M,
+                                                       const double* __restrict__ mom_t, const double* __restrict__ mom_r,
+                                                       PrepParams P, Derived* __restrict__ out) {
+  __shared__ double lds[16 * 3];
+  __shared__ double red_max[16];
+  __shared__ double abar_s;
+  prepare_body(aX, wX, N, aY, mY, M, mom_t, mom_r, P, out, lds, red_max, &abar_s);
+}
+
+// One block per registration of a batch.
+__global__ __launch_bounds__(1024) void prepare_batch_kernel(const PrepDesc* __restrict__ d, PrepParams P,
+                                                             Derived* __restrict__ outs) {
+  __shared__ double lds[16 * 3];
+  __shared__ double red_max[16];
+  __shared__ double abar_s;
+  const PrepDesc& g = d[blockIdx.x];
+  prepare_body(g.aX, g.wX, g.N, g.aY, g.mY, g.M, g.mom_t, g.mom_r, P, outs + blockIdx.x, lds, red_max, &abar_s);
+}
+
 // Reference in the layout the pair loop reads: float4 (x - xbar, b) and
 // the log2 weight lw (reference mass and, for g = a a s, a_j / abar).
-__global__ __launch_bounds__(256) void pack_ref_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                       const float* __restrict__ Zc, const float* __restrict__ aX,
-                                                       const float* __restrict__ wX, int64_t N,
-                                                       const Derived* __restrict__ dv, float4* __restrict__ ref4,
-                                                       float* __restrict__ lw) {
-  // grid covers N rounded up to whole tiles of 256: the tail gets
-  // zero-weight padding (lw = -inf, so exp2 gives exactly 0)
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ inline void pack_ref_body(const float* __restrict__ X, const float* __restrict__ Y,
+                                     const float* __restrict__ Zc, const float* __restrict__ aX,
+                                     const float* __restrict__ wX, int64_t N, const Derived* __restrict__ dv,
+                                     float4* __restrict__ ref4, float* __restrict__ lw, int64_t j) {
   if (j >= N) {
     ref4[j] = make_float4(0.f, 0.f, 0.f, 0.f);
     lw[j] = -INFINITY;
@@ -135,6 +150,25 @@ __global__ __launch_bounds__(256) void pack_ref_kernel(const float* __restrict__
   double l = wX ? log2((double)wX[j]) : 0.0;
   if (D.g_mode == 1.0) l += log2((double)aX[j] / D.abar);
   lw[j] = (float)l;
+}
+
+// The grid covers N rounded up to whole tiles of 256: the tail gets
+// zero-weight padding (lw = -inf, so exp2 gives exactly 0).
+__global__ __launch_bounds__(256) void pack_ref_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                       const float* __restrict__ Zc, const float* __restrict__ aX,
+                                                       const float* __restrict__ wX, int64_t N,
+                                                       const Derived* __restrict__ dv, float4* __restrict__ ref4,
+                                                       float* __restrict__ lw) {
+  pack_ref_body(X, Y, Zc, aX, wX, N, dv, ref4, lw, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void pack_batch_kernel(const PrepDesc* __restrict__ d, const int* __restrict__ blk2reg,
+                                                         const Derived* __restrict__ dvs, float4* __restrict__ ref4,
+                                                         float* __restrict__ lw) {
+  const int r = blk2reg[blockIdx.x];
+  const PrepDesc& g = d[r];
+  pack_ref_body(g.xx, g.xy, g.xz, g.aX, g.wX, g.N, dvs + r, ref4 + g.ref_off, lw + g.ref_off,
+                (int64_t)(blockIdx.x - g.blk0) * 256 + threadIdx.x);
 }
 
 template <int PM>
@@ -154,15 +188,11 @@ __device__ inline float pair_coef(float rx, float ry, float rz, float db, float 
 // SM = false: the reference tile is staged in LDS and read by broadcast.
 // SM = true: every lane of a wave reads the same reference point, so the
 // loads go through the scalar unit into SGPRs (no LDS, no barriers).
+// One work item: template points [iblk*256*R, (iblk+1)*256*R) against the
+// reference chunk `chunk`; writes its 13 wrench partials to wpart[slot].
 template <int R, int PM, bool WU, bool WF, bool SM>
-__global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
-  __shared__ float4 s_ref[SM ? 1 : F_TJ];
-  __shared__ float s_lw[SM ? 1 : F_TJ];
-  __shared__ double s_red[(F_BT / 64) * 13];
-
-  const int n_iblk = (A.M + F_BT * R - 1) / (F_BT * R);
-  const int iblk = blockIdx.x % n_iblk;
-  const int chunk = blockIdx.x / n_iblk;
+__device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int slot, float4* s_ref, float* s_lw,
+                                   double* s_red) {
   const Derived& D = *A.dv;
 
   // pose: y - xbar = sR (y0 - ybar0) + (sR ybar0 + t - xbar)
@@ -341,9 +371,36 @@ __global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
   }
   block_sum<13, F_BT>(w, s_red);
   if (threadIdx.x == 0) {
-    double* o = A.wpart + (int64_t)blockIdx.x * WR_STRIDE;
+    double* o = A.wpart + (int64_t)slot * WR_STRIDE;
 #pragma unroll
     for (int e = 0; e < 13; ++e) o[e] = w[e];
+  }
+}
+
+template <int R, int PM, bool WU, bool WF, bool SM>
+__global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
+  __shared__ float4 s_ref[SM ? 1 : F_TJ];
+  __shared__ float s_lw[SM ? 1 : F_TJ];
+  __shared__ double s_red[(F_BT / 64) * 13];
+  const int n_iblk = (A.M + F_BT * R - 1) / (F_BT * R);
+  force_block<R, PM, WU, WF, SM>(A, blockIdx.x % n_iblk, blockIdx.x / n_iblk, blockIdx.x, s_ref, s_lw, s_red);
+}
+
+// Persistent form over a batch of registrations: the grid strides over a
+// work list of (registration, template block, reference chunk) items, sorted
+// by decreasing cost; each item writes the partial wrench to its own slot,
+// so the per-registration sums do not depend on the execution order.
+template <int R, int PM, bool WU>
+__global__ __launch_bounds__(F_BT) void force_batch_kernel(BatchArgs B) {
+  __shared__ float4 s_ref[F_TJ];
+  __shared__ float s_lw[F_TJ];
+  __shared__ double s_red[(F_BT / 64) * 13];
+  for (int it = blockIdx.x; it < B.n_items; it += gridDim.x) {
+    const int4 item = B.items[it];  // (registration, template block, chunk, output slot)
+    const RegDesc& g = B.regs[item.x];
+    ForceArgs A{g.y0x, g.y0y, g.y0z, g.aY, g.mY, B.ref4 + g.ref_off, B.reflw + g.ref_off,
+                B.poses + (int64_t)13 * item.x, B.dvs + item.x, g.M, g.N, B.chunk_len, 0, B.t, 0.0, B.wpart, nullptr};
+    force_block<R, PM, WU, false, false>(A, item.y, item.z, item.w, s_ref, s_lw, s_red);
   }
 }
 
@@ -360,6 +417,17 @@ __global__ __launch_bounds__(256) void reduce_f_kernel(const double* __restrict_
 hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const float* aY, const float* mY, int64_t M,
                           const double* mom_t, const double* mom_r, const PrepParams& P, Derived* out, hipStream_t st) {
   hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(1024), 0, st, aX, wX, N, aY, mY, M, mom_t, mom_r, P, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare_batch(const PrepDesc* d, int B, const PrepParams& P, Derived* outs, hipStream_t st) {
+  hipLaunchKernelGGL(prepare_batch_kernel, dim3(B), dim3(1024), 0, st, d, P, outs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_batch(const PrepDesc* d, const int* blk2reg, int n_blocks, const Derived* dvs, float4* ref4,
+                             float* lw, hipStream_t st) {
+  hipLaunchKernelGGL(pack_batch_kernel, dim3(n_blocks), dim3(256), 0, st, d, blk2reg, dvs, ref4, lw);
   return hipGetLastError();
 }
 
@@ -414,6 +482,32 @@ hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool wan
     case 8: launch_force_r<8>(A, pm, sm, nblk, want_u, want_f, st); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_force_batch(const BatchArgs& B, int R, int pm, bool want_u, int grid, hipStream_t st) {
+#define SGR_FB(RR, PP, UU) hipLaunchKernelGGL((force_batch_kernel<RR, PP, UU>), dim3(grid), dim3(F_BT), 0, st, B)
+#define SGR_FB_R(RR)                      \
+  do {                                     \
+    if (pm == 1) {                         \
+      if (want_u) SGR_FB(RR, 1, true);     \
+      else SGR_FB(RR, 1, false);           \
+    } else if (pm == 3) {                  \
+      if (want_u) SGR_FB(RR, 3, true);     \
+      else SGR_FB(RR, 3, false);           \
+    } else {                               \
+      if (want_u) SGR_FB(RR, 0, true);     \
+      else SGR_FB(RR, 0, false);           \
+    }                                      \
+  } while (0)
+  switch (R) {
+    case 1: SGR_FB_R(1); break;
+    case 2: SGR_FB_R(2); break;
+    case 4: SGR_FB_R(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SGR_FB_R
+#undef SGR_FB
   return hipGetLastError();
 }
 

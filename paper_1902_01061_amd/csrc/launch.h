@@ -37,6 +37,59 @@ struct ForceArgs {
   double* fpart;        // [n_chunks][M][3] or nullptr
 };
 
+// A cloud for the batched descriptor kernels.
+struct CloudDesc {
+  const float* x;
+  const float* y;
+  const float* z;
+  float* a_out;
+  int n;
+  int pad;
+};
+
+// One registration's inputs for the batched prepare / pack kernels.
+struct PrepDesc {
+  const float* xx;
+  const float* xy;
+  const float* xz;
+  const float* aX;
+  const float* wX;
+  const float* aY;
+  const float* mY;
+  const double* mom_t;
+  const double* mom_r;
+  int64_t ref_off;  // offset of the padded packed reference
+  int N, M;
+  int blk0;         // first pack block of this registration
+  int pad;
+};
+
+// One registration of a batch (device-resident table).
+struct RegDesc {
+  const float* y0x;
+  const float* y0y;
+  const float* y0z;
+  const float* aY;
+  const float* mY;
+  int64_t ref_off;      // offset of its packed reference in the batch arrays
+  int M, N;
+  int wslot0;           // first wrench slot of its items
+  int n_items;
+};
+
+struct BatchArgs {
+  const RegDesc* regs;
+  const int4* items;    // (registration, template block, chunk, wrench slot)
+  int n_items;
+  const float4* ref4;
+  const float* reflw;
+  const double* poses;  // [B][13]
+  const Derived* dvs;   // [B]
+  int chunk_len;
+  int t;
+  double* wpart;
+};
+
 struct AdjArgs {
   const float* y0x;
   const float* y0y;
@@ -74,6 +127,16 @@ hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const flo
 hipError_t launch_pack_ref(const float* x, const float* y, const float* z, const float* aX, const float* wX, int64_t N,
                            const Derived* dv, float4* ref4, float* lw, hipStream_t st);
 hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st, bool sm);
+hipError_t launch_knn_desc_batch(const CloudDesc* clouds, const int2* blocks, int n_blocks, int k, hipStream_t st);
+hipError_t launch_moments_batch(const CloudDesc* clouds, int n_clouds, double* out, hipStream_t st);
+hipError_t launch_prepare_batch(const PrepDesc* d, int B, const PrepParams& P, Derived* outs, hipStream_t st);
+hipError_t launch_pack_batch(const PrepDesc* d, const int* blk2reg, int n_blocks, const Derived* dvs, float4* ref4,
+                             float* lw, hipStream_t st);
+hipError_t launch_update_batch(const double* wpart, const RegDesc* regs, int B, double* poses, Derived* dvs, int t,
+                               int do_update, double* energy_out, double* stats, int E, hipStream_t st);
+hipError_t launch_init_multistart(const double* R0, int S, const double* mom_t, double* poses, hipStream_t st);
+hipError_t launch_argmin(const double* v, int n, int32_t* out, hipStream_t st);
+hipError_t launch_force_batch(const BatchArgs& B, int R, int pm, bool want_u, int grid, hipStream_t st);
 hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, float* f_out, hipStream_t st);
 int force_points_per_block(int R);
 int force_tile_j();

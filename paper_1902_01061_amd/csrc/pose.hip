@@ -18,31 +18,26 @@ __device__ inline double G_sched(const Derived& D, int t) {
   return 0.1 * D.G1 + 0.9 * D.G1 / (1.0 + exp(-(((double)t - 1.0) - 0.5 * D.E)));
 }
 
-__global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ wpart, int nblk,
-                                                     const double* __restrict__ pose_in, double* __restrict__ pose_out,
-                                                     Derived* __restrict__ dv, int t, double G_fixed, int do_update,
-                                                     double* __restrict__ wrench_out, double* __restrict__ stats_row) {
-  __shared__ double lds[4 * 13];
-  __shared__ double W[WR_STRIDE];
-  {
-    // thread b sums the partials of blocks b, b+256, ... (13 independent
-    // loads per block), then a fixed-order block sum: deterministic.
-    double v[13];
+// Sum of `n` wrench partial rows starting at `wpart` (fixed order); result in
+// W[0..12], valid for thread 0 only.
+__device__ inline void sum_partials(const double* __restrict__ wpart, int n, double* lds, double W[13]) {
+  double v[13];
 #pragma unroll
-    for (int e = 0; e < 13; ++e) v[e] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) {
-      const double* src = wpart + (int64_t)b * WR_STRIDE;
+  for (int e = 0; e < 13; ++e) v[e] = 0.0;
+  for (int b = threadIdx.x; b < n; b += 256) {
+    const double* src = wpart + (int64_t)b * WR_STRIDE;
 #pragma unroll
-      for (int e = 0; e < 13; ++e) v[e] += src[e];
-    }
-    block_sum<13, 256>(v, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int e = 0; e < 13; ++e) W[e] = v[e];
-    }
+    for (int e = 0; e < 13; ++e) v[e] += src[e];
   }
-  if (threadIdx.x != 0) return;
+  block_sum<13, 256>(v, lds);
+#pragma unroll
+  for (int e = 0; e < 13; ++e) W[e] = v[e];
+}
 
+// The update itself (one thread).
+__device__ void pose_update(const double W[13], const double* __restrict__ pose_in, double* __restrict__ pose_out,
+                            Derived* __restrict__ dv, int t, double G_fixed, int do_update,
+                            double* __restrict__ wrench_out, double* __restrict__ stats_row) {
   Derived& D = *dv;
   const double G = G_fixed > 0 ? G_fixed : G_sched(D, t);
   if (wrench_out) {
@@ -134,6 +129,76 @@ __global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ 
     for (int e = ST_STATUS + 1; e < STATS_STRIDE; ++e) stats_row[e] = 0.0;
   }
 }
+
+__global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ wpart, int nblk,
+                                                     const double* __restrict__ pose_in, double* __restrict__ pose_out,
+                                                     Derived* __restrict__ dv, int t, double G_fixed, int do_update,
+                                                     double* __restrict__ wrench_out, double* __restrict__ stats_row) {
+  __shared__ double lds[4 * 13];
+  double W[13];
+  sum_partials(wpart, nblk, lds, W);
+  if (threadIdx.x == 0) pose_update(W, pose_in, pose_out, dv, t, G_fixed, do_update, wrench_out, stats_row);
+}
+
+// One block per registration of a batch; its items own the wrench slots
+// [wslot0, wslot0 + n_items).  energy_out[r] (nullable) receives U.
+__global__ __launch_bounds__(256) void update_batch_kernel(const double* __restrict__ wpart,
+                                                           const RegDesc* __restrict__ regs, double* __restrict__ poses,
+                                                           Derived* __restrict__ dvs, int t, int do_update,
+                                                           double* __restrict__ energy_out, double* __restrict__ stats,
+                                                           int E) {
+  __shared__ double lds[4 * 13];
+  const int r = blockIdx.x;
+  const RegDesc& g = regs[r];
+  double W[13];
+  sum_partials(wpart + (int64_t)g.wslot0 * WR_STRIDE, g.n_items, lds, W);
+  if (threadIdx.x == 0) {
+    double* pose = poses + 13 * (int64_t)r;
+    pose_update(W, pose, pose, dvs + r, t, 0.0, do_update, nullptr,
+                stats ? stats + ((int64_t)r * E + t) * STATS_STRIDE : nullptr);
+    if (energy_out) energy_out[r] = W[WR_U];
+  }
+}
+
+// Multi-start initial poses: rotate the template by R0[s] about its centroid.
+__global__ void init_multistart_kernel(const double* __restrict__ R0, int S, const double* __restrict__ mom_t,
+                                       double* __restrict__ poses) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const double* R = R0 + 9 * (int64_t)s;
+  double* P = poses + 13 * (int64_t)s;
+  P[0] = 1.0;
+  for (int e = 0; e < 9; ++e) P[1 + e] = R[e];
+  for (int r = 0; r < 3; ++r)
+    P[10 + r] = mom_t[r] - (R[3 * r] * mom_t[0] + R[3 * r + 1] * mom_t[1] + R[3 * r + 2] * mom_t[2]);
+}
+
+// Index of the smallest value (ties: the lowest index; NaN never wins).
+__global__ void argmin_kernel(const double* __restrict__ v, int n, int32_t* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  int best = -1;
+  for (int i = 0; i < n; ++i)
+    if (!isnan(v[i]) && (best < 0 || v[i] < v[best])) best = i;
+  out[0] = best;
+}
+
+hipError_t launch_update_batch(const double* wpart, const RegDesc* regs, int B, double* poses, Derived* dvs, int t,
+                               int do_update, double* energy_out, double* stats, int E, hipStream_t st) {
+  hipLaunchKernelGGL(update_batch_kernel, dim3(B), dim3(256), 0, st, wpart, regs, poses, dvs, t, do_update, energy_out,
+                     stats, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_multistart(const double* R0, int S, const double* mom_t, double* poses, hipStream_t st) {
+  hipLaunchKernelGGL(init_multistart_kernel, dim3((S + 63) / 64), dim3(64), 0, st, R0, S, mom_t, poses);
+  return hipGetLastError();
+}
+
+hipError_t launch_argmin(const double* v, int n, int32_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(argmin_kernel, dim3(1), dim3(64), 0, st, v, n, out);
+  return hipGetLastError();
+}
+
 
 __global__ void fill_kernel(double* __restrict__ p, int n, double v) {
   const int i = blockIdx.x * 256 + threadIdx.x;
