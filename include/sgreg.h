@@ -86,7 +86,13 @@ typedef struct {
   double eps;
   double G1;
   int32_t E;
-  int32_t flags; /* bit 0: disable graph capture in sgr_register */
+  int32_t flags; /* bit 0: no graph capture in sgr_register / batch calls;
+                    bit 1: mixed precision (p = 1 only): the similarity-weighted
+                    sums over the reference run as a bf16 matrix product on the
+                    matrix cores (pair weights FP32, rounded to bf16; coordinates
+                    split into bf16 head + tail; FP32 accumulate, FP64 wrench);
+                    the energy U is then reported as 0 except by the FP32 final
+                    iteration of sgr_register; not for batch calls. */
   double dt2;
 } sgr_params;
 

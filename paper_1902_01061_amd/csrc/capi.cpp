@@ -90,6 +90,7 @@ int check_params(const sgr_params* p) {
   if (p->p < 1.0 && !(p->eps > 0)) return fail(SGR_EINVAL, "p < 1 needs eps > 0 (the force would diverge at r = 0)");
   if (p->g_mode != 0 && p->g_mode != 1) return fail(SGR_EINVAL, "g_mode must be 0 (g = s) or 1 (g = a a s)");
   if (!(p->G1 > 0) || !std::isfinite(p->G1)) return fail(SGR_EINVAL, "G1 must be positive");
+  if (p->flags & ~3) return fail(SGR_EINVAL, "unknown flag bits");
   if (!std::isfinite(p->sigma) || !std::isfinite(p->eps) || p->eps < 0) return fail(SGR_EINVAL, "bad sigma/eps");
   if (!std::isfinite(p->dt2)) return fail(SGR_EINVAL, "bad dt2");
   return SGR_OK;
@@ -108,6 +109,22 @@ PrepParams prep_of(const sgr_params* p) {
 }
 
 int pmode_of(double p) { return p == 1.0 ? 1 : (p == 3.0 ? 3 : 0); }
+
+constexpr int FLAG_NO_GRAPH = 1;
+constexpr int FLAG_MIXED = 2;
+
+bool is_mixed(const sgr_params* p) { return (p->flags & FLAG_MIXED) != 0; }
+
+int check_mixed(const sgr_params* p) {
+  if (is_mixed(p) && p->p != 1.0) return fail(SGR_EINVAL, "the mixed-precision force is implemented for p = 1 only");
+  return SGR_OK;
+}
+
+// Tiles for a call: the mixed kernel has a fixed 256-point template block.
+Tiles tiles_for(const sgr_ctx* ctx, int M, int N, const sgr_params* p) {
+  if (is_mixed(p)) return TileTable::make(M, N, 1, 8 * ctx->n_cu);
+  return ctx->tiles.pick(M, N, pmode_of(p->p));
+}
 
 // The packed reference is padded to whole tiles with zero-weight points.
 size_t pad_n(int64_t N) { return (size_t)((N + 255) / 256) * 256; }
@@ -390,7 +407,8 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
-  const Tiles T = ctx->tiles.pick(M, N, pmode_of(prm->p));
+  if (int e = check_mixed(prm)) return e;
+  const Tiles T = tiles_for(ctx, M, N, prm);
   Carve cv{nullptr};
   cv.take<Derived>(1);
   cv.take<float4>(pad_n(N));
@@ -409,7 +427,10 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
   ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, (const double*)in, dv, M, N,
               T.chunk_len, T.n_chunks, t, 0.0, wpart, fpart};
-  HIPCHK(launch_force(A, T.R, pmode_of(prm->p), wrench_out != nullptr, f_out != nullptr, st, T.sm));
+  if (is_mixed(prm))
+    HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
+  else
+    HIPCHK(launch_force(A, T.R, pmode_of(prm->p), wrench_out != nullptr, f_out != nullptr, st, T.sm));
   if (f_out) HIPCHK(launch_reduce_f(fpart, T.n_chunks, M, f_out, st));
   HIPCHK(launch_update(wpart, T.nblk, (const double*)in, (double*)out, dv, t, 0.0, 1, wrench_out, nullptr, st));
   return SGR_OK;
@@ -428,7 +449,9 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
   const int pm = pmode_of(prm->p);
-  const Tiles T = ctx->tiles.pick(M, N, pm);
+  if (int e = check_mixed(prm)) return e;
+  const Tiles T = ctx->tiles.pick(M, N, pm);     // FP32 kernel (and the final energy)
+  const Tiles TM = tiles_for(ctx, M, N, prm);    // the kernel of the other iterations
   Carve cv{nullptr};
   cv.take<float>(N);
   cv.take<float>(M);
@@ -436,7 +459,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   cv.take<Derived>(1);
   cv.take<float4>(pad_n(N));
   cv.take<float>(pad_n(N));
-  cv.take<double>((size_t)T.nblk * WR_STRIDE);
+  cv.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   float* aX = w.take<float>(N);
@@ -445,7 +468,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   Derived* dv = w.take<Derived>(1);
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
-  double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
+  double* wpart = w.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
 
   HIPCHK(launch_knn_desc(ref->x, ref->y, ref->z, N, prm->k, aX, nullptr, st));
   HIPCHK(launch_knn_desc(tmpl->x, tmpl->y, tmpl->z, M, prm->k, aY, nullptr, st));
@@ -456,11 +479,17 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
 
   auto loop = [&](hipStream_t s) -> int {
     for (int t = 0; t < prm->E; ++t) {
-      const bool wu = stats != nullptr || t == prm->E - 1;
+      const bool last = t == prm->E - 1;
+      const bool mixed = is_mixed(prm) && !last;   // the final energy comes from the FP32 kernel
+      const bool wu = !mixed && (stats != nullptr || last);
+      const Tiles& Tt = mixed ? TM : T;
       ForceArgs A{tmpl->x, tmpl->y, tmpl->z, aY, tmpl->m, ref4, lw, (const double*)inout, dv, M, N,
-                  T.chunk_len, T.n_chunks, t, 0.0, wpart, nullptr};
-      HIPCHK(launch_force(A, T.R, pm, wu, false, s, T.sm));
-      HIPCHK(launch_update(wpart, T.nblk, (const double*)inout, (double*)inout, dv, t, 0.0, 1, nullptr,
+                  Tt.chunk_len, Tt.n_chunks, t, 0.0, wpart, nullptr};
+      if (mixed)
+        HIPCHK(launch_force_mixed(A, false, s));
+      else
+        HIPCHK(launch_force(A, T.R, pm, wu, false, s, T.sm));
+      HIPCHK(launch_update(wpart, Tt.nblk, (const double*)inout, (double*)inout, dv, t, 0.0, 1, nullptr,
                            stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
     }
     return SGR_OK;
@@ -566,7 +595,8 @@ int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
   const int pm = pmode_of(prm->p);
-  const Tiles T = ctx->tiles.pick(M, N, pm);
+  if (int e = check_mixed(prm)) return e;
+  const Tiles T = tiles_for(ctx, M, N, prm);
   Carve cv{nullptr};
   cv.take<double>(16);
   cv.take<double>(16);
@@ -590,7 +620,10 @@ int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
   ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, pose, dv, M, N,
               T.chunk_len, T.n_chunks, 0, G, wpart, f_out ? fpart : nullptr};
-  HIPCHK(launch_force(A, T.R, pm, wrench_out != nullptr, f_out != nullptr, st, T.sm));
+  if (is_mixed(prm))
+    HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
+  else
+    HIPCHK(launch_force(A, T.R, pm, wrench_out != nullptr, f_out != nullptr, st, T.sm));
   if (f_out) HIPCHK(launch_reduce_f(fpart, T.n_chunks, M, f_out, st));
   if (wrench_out) HIPCHK(launch_update(wpart, T.nblk, pose, nullptr, dv, 0, G, 0, wrench_out, nullptr, st));
   return SGR_OK;
@@ -677,7 +710,11 @@ int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const
   pl->a_t = a_t;
   pl->prm = *prm;
   pl->pm = pmode_of(prm->p);
-  pl->T = ctx->tiles.pick(M, N, pl->pm);
+  if (int e = check_mixed(prm)) {
+    delete pl;
+    return e;
+  }
+  pl->T = tiles_for(ctx, M, N, prm);
   Carve cv{nullptr};
   cv.take<Derived>(1);
   cv.take<float4>(pad_n(N));
@@ -729,7 +766,10 @@ int sgr_plan_force(sgr_plan* pl, int t, double G, const sgr_pose* pose, double* 
   HIPCHK(hipSetDevice(pl->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ForceArgs A = plan_args(pl, t, G, pose, f_out != nullptr);
-  HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, f_out != nullptr, st, pl->T.sm));
+  if (is_mixed(&pl->prm))
+    HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
+  else
+    HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, f_out != nullptr, st, pl->T.sm));
   if (f_out) HIPCHK(launch_reduce_f(pl->fpart, pl->T.n_chunks, (int)pl->tmpl.n, f_out, st));
   if (wrench_out)
     HIPCHK(launch_update(pl->wpart, pl->T.nblk, (const double*)pose, nullptr, pl->dv, t, G, 0, wrench_out, nullptr,
@@ -743,7 +783,10 @@ int sgr_plan_step(sgr_plan* pl, int t, const sgr_pose* pose_in, sgr_pose* pose_o
   HIPCHK(hipSetDevice(pl->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ForceArgs A = plan_args(pl, t, 0.0, pose_in, false);
-  HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, false, st, pl->T.sm));
+  if (is_mixed(&pl->prm))
+    HIPCHK(launch_force_mixed(A, false, st));
+  else
+    HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, false, st, pl->T.sm));
   HIPCHK(launch_update(pl->wpart, pl->T.nblk, (const double*)pose_in, (double*)pose_out, pl->dv, t, 0.0, 1,
                        wrench_out, nullptr, st));
   return SGR_OK;
@@ -754,6 +797,7 @@ int sgr_register_batch(sgr_ctx* ctx, int B, const sgr_cloud* tmpls, const sgr_cl
   if (!ctx || !tmpls || !refs || !poses) return fail(SGR_EINVAL, "NULL argument");
   if (B < 1) return fail(SGR_EINVAL, "empty batch");
   if (int e = check_params(prm)) return e;
+  if (is_mixed(prm)) return fail(SGR_EINVAL, "the batched form runs the FP32 force only");
   if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
   if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
   BatchIn in;
@@ -781,6 +825,7 @@ int sgr_multistart(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, co
   if (int e = check_cloud(tmpl, "template")) return e;
   if (int e = check_cloud(ref, "reference")) return e;
   if (int e = check_params(prm)) return e;
+  if (is_mixed(prm)) return fail(SGR_EINVAL, "the batched form runs the FP32 force only");
   if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
   if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
   if (tmpl->n < prm->k || ref->n < prm->k) return fail(SGR_EINVAL, "a cloud has fewer points than k");

@@ -137,6 +137,8 @@ hipError_t launch_update_batch(const double* wpart, const RegDesc* regs, int B, 
 hipError_t launch_init_multistart(const double* R0, int S, const double* mom_t, double* poses, hipStream_t st);
 hipError_t launch_argmin(const double* v, int n, int32_t* out, hipStream_t st);
 hipError_t launch_force_batch(const BatchArgs& B, int R, int pm, bool want_u, int grid, hipStream_t st);
+hipError_t launch_force_mixed(const ForceArgs& A, bool want_f, hipStream_t st);
+int mixed_points_per_block();
 hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, float* f_out, hipStream_t st);
 int force_points_per_block(int R);
 int force_tile_j();
