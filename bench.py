@@ -76,6 +76,141 @@ def cpu_baseline(pr, E: int, k: int, target_s: float):
                       f"would take {pr.M * pr.N * E / rate:.0f} s at this rate (extrapolated)"}
 
 
+def _pose_err(sg, pose, pr):
+    """Pose RMSE over inlier template points against the generating transform,
+    divided by the reference bounding-box diagonal."""
+    import numpy as np
+
+    s_, R_, t_ = sg.pose_to_srt(pose)
+    inl = pr.corr >= 0
+    Y0 = pr.tmpl[inl] if inl.any() else pr.tmpl
+    Y0 = Y0.astype(np.float64)
+    est = s_ * Y0 @ R_.T + t_
+    truth = (Y0 - pr.gt_t) @ pr.gt_R / pr.gt_s
+    diam = float(np.linalg.norm(pr.ref.max(0) - pr.ref.min(0)))
+    return float(np.sqrt(np.mean(np.sum((est - truth) ** 2, axis=1)))) / diam
+
+
+def _timed(fn, reps=1):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, out
+
+
+def extra_batch(sg, ctx):
+    """256 uneven registrations in one batched call, and a 32-start sweep."""
+    import numpy as np
+
+    from synth import config4, config4_multistart
+
+    pairs = config4()
+    E = 100
+    prm = sg.Params(p=1.0, k=16, E=E)
+    tms = [sg.Cloud(p.tmpl) for p in pairs]
+    rfs = [sg.Cloud(p.ref) for p in pairs]
+    ctx.register_batch(tms, rfs, prm)             # warm-up (graph capture)
+    dt, (poses, energy, _) = _timed(lambda: ctx.register_batch(tms, rfs, prm))
+    pairs_total = sum(p.M * p.N for p in pairs) * E
+    errs = [_pose_err(sg, poses[r], pr) for r, pr in enumerate(pairs)]
+    ms_pr, R0 = config4_multistart()
+    tm, rf = sg.Cloud(ms_pr.tmpl), sg.Cloud(ms_pr.ref)
+    ctx.multistart(tm, rf, prm, R0)
+    dtm, (mposes, menergy, best) = _timed(lambda: ctx.multistart(tm, rf, prm, R0))
+    start_err = [_pose_err(sg, mposes[s], ms_pr) for s in range(len(R0))]
+    return {"registrations": len(pairs), "points_range": [min(p.N for p in pairs), max(p.N for p in pairs)],
+            "iterations": E, "ms_per_batch": dt * 1e3, "pairs_per_s": pairs_total / dt,
+            "pose_rmse_over_diameter_median": float(np.median(errs)),
+            "multistart": {"starts": len(R0), "M": ms_pr.M, "N": ms_pr.N, "ms": dtm * 1e3,
+                           "pairs_per_s": len(R0) * ms_pr.M * ms_pr.N * E / dtm, "best_start": best,
+                           "best_pose_rmse_over_diameter": start_err[best],
+                           "min_pose_rmse_over_diameter": float(min(start_err))}}
+
+
+def extra_adjoint(sg, ctx):
+    """Forward + adjoint of the force field at 8192 x 8192 (p = 2, eps = 0.05 L)."""
+    import numpy as np
+    import torch
+
+    from synth import config3
+
+    pr = config3()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    a_t, _ = ctx.descriptors(tm, 16)
+    a_r, mom_r = ctx.descriptors(rf, 16)
+    L = float(np.sqrt(mom_r[9].item()))
+    sigma = float(a_r.double().std(unbiased=False).item())
+    prm = sg.Params(p=2.0, k=16, sigma=sigma, eps=0.05 * L)
+    G = 5000.0
+    gf = torch.randn((pr.M, 3), device="cuda")
+    fwd = lambda: ctx.force_fwd(tm, a_t, rf, a_r, mom_r, prm, G)
+    f, _ = fwd()
+    bwd = lambda: ctx.force_bwd(tm, a_t, rf, a_r, mom_r, prm, G, f, gf, None)
+    bwd()
+    tf, _ = _timed(fwd, 20)
+    tb, (gy, gm, gse) = _timed(bwd, 20)
+    return {"M": pr.M, "N": pr.N, "p": 2, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3,
+            "fwd_pairs_per_s": pr.M * pr.N / tf, "bwd_pairs_per_s": pr.M * pr.N / tb,
+            "grads_finite": bool(torch.isfinite(gy).all().item() and torch.isfinite(gse).all().item())}
+
+
+def extra_scene(sg, ctx, cpu_rows: int):
+    """Depth-frame scene (307,200 x 250,000, g = a a s): FP32 and mixed
+    registrations, their pose difference per iteration, and the one-step
+    force error of both against the FP64 oracle on sampled template rows."""
+    import numpy as np
+    import torch
+
+    from oracle import ref as O
+    from synth import config5
+
+    pr = config5()
+    E = 100
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    out = {"M": pr.M, "N": pr.N, "iterations": E, "g_mode": 1}
+    res = {}
+    for name, flags in (("fp32", 0), ("mixed", 2)):
+        prm = sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=flags)
+        ctx.register(tm, rf, prm)
+        dt, (pose, _) = _timed(lambda: ctx.register(tm, rf, prm))
+        _, st = ctx.register(tm, rf, prm, stats=True)     # trajectory for the comparison (untimed)
+        res[name] = (dt, pose, st.cpu().numpy())
+        out[name] = {"ms_per_registration": dt * 1e3, "pairs_per_s": pr.M * pr.N * E / dt,
+                     "pose_rmse_over_diameter": _pose_err(sg, pose, pr)}
+    out["mixed_speedup"] = res["fp32"][0] / res["mixed"][0]
+    # per-iteration pose difference, mixed vs FP32, as RMSE of transformed template points / diameter
+    diam = float(np.linalg.norm(pr.ref.max(0) - pr.ref.min(0)))
+    sub = pr.tmpl[:: max(1, pr.M // 5000)].astype(np.float64)
+    def apply(row):
+        s_, R_, t_ = row[14], row[15:24].reshape(3, 3), row[24:27]
+        return s_ * sub @ R_.T + t_
+    diffs = [float(np.sqrt(np.mean(np.sum((apply(res["mixed"][2][t]) - apply(res["fp32"][2][t])) ** 2, 1)))) / diam
+             for t in range(E)]
+    out["mixed_vs_fp32_pose_diff_per_iter"] = {"t0..4": diffs[:5], "t10": diffs[10], "t50": diffs[50],
+                                                 "t99": diffs[99]}
+    # one-step force against the FP64 oracle at the identity pose (sampled rows)
+    a_t, mom_t = ctx.descriptors(tm, 16)
+    a_r, mom_r = ctx.descriptors(rf, 16)
+    rows = np.random.default_rng(0).choice(pr.M, cpu_rows, replace=False)
+    aX = a_r.cpu().numpy().astype(np.float64)
+    aY = a_t.cpu().numpy().astype(np.float64)
+    S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=1.0, g_mode=1, k=16, E=E), aX=aX, aY=aY)
+    G = O.G_schedule(0, E)
+    f_ora, _ = O.forces_c(pr.tmpl.astype(np.float64), S, G, rows=rows)
+    for name, flags in (("fp32", 0), ("mixed", 2)):
+        plan = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=flags))
+        _, f = plan.force(sg.pose_identity(), t=0, want_wrench=False, want_f=True)
+        f = f.cpu().numpy().astype(np.float64)[rows]
+        out[name]["one_step_force_rel_err_vs_oracle"] = float(np.linalg.norm(f - f_ora) / np.linalg.norm(f_ora))
+        plan.close()
+    out["oracle_rows_sampled"] = int(cpu_rows)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +219,8 @@ def main() -> int:
     ap.add_argument("--kernel-reps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batch / adjoint / mixed / scene legs")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -108,6 +245,12 @@ def main() -> int:
     ident = sg.pose_identity()
     pose = ident.clone()
 
+    a_t, mom_t = ctx.descriptors(tm, k)
+    a_r, mom_r = ctx.descriptors(rf, k)
+    tuned = None
+    if not args.no_autotune:
+        tuned, tuned_ms = ctx.autotune(tm, a_t, rf, a_r, mom_t, mom_r, prm, reps=5)
+        log(f"autotuned force kernel launch: R={tuned[0]} blocks/CU={tuned[1]} variant={tuned[2]} ({tuned_ms:.4f} ms)")
     for w in range(args.warmup):
         pose.copy_(ident)
         ctx.register(tm, rf, prm, pose=pose)
@@ -134,8 +277,6 @@ def main() -> int:
     nn_rmse = float(ctx.residual(tm, rf, pose).item())
 
     # dominant kernel: the all-pairs force kernel alone, on the final pose
-    a_t, mom_t = ctx.descriptors(tm, k)
-    a_r, mom_r = ctx.descriptors(rf, k)
     plan = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, prm)
     for _ in range(3):
         plan.force(pose, t=E - 1, want_wrench=False)
@@ -178,6 +319,27 @@ def main() -> int:
                      "kernel": "force_kernel", "ms_per_launch": k_ms, "pairs_per_launch": M * N,
                      "flops_per_pair": fpp, "pairs_per_s": k_pairs},
     }
+    if tuned is not None:
+        out["roofline"]["launch"] = {"R": tuned[0], "blocks_per_cu": tuned[1],
+                                     "variant": ["lds", "scalar-loads"][tuned[2]]}
+    if not args.no_extras:
+        # the same registration with the mixed-precision force (bf16 matrix cores)
+        prm_m = sg.Params(p=p, k=k, E=E, flags=2)
+        pm_ = ident.clone()
+        ctx.register(tm, rf, prm_m, pose=pm_)
+        dtm, _ = _timed(lambda: (pm_.copy_(ident), ctx.register(tm, rf, prm_m, pose=pm_)), args.steps)
+        out["mixed"] = {"ms_per_registration": dtm * 1e3, "pairs_per_s": M * N * E / dtm,
+                        "speedup_vs_fp32": ms_per_step / (dtm * 1e3),
+                        "pose_rmse_over_diameter": _pose_err(sg, pm_, pr),
+                        "fp32_pose_rmse_over_diameter": pose_rmse / diam}
+        log(f"mixed: {dtm * 1e3:.1f} ms/registration")
+        out["batch"] = extra_batch(sg, ctx)
+        log(f"batch: {out['batch']['ms_per_batch']:.1f} ms")
+        out["adjoint"] = extra_adjoint(sg, ctx)
+        log(f"adjoint: fwd {out['adjoint']['fwd_ms']:.3f} ms, bwd {out['adjoint']['bwd_ms']:.3f} ms")
+        out["scene"] = extra_scene(sg, ctx, cpu_rows=48)
+        log(f"scene: fp32 {out['scene']['fp32']['ms_per_registration']:.1f} ms, "
+            f"mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(pr, E, k, args.cpu_seconds)

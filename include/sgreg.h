@@ -175,6 +175,21 @@ int sgr_plan_force(sgr_plan* plan, int t, double G, const sgr_pose* pose, double
  * entry. */
 int sgr_set_tiles(sgr_ctx* ctx, int64_t M, int64_t N, double p, int R, int blocks_per_cu, int variant);
 
+/* Autotuner: times the pair-force kernel for every launch shape (R in
+ * {2, 4, 8}, blocks per CU in {8, 12, 16}, LDS or scalar-load variant)
+ * on this pair, `reps` launches each, and stores the fastest in the tile
+ * table for the (M, N, p) bucket.  best (host int[3], nullable): R,
+ * blocks_per_cu, variant; best_ms (host, nullable): its time per launch.
+ * Synchronises the stream. */
+int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                 const double* mom_t, const double* mom_r, const sgr_params* prm, int reps, int* best,
+                 double* best_ms, sgr_stream_t stream);
+
+/* Persist / restore the tile table as JSON {"arch": ..., "entries": [...]};
+ * loading a table written for another architecture fails (SGR_EINVAL). */
+int sgr_tiles_save(sgr_ctx* ctx, const char* path);
+int sgr_tiles_load(sgr_ctx* ctx, const char* path);
+
 /* The force field at template positions `tmpl` (used as they are, identity
  * pose): f_out[M][3] (float32) and wrench_out[13] (F, K, U as in sgr_step),
  * with force constant G > 0.  mom_r: reference moments.  The forward pass

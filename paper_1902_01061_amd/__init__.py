@@ -126,6 +126,23 @@ class Context:
     def set_tiles(self, M: int, N: int, p: float, R: int, blocks_per_cu: int, variant: int = 0):
         check(lib().sgr_set_tiles(self._h, int(M), int(N), float(p), int(R), int(blocks_per_cu), int(variant)))
 
+    def autotune(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params, reps: int = 5):
+        """Time every launch shape of the force kernel on this pair and keep
+        the fastest for its size bucket; returns ((R, blocks_per_cu, variant), ms)."""
+        best = (ctypes.c_int * 3)()
+        ms = ctypes.c_double()
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_autotune(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_t),
+                                 _ptr(mom_r), ctypes.byref(pr), int(reps), best, ctypes.byref(ms),
+                                 _stream(self.device)))
+        return (best[0], best[1], best[2]), ms.value
+
+    def save_tiles(self, path: str):
+        check(lib().sgr_tiles_save(self._h, str(path).encode()))
+
+    def load_tiles(self, path: str):
+        check(lib().sgr_tiles_load(self._h, str(path).encode()))
+
     # -------------------------------------------------------------- calls
     def descriptors(self, cloud: Cloud, k: int):
         a = torch.empty(cloud.n, dtype=torch.float32, device=self.device)

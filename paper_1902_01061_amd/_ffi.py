@@ -56,6 +56,9 @@ SIGNATURES = {
     "sgr_set_tiles": [P, I64, I64, D, I, I, I],
     "sgr_force_fwd": [P, CP, P, CP, P, P, PP, D, P, P, P],
     "sgr_register_batch": [P, I, CP, CP, PP, P, P, P, P],
+    "sgr_autotune": [P, CP, P, CP, P, P, P, PP, I, P, P, P],
+    "sgr_tiles_save": [P, ctypes.c_char_p],
+    "sgr_tiles_load": [P, ctypes.c_char_p],
     "sgr_multistart": [P, CP, CP, PP, I, P, P, P, P, P],
     "sgr_force_bwd": [P, CP, P, CP, P, P, PP, D, P, P, P, P, P, P, P],
 }

@@ -38,6 +38,7 @@ struct GraphCache {
 struct sgr_ctx {
   int device = 0;
   int n_cu = 256;
+  std::string arch;
   hipStream_t cap = nullptr;
   char* ws = nullptr;
   size_t ws_size = 0;
@@ -349,7 +350,12 @@ int sgr_create(sgr_ctx** out, int device) {
   sgr_ctx* c = new sgr_ctx();
   c->device = device;
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->n_cu = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
+    const size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch.resize(colon);
+  }
   if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return fail(SGR_EHIP, "stream creation failed");
@@ -579,6 +585,129 @@ int sgr_set_tiles(sgr_ctx* ctx, int64_t M, int64_t N, double p, int R, int block
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(SGR_EINVAL, "blocks_per_cu must be in [1, 64]");
   if (variant != 0 && variant != 1) return fail(SGR_EINVAL, "variant must be 0 (LDS) or 1 (scalar loads)");
   ctx->tiles.over[key] = std::make_tuple(R, blocks_per_cu, variant);
+  return SGR_OK;
+}
+
+int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                 const double* mom_t, const double* mom_r, const sgr_params* prm, int reps, int* best,
+                 double* best_ms, sgr_stream_t stream) {
+  if (!ctx || !a_t || !a_r || !mom_t || !mom_r) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (reps < 1) reps = 5;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  const int pm = pmode_of(prm->p);
+  const auto key = std::make_tuple(log2_bucket(M), log2_bucket(N), pm);
+  // size the workspace for the largest candidate
+  size_t need = 0;
+  for (int R : {2, 4, 8})
+    for (int bpc : {8, 12, 16}) {
+      const Tiles T = TileTable::make(M, N, R, bpc * ctx->n_cu);
+      Carve cv{nullptr};
+      cv.take<double>(16);
+      cv.take<Derived>(1);
+      cv.take<float4>(pad_n(N));
+      cv.take<float>(pad_n(N));
+      cv.take<double>((size_t)T.nblk * WR_STRIDE);
+      need = std::max(need, cv.off);
+    }
+  if (int e = ensure_ws(ctx, need)) return e;
+  Carve w{ctx->ws};
+  double* pose = w.take<double>(16);
+  Derived* dv = w.take<Derived>(1);
+  float4* ref4 = w.take<float4>(pad_n(N));
+  float* lw = w.take<float>(pad_n(N));
+  const size_t wp_off = w.off;
+  HIPCHK(launch_identity_pose(pose, st));
+  HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
+  HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best_t = 1e300;
+  int bR = 4, bB = 8, bV = 0;
+  for (int v : {0, 1})
+    for (int R : {2, 4, 8})
+      for (int bpc : {8, 12, 16}) {
+        const Tiles T = TileTable::make(M, N, R, bpc * ctx->n_cu, v);
+        Carve wc{ctx->ws, wp_off};
+        double* wpart = wc.take<double>((size_t)T.nblk * WR_STRIDE);
+        ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, pose, dv, M, N,
+                    T.chunk_len, T.n_chunks, prm->E - 1, 0.0, wpart, nullptr};
+        HIPCHK(launch_force(A, T.R, pm, false, false, st, T.sm));
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) HIPCHK(launch_force(A, T.R, pm, false, false, st, T.sm));
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / reps;
+        if (per < best_t) {
+          best_t = per;
+          bR = R;
+          bB = bpc;
+          bV = v;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tiles.over[key] = std::make_tuple(bR, bB, bV);
+  if (best) {
+    best[0] = bR;
+    best[1] = bB;
+    best[2] = bV;
+  }
+  if (best_ms) *best_ms = best_t;
+  return SGR_OK;
+}
+
+int sgr_tiles_save(sgr_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(SGR_EINVAL, "NULL argument");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(SGR_EINVAL, std::string("cannot write ") + path);
+  std::fprintf(f, "{\"arch\": \"%s\", \"entries\": [", ctx->arch.c_str());
+  bool first = true;
+  for (const auto& kv : ctx->tiles.over) {
+    std::fprintf(f, "%s\n  {\"m_bucket\": %d, \"n_bucket\": %d, \"p_mode\": %d, \"R\": %d, \"blocks_per_cu\": %d, "
+                 "\"variant\": %d}", first ? "" : ",", std::get<0>(kv.first), std::get<1>(kv.first),
+                 std::get<2>(kv.first), std::get<0>(kv.second), std::get<1>(kv.second), std::get<2>(kv.second));
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  std::fclose(f);
+  return SGR_OK;
+}
+
+int sgr_tiles_load(sgr_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(SGR_EINVAL, "NULL argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(SGR_EINVAL, std::string("cannot read ") + path);
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, n);
+  std::fclose(f);
+  const size_t a = txt.find("\"arch\": \"");
+  if (a == std::string::npos) return fail(SGR_EINVAL, "not a tile table");
+  const size_t a0 = a + 9, a1 = txt.find('"', a0);
+  if (txt.compare(a0, a1 - a0, ctx->arch) != 0) return fail(SGR_EINVAL, "tile table is for another architecture");
+  size_t pos = 0;
+  int loaded = 0;
+  while ((pos = txt.find("{\"m_bucket\":", pos)) != std::string::npos) {
+    int mb, nb, pmv, R, bpc, v;
+    if (std::sscanf(txt.c_str() + pos,
+                    "{\"m_bucket\": %d, \"n_bucket\": %d, \"p_mode\": %d, \"R\": %d, \"blocks_per_cu\": %d, "
+                    "\"variant\": %d}", &mb, &nb, &pmv, &R, &bpc, &v) != 6)
+      return fail(SGR_EINVAL, "malformed tile table entry");
+    if ((R != 1 && R != 2 && R != 4 && R != 8) || bpc < 1 || bpc > 64 || (v != 0 && v != 1))
+      return fail(SGR_EINVAL, "tile table entry out of range");
+    ctx->tiles.over[std::make_tuple(mb, nb, pmv)] = std::make_tuple(R, bpc, v);
+    ++loaded;
+    ++pos;
+  }
   return SGR_OK;
 }
 
