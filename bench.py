@@ -221,6 +221,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch / adjoint / mixed / scene legs")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tiles-cache", default="", help="tile table file: loaded if present, else written after tuning")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (traffic-counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -231,6 +234,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = 64 * 1024 * 1024       # float32 elements: 256 MiB read + 256 MiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": 4 * n, "bytes_written": 4 * n, "copies": 5}))
+        return 0
 
     import paper_1902_01061_amd as sg
     from synth import config2
@@ -248,9 +261,14 @@ def main() -> int:
     a_t, mom_t = ctx.descriptors(tm, k)
     a_r, mom_r = ctx.descriptors(rf, k)
     tuned = None
-    if not args.no_autotune:
+    if args.tiles_cache and os.path.exists(args.tiles_cache):
+        ctx.load_tiles(args.tiles_cache)
+        log(f"tile table loaded from {args.tiles_cache}")
+    elif not args.no_autotune:
         tuned, tuned_ms = ctx.autotune(tm, a_t, rf, a_r, mom_t, mom_r, prm, reps=5)
         log(f"autotuned force kernel launch: R={tuned[0]} blocks/CU={tuned[1]} variant={tuned[2]} ({tuned_ms:.4f} ms)")
+        if args.tiles_cache:
+            ctx.save_tiles(args.tiles_cache)
     for w in range(args.warmup):
         pose.copy_(ident)
         ctx.register(tm, rf, prm, pose=pose)

@@ -228,18 +228,20 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
     }
   }
 
-  // FP64 running sums per point.  r-form: (tx, ty, tz) = sum_j c_ij r_ij.
-  // Moment form (p = 1, no energy): t0 = sum_j c'_ij, (tx, ty, tz) =
-  // sum_j c'_ij x_j with c'_ij = exp2(2 b_i b_j + lw_j - b_j^2) = c_ij exp2(b_i^2),
-  // so sum_j c_ij r_ij = exp2(-b_i^2) (y_i t0 - t).  It needs no r and a single
-  // FMA for the exponent: 5 VALU + 1 exp2 per pair instead of 8 + 1.  It is
-  // used when the prepare kernel has shown the expanded exponent to stay
-  // below 64 for every pair (expand_ok), so c' cannot overflow.
+  // FP64 running sums per point.  r-form: (tx, ty, tz) = sum_j c_ij r_ij
+  // (and tu = sum_j c_ij q_ij).  Moment form (p = 1): t0 = sum_j c, (tx, ty,
+  // tz) = sum_j c x_j and tq = sum_j c |x_j|^2, so that sum_j c r =
+  // y_i t0 - t and sum_j c q = |y_i|^2 t0 - 2 y_i.t + tq + eps^2 t0; it needs
+  // no r_ij.  Its exponent is either lw_j - (b_i - b_j)^2 (one sub and one
+  // FMA: 6 VALU + 1 exp2 per pair) or, when the prepare kernel has shown it
+  // cannot overflow (expand_ok), the expanded 2 b_i b_j + (lw_j - b_j^2)
+  // (one FMA: 5 VALU + 1 exp2), whose extra factor exp2(b_i^2) is divided
+  // out in FP64 at the end.
   double t0[R], tx[R], ty[R], tz[R], tu[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) t0[r] = tx[r] = ty[r] = tz[r] = tu[r] = 0.0;
-  constexpr bool MOM_CAPABLE = (PM == 1) && !WU;
-  const bool mom = MOM_CAPABLE && D.expand_ok != 0.0;
+  constexpr bool MOM = (PM == 1);
+  const bool expd = MOM && D.expand_ok != 0.0;
   float al[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) al[r] = 2.f * bi[r];
@@ -265,15 +267,17 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
       }
       __syncthreads();
     }
-    if constexpr (MOM_CAPABLE) {
-      if (mom) {
-        float a0[R], ax[R], ay[R], az[R];
+    if constexpr (MOM) {
+      float a0[R], ax[R], ay[R], az[R], aq[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) a0[r] = ax[r] = ay[r] = az[r] = 0.f;
+      for (int r = 0; r < R; ++r) a0[r] = ax[r] = ay[r] = az[r] = aq[r] = 0.f;
+      if (expd) {
 #pragma unroll 2
         for (int jj = 0; jj < F_TJ; ++jj) {
           const float4 X = SM ? gref[jj] : s_ref[jj];
           const float beta = __builtin_fmaf(-X.w, X.w, SM ? glw[jj] : s_lw[jj]);
+          float x2 = 0.f;
+          if constexpr (WU) x2 = __builtin_fmaf(X.x, X.x, __builtin_fmaf(X.y, X.y, X.z * X.z));
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const float c = __builtin_amdgcn_exp2f(__builtin_fmaf(al[r], X.w, beta));
@@ -281,53 +285,78 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
             ax[r] = __builtin_fmaf(c, X.x, ax[r]);
             ay[r] = __builtin_fmaf(c, X.y, ay[r]);
             az[r] = __builtin_fmaf(c, X.z, az[r]);
+            if constexpr (WU) aq[r] = __builtin_fmaf(c, x2, aq[r]);
           }
         }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          t0[r] += (double)a0[r];
-          tx[r] += (double)ax[r];
-          ty[r] += (double)ay[r];
-          tz[r] += (double)az[r];
-        }
-        continue;
-      }
-    }
-    float ax[R], ay[R], az[R], au[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = au[r] = 0.f;
+      } else {
 #pragma unroll 2
-    for (int jj = 0; jj < F_TJ; ++jj) {
-      const float4 X = SM ? gref[jj] : s_ref[jj];
-      const float lw = SM ? glw[jj] : s_lw[jj];
+        for (int jj = 0; jj < F_TJ; ++jj) {
+          const float4 X = SM ? gref[jj] : s_ref[jj];
+          const float lw = SM ? glw[jj] : s_lw[jj];
+          float x2 = 0.f;
+          if constexpr (WU) x2 = __builtin_fmaf(X.x, X.x, __builtin_fmaf(X.y, X.y, X.z * X.z));
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const float db = bi[r] - X.w;
+            const float c = __builtin_amdgcn_exp2f(__builtin_fmaf(-db, db, lw));
+            a0[r] += c;
+            ax[r] = __builtin_fmaf(c, X.x, ax[r]);
+            ay[r] = __builtin_fmaf(c, X.y, ay[r]);
+            az[r] = __builtin_fmaf(c, X.z, az[r]);
+            if constexpr (WU) aq[r] = __builtin_fmaf(c, x2, aq[r]);
+          }
+        }
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const float rx = yx[r] - X.x, ry = yy[r] - X.y, rz = yz[r] - X.z;
-        float q;
-        const float c = pair_coef<PM>(rx, ry, rz, bi[r] - X.w, lw, eps2, hp, q);
-        ax[r] = __builtin_fmaf(c, rx, ax[r]);
-        ay[r] = __builtin_fmaf(c, ry, ay[r]);
-        az[r] = __builtin_fmaf(c, rz, az[r]);
-        if constexpr (WU) au[r] = __builtin_fmaf(c, q, au[r]);
+        t0[r] += (double)a0[r];
+        tx[r] += (double)ax[r];
+        ty[r] += (double)ay[r];
+        tz[r] += (double)az[r];
+        if constexpr (WU) tu[r] += (double)aq[r];
+      }
+    } else {
+      float ax[R], ay[R], az[R], au[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = au[r] = 0.f;
+#pragma unroll 2
+      for (int jj = 0; jj < F_TJ; ++jj) {
+        const float4 X = SM ? gref[jj] : s_ref[jj];
+        const float lw = SM ? glw[jj] : s_lw[jj];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float rx = yx[r] - X.x, ry = yy[r] - X.y, rz = yz[r] - X.z;
+          float q;
+          const float c = pair_coef<PM>(rx, ry, rz, bi[r] - X.w, lw, eps2, hp, q);
+          ax[r] = __builtin_fmaf(c, rx, ax[r]);
+          ay[r] = __builtin_fmaf(c, ry, ay[r]);
+          az[r] = __builtin_fmaf(c, rz, az[r]);
+          if constexpr (WU) au[r] = __builtin_fmaf(c, q, au[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        tx[r] += (double)ax[r];
+        ty[r] += (double)ay[r];
+        tz[r] += (double)az[r];
+        if constexpr (WU) tu[r] += (double)au[r];
       }
     }
+  }
+  if constexpr (MOM) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      tx[r] += (double)ax[r];
-      ty[r] += (double)ay[r];
-      tz[r] += (double)az[r];
-      if constexpr (WU) tu[r] += (double)au[r];
+      const double sc = expd ? exp2(-(double)bi[r] * (double)bi[r]) : 1.0;
+      const double py = yx[r], pyy = yy[r], pz = yz[r];
+      if constexpr (WU)
+        tu[r] = sc * ((py * py + pyy * pyy + pz * pz + D.eps2) * t0[r] - 2.0 * (py * tx[r] + pyy * ty[r] + pz * tz[r]) +
+                      tu[r]);
+      tx[r] = sc * (py * t0[r] - tx[r]);
+      ty[r] = sc * (pyy * t0[r] - ty[r]);
+      tz[r] = sc * (pz * t0[r] - tz[r]);
     }
   }
-  if (mom) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double sc = exp2(-(double)bi[r] * (double)bi[r]);
-      tx[r] = sc * ((double)yx[r] * t0[r] - tx[r]);
-      ty[r] = sc * ((double)yy[r] * t0[r] - ty[r]);
-      tz[r] = sc * ((double)yz[r] * t0[r] - tz[r]);
-    }
-  }
+
 
   // Per-point force and its contributions to F, K, U.
   const double G = A.G > 0 ? A.G : G_at(D, A.t);
