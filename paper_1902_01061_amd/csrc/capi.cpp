@@ -252,6 +252,9 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   cv.take<float>(ref_total);
   cv.take<double>((size_t)n_items * WR_STRIDE);
   cv.take<double>(B);
+  size_t gws_size = 0;
+  for (int c = 0; c < ncl; ++c) gws_size = std::max(gws_size, grid_knn_workspace((int)in.clouds[c]->n, prm->k));
+  cv.take<char>(gws_size);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   CloudDesc* d_cds = w.take<CloudDesc>(ncl);
@@ -267,6 +270,7 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   float* d_lw = w.take<float>(ref_total);
   double* d_wpart = w.take<double>((size_t)n_items * WR_STRIDE);
   double* d_energy = w.take<double>(B);
+  char* d_gws = w.take<char>(gws_size);
 
   for (int c = 0; c < ncl; ++c)
     cds[c] = CloudDesc{in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, d_a + a_off[c], (int)in.clouds[c]->n, 0};
@@ -291,7 +295,11 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   HIPCHK(hipMemcpyAsync(d_regs, regs.data(), sizeof(RegDesc) * B, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_items, items.data(), sizeof(int4) * n_items, hipMemcpyHostToDevice, st));
 
-  HIPCHK(launch_knn_desc_batch(d_cds, d_kb, (int)kblocks.size(), prm->k, st));
+  // descriptors: one grid kNN per cloud (they share the grid workspace in
+  // stream order)
+  for (int c = 0; c < ncl; ++c)
+    HIPCHK(launch_grid_knn(in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, (int)in.clouds[c]->n, prm->k,
+                           d_a + a_off[c], nullptr, d_gws, st));
   HIPCHK(launch_moments_batch(d_cds, ncl, d_mom, st));
   HIPCHK(launch_prepare_batch(d_prep, B, prep_of(prm), d_dv, st));
   HIPCHK(launch_pack_batch(d_prep, d_b2r, (int)blk2reg.size(), d_dv, d_ref4, d_lw, st));
@@ -387,7 +395,10 @@ int sgr_descriptors(sgr_ctx* ctx, const sgr_cloud* c, int k, float* a_out, doubl
   if (!a_out && !moments_out) return fail(SGR_EINVAL, "nothing to compute");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
-  if (a_out) HIPCHK(launch_knn_desc(c->x, c->y, c->z, (int)c->n, k, a_out, nullptr, st));
+  if (a_out) {
+    if (int e = ensure_ws(ctx, grid_knn_workspace((int)c->n, k))) return e;
+    HIPCHK(launch_grid_knn(c->x, c->y, c->z, (int)c->n, k, a_out, nullptr, ctx->ws, st));
+  }
   if (moments_out) HIPCHK(launch_moments(c->x, c->y, c->z, c->n, moments_out, st));
   return SGR_OK;
 }
@@ -398,7 +409,8 @@ int sgr_knn(sgr_ctx* ctx, const sgr_cloud* c, int k, int32_t* idx_out, sgr_strea
   if (k < 1 || k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
   if (c->n < k) return fail(SGR_EINVAL, "cloud has fewer points than k");
   HIPCHK(hipSetDevice(ctx->device));
-  HIPCHK(launch_knn_desc(c->x, c->y, c->z, (int)c->n, k, nullptr, idx_out, (hipStream_t)stream));
+  if (int e = ensure_ws(ctx, grid_knn_workspace((int)c->n, k))) return e;
+  HIPCHK(launch_grid_knn(c->x, c->y, c->z, (int)c->n, k, nullptr, idx_out, ctx->ws, (hipStream_t)stream));
   return SGR_OK;
 }
 
@@ -466,6 +478,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   cv.take<float4>(pad_n(N));
   cv.take<float>(pad_n(N));
   cv.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
+  cv.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   float* aX = w.take<float>(N);
@@ -475,9 +488,10 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
   double* wpart = w.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
+  char* gws = w.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
 
-  HIPCHK(launch_knn_desc(ref->x, ref->y, ref->z, N, prm->k, aX, nullptr, st));
-  HIPCHK(launch_knn_desc(tmpl->x, tmpl->y, tmpl->z, M, prm->k, aY, nullptr, st));
+  HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, prm->k, aX, nullptr, gws, st));
+  HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, prm->k, aY, nullptr, gws, st));
   HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, mom + 10, st));
   HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom, st));
   HIPCHK(launch_prepare(aX, ref->m, N, aY, tmpl->m, M, mom, mom + 10, prep_of(prm), dv, st));

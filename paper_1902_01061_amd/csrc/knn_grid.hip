@@ -1,0 +1,356 @@
+// Exact k nearest neighbours through a uniform grid (same result as the
+// brute-force kernel: float32 squared distance ((dx*dx + dy*dy) + dz*dz),
+// every operation rounded, ties by index), followed by the same FP64
+// neighbourhood covariance and curvature (Sec. III-A).
+//
+// 1. grid_setup: bounding box and a cell size h with about two points per
+//    cell of the bounding volume (fewer cells than the allocated maximum);
+// 2. counting sort of the points by cell (cell counts, exclusive scan,
+//    scatter); the order inside a cell does not matter because candidates
+//    are ranked by the (distance, index) key;
+// 3. one query per lane, in cell order (neighbouring lanes search the same
+//    cells): shells of cells at Chebyshev radius 0, 1, 2, ... are scanned
+//    until the current k-th distance is below the distance from the query to
+//    the unsearched region (with a margin that covers the float32 rounding
+//    of cell assignment and of the key), so no closer point can be missed.
+#include "common.h"
+#include "launch.h"
+
+namespace sgr {
+
+struct GridInfo {
+  float lo[3];
+  float h;
+  int dims[3];
+  int ncells;
+};
+
+constexpr int GQ_BT = 256;
+constexpr int SCAN_B = 1024;
+
+__global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                          const float* __restrict__ Zc, int n, int max_cells,
+                                                          GridInfo* __restrict__ gi) {
+  __shared__ float red[16][6];
+  float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    const float p[3] = {X[i], Y[i], Zc[i]};
+    for (int a = 0; a < 3; ++a) {
+      v[a] = fminf(v[a], p[a]);
+      v[3 + a] = fmaxf(v[3 + a], p[a]);
+    }
+  }
+  for (int a = 0; a < 6; ++a) {
+    float m = v[a];
+    for (int off = 32; off > 0; off >>= 1) {
+      const float o = __shfl_xor(m, off, 64);
+      m = a < 3 ? fminf(m, o) : fmaxf(m, o);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][a] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int a = 0; a < 6; ++a)
+    for (int w = 1; w < 16; ++w) red[0][a] = a < 3 ? fminf(red[0][a], red[w][a]) : fmaxf(red[0][a], red[w][a]);
+  GridInfo G;
+  double e[3];
+  for (int a = 0; a < 3; ++a) {
+    G.lo[a] = red[0][a];
+    e[a] = (double)red[0][3 + a] - (double)red[0][a];
+  }
+  // cell size for about two points per cell of the bounding volume; flat or
+  // linear clouds fall back to their non-degenerate extents
+  double s[3] = {e[0], e[1], e[2]};
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2 - i; ++j)
+      if (s[j] < s[j + 1]) {
+        const double t = s[j];
+        s[j] = s[j + 1];
+        s[j + 1] = t;
+      }
+  const double rho = 2.0;
+  double h;
+  if (s[2] > 1e-6 * s[0])
+    h = cbrt(s[0] * s[1] * s[2] * rho / n);
+  else if (s[1] > 1e-6 * s[0])
+    h = sqrt(s[0] * s[1] * rho / n);
+  else
+    h = s[0] * rho / n;
+  if (!(h > 0) || !isfinite(h)) h = 1.0;
+  int d[3];
+  for (int it = 0; it < 200; ++it) {
+    long long tot = 1;
+    for (int a = 0; a < 3; ++a) {
+      d[a] = (int)fmin(1024.0, floor(e[a] / h) + 1.0);
+      tot *= d[a];
+    }
+    if (tot <= max_cells) break;
+    h *= 1.1;
+  }
+  G.h = (float)h;
+  for (int a = 0; a < 3; ++a) G.dims[a] = d[a];
+  G.ncells = d[0] * d[1] * d[2];
+  *gi = G;
+}
+
+// Cell coordinates and cell faces are computed in FP64 so that rounding
+// cannot move a point across a face by more than a negligible fraction of a
+// cell, whatever the offset of the cloud from the origin.
+__device__ inline int cell_coord(float p, float lo, float h, int dim) {
+  const double u = floor(((double)p - (double)lo) / (double)h);
+  const int c = u < 0.0 ? 0 : (u >= (double)dim ? dim - 1 : (int)u);
+  return c;
+}
+
+__global__ __launch_bounds__(256) void grid_count_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                         const float* __restrict__ Zc, int n,
+                                                         const GridInfo* __restrict__ gi, int* __restrict__ cell_of,
+                                                         int* __restrict__ counts) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const GridInfo& G = *gi;
+  const int cx = cell_coord(X[i], G.lo[0], G.h, G.dims[0]);
+  const int cy = cell_coord(Y[i], G.lo[1], G.h, G.dims[1]);
+  const int cz = cell_coord(Zc[i], G.lo[2], G.h, G.dims[2]);
+  const int c = (cz * G.dims[1] + cy) * G.dims[0] + cx;
+  cell_of[i] = c;
+  atomicAdd(&counts[c], 1);
+}
+
+// Exclusive scan of counts[0, m) into starts[0, m], in three passes.
+__global__ __launch_bounds__(SCAN_B) void scan_local_kernel(const int* __restrict__ in, int m, int* __restrict__ out,
+                                                            int* __restrict__ bsum) {
+  __shared__ int s[SCAN_B];
+  const int i = blockIdx.x * SCAN_B + threadIdx.x;
+  const int v = i < m ? in[i] : 0;
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < SCAN_B; off <<= 1) {
+    const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < m) out[i] = s[threadIdx.x] - v;
+  if (threadIdx.x == SCAN_B - 1) bsum[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(int* __restrict__ bsum, int nb) {
+  // serial over block sums in one thread per 1024-chunk, nb is small
+  if (threadIdx.x != 0) return;
+  int acc = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int v = bsum[b];
+    bsum[b] = acc;
+    acc += v;
+  }
+  bsum[nb] = acc;
+}
+
+__global__ __launch_bounds__(SCAN_B) void scan_add_kernel(int* __restrict__ out, int m, const int* __restrict__ bsum,
+                                                          int nb) {
+  const int i = blockIdx.x * SCAN_B + threadIdx.x;
+  if (i < m) out[i] += bsum[blockIdx.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = bsum[nb];
+}
+
+__global__ __launch_bounds__(256) void grid_scatter_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                           const float* __restrict__ Zc, int n,
+                                                           const int* __restrict__ cell_of,
+                                                           const int* __restrict__ starts, int* __restrict__ cursor,
+                                                           float4* __restrict__ spts) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int c = cell_of[i];
+  const int pos = starts[c] + atomicAdd(&cursor[c], 1);
+  spts[pos] = make_float4(X[i], Y[i], Zc[i], __int_as_float(i));
+}
+
+__device__ inline bool key_less(float d, int i, float bd, int bi) { return d < bd || (d == bd && i < bi); }
+
+// Writes the k neighbour indices of every point (row = original index,
+// sorted by key; -1 where fewer than k finite points exist).
+template <int KC>
+__global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
+                                                         const GridInfo* __restrict__ gi, int n, int k,
+                                                         int32_t* __restrict__ idx_out) {
+  const int t = blockIdx.x * GQ_BT + threadIdx.x;
+  if (t >= n) return;  // no barriers below
+  const GridInfo G = *gi;
+  const float4 q = spts[t];
+  const int qi = __float_as_int(q.w);
+  const float qv[3] = {q.x, q.y, q.z};
+  int c[3];
+  for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
+  float bd[KC];
+  int bi[KC];
+#pragma unroll
+  for (int s = 0; s < KC; ++s) {
+    bd[s] = (s < KC - k) ? -INFINITY : INFINITY;
+    bi[s] = -1;
+  }
+  const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
+  for (int r = 0; r <= rmax; ++r) {
+    for (int dz = -r; dz <= r; ++dz) {
+      const int cz = c[2] + dz;
+      if (cz < 0 || cz >= G.dims[2]) continue;
+      for (int dy = -r; dy <= r; ++dy) {
+        const int cy = c[1] + dy;
+        if (cy < 0 || cy >= G.dims[1]) continue;
+        const bool inner = (abs(dz) < r) && (abs(dy) < r);
+        for (int dx = -r; dx <= r; dx += (inner && r > 0) ? 2 * r : 1) {
+          const int cx = c[0] + dx;
+          if (cx < 0 || cx >= G.dims[0]) continue;
+          const int cell = (cz * G.dims[1] + cy) * G.dims[0] + cx;
+          const int p1 = starts[cell + 1];
+          for (int p = starts[cell]; p < p1; ++p) {
+            const float4 P = spts[p];
+            const int j = __float_as_int(P.w);
+            const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
+            const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+            if (key_less(d2, j, bd[KC - 1], bi[KC - 1])) {
+              float cd = d2;
+              int ci = j;
+#pragma unroll
+              for (int s = 0; s < KC; ++s) {
+                const bool sw = key_less(cd, ci, bd[s], bi[s]);
+                const float td = bd[s];
+                const int ti = bi[s];
+                bd[s] = sw ? cd : td;
+                bi[s] = sw ? ci : ti;
+                cd = sw ? td : cd;
+                ci = sw ? ti : ci;
+              }
+            }
+          }
+        }
+      }
+    }
+    // distance from the query to any cell outside the searched cube
+    double lb = INFINITY;
+    bool all = true;
+    for (int a = 0; a < 3; ++a) {
+      if (c[a] - r > 0) {
+        lb = fmin(lb, (double)qv[a] - ((double)G.lo[a] + (double)(c[a] - r) * (double)G.h));
+        all = false;
+      }
+      if (c[a] + r < G.dims[a] - 1) {
+        lb = fmin(lb, ((double)G.lo[a] + (double)(c[a] + r + 1) * (double)G.h) - (double)qv[a]);
+        all = false;
+      }
+    }
+    if (all) break;
+    // margin: 1e-3 of a cell for the face, 1e-5 relative for the float32 key
+    const double lbs = lb - 1e-3 * (double)G.h;
+    if (lbs > 0.0 && (double)bd[KC - 1] * 1.00001 < lbs * lbs) break;
+  }
+  for (int s = 0; s < k; ++s) idx_out[(int64_t)qi * k + s] = bi[KC - k + s];
+}
+
+// Curvature from the neighbour lists (FP64 covariance, 1/k, centred).
+__global__ __launch_bounds__(256) void curvature_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                        const float* __restrict__ Zc, int n, int k,
+                                                        const int32_t* __restrict__ idx, float* __restrict__ a_out) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int32_t* nb = idx + (int64_t)q * k;
+  bool missing = false;
+  double m[3] = {0, 0, 0};
+  for (int s = 0; s < k; ++s) {
+    const int id = nb[s];
+    if (id < 0) {
+      missing = true;
+      continue;
+    }
+    m[0] += (double)X[id];
+    m[1] += (double)Y[id];
+    m[2] += (double)Zc[id];
+  }
+  if (missing) {
+    a_out[q] = NAN;
+    return;
+  }
+  const double invk = 1.0 / (double)k;
+  for (int a = 0; a < 3; ++a) m[a] *= invk;
+  double C[6] = {0, 0, 0, 0, 0, 0};
+  for (int s = 0; s < k; ++s) {
+    const int id = nb[s];
+    const double ex = (double)X[id] - m[0], ey = (double)Y[id] - m[1], ez = (double)Zc[id] - m[2];
+    C[0] += ex * ex;
+    C[1] += ey * ey;
+    C[2] += ez * ez;
+    C[3] += ex * ey;
+    C[4] += ex * ez;
+    C[5] += ey * ez;
+  }
+  for (int c = 0; c < 6; ++c) C[c] *= invk;
+  double lam[3];
+  eig_psd3(C, lam);
+  const double tr = C[0] + C[1] + C[2];
+  a_out[q] = (tr > 0.0) ? (float)(lam[2] / tr) : 0.f;
+}
+
+int grid_max_cells(int n) {
+  int m = 1024;
+  while (m < 2 * n && m < (1 << 24)) m <<= 1;
+  return m;
+}
+
+size_t grid_knn_workspace(int n, int k) {
+  const int max_cells = grid_max_cells(n);
+  const int nb = (max_cells + SCAN_B - 1) / SCAN_B;
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
+  add(sizeof(GridInfo));
+  add(sizeof(int) * (size_t)n);            // cell_of
+  add(sizeof(int) * (size_t)max_cells);    // counts
+  add(sizeof(int) * (size_t)max_cells);    // cursor
+  add(sizeof(int) * ((size_t)max_cells + 1));  // starts
+  add(sizeof(int) * ((size_t)nb + 1));     // block sums
+  add(sizeof(float4) * (size_t)n);         // sorted points
+  add(sizeof(int32_t) * (size_t)n * k);    // neighbour lists
+  return b;
+}
+
+hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n, int k, float* a_out,
+                           int32_t* idx_out, void* ws, hipStream_t st) {
+  const int max_cells = grid_max_cells(n);
+  const int nb = (max_cells + SCAN_B - 1) / SCAN_B;
+  char* p = (char*)ws;
+  auto take = [&](size_t bytes) {
+    char* r = p;
+    p += (bytes + 255) & ~size_t(255);
+    return (void*)r;
+  };
+  GridInfo* gi = (GridInfo*)take(sizeof(GridInfo));
+  int* cell_of = (int*)take(sizeof(int) * (size_t)n);
+  int* counts = (int*)take(sizeof(int) * (size_t)max_cells);
+  int* cursor = (int*)take(sizeof(int) * (size_t)max_cells);
+  int* starts = (int*)take(sizeof(int) * ((size_t)max_cells + 1));
+  int* bsum = (int*)take(sizeof(int) * ((size_t)nb + 1));
+  float4* spts = (float4*)take(sizeof(float4) * (size_t)n);
+  int32_t* nbr = (int32_t*)take(sizeof(int32_t) * (size_t)n * k);
+  int32_t* lists = idx_out ? idx_out : nbr;
+  const dim3 gn((n + 255) / 256), b256(256);
+  hipLaunchKernelGGL(grid_setup_kernel, dim3(1), dim3(1024), 0, st, x, y, z, n, max_cells, gi);
+  if (hipError_t e = launch_fill_i(counts, max_cells, st)) return e;
+  if (hipError_t e = launch_fill_i(cursor, max_cells, st)) return e;
+  hipLaunchKernelGGL(grid_count_kernel, gn, b256, 0, st, x, y, z, n, gi, cell_of, counts);
+  hipLaunchKernelGGL(scan_local_kernel, dim3(nb), dim3(SCAN_B), 0, st, counts, max_cells, starts, bsum);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(64), 0, st, bsum, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(SCAN_B), 0, st, starts, max_cells, bsum, nb);
+  hipLaunchKernelGGL(grid_scatter_kernel, gn, b256, 0, st, x, y, z, n, cell_of, starts, cursor, spts);
+  const dim3 gq((n + GQ_BT - 1) / GQ_BT), bq(GQ_BT);
+  if (k <= 8)
+    hipLaunchKernelGGL(grid_knn_kernel<8>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+  else if (k <= 16)
+    hipLaunchKernelGGL(grid_knn_kernel<16>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+  else if (k <= 24)
+    hipLaunchKernelGGL(grid_knn_kernel<24>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+  else
+    hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+  if (a_out) hipLaunchKernelGGL(curvature_kernel, gn, b256, 0, st, x, y, z, n, k, lists, a_out);
+  return hipGetLastError();
+}
+
+}  // namespace sgr

@@ -118,6 +118,11 @@ hipError_t launch_adjoint(const AdjArgs& A, int R, double* fsum_tmp, hipStream_t
 hipError_t launch_fill(double* p, int n, double v, hipStream_t st);
 hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_identity_pose(double* pose, hipStream_t st);
+hipError_t launch_fill_i(int* p, int n, hipStream_t st);
+int grid_max_cells(int n);
+size_t grid_knn_workspace(int n, int k);
+hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n, int k, float* a_out,
+                           int32_t* idx_out, void* ws, hipStream_t st);
 
 hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, hipStream_t st);

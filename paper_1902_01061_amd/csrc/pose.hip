@@ -210,6 +210,16 @@ __global__ void fill_f_kernel(float* __restrict__ p, int64_t n, float v) {
   if (i < n) p[i] = v;
 }
 
+__global__ void fill_i_kernel(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+hipError_t launch_fill_i(int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(fill_i_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
 __global__ void identity_pose_kernel(double* __restrict__ pose) {
   const int e = threadIdx.x;
   if (e < 13) pose[e] = (e == 0 || e == 1 || e == 5 || e == 9) ? 1.0 : 0.0;

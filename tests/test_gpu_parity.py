@@ -226,3 +226,26 @@ def test_error_codes(sg, ctx):
     with pytest.raises(sg.SgrError) as e:   # all curvatures 0: no similarity spread
         ctx.register(sg.Cloud(flat), sg.Cloud(flat), sg.Params(k=4, E=3))
     assert e.value.code == -2
+
+
+def _adversarial_clouds():
+    rng = np.random.default_rng(17)
+    g = np.stack(np.meshgrid(np.arange(12), np.arange(11), np.arange(7)), -1).reshape(-1, 3).astype(np.float32)
+    yield "lattice (exact ties)", g
+    yield "far from origin", (rng.normal(size=(3000, 3)) * 0.01 + 1.0e4).astype(np.float32)
+    clus = np.concatenate([rng.normal(size=(2500, 3)) * 0.05, rng.uniform(-50, 50, size=(40, 3))]).astype(np.float32)
+    yield "cluster + far outliers", clus
+    dup = rng.normal(size=(800, 3)).astype(np.float32)
+    yield "duplicated points", np.concatenate([dup, dup, dup[:300]])
+    plane = np.stack([rng.uniform(-1, 1, 2000), rng.uniform(-1, 1, 2000), np.zeros(2000)], 1).astype(np.float32)
+    yield "plane", plane
+    line = np.stack([rng.uniform(0, 5, 1500), np.zeros(1500), np.zeros(1500)], 1).astype(np.float32)
+    yield "line", line
+
+
+@pytest.mark.parametrize("k", [8, 24])
+def test_knn_adversarial_inputs_match_bruteforce(sg, ctx, k):
+    for name, P in _adversarial_clouds():
+        idx = ctx.knn(sg.Cloud(P), k).cpu().numpy()
+        ref_idx = O.knn_c(P, k)
+        assert (idx == ref_idx).all(), name

@@ -268,3 +268,28 @@ def test_c_oracle_matches_numpy():
         f2, U2 = O.forces_c(pr.tmpl, S, 42.0)
         np.testing.assert_allclose(f2, f1, rtol=1e-12, atol=1e-12 * np.abs(f1).max())
         assert U2 == pytest.approx(U1, rel=1e-12)
+
+
+def test_residual_closed_forms():
+    """RMSE with correspondences of a cloud shifted by a known vector is the
+    shift length; the one-sided NN RMSE of a cloud against itself is 0 and
+    against a copy shifted by a tenth of the smallest point spacing is that
+    shift; pose_rmse of the generating transform's inverse is 0."""
+    rng = np.random.default_rng(13)
+    X = rng.normal(size=(200, 3))
+    d = np.array([0.3, -0.4, 1.2])
+    ident = O.Pose.identity()
+    assert O.residual_corr(ident, X + d, X, np.arange(200)) == pytest.approx(np.linalg.norm(d), rel=1e-14)
+    corr = np.arange(200)
+    corr[::2] = -1                                   # half without counterpart
+    assert O.residual_corr(ident, X + d, X, corr) == pytest.approx(np.linalg.norm(d), rel=1e-14)
+    assert O.residual_nn(ident, X, X) == 0.0
+    from scipy.spatial.distance import pdist
+    h = 0.1 * pdist(X).min()
+    e = np.array([1.0, 2.0, 2.0]) / 3.0
+    assert O.residual_nn(ident, X + h * e, X) == pytest.approx(h, rel=1e-12)
+    R = rot_axis_angle([1, 1, 0], 33.0)
+    s, t = 1.3, np.array([0.5, 0.1, -2.0])
+    Y = s * X @ R.T + t
+    inv = O.Pose(1 / s, R.T, -(R.T @ t) / s)
+    assert O.pose_rmse(inv, Y, s, R, t) <= 1e-14 * np.abs(X).max()
