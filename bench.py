@@ -31,6 +31,47 @@ LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one VALU issue slot
 # p = 1: r (3) + similarity exponent (3) + weight (1) + accumulate (6) = 13;
 # p = 2: adds q = |r|^2 + eps^2 (6) and the distance factor (1) = 20.
 FLOPS_PER_PAIR = {1.0: 13, 2.0: 20}
+TILES = os.path.join(ROOT, "paper_1902_01061_amd", "tiles_gfx950.json")
+COUNTERS = os.path.join(ROOT, "profiles", "force_kernel_scan_32400x36000_counters.json")
+FORCE_SOURCES = ["paper_1902_01061_amd/csrc/force.hip", "paper_1902_01061_amd/csrc/common.h"]
+
+
+def _log2_bucket(n: int) -> int:
+    return n.bit_length() - 1
+
+
+def _launch_of(path, M, N, p):
+    """The launch shape the library will use for (M, N, p) from a tile table."""
+    pm = 1 if p == 1.0 else (3 if p == 3.0 else 0)
+    with open(path) as f:
+        tab = json.load(f)
+    for e in tab["entries"]:
+        if (e["m_bucket"], e["n_bucket"], e["p_mode"]) == (_log2_bucket(M), _log2_bucket(N), pm):
+            return {"R": e["R"], "blocks_per_cu": e["blocks_per_cu"], "variant": e["variant"]}
+    return None
+
+
+def _sources_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in FORCE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _traffic(launch):
+    """HBM bytes per launch of the force kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or
+    None when the kernel source or its launch shape changed since."""
+    if launch is None or not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as f:
+        c = json.load(f)
+    if c.get("sources_sha256") != _sources_digest() or c.get("launch") != launch:
+        return None
+    return c["traffic_bytes_per_launch"]
 
 
 def log(msg: str) -> None:
@@ -220,8 +261,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch / adjoint / mixed / scene legs")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tiles-cache", default="", help="tile table file: loaded if present, else written after tuning")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-tune the force kernel launch shape instead of loading the committed tile table")
+    ap.add_argument("--save-tiles", default="", help="write the tile table here after tuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (traffic-counter calibration)")
     args = ap.parse_args()
@@ -260,15 +302,16 @@ def main() -> int:
 
     a_t, mom_t = ctx.descriptors(tm, k)
     a_r, mom_r = ctx.descriptors(rf, k)
-    tuned = None
-    if args.tiles_cache and os.path.exists(args.tiles_cache):
-        ctx.load_tiles(args.tiles_cache)
-        log(f"tile table loaded from {args.tiles_cache}")
-    elif not args.no_autotune:
-        tuned, tuned_ms = ctx.autotune(tm, a_t, rf, a_r, mom_t, mom_r, prm, reps=5)
+    if args.autotune or not os.path.exists(TILES):
+        tuned, tuned_ms = ctx.autotune(tm, a_t, rf, a_r, mom_t, mom_r, prm, reps=10)
         log(f"autotuned force kernel launch: R={tuned[0]} blocks/CU={tuned[1]} variant={tuned[2]} ({tuned_ms:.4f} ms)")
-        if args.tiles_cache:
-            ctx.save_tiles(args.tiles_cache)
+        if args.save_tiles:
+            ctx.save_tiles(args.save_tiles)
+        launch = {"R": tuned[0], "blocks_per_cu": tuned[1], "variant": tuned[2]}
+    else:
+        ctx.load_tiles(TILES)
+        log(f"tile table loaded from {os.path.relpath(TILES, ROOT)}")
+        launch = _launch_of(TILES, M, N, p)
     for w in range(args.warmup):
         pose.copy_(ident)
         ctx.register(tm, rf, prm, pose=pose)
@@ -337,9 +380,8 @@ def main() -> int:
                      "kernel": "force_kernel", "ms_per_launch": k_ms, "pairs_per_launch": M * N,
                      "flops_per_pair": fpp, "pairs_per_s": k_pairs},
     }
-    if tuned is not None:
-        out["roofline"]["launch"] = {"R": tuned[0], "blocks_per_cu": tuned[1],
-                                     "variant": ["lds", "scalar-loads"][tuned[2]]}
+    out["roofline"]["launch"] = launch
+    out["roofline"]["traffic"] = _traffic(launch)
     if not args.no_extras:
         # the same registration with the mixed-precision force (bf16 matrix cores)
         prm_m = sg.Params(p=p, k=k, E=E, flags=2)

@@ -252,9 +252,9 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   cv.take<float>(ref_total);
   cv.take<double>((size_t)n_items * WR_STRIDE);
   cv.take<double>(B);
-  size_t gws_size = 0;
-  for (int c = 0; c < ncl; ++c) gws_size = std::max(gws_size, grid_knn_workspace((int)in.clouds[c]->n, prm->k));
-  cv.take<char>(gws_size);
+  int64_t perm_total = 0;
+  for (int r = 0; r < B; ++r) perm_total += Ms[r];
+  cv.take<int>(perm_total);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   CloudDesc* d_cds = w.take<CloudDesc>(ncl);
@@ -270,7 +270,7 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   float* d_lw = w.take<float>(ref_total);
   double* d_wpart = w.take<double>((size_t)n_items * WR_STRIDE);
   double* d_energy = w.take<double>(B);
-  char* d_gws = w.take<char>(gws_size);
+  int* d_perm = w.take<int>(perm_total);
 
   for (int c = 0; c < ncl; ++c)
     cds[c] = CloudDesc{in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, d_a + a_off[c], (int)in.clouds[c]->n, 0};
@@ -288,6 +288,13 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
     regs[r].M = (int)Ms[r];
     regs[r].N = (int)Ns[r];
   }
+  {
+    int64_t off = 0;
+    for (int r = 0; r < B; ++r) {
+      regs[r].perm = d_perm + off;
+      off += Ms[r];
+    }
+  }
   HIPCHK(hipMemcpyAsync(d_cds, cds.data(), sizeof(CloudDesc) * ncl, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_kb, kblocks.data(), sizeof(int2) * kblocks.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_prep, preps.data(), sizeof(PrepDesc) * B, hipMemcpyHostToDevice, st));
@@ -295,14 +302,14 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   HIPCHK(hipMemcpyAsync(d_regs, regs.data(), sizeof(RegDesc) * B, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_items, items.data(), sizeof(int4) * n_items, hipMemcpyHostToDevice, st));
 
-  // descriptors: one grid kNN per cloud (they share the grid workspace in
-  // stream order)
-  for (int c = 0; c < ncl; ++c)
-    HIPCHK(launch_grid_knn(in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, (int)in.clouds[c]->n, prm->k,
-                           d_a + a_off[c], nullptr, d_gws, st));
+  // descriptors of every cloud in one brute-force launch: with hundreds of
+  // small clouds a single launch keeps the chip busy, where one grid search
+  // per cloud would be a long chain of small launches
+  HIPCHK(launch_knn_desc_batch(d_cds, d_kb, (int)kblocks.size(), prm->k, st));
   HIPCHK(launch_moments_batch(d_cds, ncl, d_mom, st));
   HIPCHK(launch_prepare_batch(d_prep, B, prep_of(prm), d_dv, st));
   HIPCHK(launch_pack_batch(d_prep, d_b2r, (int)blk2reg.size(), d_dv, d_ref4, d_lw, st));
+  HIPCHK(launch_partition_batch(d_regs, B, d_dv, st));
   if (R0_multistart) HIPCHK(launch_init_multistart(R0_multistart, B, d_mom + 10 * in.tm_cloud[0], poses, st));
 
   const int grid = std::min(n_items, 8 * ctx->n_cu);
@@ -433,6 +440,7 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   cv.take<float>(pad_n(N));
   cv.take<double>((size_t)T.nblk * WR_STRIDE);
   if (f_out) cv.take<double>((size_t)T.n_chunks * M * 3);
+  cv.take<int>(M);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   Derived* dv = w.take<Derived>(1);
@@ -440,11 +448,13 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   float* lw = w.take<float>(pad_n(N));
   double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
   double* fpart = f_out ? w.take<double>((size_t)T.n_chunks * M * 3) : nullptr;
+  int* perm = w.take<int>(M);
 
   HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
+  HIPCHK(launch_partition(a_t, M, dv, perm, st));
   ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, (const double*)in, dv, M, N,
-              T.chunk_len, T.n_chunks, t, 0.0, wpart, fpart};
+              T.chunk_len, T.n_chunks, t, 0.0, wpart, fpart, perm};
   if (is_mixed(prm))
     HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
   else
@@ -479,6 +489,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   cv.take<float>(pad_n(N));
   cv.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
   cv.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
+  cv.take<int>(M);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   float* aX = w.take<float>(N);
@@ -489,6 +500,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   float* lw = w.take<float>(pad_n(N));
   double* wpart = w.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
   char* gws = w.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
+  int* perm = w.take<int>(M);
 
   HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, prm->k, aX, nullptr, gws, st));
   HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, prm->k, aY, nullptr, gws, st));
@@ -496,6 +508,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom, st));
   HIPCHK(launch_prepare(aX, ref->m, N, aY, tmpl->m, M, mom, mom + 10, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, aX, ref->m, N, dv, ref4, lw, st));
+  HIPCHK(launch_partition(aY, M, dv, perm, st));
 
   auto loop = [&](hipStream_t s) -> int {
     for (int t = 0; t < prm->E; ++t) {
@@ -504,7 +517,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
       const bool wu = !mixed && (stats != nullptr || last);
       const Tiles& Tt = mixed ? TM : T;
       ForceArgs A{tmpl->x, tmpl->y, tmpl->z, aY, tmpl->m, ref4, lw, (const double*)inout, dv, M, N,
-                  Tt.chunk_len, Tt.n_chunks, t, 0.0, wpart, nullptr};
+                  Tt.chunk_len, Tt.n_chunks, t, 0.0, wpart, nullptr, perm};
       if (mixed)
         HIPCHK(launch_force_mixed(A, false, s));
       else
@@ -625,6 +638,7 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
       cv.take<Derived>(1);
       cv.take<float4>(pad_n(N));
       cv.take<float>(pad_n(N));
+      cv.take<int>(M);
       cv.take<double>((size_t)T.nblk * WR_STRIDE);
       need = std::max(need, cv.off);
     }
@@ -634,10 +648,12 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   Derived* dv = w.take<Derived>(1);
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
+  int* perm = w.take<int>(M);
   const size_t wp_off = w.off;
   HIPCHK(launch_identity_pose(pose, st));
   HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
+  HIPCHK(launch_partition(a_t, M, dv, perm, st));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -650,7 +666,7 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
         Carve wc{ctx->ws, wp_off};
         double* wpart = wc.take<double>((size_t)T.nblk * WR_STRIDE);
         ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, pose, dv, M, N,
-                    T.chunk_len, T.n_chunks, prm->E - 1, 0.0, wpart, nullptr};
+                    T.chunk_len, T.n_chunks, prm->E - 1, 0.0, wpart, nullptr, perm};
         HIPCHK(launch_force(A, T.R, pm, false, false, st, T.sm));
         HIPCHK(hipEventRecord(e0, st));
         for (int r = 0; r < reps; ++r) HIPCHK(launch_force(A, T.R, pm, false, false, st, T.sm));
@@ -748,6 +764,7 @@ int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
   cv.take<float>(pad_n(N));
   cv.take<double>((size_t)T.nblk * WR_STRIDE);
   cv.take<double>((size_t)T.n_chunks * M * 3);
+  cv.take<int>(M);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   double* mom_t = w.take<double>(16);
@@ -757,12 +774,14 @@ int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
   float* lw = w.take<float>(pad_n(N));
   double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
   double* fpart = w.take<double>((size_t)T.n_chunks * M * 3);
+  int* perm = w.take<int>(M);
   HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom_t, st));
   HIPCHK(launch_identity_pose(pose, st));
   HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
+  HIPCHK(launch_partition(a_t, M, dv, perm, st));
   ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, pose, dv, M, N,
-              T.chunk_len, T.n_chunks, 0, G, wpart, f_out ? fpart : nullptr};
+              T.chunk_len, T.n_chunks, 0, G, wpart, f_out ? fpart : nullptr, perm};
   if (is_mixed(prm))
     HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
   else
@@ -835,6 +854,7 @@ struct sgr_plan {
   float* lw = nullptr;
   double* wpart = nullptr;
   double* fpart = nullptr;
+  int* perm = nullptr;
 };
 
 int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
@@ -864,6 +884,7 @@ int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const
   cv.take<float>(pad_n(N));
   cv.take<double>((size_t)pl->T.nblk * WR_STRIDE);
   cv.take<double>((size_t)pl->T.n_chunks * M * 3);
+  cv.take<int>(M);
   if (hipMalloc(&pl->mem, cv.off) != hipSuccess) {
     (void)hipGetLastError();
     delete pl;
@@ -875,10 +896,12 @@ int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const
   pl->lw = w.take<float>(pad_n(N));
   pl->wpart = w.take<double>((size_t)pl->T.nblk * WR_STRIDE);
   pl->fpart = w.take<double>((size_t)pl->T.n_chunks * M * 3);
+  pl->perm = w.take<int>(M);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e1 = launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), pl->dv, st);
   hipError_t e2 = e1 == hipSuccess ? launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, pl->dv, pl->ref4, pl->lw, st)
                                    : e1;
+  if (e2 == hipSuccess) e2 = launch_partition(a_t, M, pl->dv, pl->perm, st);
   if (e2 != hipSuccess) {
     (void)hipFree(pl->mem);
     delete pl;
@@ -900,7 +923,7 @@ int sgr_plan_destroy(sgr_plan* pl) {
 static ForceArgs plan_args(sgr_plan* pl, int t, double G, const sgr_pose* pose, bool with_f) {
   return ForceArgs{pl->tmpl.x, pl->tmpl.y, pl->tmpl.z, pl->a_t, pl->tmpl.m, pl->ref4, pl->lw,
                    (const double*)pose, pl->dv, (int)pl->tmpl.n, (int)pl->ref.n, pl->T.chunk_len, pl->T.n_chunks,
-                   t, G, pl->wpart, with_f ? pl->fpart : nullptr};
+                   t, G, pl->wpart, with_f ? pl->fpart : nullptr, pl->perm};
 }
 
 int sgr_plan_force(sgr_plan* pl, int t, double G, const sgr_pose* pose, double* wrench_out, float* f_out,

@@ -35,7 +35,11 @@ struct Derived {
   double p;
   double g_mode;
   double expand_ok;  // 1: the expanded similarity exponent 2 b_i b_j - b_j^2 + lw_j stays
-                     //    below 2^64 for every pair (b centred at the mean curvature)
+                     //    below 64 for every pair (b centred at the mean curvature)
+  double lw_max;     // largest log2 weight of the reference (0 if none is positive)
+  double Vw[9];      // right singular vectors of the last cross-covariance (warm start)
+  int32_t n_safe;    // template points [perm[0], perm[n_safe]) admit the expanded exponent
+  int32_t pad2;
   int32_t status;    // 0 ok; bit flags set by the update kernel
   int32_t pad;
 };
@@ -69,14 +73,17 @@ SGR_HD void cross3(const double a[3], const double b[3], double o[3]) {
 // column-major in the sense u[k][*] = k-th left singular vector.  A column of
 // A that collapses to zero leaves its u[k] undefined (set to 0); callers
 // only use the vectors of non-zero singular values.
-SGR_HD void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3][3]) {
+SGR_HD void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3][3], const double* V0 = nullptr) {
   double a[3][3];  // a[col][row]
   double vv[3][3]; // vv[col][row]
+  // start from V0 (row-major, columns = right singular vectors of a nearby
+  // matrix) when given: A V0 is then nearly column-orthogonal and the
+  // rotations below converge in one or two sweeps
   for (int c = 0; c < 3; ++c)
-    for (int r = 0; r < 3; ++r) {
-      a[c][r] = A_in[r * 3 + c];
-      vv[c][r] = (r == c) ? 1.0 : 0.0;
-    }
+    for (int r = 0; r < 3; ++r) vv[c][r] = V0 ? V0[r * 3 + c] : ((r == c) ? 1.0 : 0.0);
+  for (int c = 0; c < 3; ++c)
+    for (int r = 0; r < 3; ++r)
+      a[c][r] = A_in[r * 3 + 0] * vv[c][0] + A_in[r * 3 + 1] * vv[c][1] + A_in[r * 3 + 2] * vv[c][2];
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0;
     for (int pq = 0; pq < 3; ++pq) {
@@ -138,9 +145,19 @@ SGR_HD void eig_psd3(const double S6[6], double lam[3]) {
 // singular pairs: R = v1 u1^T + v2 u2^T + (v1 x v2)(u1 x u2)^T, which is
 // the same matrix and needs no sign bookkeeping.  Returns false if C has
 // rank < 2 (the rotation is then not determined).
-SGR_HD bool kabsch_rot(const double C[9], double R[9]) {
+SGR_HD bool kabsch_rot(const double C[9], double R[9], double* Vwarm = nullptr) {
   double sv[3], u[3][3], v[3][3];
-  svd3(C, sv, u, v);
+  svd3(C, sv, u, v, Vwarm);
+  if (Vwarm) {
+    // keep the (sorted) right singular vectors, as a proper rotation, for the next call
+    double v3[3];
+    cross3(v[0], v[1], v3);
+    for (int r = 0; r < 3; ++r) {
+      Vwarm[r * 3 + 0] = v[0][r];
+      Vwarm[r * 3 + 1] = v[1][r];
+      Vwarm[r * 3 + 2] = v3[r];
+    }
+  }
   if (!(sv[1] > 0.0) || !(sv[1] > sv[0] * 1e-14)) return false;
   double u3[3], v3[3];
   cross3(u[0], u[1], u3);

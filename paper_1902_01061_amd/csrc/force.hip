@@ -102,8 +102,12 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   D.g_mode = (double)P.g_mode;
   {
     const double bmax = mx[0] * D.bscale;
-    D.expand_ok = (bmax * bmax + fmax(mx[1], 0.0) <= 64.0) ? 1.0 : 0.0;
+    D.lw_max = fmax(mx[1], 0.0);
+    D.expand_ok = (bmax * bmax + D.lw_max <= 64.0) ? 1.0 : 0.0;
   }
+  for (int e = 0; e < 9; ++e) D.Vw[e] = (e % 4 == 0) ? 1.0 : 0.0;
+  D.n_safe = 0;
+  D.pad2 = 0;
   if (!(D.lamX > 0) || !(D.lamY0 > 0) || !(D.sigma > 0) || !(D.Z > 0) || !(D.Mtot > 0) ||
       (P.g_mode == 1 && !(abar > 0)))
     st |= ST_DEGENERATE;
@@ -131,6 +135,59 @@ __global__ __launch_bounds__(1024) void prepare_batch_kernel(const PrepDesc* __r
   __shared__ double abar_s;
   const PrepDesc& g = d[blockIdx.x];
   prepare_body(g.aX, g.wX, g.N, g.aY, g.mY, g.M, g.mom_t, g.mom_r, P, outs + blockIdx.x, lds, red_max, &abar_s);
+}
+
+// Stable partition of the template points: those whose expanded similarity
+// exponent stays below 64 for every reference point (b_i^2 + lw_max <= 64)
+// first, the rest after; n_safe counts the first group.  A block of the
+// force kernel whose points all lie in the first group can use the
+// one-FMA exponent.  One block, deterministic.
+__device__ inline void partition_body(const float* __restrict__ aY, int M, Derived* __restrict__ dv,
+                                      int* __restrict__ perm, int* s_cnt) {
+  const Derived& D = *dv;
+  const int C = (M + 1023) / 1024;
+  const int lo = min(M, (int)threadIdx.x * C), hi = min(M, lo + C);
+  auto safe = [&](int i) {
+    const double b = (double)(float)(((double)aY[i] - D.abar) * D.bscale);
+    return b * b + D.lw_max <= 64.0;
+  };
+  int cnt = 0;
+  for (int i = lo; i < hi; ++i) cnt += safe(i) ? 1 : 0;
+  s_cnt[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const int v = s_cnt[t];
+      s_cnt[t] = acc;
+      acc += v;
+    }
+    s_cnt[1024] = acc;
+  }
+  __syncthreads();
+  const int total = s_cnt[1024];
+  int ps = s_cnt[threadIdx.x];
+  int pu = total + (lo - s_cnt[threadIdx.x]);
+  for (int i = lo; i < hi; ++i) {
+    if (safe(i))
+      perm[ps++] = i;
+    else
+      perm[pu++] = i;
+  }
+  if (threadIdx.x == 0) dv->n_safe = total;
+}
+
+__global__ __launch_bounds__(1024) void partition_kernel(const float* __restrict__ aY, int M, Derived* __restrict__ dv,
+                                                         int* __restrict__ perm) {
+  __shared__ int s_cnt[1025];
+  partition_body(aY, M, dv, perm, s_cnt);
+}
+
+__global__ __launch_bounds__(1024) void partition_batch_kernel(const RegDesc* __restrict__ regs,
+                                                               Derived* __restrict__ dvs) {
+  __shared__ int s_cnt[1025];
+  const RegDesc& g = regs[blockIdx.x];
+  partition_body(g.aY, g.M, dvs + blockIdx.x, g.perm, s_cnt);
 }
 
 // Reference in the layout the pair loop reads: float4 (x - xbar, b) and
@@ -213,7 +270,8 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
   int ii[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = iblk * F_BT * R + r * F_BT + threadIdx.x;
+    const int ip = iblk * F_BT * R + r * F_BT + threadIdx.x;
+    const int i = ip < A.M ? (A.perm ? A.perm[ip] : ip) : A.M;
     ii[r] = i;
     if (i < A.M) {
       const double ex = (double)A.y0x[i] - D.ybar0[0], ey = (double)A.y0y[i] - D.ybar0[1],
@@ -241,7 +299,8 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
 #pragma unroll
   for (int r = 0; r < R; ++r) t0[r] = tx[r] = ty[r] = tz[r] = tu[r] = 0.0;
   constexpr bool MOM = (PM == 1);
-  const bool expd = MOM && D.expand_ok != 0.0;
+  // expanded exponent: every point of this block must admit it
+  const bool expd = MOM && (D.expand_ok != 0.0 || (A.perm && min(A.M, (iblk + 1) * F_BT * R) <= D.n_safe));
   float al[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) al[r] = 2.f * bi[r];
@@ -428,7 +487,8 @@ __global__ __launch_bounds__(F_BT) void force_batch_kernel(BatchArgs B) {
     const int4 item = B.items[it];  // (registration, template block, chunk, output slot)
     const RegDesc& g = B.regs[item.x];
     ForceArgs A{g.y0x, g.y0y, g.y0z, g.aY, g.mY, B.ref4 + g.ref_off, B.reflw + g.ref_off,
-                B.poses + (int64_t)13 * item.x, B.dvs + item.x, g.M, g.N, B.chunk_len, 0, B.t, 0.0, B.wpart, nullptr};
+                B.poses + (int64_t)13 * item.x, B.dvs + item.x, g.M, g.N, B.chunk_len, 0, B.t, 0.0, B.wpart, nullptr,
+                g.perm};
     force_block<R, PM, WU, false, false>(A, item.y, item.z, item.w, s_ref, s_lw, s_red);
   }
 }
@@ -446,6 +506,16 @@ __global__ __launch_bounds__(256) void reduce_f_kernel(const double* __restrict_
 hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const float* aY, const float* mY, int64_t M,
                           const double* mom_t, const double* mom_r, const PrepParams& P, Derived* out, hipStream_t st) {
   hipLaunchKernelGGL(prepare_kernel, dim3(1), dim3(1024), 0, st, aX, wX, N, aY, mY, M, mom_t, mom_r, P, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_partition(const float* aY, int M, Derived* dv, int* perm, hipStream_t st) {
+  hipLaunchKernelGGL(partition_kernel, dim3(1), dim3(1024), 0, st, aY, M, dv, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_partition_batch(const RegDesc* regs, int B, Derived* dvs, hipStream_t st) {
+  hipLaunchKernelGGL(partition_batch_kernel, dim3(B), dim3(1024), 0, st, regs, dvs);
   return hipGetLastError();
 }
 

@@ -35,6 +35,7 @@ struct ForceArgs {
   double G;             // explicit force constant, or <= 0
   double* wpart;        // [n_blocks][WR_STRIDE]
   double* fpart;        // [n_chunks][M][3] or nullptr
+  const int* perm = nullptr;  // template visiting order (see launch_partition) or nullptr
 };
 
 // A cloud for the batched descriptor kernels.
@@ -75,6 +76,7 @@ struct RegDesc {
   int M, N;
   int wslot0;           // first wrench slot of its items
   int n_items;
+  int* perm;            // template visiting order [M]
 };
 
 struct BatchArgs {
@@ -142,6 +144,8 @@ hipError_t launch_update_batch(const double* wpart, const RegDesc* regs, int B, 
 hipError_t launch_init_multistart(const double* R0, int S, const double* mom_t, double* poses, hipStream_t st);
 hipError_t launch_argmin(const double* v, int n, int32_t* out, hipStream_t st);
 hipError_t launch_force_batch(const BatchArgs& B, int R, int pm, bool want_u, int grid, hipStream_t st);
+hipError_t launch_partition(const float* aY, int M, Derived* dv, int* perm, hipStream_t st);
+hipError_t launch_partition_batch(const RegDesc* regs, int B, Derived* dvs, hipStream_t st);
 hipError_t launch_force_mixed(const ForceArgs& A, bool want_f, hipStream_t st);
 int mixed_points_per_block();
 hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, float* f_out, hipStream_t st);

@@ -74,7 +74,7 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
     double Rk[9];
     if (!ok) {
       st |= ST_NONFINITE;
-    } else if (!kabsch_rot(C, Rk)) {
+    } else if (!kabsch_rot(C, Rk, D.Vw)) {
       st |= ST_SINGULAR;
     } else {
       c = sqrt(D.lamX / (s * s * D.lamY0));
