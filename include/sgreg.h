@@ -169,16 +169,18 @@ int sgr_plan_force(sgr_plan* plan, int t, double G, const sgr_pose* pose, double
 /* Launch shape of the pair-force kernel for the size bucket of (M, N) and
  * the distance-law mode of p (1, 3 or other): R template points per lane
  * (1, 2, 4 or 8), a target of blocks_per_cu blocks of 256 threads per
- * compute unit (the reference is split into chunks to reach it) and the
- * variant (0: reference tiles staged in LDS; 1: read through scalar
+ * compute unit (each template block's reference range is cut into equal
+ * chunks at multiples of 64 points to reach it; without an entry the
+ * target is one wave of resident blocks, from the kernel's occupancy) and
+ * the variant (0: reference tiles staged in LDS; 1: read through scalar
  * loads).  Affects plans and calls created afterwards.  R = 0 removes the
  * entry. */
 int sgr_set_tiles(sgr_ctx* ctx, int64_t M, int64_t N, double p, int R, int blocks_per_cu, int variant);
 
 /* Autotuner: times the pair-force kernel for every launch shape (R in
- * {2, 4, 8}, blocks per CU in {8, 12, 16}, LDS or scalar-load variant)
- * on this pair, `reps` launches each, and stores the fastest in the tile
- * table for the (M, N, p) bucket.  best (host int[3], nullable): R,
+ * {1, 2, 4, 8}, LDS or scalar-load variant, one or two waves of resident
+ * blocks) on this pair, `reps` launches each, and stores the fastest in the
+ * tile table for the (M, N, p) bucket.  best (host int[3], nullable): R,
  * blocks_per_cu, variant; best_ms (host, nullable): its time per launch.
  * Synchronises the stream. */
 int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,

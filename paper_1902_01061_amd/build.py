@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libsgreg.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["descriptors.hip", "force.hip", "pose.hip", "residual.hip", "adjoint.hip", "mixed.hip", "knn_grid.hip", "capi.cpp"]
+SOURCES = ["descriptors.hip", "force.hip", "pose.hip", "residual.hip", "adjoint.hip", "mixed.hip", "knn_grid.hip", "sort.hip", "capi.cpp"]
 # Packed FP32 instructions are disabled for every HIP translation unit.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-ffp-contract=fast", "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include")]

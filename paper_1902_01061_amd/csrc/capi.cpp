@@ -127,6 +127,34 @@ Tiles tiles_for(const sgr_ctx* ctx, int M, int N, const sgr_params* p) {
   return ctx->tiles.pick(M, N, pmode_of(p->p));
 }
 
+// Shape of one FP32 force launch for a single registration: every template
+// block gets n_chunks reference chunks cut at multiples of 64 points, with
+// n_chunks chosen so that the launch is about T.bpc blocks per CU (by
+// default one wave of resident blocks, from the kernel's occupancy).
+// Whole-tile chunks would leave the last wave of blocks partly empty
+// whenever the work is not a multiple of the resident block count.
+// `slots` is the number of wrench slots the launch writes.
+struct FLaunch {
+  int n_chunks = 0, slots = 0;
+};
+
+FLaunch force_shape(const sgr_ctx* ctx, int M, int N, const Tiles& T, int pm) {
+  const int64_t n_iblk = (M + 256 * T.R - 1) / (256 * T.R);
+  const int64_t n_tiles = (N + 255) / 256;  // at least one LDS tile per chunk
+  const int bpc = T.bpc > 0 ? T.bpc : force_blocks_per_cu(T.R, pm, T.sm != 0);
+  const int64_t nc = std::max<int64_t>(1, std::min<int64_t>(n_tiles, (int64_t)bpc * ctx->n_cu / n_iblk));
+  FLaunch L;
+  L.n_chunks = (int)nc;
+  L.slots = (int)(n_iblk * nc);
+  return L;
+}
+
+hipError_t run_force(ForceArgs A, const Tiles& T, const FLaunch& L, int pm, bool wu, bool wf, hipStream_t st) {
+  A.chunk_len = 0;
+  A.n_chunks = L.n_chunks;
+  return launch_force(A, T.R, pm, wu, wf, st, T.sm != 0);
+}
+
 // The packed reference is padded to whole tiles with zero-weight points.
 size_t pad_n(int64_t N) { return (size_t)((N + 255) / 256) * 256; }
 
@@ -255,6 +283,10 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   int64_t perm_total = 0;
   for (int r = 0; r < B; ++r) perm_total += Ms[r];
   cv.take<int>(perm_total);
+  cv.take<float4>(perm_total);
+  cv.take<float2>(perm_total);
+  cv.take<int>(B + 1);
+  cv.take<char>(sort_perm_workspace(perm_total, B));
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   CloudDesc* d_cds = w.take<CloudDesc>(ncl);
@@ -271,6 +303,10 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   double* d_wpart = w.take<double>((size_t)n_items * WR_STRIDE);
   double* d_energy = w.take<double>(B);
   int* d_perm = w.take<int>(perm_total);
+  float4* d_tm4 = w.take<float4>(perm_total);
+  float2* d_tmx = w.take<float2>(perm_total);
+  int* d_poff = w.take<int>(B + 1);
+  char* d_sws = w.take<char>(sort_perm_workspace(perm_total, B));
 
   for (int c = 0; c < ncl; ++c)
     cds[c] = CloudDesc{in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, d_a + a_off[c], (int)in.clouds[c]->n, 0};
@@ -288,12 +324,12 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
     regs[r].M = (int)Ms[r];
     regs[r].N = (int)Ns[r];
   }
-  {
-    int64_t off = 0;
-    for (int r = 0; r < B; ++r) {
-      regs[r].perm = d_perm + off;
-      off += Ms[r];
-    }
+  std::vector<int> poff(B + 1, 0);
+  for (int r = 0; r < B; ++r) {
+    regs[r].perm = d_perm + poff[r];
+    regs[r].tm4 = d_tm4 + poff[r];
+    regs[r].tmx = d_tmx + poff[r];
+    poff[r + 1] = poff[r] + (int)Ms[r];
   }
   HIPCHK(hipMemcpyAsync(d_cds, cds.data(), sizeof(CloudDesc) * ncl, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_kb, kblocks.data(), sizeof(int2) * kblocks.size(), hipMemcpyHostToDevice, st));
@@ -301,6 +337,7 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   HIPCHK(hipMemcpyAsync(d_b2r, blk2reg.data(), sizeof(int) * blk2reg.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_regs, regs.data(), sizeof(RegDesc) * B, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_items, items.data(), sizeof(int4) * n_items, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_poff, poff.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, st));
 
   // descriptors of every cloud in one brute-force launch: with hundreds of
   // small clouds a single launch keeps the chip busy, where one grid search
@@ -309,7 +346,11 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   HIPCHK(launch_moments_batch(d_cds, ncl, d_mom, st));
   HIPCHK(launch_prepare_batch(d_prep, B, prep_of(prm), d_dv, st));
   HIPCHK(launch_pack_batch(d_prep, d_b2r, (int)blk2reg.size(), d_dv, d_ref4, d_lw, st));
-  HIPCHK(launch_partition_batch(d_regs, B, d_dv, st));
+  {
+    const int max_M = (int)*std::max_element(Ms.begin(), Ms.end());
+    HIPCHK(launch_sort_perm_batch(d_regs, B, d_poff, perm_total, max_M, d_perm, d_sws, st));
+    HIPCHK(launch_pack_tmpl_batch(d_regs, B, max_M, d_dv, st));
+  }
   if (R0_multistart) HIPCHK(launch_init_multistart(R0_multistart, B, d_mom + 10 * in.tm_cloud[0], poses, st));
 
   const int grid = std::min(n_items, 8 * ctx->n_cu);
@@ -438,29 +479,43 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   cv.take<Derived>(1);
   cv.take<float4>(pad_n(N));
   cv.take<float>(pad_n(N));
-  cv.take<double>((size_t)T.nblk * WR_STRIDE);
-  if (f_out) cv.take<double>((size_t)T.n_chunks * M * 3);
+  const FLaunch L0 = force_shape(ctx, M, N, T, pmode_of(prm->p));
+  const int nslot = is_mixed(prm) ? T.nblk : L0.slots;
+  const int nch = is_mixed(prm) ? T.n_chunks : L0.n_chunks;
+  cv.take<double>((size_t)nslot * WR_STRIDE);
+  if (f_out) cv.take<double>((size_t)nch * M * 3);
   cv.take<int>(M);
+  cv.take<char>(sort_perm_workspace(M, 1));
+  cv.take<float4>(M);
+  cv.take<float2>(M);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   Derived* dv = w.take<Derived>(1);
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
-  double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
-  double* fpart = f_out ? w.take<double>((size_t)T.n_chunks * M * 3) : nullptr;
+  double* wpart = w.take<double>((size_t)nslot * WR_STRIDE);
+  double* fpart = f_out ? w.take<double>((size_t)nch * M * 3) : nullptr;
   int* perm = w.take<int>(M);
+  char* sws = w.take<char>(sort_perm_workspace(M, 1));
+  float4* tm4 = w.take<float4>(M);
+  float2* tmx = w.take<float2>(M);
 
   HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
-  HIPCHK(launch_partition(a_t, M, dv, perm, st));
+  HIPCHK(launch_sort_perm(a_t, M, perm, sws, st));
+  HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, M, perm, dv, tm4, tmx, st));
   ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, (const double*)in, dv, M, N,
-              T.chunk_len, T.n_chunks, t, 0.0, wpart, fpart, perm};
-  if (is_mixed(prm))
+              T.chunk_len, T.n_chunks, t, 0.0, wpart, fpart, perm, tm4, tmx};
+  int used = T.nblk;
+  if (is_mixed(prm)) {
     HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
-  else
-    HIPCHK(launch_force(A, T.R, pmode_of(prm->p), wrench_out != nullptr, f_out != nullptr, st, T.sm));
-  if (f_out) HIPCHK(launch_reduce_f(fpart, T.n_chunks, M, f_out, st));
-  HIPCHK(launch_update(wpart, T.nblk, (const double*)in, (double*)out, dv, t, 0.0, 1, wrench_out, nullptr, st));
+  } else {
+    const FLaunch L = force_shape(ctx, M, N, T, pmode_of(prm->p));
+    HIPCHK(run_force(A, T, L, pmode_of(prm->p), wrench_out != nullptr, f_out != nullptr, st));
+    used = L.slots;
+  }
+  if (f_out) HIPCHK(launch_reduce_f(fpart, nch, M, perm, f_out, st));
+  HIPCHK(launch_update(wpart, used, (const double*)in, (double*)out, dv, t, 0.0, 1, wrench_out, nullptr, st));
   return SGR_OK;
 }
 
@@ -487,9 +542,13 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   cv.take<Derived>(1);
   cv.take<float4>(pad_n(N));
   cv.take<float>(pad_n(N));
-  cv.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
+  const int nslot = std::max(force_shape(ctx, M, N, T, pm).slots, TM.nblk);
+  cv.take<double>((size_t)nslot * WR_STRIDE);
   cv.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
   cv.take<int>(M);
+  cv.take<char>(sort_perm_workspace(M, 1));
+  cv.take<float4>(M);
+  cv.take<float2>(M);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   float* aX = w.take<float>(N);
@@ -498,9 +557,12 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   Derived* dv = w.take<Derived>(1);
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
-  double* wpart = w.take<double>((size_t)std::max(T.nblk, TM.nblk) * WR_STRIDE);
+  double* wpart = w.take<double>((size_t)nslot * WR_STRIDE);
   char* gws = w.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
   int* perm = w.take<int>(M);
+  char* sws = w.take<char>(sort_perm_workspace(M, 1));
+  float4* tm4 = w.take<float4>(M);
+  float2* tmx = w.take<float2>(M);
 
   HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, prm->k, aX, nullptr, gws, st));
   HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, prm->k, aY, nullptr, gws, st));
@@ -508,7 +570,8 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom, st));
   HIPCHK(launch_prepare(aX, ref->m, N, aY, tmpl->m, M, mom, mom + 10, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, aX, ref->m, N, dv, ref4, lw, st));
-  HIPCHK(launch_partition(aY, M, dv, perm, st));
+  HIPCHK(launch_sort_perm(aY, M, perm, sws, st));
+  HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, aY, tmpl->m, M, perm, dv, tm4, tmx, st));
 
   auto loop = [&](hipStream_t s) -> int {
     for (int t = 0; t < prm->E; ++t) {
@@ -517,12 +580,16 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
       const bool wu = !mixed && (stats != nullptr || last);
       const Tiles& Tt = mixed ? TM : T;
       ForceArgs A{tmpl->x, tmpl->y, tmpl->z, aY, tmpl->m, ref4, lw, (const double*)inout, dv, M, N,
-                  Tt.chunk_len, Tt.n_chunks, t, 0.0, wpart, nullptr, perm};
-      if (mixed)
+                  Tt.chunk_len, Tt.n_chunks, t, 0.0, wpart, nullptr, perm, tm4, tmx};
+      int used = Tt.nblk;
+      if (mixed) {
         HIPCHK(launch_force_mixed(A, false, s));
-      else
-        HIPCHK(launch_force(A, T.R, pm, wu, false, s, T.sm));
-      HIPCHK(launch_update(wpart, Tt.nblk, (const double*)inout, (double*)inout, dv, t, 0.0, 1, nullptr,
+      } else {
+        const FLaunch L = force_shape(ctx, M, N, T, pm);
+        HIPCHK(run_force(A, T, L, pm, wu, false, s));
+        used = L.slots;
+      }
+      HIPCHK(launch_update(wpart, used, (const double*)inout, (double*)inout, dv, t, 0.0, 1, nullptr,
                            stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
     }
     return SGR_OK;
@@ -628,18 +695,25 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   const int M = (int)tmpl->n, N = (int)ref->n;
   const int pm = pmode_of(prm->p);
   const auto key = std::make_tuple(log2_bucket(M), log2_bucket(N), pm);
+  // Candidates: template points per lane, the reference load variant, and
+  // one or two waves of resident blocks (from the kernel's occupancy).
+  const int cand_R[4] = {1, 2, 4, 8};
   // size the workspace for the largest candidate
   size_t need = 0;
-  for (int R : {2, 4, 8})
-    for (int bpc : {8, 12, 16}) {
-      const Tiles T = TileTable::make(M, N, R, bpc * ctx->n_cu);
+  for (int R : cand_R)
+    for (int v : {0, 1}) {
+      Tiles T = TileTable::make(M, N, R, 8 * ctx->n_cu, v);
+      T.bpc = 2 * force_blocks_per_cu(R, pm, v != 0);
       Carve cv{nullptr};
       cv.take<double>(16);
       cv.take<Derived>(1);
       cv.take<float4>(pad_n(N));
       cv.take<float>(pad_n(N));
       cv.take<int>(M);
-      cv.take<double>((size_t)T.nblk * WR_STRIDE);
+      cv.take<char>(sort_perm_workspace(M, 1));
+      cv.take<float4>(M);
+      cv.take<float2>(M);
+      cv.take<double>((size_t)force_shape(ctx, M, N, T, pm).slots * WR_STRIDE);
       need = std::max(need, cv.off);
     }
   if (int e = ensure_ws(ctx, need)) return e;
@@ -649,27 +723,33 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
   int* perm = w.take<int>(M);
+  char* sws = w.take<char>(sort_perm_workspace(M, 1));
+  float4* tm4 = w.take<float4>(M);
+  float2* tmx = w.take<float2>(M);
   const size_t wp_off = w.off;
   HIPCHK(launch_identity_pose(pose, st));
   HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
-  HIPCHK(launch_partition(a_t, M, dv, perm, st));
+  HIPCHK(launch_sort_perm(a_t, M, perm, sws, st));
+  HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, M, perm, dv, tm4, tmx, st));
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   double best_t = 1e300;
   int bR = 4, bB = 8, bV = 0;
   for (int v : {0, 1})
-    for (int R : {2, 4, 8})
-      for (int bpc : {8, 12, 16}) {
-        const Tiles T = TileTable::make(M, N, R, bpc * ctx->n_cu, v);
+    for (int R : cand_R)
+      for (int waves : {1, 2}) {
+        Tiles T = TileTable::make(M, N, R, 8 * ctx->n_cu, v);
+        T.bpc = waves * force_blocks_per_cu(R, pm, v != 0);
+        const FLaunch L = force_shape(ctx, M, N, T, pm);
         Carve wc{ctx->ws, wp_off};
-        double* wpart = wc.take<double>((size_t)T.nblk * WR_STRIDE);
+        double* wpart = wc.take<double>((size_t)L.slots * WR_STRIDE);
         ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, pose, dv, M, N,
-                    T.chunk_len, T.n_chunks, prm->E - 1, 0.0, wpart, nullptr, perm};
-        HIPCHK(launch_force(A, T.R, pm, false, false, st, T.sm));
+                    T.chunk_len, T.n_chunks, prm->E - 1, 0.0, wpart, nullptr, perm, tm4, tmx};
+        HIPCHK(run_force(A, T, L, pm, false, false, st));
         HIPCHK(hipEventRecord(e0, st));
-        for (int r = 0; r < reps; ++r) HIPCHK(launch_force(A, T.R, pm, false, false, st, T.sm));
+        for (int r = 0; r < reps; ++r) HIPCHK(run_force(A, T, L, pm, false, false, st));
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -678,7 +758,7 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
         if (per < best_t) {
           best_t = per;
           bR = R;
-          bB = bpc;
+          bB = T.bpc;
           bV = v;
         }
       }
@@ -762,9 +842,15 @@ int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
   cv.take<Derived>(1);
   cv.take<float4>(pad_n(N));
   cv.take<float>(pad_n(N));
-  cv.take<double>((size_t)T.nblk * WR_STRIDE);
-  cv.take<double>((size_t)T.n_chunks * M * 3);
+  const FLaunch L0 = force_shape(ctx, M, N, T, pm);
+  const int nslot = is_mixed(prm) ? T.nblk : L0.slots;
+  const int nch = is_mixed(prm) ? T.n_chunks : L0.n_chunks;
+  cv.take<double>((size_t)nslot * WR_STRIDE);
+  cv.take<double>((size_t)nch * M * 3);
   cv.take<int>(M);
+  cv.take<char>(sort_perm_workspace(M, 1));
+  cv.take<float4>(M);
+  cv.take<float2>(M);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   double* mom_t = w.take<double>(16);
@@ -772,22 +858,30 @@ int sgr_force_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
   Derived* dv = w.take<Derived>(1);
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
-  double* wpart = w.take<double>((size_t)T.nblk * WR_STRIDE);
-  double* fpart = w.take<double>((size_t)T.n_chunks * M * 3);
+  double* wpart = w.take<double>((size_t)nslot * WR_STRIDE);
+  double* fpart = w.take<double>((size_t)nch * M * 3);
   int* perm = w.take<int>(M);
+  char* sws = w.take<char>(sort_perm_workspace(M, 1));
+  float4* tm4 = w.take<float4>(M);
+  float2* tmx = w.take<float2>(M);
   HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom_t, st));
   HIPCHK(launch_identity_pose(pose, st));
   HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), dv, st));
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, dv, ref4, lw, st));
-  HIPCHK(launch_partition(a_t, M, dv, perm, st));
+  HIPCHK(launch_sort_perm(a_t, M, perm, sws, st));
+  HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, M, perm, dv, tm4, tmx, st));
   ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, ref4, lw, pose, dv, M, N,
-              T.chunk_len, T.n_chunks, 0, G, wpart, f_out ? fpart : nullptr, perm};
-  if (is_mixed(prm))
+              T.chunk_len, T.n_chunks, 0, G, wpart, f_out ? fpart : nullptr, perm, tm4, tmx};
+  int used = T.nblk;
+  if (is_mixed(prm)) {
     HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
-  else
-    HIPCHK(launch_force(A, T.R, pm, wrench_out != nullptr, f_out != nullptr, st, T.sm));
-  if (f_out) HIPCHK(launch_reduce_f(fpart, T.n_chunks, M, f_out, st));
-  if (wrench_out) HIPCHK(launch_update(wpart, T.nblk, pose, nullptr, dv, 0, G, 0, wrench_out, nullptr, st));
+  } else {
+    const FLaunch L = force_shape(ctx, M, N, T, pm);
+    HIPCHK(run_force(A, T, L, pm, wrench_out != nullptr, f_out != nullptr, st));
+    used = L.slots;
+  }
+  if (f_out) HIPCHK(launch_reduce_f(fpart, nch, M, perm, f_out, st));
+  if (wrench_out) HIPCHK(launch_update(wpart, used, pose, nullptr, dv, 0, G, 0, wrench_out, nullptr, st));
   return SGR_OK;
 }
 
@@ -855,6 +949,10 @@ struct sgr_plan {
   double* wpart = nullptr;
   double* fpart = nullptr;
   int* perm = nullptr;
+  float4* tm4 = nullptr;
+  float2* tmx = nullptr;
+  int nslot = 0;  // wrench slots allocated
+  int nch = 0;    // reference chunks of a launch with per-point output
 };
 
 int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
@@ -882,9 +980,17 @@ int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const
   cv.take<Derived>(1);
   cv.take<float4>(pad_n(N));
   cv.take<float>(pad_n(N));
-  cv.take<double>((size_t)pl->T.nblk * WR_STRIDE);
-  cv.take<double>((size_t)pl->T.n_chunks * M * 3);
+  {
+    const FLaunch L0 = force_shape(ctx, M, N, pl->T, pl->pm);
+    pl->nslot = is_mixed(prm) ? pl->T.nblk : L0.slots;
+    pl->nch = is_mixed(prm) ? pl->T.n_chunks : L0.n_chunks;
+  }
+  cv.take<double>((size_t)pl->nslot * WR_STRIDE);
+  cv.take<double>((size_t)pl->nch * M * 3);
   cv.take<int>(M);
+  cv.take<char>(sort_perm_workspace(M, 1));
+  cv.take<float4>(M);
+  cv.take<float2>(M);
   if (hipMalloc(&pl->mem, cv.off) != hipSuccess) {
     (void)hipGetLastError();
     delete pl;
@@ -894,14 +1000,19 @@ int sgr_plan_create(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const
   pl->dv = w.take<Derived>(1);
   pl->ref4 = w.take<float4>(pad_n(N));
   pl->lw = w.take<float>(pad_n(N));
-  pl->wpart = w.take<double>((size_t)pl->T.nblk * WR_STRIDE);
-  pl->fpart = w.take<double>((size_t)pl->T.n_chunks * M * 3);
+  pl->wpart = w.take<double>((size_t)pl->nslot * WR_STRIDE);
+  pl->fpart = w.take<double>((size_t)pl->nch * M * 3);
   pl->perm = w.take<int>(M);
+  char* sws = w.take<char>(sort_perm_workspace(M, 1));
+  pl->tm4 = w.take<float4>(M);
+  pl->tmx = w.take<float2>(M);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e1 = launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_t, mom_r, prep_of(prm), pl->dv, st);
   hipError_t e2 = e1 == hipSuccess ? launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, N, pl->dv, pl->ref4, pl->lw, st)
                                    : e1;
-  if (e2 == hipSuccess) e2 = launch_partition(a_t, M, pl->dv, pl->perm, st);
+  if (e2 == hipSuccess) e2 = launch_sort_perm(a_t, M, pl->perm, sws, st);
+  if (e2 == hipSuccess)
+    e2 = launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, M, pl->perm, pl->dv, pl->tm4, pl->tmx, st);
   if (e2 != hipSuccess) {
     (void)hipFree(pl->mem);
     delete pl;
@@ -923,7 +1034,7 @@ int sgr_plan_destroy(sgr_plan* pl) {
 static ForceArgs plan_args(sgr_plan* pl, int t, double G, const sgr_pose* pose, bool with_f) {
   return ForceArgs{pl->tmpl.x, pl->tmpl.y, pl->tmpl.z, pl->a_t, pl->tmpl.m, pl->ref4, pl->lw,
                    (const double*)pose, pl->dv, (int)pl->tmpl.n, (int)pl->ref.n, pl->T.chunk_len, pl->T.n_chunks,
-                   t, G, pl->wpart, with_f ? pl->fpart : nullptr, pl->perm};
+                   t, G, pl->wpart, with_f ? pl->fpart : nullptr, pl->perm, pl->tm4, pl->tmx};
 }
 
 int sgr_plan_force(sgr_plan* pl, int t, double G, const sgr_pose* pose, double* wrench_out, float* f_out,
@@ -932,14 +1043,17 @@ int sgr_plan_force(sgr_plan* pl, int t, double G, const sgr_pose* pose, double* 
   HIPCHK(hipSetDevice(pl->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ForceArgs A = plan_args(pl, t, G, pose, f_out != nullptr);
-  if (is_mixed(&pl->prm))
+  int used = pl->T.nblk;
+  if (is_mixed(&pl->prm)) {
     HIPCHK(launch_force_mixed(A, f_out != nullptr, st));
-  else
-    HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, f_out != nullptr, st, pl->T.sm));
-  if (f_out) HIPCHK(launch_reduce_f(pl->fpart, pl->T.n_chunks, (int)pl->tmpl.n, f_out, st));
+  } else {
+    const FLaunch L = force_shape(pl->ctx, (int)pl->tmpl.n, (int)pl->ref.n, pl->T, pl->pm);
+    HIPCHK(run_force(A, pl->T, L, pl->pm, wrench_out != nullptr, f_out != nullptr, st));
+    used = L.slots;
+  }
+  if (f_out) HIPCHK(launch_reduce_f(pl->fpart, pl->nch, (int)pl->tmpl.n, pl->perm, f_out, st));
   if (wrench_out)
-    HIPCHK(launch_update(pl->wpart, pl->T.nblk, (const double*)pose, nullptr, pl->dv, t, G, 0, wrench_out, nullptr,
-                         st));
+    HIPCHK(launch_update(pl->wpart, used, (const double*)pose, nullptr, pl->dv, t, G, 0, wrench_out, nullptr, st));
   return SGR_OK;
 }
 
@@ -949,12 +1063,16 @@ int sgr_plan_step(sgr_plan* pl, int t, const sgr_pose* pose_in, sgr_pose* pose_o
   HIPCHK(hipSetDevice(pl->ctx->device));
   hipStream_t st = (hipStream_t)stream;
   ForceArgs A = plan_args(pl, t, 0.0, pose_in, false);
-  if (is_mixed(&pl->prm))
+  int used = pl->T.nblk;
+  if (is_mixed(&pl->prm)) {
     HIPCHK(launch_force_mixed(A, false, st));
-  else
-    HIPCHK(launch_force(A, pl->T.R, pl->pm, wrench_out != nullptr, false, st, pl->T.sm));
-  HIPCHK(launch_update(pl->wpart, pl->T.nblk, (const double*)pose_in, (double*)pose_out, pl->dv, t, 0.0, 1,
-                       wrench_out, nullptr, st));
+  } else {
+    const FLaunch L = force_shape(pl->ctx, (int)pl->tmpl.n, (int)pl->ref.n, pl->T, pl->pm);
+    HIPCHK(run_force(A, pl->T, L, pl->pm, wrench_out != nullptr, false, st));
+    used = L.slots;
+  }
+  HIPCHK(launch_update(pl->wpart, used, (const double*)pose_in, (double*)pose_out, pl->dv, t, 0.0, 1, wrench_out,
+                       nullptr, st));
   return SGR_OK;
 }
 

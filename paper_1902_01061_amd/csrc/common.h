@@ -34,11 +34,13 @@ struct Derived {
   double E;
   double p;
   double g_mode;
-  double expand_ok;  // 1: the expanded similarity exponent 2 b_i b_j - b_j^2 + lw_j stays
-                     //    below 64 for every pair (b centred at the mean curvature)
+  double expand_ok;  // 1: the expanded similarity exponent 2 b_i b_j - b_j^2 + lw_j, b
+                     //    centred at the mean curvature, stays below 64 for every pair
   double lw_max;     // largest log2 weight of the reference (0 if none is positive)
+  double bref_lo;    // smallest and largest b of the reference (as rounded to FP32)
+  double bref_hi;
   double Vw[9];      // right singular vectors of the last cross-covariance (warm start)
-  int32_t n_safe;    // template points [perm[0], perm[n_safe]) admit the expanded exponent
+  int32_t pad3;
   int32_t pad2;
   int32_t status;    // 0 ok; bit flags set by the update kernel
   int32_t pad;
@@ -201,6 +203,66 @@ __device__ inline void block_sum(double (&v)[NV], double* lds) {
     }
   }
   __syncthreads();
+}
+
+// Smallest and largest value over the threads of a block of BT threads
+// (NaN is ignored; every thread receives both).  lds: 2 * BT / 64 doubles of
+// scratch, free on entry (a barrier precedes its use).
+template <int BT>
+__device__ inline void block_range(float& lo, float& hi, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, off, 64));
+    hi = fmaxf(hi, __shfl_xor(hi, off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    lds[2 * w] = (double)lo;
+    lds[2 * w + 1] = (double)hi;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < BT / 64; ++k) {
+    lo = fminf(lo, (float)lds[2 * k]);
+    hi = fmaxf(hi, (float)lds[2 * k + 1]);
+  }
+}
+
+// Expanded similarity exponent for a block of template points whose b lies
+// in [lo, hi] (eq. 3): with d = b - beta,
+//   lw_j - (b_i - b_j)^2 = 2 d_i d_j + (lw_j - d_j^2) - d_i^2,
+// so a pair costs one FMA and exp2(-d_i^2) is applied in FP64 at the end.
+// The unscaled FP32 term exp2(2 d_i d_j + lw_j - d_j^2) must not overflow:
+// since every b_j lies in [bref_lo, bref_hi], its exponent is at most
+// lw_max + (b_i - beta)^2 - dist(b_i, [bref_lo, bref_hi])^2, which is
+// linear or convex in b_i on each side of and inside the range, so its
+// largest value over the block is taken at the block's ends or at a range
+// end inside the block.  Returns whether that bound is <= 64, and sets beta:
+// 0 when fixed (the scalar-load form reads the packed reference directly),
+// else the centre of the part of the block inside the reference range, or
+// the block end nearest to the range for a block entirely outside it (which
+// makes the bound lw_max).  The template order sorted by curvature keeps
+// block ranges narrow.
+__device__ inline bool expanded_centre(float lo, float hi, const Derived& D, bool fixed, float& beta) {
+  beta = 0.f;
+  if (!(lo <= hi)) return false;
+  const float rlo = (float)D.bref_lo, rhi = (float)D.bref_hi;
+  if (!fixed) {
+    const float ilo = fmaxf(lo, rlo), ihi = fminf(hi, rhi);
+    if (ilo <= ihi)
+      beta = 0.5f * ilo + 0.5f * ihi;
+    else
+      beta = lo > rhi ? lo : hi;
+  }
+  auto bound = [&](float b) {
+    const double d = (double)b - (double)beta;
+    const double g = b > rhi ? (double)b - rhi : (b < rlo ? (double)rlo - b : 0.0);
+    return d * d - g * g;
+  };
+  double e = fmax(bound(lo), bound(hi));
+  if (rlo > lo && rlo < hi) e = fmax(e, bound(rlo));
+  if (rhi > lo && rhi < hi) e = fmax(e, bound(rhi));
+  return e + D.lw_max <= 64.0;
 }
 
 }  // namespace sgr

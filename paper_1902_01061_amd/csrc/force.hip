@@ -18,6 +18,8 @@
 // reference is split into chunks across blocks (F and K are linear in the
 // per-chunk partial forces), and a second kernel sums the block partials in
 // a fixed order, so results are bitwise reproducible.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -57,15 +59,18 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   block_sum<1, 1024>(v, lds);
   // largest |a - abar| over both clouds and largest log2 weight: bound of the
   // expanded similarity exponent (checked below once sigma is known)
-  double mx[2] = {0.0, -INFINITY};
+  // and the range of the reference curvatures
+  double mx[4] = {0.0, -INFINITY, -INFINITY, -INFINITY};
   for (int64_t j = threadIdx.x; j < N; j += 1024) {
     mx[0] = fmax(mx[0], fabs((double)aX[j] - abar));
     double l = wX ? log2((double)wX[j]) : 0.0;
     if (P.g_mode == 1) l += log2((double)aX[j] / abar);
     mx[1] = fmax(mx[1], l);
+    mx[2] = fmax(mx[2], (double)aX[j]);
+    mx[3] = fmax(mx[3], -(double)aX[j]);
   }
   for (int64_t i = threadIdx.x; i < M; i += 1024) mx[0] = fmax(mx[0], fabs((double)aY[i] - abar));
-  for (int c = 0; c < 2; ++c) {
+  for (int c = 0; c < 4; ++c) {
     double m = mx[c];
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
     if ((threadIdx.x & 63) == 0) red_max[threadIdx.x >> 6] = m;
@@ -103,11 +108,13 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   {
     const double bmax = mx[0] * D.bscale;
     D.lw_max = fmax(mx[1], 0.0);
+    D.bref_lo = (double)(float)((-mx[3] - abar) * D.bscale);
+    D.bref_hi = (double)(float)((mx[2] - abar) * D.bscale);
     D.expand_ok = (bmax * bmax + D.lw_max <= 64.0) ? 1.0 : 0.0;
   }
   for (int e = 0; e < 9; ++e) D.Vw[e] = (e % 4 == 0) ? 1.0 : 0.0;
-  D.n_safe = 0;
   D.pad2 = 0;
+  D.pad3 = 0;
   if (!(D.lamX > 0) || !(D.lamY0 > 0) || !(D.sigma > 0) || !(D.Z > 0) || !(D.Mtot > 0) ||
       (P.g_mode == 1 && !(abar > 0)))
     st |= ST_DEGENERATE;
@@ -137,57 +144,34 @@ __global__ __launch_bounds__(1024) void prepare_batch_kernel(const PrepDesc* __r
   prepare_body(g.aX, g.wX, g.N, g.aY, g.mY, g.M, g.mom_t, g.mom_r, P, outs + blockIdx.x, lds, red_max, &abar_s);
 }
 
-// Stable partition of the template points: those whose expanded similarity
-// exponent stays below 64 for every reference point (b_i^2 + lw_max <= 64)
-// first, the rest after; n_safe counts the first group.  A block of the
-// force kernel whose points all lie in the first group can use the
-// one-FMA exponent.  One block, deterministic.
-__device__ inline void partition_body(const float* __restrict__ aY, int M, Derived* __restrict__ dv,
-                                      int* __restrict__ perm, int* s_cnt) {
-  const Derived& D = *dv;
-  const int C = (M + 1023) / 1024;
-  const int lo = min(M, (int)threadIdx.x * C), hi = min(M, lo + C);
-  auto safe = [&](int i) {
-    const double b = (double)(float)(((double)aY[i] - D.abar) * D.bscale);
-    return b * b + D.lw_max <= 64.0;
-  };
-  int cnt = 0;
-  for (int i = lo; i < hi; ++i) cnt += safe(i) ? 1 : 0;
-  s_cnt[threadIdx.x] = cnt;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int t = 0; t < 1024; ++t) {
-      const int v = s_cnt[t];
-      s_cnt[t] = acc;
-      acc += v;
-    }
-    s_cnt[1024] = acc;
-  }
-  __syncthreads();
-  const int total = s_cnt[1024];
-  int ps = s_cnt[threadIdx.x];
-  int pu = total + (lo - s_cnt[threadIdx.x]);
-  for (int i = lo; i < hi; ++i) {
-    if (safe(i))
-      perm[ps++] = i;
-    else
-      perm[pu++] = i;
-  }
-  if (threadIdx.x == 0) dv->n_safe = total;
+// Template in the order the force kernel visits it: position ip holds the
+// point perm[ip] as (x0, y0, z0, b) and (a, m), so that the kernel's loads
+// are contiguous whatever the order.
+__device__ inline void pack_tmpl_body(const float* __restrict__ x, const float* __restrict__ y,
+                                      const float* __restrict__ z, const float* __restrict__ aY,
+                                      const float* __restrict__ mY, int M, const int* __restrict__ perm,
+                                      const Derived& D, float4* __restrict__ tm4, float2* __restrict__ tmx,
+                                      int ip) {
+  if (ip >= M) return;
+  const int i = perm[ip];
+  const float a = aY[i];
+  tm4[ip] = make_float4(x[i], y[i], z[i], (float)(((double)a - D.abar) * D.bscale));
+  tmx[ip] = make_float2(a, mY ? mY[i] : 1.f);
 }
 
-__global__ __launch_bounds__(1024) void partition_kernel(const float* __restrict__ aY, int M, Derived* __restrict__ dv,
-                                                         int* __restrict__ perm) {
-  __shared__ int s_cnt[1025];
-  partition_body(aY, M, dv, perm, s_cnt);
+__global__ __launch_bounds__(256) void pack_tmpl_kernel(const float* __restrict__ x, const float* __restrict__ y,
+                                                        const float* __restrict__ z, const float* __restrict__ aY,
+                                                        const float* __restrict__ mY, int M,
+                                                        const int* __restrict__ perm, const Derived* __restrict__ dv,
+                                                        float4* __restrict__ tm4, float2* __restrict__ tmx) {
+  pack_tmpl_body(x, y, z, aY, mY, M, perm, *dv, tm4, tmx, blockIdx.x * 256 + threadIdx.x);
 }
 
-__global__ __launch_bounds__(1024) void partition_batch_kernel(const RegDesc* __restrict__ regs,
-                                                               Derived* __restrict__ dvs) {
-  __shared__ int s_cnt[1025];
-  const RegDesc& g = regs[blockIdx.x];
-  partition_body(g.aY, g.M, dvs + blockIdx.x, g.perm, s_cnt);
+__global__ __launch_bounds__(256) void pack_tmpl_batch_kernel(const RegDesc* __restrict__ regs,
+                                                              const Derived* __restrict__ dvs) {
+  const RegDesc& g = regs[blockIdx.y];
+  for (int ip = blockIdx.x * 256 + threadIdx.x; ip < g.M; ip += gridDim.x * 256)
+    pack_tmpl_body(g.y0x, g.y0y, g.y0z, g.aY, g.mY, g.M, g.perm, dvs[blockIdx.y], g.tm4, g.tmx, ip);
 }
 
 // Reference in the layout the pair loop reads: float4 (x - xbar, b) and
@@ -247,67 +231,126 @@ __device__ inline float pair_coef(float rx, float ry, float rz, float db, float 
 // loads go through the scalar unit into SGPRs (no LDS, no barriers).
 // One work item: template points [iblk*256*R, (iblk+1)*256*R) against the
 // reference chunk `chunk`; writes its 13 wrench partials to wpart[slot].
-template <int R, int PM, bool WU, bool WF, bool SM>
-__device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int slot, float4* s_ref, float* s_lw,
-                                   double* s_red) {
-  const Derived& D = *A.dv;
-
-  // pose: y - xbar = sR (y0 - ybar0) + (sR ybar0 + t - xbar)
+// The pose as applied to a template point: y - xbar = sR (y0 - ybar0) + cv.
+struct PoseRT {
   double sR[9], cv[3];
-  {
-    const double s = A.pose[0];
+};
+
+__device__ inline PoseRT pose_rt(const double* __restrict__ pose, const Derived& D) {
+  PoseRT P;
+  const double s = pose[0];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) sR[e] = s * A.pose[1 + e];
+  for (int e = 0; e < 9; ++e) P.sR[e] = s * pose[1 + e];
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
-      cv[r] = sR[3 * r] * D.ybar0[0] + sR[3 * r + 1] * D.ybar0[1] + sR[3 * r + 2] * D.ybar0[2] + A.pose[10 + r] -
+  for (int r = 0; r < 3; ++r)
+    P.cv[r] = P.sR[3 * r] * D.ybar0[0] + P.sR[3 * r + 1] * D.ybar0[1] + P.sR[3 * r + 2] * D.ybar0[2] + pose[10 + r] -
               D.xbar[r];
+  return P;
+}
+
+// Template point at visiting position ip < M: its index, its similarity
+// coordinate b and its posed position relative to xbar (FP64 pose, rounded
+// once to FP32).
+__device__ inline int tmpl_index(const ForceArgs& A, int ip) { return A.perm ? A.perm[ip] : ip; }
+
+__device__ inline float tmpl_b(const ForceArgs& A, const Derived& D, int ip) {
+  if (A.tm4) return A.tm4[ip].w;
+  return (float)(((double)A.aY[tmpl_index(A, ip)] - D.abar) * D.bscale);
+}
+
+__device__ inline void tmpl_posed(const ForceArgs& A, const Derived& D, const PoseRT& P, int ip, float& px, float& py,
+                                  float& pz) {
+  float x0, y0, z0;
+  if (A.tm4) {
+    const float4 T = A.tm4[ip];
+    x0 = T.x;
+    y0 = T.y;
+    z0 = T.z;
+  } else {
+    const int i = tmpl_index(A, ip);
+    x0 = A.y0x[i];
+    y0 = A.y0y[i];
+    z0 = A.y0z[i];
   }
+  const double ex = (double)x0 - D.ybar0[0], ey = (double)y0 - D.ybar0[1], ez = (double)z0 - D.ybar0[2];
+  px = (float)(P.sR[0] * ex + P.sR[1] * ey + P.sR[2] * ez + P.cv[0]);
+  py = (float)(P.sR[3] * ex + P.sR[4] * ey + P.sR[5] * ez + P.cv[1]);
+  pz = (float)(P.sR[6] * ex + P.sR[7] * ey + P.sR[8] * ez + P.cv[2]);
+}
+
+// SM = false: the reference tile is staged in LDS and read by broadcast.
+// SM = true: every lane of a wave reads the same reference point, so the
+// loads go through the scalar unit into SGPRs (no LDS, no barriers).
+// One work item: template points at visiting positions [iblk*256*R,
+// (iblk+1)*256*R) against reference points [j0, j1); writes its 13 wrench
+// partials to wpart[slot] and, with WF, its per-point forces to
+// fpart[chunk].
+//
+// FP64 running sums per point.  r-form: (tx, ty, tz) = sum_j c_ij r_ij (and
+// tu = sum_j c_ij q_ij).  Moment form (p = 1): t0 = sum_j c, (tx, ty, tz) =
+// sum_j c x_j and tq = sum_j c |x_j|^2, so that sum_j c r = y_i t0 - t and
+// sum_j c q = |y_i|^2 t0 - 2 y_i.t + tq + eps^2 t0; the pair loop needs
+// neither r_ij nor y_i, and the posed points are formed after it, so that
+// nothing but b and the sums occupies registers across the loop.  Its
+// exponent is either lw_j - (b_i - b_j)^2 (one sub and one FMA: 6 VALU + 1
+// exp2 per pair) or the expanded form below (one FMA: 5 VALU + 1 exp2).
+template <int R, int PM, bool WU, bool WF, bool SM>
+__device__ inline void force_block(const ForceArgs& A, int iblk, int j0, int j1, int chunk, int slot, float4* s_ref,
+                                   float* s_lw, double* s_red, float* s_y) {
+  const Derived& D = *A.dv;
+  constexpr bool MOM = (PM == 1);
+  const int ip0 = iblk * F_BT * R + threadIdx.x;
   const float eps2 = (float)D.eps2;
   const float hp = (float)D.hp;
 
-  float yx[R], yy[R], yz[R], bi[R];
-  int ii[R];
+  // Posed points: in registers for the r-form, whose pair loop reads them;
+  // parked in LDS (s_y, [3][R*256]) for the moment form, whose loop does not.
+  float bi[R], yx[R], yy[R], yz[R];
+  {
+    const PoseRT P = pose_rt(A.pose, D);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int ip = iblk * F_BT * R + r * F_BT + threadIdx.x;
-    const int i = ip < A.M ? (A.perm ? A.perm[ip] : ip) : A.M;
-    ii[r] = i;
-    if (i < A.M) {
-      const double ex = (double)A.y0x[i] - D.ybar0[0], ey = (double)A.y0y[i] - D.ybar0[1],
-                   ez = (double)A.y0z[i] - D.ybar0[2];
-      yx[r] = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);
-      yy[r] = (float)(sR[3] * ex + sR[4] * ey + sR[5] * ez + cv[1]);
-      yz[r] = (float)(sR[6] * ex + sR[7] * ey + sR[8] * ez + cv[2]);
-      bi[r] = (float)(((double)A.aY[i] - D.abar) * D.bscale);
-    } else {
-      yx[r] = yy[r] = yz[r] = 0.f;
+    for (int r = 0; r < R; ++r) {
+      const int ip = ip0 + r * F_BT;
       bi[r] = 0.f;
+      yx[r] = yy[r] = yz[r] = 0.f;
+      if (ip < A.M) {
+        bi[r] = tmpl_b(A, D, ip);
+        tmpl_posed(A, D, P, ip, yx[r], yy[r], yz[r]);
+      }
+      if constexpr (MOM) {
+        s_y[r * F_BT + threadIdx.x] = yx[r];
+        s_y[(R + r) * F_BT + threadIdx.x] = yy[r];
+        s_y[(2 * R + r) * F_BT + threadIdx.x] = yz[r];
+      }
     }
   }
 
-  // FP64 running sums per point.  r-form: (tx, ty, tz) = sum_j c_ij r_ij
-  // (and tu = sum_j c_ij q_ij).  Moment form (p = 1): t0 = sum_j c, (tx, ty,
-  // tz) = sum_j c x_j and tq = sum_j c |x_j|^2, so that sum_j c r =
-  // y_i t0 - t and sum_j c q = |y_i|^2 t0 - 2 y_i.t + tq + eps^2 t0; it needs
-  // no r_ij.  Its exponent is either lw_j - (b_i - b_j)^2 (one sub and one
-  // FMA: 6 VALU + 1 exp2 per pair) or, when the prepare kernel has shown it
-  // cannot overflow (expand_ok), the expanded 2 b_i b_j + (lw_j - b_j^2)
-  // (one FMA: 5 VALU + 1 exp2), whose extra factor exp2(b_i^2) is divided
-  // out in FP64 at the end.
   double t0[R], tx[R], ty[R], tz[R], tu[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) t0[r] = tx[r] = ty[r] = tz[r] = tu[r] = 0.0;
-  constexpr bool MOM = (PM == 1);
-  // expanded exponent: every point of this block must admit it
-  const bool expd = MOM && (D.expand_ok != 0.0 || (A.perm && min(A.M, (iblk + 1) * F_BT * R) <= D.n_safe));
+  // Expanded exponent centred on beta (see expanded_centre): one FMA per
+  // pair; the LDS form stages d_j = b_j - beta and lw_j - d_j^2 with the
+  // tile, the scalar form keeps beta = 0 and reads the packed reference.
+  float beta = 0.f;
+  bool expd = false;
+  if constexpr (MOM) {
+    float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (ip0 + r * F_BT < A.M) {
+        lo = fminf(lo, bi[r]);
+        hi = fmaxf(hi, bi[r]);
+      }
+    block_range<F_BT>(lo, hi, s_red);
+    expd = expanded_centre(lo, hi, D, SM, beta);
+  }
   float al[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) al[r] = 2.f * bi[r];
+  for (int r = 0; r < R; ++r) al[r] = 2.f * (bi[r] - beta);
 
-  const int j0 = chunk * A.chunk_len;
-  const int j1 = min(A.N, j0 + A.chunk_len);
   for (int base = j0; base < j1; base += F_TJ) {
+    // points of this tile, rounded up to even (the padding has zero weight)
+    const int tn = (min(F_TJ, j1 - base) + 1) & ~1;
     // reference point jj of this tile (the packed arrays are padded to whole
     // tiles with zero-weight points, so no bounds test is needed)
     const float4* __restrict__ gref = A.ref4 + base;
@@ -316,13 +359,22 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
       __syncthreads();
       {
         const int j = base + threadIdx.x;
+        float4 X = make_float4(0.f, 0.f, 0.f, 0.f);  // beyond this range: zero weight
+        float l = -INFINITY;                            // (exp2(-inf) = 0), finite coordinates
         if (j < j1) {
-          s_ref[threadIdx.x] = gref[threadIdx.x];
-          s_lw[threadIdx.x] = glw[threadIdx.x];
-        } else {  // beyond this chunk: zero weight (exp2(-inf) = 0), finite coordinates
-          s_ref[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-          s_lw[threadIdx.x] = -INFINITY;
+          X = gref[threadIdx.x];
+          l = glw[threadIdx.x];
         }
+        if (expd) {
+          // |d_j| is capped at 1e18 so that 2 d_i d_j stays finite; such a
+          // term has lw_j - d_j^2 = -1e36 and weight 0 either way (NaN stays NaN)
+          float d = X.w - beta;
+          if (fabsf(d) > 1e18f) d = copysignf(1e18f, d);
+          X.w = d;
+          l = __builtin_fmaf(-d, d, l);
+        }
+        s_ref[threadIdx.x] = X;
+        s_lw[threadIdx.x] = l;
       }
       __syncthreads();
     }
@@ -330,16 +382,37 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
       float a0[R], ax[R], ay[R], az[R], aq[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) a0[r] = ax[r] = ay[r] = az[r] = aq[r] = 0.f;
-      if (expd) {
+      if (expd && !SM && !WU) {
+        // two reference points per step: all 2R exponentials first, then
+        // the accumulation, which leaves the exp2 latency off the FMA chains
 #pragma unroll 2
-        for (int jj = 0; jj < F_TJ; ++jj) {
+        for (int jj = 0; jj < tn; jj += 2) {
+          const float4 X0 = s_ref[jj], X1 = s_ref[jj + 1];
+          const float c0 = s_lw[jj], c1 = s_lw[jj + 1];
+          float w0[R], w1[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            w0[r] = __builtin_amdgcn_exp2f(__builtin_fmaf(al[r], X0.w, c0));
+            w1[r] = __builtin_amdgcn_exp2f(__builtin_fmaf(al[r], X1.w, c1));
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            a0[r] += w0[r] + w1[r];
+            ax[r] = __builtin_fmaf(w0[r], X0.x, __builtin_fmaf(w1[r], X1.x, ax[r]));
+            ay[r] = __builtin_fmaf(w0[r], X0.y, __builtin_fmaf(w1[r], X1.y, ay[r]));
+            az[r] = __builtin_fmaf(w0[r], X0.z, __builtin_fmaf(w1[r], X1.z, az[r]));
+          }
+        }
+      } else if (expd) {
+#pragma unroll 2
+        for (int jj = 0; jj < tn; ++jj) {
           const float4 X = SM ? gref[jj] : s_ref[jj];
-          const float beta = __builtin_fmaf(-X.w, X.w, SM ? glw[jj] : s_lw[jj]);
+          const float cj = SM ? __builtin_fmaf(-X.w, X.w, glw[jj]) : s_lw[jj];
           float x2 = 0.f;
           if constexpr (WU) x2 = __builtin_fmaf(X.x, X.x, __builtin_fmaf(X.y, X.y, X.z * X.z));
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            const float c = __builtin_amdgcn_exp2f(__builtin_fmaf(al[r], X.w, beta));
+            const float c = __builtin_amdgcn_exp2f(__builtin_fmaf(al[r], X.w, cj));
             a0[r] += c;
             ax[r] = __builtin_fmaf(c, X.x, ax[r]);
             ay[r] = __builtin_fmaf(c, X.y, ay[r]);
@@ -349,7 +422,7 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
         }
       } else {
 #pragma unroll 2
-        for (int jj = 0; jj < F_TJ; ++jj) {
+        for (int jj = 0; jj < tn; ++jj) {
           const float4 X = SM ? gref[jj] : s_ref[jj];
           const float lw = SM ? glw[jj] : s_lw[jj];
           float x2 = 0.f;
@@ -379,7 +452,7 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
 #pragma unroll
       for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = au[r] = 0.f;
 #pragma unroll 2
-      for (int jj = 0; jj < F_TJ; ++jj) {
+      for (int jj = 0; jj < tn; ++jj) {
         const float4 X = SM ? gref[jj] : s_ref[jj];
         const float lw = SM ? glw[jj] : s_lw[jj];
 #pragma unroll
@@ -402,22 +475,14 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
       }
     }
   }
-  if constexpr (MOM) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const double sc = expd ? exp2(-(double)bi[r] * (double)bi[r]) : 1.0;
-      const double py = yx[r], pyy = yy[r], pz = yz[r];
-      if constexpr (WU)
-        tu[r] = sc * ((py * py + pyy * pyy + pz * pz + D.eps2) * t0[r] - 2.0 * (py * tx[r] + pyy * ty[r] + pz * tz[r]) +
-                      tu[r]);
-      tx[r] = sc * (py * t0[r] - tx[r]);
-      ty[r] = sc * (pyy * t0[r] - ty[r]);
-      tz[r] = sc * (pz * t0[r] - tz[r]);
-    }
-  }
-
 
   // Per-point force and its contributions to F, K, U.
+  double cv[3];
+  {
+    const PoseRT P = pose_rt(A.pose, D);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cv[c] = P.cv[c];
+  }
   const double G = A.G > 0 ? A.G : G_at(D, A.t);
   const double coef = -(G / D.Z) * D.coefL;
   const double ucoef = (G / D.Z) * D.coefL / (D.p + 1.0);
@@ -426,17 +491,37 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
   for (int e = 0; e < 13; ++e) w[e] = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = ii[r];
-    if (i >= A.M) continue;
-    double gi = 1.0;
-    if (D.g_mode == 1.0) gi = (double)A.aY[i] / D.abar;
+    const int ip = ip0 + r * F_BT;
+    if (ip >= A.M) continue;
+    if constexpr (MOM) {
+      yx[r] = s_y[r * F_BT + threadIdx.x];
+      yy[r] = s_y[(R + r) * F_BT + threadIdx.x];
+      yz[r] = s_y[(2 * R + r) * F_BT + threadIdx.x];
+      const double dl = (double)(bi[r] - beta);
+      const double sc = expd ? exp2(-dl * dl) : 1.0;
+      const double py = yx[r], pyy = yy[r], pz = yz[r];
+      if constexpr (WU)
+        tu[r] = sc * ((py * py + pyy * pyy + pz * pz + D.eps2) * t0[r] - 2.0 * (py * tx[r] + pyy * ty[r] + pz * tz[r]) +
+                      tu[r]);
+      tx[r] = sc * (py * t0[r] - tx[r]);
+      ty[r] = sc * (pyy * t0[r] - ty[r]);
+      tz[r] = sc * (pz * t0[r] - tz[r]);
+    }
+    double ai, mi;
+    if (A.tmx) {
+      const float2 T = A.tmx[ip];
+      ai = (double)T.x;
+      mi = (double)T.y;
+    } else {
+      const int i = tmpl_index(A, ip);
+      ai = (double)A.aY[i];
+      mi = A.mY ? (double)A.mY[i] : 1.0;
+    }
+    const double gi = D.g_mode == 1.0 ? ai / D.abar : 1.0;
     const double fx = coef * gi * tx[r], fy = coef * gi * ty[r], fz = coef * gi * tz[r];
-    const double mi = A.mY ? (double)A.mY[i] : 1.0;
-    const double ex = (double)A.y0x[i] - D.ybar0[0], ey = (double)A.y0y[i] - D.ybar0[1],
-                 ez = (double)A.y0z[i] - D.ybar0[2];
-    const double cx = sR[0] * ex + sR[1] * ey + sR[2] * ez;
-    const double cy = sR[3] * ex + sR[4] * ey + sR[5] * ez;
-    const double cz = sR[6] * ex + sR[7] * ey + sR[8] * ez;
+    // lever arm y_i - ybar = sR (y0_i - ybar0), from the posed FP32 point
+    // (relative rounding 2^-24)
+    const double cx = (double)yx[r] - cv[0], cy = (double)yy[r] - cv[1], cz = (double)yz[r] - cv[2];
     w[WR_F + 0] += mi * fx;
     w[WR_F + 1] += mi * fy;
     w[WR_F + 2] += mi * fz;
@@ -451,7 +536,7 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int chunk, int 
     w[WR_K + 8] += fz * cz;
     if constexpr (WU) w[WR_U] += ucoef * gi * tu[r];
     if constexpr (WF) {
-      double* fp = A.fpart + ((int64_t)chunk * A.M + i) * 3;
+      double* fp = A.fpart + ((int64_t)chunk * A.M + ip) * 3;  // visiting order
       fp[0] = fx;
       fp[1] = fy;
       fp[2] = fz;
@@ -470,8 +555,20 @@ __global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
   __shared__ float4 s_ref[SM ? 1 : F_TJ];
   __shared__ float s_lw[SM ? 1 : F_TJ];
   __shared__ double s_red[(F_BT / 64) * 13];
+  __shared__ float s_y[PM == 1 ? 3 * R * F_BT : 1];
   const int n_iblk = (A.M + F_BT * R - 1) / (F_BT * R);
-  force_block<R, PM, WU, WF, SM>(A, blockIdx.x % n_iblk, blockIdx.x / n_iblk, blockIdx.x, s_ref, s_lw, s_red);
+  const int chunk = blockIdx.x / n_iblk;
+  int j0, j1;
+  if (A.chunk_len > 0) {
+    j0 = chunk * A.chunk_len;
+    j1 = min(A.N, j0 + A.chunk_len);
+  } else {
+    // balanced chunks: chunk c covers the 64-point groups [c n / C, (c + 1) n / C)
+    const int64_t n_sub = (A.N + 63) / 64;
+    j0 = (int)(chunk * n_sub / A.n_chunks) * 64;
+    j1 = min(A.N, (int)((chunk + 1) * n_sub / A.n_chunks) * 64);
+  }
+  force_block<R, PM, WU, WF, SM>(A, blockIdx.x % n_iblk, j0, j1, chunk, blockIdx.x, s_ref, s_lw, s_red, s_y);
 }
 
 // Persistent form over a batch of registrations: the grid strides over a
@@ -483,24 +580,29 @@ __global__ __launch_bounds__(F_BT) void force_batch_kernel(BatchArgs B) {
   __shared__ float4 s_ref[F_TJ];
   __shared__ float s_lw[F_TJ];
   __shared__ double s_red[(F_BT / 64) * 13];
+  __shared__ float s_y[PM == 1 ? 3 * R * F_BT : 1];
   for (int it = blockIdx.x; it < B.n_items; it += gridDim.x) {
     const int4 item = B.items[it];  // (registration, template block, chunk, output slot)
     const RegDesc& g = B.regs[item.x];
     ForceArgs A{g.y0x, g.y0y, g.y0z, g.aY, g.mY, B.ref4 + g.ref_off, B.reflw + g.ref_off,
                 B.poses + (int64_t)13 * item.x, B.dvs + item.x, g.M, g.N, B.chunk_len, 0, B.t, 0.0, B.wpart, nullptr,
-                g.perm};
-    force_block<R, PM, WU, false, false>(A, item.y, item.z, item.w, s_ref, s_lw, s_red);
+                g.perm, g.tm4, g.tmx};
+    const int j0 = item.z * B.chunk_len;
+    force_block<R, PM, WU, false, false>(A, item.y, j0, min(g.N, j0 + B.chunk_len), item.z, item.w, s_ref, s_lw,
+                                         s_red, s_y);
   }
 }
 
-// f_out[i] = sum over chunks of the per-chunk forces (fixed order).
+// f_out[perm[ip]] = sum over chunks of the per-chunk forces of visiting
+// position ip (fixed order); perm may be null (identity).
 __global__ __launch_bounds__(256) void reduce_f_kernel(const double* __restrict__ fpart, int n_chunks, int M,
-                                                       float* __restrict__ f_out) {
+                                                       const int* __restrict__ perm, float* __restrict__ f_out) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)M * 3) return;
   double s = 0.0;
   for (int c = 0; c < n_chunks; ++c) s += fpart[(int64_t)c * M * 3 + e];
-  f_out[e] = (float)s;
+  const int64_t ip = e / 3;
+  f_out[(perm ? (int64_t)perm[ip] : ip) * 3 + (e - ip * 3)] = (float)s;
 }
 
 hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const float* aY, const float* mY, int64_t M,
@@ -509,13 +611,16 @@ hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const flo
   return hipGetLastError();
 }
 
-hipError_t launch_partition(const float* aY, int M, Derived* dv, int* perm, hipStream_t st) {
-  hipLaunchKernelGGL(partition_kernel, dim3(1), dim3(1024), 0, st, aY, M, dv, perm);
+hipError_t launch_pack_tmpl(const float* x, const float* y, const float* z, const float* aY, const float* mY, int M,
+                            const int* perm, const Derived* dv, float4* tm4, float2* tmx, hipStream_t st) {
+  hipLaunchKernelGGL(pack_tmpl_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, x, y, z, aY, mY, M, perm,
+                     dv, tm4, tmx);
   return hipGetLastError();
 }
 
-hipError_t launch_partition_batch(const RegDesc* regs, int B, Derived* dvs, hipStream_t st) {
-  hipLaunchKernelGGL(partition_batch_kernel, dim3(B), dim3(1024), 0, st, regs, dvs);
+hipError_t launch_pack_tmpl_batch(const RegDesc* regs, int B, int max_M, const Derived* dvs, hipStream_t st) {
+  const unsigned gx = (unsigned)std::min(64, (max_M + 255) / 256);
+  hipLaunchKernelGGL(pack_tmpl_batch_kernel, dim3(gx, (unsigned)B), dim3(256), 0, st, regs, dvs);
   return hipGetLastError();
 }
 
@@ -568,6 +673,38 @@ static void launch_force_r(const ForceArgs& A, int pm, bool sm, int nblk, bool w
   }
 }
 
+// Resident blocks per CU of the force kernel (cached per instantiation).
+template <int R, int PM, bool SM>
+static int force_occ() {
+  static int occ = 0;
+  if (occ == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, force_kernel<R, PM, false, false, SM>, F_BT, 0) !=
+            hipSuccess ||
+        n < 1)
+      n = 1;
+    occ = n;
+  }
+  return occ;
+}
+
+template <int R>
+static int force_occ_r(int pm, bool sm) {
+  if (pm == 1) return sm ? force_occ<R, 1, true>() : force_occ<R, 1, false>();
+  if (pm == 3) return sm ? force_occ<R, 3, true>() : force_occ<R, 3, false>();
+  return sm ? force_occ<R, 0, true>() : force_occ<R, 0, false>();
+}
+
+int force_blocks_per_cu(int R, int pm, bool sm) {
+  switch (R) {
+    case 1: return force_occ_r<1>(pm, sm);
+    case 2: return force_occ_r<2>(pm, sm);
+    case 4: return force_occ_r<4>(pm, sm);
+    case 8: return force_occ_r<8>(pm, sm);
+    default: return 1;
+  }
+}
+
 int force_points_per_block(int R) { return F_BT * R; }
 int force_tile_j() { return F_TJ; }
 
@@ -610,9 +747,10 @@ hipError_t launch_force_batch(const BatchArgs& B, int R, int pm, bool want_u, in
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, float* f_out, hipStream_t st) {
+hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, const int* perm, float* f_out, hipStream_t st) {
   const int64_t n = (int64_t)M * 3;
-  hipLaunchKernelGGL(reduce_f_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, fpart, n_chunks, M, f_out);
+  hipLaunchKernelGGL(reduce_f_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, fpart, n_chunks, M, perm,
+                     f_out);
   return hipGetLastError();
 }
 

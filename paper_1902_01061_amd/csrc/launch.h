@@ -29,13 +29,18 @@ struct ForceArgs {
   const double* pose;   // 13 doubles
   const Derived* dv;
   int M, N;
-  int chunk_len;        // reference points per block (multiple of the LDS tile)
+  int chunk_len;        // reference points per block (multiple of the LDS tile), or 0: n_chunks
+                        // balanced chunks cut at multiples of 64 points (force kernel only)
   int n_chunks;
   int t;                // iteration index (G from eq. 12 when G <= 0)
   double G;             // explicit force constant, or <= 0
   double* wpart;        // [n_blocks][WR_STRIDE]
   double* fpart;        // [n_chunks][M][3] or nullptr
-  const int* perm = nullptr;  // template visiting order (see launch_partition) or nullptr
+  const int* perm = nullptr;  // template visiting order (see launch_sort_perm) or nullptr
+  // Template packed in visiting order (launch_pack_tmpl), or nullptr: position
+  // ip holds (x0, y0, z0, b) and (a, m) of the point perm[ip].
+  const float4* tm4 = nullptr;
+  const float2* tmx = nullptr;
 };
 
 // A cloud for the batched descriptor kernels.
@@ -77,6 +82,8 @@ struct RegDesc {
   int wslot0;           // first wrench slot of its items
   int n_items;
   int* perm;            // template visiting order [M]
+  float4* tm4;          // template packed in that order [M]
+  float2* tmx;          // [M]
 };
 
 struct BatchArgs {
@@ -134,6 +141,9 @@ hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const flo
 hipError_t launch_pack_ref(const float* x, const float* y, const float* z, const float* aX, const float* wX, int64_t N,
                            const Derived* dv, float4* ref4, float* lw, hipStream_t st);
 hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st, bool sm);
+// Resident blocks per CU of the force kernel without energy or per-point
+// output (R points per lane, p mode, scalar-load variant).
+int force_blocks_per_cu(int R, int pm, bool sm);
 hipError_t launch_knn_desc_batch(const CloudDesc* clouds, const int2* blocks, int n_blocks, int k, hipStream_t st);
 hipError_t launch_moments_batch(const CloudDesc* clouds, int n_clouds, double* out, hipStream_t st);
 hipError_t launch_prepare_batch(const PrepDesc* d, int B, const PrepParams& P, Derived* outs, hipStream_t st);
@@ -144,11 +154,21 @@ hipError_t launch_update_batch(const double* wpart, const RegDesc* regs, int B, 
 hipError_t launch_init_multistart(const double* R0, int S, const double* mom_t, double* poses, hipStream_t st);
 hipError_t launch_argmin(const double* v, int n, int32_t* out, hipStream_t st);
 hipError_t launch_force_batch(const BatchArgs& B, int R, int pm, bool want_u, int grid, hipStream_t st);
-hipError_t launch_partition(const float* aY, int M, Derived* dv, int* perm, hipStream_t st);
-hipError_t launch_partition_batch(const RegDesc* regs, int B, Derived* dvs, hipStream_t st);
+// Template visiting order: perm = indices of aY in ascending order (stable).
+// ws must hold sort_perm_workspace(n, nseg) bytes (n points, nseg registrations).
+size_t sort_perm_workspace(int64_t n, int nseg);
+// Template copied into visiting order (x0, y0, z0, b) / (a, m), b from dv.
+hipError_t launch_pack_tmpl(const float* x, const float* y, const float* z, const float* aY, const float* mY, int M,
+                            const int* perm, const Derived* dv, float4* tm4, float2* tmx, hipStream_t st);
+hipError_t launch_pack_tmpl_batch(const RegDesc* regs, int B, int max_M, const Derived* dvs, hipStream_t st);
+hipError_t launch_sort_perm(const float* aY, int M, int* perm, void* ws, hipStream_t st);
+// Batch form: registration r sorts regs[r].aY into perm[off[r] .. off[r+1]) (off on the device, B + 1 entries).
+hipError_t launch_sort_perm_batch(const RegDesc* regs, int B, const int* off, int64_t total, int max_M, int* perm,
+                                  void* ws, hipStream_t st);
 hipError_t launch_force_mixed(const ForceArgs& A, bool want_f, hipStream_t st);
 int mixed_points_per_block();
-hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, float* f_out, hipStream_t st);
+// f_out[perm[ip]] (perm nullable) = sum over chunks of fpart[chunk][ip] (visiting order).
+hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, const int* perm, float* f_out, hipStream_t st);
 int force_points_per_block(int R);
 int force_tile_j();
 hipError_t launch_update(const double* wpart, int nblk, const double* pose_in, double* pose_out, Derived* dv, int t,

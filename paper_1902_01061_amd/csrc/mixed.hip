@@ -8,8 +8,9 @@
 // and V = (1, x_hi, y_hi, z_hi, x_lo, y_lo, z_lo, 0) (N x 8, each coordinate
 // split into a bf16 head and a bf16 tail), S = P V is a dense contraction
 // over the long reference dimension.  The pair weights are formed on the
-// FP32 VALU (one sub, one FMA, one exp2 per pair), rounded to bf16 (round to
-// nearest even, unbiased) and fed as the A operand of
+// FP32 VALU (one FMA and one exp2 per pair with the exponent expanded about
+// the block's range of b, as in the FP32 kernel; one sub more otherwise),
+// rounded to bf16 (round to nearest even, unbiased) and fed as the A operand of
 // v_mfma_f32_16x16x32_bf16; V is the B operand; accumulation is FP32 per
 // 256-point tile and FP64 across tiles.  Each wave owns 4 blocks of 16
 // template rows and reuses each B fragment four times.
@@ -32,8 +33,8 @@ constexpr int MX_PTS = MX_BT / 64 * MX_RB * 16;  // template points per block (2
 
 template <bool WF>
 __global__ __launch_bounds__(MX_BT) void force_mixed_kernel(ForceArgs A) {
-  __shared__ float2 s_bl[MX_TJ];           // (b_j, lw_j)
-  __shared__ __bf16 s_vt[8][MX_TJ];        // V transposed
+  __shared__ float2 s_bl[MX_TJ];           // (b_j, lw_j), or (d_j, lw_j - d_j^2) in the expanded form
+  __shared__ __bf16 s_vt[16][MX_TJ];       // V transposed; rows 8..15 stay zero (unused B columns)
   __shared__ double s_T[MX_BT / 64][64][8];
   __shared__ double s_red[(MX_BT / 64) * 13];
 
@@ -42,14 +43,36 @@ __global__ __launch_bounds__(MX_BT) void force_mixed_kernel(ForceArgs A) {
   const int chunk = blockIdx.x / n_iblk;
   const Derived& D = *A.dv;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int i_wave = iblk * MX_PTS + w * 64;  // first template point of this wave
+  const int i_wave = iblk * MX_PTS + w * 64;  // first template position of this wave
+  const bool packed = A.tm4 != nullptr;
+  // b of the template point at visiting position ip (< M)
+  auto b_at = [&](int ip) -> float {
+    return packed ? A.tm4[ip].w : (float)(((double)A.aY[ip] - D.abar) * D.bscale);
+  };
+
+#pragma unroll
+  for (int r = 8; r < 16; ++r) s_vt[r][threadIdx.x] = (__bf16)0.0f;
 
   float bi[MX_RB];
+  float lo = INFINITY, hi = -INFINITY;
 #pragma unroll
   for (int rb = 0; rb < MX_RB; ++rb) {
-    const int i = i_wave + rb * 16 + (l & 15);
-    bi[rb] = i < A.M ? (float)(((double)A.aY[i] - D.abar) * D.bscale) : 0.f;
+    const int ip = i_wave + rb * 16 + (l & 15);
+    bi[rb] = 0.f;
+    if (ip < A.M) {
+      bi[rb] = b_at(ip);
+      lo = fminf(lo, bi[rb]);
+      hi = fmaxf(hi, bi[rb]);
+    }
   }
+  // expanded exponent centred on the block's range of b (one FMA per weight)
+  block_range<MX_BT>(lo, hi, s_red);
+  float beta;
+  const bool expd = expanded_centre(lo, hi, D, false, beta);
+  float al[MX_RB];
+#pragma unroll
+  for (int rb = 0; rb < MX_RB; ++rb) al[rb] = 2.f * (bi[rb] - beta);
+
   double T[MX_RB][4];
 #pragma unroll
   for (int rb = 0; rb < MX_RB; ++rb)
@@ -69,7 +92,14 @@ __global__ __launch_bounds__(MX_BT) void force_mixed_kernel(ForceArgs A) {
         X = A.ref4[j];
         lw = A.reflw[j];
       }
-      s_bl[t] = make_float2(X.w, lw);
+      if (expd) {
+        // |d_j| capped so that 2 d_i d_j stays finite (weight 0 either way)
+        float d = X.w - beta;
+        if (fabsf(d) > 1e18f) d = copysignf(1e18f, d);
+        s_bl[t] = make_float2(d, __builtin_fmaf(-d, d, lw));
+      } else {
+        s_bl[t] = make_float2(X.w, lw);
+      }
       const __bf16 xh = (__bf16)X.x, yh = (__bf16)X.y, zh = (__bf16)X.z;
       s_vt[0][t] = (__bf16)1.0f;
       s_vt[1][t] = xh;
@@ -84,28 +114,41 @@ __global__ __launch_bounds__(MX_BT) void force_mixed_kernel(ForceArgs A) {
     f32x4 C[MX_RB];
 #pragma unroll
     for (int rb = 0; rb < MX_RB; ++rb) C[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (expd) {
 #pragma unroll 2
-    for (int kb = 0; kb < MX_TJ; kb += 32) {
-      const int jb = kb + kq;
-      float2 bl[8];
+      for (int kb = 0; kb < MX_TJ; kb += 32) {
+        const int jb = kb + kq;
+        float2 bl[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) bl[e] = s_bl[jb + e];
-      bf16x8 bfrag;
-      if (col < 8) {
-        bfrag = *reinterpret_cast<const bf16x8*>(&s_vt[col][jb]);
-      } else {
+        for (int e = 0; e < 8; ++e) bl[e] = s_bl[jb + e];
+        const bf16x8 bfrag = *reinterpret_cast<const bf16x8*>(&s_vt[col][jb]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bfrag[e] = (__bf16)0.0f;
-      }
+        for (int rb = 0; rb < MX_RB; ++rb) {
+          bf16x8 afrag;
 #pragma unroll
-      for (int rb = 0; rb < MX_RB; ++rb) {
-        bf16x8 afrag;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float db = bi[rb] - bl[e].x;
-          afrag[e] = (__bf16)__builtin_amdgcn_exp2f(__builtin_fmaf(-db, db, bl[e].y));
+          for (int e = 0; e < 8; ++e)
+            afrag[e] = (__bf16)__builtin_amdgcn_exp2f(__builtin_fmaf(al[rb], bl[e].x, bl[e].y));
+          C[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, C[rb], 0, 0, 0);
         }
-        C[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, C[rb], 0, 0, 0);
+      }
+    } else {
+#pragma unroll 2
+      for (int kb = 0; kb < MX_TJ; kb += 32) {
+        const int jb = kb + kq;
+        float2 bl[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bl[e] = s_bl[jb + e];
+        const bf16x8 bfrag = *reinterpret_cast<const bf16x8*>(&s_vt[col][jb]);
+#pragma unroll
+        for (int rb = 0; rb < MX_RB; ++rb) {
+          bf16x8 afrag;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float db = bi[rb] - bl[e].x;
+            afrag[e] = (__bf16)__builtin_amdgcn_exp2f(__builtin_fmaf(-db, db, bl[e].y));
+          }
+          C[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, C[rb], 0, 0, 0);
+        }
       }
     }
 #pragma unroll
@@ -137,22 +180,42 @@ __global__ __launch_bounds__(MX_BT) void force_mixed_kernel(ForceArgs A) {
   double wv[13];
 #pragma unroll
   for (int e = 0; e < 13; ++e) wv[e] = 0.0;
-  const int i = i_wave + l;  // row l of this wave's 64: rb = l / 16, row = l % 16
-  if (i < A.M) {
+  const int ip = i_wave + l;  // row l of this wave's 64: rb = l / 16, row = l % 16
+  if (ip < A.M) {
     const double* S = s_T[w][l];
-    const double ex = (double)A.y0x[i] - D.ybar0[0], ey = (double)A.y0y[i] - D.ybar0[1],
-                 ez = (double)A.y0z[i] - D.ybar0[2];
+    float x0, y0, z0;
+    double ai, mi;
+    if (packed) {
+      const float4 P4 = A.tm4[ip];
+      const float2 PX = A.tmx[ip];
+      x0 = P4.x;
+      y0 = P4.y;
+      z0 = P4.z;
+      ai = (double)PX.x;
+      mi = (double)PX.y;
+    } else {
+      x0 = A.y0x[ip];
+      y0 = A.y0y[ip];
+      z0 = A.y0z[ip];
+      ai = (double)A.aY[ip];
+      mi = A.mY ? (double)A.mY[ip] : 1.0;
+    }
+    const double ex = (double)x0 - D.ybar0[0], ey = (double)y0 - D.ybar0[1], ez = (double)z0 - D.ybar0[2];
     const double cx = sR[0] * ex + sR[1] * ey + sR[2] * ez;
     const double cy = sR[3] * ex + sR[4] * ey + sR[5] * ez;
     const double cz = sR[6] * ex + sR[7] * ey + sR[8] * ez;
     // the float32 point the FP32 path would use
     const double yx = (float)(cx + cv[0]), yy = (float)(cy + cv[1]), yz = (float)(cz + cv[2]);
-    const double gi = (D.g_mode == 1.0) ? (double)A.aY[i] / D.abar : 1.0;
-    const double k0 = coef * gi;
+    const double gi = (D.g_mode == 1.0) ? ai / D.abar : 1.0;
+    double sc = 1.0;
+    if (expd) {
+      const double dl = (double)(b_at(ip) - beta);
+      sc = exp2(-dl * dl);
+    }
+    const double k0 = coef * gi * sc;
     const double fx = k0 * (yx * S[0] - (S[1] + S[4]));
     const double fy = k0 * (yy * S[0] - (S[2] + S[5]));
     const double fz = k0 * (yz * S[0] - (S[3] + S[6]));
-    const double mi = A.mY ? (double)A.mY[i] : 1.0;
     wv[WR_F + 0] = mi * fx;
     wv[WR_F + 1] = mi * fy;
     wv[WR_F + 2] = mi * fz;
@@ -166,7 +229,7 @@ __global__ __launch_bounds__(MX_BT) void force_mixed_kernel(ForceArgs A) {
     wv[WR_K + 7] = fz * cy;
     wv[WR_K + 8] = fz * cz;
     if constexpr (WF) {
-      double* fp = A.fpart + ((int64_t)chunk * A.M + i) * 3;
+      double* fp = A.fpart + ((int64_t)chunk * A.M + ip) * 3;  // visiting order
       fp[0] = fx;
       fp[1] = fy;
       fp[2] = fz;

@@ -1,7 +1,9 @@
 // Launch shape of the pair-force kernel: template points per lane (R),
-// template blocks, reference chunks.  A default heuristic fills the chip
-// (about 8 blocks of 4 waves per CU); the autotuner can override it per
-// (M, N, p-mode) bucket.
+// template blocks, reference chunks.  The defaults are R = 2 (R = 1 for
+// small templates) and, for the FP32 force kernel, one wave of resident
+// blocks; the tile-multiple chunking here (8 blocks per CU) serves the
+// mixed-precision and adjoint kernels.  The autotuner can override R, the
+// blocks per CU and the load variant per (M, N, p-mode) bucket.
 #pragma once
 #include <stdint.h>
 
@@ -12,7 +14,8 @@ namespace sgr {
 
 struct Tiles {
   int R;
-  int sm;  // 1: reference read through scalar loads instead of LDS
+  int sm;   // 1: reference read through scalar loads instead of LDS
+  int bpc;  // FP32 force kernel: blocks per CU (0: one wave of resident blocks)
   int n_iblk;
   int n_chunks;
   int chunk_len;
@@ -37,6 +40,7 @@ struct TileTable {
     Tiles T;
     T.R = R;
     T.sm = sm;
+    T.bpc = 0;
     T.n_iblk = (M + bt * R - 1) / (bt * R);
     int nc = (target_blocks + T.n_iblk - 1) / T.n_iblk;
     const int max_nc = (N + tj - 1) / tj;
@@ -52,11 +56,12 @@ struct TileTable {
 
   Tiles pick(int M, int N, int pm) const {
     auto it = over.find(std::make_tuple(log2_bucket(M), log2_bucket(N), pm));
-    if (it != over.end())
-      return make(M, N, std::get<0>(it->second), std::get<1>(it->second) * n_cu, std::get<2>(it->second));
-    int R = 4;
-    if (M <= 256 * 4 * 16) R = 2;
-    if (M <= 256 * 2 * 4) R = 1;
+    if (it != over.end()) {
+      Tiles T = make(M, N, std::get<0>(it->second), std::get<1>(it->second) * n_cu, std::get<2>(it->second));
+      T.bpc = std::get<1>(it->second);
+      return T;
+    }
+    const int R = M <= 256 * 2 * 4 ? 1 : 2;
     return make(M, N, R, 8 * n_cu);
   }
 };

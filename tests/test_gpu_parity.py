@@ -120,6 +120,30 @@ def test_step_matches_oracle(sg, ctx, p, g_mode, eps, masses):
         assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * D
 
 
+@pytest.mark.parametrize("g_mode,masses", [(0, False), (1, True)])
+def test_step_far_curvature_blocks_match_oracle(sg, ctx, g_mode, masses):
+    """Template curvatures far from the reference mean in units of sigma
+    (|b| of 11 to 14, where exp2(2 b_i b_j) would overflow FP32) on most
+    points and spread over the whole range on the rest: the kernel visits the
+    template sorted by curvature, centres the expanded exponent on each
+    block's range, and falls back to the exact exponent on wide blocks."""
+    pr = random_pair(5000, 2900, seed=23)
+    rng = np.random.default_rng(5)
+    aX32 = rng.uniform(0.0, 0.3, pr.N).astype(np.float32)
+    far = rng.random(pr.M) < 0.7
+    aY32 = np.where(far, rng.uniform(0.25, 0.27, pr.M), rng.uniform(0.0, 0.3, pr.M)).astype(np.float32)
+    wX = rng.uniform(0.5, 2.0, pr.N).astype(np.float32).astype(np.float64) if masses else None
+    mY = rng.uniform(0.5, 2.0, pr.M).astype(np.float32).astype(np.float64) if masses else None
+    prm = O.Params(p=1.0, g_mode=g_mode, k=16, sigma=0.01, E=40)
+    pose = O.Pose(0.9, rot_axis_angle([0, 1, 1], 15.0), np.array([0.05, 0.1, -0.1]))
+    so, ora_pose, pout, wr, f = _one_step(sg, ctx, pr, prm, pose, 21, aX32, aY32, wX, mY)
+    e = _check_wrench(so, wr, f, pose.apply(pr.tmpl), mY)
+    print(f"far-curvature step errors e_f={e[0]:.2e} e_F={e[1]:.2e} e_K={e[2]:.2e}")
+    gp = O.Pose(pout[0], pout[1:10].reshape(3, 3), pout[10:13])
+    d = gp.apply(pr.tmpl) - ora_pose.apply(pr.tmpl)
+    assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * O.diameter(pr.ref)
+
+
 def test_step_full_size_config2(sg, ctx):
     """Bench-size one-step parity: f on sampled rows, F and K in full."""
     pr = config2()
