@@ -194,9 +194,54 @@ def extra_adjoint(sg, ctx):
     bwd()
     tf, _ = _timed(fwd, 20)
     tb, (gy, gm, gse) = _timed(bwd, 20)
-    return {"M": pr.M, "N": pr.N, "p": 2, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3,
-            "fwd_pairs_per_s": pr.M * pr.N / tf, "bwd_pairs_per_s": pr.M * pr.N / tb,
-            "grads_finite": bool(torch.isfinite(gy).all().item() and torch.isfinite(gse).all().item())}
+    out = {"M": pr.M, "N": pr.N, "p": 2, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3,
+           "fwd_pairs_per_s": pr.M * pr.N / tf, "bwd_pairs_per_s": pr.M * pr.N / tb,
+           "grads_finite": bool(torch.isfinite(gy).all().item() and torch.isfinite(gse).all().item())}
+
+    # 50 unrolled iterations with pose checkpoints every 10, differentiated
+    # w.r.t. (sigma, eps, initial pose); the loss is the squared pose error
+    # against the generating transform on the inlier template points.
+    E, K = 50, 10
+    a_t, mom_t = ctx.descriptors(tm, 16)
+    prm_u = sg.Params(p=2.0, k=16, sigma=sigma, eps=0.05 * L, E=E)
+    inl = pr.corr >= 0
+    Yi = torch.as_tensor(pr.tmpl[inl], dtype=torch.float64, device="cuda")
+    Zi = torch.as_tensor((pr.tmpl[inl].astype(np.float64) - pr.gt_t) @ pr.gt_R / pr.gt_s, dtype=torch.float64,
+                         device="cuda")
+
+    def loss_of(pose):
+        est = pose[0] * Yi @ pose[1:10].view(3, 3).T + pose[10:13]
+        return ((est - Zi) ** 2).sum(dim=1).mean()
+
+    def run(log_sigma):
+        ls = torch.tensor(log_sigma, dtype=torch.float64, requires_grad=True)
+        eps = torch.tensor(0.05 * L, dtype=torch.float64, requires_grad=True)
+        p0 = sg.pose_identity().requires_grad_(True)
+        pose = sg.UnrolledRegistration.apply(ls.exp(), eps, p0, ctx, tm, a_t, rf, a_r, mom_t, mom_r, prm_u, K)
+        lo = loss_of(pose)
+        lo.backward()
+        return float(lo.item()), float(ls.grad.item()), float(eps.grad.item())
+
+    run(np.log(sigma))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lo0, g0, ge0 = run(np.log(sigma))
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    pose_f, _ = ctx.unrolled_fwd(tm, a_t, rf, a_r, mom_t, mom_r, prm_u, K)
+    t_f, _ = _timed(lambda: ctx.unrolled_fwd(tm, a_t, rf, a_r, mom_t, mom_r, prm_u, K), 3)
+    # bandwidth tuning: a few gradient steps on log sigma, the first one of size 0.2
+    traj = [(sigma, lo0)]
+    ls, g = float(np.log(sigma)), g0
+    eta = 0.2 / max(abs(g), 1e-300)
+    for _ in range(4):
+        ls -= eta * g
+        lo, g, _ = run(ls)
+        traj.append((float(np.exp(ls)), lo))
+    out["unrolled"] = {"iterations": E, "checkpoint_every": K, "fwd_ms": t_f * 1e3,
+                       "fwd_plus_bwd_ms": t_fb * 1e3, "loss": lo0, "dloss_dlog_sigma": g0, "dloss_deps": ge0,
+                       "sigma_tuning": [{"sigma": a, "loss": b} for a, b in traj]}
+    return out
 
 
 def extra_scene(sg, ctx, cpu_rows: int):

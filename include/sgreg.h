@@ -211,6 +211,34 @@ int sgr_force_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
                   const double* mom_r, const sgr_params* prm, double G, const float* f, const float* grad_f,
                   const double* grad_wrench, float* grad_y, float* grad_m, double* grad_se, sgr_stream_t stream);
 
+/* Differentiable registration, forward (Sec. III-B iterated, eq. 12): E =
+ * prm->E iterations of the force (eqs. 3, 5, 10, 11) and the rigid update
+ * (eqs. 5.5, 6, 8, 9) from the pose in `pose` (device, updated in place),
+ * with the curvatures a_t, a_r (device float32) held constant and the input
+ * moments mom_t, mom_r (device float64[10], as sgr_descriptors returns).
+ * The pose before iterations 0, K, 2K, ... is stored in
+ * ckpt[ceil(E / K)][13] (device float64): only poses are checkpointed.
+ * sigma must be given (> 0); the FP32 force is used (the mixed flag is
+ * rejected) and the update's SVD starts cold, so that a segment recomputed
+ * from its checkpoint reproduces the forward poses bit for bit. */
+int sgr_unrolled_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                     const double* mom_t, const double* mom_r, const sgr_params* prm, int K, sgr_pose* pose,
+                     double* ckpt, sgr_stream_t stream);
+
+/* Reverse pass of sgr_unrolled_fwd: given grad_final[13] = dL/d(final
+ * pose) (device float64), writes grad_pose0[13] = dL/d(initial pose) and
+ * grad_se[2] = dL/d(sigma, eps) (device float64).  Walks the iterations
+ * backwards, recomputing each K-iteration segment from its checkpoint; per
+ * iteration: the per-point forces and wrench at that pose, the adjoint of
+ * the rigid update (Kabsch polar factor, scale, translation, re-
+ * orthonormalisation), the adjoint of the force field at the posed template
+ * (as sgr_force_bwd) and the pullback of its per-point gradient onto the
+ * pose.  Same arguments as the forward pass, which must have run with
+ * them.  Assumes every update was applied (status 0). */
+int sgr_unrolled_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                     const double* mom_t, const double* mom_r, const sgr_params* prm, int K, const double* ckpt,
+                     const double* grad_final, double* grad_pose0, double* grad_se, sgr_stream_t stream);
+
 /* B independent registrations of uneven sizes with shared parameters
  * (tmpls, refs: HOST arrays of B cloud views).  Descriptors of all 2B
  * clouds run in one launch; each iteration is one persistent launch over a

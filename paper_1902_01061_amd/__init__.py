@@ -16,8 +16,8 @@ import torch
 from . import _ffi
 from ._ffi import SgrCloud, SgrError, SgrParams, check, lib
 
-__all__ = ["Params", "Cloud", "Context", "Plan", "ForceField", "SgrError", "pose_identity", "pose_to_srt",
-           "pose_from_srt"]
+__all__ = ["Params", "Cloud", "Context", "Plan", "ForceField", "UnrolledRegistration", "SgrError", "pose_identity",
+           "pose_to_srt", "pose_from_srt"]
 
 lib()  # fail at import when the native library is absent
 
@@ -197,6 +197,32 @@ class Context:
                                   _ptr(gm), _ptr(gse), _stream(self.device)))
         return gy, gm, gse
 
+    def unrolled_fwd(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params, ckpt_every: int = 10,
+                     pose=None):
+        """params.E iterations with the curvatures held constant; returns the
+        final pose and the pose checkpoints [ceil(E / ckpt_every), 13]."""
+        pose = pose_identity(self.device) if pose is None else pose.to(self.device, torch.float64).clone()
+        pose = pose.contiguous()
+        n = (params.E + ckpt_every - 1) // ckpt_every if ckpt_every >= 1 else 1  # the library rejects < 1
+        ckpt = torch.empty((n, 13), dtype=torch.float64, device=self.device)
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_unrolled_fwd(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_t),
+                                     _ptr(mom_r), ctypes.byref(pr), int(ckpt_every), _ptr(pose), _ptr(ckpt),
+                                     _stream(self.device)))
+        return pose, ckpt
+
+    def unrolled_bwd(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params, ckpt_every: int, ckpt,
+                     grad_final):
+        """dL/d(initial pose) [13] and dL/d(sigma, eps) [2] from dL/d(final pose)."""
+        g0 = torch.empty(13, dtype=torch.float64, device=self.device)
+        gse = torch.empty(2, dtype=torch.float64, device=self.device)
+        gf = grad_final.to(self.device, torch.float64).contiguous()
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_unrolled_bwd(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_t),
+                                     _ptr(mom_r), ctypes.byref(pr), int(ckpt_every), _ptr(ckpt.contiguous()),
+                                     _ptr(gf), _ptr(g0), _ptr(gse), _stream(self.device)))
+        return g0, gse
+
     def register_batch(self, tmpls, refs, params: Params, poses=None, want_energy=True, stats=False):
         """B registrations in one batched call; returns (poses [B, 13], energy [B] or None, stats)."""
         B = len(tmpls)
@@ -300,3 +326,30 @@ class ForceField(torch.autograd.Function):
         gy, gm, gse = sctx.force_bwd(tm, a_t, ref, a_r, mom_r, prm, G, f, grad_f, grad_w, want_m=has_m,
                                      want_se=True)
         return (None, gy, gm if has_m else None, gse[0], gse[1], None, None, None, None, None, None)
+
+
+class UnrolledRegistration(torch.autograd.Function):
+    """Final pose of params.E registration iterations as a differentiable
+    function of the similarity spread sigma, the softening eps and the
+    initial pose (forward and reverse passes are the library's kernels; the
+    reverse pass recomputes each segment of ckpt_every iterations from the
+    pose checkpoints of the forward pass).  apply(sigma, eps, pose0, ctx,
+    tmpl, a_t, ref, a_r, mom_t, mom_r, params, ckpt_every) -> pose [13]."""
+
+    @staticmethod
+    def forward(fctx, sigma, eps, pose0, sctx, tmpl, a_t, ref, a_r, mom_t, mom_r, params, ckpt_every):
+        prm = dataclasses.replace(params, sigma=float(sigma), eps=float(eps))
+        pose, ckpt = sctx.unrolled_fwd(tmpl, a_t, ref, a_r, mom_t, mom_r, prm, ckpt_every, pose0.detach())
+        fctx.save_for_backward(ckpt)
+        fctx.args = (sctx, tmpl, a_t, ref, a_r, mom_t, mom_r, prm, ckpt_every)
+        fctx.like = (sigma, eps, pose0)
+        return pose
+
+    @staticmethod
+    def backward(fctx, grad_pose):
+        (ckpt,) = fctx.saved_tensors
+        sctx, tmpl, a_t, ref, a_r, mom_t, mom_r, prm, k = fctx.args
+        g0, gse = sctx.unrolled_bwd(tmpl, a_t, ref, a_r, mom_t, mom_r, prm, k, ckpt, grad_pose)
+        sigma, eps, pose0 = fctx.like
+        as_like = lambda g, x: g.to(x.device, x.dtype) if torch.is_tensor(x) else g
+        return (as_like(gse[0], sigma), as_like(gse[1], eps), as_like(g0, pose0)) + (None,) * 9

@@ -61,6 +61,8 @@ SIGNATURES = {
     "sgr_tiles_load": [P, ctypes.c_char_p],
     "sgr_multistart": [P, CP, CP, PP, I, P, P, P, P, P],
     "sgr_force_bwd": [P, CP, P, CP, P, P, PP, D, P, P, P, P, P, P, P],
+    "sgr_unrolled_fwd": [P, CP, P, CP, P, P, P, PP, I, P, P, P],
+    "sgr_unrolled_bwd": [P, CP, P, CP, P, P, P, PP, I, P, P, P, P, P],
 }
 
 

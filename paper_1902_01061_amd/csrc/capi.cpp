@@ -391,6 +391,91 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   return SGR_OK;
 }
 
+
+// ------------------------------------------------- unrolled differentiation
+// Host copy of G_t (eq. 12), as the force kernel evaluates it.
+double G_host(const sgr_params* prm, int t) {
+  return 0.1 * prm->G1 + 0.9 * prm->G1 / (1.0 + std::exp(-(((double)t - 1.0) - 0.5 * prm->E)));
+}
+
+int check_unrolled(const sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                   const double* mom_t, const double* mom_r, const sgr_params* prm, int K) {
+  if (!ctx || !a_t || !a_r || !mom_t || !mom_r) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (is_mixed(prm)) return fail(SGR_EINVAL, "the unrolled registration uses the FP32 force");
+  if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
+  if (K < 1) return fail(SGR_EINVAL, "the checkpoint interval must be >= 1");
+  if (!(prm->sigma > 0)) return fail(SGR_EINVAL, "the unrolled registration needs an explicit sigma > 0");
+  return SGR_OK;
+}
+
+// State of an unrolled registration in the context workspace: the same
+// set-up and force launch as sgr_register's iteration loop.
+struct Unrolled {
+  int M = 0, N = 0, pm = 1;
+  Tiles T{};
+  FLaunch L{};
+  Derived* dv = nullptr;
+  float4* ref4 = nullptr;
+  float* lw = nullptr;
+  int* perm = nullptr;
+  char* sws = nullptr;
+  float4* tm4 = nullptr;
+  float2* tmx = nullptr;
+  double* wpart = nullptr;
+  double* fpart = nullptr;  // per-point forces (backward only)
+};
+
+void unrolled_shape(const sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm,
+                    Unrolled& U) {
+  U.M = (int)tmpl->n;
+  U.N = (int)ref->n;
+  U.pm = pmode_of(prm->p);
+  U.T = ctx->tiles.pick(U.M, U.N, U.pm);
+  U.L = force_shape(ctx, U.M, U.N, U.T, U.pm);
+}
+
+void carve_unrolled(Carve& c, Unrolled& U, bool with_f) {
+  U.dv = c.take<Derived>(1);
+  U.ref4 = c.take<float4>(pad_n(U.N));
+  U.lw = c.take<float>(pad_n(U.N));
+  U.perm = c.take<int>(U.M);
+  U.sws = c.take<char>(sort_perm_workspace(U.M, 1));
+  U.tm4 = c.take<float4>(U.M);
+  U.tmx = c.take<float2>(U.M);
+  U.wpart = c.take<double>((size_t)U.L.slots * WR_STRIDE);
+  U.fpart = with_f ? c.take<double>((size_t)U.L.n_chunks * U.M * 3) : nullptr;
+}
+
+int setup_unrolled(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                   const double* mom_t, const double* mom_r, const sgr_params* prm, const Unrolled& U,
+                   hipStream_t st) {
+  // cold-started SVD in the update: a recomputed segment then reproduces the
+  // forward poses bit for bit
+  PrepParams P = prep_of(prm);
+  P.cold_svd = 1;
+  HIPCHK(launch_prepare(a_r, ref->m, U.N, a_t, tmpl->m, U.M, mom_t, mom_r, P, U.dv, st));
+  HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, a_r, ref->m, U.N, U.dv, U.ref4, U.lw, st));
+  HIPCHK(launch_sort_perm(a_t, U.M, U.perm, U.sws, st));
+  HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, U.M, U.perm, U.dv, U.tm4, U.tmx, st));
+  return SGR_OK;
+}
+
+// Force of iteration t at pose_in.  With pose_out: the rigid update into
+// pose_out.  With W_out: the wrench (no update).  With f_out: per-point forces.
+int unrolled_force(const sgr_cloud* tmpl, const float* a_t, const Unrolled& U, int t, const double* pose_in,
+                   double* pose_out, double* W_out, float* f_out, hipStream_t st) {
+  const bool wf = f_out != nullptr;
+  ForceArgs A{tmpl->x, tmpl->y, tmpl->z, a_t, tmpl->m, U.ref4, U.lw, pose_in, U.dv, U.M, U.N,
+              U.T.chunk_len, U.T.n_chunks, t, 0.0, U.wpart, wf ? U.fpart : nullptr, U.perm, U.tm4, U.tmx};
+  HIPCHK(run_force(A, U.T, U.L, U.pm, false, wf, st));
+  if (wf) HIPCHK(launch_reduce_f(U.fpart, U.L.n_chunks, U.M, U.perm, f_out, st));
+  HIPCHK(launch_update(U.wpart, U.L.slots, pose_in, pose_out, U.dv, t, 0.0, pose_out ? 1 : 0, W_out, nullptr, st));
+  return SGR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1125,6 +1210,116 @@ int sgr_multistart(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, co
   }
   HIPCHK(hipSetDevice(ctx->device));
   return run_batch(ctx, in, prm, (double*)poses, R0, energy_out, nullptr, best_out, (hipStream_t)stream);
+}
+
+
+int sgr_unrolled_fwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                     const double* mom_t, const double* mom_r, const sgr_params* prm, int K, sgr_pose* pose,
+                     double* ckpt, sgr_stream_t stream) {
+  if (int e = check_unrolled(ctx, tmpl, a_t, ref, a_r, mom_t, mom_r, prm, K)) return e;
+  if (!pose || !ckpt) return fail(SGR_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  Unrolled U;
+  unrolled_shape(ctx, tmpl, ref, prm, U);
+  Carve cv{nullptr};
+  carve_unrolled(cv, U, false);
+  if (int e = ensure_ws(ctx, cv.off)) return e;
+  Carve w{ctx->ws};
+  carve_unrolled(w, U, false);
+  if (int e = setup_unrolled(tmpl, a_t, ref, a_r, mom_t, mom_r, prm, U, st)) return e;
+  double* P = (double*)pose;
+  for (int t = 0; t < prm->E; ++t) {
+    if (t % K == 0)
+      HIPCHK(hipMemcpyAsync(ckpt + (size_t)(t / K) * 13, P, 13 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (int e = unrolled_force(tmpl, a_t, U, t, P, P, nullptr, nullptr, st)) return e;
+  }
+  return SGR_OK;
+}
+
+int sgr_unrolled_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                     const double* mom_t, const double* mom_r, const sgr_params* prm, int K, const double* ckpt,
+                     const double* grad_final, double* grad_pose0, double* grad_se, sgr_stream_t stream) {
+  if (int e = check_unrolled(ctx, tmpl, a_t, ref, a_r, mom_t, mom_r, prm, K)) return e;
+  if (!ckpt || !grad_final || !grad_pose0 || !grad_se) return fail(SGR_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  Unrolled U;
+  unrolled_shape(ctx, tmpl, ref, prm, U);
+  const int M = U.M, N = U.N, E = prm->E;
+  // the adjoint kernels use tile-multiple chunks (at most 4 points per lane)
+  Tiles TA = U.T;
+  if (TA.R > 4) TA = TileTable::make(M, N, 4, 8 * ctx->n_cu);
+  const int nseg = (E + K - 1) / K;
+  const int npg = pose_grad_blocks(M);
+  auto carve_rest = [&](Carve& c, double** seg, double** W, double** g0, double** g1, double** gW, double** gse_t,
+                        double** mom_y, Derived** dva, double** fsum, double** pg, float** Y, float** f, float** gf0,
+                        float** gy, float** lam, double** ypart, double** spart) {
+    carve_unrolled(c, U, true);
+    *seg = c.take<double>((size_t)(K + 1) * 13);
+    *W = c.take<double>(16);
+    *g0 = c.take<double>(16);
+    *g1 = c.take<double>(16);
+    *gW = c.take<double>(16);
+    *gse_t = c.take<double>(2);
+    *mom_y = c.take<double>(16);
+    *dva = c.take<Derived>(1);
+    *fsum = c.take<double>(16);
+    *pg = c.take<double>((size_t)npg * 12);
+    *Y = c.take<float>((size_t)M * 3);
+    *f = c.take<float>((size_t)M * 3);
+    *gf0 = c.take<float>((size_t)M * 3);
+    *gy = c.take<float>((size_t)M * 3);
+    *lam = c.take<float>((size_t)M * 3);
+    *ypart = c.take<double>((size_t)TA.n_chunks * M * 4);
+    *spart = c.take<double>((size_t)TA.nblk * 2);
+  };
+  double *seg, *W, *g0, *g1, *gW, *gse_t, *mom_y, *fsum, *pg, *ypart, *spart;
+  Derived* dva;
+  float *Y, *f, *gf0, *gy, *lam;
+  {
+    Carve cv{nullptr};
+    carve_rest(cv, &seg, &W, &g0, &g1, &gW, &gse_t, &mom_y, &dva, &fsum, &pg, &Y, &f, &gf0, &gy, &lam, &ypart, &spart);
+    if (int e = ensure_ws(ctx, cv.off)) return e;
+  }
+  Carve w{ctx->ws};
+  carve_rest(w, &seg, &W, &g0, &g1, &gW, &gse_t, &mom_y, &dva, &fsum, &pg, &Y, &f, &gf0, &gy, &lam, &ypart, &spart);
+  if (int e = setup_unrolled(tmpl, a_t, ref, a_r, mom_t, mom_r, prm, U, st)) return e;
+  HIPCHK(launch_fill_f(gf0, (int64_t)M * 3, 0.f, st));
+  HIPCHK(launch_fill(grad_se, 2, 0.0, st));
+  HIPCHK(hipMemcpyAsync(g0, grad_final, 13 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  float* Yx = Y;
+  float* Yy = Y + M;
+  float* Yz = Y + 2 * (size_t)M;
+  for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+    const int t0 = sgi * K, t1 = std::min(E, t0 + K);
+    // poses of this segment, recomputed from its checkpoint
+    HIPCHK(hipMemcpyAsync(seg, ckpt + (size_t)sgi * 13, 13 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    for (int t = t0; t < t1 - 1; ++t)
+      if (int e = unrolled_force(tmpl, a_t, U, t, seg + (size_t)(t - t0) * 13, seg + (size_t)(t - t0 + 1) * 13,
+                                 nullptr, nullptr, st))
+        return e;
+    for (int t = t1 - 1; t >= t0; --t) {
+      const double* Pt = seg + (size_t)(t - t0) * 13;
+      // forward quantities of iteration t: per-point forces and the wrench
+      if (int e = unrolled_force(tmpl, a_t, U, t, Pt, nullptr, W, f, st)) return e;
+      // update: cotangent of the pose it starts from and of (F, K)
+      HIPCHK(launch_update_bwd(Pt, W, g0, U.dv, g1, gW, st));
+      // force field at the posed template: per-point gradient and (sigma, eps)
+      HIPCHK(launch_pose_points(tmpl->x, tmpl->y, tmpl->z, M, Pt, Yx, Yy, Yz, st));
+      HIPCHK(launch_moments(Yx, Yy, Yz, M, mom_y, st));
+      HIPCHK(launch_prepare(a_r, ref->m, N, a_t, tmpl->m, M, mom_y, mom_r, prep_of(prm), dva, st));
+      AdjArgs AA{Yx, Yy, Yz, a_t, tmpl->m, U.ref4, U.lw, dva, M, N, TA.chunk_len, TA.n_chunks, TA.nblk,
+                 U.pm == 1, G_host(prm, t), f, gf0, gW, lam, ypart, spart, gy, nullptr, gse_t};
+      HIPCHK(launch_adjoint(AA, TA.R, fsum, st));
+      HIPCHK(launch_axpy(gse_t, 2, grad_se, st));
+      // y_i = s R y0_i + t: per-point gradient onto the pose
+      HIPCHK(launch_pose_grad(gy, tmpl->x, tmpl->y, tmpl->z, M, Pt, pg, g1, st));
+      std::swap(g0, g1);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(grad_pose0, g0, 13 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  return SGR_OK;
 }
 
 }  // extern "C"

@@ -40,7 +40,7 @@ struct Derived {
   double bref_lo;    // smallest and largest b of the reference (as rounded to FP32)
   double bref_hi;
   double Vw[9];      // right singular vectors of the last cross-covariance (warm start)
-  int32_t pad3;
+  int32_t cold_svd;  // 1: no warm start of the update's SVD
   int32_t pad2;
   int32_t status;    // 0 ok; bit flags set by the update kernel
   int32_t pad;

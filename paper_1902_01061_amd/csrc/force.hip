@@ -114,7 +114,7 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   }
   for (int e = 0; e < 9; ++e) D.Vw[e] = (e % 4 == 0) ? 1.0 : 0.0;
   D.pad2 = 0;
-  D.pad3 = 0;
+  D.cold_svd = P.cold_svd;
   if (!(D.lamX > 0) || !(D.lamY0 > 0) || !(D.sigma > 0) || !(D.Z > 0) || !(D.Mtot > 0) ||
       (P.g_mode == 1 && !(abar > 0)))
     st |= ST_DEGENERATE;

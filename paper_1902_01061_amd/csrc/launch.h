@@ -16,6 +16,7 @@ struct PrepParams {
   double dt2;
   int32_t E;
   int32_t g_mode;
+  int32_t cold_svd = 0;  // 1: the update's SVD starts cold (a deterministic function of C)
 };
 
 struct ForceArgs {
@@ -124,6 +125,19 @@ struct AdjArgs {
 };
 
 hipError_t launch_adjoint(const AdjArgs& A, int R, double* fsum_tmp, hipStream_t st);
+// Adjoint of one rigid update: gpose_in[13] and gW[16] from gpose_out[13]
+// (pose_in the pose the update started from, W its wrench).
+hipError_t launch_update_bwd(const double* pose_in, const double* W, const double* gpose_out, const Derived* dv,
+                             double* gpose_in, double* gW, hipStream_t st);
+// o = s R p + t for the template points (FP32 out).
+hipError_t launch_pose_points(const float* x, const float* y, const float* z, int M, const double* pose, float* ox,
+                              float* oy, float* oz, hipStream_t st);
+// gpose += pose cotangent of the per-point gradient gy [M][3] of y = s R p + t;
+// part needs pose_grad_blocks(M) * 12 doubles.
+int pose_grad_blocks(int M);
+hipError_t launch_pose_grad(const float* gy, const float* x, const float* y, const float* z, int M, const double* pose,
+                            double* part, double* gpose, hipStream_t st);
+hipError_t launch_axpy(const double* x, int n, double* y, hipStream_t st);
 hipError_t launch_fill(double* p, int n, double v, hipStream_t st);
 hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_identity_pose(double* pose, hipStream_t st);
