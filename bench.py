@@ -294,6 +294,36 @@ def extra_scene(sg, ctx, cpu_rows: int):
         out[name]["one_step_force_rel_err_vs_oracle"] = float(np.linalg.norm(f - f_ora) / np.linalg.norm(f_ora))
         plan.close()
     out["oracle_rows_sampled"] = int(cpu_rows)
+
+    # Change detection: template points with nothing within tau of their
+    # registered position (added objects), and the reverse under the inverse
+    # pose (removed objects), at the generating transform and at the FP32
+    # registration's pose, scored against the scene's own change labels.
+    tau, s_min = 0.05, 0.0
+    sigma = float(a_r.double().std(unbiased=False).item())
+    R_inv = pr.gt_R.T
+    gt = torch.tensor(np.concatenate([[1.0 / pr.gt_s], R_inv.reshape(-1), -(R_inv @ pr.gt_t) / pr.gt_s]),
+                      dtype=torch.float64, device="cuda")
+    # template points that fall inside the reference camera's image (no
+    # occlusion test): outside it the reference has no data at all
+    Xc = (pr.tmpl.astype(np.float64) - pr.gt_t) @ pr.gt_R / pr.gt_s
+    with np.errstate(divide="ignore", invalid="ignore"):
+        in_view = (Xc[:, 2] > 0) & (np.abs(Xc[:, 0] / Xc[:, 2]) <= 319.5 / 525) & \
+                  (np.abs(Xc[:, 1] / Xc[:, 2]) <= 239.5 / 525)
+    cd = {"tau": tau, "template_points_in_reference_view": int(in_view.sum())}
+    for name, pose in (("generating_transform", gt), ("fp32_registration", res["fp32"][1])):
+        dt_f, (f, _, _) = _timed(lambda: ctx.change_detect(tm, a_t, rf, a_r, pose, tau, sigma, s_min), 3)
+        inv = sg.pose_inverse(pose)
+        dt_r, (g, _, _) = _timed(lambda: ctx.change_detect(rf, a_r, tm, a_t, inv, tau, sigma, s_min), 3)
+        hit = (f.cpu().numpy() & 1) > 0
+        ghit = (g.cpu().numpy() & 1) > 0
+        cd[name] = {"ms_template_to_reference": dt_f * 1e3, "ms_reference_to_template": dt_r * 1e3,
+                    "added_recall": float(hit[pr.changed].mean()),
+                    "flag_rate_unchanged_in_reference_view": float(hit[~pr.changed & in_view].mean()),
+                    "flag_rate_unchanged_all": float(hit[~pr.changed].mean()),
+                    "removed_recall": float(ghit[pr.ref_changed].mean()),
+                    "reverse_flag_rate_unchanged": float(ghit[~pr.ref_changed].mean())}
+    out["change_detection"] = cd
     return out
 
 

@@ -239,6 +239,27 @@ int sgr_unrolled_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
                      const double* mom_t, const double* mom_r, const sgr_params* prm, int K, const double* ckpt,
                      const double* grad_final, double* grad_pose0, double* grad_se, sgr_stream_t stream);
 
+/* Change detection after registration (the application of Sec. I and
+ * Sec. IV: registered template parts with no similar reference part nearby
+ * show the change).  For every template point i, posed by `pose` (device,
+ * 13 float64) as T(y_i) = s ((R_r0 y_0 + R_r1 y_1) + R_r2 y_2) + t_r in FP64
+ * with every operation rounded on its own, then rounded to float32, and with
+ * j its nearest reference point (float32 key ((dx*dx + dy*dy) + dz*dz),
+ * ties by index, as the descriptors' neighbours):
+ *   flags_out[i] bit 0: key > (float)(tau^2)        (nothing within tau),
+ *   flags_out[i] bit 1: (a_i - a_j)^2 > sigma^2 (-ln s_min) in FP64, i.e.
+ *                       the shape similarity of eq. 3 is below s_min.
+ * tau > 0 (+inf disables the distance test); s_min <= 0 disables the shape
+ * test, else s_min <= 1 and sigma > 0.  a_t, a_r: curvatures (device
+ * float32).  Outputs (device): flags_out[M] uint8; nn_out[M] int32 and
+ * d2_out[M] float32 (the key), both nullable.  A template point with a
+ * non-finite posed coordinate gets nn -1 and bit 0.  For the reverse
+ * direction (reference parts missing from the template) swap the clouds and
+ * pass the inverse pose. */
+int sgr_change_detect(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                      const sgr_pose* pose, double tau, double sigma, double s_min, uint8_t* flags_out,
+                      int32_t* nn_out, float* d2_out, sgr_stream_t stream);
+
 /* B independent registrations of uneven sizes with shared parameters
  * (tmpls, refs: HOST arrays of B cloud views).  Descriptors of all 2B
  * clouds run in one launch; each iteration is one persistent launch over a

@@ -397,3 +397,82 @@ def knn_c(P: np.ndarray, k: int, queries=None) -> np.ndarray:
     out = np.empty((len(q), k), dtype=np.int64)
     _clib().ora_knn(len(P), _ptr(P), int(k), len(q), _ptr(q), _ptr(out))
     return out
+
+
+# ------------------------------------------------------- change detection
+def posed32(Y0, pose: "Pose") -> np.ndarray:
+    """T(y) = s R y + t in FP64 with every operation rounded on its own, in
+    the order s ((R_r0 y_0 + R_r1 y_1) + R_r2 y_2) + t_r, then rounded to
+    float32: the posed template on which change detection decides."""
+    Y = np.asarray(Y0, np.float32).astype(np.float64)
+    out = np.empty_like(Y)
+    for r in range(3):
+        a = pose.R[r, 0] * Y[:, 0]
+        b = pose.R[r, 1] * Y[:, 1]
+        c = pose.R[r, 2] * Y[:, 2]
+        out[:, r] = pose.s * ((a + b) + c) + pose.t[r]
+    return out.astype(np.float32)
+
+
+def nearest(Q: np.ndarray, X: np.ndarray):
+    """Nearest row of X to each row of Q by (float32 key of sqdist32, index).
+    Candidates from a float64 k-d tree are ranked by the key; a query whose
+    best key is not clearly inside the candidate radius is redone by brute
+    force, so the result is exact.  Non-finite queries: (-1, inf)."""
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    nq = Q.shape[0]
+    nn = np.full(nq, -1, dtype=np.int64)
+    key = np.full(nq, np.inf, dtype=np.float32)
+    ok = np.isfinite(Q).all(axis=1)
+    idx_all = np.arange(X.shape[0])
+
+    def brute(i):
+        d = sqdist32(X, Q[i])
+        j = int(np.lexsort((idx_all, d))[0])
+        return j, d[j]
+
+    if X.shape[0] <= 64:
+        for i in np.nonzero(ok)[0]:
+            nn[i], key[i] = brute(i)
+        return nn, key
+    from scipy.spatial import cKDTree
+
+    tree = cKDTree(X.astype(np.float64))
+    kk = min(8, X.shape[0])
+    qi = np.nonzero(ok)[0]
+    dd, cand = tree.query(Q[qi].astype(np.float64), k=kk)
+    # float32 keys of all candidates, in the same operation order as sqdist32
+    d = X[cand] - Q[qi][:, None, :]
+    k32 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    o = np.lexsort((cand, k32), axis=-1)[:, 0]      # primary key, ties by index
+    rows = np.arange(len(qi))
+    best, bidx = k32[rows, o], cand[rows, o]
+    # every point outside the candidate set lies at float64 distance
+    # >= dd[:, -1]; float32 rounding moves keys by far less unless the radii
+    # nearly coincide, in which case the query is redone by brute force
+    clear = best.astype(np.float64) * (1 + 1e-5) + 1e-30 < dd[:, -1] ** 2
+    nn[qi[clear]], key[qi[clear]] = bidx[clear], best[clear]
+    for i in qi[~clear]:
+        nn[i], key[i] = brute(i)
+    return nn, key
+
+
+def change_flags(Y0, aY, X, aX, pose: "Pose", tau: float, sigma: float, s_min: float):
+    """Change detection after registration (Sec. I and IV: registered
+    template parts without a similar reference part nearby).  Per template
+    point, with j its nearest reference point to the posed point:
+    bit 0: float32 key > float32(tau^2); bit 1 (s_min > 0): (a_i - a_j)^2
+    in FP64 > sigma^2 (-ln s_min), i.e. the shape similarity of eq. 3 is
+    below s_min.  Returns (flags uint8, nn int64, key float32)."""
+    Q = posed32(Y0, pose)
+    nn, key = nearest(Q, X)
+    tau2 = np.float32(tau * tau)
+    thr = sigma * sigma * (-math.log(s_min)) if s_min > 0 else math.inf
+    flags = np.zeros(len(Q), dtype=np.uint8)
+    valid = nn >= 0
+    flags[~valid] = 1
+    flags[valid & (key > tau2)] |= 1
+    da = np.asarray(aY, np.float32).astype(np.float64) - np.asarray(aX, np.float32).astype(np.float64)[np.maximum(nn, 0)]
+    flags[valid & (da * da > thr)] |= 2
+    return flags, nn, key

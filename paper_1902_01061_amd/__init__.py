@@ -17,7 +17,7 @@ from . import _ffi
 from ._ffi import SgrCloud, SgrError, SgrParams, check, lib
 
 __all__ = ["Params", "Cloud", "Context", "Plan", "ForceField", "UnrolledRegistration", "SgrError", "pose_identity",
-           "pose_to_srt", "pose_from_srt"]
+           "pose_inverse", "pose_to_srt", "pose_from_srt"]
 
 lib()  # fail at import when the native library is absent
 
@@ -83,6 +83,16 @@ class Cloud:
         s = self.soa
         return SgrCloud(s[0].data_ptr(), s[1].data_ptr(), s[2].data_ptr(),
                         self.m.data_ptr() if self.m is not None else None, self.n)
+
+
+def pose_inverse(pose: torch.Tensor) -> torch.Tensor:
+    """The pose of T^-1(x) = (1/s) R^T (x - t) (13 float64, same layout)."""
+    s, R, t = pose[0], pose[1:10].view(3, 3), pose[10:13]
+    out = torch.empty_like(pose)
+    out[0] = 1.0 / s
+    out[1:10] = R.T.reshape(-1)
+    out[10:13] = -(R.T @ t) / s
+    return out
 
 
 def pose_identity(device=None) -> torch.Tensor:
@@ -222,6 +232,20 @@ class Context:
                                      _ptr(mom_r), ctypes.byref(pr), int(ckpt_every), _ptr(ckpt.contiguous()),
                                      _ptr(gf), _ptr(g0), _ptr(gse), _stream(self.device)))
         return g0, gse
+
+    def change_detect(self, tmpl: Cloud, a_t, ref: Cloud, a_r, pose, tau: float, sigma: float = 0.0,
+                      s_min: float = 0.0):
+        """Per template point: flags (uint8; bit 0 nothing within tau, bit 1
+        nearest point's shape similarity below s_min), nearest reference
+        index (int32) and its float32 squared distance."""
+        flags = torch.empty(tmpl.n, dtype=torch.uint8, device=self.device)
+        nn = torch.empty(tmpl.n, dtype=torch.int32, device=self.device)
+        d2 = torch.empty(tmpl.n, dtype=torch.float32, device=self.device)
+        ct, cr = tmpl.c(), ref.c()
+        check(lib().sgr_change_detect(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r),
+                                      _ptr(pose.to(self.device, torch.float64).contiguous()), float(tau), float(sigma),
+                                      float(s_min), _ptr(flags), _ptr(nn), _ptr(d2), _stream(self.device)))
+        return flags, nn, d2
 
     def register_batch(self, tmpls, refs, params: Params, poses=None, want_energy=True, stats=False):
         """B registrations in one batched call; returns (poses [B, 13], energy [B] or None, stats)."""

@@ -63,6 +63,7 @@ SIGNATURES = {
     "sgr_force_bwd": [P, CP, P, CP, P, P, PP, D, P, P, P, P, P, P, P],
     "sgr_unrolled_fwd": [P, CP, P, CP, P, P, P, PP, I, P, P, P],
     "sgr_unrolled_bwd": [P, CP, P, CP, P, P, P, PP, I, P, P, P, P, P],
+    "sgr_change_detect": [P, CP, P, CP, P, P, D, D, D, P, P, P, P],
 }
 
 

@@ -12,15 +12,22 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libsgreg.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["descriptors.hip", "force.hip", "pose.hip", "residual.hip", "adjoint.hip", "mixed.hip", "knn_grid.hip", "sort.hip", "capi.cpp"]
+SOURCES = ["descriptors.hip", "force.hip", "pose.hip", "residual.hip", "adjoint.hip", "mixed.hip", "knn_grid.hip",
+           "sort.hip", "change.hip", "capi.cpp"]
+# Translation units whose results are integers decided by floating point
+# (neighbour ranks by the float32 key (dx*dx + dy*dy) + dz*dz, change flags)
+# are compiled without fused multiply-add, so that every operation is
+# rounded on its own exactly as the key is defined; the others may fuse.
+NO_FUSION = {"descriptors.hip", "knn_grid.hip", "change.hip"}
 # Packed FP32 instructions are disabled for every HIP translation unit.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-         "-packed-fp32-ops", "-ffp-contract=fast", "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include")]
+         "-packed-fp32-ops", "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include")]
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    contract = "-ffp-contract=off" if src in NO_FUSION else "-ffp-contract=fast"
+    cmd = ["hipcc", *FLAGS, contract, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")

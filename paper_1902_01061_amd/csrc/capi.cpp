@@ -1322,4 +1322,35 @@ int sgr_unrolled_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
   return SGR_OK;
 }
 
+
+int sgr_change_detect(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                      const sgr_pose* pose, double tau, double sigma, double s_min, uint8_t* flags_out,
+                      int32_t* nn_out, float* d2_out, sgr_stream_t stream) {
+  if (!ctx || !a_t || !a_r || !pose || !flags_out) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (!(tau > 0)) return fail(SGR_EINVAL, "tau must be > 0 (+inf disables the distance test)");
+  if (s_min > 1.0) return fail(SGR_EINVAL, "s_min must be <= 1 (<= 0 disables the shape test)");
+  if (s_min > 0 && !(sigma > 0 && std::isfinite(sigma))) return fail(SGR_EINVAL, "the shape test needs sigma > 0");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  Carve cv{nullptr};
+  cv.take<char>(change_workspace(M, N));
+  cv.take<int32_t>(M);
+  cv.take<float>(M);
+  if (int e = ensure_ws(ctx, cv.off)) return e;
+  Carve w{ctx->ws};
+  char* cws = w.take<char>(change_workspace(M, N));
+  int32_t* nn = nn_out ? nn_out : w.take<int32_t>(M);
+  float* d2 = d2_out ? d2_out : w.take<float>(M);
+  // both thresholds rounded once, as a reader would: tau^2 to float32, and
+  // sigma^2 (-ln s_min) in FP64
+  const float tau2 = (float)(tau * tau);
+  const double thr = s_min > 0 ? sigma * sigma * (-std::log(s_min)) : INFINITY;
+  HIPCHK(launch_change(tmpl->x, tmpl->y, tmpl->z, a_t, M, ref->x, ref->y, ref->z, a_r, N, (const double*)pose, tau2,
+                       thr, flags_out, nn, d2, cws, st));
+  return SGR_OK;
+}
+
 }  // extern "C"

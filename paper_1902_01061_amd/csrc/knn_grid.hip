@@ -312,8 +312,20 @@ size_t grid_knn_workspace(int n, int k) {
   return b;
 }
 
-hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n, int k, float* a_out,
-                           int32_t* idx_out, void* ws, hipStream_t st) {
+namespace {
+
+struct GridBufs {
+  GridInfo* gi;
+  int* cell_of;
+  int* counts;
+  int* cursor;
+  int* starts;
+  int* bsum;
+  float4* spts;
+  int32_t* nbr;
+};
+
+GridBufs carve_grid(void* ws, int n, int k) {
   const int max_cells = grid_max_cells(n);
   const int nb = (max_cells + SCAN_B - 1) / SCAN_B;
   char* p = (char*)ws;
@@ -322,34 +334,127 @@ hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n
     p += (bytes + 255) & ~size_t(255);
     return (void*)r;
   };
-  GridInfo* gi = (GridInfo*)take(sizeof(GridInfo));
-  int* cell_of = (int*)take(sizeof(int) * (size_t)n);
-  int* counts = (int*)take(sizeof(int) * (size_t)max_cells);
-  int* cursor = (int*)take(sizeof(int) * (size_t)max_cells);
-  int* starts = (int*)take(sizeof(int) * ((size_t)max_cells + 1));
-  int* bsum = (int*)take(sizeof(int) * ((size_t)nb + 1));
-  float4* spts = (float4*)take(sizeof(float4) * (size_t)n);
-  int32_t* nbr = (int32_t*)take(sizeof(int32_t) * (size_t)n * k);
-  int32_t* lists = idx_out ? idx_out : nbr;
+  GridBufs B;
+  B.gi = (GridInfo*)take(sizeof(GridInfo));
+  B.cell_of = (int*)take(sizeof(int) * (size_t)n);
+  B.counts = (int*)take(sizeof(int) * (size_t)max_cells);
+  B.cursor = (int*)take(sizeof(int) * (size_t)max_cells);
+  B.starts = (int*)take(sizeof(int) * ((size_t)max_cells + 1));
+  B.bsum = (int*)take(sizeof(int) * ((size_t)nb + 1));
+  B.spts = (float4*)take(sizeof(float4) * (size_t)n);
+  B.nbr = (int32_t*)take(sizeof(int32_t) * (size_t)n * k);
+  return B;
+}
+
+// Uniform grid of the points, counting-sorted by cell.
+hipError_t build_grid(const float* x, const float* y, const float* z, int n, const GridBufs& B, hipStream_t st) {
+  const int max_cells = grid_max_cells(n);
+  const int nb = (max_cells + SCAN_B - 1) / SCAN_B;
   const dim3 gn((n + 255) / 256), b256(256);
-  hipLaunchKernelGGL(grid_setup_kernel, dim3(1), dim3(1024), 0, st, x, y, z, n, max_cells, gi);
-  if (hipError_t e = launch_fill_i(counts, max_cells, st)) return e;
-  if (hipError_t e = launch_fill_i(cursor, max_cells, st)) return e;
-  hipLaunchKernelGGL(grid_count_kernel, gn, b256, 0, st, x, y, z, n, gi, cell_of, counts);
-  hipLaunchKernelGGL(scan_local_kernel, dim3(nb), dim3(SCAN_B), 0, st, counts, max_cells, starts, bsum);
-  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(64), 0, st, bsum, nb);
-  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(SCAN_B), 0, st, starts, max_cells, bsum, nb);
-  hipLaunchKernelGGL(grid_scatter_kernel, gn, b256, 0, st, x, y, z, n, cell_of, starts, cursor, spts);
+  hipLaunchKernelGGL(grid_setup_kernel, dim3(1), dim3(1024), 0, st, x, y, z, n, max_cells, B.gi);
+  if (hipError_t e = launch_fill_i(B.counts, max_cells, st)) return e;
+  if (hipError_t e = launch_fill_i(B.cursor, max_cells, st)) return e;
+  hipLaunchKernelGGL(grid_count_kernel, gn, b256, 0, st, x, y, z, n, B.gi, B.cell_of, B.counts);
+  hipLaunchKernelGGL(scan_local_kernel, dim3(nb), dim3(SCAN_B), 0, st, B.counts, max_cells, B.starts, B.bsum);
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(64), 0, st, B.bsum, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(SCAN_B), 0, st, B.starts, max_cells, B.bsum, nb);
+  hipLaunchKernelGGL(grid_scatter_kernel, gn, b256, 0, st, x, y, z, n, B.cell_of, B.starts, B.cursor, B.spts);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n, int k, float* a_out,
+                           int32_t* idx_out, void* ws, hipStream_t st) {
+  const GridBufs B = carve_grid(ws, n, k);
+  if (hipError_t e = build_grid(x, y, z, n, B, st)) return e;
+  int32_t* lists = idx_out ? idx_out : B.nbr;
+  const dim3 gn((n + 255) / 256), b256(256);
   const dim3 gq((n + GQ_BT - 1) / GQ_BT), bq(GQ_BT);
   if (k <= 8)
-    hipLaunchKernelGGL(grid_knn_kernel<8>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+    hipLaunchKernelGGL(grid_knn_kernel<8>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
   else if (k <= 16)
-    hipLaunchKernelGGL(grid_knn_kernel<16>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+    hipLaunchKernelGGL(grid_knn_kernel<16>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
   else if (k <= 24)
-    hipLaunchKernelGGL(grid_knn_kernel<24>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+    hipLaunchKernelGGL(grid_knn_kernel<24>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
   else
-    hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, spts, starts, gi, n, k, lists);
+    hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
   if (a_out) hipLaunchKernelGGL(curvature_kernel, gn, b256, 0, st, x, y, z, n, k, lists, a_out);
+  return hipGetLastError();
+}
+
+// Nearest point of the grid's cloud to each query (any points, inside or
+// outside the grid's box): the same shell search and (key, index) order as
+// grid_knn_kernel with k = 1.  A query with a non-finite coordinate gets
+// index -1 and key +inf.
+__global__ __launch_bounds__(GQ_BT) void grid_nn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
+                                                        const GridInfo* __restrict__ gi, const float* __restrict__ qx,
+                                                        const float* __restrict__ qy, const float* __restrict__ qz,
+                                                        int nq, int32_t* __restrict__ nn, float* __restrict__ key) {
+  const int t = blockIdx.x * GQ_BT + threadIdx.x;
+  if (t >= nq) return;  // no barriers below
+  const GridInfo G = *gi;
+  const float qv[3] = {qx[t], qy[t], qz[t]};
+  float bd = INFINITY;
+  int bi = -1;
+  if (isfinite(qv[0]) && isfinite(qv[1]) && isfinite(qv[2])) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
+    const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
+    for (int r = 0; r <= rmax; ++r) {
+      for (int dz = -r; dz <= r; ++dz) {
+        const int cz = c[2] + dz;
+        if (cz < 0 || cz >= G.dims[2]) continue;
+        for (int dy = -r; dy <= r; ++dy) {
+          const int cy = c[1] + dy;
+          if (cy < 0 || cy >= G.dims[1]) continue;
+          const bool inner = (abs(dz) < r) && (abs(dy) < r);
+          for (int dx = -r; dx <= r; dx += (inner && r > 0) ? 2 * r : 1) {
+            const int cx = c[0] + dx;
+            if (cx < 0 || cx >= G.dims[0]) continue;
+            const int cell = (cz * G.dims[1] + cy) * G.dims[0] + cx;
+            const int p1 = starts[cell + 1];
+            for (int p = starts[cell]; p < p1; ++p) {
+              const float4 P = spts[p];
+              const int j = __float_as_int(P.w);
+              const float ex = __fsub_rn(P.x, qv[0]), ey = __fsub_rn(P.y, qv[1]), ez = __fsub_rn(P.z, qv[2]);
+              const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+              if (key_less(d2, j, bd, bi)) {
+                bd = d2;
+                bi = j;
+              }
+            }
+          }
+        }
+      }
+      // distance from the query to any cell outside the searched cube
+      double lb = INFINITY;
+      bool all = true;
+      for (int a = 0; a < 3; ++a) {
+        if (c[a] - r > 0) {
+          lb = fmin(lb, (double)qv[a] - ((double)G.lo[a] + (double)(c[a] - r) * (double)G.h));
+          all = false;
+        }
+        if (c[a] + r < G.dims[a] - 1) {
+          lb = fmin(lb, ((double)G.lo[a] + (double)(c[a] + r + 1) * (double)G.h) - (double)qv[a]);
+          all = false;
+        }
+      }
+      if (all) break;
+      const double lbs = lb - 1e-3 * (double)G.h;
+      if (lbs > 0.0 && (double)bd * 1.00001 < lbs * lbs) break;
+    }
+  }
+  nn[t] = bi;
+  key[t] = bd;
+}
+
+hipError_t launch_grid_nn(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
+                          const float* qz, int nq, int32_t* nn, float* key, void* ws, hipStream_t st) {
+  const GridBufs B = carve_grid(ws, n, 1);
+  if (hipError_t e = build_grid(x, y, z, n, B, st)) return e;
+  hipLaunchKernelGGL(grid_nn_kernel, dim3((nq + GQ_BT - 1) / GQ_BT), dim3(GQ_BT), 0, st, B.spts, B.starts, B.gi, qx,
+                     qy, qz, nq, nn, key);
   return hipGetLastError();
 }
 

@@ -146,6 +146,16 @@ int grid_max_cells(int n);
 size_t grid_knn_workspace(int n, int k);
 hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, void* ws, hipStream_t st);
+// Nearest point of the cloud (x, y, z, n) to each query, same order as the
+// grid kNN (FP32 key, ties by index); ws: grid_knn_workspace(n, 1) bytes.
+hipError_t launch_grid_nn(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
+                          const float* qz, int nq, int32_t* nn, float* key, void* ws, hipStream_t st);
+// Change flags of the posed template against the reference (see change.hip);
+// ws: change_workspace(M, N) bytes.
+size_t change_workspace(int M, int N);
+hipError_t launch_change(const float* yx, const float* yy, const float* yz, const float* aY, int M, const float* xx,
+                         const float* xy, const float* xz, const float* aX, int N, const double* pose, float tau2,
+                         double shape_thr, uint8_t* flags, int32_t* nn, float* key, void* ws, hipStream_t st);
 
 hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, hipStream_t st);

@@ -35,6 +35,8 @@ class Pair:
     g_mode: int = 0          # 0: g = s, 1: g = a a s
     p: int = 2
     eps_rel: float = 0.0     # softening as a fraction of the cloud length scale
+    changed: np.ndarray | None = None      # (M,) bool: template point on an object absent from the reference
+    ref_changed: np.ndarray | None = None  # (N,) bool: reference point on an object absent from the template
 
     @property
     def N(self) -> int:
@@ -253,23 +255,26 @@ def config4_multistart(n: int = 20000, S: int = 32, wl: int = 4, iters: int = 10
 
 
 # ------------------------------------------------------------- depth room
-def _raycast_room(dirs: np.ndarray, boxes, room_lo, room_hi) -> np.ndarray:
+def _raycast_room(dirs: np.ndarray, boxes, room_lo, room_hi, want_id: bool = False):
     """Distance along each unit ray (from the origin) to the first surface
-    of a closed axis-aligned room containing axis-aligned boxes."""
+    of a closed axis-aligned room containing axis-aligned boxes (and, with
+    want_id, the index of the box hit, -1 for the room)."""
     with np.errstate(divide="ignore", invalid="ignore"):
         inv = 1.0 / dirs
         t1 = (room_lo - 0.0) * inv
         t2 = (room_hi - 0.0) * inv
         tfar = np.nanmin(np.maximum(t1, t2), axis=1)  # exit of the room box
         best = tfar.copy()
-        for lo, hi in boxes:
+        hit_id = np.full(best.shape, -1, dtype=np.int64)
+        for b_i, (lo, hi) in enumerate(boxes):
             a = lo * inv
             b = hi * inv
             tn = np.nanmax(np.minimum(a, b), axis=1)
             tf = np.nanmin(np.maximum(a, b), axis=1)
             hit = (tf >= tn) & (tn > 1e-6) & (tn < best)
             best = np.where(hit, tn, best)
-    return best
+            hit_id = np.where(hit, b_i, hit_id)
+    return (best, hit_id) if want_id else best
 
 
 ROOM = ((-2.5, -1.2, -0.5), (2.5, 1.8, 3.5))   # 5 x 3 x 4 m, camera 1.2 m above the floor
@@ -287,9 +292,10 @@ def _room_boxes(rng: np.random.Generator, count: int, floor_y: float):
     return boxes
 
 
-def _render(boxes, cam_R, rng_noise, width=640, height=480, f=525.0, room=ROOM):
+def _render(boxes, cam_R, rng_noise, width=640, height=480, f=525.0, room=ROOM, want_id: bool = False):
     """Render a depth frame from a camera at the origin with orientation
-    ``cam_R`` (camera-to-world), return points in the camera frame."""
+    ``cam_R`` (camera-to-world), return points in the camera frame (and,
+    with want_id, the box each pixel sees, -1 for the room)."""
     cx, cy = (width - 1) / 2, (height - 1) / 2
     u, v = np.meshgrid(np.arange(width), np.arange(height))
     d_cam = np.stack([(u - cx) / f, -(v - cy) / f, np.ones_like(u, dtype=np.float64)], axis=-1).reshape(-1, 3)
@@ -297,10 +303,21 @@ def _render(boxes, cam_R, rng_noise, width=640, height=480, f=525.0, room=ROOM):
     dirs_cam = d_cam * z_per_len[:, None]
     dirs_w = dirs_cam @ cam_R.T
     lo, hi = np.array(room[0]), np.array(room[1])
-    dist = _raycast_room(dirs_w, boxes, lo, hi)
+    dist, hit_id = _raycast_room(dirs_w, boxes, lo, hi, want_id=True)
     z = dist * z_per_len
     z = z + rng_noise.normal(0.0, 1.0, size=z.shape) * 0.001 * z * z
-    return d_cam * z[:, None]
+    pts = d_cam * z[:, None]
+    return (pts, hit_id) if want_id else pts
+
+
+def _visible_pixels(boxes, cam_R, idx, width=640, height=480, f=525.0, room=ROOM) -> int:
+    """Number of pixels of a depth frame that see box ``idx``."""
+    cx, cy = (width - 1) / 2, (height - 1) / 2
+    u, v = np.meshgrid(np.arange(width), np.arange(height))
+    d_cam = np.stack([(u - cx) / f, -(v - cy) / f, np.ones_like(u, dtype=np.float64)], axis=-1).reshape(-1, 3)
+    dirs_w = (d_cam / np.linalg.norm(d_cam, axis=1)[:, None]) @ cam_R.T
+    _, hit_id = _raycast_room(dirs_w, boxes, np.array(room[0]), np.array(room[1]), want_id=True)
+    return int(np.count_nonzero(hit_id == idx))
 
 
 def config5(wl: int = 5, iters: int = 100, m: int = 250000) -> Pair:
@@ -311,20 +328,34 @@ def config5(wl: int = 5, iters: int = 100, m: int = 250000) -> Pair:
     rng = np.random.default_rng(1000 * wl + 0)
     floor_y = ROOM[0][1]
     boxes = _room_boxes(rng, 20, floor_y)
-    pitch = rot_axis_angle([1, 0, 0], -20.0)  # both views look 20 deg down
-    ref = _render(boxes, pitch, np.random.default_rng(1000 * wl + 2))
+    pitch = rot_axis_angle([1, 0, 0], 20.0)  # both views look 20 deg down (+y is up, the floor at y = -1.2)
+    ref, ref_id = _render(boxes, pitch, np.random.default_rng(1000 * wl + 2), want_id=True)
     rng_c = np.random.default_rng(1000 * wl + 3)
     boxes2 = list(boxes)
-    boxes2.pop(int(rng_c.integers(len(boxes2))))
-    boxes2 += _room_boxes(rng_c, 2, floor_y)
+    removed = int(rng_c.integers(len(boxes2)))
+    boxes2.pop(removed)
     Rc = rot_axis_angle([0, 1, 0], 30.0) @ pitch  # camera-to-world of the second view
-    tm = _render(boxes2, Rc, np.random.default_rng(1000 * wl + 12))
+    # two added boxes, each drawn until it overlaps no other box and at least
+    # 2000 pixels of the second view see it (so the change is observable)
+    for _ in range(2):
+        while True:
+            cand = _room_boxes(rng_c, 1, floor_y)[0]
+            overlap = any(np.all(cand[0][[0, 2]] < hi[[0, 2]]) and np.all(lo[[0, 2]] < cand[1][[0, 2]])
+                          for lo, hi in boxes2)
+            if not overlap and _visible_pixels(boxes2 + [cand], Rc, len(boxes2)) >= 2000:
+                boxes2.append(cand)
+                break
+    tm, tm_id = _render(boxes2, Rc, np.random.default_rng(1000 * wl + 12), want_id=True)
     rng_s = np.random.default_rng(1000 * wl + 4)
     sel = np.sort(rng_s.choice(tm.shape[0], size=m, replace=False))
     tmpl = tm[sel]
+    # ground-truth change labels: template points on the two added boxes,
+    # reference points on the removed one
+    changed = tm_id[sel] >= len(boxes2) - 2
+    ref_changed = ref_id == removed
     # reference camera -> world -> second camera: y = Rc^T pitch x
     return _pair(f"depth-room {m}x{ref.shape[0]}", ref, tmpl, 1.0, Rc.T @ pitch, np.zeros(3),
-                 np.full(m, -1), k=16, iters=iters, g_mode=1)
+                 np.full(m, -1), k=16, iters=iters, g_mode=1, changed=changed, ref_changed=ref_changed)
 
 
 def random_pair(M: int, N: int, seed: int, spread: float = 1.0) -> Pair:

@@ -293,3 +293,65 @@ def test_residual_closed_forms():
     Y = s * X @ R.T + t
     inv = O.Pose(1 / s, R.T, -(R.T @ t) / s)
     assert O.pose_rmse(inv, Y, s, R, t) <= 1e-14 * np.abs(X).max()
+
+
+# ------------------------------------------------------ change detection
+def test_nearest_matches_brute_force_with_ties_and_far_queries():
+    """The k-d tree path of the nearest-point search returns what a brute
+    force over all points returns (float32 key, ties by lowest index): with
+    exactly duplicated reference points, lattice queries equidistant from
+    several points, and queries far outside the cloud."""
+    rng = np.random.default_rng(21)
+    X = rng.normal(size=(3000, 3)).astype(np.float32)
+    X[100:110] = X[50]                                 # exact duplicates of point 50
+    L = np.array([[i, j, k] for i in range(4) for j in range(4) for k in range(4)], np.float32)
+    X = np.concatenate([X, L])                          # a unit lattice: midpoint queries tie
+    Q = np.concatenate([rng.normal(size=(500, 3)), X[[50, 7, 3001]], L[:20] + 0.5,
+                        rng.normal(size=(20, 3)) * 50.0]).astype(np.float32)
+    nn, key = O.nearest(Q, X)
+    idx = np.arange(len(X))
+    for i in range(len(Q)):
+        d = O.sqdist32(X, Q[i])
+        j = int(np.lexsort((idx, d))[0])
+        assert nn[i] == j and key[i] == d[j]
+    assert nn[500] == 50                               # duplicate: lowest index wins
+    bad = np.array([[np.nan, 0, 0]], np.float32)
+    nb, kb = O.nearest(bad, X)
+    assert nb[0] == -1 and np.isinf(kb[0])
+
+
+def test_posed32_closed_form():
+    """A quarter turn about z with scale 2 and an integer shift maps integer
+    points to exactly known float32 values."""
+    R = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    pose = O.Pose(2.0, R, np.array([1.0, -3.0, 0.5]))
+    Y = np.array([[1, 2, 3], [-4, 0, 7]], np.float32)
+    want = np.array([[2 * -2 + 1, 2 * 1 - 3, 2 * 3 + 0.5], [2 * 0 + 1, 2 * -4 - 3, 2 * 7 + 0.5]], np.float32)
+    np.testing.assert_array_equal(O.posed32(Y, pose), want)
+
+
+def test_change_flags_self_pair_added_object_and_shape_change():
+    """Against itself at the identity pose nothing is flagged; a cluster
+    placed far from the reference is flagged by distance only; shifting
+    some curvatures by more (less) than sigma sqrt(-ln s_min) sets (does not
+    set) the shape bit."""
+    rng = np.random.default_rng(22)
+    X = rng.normal(size=(2000, 3)).astype(np.float32)
+    aX = rng.uniform(0.0, 0.2, 2000).astype(np.float32)
+    ident = O.Pose.identity()
+    sigma, s_min, tau = 0.05, 0.5, 0.05
+    f, nn, key = O.change_flags(X, aX, X, aX, ident, tau, sigma, s_min)
+    assert not f.any() and (key == 0).all()
+    blob = (rng.normal(size=(100, 3)) * 0.1 + np.array([10.0, 0.0, 0.0])).astype(np.float32)
+    Y = np.concatenate([X, blob])
+    aY = np.concatenate([aX, np.full(100, 0.1, np.float32)])
+    f, nn, key = O.change_flags(Y, aY, X, aX, ident, tau, sigma, s_min)
+    assert not f[:2000].any() and (f[2000:] & 1).all()
+    thr = sigma * np.sqrt(-np.log(s_min))
+    aY2 = aX.copy()
+    aY2[:50] += np.float32(1.5 * thr)
+    aY2[50:100] += np.float32(0.5 * thr)
+    f, nn, key = O.change_flags(X, aY2, X, aX, ident, tau, sigma, s_min)
+    assert (f[:50] == 2).all() and not f[50:].any()
+    f, _, _ = O.change_flags(X, aY2, X, aX, ident, tau, sigma, 0.0)   # shape test off
+    assert not f.any()
