@@ -244,16 +244,17 @@ int sgr_unrolled_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
  * show the change).  For every template point i, posed by `pose` (device,
  * 13 float64) as T(y_i) = s ((R_r0 y_0 + R_r1 y_1) + R_r2 y_2) + t_r in FP64
  * with every operation rounded on its own, then rounded to float32, and with
- * j its nearest reference point (float32 key ((dx*dx + dy*dy) + dz*dz),
- * ties by index, as the descriptors' neighbours):
- *   flags_out[i] bit 0: key > (float)(tau^2)        (nothing within tau),
+ * j its nearest reference point among those whose float32 key ((dx*dx +
+ * dy*dy) + dz*dz) is <= (float)(tau^2), ties by index as the descriptors'
+ * neighbours:
+ *   flags_out[i] bit 0: there is no such point        (nothing within tau),
  *   flags_out[i] bit 1: (a_i - a_j)^2 > sigma^2 (-ln s_min) in FP64, i.e.
  *                       the shape similarity of eq. 3 is below s_min.
- * tau > 0 (+inf disables the distance test); s_min <= 0 disables the shape
- * test, else s_min <= 1 and sigma > 0.  a_t, a_r: curvatures (device
- * float32).  Outputs (device): flags_out[M] uint8; nn_out[M] int32 and
- * d2_out[M] float32 (the key), both nullable.  A template point with a
- * non-finite posed coordinate gets nn -1 and bit 0.  For the reverse
+ * tau > 0 (+inf: the nearest point at any distance, bit 0 only for
+ * non-finite points); s_min <= 0 disables the shape test, else s_min <= 1
+ * and sigma > 0.  a_t, a_r: curvatures (device float32).  Outputs (device):
+ * flags_out[M] uint8; nn_out[M] int32 (-1: none within tau) and d2_out[M]
+ * float32 (its key, +inf if none), both nullable.  For the reverse
  * direction (reference parts missing from the template) swap the clouds and
  * pass the inverse pose. */
 int sgr_change_detect(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,

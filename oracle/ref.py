@@ -461,18 +461,21 @@ def nearest(Q: np.ndarray, X: np.ndarray):
 def change_flags(Y0, aY, X, aX, pose: "Pose", tau: float, sigma: float, s_min: float):
     """Change detection after registration (Sec. I and IV: registered
     template parts without a similar reference part nearby).  Per template
-    point, with j its nearest reference point to the posed point:
-    bit 0: float32 key > float32(tau^2); bit 1 (s_min > 0): (a_i - a_j)^2
-    in FP64 > sigma^2 (-ln s_min), i.e. the shape similarity of eq. 3 is
-    below s_min.  Returns (flags uint8, nn int64, key float32)."""
+    point, with j its nearest reference point to the posed point among
+    those with float32 key <= float32(tau^2): bit 0: there is none (nn -1,
+    key +inf); bit 1 (s_min > 0): (a_i - a_j)^2 in FP64 > sigma^2 (-ln
+    s_min), i.e. the shape similarity of eq. 3 is below s_min.  Returns
+    (flags uint8, nn int64, key float32)."""
     Q = posed32(Y0, pose)
     nn, key = nearest(Q, X)
     tau2 = np.float32(tau * tau)
+    far = ~(key <= tau2)
+    nn[far] = -1
+    key[far] = np.inf
     thr = sigma * sigma * (-math.log(s_min)) if s_min > 0 else math.inf
     flags = np.zeros(len(Q), dtype=np.uint8)
     valid = nn >= 0
     flags[~valid] = 1
-    flags[valid & (key > tau2)] |= 1
     da = np.asarray(aY, np.float32).astype(np.float64) - np.asarray(aX, np.float32).astype(np.float64)[np.maximum(nn, 0)]
     flags[valid & (da * da > thr)] |= 2
     return flags, nn, key

@@ -1,8 +1,8 @@
 // Change detection after registration (the application of Sec. I and
 // Sec. IV: parts of the registered template with no similar reference part
 // nearby show the change).  For every template point i, posed by the final
-// registration pose, with j its nearest reference point:
-//   bit 0: |T(y_i) - x_j|^2 > tau^2              (nothing near it),
+// registration pose, with j its nearest reference point within tau:
+//   bit 0: there is none (nothing near it),
 //   bit 1: (a_i - a_j)^2 > sigma^2 (-ln s_min)   (the nearest point's shape
 //          similarity exp(-(a_i - a_j)^2 / sigma^2) of eq. 3 is below s_min).
 // Both decisions are taken in a precision a reader can reproduce: the posed
@@ -45,9 +45,8 @@ __global__ __launch_bounds__(256) void change_flags_kernel(const float* __restri
   const int j = nn[i];
   uint8_t f = 0;
   if (j < 0) {
-    f = 1;  // no finite reference point (or a non-finite posed point)
+    f = 1;  // no reference point within tau (or a non-finite posed point)
   } else {
-    if (key[i] > tau2) f |= 1;
     const double da = (double)aY[i] - (double)aX[j];
     if (da * da > shape_thr) f |= 2;
   }
@@ -66,7 +65,7 @@ hipError_t launch_change(const float* yx, const float* yy, const float* yz, cons
   float* qz = (float*)(p + 2 * qb);
   void* gws = p + 3 * qb;
   hipLaunchKernelGGL(posed_exact_kernel, dim3((M + 255) / 256), dim3(256), 0, st, yx, yy, yz, M, pose, qx, qy, qz);
-  if (hipError_t e = launch_grid_nn(xx, xy, xz, N, qx, qy, qz, M, nn, key, gws, st)) return e;
+  if (hipError_t e = launch_grid_nn(xx, xy, xz, N, qx, qy, qz, M, tau2, nn, key, gws, st)) return e;
   hipLaunchKernelGGL(change_flags_kernel, dim3((M + 255) / 256), dim3(256), 0, st, aY, aX, nn, key, M, tau2, shape_thr,
                      flags);
   return hipGetLastError();

@@ -384,13 +384,15 @@ hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n
 }
 
 // Nearest point of the grid's cloud to each query (any points, inside or
-// outside the grid's box): the same shell search and (key, index) order as
-// grid_knn_kernel with k = 1.  A query with a non-finite coordinate gets
-// index -1 and key +inf.
+// outside the grid's box) among the points whose key is <= max_key: the
+// same shell search and (key, index) order as grid_knn_kernel with k = 1,
+// stopped once the unsearched cells lie beyond max_key.  A query with no
+// such point, or with a non-finite coordinate, gets index -1 and key +inf.
 __global__ __launch_bounds__(GQ_BT) void grid_nn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
                                                         const GridInfo* __restrict__ gi, const float* __restrict__ qx,
                                                         const float* __restrict__ qy, const float* __restrict__ qz,
-                                                        int nq, int32_t* __restrict__ nn, float* __restrict__ key) {
+                                                        int nq, float max_key, int32_t* __restrict__ nn,
+                                                        float* __restrict__ key) {
   const int t = blockIdx.x * GQ_BT + threadIdx.x;
   if (t >= nq) return;  // no barriers below
   const GridInfo G = *gi;
@@ -442,19 +444,24 @@ __global__ __launch_bounds__(GQ_BT) void grid_nn_kernel(const float4* __restrict
       }
       if (all) break;
       const double lbs = lb - 1e-3 * (double)G.h;
-      if (lbs > 0.0 && (double)bd * 1.00001 < lbs * lbs) break;
+      // nothing unsearched can beat the current best, or reach max_key
+      if (lbs > 0.0 && fmin((double)bd, (double)max_key) * 1.00001 < lbs * lbs) break;
     }
+  }
+  if (!(bd <= max_key)) {
+    bd = INFINITY;
+    bi = -1;
   }
   nn[t] = bi;
   key[t] = bd;
 }
 
 hipError_t launch_grid_nn(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
-                          const float* qz, int nq, int32_t* nn, float* key, void* ws, hipStream_t st) {
+                          const float* qz, int nq, float max_key, int32_t* nn, float* key, void* ws, hipStream_t st) {
   const GridBufs B = carve_grid(ws, n, 1);
   if (hipError_t e = build_grid(x, y, z, n, B, st)) return e;
   hipLaunchKernelGGL(grid_nn_kernel, dim3((nq + GQ_BT - 1) / GQ_BT), dim3(GQ_BT), 0, st, B.spts, B.starts, B.gi, qx,
-                     qy, qz, nq, nn, key);
+                     qy, qz, nq, max_key, nn, key);
   return hipGetLastError();
 }
 

@@ -146,10 +146,11 @@ int grid_max_cells(int n);
 size_t grid_knn_workspace(int n, int k);
 hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, void* ws, hipStream_t st);
-// Nearest point of the cloud (x, y, z, n) to each query, same order as the
-// grid kNN (FP32 key, ties by index); ws: grid_knn_workspace(n, 1) bytes.
+// Nearest point of the cloud (x, y, z, n) to each query among those with
+// key <= max_key (-1 / +inf if none), same order as the grid kNN (FP32 key,
+// ties by index); ws: grid_knn_workspace(n, 1) bytes.
 hipError_t launch_grid_nn(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,
-                          const float* qz, int nq, int32_t* nn, float* key, void* ws, hipStream_t st);
+                          const float* qz, int nq, float max_key, int32_t* nn, float* key, void* ws, hipStream_t st);
 // Change flags of the posed template against the reference (see change.hip);
 // ws: change_workspace(M, N) bytes.
 size_t change_workspace(int M, int N);
