@@ -34,7 +34,7 @@ void ora_forces(int64_t M, int64_t N, const double* Y, const double* aY, const d
       double q = rx * rx + ry * ry + rz * rz + eps * eps;
       double da = aY[i] - aX[j];
       double s = exp(-(da * da) / (sigma * sigma));
-      double g = (g_mode == 1) ? (aY[i] / abar) * (aX[j] / abar) * s : s;
+      double g = (g_mode == 1) ? (aY[i] / abar) * (aX[j] / abar) * s : (g_mode == 2 ? 1.0 : s);
       double h = (hp == 0.0) ? 1.0 : pow(q / (L * L), hp);
       double c = wX[j] * g * h;
       fx += c * rx;

@@ -21,7 +21,12 @@ passages the paper leaves open (each is repeated where it is used):
   of the reference covariance) are added for dimensional consistency:
   h = ((d^2 + eps^2)/L^2)^((p-1)/2); eps = 0 reproduces the paper exactly.
 * g(s) = s (Sec. IV, equal weightage) or g = (a_i/abar)(a_j/abar) s (eq. 10),
-  with abar the mean reference descriptor.
+  with abar the mean reference descriptor; g = 1 (g_mode 2) drops the shape
+  term and leaves the masses, so p = -2 with eps > 0 is eq. (1): the text
+  states |f| ~ 1/d^2, so the numerator of eq. (1) is read as the vector
+  r = y_i - x_j (standard softened gravity r/(d^2 + eps^2)^(3/2)), not a
+  unit vector, whose force would fall as 1/d^3.  Eq. (1)'s friction term is
+  not part of this force.
 * The similarity spread sigma defaults to the population std of the
   reference descriptors (the paper gives no value, eq. 3).
 * Curvature (Sec. III-A): PCA surface variation lambda_0/(lambda_0 +
@@ -52,7 +57,7 @@ G1_DEFAULT = 10000.0
 @dataclasses.dataclass
 class Params:
     p: float = 1.0           # distance exponent, p >= 1 (eq. 11); 1 is the stable choice
-    g_mode: int = 0          # 0: g = s ; 1: g = (a_i/abar)(a_j/abar) s   (eq. 10)
+    g_mode: int = 0          # 0: g = s ; 1: g = (a_i/abar)(a_j/abar) s (eq. 10) ; 2: g = 1 (eq. 1)
     k: int = 16
     sigma: float = 0.0       # <= 0: population std of the reference descriptors
     eps: float = 0.0         # softening (0 = the paper's law)
@@ -202,6 +207,8 @@ def pair_weights(Yi, aYi, S: Setup):
     s = np.exp(-((aYi[:, None] - S.aX[None, :]) ** 2) / S.sigma ** 2)        # eq. 3
     if prm.g_mode == 1:                                                       # eq. 10
         g = (aYi[:, None] / S.abar) * (S.aX[None, :] / S.abar) * s
+    elif prm.g_mode == 2:                                                     # eq. 1: masses only
+        g = np.ones_like(s)
     else:
         g = s
     h = (q / S.L ** 2) ** ((prm.p - 1) / 2.0)                                 # eqs. 4, 11

@@ -95,6 +95,61 @@ def test_force_is_negative_energy_gradient():
                 assert -dU == pytest.approx(f[i, c], rel=1e-6, abs=1e-8)
 
 
+def test_gravitational_mode_is_eq1_written_out():
+    """g = 1, p = -2, eps > 0 is the softened inverse-square attraction of
+    eq. (1): per unit template mass f_i = -G' sum_j m_j r_ij / (|r_ij|^2 +
+    eps^2)^(3/2) with G' = G L^3 / Z, and U = -G' sum_ij m_j / sqrt(|r_ij|^2 +
+    eps^2) (the Newtonian potential).  Written here with plain loops over
+    pairs, without the oracle's normalised form."""
+    pr = random_pair(9, 13, seed=21)
+    X, Y = pr.ref.astype(np.float64), pr.tmpl.astype(np.float64)
+    rng = np.random.default_rng(4)
+    m = rng.uniform(0.5, 2.0, 13)
+    eps, L, G = 0.07, 0.6, 2.5
+    S = _setup(X, rng.uniform(0, 0.3, 13), rng.uniform(0, 0.3, 9), p=-2.0, g_mode=2, sigma=0.05, eps=eps, L=L,
+               wX=m)
+    Gp = G * L ** 3 / m.sum()
+    f_ref = np.zeros((9, 3))
+    U_ref = 0.0
+    for i in range(9):
+        for j in range(13):
+            r = Y[i] - X[j]
+            d2 = r @ r + eps * eps
+            f_ref[i] -= Gp * m[j] * r / d2 ** 1.5
+            U_ref -= Gp * m[j] / math.sqrt(d2)
+    for fn in (O.forces, O.forces_c):
+        f, U = fn(Y, S, G)
+        np.testing.assert_allclose(f, f_ref, rtol=1e-12, atol=1e-14)
+        assert U == pytest.approx(U_ref, rel=1e-12)
+    # the shape term is gone: the descriptors do not enter
+    S2 = _setup(X, rng.uniform(0, 0.3, 13), rng.uniform(0, 0.3, 9), p=-2.0, g_mode=2, sigma=0.05, eps=eps, L=L,
+                wX=m)
+    np.testing.assert_array_equal(O.forces(Y, S2, G)[0], O.forces(Y, S, G)[0])
+
+
+def test_gravitational_mode_third_law_and_energy_gradient():
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(40, 3))
+    a = rng.uniform(0.0, 0.3, 40)
+    S = _setup(X, a, a, p=-2.0, g_mode=2, sigma=0.07, eps=0.1, L=0.8)
+    f, _ = O.forces(X, S, 100.0)
+    scale = np.abs(f).sum()
+    assert np.abs(f.sum(axis=0)).max() <= 1e-13 * scale
+    K = f.T @ (X - X.mean(0))
+    assert np.abs(K - K.T).max() <= 1e-13 * scale * np.abs(X).max()
+    Y = rng.normal(size=(5, 3))
+    S = _setup(X, a, rng.uniform(0.0, 0.3, 5), p=-2.0, g_mode=2, sigma=0.07, eps=0.05, L=0.8)
+    f, _ = O.forces(Y, S, 3.0)
+    h = 1e-6
+    for i in range(5):
+        for c in range(3):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            dU = (O.forces(Yp, S, 3.0)[1] - O.forces(Ym, S, 3.0)[1]) / (2 * h)
+            assert -dU == pytest.approx(f[i, c], rel=1e-6, abs=1e-8)
+
+
 def test_force_equivariance():
     pr = random_pair(20, 35, seed=8)
     X = pr.ref.astype(np.float64)
@@ -261,7 +316,7 @@ def test_pose_composition_matches_point_update():
 def test_c_oracle_matches_numpy():
     pr = random_pair(70, 90, seed=12)
     rng = np.random.default_rng(9)
-    for p, g_mode, eps in ((1.0, 0, 0.0), (2.0, 1, 0.03), (3.0, 0, 0.0), (2.5, 0, 0.1)):
+    for p, g_mode, eps in ((1.0, 0, 0.0), (2.0, 1, 0.03), (3.0, 0, 0.0), (2.5, 0, 0.1), (-2.0, 2, 0.05)):
         S = _setup(pr.ref.astype(np.float64), rng.uniform(0.01, 0.3, 90), rng.uniform(0.01, 0.3, 70),
                    p=p, g_mode=g_mode, sigma=0.08, eps=eps, L=0.7, wX=rng.uniform(0.5, 2, 90))
         f1, U1 = O.forces(pr.tmpl, S, 42.0)
