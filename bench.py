@@ -244,6 +244,31 @@ def extra_adjoint(sg, ctx):
     return out
 
 
+def extra_force_law(sg, ctx, E: int, k: int):
+    """The method's force law (p = 1, g = s, eq. 5 with eqs. 3, 11) against
+    the gravitational law of eq. (1) (p = -2, softening eps = 0.05 L, g = 1:
+    no shape term), both with the G schedule of eq. 12, on the workload pair
+    and on the small pair: time and pose error after E iterations."""
+    import numpy as np
+
+    from synth import config1, config2
+
+    out = {}
+    for name, pr in (("small", config1()), ("workload", config2())):
+        tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+        L = float(np.sqrt(np.linalg.eigvalsh(np.cov(pr.ref.astype(np.float64).T, bias=True))[-1]))
+        row = {"M": pr.M, "N": pr.N, "iterations": E}
+        for law, prm in (("shape_p1", sg.Params(p=1.0, k=k, E=E)),
+                         ("gravitational_p-2", sg.Params(p=-2.0, g_mode=2, eps=0.05 * L, k=k, E=E))):
+            pose = sg.pose_identity()
+            ctx.register(tm, rf, prm, pose=pose)
+            dt, _ = _timed(lambda: (pose.copy_(sg.pose_identity()), ctx.register(tm, rf, prm, pose=pose)))
+            row[law] = {"ms_per_registration": dt * 1e3, "pose_rmse_over_diameter": _pose_err(sg, pose, pr),
+                        "nn_rmse": float(ctx.residual(tm, rf, pose).item())}
+        out[name] = row
+    return out
+
+
 def extra_scene(sg, ctx, cpu_rows: int):
     """Depth-frame scene (307,200 x 250,000, g = a a s): FP32 and mixed
     registrations, their pose difference per iteration, and the one-step
@@ -472,6 +497,9 @@ def main() -> int:
         log(f"batch: {out['batch']['ms_per_batch']:.1f} ms")
         out["adjoint"] = extra_adjoint(sg, ctx)
         log(f"adjoint: fwd {out['adjoint']['fwd_ms']:.3f} ms, bwd {out['adjoint']['bwd_ms']:.3f} ms")
+        out["force_law"] = extra_force_law(sg, ctx, E, k)
+        log(f"force law: workload pose error p=1 {out['force_law']['workload']['shape_p1']['pose_rmse_over_diameter']:.2e}"
+            f", gravitational {out['force_law']['workload']['gravitational_p-2']['pose_rmse_over_diameter']:.2e}")
         out["scene"] = extra_scene(sg, ctx, cpu_rows=48)
         log(f"scene: fp32 {out['scene']['fp32']['ms_per_registration']:.1f} ms, "
             f"mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms")

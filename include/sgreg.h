@@ -62,11 +62,15 @@ typedef struct {
 
 /* Parameters of the method.  Readings of passages the paper leaves open:
  *  p      distance exponent of eq. (11), h(d) n = d^(p-1) r, p >= 1
- *         (p < 1 only with eps > 0).  1 is the default: larger p overshoots
+ *         (p < 1 only with eps > 0; p = -1, whose potential is a
+ *         logarithm, is rejected).  1 is the default: larger p overshoots
  *         (Sec. IV warns of oscillation), p = 2 flips the template once
  *         G dt2 nears 1.
  *  g_mode 0: g = s (Sec. IV, equal weightage); 1: g = (a_i/abar)(a_j/abar) s
- *         (eq. 10), abar = mean reference curvature.
+ *         (eq. 10), abar = mean reference curvature; 2: g = 1 (no shape
+ *         term, the masses alone weight the pairs).  p = -2 with eps > 0 and
+ *         g_mode 2 is the gravitational force of eq. (1) (inverse square
+ *         with softening), without its velocity (friction) state.
  *  k      neighbours (self included) for the curvature descriptor.
  *  sigma  RBF spread of eq. (3); <= 0 selects the population std of the
  *         reference curvatures.

@@ -89,7 +89,9 @@ int check_params(const sgr_params* p) {
   if (!p) return fail(SGR_EINVAL, "NULL params");
   if (!std::isfinite(p->p)) return fail(SGR_EINVAL, "p must be finite");
   if (p->p < 1.0 && !(p->eps > 0)) return fail(SGR_EINVAL, "p < 1 needs eps > 0 (the force would diverge at r = 0)");
-  if (p->g_mode != 0 && p->g_mode != 1) return fail(SGR_EINVAL, "g_mode must be 0 (g = s) or 1 (g = a a s)");
+  if (p->p == -1.0) return fail(SGR_EINVAL, "p = -1 has a logarithmic potential; the energy U is defined for p != -1");
+  if (p->g_mode < 0 || p->g_mode > 2)
+    return fail(SGR_EINVAL, "g_mode must be 0 (g = s), 1 (g = a a s) or 2 (g = 1, masses only)");
   if (!(p->G1 > 0) || !std::isfinite(p->G1)) return fail(SGR_EINVAL, "G1 must be positive");
   if (p->flags & ~3) return fail(SGR_EINVAL, "unknown flag bits");
   if (!std::isfinite(p->sigma) || !std::isfinite(p->eps) || p->eps < 0) return fail(SGR_EINVAL, "bad sigma/eps");

@@ -96,7 +96,8 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   D.Z = s[1];
   D.Mtot = s[2];
   D.Mcount = (double)M;
-  D.bscale = sqrt(1.4426950408889634) / D.sigma;  // sqrt(log2 e) / sigma
+  // sqrt(log2 e) / sigma; 0 for g = 1 (no shape term: every b is 0 and s = 1)
+  D.bscale = P.g_mode == 2 ? 0.0 : sqrt(1.4426950408889634) / D.sigma;
   D.coefL = exp((1.0 - P.p) * log(D.L));
   D.hp = 0.5 * (P.p - 1.0);
   D.eps2 = P.eps * P.eps;
@@ -115,7 +116,7 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   for (int e = 0; e < 9; ++e) D.Vw[e] = (e % 4 == 0) ? 1.0 : 0.0;
   D.pad2 = 0;
   D.cold_svd = P.cold_svd;
-  if (!(D.lamX > 0) || !(D.lamY0 > 0) || !(D.sigma > 0) || !(D.Z > 0) || !(D.Mtot > 0) ||
+  if (!(D.lamX > 0) || !(D.lamY0 > 0) || (P.g_mode != 2 && !(D.sigma > 0)) || !(D.Z > 0) || !(D.Mtot > 0) ||
       (P.g_mode == 1 && !(abar > 0)))
     st |= ST_DEGENERATE;
   D.status = st;

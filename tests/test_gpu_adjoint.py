@@ -46,7 +46,8 @@ def _loss_oracle(Y, m, sigma, eps, X, aX, aY, wX, p, g_mode, gf, gF, gK):
     return float(np.sum(gf * f) + gF @ F + np.sum(gK * K))
 
 
-@pytest.mark.parametrize("p,g_mode,eps", [(1.0, 0, 0.0), (2.0, 0, 0.05), (2.0, 1, 0.02), (1.5, 0, 0.1)])
+@pytest.mark.parametrize("p,g_mode,eps", [(1.0, 0, 0.0), (2.0, 0, 0.05), (2.0, 1, 0.02), (1.5, 0, 0.1),
+                                        (-2.0, 2, 0.05)])
 def test_force_adjoint_matches_fp64_finite_differences(sg, ctx, p, g_mode, eps):
     pr = random_pair(150, 700, seed=31)
     rng = np.random.default_rng(5)

@@ -97,7 +97,7 @@ def _check_wrench(so, wr, f, Y, mY=None):
 
 @pytest.mark.parametrize("p,g_mode,eps,masses", [
     (1.0, 0, 0.0, False), (2.0, 0, 0.0, False), (3.0, 1, 0.0, False), (1.5, 0, 0.05, True),
-    (2.0, 1, 0.02, True)])
+    (2.0, 1, 0.02, True), (-2.0, 2, 0.05, True)])
 def test_step_matches_oracle(sg, ctx, p, g_mode, eps, masses):
     pr = random_pair(1300, 2900, seed=21)          # several tiles, ragged tails
     rng = np.random.default_rng(4)
@@ -192,6 +192,19 @@ def test_register_config1_matches_oracle(sg, ctx):
         O.Pose.identity(), pr.tmpl, pr.gt_s, pr.gt_R, pr.gt_t)
 
 
+def test_register_gravitational_law_matches_oracle(sg, ctx):
+    """The gravitational law of eq. (1) (p = -2, eps = 0.05 L, g = 1) through
+    the whole registration loop."""
+    pr = config1()
+    L = float(np.sqrt(np.linalg.eigvalsh(np.cov(pr.ref.astype(np.float64).T, bias=True))[-1]))
+    prm = O.Params(p=-2.0, g_mode=2, k=16, eps=0.05 * L, E=60)
+    po, pg = _register_both(sg, ctx, pr, prm)
+    d = pg.apply(pr.tmpl) - po.apply(pr.tmpl)
+    err = np.sqrt(np.mean(np.sum(d * d, axis=1))) / O.diameter(pr.ref)
+    print(f"gravitational-law registration parity RMSE / diameter = {err:.2e}")
+    assert err <= 1e-4
+
+
 def test_register_graph_replay_and_determinism(sg, ctx):
     pr = config1(n=2000)
     tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
@@ -245,11 +258,26 @@ def test_error_codes(sg, ctx):
     with pytest.raises(sg.SgrError) as e:
         ctx.register(tm, rf, sg.Params(p=0.5, eps=0.0, k=4, E=3))
     assert e.value.code == -1
+    with pytest.raises(sg.SgrError) as e:   # logarithmic potential
+        ctx.register(tm, rf, sg.Params(p=-1.0, eps=0.1, k=4, E=3))
+    assert e.value.code == -1
+    with pytest.raises(sg.SgrError) as e:
+        ctx.register(tm, rf, sg.Params(g_mode=3, k=4, E=3))
+    assert e.value.code == -1
     flat = np.zeros((40, 3), np.float32)
     flat[:, 0] = np.arange(40)
     with pytest.raises(sg.SgrError) as e:   # all curvatures 0: no similarity spread
         ctx.register(sg.Cloud(flat), sg.Cloud(flat), sg.Params(k=4, E=3))
     assert e.value.code == -2
+    # a plane: every curvature is exactly 0 as well, and the rotation is
+    # determined; without the shape term (g = 1) the spread is not needed
+    plane = np.zeros((64, 3), np.float32)
+    plane[:, 0], plane[:, 1] = np.arange(64) % 8, np.arange(64) // 8
+    with pytest.raises(sg.SgrError) as e:
+        ctx.register(sg.Cloud(plane), sg.Cloud(plane), sg.Params(k=4, E=3))
+    assert e.value.code == -2
+    pose, _ = ctx.register(sg.Cloud(plane), sg.Cloud(plane), sg.Params(p=-2.0, g_mode=2, eps=0.5, k=4, E=3))
+    assert np.isfinite(pose.cpu().numpy()).all()
 
 
 def _adversarial_clouds():
