@@ -29,6 +29,14 @@ passages the paper leaves open (each is repeated where it is used):
   not part of this force.
 * The similarity spread sigma defaults to the population std of the
   reference descriptors (the paper gives no value, eq. 3).
+* Radius neighbourhoods (Sec. IV: radius sqrt(eX), sqrt(eY), eX and eY the
+  largest covariance eigenvalues of Sec. III-B): the members are decided by
+  the same float32 key as the k nearest neighbours, against the float32
+  threshold float32(scale^2 * lambda_max); the query is a member of its own
+  neighbourhood.  The pyramidal schedule (Sec. IV, its figure is in a
+  supplement that is not available) is read as a list of levels, each with a
+  radius scale, a sigma scale and an iteration count; t and the G schedule
+  run on across levels.
 * Curvature (Sec. III-A): PCA surface variation lambda_0/(lambda_0 +
   lambda_1 + lambda_2) of the k nearest neighbours, self included, ties in
   float32 squared distance broken by index, covariance normalised by 1/k.
@@ -147,6 +155,48 @@ def descriptors(P: np.ndarray, k: int, queries=None) -> np.ndarray:
     """Curvature of every point (or of the ``queries`` rows) of cloud P."""
     P = np.ascontiguousarray(P, dtype=np.float32)
     return surface_variation(P, knn(P, k, queries))
+
+
+def radius_descriptors(P: np.ndarray, r2, queries=None):
+    """Curvature of radius neighbourhoods (Sec. IV: neighbourhood radius
+    sqrt(eX) for the reference, sqrt(eY) for the template).  The members of
+    query i are the points j whose float32 key sqdist32 (the kNN key) is
+    <= the float32 threshold r2, the query itself included; a_i is the
+    surface variation of their covariance (1/n, centred at their mean).
+    Returns (a float64, member count int64); a = NaN where there is no member
+    (a non-finite query), 0 where the covariance trace is 0."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    r2 = np.float32(r2)
+    n = P.shape[0]
+    queries = np.arange(n) if queries is None else np.asarray(queries)
+    fin = np.isfinite(P).all(axis=1)
+    a = np.full(len(queries), np.nan)
+    cnt = np.zeros(len(queries), dtype=np.int64)
+    tree = None
+    if n > 4096:
+        from scipy.spatial import cKDTree
+
+        fidx = np.flatnonzero(fin)
+        tree = cKDTree(P[fidx].astype(np.float64))
+        # the float32 key is within a few 1e-7 of the true squared distance,
+        # so this ball holds every member
+        rad = float(np.sqrt(float(r2) * (1 + 1e-5))) + 1e-30
+    P64 = P.astype(np.float64)
+    for r, i in enumerate(queries):
+        if not fin[i]:
+            continue
+        if tree is None:
+            cand = np.arange(n)
+        else:
+            cand = fidx[np.asarray(tree.query_ball_point(P64[i], rad), dtype=np.int64)]
+        mem = cand[sqdist32(P[cand], P[i]) <= r2]
+        cnt[r] = len(mem)
+        Q = P64[mem]
+        Qc = Q - Q.mean(axis=0)
+        lam = np.linalg.eigvalsh(Qc.T @ Qc / len(mem))
+        tr = lam.sum()
+        a[r] = lam[0] / tr if tr > 0 else 0.0
+    return a, cnt
 
 
 def moments(P: np.ndarray):
@@ -319,6 +369,47 @@ def register(Y0, S: Setup, E=None, pose0: Pose | None = None, t0: int = 0, keep=
         if keep:
             hist.append(so)
     return pose, Y, hist
+
+
+# ------------------------------------------------------- pyramidal schedule
+@dataclasses.dataclass
+class Level:
+    """One level of the pyramidal schedule (Sec. IV, for noisy data: the
+    neighbourhood and sigma shrink with the iterations).  radius_scale > 0:
+    radius neighbourhoods of radius radius_scale * sqrt(lambda_max) of each
+    cloud's own covariance; 0: the k nearest neighbours.  sigma_scale
+    multiplies the level's sigma (the explicit one, else the std of the
+    level's reference curvatures)."""
+    radius_scale: float
+    sigma_scale: float
+    iters: int
+    k: int = 16
+
+
+def level_descriptors(P: np.ndarray, lev: Level) -> np.ndarray:
+    """Curvatures of cloud P for one level; the float32 radius threshold is
+    float32((radius_scale * radius_scale) * lambda_max)."""
+    if lev.radius_scale > 0:
+        lam = moments(P)[2]
+        return radius_descriptors(P, np.float32((lev.radius_scale * lev.radius_scale) * lam))[0]
+    return descriptors(P, lev.k)
+
+
+def register_pyramid(X, Y0, prm: Params, levels, pose0: Pose | None = None, wX=None, mY=None):
+    """Registration through the levels in order: each level recomputes both
+    clouds' curvatures and sigma, then runs its iterations from the pose the
+    previous level reached.  The iteration count t runs on over the levels, so
+    the G schedule of eq. 12 spans E = the sum of the levels' iterations."""
+    if sum(lev.iters for lev in levels) != prm.E:
+        raise ValueError("the levels' iterations must add up to E")
+    pose = Pose.identity() if pose0 is None else pose0
+    t0 = 0
+    for lev in levels:
+        S = make_setup(X, Y0, prm, aX=level_descriptors(X, lev), aY=level_descriptors(Y0, lev), wX=wX, mY=mY)
+        S.sigma *= lev.sigma_scale
+        pose, _, _ = register(Y0, S, E=lev.iters, pose0=pose, t0=t0)
+        t0 += lev.iters
+    return pose
 
 
 # ---------------------------------------------------------------- metrics

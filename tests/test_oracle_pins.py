@@ -237,6 +237,90 @@ def _horn_rotation(A, B):
     return quat_to_R(q).T        # column rotation of B ~ R_col A -> row form R_col^T
 
 
+# ------------------------------------------------------------ radius neighbourhoods
+def test_radius_descriptor_box_corners_closed_form():
+    """The 8 corners of a box with half-sides (3, 2, 1), radius covering all:
+    covariance diag(9, 4, 1), so every a = 1/14."""
+    P = np.array([[sx * 3.0, sy * 2.0, sz * 1.0] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)],
+                 np.float32) + np.float32([5, -7, 2])
+    a, cnt = O.radius_descriptors(P, 100.0)
+    assert (cnt == 8).all()
+    np.testing.assert_allclose(a, 1.0 / 14.0, rtol=1e-14)
+
+
+def test_radius_membership_is_inclusive_and_counts_self():
+    P = np.zeros((10, 3), np.float32)
+    P[:, 0] = np.arange(10)
+    a, cnt = O.radius_descriptors(P, 1.0)           # key 1.0 <= 1.0: both lattice neighbours
+    assert list(cnt) == [2] + [3] * 8 + [2]
+    assert (a == 0.0).all()                          # collinear: lambda_0 = lambda_1 = 0
+    a, cnt = O.radius_descriptors(P, np.nextafter(np.float32(1.0), np.float32(0)))
+    assert (cnt == 1).all() and (a == 0.0).all()     # self only: trace 0
+    Q = np.concatenate([P, P[3:4], [[np.nan, 0, 0]]]).astype(np.float32)
+    a, cnt = O.radius_descriptors(Q, 0.0)
+    assert cnt[3] == 2 and cnt[10] == 2 and cnt[0] == 1
+    assert cnt[11] == 0 and np.isnan(a[11])          # a non-finite query has no neighbourhood
+    assert not np.isnan(a[:11]).any()
+
+
+def test_radius_equals_knn_when_the_radius_isolates_k_points():
+    """With r2 set to the float32 key of a point's k-th neighbour (no tie),
+    the radius neighbourhood is the kNN neighbourhood, whose curvature is
+    pinned separately."""
+    P = ellipsoid_patch(3000, 7).astype(np.float32)
+    q = np.arange(0, 3000, 37)
+    nb = O.knn_bruteforce(P, 16, q)
+    for r, i in enumerate(q):
+        d = O.sqdist32(P[nb[r]], P[i])
+        a, cnt = O.radius_descriptors(P, d.max(), [i])
+        assert cnt[0] == 16
+        assert a[0] == pytest.approx(O.surface_variation(P, nb[r:r + 1])[0], rel=1e-11, abs=1e-15)
+
+
+def test_radius_tree_path_matches_brute_force():
+    """Clouds above 4096 points take k-d tree candidates; membership and
+    curvature equal a brute-force scan of every point."""
+    P = ellipsoid_patch(6000, 9).astype(np.float32)
+    P[17] = np.nan
+    lam = O.moments(P[np.isfinite(P).all(axis=1)])[2]
+    q = np.arange(0, 6000, 151)
+    for scale in (0.05, 0.4):
+        r2 = np.float32(scale * scale * lam)
+        a, cnt = O.radius_descriptors(P, r2, q)
+        for r, i in enumerate(q):
+            mem = np.flatnonzero(O.sqdist32(P, P[i]) <= r2)
+            assert cnt[r] == len(mem)
+            Q = P[mem].astype(np.float64)
+            lam3 = np.linalg.eigvalsh(np.cov(Q.T, bias=True).reshape(3, 3))
+            want = lam3[0] / lam3.sum() if lam3.sum() > 0 else 0.0
+            assert a[r] == pytest.approx(want, rel=1e-10, abs=1e-14)
+        assert (cnt > 1).mean() > 0.5
+
+
+def test_pyramid_split_level_equals_one_level_and_checks_E():
+    """t runs on across levels: two identical levels of 7 + 5 iterations are
+    one level of 12 (up to the rounding of re-posing the template from the
+    pose at the level boundary; restarting t would move G and the pose by
+    far more)."""
+    pr = config1(n=500)
+    prm = O.Params(p=1.0, k=16, E=12)
+    one = O.register_pyramid(pr.ref, pr.tmpl, prm, [O.Level(0.3, 0.7, 12)])
+    two = O.register_pyramid(pr.ref, pr.tmpl, prm, [O.Level(0.3, 0.7, 7), O.Level(0.3, 0.7, 5)])
+    np.testing.assert_allclose(two.as_array(), one.as_array(), rtol=0, atol=1e-13)
+    lev = O.Level(0.3, 0.7, 7)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=O.level_descriptors(pr.ref, lev), aY=O.level_descriptors(pr.tmpl, lev))
+    S.sigma *= lev.sigma_scale
+    mid, _, _ = O.register(pr.tmpl, S, E=7)
+    restart, _, _ = O.register(pr.tmpl, S, E=5, pose0=mid, t0=0)
+    assert np.abs(restart.as_array() - two.as_array()).max() > 1e-6
+    knn = O.register_pyramid(pr.ref, pr.tmpl, prm, [O.Level(0.0, 1.0, 12, k=16)])
+    S = O.make_setup(pr.ref, pr.tmpl, prm)
+    ref_pose, _, _ = O.register(pr.tmpl, S)
+    np.testing.assert_array_equal(knn.as_array(), ref_pose.as_array())
+    with pytest.raises(ValueError):
+        O.register_pyramid(pr.ref, pr.tmpl, prm, [O.Level(0.3, 1.0, 11)])
+
+
 def test_kabsch_pure_rotation_and_spd():
     rng = np.random.default_rng(4)
     Y = rng.normal(size=(30, 3)) * [1.0, 0.5, 0.2]
