@@ -143,6 +143,50 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
 int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm,
                  sgr_pose* inout, double* stats, sgr_stream_t stream);
 
+/* Curvature of radius neighbourhoods (Sec. IV sets the radius of the local
+ * neighbourhood to sqrt(eX) for the reference and sqrt(eY) for the template,
+ * eX and eY the largest covariance eigenvalues of Sec. III-B; moments_out[9]
+ * of sgr_descriptors is that eigenvalue).  The members of point i are the
+ * points j whose float32 key ((dx*dx + dy*dy) + dz*dz, each operation
+ * rounded, the key of sgr_knn) is <= r2, i itself included.
+ * a_out[n] (float32, nullable): surface variation of the members' covariance
+ *   (1/n_i, centred at their mean), 0 if its trace is 0, NaN if i has no
+ *   member (a non-finite point).
+ * count_out[n] (int32, nullable): n_i.
+ * Every point is scanned: the cost is n^2 key evaluations whatever r2.
+ * Errors: SGR_EINVAL if r2 is negative or not finite, or both outputs are
+ * NULL. */
+int sgr_descriptors_radius(sgr_ctx* ctx, const sgr_cloud* c, float r2, float* a_out, int32_t* count_out,
+                           sgr_stream_t stream);
+
+/* One level of the pyramidal schedule (Sec. IV: for noisy data the size of
+ * the neighbourhood and sigma of eq. (3) decrease with the iterations).
+ *  radius_scale > 0: radius neighbourhoods of radius radius_scale *
+ *                sqrt(lambda_max) of each cloud's own covariance (1 is the
+ *                paper's sqrt(eX), sqrt(eY)); the float32 threshold is
+ *                (float)((radius_scale * radius_scale) * lambda_max).
+ *  radius_scale = 0: the k nearest neighbours (k in [1, 32]).
+ *  sigma_scale > 0: multiplies the level's sigma (params.sigma if > 0, else
+ *                the std of the level's reference curvatures).
+ *  iters >= 1: iterations run with this level's curvatures. */
+typedef struct {
+  double radius_scale;
+  double sigma_scale;
+  int32_t iters;
+  int32_t k;
+} sgr_level;
+
+/* "register" through the levels in order: each level recomputes both
+ * clouds' curvatures, sigma and the packed clouds, then runs its iterations
+ * from the pose the previous level reached.  t runs on across the levels,
+ * so G (eq. 12) follows prm->E, which must equal the sum of the levels'
+ * iters; prm->k is not used (each level names its neighbourhood).  inout,
+ * stats and the errors as in sgr_register (the failing level is named);
+ * levels is host memory, 1 <= n_levels <= 64. */
+int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm,
+                         const sgr_level* levels, int n_levels, sgr_pose* inout, double* stats,
+                         sgr_stream_t stream);
+
 /* "residual": with corr (int32[M], -1 = none): sqrt(mean |T(y_i) - x_corr(i)|^2)
  * over i with corr >= 0; with corr == NULL: one-sided nearest-neighbour RMSE
  * template -> reference (nearest by float32 distance of the float32-rounded

@@ -40,6 +40,17 @@ class Params:
                          float(self.G1), int(self.E), int(self.flags), float(self.dt2))
 
 
+@dataclasses.dataclass
+class Level:
+    """One level of the pyramidal schedule: radius_scale > 0 selects radius
+    neighbourhoods of radius radius_scale * sqrt(lambda_max) of each cloud,
+    0 the k nearest neighbours; sigma_scale multiplies the level's sigma."""
+    radius_scale: float
+    sigma_scale: float
+    iters: int
+    k: int = 16
+
+
 def _dev(device) -> torch.device:
     d = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     if d.type != "cuda":
@@ -246,6 +257,28 @@ class Context:
                                       _ptr(pose.to(self.device, torch.float64).contiguous()), float(tau), float(sigma),
                                       float(s_min), _ptr(flags), _ptr(nn), _ptr(d2), _stream(self.device)))
         return flags, nn, d2
+
+    def descriptors_radius(self, cloud: Cloud, r2: float, want_count=True):
+        """Curvature of the radius neighbourhood (float32 key <= r2) of every
+        point, and the member counts."""
+        a = torch.empty(cloud.n, dtype=torch.float32, device=self.device)
+        cnt = torch.empty(cloud.n, dtype=torch.int32, device=self.device) if want_count else None
+        cc = cloud.c()
+        check(lib().sgr_descriptors_radius(self._h, ctypes.byref(cc), ctypes.c_float(r2), _ptr(a), _ptr(cnt),
+                                           _stream(self.device)))
+        return a, cnt
+
+    def register_pyramid(self, tmpl: Cloud, ref: Cloud, params: Params, levels, pose=None, stats=False):
+        """register() through the levels of a pyramidal schedule; params.E
+        must equal the sum of the levels' iterations."""
+        pose = pose_identity(self.device) if pose is None else pose
+        st = torch.empty((params.E, 32), dtype=torch.float64, device=self.device) if stats else None
+        lv = (_ffi.SgrLevel * len(levels))(*[_ffi.SgrLevel(float(v.radius_scale), float(v.sigma_scale), int(v.iters),
+                                                          int(v.k)) for v in levels])
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_register_pyramid(self._h, ctypes.byref(ct), ctypes.byref(cr), ctypes.byref(pr), lv,
+                                         len(levels), _ptr(pose), _ptr(st), _stream(self.device)))
+        return pose, st
 
     def register_batch(self, tmpls, refs, params: Params, poses=None, want_energy=True, stats=False):
         """B registrations in one batched call; returns (poses [B, 13], energy [B] or None, stats)."""

@@ -26,6 +26,11 @@ class SgrParams(ctypes.Structure):
                 ("E", ctypes.c_int32), ("flags", ctypes.c_int32), ("dt2", ctypes.c_double)]
 
 
+class SgrLevel(ctypes.Structure):
+    _fields_ = [("radius_scale", ctypes.c_double), ("sigma_scale", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("k", ctypes.c_int32)]
+
+
 class SgrError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"sgreg error {code}: {msg}")
@@ -64,6 +69,8 @@ SIGNATURES = {
     "sgr_unrolled_fwd": [P, CP, P, CP, P, P, P, PP, I, P, P, P],
     "sgr_unrolled_bwd": [P, CP, P, CP, P, P, P, PP, I, P, P, P, P, P],
     "sgr_change_detect": [P, CP, P, CP, P, P, D, D, D, P, P, P, P],
+    "sgr_descriptors_radius": [P, CP, ctypes.c_float, P, P, P],
+    "sgr_register_pyramid": [P, CP, CP, PP, ctypes.POINTER(SgrLevel), I, P, P, P],
 }
 
 

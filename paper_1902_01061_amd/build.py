@@ -13,12 +13,12 @@ OUT = os.path.join(HERE, "libsgreg.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["descriptors.hip", "force.hip", "pose.hip", "residual.hip", "adjoint.hip", "mixed.hip", "knn_grid.hip",
-           "sort.hip", "change.hip", "capi.cpp"]
+           "sort.hip", "change.hip", "radius.hip", "capi.cpp"]
 # Translation units whose results are integers decided by floating point
 # (neighbour ranks by the float32 key (dx*dx + dy*dy) + dz*dz, change flags)
 # are compiled without fused multiply-add, so that every operation is
 # rounded on its own exactly as the key is defined; the others may fuse.
-NO_FUSION = {"descriptors.hip", "knn_grid.hip", "change.hip"}
+NO_FUSION = {"descriptors.hip", "knn_grid.hip", "change.hip", "radius.hip"}
 # Packed FP32 instructions are disabled for every HIP translation unit.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
          "-packed-fp32-ops", "-munsafe-fp-atomics", "-I", os.path.join(ROOT, "include")]

@@ -44,6 +44,7 @@ struct sgr_ctx {
   size_t ws_size = 0;
   GraphCache gc;   // single registration
   GraphCache gcb;  // batch / multi-start
+  std::vector<GraphCache> gcp;  // pyramidal schedule, one per level
   TileTable tiles;
 };
 
@@ -394,6 +395,118 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
 }
 
 
+// ------------------------------------------------- single registration
+// Device buffers of one registration (curvatures, moments of both clouds,
+// derived constants, packed reference and template, wrench slots, search and
+// sort scratch), carved from the context workspace.
+struct SingleWs {
+  float* aX;
+  float* aY;
+  double* mom;  // template [0, 10), reference [10, 20)
+  Derived* dv;
+  float4* ref4;
+  float* lw;
+  double* wpart;
+  char* gws;
+  int* perm;
+  char* sws;
+  float4* tm4;
+  float2* tmx;
+  Tiles T, TM;  // FP32 kernel (and the final energy); kernel of the other iterations
+  int nslot;
+};
+
+// kmax: largest k of a nearest-neighbour search the call makes (0: none).
+int carve_single(sgr_ctx* ctx, int M, int N, const sgr_params* prm, int kmax, SingleWs& w) {
+  const int pm = pmode_of(prm->p);
+  w.T = ctx->tiles.pick(M, N, pm);
+  w.TM = tiles_for(ctx, M, N, prm);
+  w.nslot = std::max(force_shape(ctx, M, N, w.T, pm).slots, w.TM.nblk);
+  const size_t gbytes = kmax > 0 ? std::max(grid_knn_workspace(N, kmax), grid_knn_workspace(M, kmax)) : 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    Carve c{pass ? ctx->ws : nullptr};
+    w.aX = c.take<float>(N);
+    w.aY = c.take<float>(M);
+    w.mom = c.take<double>(20);
+    w.dv = c.take<Derived>(1);
+    w.ref4 = c.take<float4>(pad_n(N));
+    w.lw = c.take<float>(pad_n(N));
+    w.wpart = c.take<double>((size_t)w.nslot * WR_STRIDE);
+    w.gws = c.take<char>(gbytes);
+    w.perm = c.take<int>(M);
+    w.sws = c.take<char>(sort_perm_workspace(M, 1));
+    w.tm4 = c.take<float4>(M);
+    w.tmx = c.take<float2>(M);
+    if (!pass)
+      if (int e = ensure_ws(ctx, c.off)) return e;
+  }
+  return SGR_OK;
+}
+
+// Derived constants from the curvatures and moments already in w, then the
+// packed reference and the curvature-sorted packed template.
+int setup_single(const sgr_cloud* tmpl, const sgr_cloud* ref, const PrepParams& P, SingleWs& w, hipStream_t st) {
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  HIPCHK(launch_prepare(w.aX, ref->m, N, w.aY, tmpl->m, M, w.mom, w.mom + 10, P, w.dv, st));
+  HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, w.aX, ref->m, N, w.dv, w.ref4, w.lw, st));
+  HIPCHK(launch_sort_perm(w.aY, M, w.perm, w.sws, st));
+  HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, w.aY, tmpl->m, M, w.perm, w.dv, w.tm4, w.tmx, st));
+  return SGR_OK;
+}
+
+// Iterations [t0, t1) of (force, update) on the pose in place, captured in a
+// graph cached in gc unless FLAG_NO_GRAPH is set or there is one iteration.
+// G follows eq. 12 over prm->E; the last of the E iterations uses the FP32
+// kernel and accumulates the energy.
+int run_single_loop(sgr_ctx* ctx, GraphCache& gc, const sgr_cloud* tmpl, const sgr_cloud* ref,
+                    const sgr_params* prm, const SingleWs& w, sgr_pose* inout, double* stats, int t0, int t1,
+                    hipStream_t st) {
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  const int pm = pmode_of(prm->p);
+  auto loop = [&](hipStream_t s) -> int {
+    for (int t = t0; t < t1; ++t) {
+      const bool last = t == prm->E - 1;
+      const bool mixed = is_mixed(prm) && !last;   // the final energy comes from the FP32 kernel
+      const bool wu = !mixed && (stats != nullptr || last);
+      const Tiles& Tt = mixed ? w.TM : w.T;
+      ForceArgs A{tmpl->x, tmpl->y, tmpl->z, w.aY, tmpl->m, w.ref4, w.lw, (const double*)inout, w.dv, M, N,
+                  Tt.chunk_len, Tt.n_chunks, t, 0.0, w.wpart, nullptr, w.perm, w.tm4, w.tmx};
+      int used = Tt.nblk;
+      if (mixed) {
+        HIPCHK(launch_force_mixed(A, false, s));
+      } else {
+        const FLaunch L = force_shape(ctx, M, N, w.T, pm);
+        HIPCHK(run_force(A, w.T, L, pm, wu, false, s));
+        used = L.slots;
+      }
+      HIPCHK(launch_update(w.wpart, used, (const double*)inout, (double*)inout, w.dv, t, 0.0, 1, nullptr,
+                           stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
+    }
+    return SGR_OK;
+  };
+  if ((prm->flags & FLAG_NO_GRAPH) || t1 - t0 < 2) return loop(st);
+  struct Key {
+    const void* p[10];
+    int64_t n[2];
+    int32_t t[2];
+    sgr_params prm;
+    Tiles T;
+    void* ws;
+  } key;
+  std::memset(&key, 0, sizeof(key));
+  const void* ptrs[10] = {tmpl->x, tmpl->y, tmpl->z, tmpl->m, ref->x, ref->y, ref->z, ref->m, inout, stats};
+  std::memcpy(key.p, ptrs, sizeof(ptrs));
+  key.n[0] = M;
+  key.n[1] = N;
+  key.t[0] = t0;
+  key.t[1] = t1;
+  key.prm = *prm;
+  key.T = w.T;
+  key.ws = ctx->ws;
+  std::vector<uint8_t> kb((uint8_t*)&key, (uint8_t*)&key + sizeof(key));
+  return run_graph(ctx, gc, kb, loop, st);
+}
+
 // ------------------------------------------------- unrolled differentiation
 // Host copy of G_t (eq. 12), as the force kernel evaluates it.
 double G_host(const sgr_params* prm, int t) {
@@ -512,7 +625,9 @@ int sgr_destroy(sgr_ctx* ctx) {
   if (!ctx) return SGR_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  for (GraphCache* g : {&ctx->gc, &ctx->gcb}) {
+  std::vector<GraphCache*> caches = {&ctx->gc, &ctx->gcb};
+  for (GraphCache& g : ctx->gcp) caches.push_back(&g);
+  for (GraphCache* g : caches) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
   }
@@ -615,124 +730,96 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
   if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
   if (tmpl->n < prm->k || ref->n < prm->k) return fail(SGR_EINVAL, "a cloud has fewer points than k");
+  if (int e = check_mixed(prm)) return e;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
-  const int pm = pmode_of(prm->p);
-  if (int e = check_mixed(prm)) return e;
-  const Tiles T = ctx->tiles.pick(M, N, pm);     // FP32 kernel (and the final energy)
-  const Tiles TM = tiles_for(ctx, M, N, prm);    // the kernel of the other iterations
-  Carve cv{nullptr};
-  cv.take<float>(N);
-  cv.take<float>(M);
-  cv.take<double>(20);
-  cv.take<Derived>(1);
-  cv.take<float4>(pad_n(N));
-  cv.take<float>(pad_n(N));
-  const int nslot = std::max(force_shape(ctx, M, N, T, pm).slots, TM.nblk);
-  cv.take<double>((size_t)nslot * WR_STRIDE);
-  cv.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
-  cv.take<int>(M);
-  cv.take<char>(sort_perm_workspace(M, 1));
-  cv.take<float4>(M);
-  cv.take<float2>(M);
-  if (int e = ensure_ws(ctx, cv.off)) return e;
-  Carve w{ctx->ws};
-  float* aX = w.take<float>(N);
-  float* aY = w.take<float>(M);
-  double* mom = w.take<double>(20);
-  Derived* dv = w.take<Derived>(1);
-  float4* ref4 = w.take<float4>(pad_n(N));
-  float* lw = w.take<float>(pad_n(N));
-  double* wpart = w.take<double>((size_t)nslot * WR_STRIDE);
-  char* gws = w.take<char>(std::max(grid_knn_workspace(N, prm->k), grid_knn_workspace(M, prm->k)));
-  int* perm = w.take<int>(M);
-  char* sws = w.take<char>(sort_perm_workspace(M, 1));
-  float4* tm4 = w.take<float4>(M);
-  float2* tmx = w.take<float2>(M);
-
-  HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, prm->k, aX, nullptr, gws, st));
-  HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, prm->k, aY, nullptr, gws, st));
-  HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, mom + 10, st));
-  HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, mom, st));
-  HIPCHK(launch_prepare(aX, ref->m, N, aY, tmpl->m, M, mom, mom + 10, prep_of(prm), dv, st));
-  HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, aX, ref->m, N, dv, ref4, lw, st));
-  HIPCHK(launch_sort_perm(aY, M, perm, sws, st));
-  HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, aY, tmpl->m, M, perm, dv, tm4, tmx, st));
-
-  auto loop = [&](hipStream_t s) -> int {
-    for (int t = 0; t < prm->E; ++t) {
-      const bool last = t == prm->E - 1;
-      const bool mixed = is_mixed(prm) && !last;   // the final energy comes from the FP32 kernel
-      const bool wu = !mixed && (stats != nullptr || last);
-      const Tiles& Tt = mixed ? TM : T;
-      ForceArgs A{tmpl->x, tmpl->y, tmpl->z, aY, tmpl->m, ref4, lw, (const double*)inout, dv, M, N,
-                  Tt.chunk_len, Tt.n_chunks, t, 0.0, wpart, nullptr, perm, tm4, tmx};
-      int used = Tt.nblk;
-      if (mixed) {
-        HIPCHK(launch_force_mixed(A, false, s));
-      } else {
-        const FLaunch L = force_shape(ctx, M, N, T, pm);
-        HIPCHK(run_force(A, T, L, pm, wu, false, s));
-        used = L.slots;
-      }
-      HIPCHK(launch_update(wpart, used, (const double*)inout, (double*)inout, dv, t, 0.0, 1, nullptr,
-                           stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
-    }
-    return SGR_OK;
-  };
-
-  const bool use_graph = (prm->flags & 1) == 0 && prm->E > 1;
-  if (!use_graph) {
-    if (int e = loop(st)) return e;
-  } else {
-    struct Key {
-      const void* p[10];
-      int64_t n[2];
-      sgr_params prm;
-      Tiles T;
-      void* ws;
-    } key;
-    std::memset(&key, 0, sizeof(key));
-    const void* ptrs[10] = {tmpl->x, tmpl->y, tmpl->z, tmpl->m, ref->x, ref->y, ref->z, ref->m, inout, stats};
-    std::memcpy(key.p, ptrs, sizeof(ptrs));
-    key.n[0] = M;
-    key.n[1] = N;
-    key.prm = *prm;
-    key.T = T;
-    key.ws = ctx->ws;
-    std::vector<uint8_t> kb((uint8_t*)&key, (uint8_t*)&key + sizeof(key));
-    if (!ctx->gc.exec || kb != ctx->gc.key) {
-      if (ctx->gc.exec) (void)hipGraphExecDestroy(ctx->gc.exec);
-      if (ctx->gc.graph) (void)hipGraphDestroy(ctx->gc.graph);
-      ctx->gc.exec = nullptr;
-      ctx->gc.graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
-      int e = loop(ctx->cap);
-      hipGraph_t g = nullptr;
-      hipError_t ce = hipStreamEndCapture(ctx->cap, &g);
-      if (e) {
-        if (g) (void)hipGraphDestroy(g);
-        return e;
-      }
-      if (ce != hipSuccess) return fail(SGR_EHIP, std::string("graph capture: ") + hipGetErrorString(ce));
-      hipGraphExec_t ex = nullptr;
-      hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      if (ie != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return fail(SGR_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
-      }
-      ctx->gc.graph = g;
-      ctx->gc.exec = ex;
-      ctx->gc.key = kb;
-    }
-    HIPCHK(hipGraphLaunch(ctx->gc.exec, st));
-  }
+  SingleWs w;
+  if (int e = carve_single(ctx, M, N, prm, prm->k, w)) return e;
+  HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, prm->k, w.aX, nullptr, w.gws, st));
+  HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, prm->k, w.aY, nullptr, w.gws, st));
+  HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, w.mom + 10, st));
+  HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, w.mom, st));
+  if (int e = setup_single(tmpl, ref, prep_of(prm), w, st)) return e;
+  if (int e = run_single_loop(ctx, ctx->gc, tmpl, ref, prm, w, inout, stats, 0, prm->E, st)) return e;
   int32_t status = 0;
-  HIPCHK(hipMemcpyAsync(&status, &dv->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&status, &w.dv->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (status & ST_DEGENERATE) return fail(SGR_EDEGENERATE, "degenerate input: zero variance or zero curvature spread");
   if (status) return fail(SGR_ENUMERIC, "numeric failure in the update (status " + std::to_string(status) + ")");
+  return SGR_OK;
+}
+
+int sgr_descriptors_radius(sgr_ctx* ctx, const sgr_cloud* c, float r2, float* a_out, int32_t* count_out,
+                           sgr_stream_t stream) {
+  if (!ctx) return fail(SGR_EINVAL, "NULL ctx");
+  if (int e = check_cloud(c, "cloud")) return e;
+  if (!(r2 >= 0.0f) || !std::isfinite(r2)) return fail(SGR_EINVAL, "r2 must be finite and >= 0");
+  if (!a_out && !count_out) return fail(SGR_EINVAL, "nothing to compute");
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(launch_radius_desc(c->x, c->y, c->z, (int)c->n, nullptr, 0.0, r2, a_out, count_out, (hipStream_t)stream));
+  return SGR_OK;
+}
+
+int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm,
+                         const sgr_level* levels, int n_levels, sgr_pose* inout, double* stats, sgr_stream_t stream) {
+  if (!ctx || !inout || !levels) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (int e = check_mixed(prm)) return e;
+  if (n_levels < 1 || n_levels > 64) return fail(SGR_EINVAL, "n_levels must be in [1, 64]");
+  int64_t total = 0;
+  int kmax = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    const sgr_level& v = levels[l];
+    if (v.iters < 1) return fail(SGR_EINVAL, "every level needs iters >= 1");
+    if (!std::isfinite(v.radius_scale) || v.radius_scale < 0) return fail(SGR_EINVAL, "radius_scale must be >= 0");
+    if (!std::isfinite(v.sigma_scale) || !(v.sigma_scale > 0)) return fail(SGR_EINVAL, "sigma_scale must be > 0");
+    if (v.radius_scale == 0) {
+      if (v.k < 1 || v.k > 32) return fail(SGR_EINVAL, "a kNN level needs k in [1, 32]");
+      if (tmpl->n < v.k || ref->n < v.k) return fail(SGR_EINVAL, "a cloud has fewer points than a level's k");
+      kmax = std::max(kmax, (int)v.k);
+    }
+    total += v.iters;
+  }
+  if (total != prm->E) return fail(SGR_EINVAL, "the levels' iterations must add up to E");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  SingleWs w;
+  if (int e = carve_single(ctx, M, N, prm, kmax, w)) return e;
+  if ((int)ctx->gcp.size() < n_levels) ctx->gcp.resize(n_levels);
+  HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, w.mom + 10, st));
+  HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, w.mom, st));
+  std::vector<int32_t> status(n_levels, 0);
+  int t0 = 0;
+  for (int l = 0; l < n_levels; ++l) {
+    const sgr_level& v = levels[l];
+    if (v.radius_scale > 0) {
+      const double s2 = v.radius_scale * v.radius_scale;
+      HIPCHK(launch_radius_desc(ref->x, ref->y, ref->z, N, w.mom + 10, s2, 0.f, w.aX, nullptr, st));
+      HIPCHK(launch_radius_desc(tmpl->x, tmpl->y, tmpl->z, M, w.mom, s2, 0.f, w.aY, nullptr, st));
+    } else {
+      HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, v.k, w.aX, nullptr, w.gws, st));
+      HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, v.k, w.aY, nullptr, w.gws, st));
+    }
+    PrepParams P = prep_of(prm);
+    P.sigma_scale = v.sigma_scale;
+    if (int e = setup_single(tmpl, ref, P, w, st)) return e;
+    if (int e = run_single_loop(ctx, ctx->gcp[l], tmpl, ref, prm, w, inout, stats, t0, t0 + v.iters, st)) return e;
+    HIPCHK(hipMemcpyAsync(&status[l], &w.dv->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    t0 += v.iters;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int l = 0; l < n_levels; ++l) {
+    if (status[l] & ST_DEGENERATE)
+      return fail(SGR_EDEGENERATE, "degenerate input at level " + std::to_string(l) +
+                                       ": zero variance or zero curvature spread");
+    if (status[l])
+      return fail(SGR_ENUMERIC, "numeric failure in the update at level " + std::to_string(l) + " (status " +
+                                    std::to_string(status[l]) + ")");
+  }
   return SGR_OK;
 }
 

@@ -92,7 +92,7 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   D.lamY0 = mom_t[9];
   D.abar = abar;
   const double sd = sqrt(v[0] / (double)N);
-  D.sigma = P.sigma > 0 ? P.sigma : sd;
+  D.sigma = (P.sigma > 0 ? P.sigma : sd) * P.sigma_scale;
   D.Z = s[1];
   D.Mtot = s[2];
   D.Mcount = (double)M;

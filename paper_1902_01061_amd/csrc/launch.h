@@ -17,6 +17,7 @@ struct PrepParams {
   int32_t E;
   int32_t g_mode;
   int32_t cold_svd = 0;  // 1: the update's SVD starts cold (a deterministic function of C)
+  double sigma_scale = 1.0;  // multiplies sigma (explicit or the std of the reference curvatures)
 };
 
 struct ForceArgs {
@@ -161,6 +162,12 @@ hipError_t launch_change(const float* yx, const float* yy, const float* yz, cons
 hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, hipStream_t st);
 hipError_t launch_moments(const float* x, const float* y, const float* z, int64_t n, double* out, hipStream_t st);
+// Curvature of the radius neighbourhood of every point: members have float32
+// key <= r2, where r2 = (float)(scale2 * mom[9]) when mom is given (mom[9] =
+// largest covariance eigenvalue, as launch_moments writes it), else r2_in.
+// a_out and cnt_out (member counts) may each be nullptr.
+hipError_t launch_radius_desc(const float* x, const float* y, const float* z, int n, const double* mom, double scale2,
+                              float r2_in, float* a_out, int32_t* cnt_out, hipStream_t st);
 hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const float* aY, const float* mY, int64_t M,
                           const double* mom_t, const double* mom_r, const PrepParams& P, Derived* out, hipStream_t st);
 hipError_t launch_pack_ref(const float* x, const float* y, const float* z, const float* aX, const float* wX, int64_t N,
