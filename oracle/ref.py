@@ -157,6 +157,44 @@ def descriptors(P: np.ndarray, k: int, queries=None) -> np.ndarray:
     return surface_variation(P, knn(P, k, queries))
 
 
+def tent_weights(u: np.ndarray, D: int) -> np.ndarray:
+    """Soft binning of values u in [0, 1] into D bins centred at b/(D-1):
+    bin b receives max(0, 1 - (D-1)|u - b/(D-1)|), so every u spreads a unit
+    weight over its two nearest centres (linear interpolation).  (n, D)."""
+    u = np.asarray(u, np.float64)
+    c = np.arange(D) / (D - 1)
+    return np.maximum(0.0, 1.0 - (D - 1) * np.abs(u[:, None] - c[None, :]))
+
+
+def normals(P: np.ndarray, nbr: np.ndarray):
+    """Unit normal of each point: the eigenvector of the smallest eigenvalue
+    of its neighbourhood covariance (1/k, centred at the neighbourhood mean);
+    its sign is arbitrary.  Also returns the eigenvalues (ascending), from
+    which a caller can tell whether the normal is determined (lambda_0 <
+    lambda_1)."""
+    Q = P.astype(np.float64)[nbr]
+    Qc = Q - Q.mean(axis=1, keepdims=True)
+    C = np.einsum("nki,nkj->nij", Qc, Qc) / nbr.shape[1]
+    lam, vec = np.linalg.eigh(C)
+    return vec[:, :, 0], lam
+
+
+def normal_histograms(P: np.ndarray, k: int, D: int, queries=None):
+    """Vector shape descriptor (Sec. III-A names histograms of normals among
+    the features evaluated): for point i with k nearest neighbours N_i (self
+    included), h_i = (1/k) sum_{j in N_i} tent_weights(|n_i . n_j|), D bins
+    over [0, 1].  |.| removes the arbitrary sign of the normals; the soft
+    bins make h continuous in the normals.  Returns (h (nq, D), eigenvalues
+    of each query's covariance)."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    n_all, lam_all = normals(P, knn(P, k))
+    q = np.arange(len(P)) if queries is None else np.asarray(queries)
+    nbr = knn(P, k, q)
+    u = np.abs(np.einsum("qc,qkc->qk", n_all[q], n_all[nbr]))
+    h = tent_weights(np.minimum(u, 1.0).reshape(-1), D).reshape(len(q), k, D).mean(axis=1)
+    return h, lam_all[q]
+
+
 def radius_descriptors(P: np.ndarray, r2, queries=None):
     """Curvature of radius neighbourhoods (Sec. IV: neighbourhood radius
     sqrt(eX) for the reference, sqrt(eY) for the template).  The members of
@@ -241,9 +279,20 @@ def make_setup(X, Y0, prm: Params, aX=None, aY=None, wX=None, mY=None) -> Setup:
     wX = np.ones(N) if wX is None else np.asarray(wX, dtype=np.float64)
     mY = np.ones(M) if mY is None else np.asarray(mY, dtype=np.float64)
     _, _, lamX = moments(X)
-    sigma = prm.sigma if prm.sigma > 0 else float(np.std(np.asarray(aX, dtype=np.float64)))
+    aX64 = np.asarray(aX, dtype=np.float64)
+    if aX64.ndim == 2:
+        # vector descriptors: sigma^2 = mean_j |a_j - abar|^2, the population
+        # spread (the std of the scalar case when D = 1); g_mode 1 needs a
+        # scalar curvature
+        if prm.g_mode == 1:
+            raise ValueError("g_mode 1 needs scalar descriptors")
+        spread = float(np.sqrt(np.mean(np.sum((aX64 - aX64.mean(axis=0)) ** 2, axis=1))))
+    else:
+        spread = float(np.std(aX64))
+    sigma = prm.sigma if prm.sigma > 0 else spread
     return Setup(X=X, aX=np.asarray(aX, np.float64), aY=np.asarray(aY, np.float64), wX=wX, mY=mY,
-                 lamX=lamX, L=math.sqrt(lamX), abar=float(np.mean(aX)), sigma=sigma,
+                 lamX=lamX, L=math.sqrt(lamX), abar=float(np.mean(aX)) if aX64.ndim == 1 else float("nan"),
+                 sigma=sigma,
                  Z=float(wX.sum()), prm=prm)
 
 
@@ -254,7 +303,13 @@ def pair_weights(Yi, aYi, S: Setup):
     prm = S.prm
     r = Yi[:, None, :] - S.X[None, :, :]
     q = np.einsum("bnk,bnk->bn", r, r) + prm.eps ** 2
-    s = np.exp(-((aYi[:, None] - S.aX[None, :]) ** 2) / S.sigma ** 2)        # eq. 3
+    if S.aX.ndim == 2:                                                        # vector descriptors
+        d2 = np.zeros((len(aYi), len(S.aX)))
+        for c in range(S.aX.shape[1]):
+            d2 += (aYi[:, None, c] - S.aX[None, :, c]) ** 2
+    else:
+        d2 = (aYi[:, None] - S.aX[None, :]) ** 2
+    s = np.exp(-d2 / S.sigma ** 2)                                            # eq. 3
     if prm.g_mode == 1:                                                       # eq. 10
         g = (aYi[:, None] / S.abar) * (S.aX[None, :] / S.abar) * s
     elif prm.g_mode == 2:                                                     # eq. 1: masses only

@@ -321,6 +321,71 @@ def test_pyramid_split_level_equals_one_level_and_checks_E():
         O.register_pyramid(pr.ref, pr.tmpl, prm, [O.Level(0.3, 1.0, 11)])
 
 
+# ------------------------------------------------------------ vector descriptors
+def test_tent_weights_by_hand_and_partition_of_unity():
+    w = O.tent_weights(np.array([0.0, 0.25, 0.5, 0.8, 1.0]), 3)      # centres 0, 0.5, 1
+    np.testing.assert_allclose(w, [[1, 0, 0], [0.5, 0.5, 0], [0, 1, 0], [0, 0.4, 0.6], [0, 0, 1]], atol=1e-15)
+    u = np.random.default_rng(2).random(1000)
+    for D in (2, 5, 16, 30):
+        np.testing.assert_allclose(O.tent_weights(u, D).sum(axis=1), 1.0, rtol=1e-14)
+
+
+def test_normal_histograms_planes_and_crease():
+    """On a plane every normal is the same, so every h is the last unit
+    vector; on two perpendicular half-planes, points whose neighbourhoods do
+    not reach the crease have the same, and points at the crease, whose
+    normals tilt towards the bisector, spread their weight below the last
+    bin."""
+    g = np.stack(np.meshgrid(np.arange(20), np.arange(20)), -1).reshape(-1, 2).astype(np.float64) * 0.1
+    plane = np.concatenate([g, np.zeros((len(g), 1))], axis=1)
+    rng = np.random.default_rng(3)
+    plane = plane @ O.Pose(1.0, rot_axis_angle([1, 2, 3], 40.0), np.zeros(3)).R.T + 2.0
+    h, _ = O.normal_histograms(plane.astype(np.float32), 8, 16)
+    np.testing.assert_allclose(h[:, -1], 1.0, atol=1e-6)
+    np.testing.assert_allclose(h[:, :-1], 0.0, atol=1e-6)
+    a = np.concatenate([g[:, :1] * 0 + g[:, :1], g[:, 1:], np.zeros((len(g), 1))], axis=1)    # z = 0, x >= 0
+    b = np.concatenate([-np.ones((len(g), 1)) * 0.05 - g[:, :1] * 0, g[:, 1:], g[:, :1] + 0.05], axis=1)  # x = -0.05
+    P = np.concatenate([a, b]).astype(np.float32)
+    h, lam = O.normal_histograms(P, 8, 16)
+    far = (P[:, 0] > 0.45) | (P[:, 2] > 0.45)
+    np.testing.assert_allclose(h[far, -1], 1.0, atol=1e-6)
+    near = (P[:, 0] < 0.05) & (P[:, 2] < 0.01)
+    assert near.sum() == 20 and (h[near, -1] < 0.9).all()
+    np.testing.assert_allclose(h.sum(axis=1), 1.0, rtol=1e-12)
+
+
+def test_normal_histograms_invariance():
+    P = ellipsoid_patch(3000, 11).astype(np.float64)
+    q = np.arange(0, 3000, 29)
+    h, lam = O.normal_histograms(P.astype(np.float32), 16, 16, q)
+    T = (2.5 * P @ rot_axis_angle([0.3, -1, 0.5], 77.0).T + np.array([4.0, -2.0, 1.0])).astype(np.float32)
+    h2, lam2 = O.normal_histograms(T, 16, 16, q)
+    ok = (lam[:, 1] - lam[:, 0]) > 1e-3 * lam.sum(axis=1)     # normal determined
+    assert ok.mean() > 0.9
+    np.testing.assert_allclose(h2[ok], h[ok], atol=2e-4)      # float32 inputs: neighbours may move slightly
+
+
+def test_vector_similarity_reduces_to_scalar_and_is_permutation_invariant():
+    """D = 1 vector descriptors give the scalar force (eq. 3), and the force
+    does not depend on the order of the descriptor dimensions."""
+    pr = random_pair(30, 45, seed=14)
+    rng = np.random.default_rng(8)
+    aX, aY = rng.uniform(0, 0.3, 45), rng.uniform(0, 0.3, 30)
+    S1 = _setup(pr.ref.astype(np.float64), aX, aY, p=1.0, sigma=0.0, L=0.8)
+    Sv = _setup(pr.ref.astype(np.float64), aX[:, None], aY[:, None], p=1.0, sigma=0.0, L=0.8)
+    assert Sv.sigma == pytest.approx(S1.sigma, rel=1e-14)
+    f1, U1 = O.forces(pr.tmpl, S1, 3.0)
+    fv, Uv = O.forces(pr.tmpl, Sv, 3.0)
+    np.testing.assert_allclose(fv, f1, rtol=1e-13, atol=1e-15)
+    AX, AY = rng.random((45, 16)), rng.random((30, 16))
+    perm = rng.permutation(16)
+    Sa = _setup(pr.ref.astype(np.float64), AX, AY, p=2.0, sigma=0.0, eps=0.01, L=0.8)
+    Sb = _setup(pr.ref.astype(np.float64), AX[:, perm], AY[:, perm], p=2.0, sigma=0.0, eps=0.01, L=0.8)
+    np.testing.assert_allclose(O.forces(pr.tmpl, Sb, 3.0)[0], O.forces(pr.tmpl, Sa, 3.0)[0], rtol=1e-12)
+    with pytest.raises(ValueError):
+        _setup(pr.ref.astype(np.float64), AX, AY, g_mode=1)
+
+
 def test_kabsch_pure_rotation_and_spd():
     rng = np.random.default_rng(4)
     Y = rng.normal(size=(30, 3)) * [1.0, 0.5, 0.2]
