@@ -187,6 +187,34 @@ int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* r
                          const sgr_level* levels, int n_levels, sgr_pose* inout, double* stats,
                          sgr_stream_t stream);
 
+/* Vector shape descriptor (Sec. III-A lists histograms of normals among
+ * the local shape features): h_out[n][D] (float32, row-major), the soft
+ * histogram of u = |n_i . n_j| over the k nearest neighbours j of point i
+ * (self included, lists as sgr_knn), n the unit normal (eigenvector of the
+ * smallest eigenvalue of the neighbourhood covariance, 1/k, centred; its sign
+ * is arbitrary, hence |.|).  Bin b (centre b/(D-1)) receives the tent weight
+ * max(0, 1 - (D-1)|u - b/(D-1)|); h_i sums to 1.  A point with a non-finite
+ * neighbour normal gets NaN.  Where the two smallest eigenvalues coincide the
+ * normal, and with it h, is not determined.
+ * Errors: SGR_EINVAL if k < 1, k > 32, n < k, or D outside [2, 30]. */
+int sgr_descriptors_hn(sgr_ctx* ctx, const sgr_cloud* c, int k, int D, float* h_out, sgr_stream_t stream);
+
+/* sgr_step and sgr_register with vector descriptors: eq. (3) with
+ * |a_i - a_j|^2 summed over D dimensions, a_t[M][D] and a_r[N][D] (device,
+ * float32, row-major; e.g. from sgr_descriptors_hn).  sigma <= 0 selects
+ * sigma^2 = mean_j |a_j - abar|^2 over the reference (abar its mean; the std
+ * of the scalar case when D = 1).  The similarity exponents of all pairs are
+ * one dense contraction, evaluated on the matrix cores in FP32.  Supported:
+ * p = 1, g_mode 0, no mixed precision, 1 <= D <= 30 (SGR_EINVAL otherwise).
+ * Other arguments, outputs and errors as in sgr_step / sgr_register
+ * (sgr_register_vec computes the moments itself; SGR_EDEGENERATE also for
+ * zero descriptor spread). */
+int sgr_step_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                 int D, const double* mom_t, const double* mom_r, const sgr_params* prm, int t,
+                 const sgr_pose* in, sgr_pose* out, double* wrench_out, float* f_out, sgr_stream_t stream);
+int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                     int D, const sgr_params* prm, sgr_pose* inout, double* stats, sgr_stream_t stream);
+
 /* "residual": with corr (int32[M], -1 = none): sqrt(mean |T(y_i) - x_corr(i)|^2)
  * over i with corr >= 0; with corr == NULL: one-sided nearest-neighbour RMSE
  * template -> reference (nearest by float32 distance of the float32-rounded

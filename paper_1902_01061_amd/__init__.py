@@ -280,6 +280,41 @@ class Context:
                                          len(levels), _ptr(pose), _ptr(st), _stream(self.device)))
         return pose, st
 
+    def descriptors_hn(self, cloud: Cloud, k: int, D: int) -> torch.Tensor:
+        """Soft histograms of normals, (n, D) float32."""
+        h = torch.empty((cloud.n, D), dtype=torch.float32, device=self.device)
+        c = cloud.c()
+        check(lib().sgr_descriptors_hn(self._h, ctypes.byref(c), int(k), int(D), _ptr(h), _stream(self.device)))
+        return h
+
+    def step_vec(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params, t: int, pose_in,
+                 want_wrench=False, want_f=False):
+        """step() with vector descriptors a_t (M, D), a_r (N, D)."""
+        D = int(a_t.shape[1])
+        if a_r.shape[1] != D:
+            raise ValueError("descriptor widths differ")
+        pout = torch.empty(13, dtype=torch.float64, device=self.device)
+        wr = torch.empty(13, dtype=torch.float64, device=self.device) if want_wrench else None
+        f = torch.empty((tmpl.n, 3), dtype=torch.float32, device=self.device) if want_f else None
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_step_vec(self._h, ctypes.byref(ct), _ptr(a_t.contiguous()), ctypes.byref(cr),
+                                 _ptr(a_r.contiguous()), D, _ptr(mom_t), _ptr(mom_r), ctypes.byref(pr), int(t),
+                                 _ptr(pose_in), _ptr(pout), _ptr(wr), _ptr(f), _stream(self.device)))
+        return pout, wr, f
+
+    def register_vec(self, tmpl: Cloud, a_t, ref: Cloud, a_r, params: Params, pose=None, stats=False):
+        """register() with vector descriptors a_t (M, D), a_r (N, D)."""
+        D = int(a_t.shape[1])
+        if a_r.shape[1] != D:
+            raise ValueError("descriptor widths differ")
+        pose = pose_identity(self.device) if pose is None else pose
+        st = torch.empty((params.E, 32), dtype=torch.float64, device=self.device) if stats else None
+        ct, cr, pr = tmpl.c(), ref.c(), params.c()
+        check(lib().sgr_register_vec(self._h, ctypes.byref(ct), _ptr(a_t.contiguous()), ctypes.byref(cr),
+                                     _ptr(a_r.contiguous()), D, ctypes.byref(pr), _ptr(pose), _ptr(st),
+                                     _stream(self.device)))
+        return pose, st
+
     def register_batch(self, tmpls, refs, params: Params, poses=None, want_energy=True, stats=False):
         """B registrations in one batched call; returns (poses [B, 13], energy [B] or None, stats)."""
         B = len(tmpls)

@@ -45,6 +45,7 @@ struct sgr_ctx {
   GraphCache gc;   // single registration
   GraphCache gcb;  // batch / multi-start
   std::vector<GraphCache> gcp;  // pyramidal schedule, one per level
+  GraphCache gcv;  // vector descriptors
   TileTable tiles;
 };
 
@@ -507,6 +508,80 @@ int run_single_loop(sgr_ctx* ctx, GraphCache& gc, const sgr_cloud* tmpl, const s
   return run_graph(ctx, gc, kb, loop, st);
 }
 
+// ------------------------------------------------- vector descriptors
+int check_vec(const sgr_params* p, int D) {
+  if (D < 1 || D > 30) return fail(SGR_EINVAL, "vector descriptors need 1 <= D <= 30");
+  if (p->p != 1.0) return fail(SGR_EINVAL, "the vector-descriptor force is implemented for p = 1");
+  if (p->g_mode != 0) return fail(SGR_EINVAL, "the vector-descriptor force uses g = s (g_mode 0)");
+  if (is_mixed(p)) return fail(SGR_EINVAL, "the vector-descriptor force has no mixed-precision form");
+  return SGR_OK;
+}
+
+// Device buffers of the vector-descriptor force: set-up constants,
+// augmented rows, reference coordinates, wrench slots, per-chunk forces.
+struct VecWs {
+  Derived* dv;
+  double* vd;
+  float* At;
+  float* Bt;
+  float4* ref4;
+  double* wpart;
+  double* fpart;
+  double* mom;
+  int K, n_chunks, slots;
+};
+
+int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, VecWs& w) {
+  w.K = vforce_K(D);
+  w.n_chunks = vforce_chunks(M, N, ctx->n_cu);
+  w.slots = vforce_n_iblk(M) * w.n_chunks;
+  for (int pass = 0; pass < 2; ++pass) {
+    Carve c{pass ? ctx->ws : nullptr};
+    w.dv = c.take<Derived>(1);
+    w.vd = c.take<double>(34);
+    w.At = c.take<float>((size_t)vforce_pad_rows(M) * w.K);
+    w.Bt = c.take<float>((size_t)vforce_pad_refs(N) * w.K);
+    w.ref4 = c.take<float4>((size_t)vforce_pad_refs(N));
+    w.wpart = c.take<double>((size_t)w.slots * WR_STRIDE);
+    w.fpart = with_f ? c.take<double>((size_t)w.n_chunks * M * 3) : nullptr;
+    w.mom = with_mom ? c.take<double>(20) : nullptr;
+    if (!pass)
+      if (int e = ensure_ws(ctx, c.off)) return e;
+  }
+  return SGR_OK;
+}
+
+int setup_vec(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r, int D,
+              const double* mom_t, const double* mom_r, const sgr_params* prm, VecWs& w, hipStream_t st) {
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  HIPCHK(launch_prepare(nullptr, ref->m, N, nullptr, tmpl->m, M, mom_t, mom_r, prep_of(prm), w.dv, st));
+  HIPCHK(launch_vprep(a_r, N, D, prm->sigma, w.dv, w.vd, st));
+  HIPCHK(launch_vpack(ref->x, ref->y, ref->z, a_r, ref->m, N, a_t, M, D, w.dv, w.vd, w.Bt, w.ref4, w.At, st));
+  return SGR_OK;
+}
+
+VForceArgs vargs(const sgr_cloud* tmpl, const sgr_cloud* ref, const VecWs& w, const double* pose, int t) {
+  VForceArgs A;
+  A.At = w.At;
+  A.Bt = w.Bt;
+  A.ref4 = w.ref4;
+  A.y0x = tmpl->x;
+  A.y0y = tmpl->y;
+  A.y0z = tmpl->z;
+  A.mY = tmpl->m;
+  A.pose = pose;
+  A.dv = w.dv;
+  A.M = (int)tmpl->n;
+  A.N = (int)ref->n;
+  A.K = w.K;
+  A.n_chunks = w.n_chunks;
+  A.t = t;
+  A.G = 0.0;
+  A.wpart = w.wpart;
+  A.fpart = w.fpart;
+  return A;
+}
+
 // ------------------------------------------------- unrolled differentiation
 // Host copy of G_t (eq. 12), as the force kernel evaluates it.
 double G_host(const sgr_params* prm, int t) {
@@ -625,7 +700,7 @@ int sgr_destroy(sgr_ctx* ctx) {
   if (!ctx) return SGR_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
-  std::vector<GraphCache*> caches = {&ctx->gc, &ctx->gcb};
+  std::vector<GraphCache*> caches = {&ctx->gc, &ctx->gcb, &ctx->gcv};
   for (GraphCache& g : ctx->gcp) caches.push_back(&g);
   for (GraphCache* g : caches) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
@@ -820,6 +895,85 @@ int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* r
       return fail(SGR_ENUMERIC, "numeric failure in the update at level " + std::to_string(l) + " (status " +
                                     std::to_string(status[l]) + ")");
   }
+  return SGR_OK;
+}
+
+int sgr_descriptors_hn(sgr_ctx* ctx, const sgr_cloud* c, int k, int D, float* h_out, sgr_stream_t stream) {
+  if (!ctx || !h_out) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(c, "cloud")) return e;
+  if (k < 1 || k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
+  if (c->n < k) return fail(SGR_EINVAL, "cloud has fewer points than k");
+  if (D < 2 || D > 30) return fail(SGR_EINVAL, "D must be in [2, 30]");
+  HIPCHK(hipSetDevice(ctx->device));
+  if (int e = ensure_ws(ctx, normal_hist_workspace((int)c->n, k))) return e;
+  HIPCHK(launch_normal_hist(c->x, c->y, c->z, (int)c->n, k, D, h_out, ctx->ws, (hipStream_t)stream));
+  return SGR_OK;
+}
+
+int sgr_step_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r, int D,
+                 const double* mom_t, const double* mom_r, const sgr_params* prm, int t, const sgr_pose* in,
+                 sgr_pose* out, double* wrench_out, float* f_out, sgr_stream_t stream) {
+  if (!ctx) return fail(SGR_EINVAL, "NULL ctx");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (int e = check_vec(prm, D)) return e;
+  if (!a_t || !a_r || !mom_t || !mom_r || !in || !out) return fail(SGR_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int M = (int)tmpl->n;
+  VecWs w;
+  if (int e = carve_vec(ctx, M, (int)ref->n, D, f_out != nullptr, false, w)) return e;
+  if (int e = setup_vec(tmpl, a_t, ref, a_r, D, mom_t, mom_r, prm, w, st)) return e;
+  HIPCHK(launch_vforce(vargs(tmpl, ref, w, (const double*)in, t), wrench_out != nullptr, f_out != nullptr, st));
+  if (f_out) HIPCHK(launch_reduce_f(w.fpart, w.n_chunks, M, nullptr, f_out, st));
+  HIPCHK(launch_update(w.wpart, w.slots, (const double*)in, (double*)out, w.dv, t, 0.0, 1, wrench_out, nullptr, st));
+  return SGR_OK;
+}
+
+int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                     int D, const sgr_params* prm, sgr_pose* inout, double* stats, sgr_stream_t stream) {
+  if (!ctx || !inout || !a_t || !a_r) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(tmpl, "template")) return e;
+  if (int e = check_cloud(ref, "reference")) return e;
+  if (int e = check_params(prm)) return e;
+  if (int e = check_vec(prm, D)) return e;
+  if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const int M = (int)tmpl->n, N = (int)ref->n;
+  VecWs w;
+  if (int e = carve_vec(ctx, M, N, D, false, true, w)) return e;
+  HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, w.mom + 10, st));
+  HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, w.mom, st));
+  if (int e = setup_vec(tmpl, a_t, ref, a_r, D, w.mom, w.mom + 10, prm, w, st)) return e;
+  auto loop = [&](hipStream_t s) -> int {
+    for (int t = 0; t < prm->E; ++t) {
+      const bool wu = stats != nullptr || t == prm->E - 1;
+      HIPCHK(launch_vforce(vargs(tmpl, ref, w, (const double*)inout, t), wu, false, s));
+      HIPCHK(launch_update(w.wpart, w.slots, (const double*)inout, (double*)inout, w.dv, t, 0.0, 1, nullptr,
+                           stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
+    }
+    return SGR_OK;
+  };
+  if ((prm->flags & FLAG_NO_GRAPH) || prm->E < 2) {
+    if (int e = loop(st)) return e;
+  } else {
+    std::vector<uint8_t> key;
+    const void* ptrs[12] = {tmpl->x, tmpl->y, tmpl->z, tmpl->m, ref->x, ref->y, ref->z, ref->m, inout, stats, a_t, a_r};
+    key_add(key, ptrs, 12);
+    const int64_t dims[3] = {M, N, D};
+    key_add(key, dims, 3);
+    key_add(key, prm, 1);
+    const void* wsp = ctx->ws;
+    key_add(key, &wsp, 1);
+    if (int e = run_graph(ctx, ctx->gcv, key, loop, st)) return e;
+  }
+  int32_t status = 0;
+  HIPCHK(hipMemcpyAsync(&status, &w.dv->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (status & ST_DEGENERATE) return fail(SGR_EDEGENERATE, "degenerate input: zero variance or zero descriptor spread");
+  if (status) return fail(SGR_ENUMERIC, "numeric failure in the update (status " + std::to_string(status) + ")");
   return SGR_OK;
 }
 

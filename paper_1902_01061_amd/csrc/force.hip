@@ -41,9 +41,12 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
                                     const PrepParams& P, Derived* __restrict__ out, double* lds, double* red_max,
                                     double* abar_p) {
   double& abar_s = *abar_p;
+  // aX == nullptr (and aY == nullptr): no scalar curvature (a caller that
+  // weights pairs by other descriptors, or by the masses alone); the
+  // curvature statistics are then 0 and sigma comes from the caller.
   double s[3] = {0, 0, 0};
   for (int64_t j = threadIdx.x; j < N; j += 1024) {
-    s[0] += (double)aX[j];
+    s[0] += aX ? (double)aX[j] : 0.0;
     s[1] += wX ? (double)wX[j] : 1.0;
   }
   for (int64_t i = threadIdx.x; i < M; i += 1024) s[2] += mY ? (double)mY[i] : 1.0;
@@ -52,7 +55,7 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   __syncthreads();
   const double abar = abar_s;
   double v[1] = {0};
-  for (int64_t j = threadIdx.x; j < N; j += 1024) {
+  for (int64_t j = threadIdx.x; j < N && aX; j += 1024) {
     const double d = (double)aX[j] - abar;
     v[0] += d * d;
   }
@@ -62,14 +65,15 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   // and the range of the reference curvatures
   double mx[4] = {0.0, -INFINITY, -INFINITY, -INFINITY};
   for (int64_t j = threadIdx.x; j < N; j += 1024) {
-    mx[0] = fmax(mx[0], fabs((double)aX[j] - abar));
+    const double a = aX ? (double)aX[j] : 0.0;
+    mx[0] = fmax(mx[0], fabs(a - abar));
     double l = wX ? log2((double)wX[j]) : 0.0;
-    if (P.g_mode == 1) l += log2((double)aX[j] / abar);
+    if (P.g_mode == 1) l += log2(a / abar);
     mx[1] = fmax(mx[1], l);
-    mx[2] = fmax(mx[2], (double)aX[j]);
-    mx[3] = fmax(mx[3], -(double)aX[j]);
+    mx[2] = fmax(mx[2], a);
+    mx[3] = fmax(mx[3], -a);
   }
-  for (int64_t i = threadIdx.x; i < M; i += 1024) mx[0] = fmax(mx[0], fabs((double)aY[i] - abar));
+  for (int64_t i = threadIdx.x; i < M && aY; i += 1024) mx[0] = fmax(mx[0], fabs((double)aY[i] - abar));
   for (int c = 0; c < 4; ++c) {
     double m = mx[c];
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
@@ -97,7 +101,7 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   D.Mtot = s[2];
   D.Mcount = (double)M;
   // sqrt(log2 e) / sigma; 0 for g = 1 (no shape term: every b is 0 and s = 1)
-  D.bscale = P.g_mode == 2 ? 0.0 : sqrt(1.4426950408889634) / D.sigma;
+  D.bscale = (P.g_mode == 2 || !aX) ? 0.0 : sqrt(1.4426950408889634) / D.sigma;
   D.coefL = exp((1.0 - P.p) * log(D.L));
   D.hp = 0.5 * (P.p - 1.0);
   D.eps2 = P.eps * P.eps;
@@ -116,7 +120,7 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   for (int e = 0; e < 9; ++e) D.Vw[e] = (e % 4 == 0) ? 1.0 : 0.0;
   D.pad2 = 0;
   D.cold_svd = P.cold_svd;
-  if (!(D.lamX > 0) || !(D.lamY0 > 0) || (P.g_mode != 2 && !(D.sigma > 0)) || !(D.Z > 0) || !(D.Mtot > 0) ||
+  if (!(D.lamX > 0) || !(D.lamY0 > 0) || (P.g_mode != 2 && aX && !(D.sigma > 0)) || !(D.Z > 0) || !(D.Mtot > 0) ||
       (P.g_mode == 1 && !(abar > 0)))
     st |= ST_DEGENERATE;
   D.status = st;

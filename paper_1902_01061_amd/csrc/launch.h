@@ -162,6 +162,38 @@ hipError_t launch_change(const float* yx, const float* yy, const float* yz, cons
 hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, hipStream_t st);
 hipError_t launch_moments(const float* x, const float* y, const float* z, int64_t n, double* out, hipStream_t st);
+// Force with vector descriptors (p = 1, g = s) on the matrix cores.
+struct VForceArgs {
+  const float* At;      // template augmented rows [Mpad][K]
+  const float* Bt;      // reference augmented rows [Npad][K]
+  const float4* ref4;   // reference x, y, z (centred at xbar), |x|^2 [Npad]
+  const float* y0x;
+  const float* y0y;
+  const float* y0z;
+  const float* mY;      // template masses or nullptr
+  const double* pose;
+  const Derived* dv;
+  int M, N, K, n_chunks, t;
+  double G;             // > 0 overrides eq. 12
+  double* wpart;        // [n_iblk * n_chunks][WR_STRIDE]
+  double* fpart;        // [n_chunks][M][3] (WF only)
+};
+int vforce_K(int D);
+int vforce_pad_rows(int M);
+int vforce_pad_refs(int N);
+int vforce_n_iblk(int M);
+int vforce_chunks(int M, int N, int n_cu);
+// vd: [34] doubles: reference mean (32), sigma, kappa = log2(e) / sigma^2
+hipError_t launch_vprep(const float* aX, int64_t N, int D, double sigma, Derived* dv, double* vd, hipStream_t st);
+hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const float* aX, const float* wX, int N,
+                        const float* aY, int M, int D, const Derived* dv, const double* vd, float* Bt, float4* ref4,
+                        float* At, hipStream_t st);
+hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st);
+// Soft histogram of normals: h_out[n][D] from the k nearest neighbours.
+size_t normal_hist_workspace(int n, int k);
+hipError_t launch_normal_hist(const float* x, const float* y, const float* z, int n, int k, int D, float* h_out,
+                              void* ws, hipStream_t st);
+
 // Curvature of the radius neighbourhood of every point: members have float32
 // key <= r2, where r2 = (float)(scale2 * mom[9]) when mom is given (mom[9] =
 // largest covariance eigenvalue, as launch_moments writes it), else r2_in.

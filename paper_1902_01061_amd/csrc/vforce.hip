@@ -1,0 +1,353 @@
+// Force with vector shape descriptors: eq. (3) with |a_i - a_j|^2 summed over
+// D dimensions, p = 1 (h = 1), g = s, as a dense contraction on the matrix
+// cores.
+//
+// With centred descriptors c = a - abar (abar the reference mean) and
+// kappa = log2(e) / sigma^2, the exponent of a pair,
+//   t_ij = lw_j - kappa |c_i - c_j|^2,
+// is one dot product of augmented rows
+//   At_i = [2 kappa c_i, -kappa |c_i|^2, 1, 0...],
+//   Bt_j = [c_j, 1, lw_j - kappa |c_j|^2, 0...],
+// of length K = 4 ceil((D + 2) / 4), so c_ij = exp2(At_i . Bt_j) for a 16 x 16
+// block of pairs comes from K/4 FP32 16x16x4 matrix instructions (products
+// of FP32 inputs, FP32 accumulation) and 16 exp2.  The p = 1 moment form then
+// needs, per template point, sum_j c, sum_j c x_j (and sum_j c |x_j|^2 for
+// the energy) over the reference, accumulated in FP32 by the vector ALU.
+//
+// Work decomposition: a block of 256 threads (4 waves) owns 256 template
+// points; wave w holds 4 row tiles of 16 points, their At rows resident in
+// registers for the whole chunk.  Reference chunks of at most 2048 points
+// (multiples of 64) stream through LDS 64 points at a time; each 16-column
+// tile gives every lane 4 pairs per row tile (rows 4 (lane / 16) + v, column
+// lane % 16).  A lane therefore sums at most 128 terms per quantity in FP32;
+// the 16 lanes of a row are then added by shuffles and everything after that
+// is FP64, as in the scalar kernel: per-point forces, the block's wrench
+// partial in wpart[slot] (same layout, consumed by the same update kernel).
+#include <algorithm>
+
+#include "common.h"
+#include "launch.h"
+
+namespace sgr {
+
+namespace {
+
+constexpr int VF_BT = 256;   // threads
+constexpr int VF_TI = 4;     // 16-row tiles per wave
+constexpr int VF_ROWS = 64 * VF_TI;  // template points per block
+constexpr int VF_TJ = 64;    // reference points per LDS stage
+constexpr double LOG2E = 1.4426950408889634;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// LDS row stride of the staged Bt: K words when K/4 is odd, else K + 4, so
+// that the 64 lanes of one read (16 columns x 4 k) hit 64 distinct banks.
+__host__ __device__ constexpr int bt_stride(int K) { return ((K / 4) & 1) ? K : K + 4; }
+
+// abar, sigma and kappa of the vector descriptors; writes sigma into the
+// Derived of the registration (its other fields come from the scalar
+// set-up, called without curvatures).
+__global__ __launch_bounds__(1024) void vprep_kernel(const float* __restrict__ aX, int64_t N, int D, double sigma_in,
+                                                     Derived* __restrict__ dv, double* __restrict__ vd) {
+  __shared__ double lds[16 * 32];
+  __shared__ double mean[32];
+  double s[32];
+  for (int c = 0; c < 32; ++c) s[c] = 0.0;
+  for (int64_t j = threadIdx.x; j < N; j += 1024) {
+#pragma unroll
+    for (int c = 0; c < 32; ++c)
+      if (c < D) s[c] += (double)aX[j * D + c];
+  }
+  block_sum<32, 1024>(s, lds);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 32; ++c) mean[c] = c < D ? s[c] / (double)N : 0.0;
+  __syncthreads();
+  double v[1] = {0.0};
+  for (int64_t j = threadIdx.x; j < N; j += 1024)
+    for (int c = 0; c < D; ++c) {
+      const double d = (double)aX[j * D + c] - mean[c];
+      v[0] += d * d;
+    }
+  block_sum<1, 1024>(v, lds);
+  if (threadIdx.x != 0) return;
+  const double sigma = sigma_in > 0 ? sigma_in : sqrt(v[0] / (double)N);
+  for (int c = 0; c < 32; ++c) vd[c] = mean[c];
+  vd[32] = sigma;
+  vd[33] = LOG2E / (sigma * sigma);
+  dv->sigma = sigma;
+  if (!(sigma > 0) || !isfinite(vd[33])) dv->status |= ST_DEGENERATE;
+}
+
+// Augmented rows, FP64 arithmetic rounded once to FP32.  Rows j >= N of the
+// reference are zero-weight padding (exponent -1e30, exp2 gives 0); rows
+// i >= M of the template are harmless padding (their sums are dropped).
+__global__ __launch_bounds__(256) void vpack_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                    const float* __restrict__ Zc, const float* __restrict__ aX,
+                                                    const float* __restrict__ wX, int N, int Npad,
+                                                    const float* __restrict__ aY, int M, int Mpad, int D, int K,
+                                                    const Derived* __restrict__ dv, const double* __restrict__ vd,
+                                                    float* __restrict__ Bt, float4* __restrict__ ref4,
+                                                    float* __restrict__ At) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const double kap = vd[33];
+  if (r < Npad) {
+    float* b = Bt + (int64_t)r * K;
+    if (r < N) {
+      double n2 = 0.0;
+      for (int c = 0; c < D; ++c) {
+        const double e = (double)aX[(int64_t)r * D + c] - vd[c];
+        b[c] = (float)e;
+        n2 += e * e;
+      }
+      const double lw = wX ? log2((double)wX[r]) : 0.0;
+      b[D] = 1.f;
+      b[D + 1] = (float)fmax(lw - kap * n2, -1e30);
+      for (int c = D + 2; c < K; ++c) b[c] = 0.f;
+      const Derived& Dd = *dv;
+      const float x = (float)((double)X[r] - Dd.xbar[0]), y = (float)((double)Y[r] - Dd.xbar[1]),
+                  z = (float)((double)Zc[r] - Dd.xbar[2]);
+      ref4[r] = make_float4(x, y, z, (float)((double)x * x + (double)y * y + (double)z * z));
+    } else {
+      for (int c = 0; c < K; ++c) b[c] = 0.f;
+      b[D] = 1.f;
+      b[D + 1] = -1e30f;
+      ref4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  if (r < Mpad) {
+    float* a = At + (int64_t)r * K;
+    for (int c = 0; c < K; ++c) a[c] = 0.f;
+    if (r < M) {
+      double n2 = 0.0;
+      for (int c = 0; c < D; ++c) {
+        const double e = (double)aY[(int64_t)r * D + c] - vd[c];
+        a[c] = (float)(2.0 * kap * e);
+        n2 += e * e;
+      }
+      a[D] = (float)(-kap * n2);
+    }
+    a[D + 1] = 1.f;
+  }
+}
+
+__device__ inline double G_of(const Derived& D, int t) {
+  return 0.1 * D.G1 + 0.9 * D.G1 / (1.0 + exp(-(((double)t - 1.0) - 0.5 * D.E)));
+}
+
+template <int VK, bool WU, bool WF>
+__global__ __launch_bounds__(VF_BT) void vforce_kernel(VForceArgs A) {
+  constexpr int K = 4 * VK;
+  constexpr int KS = bt_stride(K);
+  constexpr int NQ = WU ? 5 : 4;
+  constexpr int LDS_B = VF_TJ * KS > NQ * VF_ROWS ? VF_TJ * KS : NQ * VF_ROWS;  // tile, then the row sums
+  __shared__ float s_B[LDS_B];
+  __shared__ float4 s_X[VF_TJ];
+  __shared__ double s_red[(VF_BT / 64) * 13];
+  const int n_iblk = (A.M + VF_ROWS - 1) / VF_ROWS;
+  const int iblk = blockIdx.x % n_iblk, chunk = blockIdx.x / n_iblk;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int row0 = iblk * VF_ROWS + w * 64;
+  // chunk bounds in units of VF_TJ
+  const int n_t = (A.N + VF_TJ - 1) / VF_TJ;
+  const int j0 = (int)((int64_t)chunk * n_t / A.n_chunks) * VF_TJ;
+  const int j1 = (int)((int64_t)(chunk + 1) * n_t / A.n_chunks) * VF_TJ;
+
+  float areg[VF_TI][VK];
+#pragma unroll
+  for (int r = 0; r < VF_TI; ++r)
+#pragma unroll
+    for (int s = 0; s < VK; ++s) areg[r][s] = A.At[(int64_t)(row0 + 16 * r + col) * K + 4 * s + kq];
+  float S[VF_TI][4][NQ];
+#pragma unroll
+  for (int r = 0; r < VF_TI; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) S[r][v][q] = 0.f;
+
+  for (int base = j0; base < j1; base += VF_TJ) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < VF_TJ * VK; e += VF_BT) {
+      const int jj = e / VK, s = e % VK;
+      const float4 b4 = *reinterpret_cast<const float4*>(A.Bt + (int64_t)(base + jj) * K + 4 * s);
+      *reinterpret_cast<float4*>(&s_B[jj * KS + 4 * s]) = b4;
+    }
+    if (threadIdx.x < VF_TJ) s_X[threadIdx.x] = A.ref4[base + threadIdx.x];
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < VF_TJ / 16; ++c) {
+      const int jl = 16 * c + col;
+      float breg[VK];
+#pragma unroll
+      for (int s = 0; s < VK; ++s) breg[s] = s_B[jl * KS + 4 * s + kq];
+      const float4 X = s_X[jl];
+#pragma unroll
+      for (int r = 0; r < VF_TI; ++r) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < VK; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[r][s], breg[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float cc = __builtin_amdgcn_exp2f(acc[v]);
+          S[r][v][0] += cc;
+          S[r][v][1] = __builtin_fmaf(cc, X.x, S[r][v][1]);
+          S[r][v][2] = __builtin_fmaf(cc, X.y, S[r][v][2]);
+          S[r][v][3] = __builtin_fmaf(cc, X.z, S[r][v][3]);
+          if constexpr (WU) S[r][v][4] = __builtin_fmaf(cc, X.w, S[r][v][4]);
+        }
+      }
+    }
+  }
+  // sums over the 16 columns (lanes of equal lane / 16); lane col < 4 then
+  // parks row 4 kq + col of each row tile in LDS, where thread t picks up
+  // row t of the block, so that the FP64 epilogue holds one row's sums
+#pragma unroll
+  for (int r = 0; r < VF_TI; ++r)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        float x = S[r][v][q];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off, 64);
+        S[r][v][q] = x;
+      }
+  __syncthreads();  // every wave is done with s_B: reuse it for the sums
+  float* s_S = s_B;
+  if (col < 4) {
+#pragma unroll
+    for (int r = 0; r < VF_TI; ++r)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        s_S[q * VF_ROWS + w * 64 + 16 * r + 4 * kq + col] =
+            col == 0 ? S[r][0][q] : col == 1 ? S[r][1][q] : col == 2 ? S[r][2][q] : S[r][3][q];
+  }
+  __syncthreads();
+
+  const Derived& D = *A.dv;
+  double sR[9], cv[3];
+  {
+    const double s = A.pose[0];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) sR[e] = s * A.pose[1 + e];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      cv[r] = sR[3 * r] * D.ybar0[0] + sR[3 * r + 1] * D.ybar0[1] + sR[3 * r + 2] * D.ybar0[2] + A.pose[10 + r] -
+              D.xbar[r];
+  }
+  const double G = A.G > 0 ? A.G : G_of(D, A.t);
+  const double coef = -(G / D.Z);
+  const double ucoef = 0.5 * (G / D.Z);
+  double wr[13];
+#pragma unroll
+  for (int e = 0; e < 13; ++e) wr[e] = 0.0;
+  // thread t finishes template point iblk * VF_ROWS + t
+  {
+    const int ip = iblk * VF_ROWS + threadIdx.x;
+    if (ip >= A.M) goto done;
+    double t[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) t[q] = (double)s_S[q * VF_ROWS + threadIdx.x];
+    const double ex = (double)A.y0x[ip] - D.ybar0[0], ey = (double)A.y0y[ip] - D.ybar0[1],
+                 ez = (double)A.y0z[ip] - D.ybar0[2];
+    const float pxf = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);
+    const float pyf = (float)(sR[3] * ex + sR[4] * ey + sR[5] * ez + cv[1]);
+    const float pzf = (float)(sR[6] * ex + sR[7] * ey + sR[8] * ez + cv[2]);
+    const double px = pxf, py = pyf, pz = pzf;
+    const double tx = px * t[0] - t[1], ty = py * t[0] - t[2], tz = pz * t[0] - t[3];
+    const double mi = A.mY ? (double)A.mY[ip] : 1.0;
+    const double fx = coef * tx, fy = coef * ty, fz = coef * tz;
+    const double cx = px - cv[0], cy = py - cv[1], cz = pz - cv[2];
+    wr[WR_F + 0] += mi * fx;
+    wr[WR_F + 1] += mi * fy;
+    wr[WR_F + 2] += mi * fz;
+    wr[WR_K + 0] += fx * cx;
+    wr[WR_K + 1] += fx * cy;
+    wr[WR_K + 2] += fx * cz;
+    wr[WR_K + 3] += fy * cx;
+    wr[WR_K + 4] += fy * cy;
+    wr[WR_K + 5] += fy * cz;
+    wr[WR_K + 6] += fz * cx;
+    wr[WR_K + 7] += fz * cy;
+    wr[WR_K + 8] += fz * cz;
+    if constexpr (WU)
+      wr[WR_U] += ucoef * ((px * px + py * py + pz * pz + D.eps2) * t[0] - 2.0 * (px * t[1] + py * t[2] + pz * t[3]) +
+                           t[4]);
+    if constexpr (WF) {
+      double* fp = A.fpart + ((int64_t)chunk * A.M + ip) * 3;
+      fp[0] = fx;
+      fp[1] = fy;
+      fp[2] = fz;
+    }
+  }
+done:
+  block_sum<13, VF_BT>(wr, s_red);
+  if (threadIdx.x == 0) {
+    double* o = A.wpart + (int64_t)blockIdx.x * WR_STRIDE;
+#pragma unroll
+    for (int e = 0; e < 13; ++e) o[e] = wr[e];
+  }
+}
+
+template <int VK>
+hipError_t launch_vk(const VForceArgs& A, bool wu, bool wf, hipStream_t st) {
+  const int n_iblk = (A.M + VF_ROWS - 1) / VF_ROWS;
+  const dim3 grid((unsigned)(n_iblk * A.n_chunks)), block(VF_BT);
+  if (wu && wf)
+    hipLaunchKernelGGL((vforce_kernel<VK, true, true>), grid, block, 0, st, A);
+  else if (wu)
+    hipLaunchKernelGGL((vforce_kernel<VK, true, false>), grid, block, 0, st, A);
+  else if (wf)
+    hipLaunchKernelGGL((vforce_kernel<VK, false, true>), grid, block, 0, st, A);
+  else
+    hipLaunchKernelGGL((vforce_kernel<VK, false, false>), grid, block, 0, st, A);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int vforce_K(int D) { return 4 * ((D + 2 + 3) / 4); }
+int vforce_pad_rows(int M) { return (M + VF_ROWS - 1) / VF_ROWS * VF_ROWS; }
+int vforce_pad_refs(int N) { return (N + VF_TJ - 1) / VF_TJ * VF_TJ; }
+int vforce_n_iblk(int M) { return (M + VF_ROWS - 1) / VF_ROWS; }
+
+// Chunks: at most 2048 reference points each (so that a lane sums at most 128
+// terms in FP32), and enough blocks for about two per compute unit.
+int vforce_chunks(int M, int N, int n_cu) {
+  const int n_t = (N + VF_TJ - 1) / VF_TJ;
+  const int nib = vforce_n_iblk(M);
+  int nc = std::max((n_t + 31) / 32, (2 * n_cu + nib - 1) / nib);
+  return std::max(1, std::min(nc, n_t));
+}
+
+hipError_t launch_vprep(const float* aX, int64_t N, int D, double sigma, Derived* dv, double* vd, hipStream_t st) {
+  hipLaunchKernelGGL(vprep_kernel, dim3(1), dim3(1024), 0, st, aX, N, D, sigma, dv, vd);
+  return hipGetLastError();
+}
+
+hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const float* aX, const float* wX, int N,
+                        const float* aY, int M, int D, const Derived* dv, const double* vd, float* Bt, float4* ref4,
+                        float* At, hipStream_t st) {
+  const int Npad = vforce_pad_refs(N), Mpad = vforce_pad_rows(M), K = vforce_K(D);
+  const int rows = std::max(Npad, Mpad);
+  hipLaunchKernelGGL(vpack_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, X, Y, Z, aX, wX, N, Npad,
+                     aY, M, Mpad, D, K, dv, vd, Bt, ref4, At);
+  return hipGetLastError();
+}
+
+hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st) {
+  switch (A.K / 4) {
+    case 1: return launch_vk<1>(A, wu, wf, st);
+    case 2: return launch_vk<2>(A, wu, wf, st);
+    case 3: return launch_vk<3>(A, wu, wf, st);
+    case 4: return launch_vk<4>(A, wu, wf, st);
+    case 5: return launch_vk<5>(A, wu, wf, st);
+    case 6: return launch_vk<6>(A, wu, wf, st);
+    case 7: return launch_vk<7>(A, wu, wf, st);
+    case 8: return launch_vk<8>(A, wu, wf, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sgr

@@ -1,0 +1,198 @@
+"""Vector shape descriptors (soft histograms of normals) and the force whose
+similarity exponents are one dense contraction on the matrix cores, against
+the oracle.
+
+Tolerances.  Histograms: the GPU's Jacobi eigenvectors and the oracle's
+LAPACK ones agree to about 1e-15 divided by the gap between the two smallest
+eigenvalues, so points whose normal is determined (gap above 1e-3 of the
+trace) are compared to 2e-6 absolute (float32 output of values <= 1); the
+others have no unique normal and are excluded.  Forces: the exponent of a
+pair is an FP32 dot product of K = 4 ceil((D + 2) / 4) terms of magnitude up
+to about 4 kappa |a - abar|^2 (below 30 here), so it carries an absolute
+error of order K 2^-24 30, i.e. 4e-5 relative in each pair weight at worst;
+sums run in FP32 over at most 128 terms per lane before FP64.  The gate is
+the force tolerance of the scalar path, 1e-4 relative per iteration (the
+measured errors are printed)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref as O
+from synth import config1, config2, random_pair, rot_axis_angle
+from synth.clouds import ellipsoid_patch
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_01061_amd as sg
+    return sg
+
+
+@pytest.fixture(scope="module")
+def ctx(sg):
+    c = sg.Context(0)
+    yield c
+    c.close()
+
+
+def _mom(P):
+    c, S, lam = O.moments(P)
+    return np.array([c[0], c[1], c[2], S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2], lam])
+
+
+def _dt(x, dtype=torch.float32):
+    return torch.as_tensor(np.asarray(x)).to(device="cuda", dtype=dtype).contiguous()
+
+
+@pytest.mark.parametrize("n,k,D", [(3001, 16, 16), (2000, 8, 5), (700, 24, 30)])
+def test_normal_histograms_match_oracle(sg, ctx, n, k, D):
+    P = ellipsoid_patch(n, 13).astype(np.float32)
+    h = ctx.descriptors_hn(sg.Cloud(P), k, D).cpu().numpy()
+    h_o, lam = O.normal_histograms(P, k, D)
+    ok = (lam[:, 1] - lam[:, 0]) > 1e-3 * lam.sum(axis=1)
+    assert ok.mean() > 0.9
+    err = np.abs(h[ok] - h_o[ok]).max()
+    print(f"normal histograms n={n} k={k} D={D}: max abs error {err:.1e} on {ok.mean():.1%} of the points")
+    assert err <= 2e-6
+    np.testing.assert_allclose(h.sum(axis=1), 1.0, rtol=1e-5)
+
+
+def _vec_case(D, seed, kind):
+    pr = random_pair(1300, 2900, seed=seed)         # several tiles and chunks, ragged tails
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        aX = rng.random((pr.N, D)).astype(np.float32)
+        aY = rng.random((pr.M, D)).astype(np.float32)
+    else:                                            # clustered, with far outliers
+        cen = rng.random((6, D))
+        aX = (cen[rng.integers(0, 6, pr.N)] + 0.05 * rng.normal(size=(pr.N, D))).astype(np.float32)
+        aY = (cen[rng.integers(0, 6, pr.M)] + 0.05 * rng.normal(size=(pr.M, D))).astype(np.float32)
+        aY[:20] += 2.0
+    return pr, aX, aY
+
+
+def _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX=None, mY=None):
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64), wX=wX, mY=mY)
+    Y = pose.apply(pr.tmpl)
+    so = O.step(Y, S, t)
+    ora_pose = O.compose(pose, so, Y.mean(axis=0))
+    tm = sg.Cloud(pr.tmpl, masses=mY)
+    rf = sg.Cloud(pr.ref, masses=wX)
+    gp = sg.Params(p=prm.p, g_mode=prm.g_mode, k=prm.k, sigma=prm.sigma, eps=prm.eps, E=prm.E)
+    pout, wr, f = ctx.step_vec(tm, _dt(aY), rf, _dt(aX), _dt(_mom(pr.tmpl), torch.float64),
+                               _dt(_mom(pr.ref), torch.float64), gp, t, sg.pose_from_srt(pose.s, pose.R, pose.t),
+                               want_wrench=True, want_f=True)
+    return so, ora_pose, pout.cpu().numpy(), wr.cpu().numpy(), f.cpu().numpy().astype(np.float64), Y
+
+
+def _errors(so, wr, f, Y, mY=None):
+    m = np.ones(len(f)) if mY is None else np.asarray(mY, np.float64)
+    e_f = np.linalg.norm(f - so.f) / np.linalg.norm(so.f)
+    e_F = np.linalg.norm(wr[0:3] - so.F) / np.sum(m * np.linalg.norm(so.f, axis=1))
+    Yc = Y - Y.mean(axis=0)
+    e_K = np.linalg.norm(wr[3:12].reshape(3, 3) - so.K) / np.sum(np.linalg.norm(so.f, axis=1) *
+                                                                 np.linalg.norm(Yc, axis=1))
+    e_U = abs(wr[12] - so.U) / abs(so.U)
+    return e_f, e_F, e_K, e_U
+
+
+@pytest.mark.parametrize("D,kind,masses,eps", [(16, "uniform", False, 0.0), (30, "clustered", True, 0.02),
+                                                (5, "uniform", True, 0.0), (1, "clustered", False, 0.0),
+                                                (14, "clustered", False, 0.0)])
+def test_step_vec_matches_oracle(sg, ctx, D, kind, masses, eps):
+    pr, aX, aY = _vec_case(D, 40 + D, kind)
+    rng = np.random.default_rng(D)
+    wX = rng.uniform(0.5, 2.0, pr.N).astype(np.float32).astype(np.float64) if masses else None
+    mY = rng.uniform(0.5, 2.0, pr.M).astype(np.float32).astype(np.float64) if masses else None
+    prm = O.Params(p=1.0, k=16, eps=eps, E=40)
+    pose = O.Pose(1.1, rot_axis_angle([1, 2, 3], 20.0), np.array([0.1, -0.2, 0.05]))
+    for t in (0, 39):
+        so, ora_pose, pout, wr, f, Y = _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX, mY)
+        e = _errors(so, wr, f, Y, mY)
+        print(f"vector step D={D} {kind} t={t}: e_f={e[0]:.1e} e_F={e[1]:.1e} e_K={e[2]:.1e} e_U={e[3]:.1e}")
+        assert max(e) <= F_TOL, e
+        gp = O.Pose(pout[0], pout[1:10].reshape(3, 3), pout[10:13])
+        d = gp.apply(pr.tmpl) - ora_pose.apply(pr.tmpl)
+        assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * O.diameter(pr.ref)
+
+
+def test_step_vec_with_one_dimension_is_the_scalar_step(sg, ctx):
+    """D = 1 through the matrix cores and the scalar kernel agree (both
+    against the same oracle step) on the same curvatures."""
+    pr = random_pair(2100, 2600, seed=9)
+    rng = np.random.default_rng(9)
+    aX = rng.uniform(0.0, 0.3, pr.N).astype(np.float32)
+    aY = rng.uniform(0.0, 0.3, pr.M).astype(np.float32)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    gp = sg.Params(p=1.0, k=16, E=40)
+    pin = sg.pose_from_srt(0.9, rot_axis_angle([0, 1, 1], 15.0), np.array([0.05, 0.1, -0.1]))
+    mt, mr = _dt(_mom(pr.tmpl), torch.float64), _dt(_mom(pr.ref), torch.float64)
+    _, w1, f1 = ctx.step(tm, _dt(aY), rf, _dt(aX), mt, mr, gp, 7, pin, want_wrench=True, want_f=True)
+    _, w2, f2 = ctx.step_vec(tm, _dt(aY[:, None]), rf, _dt(aX[:, None]), mt, mr, gp, 7, pin, want_wrench=True,
+                             want_f=True)
+    f1, f2 = f1.cpu().numpy().astype(np.float64), f2.cpu().numpy().astype(np.float64)
+    e = np.linalg.norm(f2 - f1) / np.linalg.norm(f1)
+    print(f"D = 1 vector path vs scalar path: force difference {e:.1e}")
+    assert e <= 2e-5
+    w1, w2 = w1.cpu().numpy(), w2.cpu().numpy()
+    assert np.linalg.norm(w2[:12] - w1[:12]) <= 2e-5 * np.linalg.norm(w1[:12])
+
+
+def test_register_vec_with_normal_histograms_matches_oracle(sg, ctx):
+    pr = config1()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    hX = ctx.descriptors_hn(rf, 16, 16)
+    hY = ctx.descriptors_hn(tm, 16, 16)
+    prm = O.Params(p=1.0, k=16, E=60)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=hX.cpu().numpy().astype(np.float64),
+                     aY=hY.cpu().numpy().astype(np.float64))
+    po, _, _ = O.register(pr.tmpl, S)
+    pose, _ = ctx.register_vec(tm, hY, rf, hX, sg.Params(p=1.0, k=16, E=60))
+    s, R, t = sg.pose_to_srt(pose)
+    d = O.Pose(s, R, t).apply(pr.tmpl) - po.apply(pr.tmpl)
+    err = np.sqrt(np.mean(np.sum(d * d, axis=1))) / O.diameter(pr.ref)
+    gt = O.pose_rmse(po, pr.tmpl, pr.gt_s, pr.gt_R, pr.gt_t) / O.diameter(pr.ref)
+    print(f"vector registration parity RMSE / diameter = {err:.2e} (oracle pose error {gt:.3f} D)")
+    assert err <= 1e-4
+
+
+def test_step_vec_full_size_sampled(sg, ctx):
+    """The scan-sized pair (32 400 x 36 000) with 16-bin normal histograms:
+    forces on sampled rows against the oracle."""
+    pr = config2()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    hX = ctx.descriptors_hn(rf, 24, 16)
+    hY = ctx.descriptors_hn(tm, 24, 16)
+    gp = sg.Params(p=1.0, k=24, E=300)
+    mt, mr = _dt(_mom(pr.tmpl), torch.float64), _dt(_mom(pr.ref), torch.float64)
+    _, wr, f = ctx.step_vec(tm, hY, rf, hX, mt, mr, gp, 0, sg.pose_identity(), want_wrench=True, want_f=True)
+    prm = O.Params(p=1.0, k=24, E=300)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=hX.cpu().numpy().astype(np.float64),
+                     aY=hY.cpu().numpy().astype(np.float64))
+    rows = np.random.default_rng(1).choice(pr.M, 150, replace=False)
+    f_o, _ = O.forces(pr.tmpl.astype(np.float64), S, O.G_schedule(0, 300), rows=rows, block=50)
+    f = f.cpu().numpy().astype(np.float64)[rows]
+    e = np.linalg.norm(f - f_o) / np.linalg.norm(f_o)
+    print(f"full-size vector step: sampled force error {e:.1e}")
+    assert e <= F_TOL
+
+
+def test_vec_rejects_bad_arguments(sg, ctx):
+    pr = random_pair(100, 120, seed=2)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    a_t, a_r = _dt(np.random.rand(100, 8)), _dt(np.random.rand(120, 8))
+    for prm in (sg.Params(p=2.0, E=3), sg.Params(p=1.0, g_mode=1, E=3), sg.Params(p=1.0, E=3, flags=2)):
+        with pytest.raises(sg.SgrError):
+            ctx.register_vec(tm, a_t, rf, a_r, prm)
+    with pytest.raises(sg.SgrError):
+        ctx.register_vec(tm, _dt(np.random.rand(100, 31)), rf, _dt(np.random.rand(120, 31)), sg.Params(p=1.0, E=3))
+    with pytest.raises(sg.SgrError):
+        ctx.descriptors_hn(tm, 16, 1)
+    with pytest.raises(sg.SgrError):   # zero descriptor spread
+        ctx.register_vec(tm, _dt(np.ones((100, 8))), rf, _dt(np.ones((120, 8))), sg.Params(p=1.0, E=3))
