@@ -269,6 +269,75 @@ def extra_force_law(sg, ctx, E: int, k: int):
     return out
 
 
+def extra_pyramid(sg, ctx, E: int, k: int):
+    """Radius-neighbourhood curvature (Sec. IV, radius sqrt(lambda_max)) on
+    the workload reference, timed alone, and the pyramidal schedule (radius
+    and sigma halved twice over the E iterations) against the kNN
+    registration on the workload pair."""
+    import numpy as np
+    import torch
+
+    from synth import config2
+
+    pr = config2()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    _, mom = ctx.descriptors(rf, k)
+    r2 = float(np.float32(mom[9].item()))
+    ctx.descriptors_radius(rf, r2)
+    reps = 5
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a, cnt = ctx.descriptors_radius(rf, r2)
+    e1.record()
+    torch.cuda.synchronize()
+    r_ms = e0.elapsed_time(e1) / reps
+    third = E // 3
+    levels = [sg.Level(1.0, 1.0, third), sg.Level(0.5, 0.5, third), sg.Level(0.25, 0.25, E - 2 * third)]
+    prm = sg.Params(p=1.0, k=k, E=E)
+    out = {"radius_descriptors": {"N": pr.N, "ms": r_ms, "pair_tests_per_s": pr.N * pr.N / (r_ms * 1e-3),
+                                  "members_mean": float(cnt.float().mean().item())},
+           "levels": [[v.radius_scale, v.sigma_scale, v.iters] for v in levels]}
+    for name, fn in (("knn", lambda p: ctx.register(tm, rf, prm, pose=p)),
+                     ("pyramid", lambda p: ctx.register_pyramid(tm, rf, prm, levels, pose=p))):
+        pose = sg.pose_identity()
+        fn(pose)
+        dt, _ = _timed(lambda: (pose.copy_(sg.pose_identity()), fn(pose)))
+        out[name] = {"ms_per_registration": dt * 1e3, "pose_rmse_over_diameter": _pose_err(sg, pose, pr),
+                     "nn_rmse": float(ctx.residual(tm, rf, pose).item())}
+    return out
+
+
+def extra_vector(sg, ctx, E: int, k: int, D: int = 16):
+    """Vector shape descriptors on the workload pair: the soft histograms of
+    normals (D bins) of both clouds, then the registration whose pair
+    exponents are a K = 4 ceil((D + 2) / 4) contraction on the FP32 matrix
+    cores.  Matrix-core rate = 2 K M N E / registration time (a lower
+    bound: the time includes set-up and updates)."""
+    import torch
+
+    from synth import config2
+
+    pr = config2()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    ctx.descriptors_hn(rf, k, D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hX = ctx.descriptors_hn(rf, k, D)
+    hY = ctx.descriptors_hn(tm, k, D)
+    torch.cuda.synchronize()
+    d_ms = (time.perf_counter() - t0) * 1e3
+    prm = sg.Params(p=1.0, k=k, E=E)
+    pose = sg.pose_identity()
+    ctx.register_vec(tm, hY, rf, hX, prm, pose=pose)
+    dt, _ = _timed(lambda: (pose.copy_(sg.pose_identity()), ctx.register_vec(tm, hY, rf, hX, prm, pose=pose)))
+    K = 4 * ((D + 2 + 3) // 4)
+    return {"D": D, "K": K, "M": pr.M, "N": pr.N, "iterations": E, "descriptors_ms_both_clouds": d_ms,
+            "ms_per_registration": dt * 1e3, "pairs_per_s": pr.M * pr.N * E / dt,
+            "matrix_tflops_lower_bound": 2 * K * pr.M * pr.N * E / dt / 1e12,
+            "pose_rmse_over_diameter": _pose_err(sg, pose, pr), "nn_rmse": float(ctx.residual(tm, rf, pose).item())}
+
+
 def extra_scene(sg, ctx, cpu_rows: int):
     """Depth-frame scene (307,200 x 250,000, g = a a s): FP32 and mixed
     registrations, their pose difference per iteration, and the one-step
@@ -500,6 +569,12 @@ def main() -> int:
         out["force_law"] = extra_force_law(sg, ctx, E, k)
         log(f"force law: workload pose error p=1 {out['force_law']['workload']['shape_p1']['pose_rmse_over_diameter']:.2e}"
             f", gravitational {out['force_law']['workload']['gravitational_p-2']['pose_rmse_over_diameter']:.2e}")
+        out["pyramid"] = extra_pyramid(sg, ctx, E, k)
+        log(f"pyramid: radius descriptors {out['pyramid']['radius_descriptors']['ms']:.3f} ms, registration "
+            f"{out['pyramid']['pyramid']['ms_per_registration']:.1f} ms")
+        out["vector"] = extra_vector(sg, ctx, E, k)
+        log(f"vector descriptors: {out['vector']['ms_per_registration']:.1f} ms/registration, "
+            f"{out['vector']['pairs_per_s']:.3g} pairs/s")
         out["scene"] = extra_scene(sg, ctx, cpu_rows=48)
         log(f"scene: fp32 {out['scene']['fp32']['ms_per_registration']:.1f} ms, "
             f"mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms")

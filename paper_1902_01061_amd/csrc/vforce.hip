@@ -33,8 +33,15 @@ namespace sgr {
 namespace {
 
 constexpr int VF_BT = 256;   // threads
-constexpr int VF_TI = 4;     // 16-row tiles per wave
+#ifndef SGR_VF_TI
+#define SGR_VF_TI 4
+#endif
+#ifndef SGR_VF_WAVES
+#define SGR_VF_WAVES 0
+#endif
+constexpr int VF_TI = SGR_VF_TI;  // 16-row tiles per wave
 constexpr int VF_ROWS = 64 * VF_TI;  // template points per block
+static_assert(VF_TI == 1 || VF_TI == 2 || VF_TI == 4, "row tiles per wave");
 constexpr int VF_TJ = 64;    // reference points per LDS stage
 constexpr double LOG2E = 1.4426950408889634;
 
@@ -135,7 +142,11 @@ __device__ inline double G_of(const Derived& D, int t) {
 }
 
 template <int VK, bool WU, bool WF>
-__global__ __launch_bounds__(VF_BT) void vforce_kernel(VForceArgs A) {
+__global__ __launch_bounds__(VF_BT)
+#if SGR_VF_WAVES > 0
+__attribute__((amdgpu_waves_per_eu(SGR_VF_WAVES, SGR_VF_WAVES)))
+#endif
+void vforce_kernel(VForceArgs A) {
   constexpr int K = 4 * VK;
   constexpr int KS = bt_stride(K);
   constexpr int NQ = WU ? 5 : 4;
@@ -147,7 +158,7 @@ __global__ __launch_bounds__(VF_BT) void vforce_kernel(VForceArgs A) {
   const int iblk = blockIdx.x % n_iblk, chunk = blockIdx.x / n_iblk;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
-  const int row0 = iblk * VF_ROWS + w * 64;
+  const int row0 = iblk * VF_ROWS + w * 16 * VF_TI;
   // chunk bounds in units of VF_TJ
   const int n_t = (A.N + VF_TJ - 1) / VF_TJ;
   const int j0 = (int)((int64_t)chunk * n_t / A.n_chunks) * VF_TJ;
@@ -220,7 +231,7 @@ __global__ __launch_bounds__(VF_BT) void vforce_kernel(VForceArgs A) {
     for (int r = 0; r < VF_TI; ++r)
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        s_S[q * VF_ROWS + w * 64 + 16 * r + 4 * kq + col] =
+        s_S[q * VF_ROWS + w * 16 * VF_TI + 16 * r + 4 * kq + col] =
             col == 0 ? S[r][0][q] : col == 1 ? S[r][1][q] : col == 2 ? S[r][2][q] : S[r][3][q];
   }
   __syncthreads();
@@ -242,10 +253,10 @@ __global__ __launch_bounds__(VF_BT) void vforce_kernel(VForceArgs A) {
   double wr[13];
 #pragma unroll
   for (int e = 0; e < 13; ++e) wr[e] = 0.0;
-  // thread t finishes template point iblk * VF_ROWS + t
+  // thread t < VF_ROWS finishes template point iblk * VF_ROWS + t
   {
     const int ip = iblk * VF_ROWS + threadIdx.x;
-    if (ip >= A.M) goto done;
+    if (threadIdx.x >= VF_ROWS || ip >= A.M) goto done;
     double t[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) t[q] = (double)s_S[q * VF_ROWS + threadIdx.x];
