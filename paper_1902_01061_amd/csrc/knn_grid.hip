@@ -168,12 +168,75 @@ __global__ __launch_bounds__(256) void grid_scatter_kernel(const float* __restri
 
 __device__ inline bool key_less(float d, int i, float bd, int bi) { return d < bd || (d == bd && i < bi); }
 
+// Visits spts[p0 .. p1) in order.  A lane searching far from its cell meets
+// thousands of candidates, and with few waves per SIMD one dependent load
+// per candidate would leave it waiting on memory for most of the kernel: the
+// lane therefore issues SPAN_U independent loads, parks the points in its own
+// LDS column (buf[u * GQ_BT], no other lane touches it, no barrier) and then
+// processes them in a rolled loop, which keeps the per-candidate code (the
+// top-k insertion) in one copy.
+constexpr int SPAN_U = 8;
+
+template <class F>
+__device__ inline void span_points(const float4* __restrict__ spts, int p0, int p1, float4* buf, F&& f) {
+  for (int p = p0; p < p1; p += SPAN_U) {
+#pragma unroll
+    for (int u = 0; u < SPAN_U; ++u) buf[u * GQ_BT] = spts[min(p + u, p1 - 1)];
+    const int nu = min(SPAN_U, p1 - p);
+#pragma unroll 1
+    for (int u = 0; u < nu; ++u) f(buf[u * GQ_BT]);
+  }
+}
+
+// The points of shell r around cell c (the cells with max(|dx|, |dy|, |dz|)
+// = r) as contiguous spans of the cell-sorted point array.  The cells of one
+// (z, y) row are adjacent in that array, so a row on the shell's boundary is
+// one span (two index loads, however many cells) and a row inside the shell
+// contributes its two end cells.  Calls f(p0, p1) per span, in the order in
+// which visiting the cells one by one would meet the points; far queries
+// (outliers in empty space) thus touch about 3x fewer index words.
+template <class F>
+__device__ inline void shell_spans(const int* __restrict__ starts, const GridInfo& G, const int c[3], int r, F&& f) {
+  for (int dz = -r; dz <= r; ++dz) {
+    const int cz = c[2] + dz;
+    if (cz < 0 || cz >= G.dims[2]) continue;
+    for (int dy = -r; dy <= r; ++dy) {
+      const int cy = c[1] + dy;
+      if (cy < 0 || cy >= G.dims[1]) continue;
+      const int row = (cz * G.dims[1] + cy) * G.dims[0];
+      // up to two spans per row, handed to the single call site below (one
+      // inlined copy of the caller's per-candidate code)
+      int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+      if (r == 0 || abs(dz) == r || abs(dy) == r) {
+        a0 = starts[row + max(0, c[0] - r)];
+        a1 = starts[row + min(G.dims[0] - 1, c[0] + r) + 1];
+      } else {
+        if (c[0] - r >= 0) {
+          a0 = starts[row + c[0] - r];
+          a1 = starts[row + c[0] - r + 1];
+        }
+        if (c[0] + r < G.dims[0]) {
+          b0 = starts[row + c[0] + r];
+          b1 = starts[row + c[0] + r + 1];
+        }
+      }
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+        const int q0 = h ? b0 : a0, q1 = h ? b1 : a1;
+        if (q0 < q1) f(q0, q1);
+      }
+    }
+  }
+}
+
 // Writes the k neighbour indices of every point (row = original index,
 // sorted by key; -1 where fewer than k finite points exist).
 template <int KC>
 __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
                                                          const GridInfo* __restrict__ gi, int n, int k,
                                                          int32_t* __restrict__ idx_out) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  float4* buf = s_buf + threadIdx.x;
   const int t = blockIdx.x * GQ_BT + threadIdx.x;
   if (t >= n) return;  // no barriers below
   const GridInfo G = *gi;
@@ -182,50 +245,35 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
   const float qv[3] = {q.x, q.y, q.z};
   int c[3];
   for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
-  float bd[KC];
-  int bi[KC];
+  // The running top k as sorted 64-bit keys (float32 key bits << 32 |
+  // index): for keys >= 0 the bit pattern orders like the value, so one
+  // unsigned compare gives the (key, index) order and an insertion step is
+  // one compare and two 64-bit selects.  Slots [0, KC - k) hold the sentinel
+  // 0, which no candidate undercuts, so slot KC - 1 is always the k-th best;
+  // empty slots hold all ones (key NaN, index -1).  Candidates whose key is
+  // not below +inf (non-finite points, overflowing distances) never enter.
+  uint64_t L[KC];
 #pragma unroll
-  for (int s = 0; s < KC; ++s) {
-    bd[s] = (s < KC - k) ? -INFINITY : INFINITY;
-    bi[s] = -1;
-  }
+  for (int s = 0; s < KC; ++s) L[s] = (s < KC - k) ? 0ull : ~0ull;
   const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
   for (int r = 0; r <= rmax; ++r) {
-    for (int dz = -r; dz <= r; ++dz) {
-      const int cz = c[2] + dz;
-      if (cz < 0 || cz >= G.dims[2]) continue;
-      for (int dy = -r; dy <= r; ++dy) {
-        const int cy = c[1] + dy;
-        if (cy < 0 || cy >= G.dims[1]) continue;
-        const bool inner = (abs(dz) < r) && (abs(dy) < r);
-        for (int dx = -r; dx <= r; dx += (inner && r > 0) ? 2 * r : 1) {
-          const int cx = c[0] + dx;
-          if (cx < 0 || cx >= G.dims[0]) continue;
-          const int cell = (cz * G.dims[1] + cy) * G.dims[0] + cx;
-          const int p1 = starts[cell + 1];
-          for (int p = starts[cell]; p < p1; ++p) {
-            const float4 P = spts[p];
-            const int j = __float_as_int(P.w);
-            const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
-            const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
-            if (key_less(d2, j, bd[KC - 1], bi[KC - 1])) {
-              float cd = d2;
-              int ci = j;
+    shell_spans(starts, G, c, r, [&](int p0, int p1) {
+      span_points(spts, p0, p1, buf, [&](const float4& P) {
+        const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
+        const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+        const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
+        if (d2 < INFINITY && key < L[KC - 1]) {
+          uint64_t ck = key;
 #pragma unroll
-              for (int s = 0; s < KC; ++s) {
-                const bool sw = key_less(cd, ci, bd[s], bi[s]);
-                const float td = bd[s];
-                const int ti = bi[s];
-                bd[s] = sw ? cd : td;
-                bi[s] = sw ? ci : ti;
-                cd = sw ? td : cd;
-                ci = sw ? ti : ci;
-              }
-            }
+          for (int s = 0; s < KC; ++s) {
+            const uint64_t t = L[s];
+            const bool sw = ck < t;
+            L[s] = sw ? ck : t;
+            ck = sw ? t : ck;
           }
         }
-      }
-    }
+      });
+    });
     // distance from the query to any cell outside the searched cube
     double lb = INFINITY;
     bool all = true;
@@ -242,9 +290,13 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
     if (all) break;
     // margin: 1e-3 of a cell for the face, 1e-5 relative for the float32 key
     const double lbs = lb - 1e-3 * (double)G.h;
-    if (lbs > 0.0 && (double)bd[KC - 1] * 1.00001 < lbs * lbs) break;
+    if (lbs > 0.0 && (double)__uint_as_float((uint32_t)(L[KC - 1] >> 32)) * 1.00001 < lbs * lbs) break;
   }
-  for (int s = 0; s < k; ++s) idx_out[(int64_t)qi * k + s] = bi[KC - k + s];
+  // static slot indices only (a runtime index would put L in scratch memory)
+  const int64_t o = (int64_t)qi * k;
+#pragma unroll
+  for (int s = 0; s < KC; ++s)
+    if (s >= KC - k) idx_out[o + (s - (KC - k))] = (int32_t)(uint32_t)L[s];
 }
 
 // Curvature from the neighbour lists (FP64 covariance, 1/k, centred).
@@ -393,6 +445,8 @@ __global__ __launch_bounds__(GQ_BT) void grid_nn_kernel(const float4* __restrict
                                                         const float* __restrict__ qy, const float* __restrict__ qz,
                                                         int nq, float max_key, int32_t* __restrict__ nn,
                                                         float* __restrict__ key) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  float4* buf = s_buf + threadIdx.x;
   const int t = blockIdx.x * GQ_BT + threadIdx.x;
   if (t >= nq) return;  // no barriers below
   const GridInfo G = *gi;
@@ -404,31 +458,17 @@ __global__ __launch_bounds__(GQ_BT) void grid_nn_kernel(const float4* __restrict
     for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
     const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
     for (int r = 0; r <= rmax; ++r) {
-      for (int dz = -r; dz <= r; ++dz) {
-        const int cz = c[2] + dz;
-        if (cz < 0 || cz >= G.dims[2]) continue;
-        for (int dy = -r; dy <= r; ++dy) {
-          const int cy = c[1] + dy;
-          if (cy < 0 || cy >= G.dims[1]) continue;
-          const bool inner = (abs(dz) < r) && (abs(dy) < r);
-          for (int dx = -r; dx <= r; dx += (inner && r > 0) ? 2 * r : 1) {
-            const int cx = c[0] + dx;
-            if (cx < 0 || cx >= G.dims[0]) continue;
-            const int cell = (cz * G.dims[1] + cy) * G.dims[0] + cx;
-            const int p1 = starts[cell + 1];
-            for (int p = starts[cell]; p < p1; ++p) {
-              const float4 P = spts[p];
-              const int j = __float_as_int(P.w);
-              const float ex = __fsub_rn(P.x, qv[0]), ey = __fsub_rn(P.y, qv[1]), ez = __fsub_rn(P.z, qv[2]);
-              const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
-              if (key_less(d2, j, bd, bi)) {
-                bd = d2;
-                bi = j;
-              }
-            }
+      shell_spans(starts, G, c, r, [&](int p0, int p1) {
+        span_points(spts, p0, p1, buf, [&](const float4& P) {
+          const int j = __float_as_int(P.w);
+          const float ex = __fsub_rn(P.x, qv[0]), ey = __fsub_rn(P.y, qv[1]), ez = __fsub_rn(P.z, qv[2]);
+          const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+          if (key_less(d2, j, bd, bi)) {
+            bd = d2;
+            bi = j;
           }
-        }
-      }
+        });
+      });
       // distance from the query to any cell outside the searched cube
       double lb = INFINITY;
       bool all = true;
