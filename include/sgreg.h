@@ -96,7 +96,9 @@ typedef struct {
                     matrix cores (pair weights FP32, rounded to bf16; coordinates
                     split into bf16 head + tail; FP32 accumulate, FP64 wrench);
                     the energy U is then reported as 0 except by the FP32 final
-                    iteration of sgr_register; not for batch calls. */
+                    iteration of sgr_register; not for batch calls;
+                    bit 2: vector descriptors (sgr_step_vec, sgr_register_vec)
+                    with FP32 matrix products instead of the split-f16 form. */
   double dt2;
 } sgr_params;
 
@@ -204,7 +206,13 @@ int sgr_descriptors_hn(sgr_ctx* ctx, const sgr_cloud* c, int k, int D, float* h_
  * float32, row-major; e.g. from sgr_descriptors_hn).  sigma <= 0 selects
  * sigma^2 = mean_j |a_j - abar|^2 over the reference (abar its mean; the std
  * of the scalar case when D = 1).  The similarity exponents of all pairs are
- * one dense contraction, evaluated on the matrix cores in FP32.  Supported:
+ * one dense contraction on the matrix cores: by default each entry of the
+ * standardised operands is split into an f16 head and tail and three f16
+ * products are accumulated in FP32 (about 2^-22 relative per product); FP32
+ * products (flags bit 2, and automatically when a standardised descriptor
+ * lies more than about 140 spreads from the mean, beyond the f16 range) are
+ * about 2^-24.  The set-up synchronises the stream once to make that choice.
+ * Supported:
  * p = 1, g_mode 0, no mixed precision, 1 <= D <= 30 (SGR_EINVAL otherwise).
  * Other arguments, outputs and errors as in sgr_step / sgr_register
  * (sgr_register_vec computes the moments itself; SGR_EDEGENERATE also for

@@ -95,7 +95,7 @@ int check_params(const sgr_params* p) {
   if (p->g_mode < 0 || p->g_mode > 2)
     return fail(SGR_EINVAL, "g_mode must be 0 (g = s), 1 (g = a a s) or 2 (g = 1, masses only)");
   if (!(p->G1 > 0) || !std::isfinite(p->G1)) return fail(SGR_EINVAL, "G1 must be positive");
-  if (p->flags & ~3) return fail(SGR_EINVAL, "unknown flag bits");
+  if (p->flags & ~7) return fail(SGR_EINVAL, "unknown flag bits");
   if (!std::isfinite(p->sigma) || !std::isfinite(p->eps) || p->eps < 0) return fail(SGR_EINVAL, "bad sigma/eps");
   if (!std::isfinite(p->dt2)) return fail(SGR_EINVAL, "bad dt2");
   return SGR_OK;
@@ -117,6 +117,7 @@ int pmode_of(double p) { return p == 1.0 ? 1 : (p == 3.0 ? 3 : 0); }
 
 constexpr int FLAG_NO_GRAPH = 1;
 constexpr int FLAG_MIXED = 2;
+constexpr int FLAG_VEC_FP32 = 4;
 
 bool is_mixed(const sgr_params* p) { return (p->flags & FLAG_MIXED) != 0; }
 
@@ -529,6 +530,7 @@ struct VecWs {
   double* fpart;
   double* mom;
   int K, n_chunks, slots;
+  bool half;  // split-f16 products (decided by setup_vec)
 };
 
 int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, VecWs& w) {
@@ -538,9 +540,10 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
   for (int pass = 0; pass < 2; ++pass) {
     Carve c{pass ? ctx->ws : nullptr};
     w.dv = c.take<Derived>(1);
-    w.vd = c.take<double>(34);
-    w.At = c.take<float>((size_t)vforce_pad_rows(M) * w.K);
-    w.Bt = c.take<float>((size_t)vforce_pad_refs(N) * w.K);
+    w.vd = c.take<double>(35);
+    // rows of K floats (FP32 form) or 64 halves = 32 floats (split f16)
+    w.At = c.take<float>((size_t)vforce_pad_rows(M) * std::max(w.K, 32));
+    w.Bt = c.take<float>((size_t)vforce_pad_refs(N) * std::max(w.K, 32));
     w.ref4 = c.take<float4>((size_t)vforce_pad_refs(N));
     w.wpart = c.take<double>((size_t)w.slots * WR_STRIDE);
     w.fpart = with_f ? c.take<double>((size_t)w.n_chunks * M * 3) : nullptr;
@@ -551,12 +554,24 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
   return SGR_OK;
 }
 
+// Set-up of the vector-descriptor force.  Reads back the range of the
+// standardised descriptors (one synchronisation) to choose the split-f16
+// form, unless the caller asks for FP32 products.
 int setup_vec(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r, int D,
               const double* mom_t, const double* mom_r, const sgr_params* prm, VecWs& w, hipStream_t st) {
   const int M = (int)tmpl->n, N = (int)ref->n;
   HIPCHK(launch_prepare(nullptr, ref->m, N, nullptr, tmpl->m, M, mom_t, mom_r, prep_of(prm), w.dv, st));
-  HIPCHK(launch_vprep(a_r, N, D, prm->sigma, w.dv, w.vd, st));
-  HIPCHK(launch_vpack(ref->x, ref->y, ref->z, a_r, ref->m, N, a_t, M, D, w.dv, w.vd, w.Bt, w.ref4, w.At, st));
+  HIPCHK(launch_vprep(a_r, N, a_t, M, D, prm->sigma, w.dv, w.vd, st));
+  w.half = false;
+  if (!(prm->flags & FLAG_VEC_FP32)) {
+    double cmax = 0.0;
+    HIPCHK(hipMemcpyAsync(&cmax, w.vd + 34, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    w.half = vforce_half_ok(cmax);
+  }
+  if (w.half) w.K = 32;
+  HIPCHK(launch_vpack(ref->x, ref->y, ref->z, a_r, ref->m, N, a_t, M, D, w.half, w.dv, w.vd, w.Bt, w.ref4, w.At,
+                      st));
   return SGR_OK;
 }
 
@@ -574,6 +589,7 @@ VForceArgs vargs(const sgr_cloud* tmpl, const sgr_cloud* ref, const VecWs& w, co
   A.M = (int)tmpl->n;
   A.N = (int)ref->n;
   A.K = w.K;
+  A.half = w.half;
   A.n_chunks = w.n_chunks;
   A.t = t;
   A.G = 0.0;
@@ -962,8 +978,8 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
     std::vector<uint8_t> key;
     const void* ptrs[12] = {tmpl->x, tmpl->y, tmpl->z, tmpl->m, ref->x, ref->y, ref->z, ref->m, inout, stats, a_t, a_r};
     key_add(key, ptrs, 12);
-    const int64_t dims[3] = {M, N, D};
-    key_add(key, dims, 3);
+    const int64_t dims[4] = {M, N, D, w.half ? 1 : 0};
+    key_add(key, dims, 4);
     key_add(key, prm, 1);
     const void* wsp = ctx->ws;
     key_add(key, &wsp, 1);

@@ -164,8 +164,8 @@ hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n
 hipError_t launch_moments(const float* x, const float* y, const float* z, int64_t n, double* out, hipStream_t st);
 // Force with vector descriptors (p = 1, g = s) on the matrix cores.
 struct VForceArgs {
-  const float* At;      // template augmented rows [Mpad][K]
-  const float* Bt;      // reference augmented rows [Npad][K]
+  const void* At;       // template augmented rows [Mpad]: K floats, or 64 halves (f16 head, tail)
+  const void* Bt;       // reference augmented rows [Npad], same form
   const float4* ref4;   // reference x, y, z (centred at xbar), |x|^2 [Npad]
   const float* y0x;
   const float* y0y;
@@ -174,6 +174,7 @@ struct VForceArgs {
   const double* pose;
   const Derived* dv;
   int M, N, K, n_chunks, t;
+  bool half;            // split-f16 rows and instructions (K = 32)
   double G;             // > 0 overrides eq. 12
   double* wpart;        // [n_iblk * n_chunks][WR_STRIDE]
   double* fpart;        // [n_chunks][M][3] (WF only)
@@ -183,11 +184,15 @@ int vforce_pad_rows(int M);
 int vforce_pad_refs(int N);
 int vforce_n_iblk(int M);
 int vforce_chunks(int M, int N, int n_cu);
-// vd: [34] doubles: reference mean (32), sigma, kappa = log2(e) / sigma^2
-hipError_t launch_vprep(const float* aX, int64_t N, int D, double sigma, Derived* dv, double* vd, hipStream_t st);
+// vd: [35] doubles: reference mean (32), sigma, log2(e) / sigma^2, and the
+// largest |a - abar|^2 / sigma^2 over both clouds (for vforce_half_ok)
+hipError_t launch_vprep(const float* aX, int64_t N, const float* aY, int64_t M, int D, double sigma, Derived* dv,
+                        double* vd, hipStream_t st);
+bool vforce_half_ok(double cmax);
+// Rows: K floats each (half = false) or 64 halves each (half = true).
 hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const float* aX, const float* wX, int N,
-                        const float* aY, int M, int D, const Derived* dv, const double* vd, float* Bt, float4* ref4,
-                        float* At, hipStream_t st);
+                        const float* aY, int M, int D, bool half, const Derived* dv, const double* vd, void* Bt,
+                        float4* ref4, void* At, hipStream_t st);
 hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st);
 // Soft histogram of normals: h_out[n][D] from the k nearest neighbours.
 size_t normal_hist_workspace(int n, int k);

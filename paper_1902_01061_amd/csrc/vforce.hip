@@ -8,9 +8,17 @@
 // is one dot product of augmented rows
 //   At_i = [2 kappa c_i, -kappa |c_i|^2, 1, 0...],
 //   Bt_j = [c_j, 1, lw_j - kappa |c_j|^2, 0...],
-// of length K = 4 ceil((D + 2) / 4), so c_ij = exp2(At_i . Bt_j) for a 16 x 16
-// block of pairs comes from K/4 FP32 16x16x4 matrix instructions (products
-// of FP32 inputs, FP32 accumulation) and 16 exp2.  The p = 1 moment form then
+// (written below with the standardised c / sigma, so that every entry is of
+// order one), and c_ij = exp2(At_i . Bt_j) for a 16 x 16 block of pairs
+// comes from the matrix cores in one of two forms:
+//  - split f16 (default): every entry is split into an f16 head and an f16
+//    tail (x = h + l + O(2^-22 |x|)), and h.h + h.l + l.h, three 16x16x32
+//    f16 instructions with FP32 accumulation (tails first), give the dot
+//    product to about 2^-22 of the size of its terms, K = 32;
+//  - FP32: K/4 FP32 16x16x4 instructions, K = 4 ceil((D + 2) / 4); used when
+//    an entry would leave the f16 range (a descriptor more than about 140
+//    spreads from the mean) or when the caller asks for it.
+// 16 exp2 then turn the block into pair weights.  The p = 1 moment form then
 // needs, per template point, sum_j c, sum_j c x_j (and sum_j c |x_j|^2 for
 // the energy) over the reference, accumulated in FP32 by the vector ALU.
 //
@@ -54,10 +62,12 @@ __host__ __device__ constexpr int bt_stride(int K) { return ((K / 4) & 1) ? K : 
 // abar, sigma and kappa of the vector descriptors; writes sigma into the
 // Derived of the registration (its other fields come from the scalar
 // set-up, called without curvatures).
-__global__ __launch_bounds__(1024) void vprep_kernel(const float* __restrict__ aX, int64_t N, int D, double sigma_in,
+__global__ __launch_bounds__(1024) void vprep_kernel(const float* __restrict__ aX, int64_t N,
+                                                     const float* __restrict__ aY, int64_t M, int D, double sigma_in,
                                                      Derived* __restrict__ dv, double* __restrict__ vd) {
   __shared__ double lds[16 * 32];
   __shared__ double mean[32];
+  __shared__ double sig_s;
   double s[32];
   for (int c = 0; c < 32; ++c) s[c] = 0.0;
   for (int64_t j = threadIdx.x; j < N; j += 1024) {
@@ -76,64 +86,106 @@ __global__ __launch_bounds__(1024) void vprep_kernel(const float* __restrict__ a
       v[0] += d * d;
     }
   block_sum<1, 1024>(v, lds);
+  if (threadIdx.x == 0) sig_s = sigma_in > 0 ? sigma_in : sqrt(v[0] / (double)N);
+  __syncthreads();
+  const double sigma = sig_s;
+  // largest |a - abar|^2 / sigma^2 over both clouds (NaN-propagating): the
+  // host picks the f16 form only if every augmented entry fits its range
+  double mx = 0.0;
+  for (int64_t r = threadIdx.x; r < N + M; r += 1024) {
+    const float* a = r < N ? aX + r * D : aY + (r - N) * D;
+    double n2 = 0.0;
+    for (int c = 0; c < D; ++c) {
+      const double e = ((double)a[c] - mean[c]) / sigma;
+      n2 += e * e;
+    }
+    mx = (n2 > mx || n2 != n2) ? n2 : mx;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_xor(mx, off, 64);
+    mx = (o > mx || o != o) ? o : mx;
+  }
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
+  __syncthreads();
   if (threadIdx.x != 0) return;
-  const double sigma = sigma_in > 0 ? sigma_in : sqrt(v[0] / (double)N);
+  for (int w = 1; w < 16; ++w) mx = (lds[w] > mx || lds[w] != lds[w]) ? lds[w] : mx;
   for (int c = 0; c < 32; ++c) vd[c] = mean[c];
   vd[32] = sigma;
   vd[33] = LOG2E / (sigma * sigma);
+  vd[34] = mx;
   dv->sigma = sigma;
   if (!(sigma > 0) || !isfinite(vd[33])) dv->status |= ST_DEGENERATE;
 }
 
-// Augmented rows, FP64 arithmetic rounded once to FP32.  Rows j >= N of the
-// reference are zero-weight padding (exponent -1e30, exp2 gives 0); rows
+// Augmented rows from the standardised descriptors c = (a - abar) / sigma:
+//   At_i = [2 log2(e) c_i, -log2(e) |c_i|^2, 1, 0...],
+//   Bt_j = [c_j, 1, lw_j - log2(e) |c_j|^2, 0...],
+// FP64 arithmetic, then either rounded once to FP32 (K entries per row) or
+// split into f16 head and tail (64 halves per row: 32 heads, then 32
+// tails).  Rows j >= N of the reference are zero-weight padding (exponent
+// -30000: exp2 gives 0, and the value is an f16 head with zero tail); rows
 // i >= M of the template are harmless padding (their sums are dropped).
+__device__ inline void put_entry(void* row, int c, double x, bool half) {
+  if (half) {
+    _Float16* h = reinterpret_cast<_Float16*>(row);
+    const _Float16 hi = (_Float16)x;
+    h[c] = hi;
+    h[32 + c] = (_Float16)(x - (double)hi);
+  } else {
+    reinterpret_cast<float*>(row)[c] = (float)x;
+  }
+}
+
 __global__ __launch_bounds__(256) void vpack_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                     const float* __restrict__ Zc, const float* __restrict__ aX,
                                                     const float* __restrict__ wX, int N, int Npad,
                                                     const float* __restrict__ aY, int M, int Mpad, int D, int K,
-                                                    const Derived* __restrict__ dv, const double* __restrict__ vd,
-                                                    float* __restrict__ Bt, float4* __restrict__ ref4,
-                                                    float* __restrict__ At) {
+                                                    bool half, const Derived* __restrict__ dv,
+                                                    const double* __restrict__ vd, void* __restrict__ Bt,
+                                                    float4* __restrict__ ref4, void* __restrict__ At) {
   const int r = blockIdx.x * 256 + threadIdx.x;
-  const double kap = vd[33];
+  const double isig = 1.0 / vd[32];
+  const int Kr = half ? 32 : K;                        // entries per row
+  // exponent of zero-weight rows: exp2 of it is 0, and it is an f16 value
+  // (the f16 form is only chosen when every other entry stays below 30000)
+  const double pad_exp = half ? -30000.0 : -1e30;
+  const size_t rb = half ? 64 * sizeof(_Float16) : (size_t)K * sizeof(float);  // bytes per row
   if (r < Npad) {
-    float* b = Bt + (int64_t)r * K;
+    void* b = reinterpret_cast<char*>(Bt) + (size_t)r * rb;
+    for (int c = 0; c < Kr; ++c) put_entry(b, c, 0.0, half);
     if (r < N) {
       double n2 = 0.0;
       for (int c = 0; c < D; ++c) {
-        const double e = (double)aX[(int64_t)r * D + c] - vd[c];
-        b[c] = (float)e;
+        const double e = ((double)aX[(int64_t)r * D + c] - vd[c]) * isig;
+        put_entry(b, c, e, half);
         n2 += e * e;
       }
       const double lw = wX ? log2((double)wX[r]) : 0.0;
-      b[D] = 1.f;
-      b[D + 1] = (float)fmax(lw - kap * n2, -1e30);
-      for (int c = D + 2; c < K; ++c) b[c] = 0.f;
+      put_entry(b, D, 1.0, half);
+      put_entry(b, D + 1, fmax(lw - LOG2E * n2, pad_exp), half);
       const Derived& Dd = *dv;
       const float x = (float)((double)X[r] - Dd.xbar[0]), y = (float)((double)Y[r] - Dd.xbar[1]),
                   z = (float)((double)Zc[r] - Dd.xbar[2]);
       ref4[r] = make_float4(x, y, z, (float)((double)x * x + (double)y * y + (double)z * z));
     } else {
-      for (int c = 0; c < K; ++c) b[c] = 0.f;
-      b[D] = 1.f;
-      b[D + 1] = -1e30f;
+      put_entry(b, D, 1.0, half);
+      put_entry(b, D + 1, pad_exp, half);
       ref4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
   if (r < Mpad) {
-    float* a = At + (int64_t)r * K;
-    for (int c = 0; c < K; ++c) a[c] = 0.f;
+    void* a = reinterpret_cast<char*>(At) + (size_t)r * rb;
+    for (int c = 0; c < Kr; ++c) put_entry(a, c, 0.0, half);
     if (r < M) {
       double n2 = 0.0;
       for (int c = 0; c < D; ++c) {
-        const double e = (double)aY[(int64_t)r * D + c] - vd[c];
-        a[c] = (float)(2.0 * kap * e);
+        const double e = ((double)aY[(int64_t)r * D + c] - vd[c]) * isig;
+        put_entry(a, c, 2.0 * LOG2E * e, half);
         n2 += e * e;
       }
-      a[D] = (float)(-kap * n2);
+      put_entry(a, D, -LOG2E * n2, half);
     }
-    a[D + 1] = 1.f;
+    put_entry(a, D + 1, 1.0, half);
   }
 }
 
@@ -141,17 +193,29 @@ __device__ inline double G_of(const Derived& D, int t) {
   return 0.1 * D.G1 + 0.9 * D.G1 / (1.0 + exp(-(((double)t - 1.0) - 0.5 * D.E)));
 }
 
-template <int VK, bool WU, bool WF>
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+// H = false: FP32 rows of K = 4 VK entries, K/4 16x16x4 FP32 instructions.
+// H = true: f16 head/tail rows (64 halves), three 16x16x32 f16 instructions;
+// VK is unused.  Lane layouts (checked on the device): 16x16x4 f32 takes
+// A[i = lane % 16][k = lane / 16] and B[k = lane / 16][j = lane % 16];
+// 16x16x32 f16 takes A[i = lane % 16][k = 8 (lane / 16) + e] and
+// B[k = 8 (lane / 16) + e][j = lane % 16], e = 0..7; both return
+// D[i = 4 (lane / 16) + v][j = lane % 16], v = 0..3.
+template <int VK, bool H, bool WU, bool WF>
 __global__ __launch_bounds__(VF_BT)
 #if SGR_VF_WAVES > 0
 __attribute__((amdgpu_waves_per_eu(SGR_VF_WAVES, SGR_VF_WAVES)))
 #endif
 void vforce_kernel(VForceArgs A) {
-  constexpr int K = 4 * VK;
-  constexpr int KS = bt_stride(K);
+  constexpr int K = H ? 32 : 4 * VK;
+  // LDS words per staged reference row: FP32 rows use bt_stride(K); f16 rows
+  // (32 words) are padded to 36 words so that a 16-byte read per lane
+  // (16 rows x 4 quarter-rows) spreads over the banks
+  constexpr int KS = H ? 36 : bt_stride(K);
   constexpr int NQ = WU ? 5 : 4;
   constexpr int LDS_B = VF_TJ * KS > NQ * VF_ROWS ? VF_TJ * KS : NQ * VF_ROWS;  // tile, then the row sums
-  __shared__ float s_B[LDS_B];
+  __shared__ __attribute__((aligned(16))) float s_B[LDS_B];
   __shared__ float4 s_X[VF_TJ];
   __shared__ double s_red[(VF_BT / 64) * 13];
   const int n_iblk = (A.M + VF_ROWS - 1) / VF_ROWS;
@@ -164,11 +228,23 @@ void vforce_kernel(VForceArgs A) {
   const int j0 = (int)((int64_t)chunk * n_t / A.n_chunks) * VF_TJ;
   const int j1 = (int)((int64_t)(chunk + 1) * n_t / A.n_chunks) * VF_TJ;
 
-  float areg[VF_TI][VK];
+  float areg[VF_TI][H ? 1 : VK];
+  v8h ahi[H ? VF_TI : 1], alo[H ? VF_TI : 1];
+  if constexpr (H) {
+    const _Float16* At = reinterpret_cast<const _Float16*>(A.At);
 #pragma unroll
-  for (int r = 0; r < VF_TI; ++r)
+    for (int r = 0; r < VF_TI; ++r) {
+      const _Float16* row = At + (int64_t)(row0 + 16 * r + col) * 64;
+      ahi[r] = *reinterpret_cast<const v8h*>(row + 8 * kq);
+      alo[r] = *reinterpret_cast<const v8h*>(row + 32 + 8 * kq);
+    }
+  } else {
+    const float* At = reinterpret_cast<const float*>(A.At);
 #pragma unroll
-    for (int s = 0; s < VK; ++s) areg[r][s] = A.At[(int64_t)(row0 + 16 * r + col) * K + 4 * s + kq];
+    for (int r = 0; r < VF_TI; ++r)
+#pragma unroll
+      for (int s = 0; s < VK; ++s) areg[r][s] = At[(int64_t)(row0 + 16 * r + col) * K + 4 * s + kq];
+  }
   float S[VF_TI][4][NQ];
 #pragma unroll
   for (int r = 0; r < VF_TI; ++r)
@@ -179,25 +255,44 @@ void vforce_kernel(VForceArgs A) {
 
   for (int base = j0; base < j1; base += VF_TJ) {
     __syncthreads();
-    for (int e = threadIdx.x; e < VF_TJ * VK; e += VF_BT) {
-      const int jj = e / VK, s = e % VK;
-      const float4 b4 = *reinterpret_cast<const float4*>(A.Bt + (int64_t)(base + jj) * K + 4 * s);
-      *reinterpret_cast<float4*>(&s_B[jj * KS + 4 * s]) = b4;
+    {
+      // a staged row is RW words: K FP32 entries, or 64 halves = 32 words
+      constexpr int RW = H ? 32 : K;
+      const float* Bt = reinterpret_cast<const float*>(A.Bt);
+      for (int e = threadIdx.x; e < VF_TJ * (RW / 4); e += VF_BT) {
+        const int jj = e / (RW / 4), s = e % (RW / 4);
+        const float4 b4 = *reinterpret_cast<const float4*>(Bt + (int64_t)(base + jj) * RW + 4 * s);
+        *reinterpret_cast<float4*>(&s_B[jj * KS + 4 * s]) = b4;
+      }
     }
     if (threadIdx.x < VF_TJ) s_X[threadIdx.x] = A.ref4[base + threadIdx.x];
     __syncthreads();
 #pragma unroll 1
     for (int c = 0; c < VF_TJ / 16; ++c) {
       const int jl = 16 * c + col;
-      float breg[VK];
+      float breg[H ? 1 : VK];
+      v8h bhi, blo;
+      if constexpr (H) {
+        bhi = *reinterpret_cast<const v8h*>(&s_B[jl * KS + 4 * kq]);
+        blo = *reinterpret_cast<const v8h*>(&s_B[jl * KS + 16 + 4 * kq]);
+      } else {
 #pragma unroll
-      for (int s = 0; s < VK; ++s) breg[s] = s_B[jl * KS + 4 * s + kq];
+        for (int s = 0; s < VK; ++s) breg[s] = s_B[jl * KS + 4 * s + kq];
+      }
       const float4 X = s_X[jl];
 #pragma unroll
       for (int r = 0; r < VF_TI; ++r) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (H) {
+          // tails first: the small products are added before the large one
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo[r], bhi, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[r], blo, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[r], bhi, acc, 0, 0, 0);
+        } else {
 #pragma unroll
-        for (int s = 0; s < VK; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[r][s], breg[s], acc, 0, 0, 0);
+          for (int s = 0; s < VK; ++s)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[r][s], breg[s], acc, 0, 0, 0);
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float cc = __builtin_amdgcn_exp2f(acc[v]);
@@ -301,18 +396,18 @@ done:
   }
 }
 
-template <int VK>
+template <int VK, bool H>
 hipError_t launch_vk(const VForceArgs& A, bool wu, bool wf, hipStream_t st) {
   const int n_iblk = (A.M + VF_ROWS - 1) / VF_ROWS;
   const dim3 grid((unsigned)(n_iblk * A.n_chunks)), block(VF_BT);
   if (wu && wf)
-    hipLaunchKernelGGL((vforce_kernel<VK, true, true>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((vforce_kernel<VK, H, true, true>), grid, block, 0, st, A);
   else if (wu)
-    hipLaunchKernelGGL((vforce_kernel<VK, true, false>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((vforce_kernel<VK, H, true, false>), grid, block, 0, st, A);
   else if (wf)
-    hipLaunchKernelGGL((vforce_kernel<VK, false, true>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((vforce_kernel<VK, H, false, true>), grid, block, 0, st, A);
   else
-    hipLaunchKernelGGL((vforce_kernel<VK, false, false>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((vforce_kernel<VK, H, false, false>), grid, block, 0, st, A);
   return hipGetLastError();
 }
 
@@ -332,33 +427,39 @@ int vforce_chunks(int M, int N, int n_cu) {
   return std::max(1, std::min(nc, n_t));
 }
 
-hipError_t launch_vprep(const float* aX, int64_t N, int D, double sigma, Derived* dv, double* vd, hipStream_t st) {
-  hipLaunchKernelGGL(vprep_kernel, dim3(1), dim3(1024), 0, st, aX, N, D, sigma, dv, vd);
+hipError_t launch_vprep(const float* aX, int64_t N, const float* aY, int64_t M, int D, double sigma, Derived* dv,
+                        double* vd, hipStream_t st) {
+  hipLaunchKernelGGL(vprep_kernel, dim3(1), dim3(1024), 0, st, aX, N, aY, M, D, sigma, dv, vd);
   return hipGetLastError();
 }
 
 hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const float* aX, const float* wX, int N,
-                        const float* aY, int M, int D, const Derived* dv, const double* vd, float* Bt, float4* ref4,
-                        float* At, hipStream_t st) {
+                        const float* aY, int M, int D, bool half, const Derived* dv, const double* vd, void* Bt,
+                        float4* ref4, void* At, hipStream_t st) {
   const int Npad = vforce_pad_refs(N), Mpad = vforce_pad_rows(M), K = vforce_K(D);
   const int rows = std::max(Npad, Mpad);
   hipLaunchKernelGGL(vpack_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, X, Y, Z, aX, wX, N, Npad,
-                     aY, M, Mpad, D, K, dv, vd, Bt, ref4, At);
+                     aY, M, Mpad, D, K, half, dv, vd, Bt, ref4, At);
   return hipGetLastError();
 }
 
 hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st) {
+  if (A.half) return launch_vk<1, true>(A, wu, wf, st);
   switch (A.K / 4) {
-    case 1: return launch_vk<1>(A, wu, wf, st);
-    case 2: return launch_vk<2>(A, wu, wf, st);
-    case 3: return launch_vk<3>(A, wu, wf, st);
-    case 4: return launch_vk<4>(A, wu, wf, st);
-    case 5: return launch_vk<5>(A, wu, wf, st);
-    case 6: return launch_vk<6>(A, wu, wf, st);
-    case 7: return launch_vk<7>(A, wu, wf, st);
-    case 8: return launch_vk<8>(A, wu, wf, st);
+    case 1: return launch_vk<1, false>(A, wu, wf, st);
+    case 2: return launch_vk<2, false>(A, wu, wf, st);
+    case 3: return launch_vk<3, false>(A, wu, wf, st);
+    case 4: return launch_vk<4, false>(A, wu, wf, st);
+    case 5: return launch_vk<5, false>(A, wu, wf, st);
+    case 6: return launch_vk<6, false>(A, wu, wf, st);
+    case 7: return launch_vk<7, false>(A, wu, wf, st);
+    case 8: return launch_vk<8, false>(A, wu, wf, st);
     default: return hipErrorInvalidValue;
   }
 }
+
+// f16 form possible: every augmented entry below 30000 in magnitude (the
+// largest is log2(e) |c|^2 + |lw|; masses within 2^+-100 keep |lw| small).
+bool vforce_half_ok(double cmax) { return cmax == cmax && LOG2E * cmax <= 29000.0; }
 
 }  // namespace sgr

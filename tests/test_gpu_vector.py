@@ -74,17 +74,21 @@ def _vec_case(D, seed, kind):
         aX = (cen[rng.integers(0, 6, pr.N)] + 0.05 * rng.normal(size=(pr.N, D))).astype(np.float32)
         aY = (cen[rng.integers(0, 6, pr.M)] + 0.05 * rng.normal(size=(pr.M, D))).astype(np.float32)
         aY[:20] += 2.0
+        if kind == "extreme":                        # beyond the f16 range of the split form
+            sd = np.sqrt(np.mean(np.sum((aX - aX.mean(0)) ** 2, axis=1)))
+            aY[20:23] = aX.mean(0) + 500.0 * sd / np.sqrt(D)
+            aX[:2] = aY[20]
     return pr, aX, aY
 
 
-def _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX=None, mY=None):
+def _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX=None, mY=None, flags=0):
     S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64), wX=wX, mY=mY)
     Y = pose.apply(pr.tmpl)
     so = O.step(Y, S, t)
     ora_pose = O.compose(pose, so, Y.mean(axis=0))
     tm = sg.Cloud(pr.tmpl, masses=mY)
     rf = sg.Cloud(pr.ref, masses=wX)
-    gp = sg.Params(p=prm.p, g_mode=prm.g_mode, k=prm.k, sigma=prm.sigma, eps=prm.eps, E=prm.E)
+    gp = sg.Params(p=prm.p, g_mode=prm.g_mode, k=prm.k, sigma=prm.sigma, eps=prm.eps, E=prm.E, flags=flags)
     pout, wr, f = ctx.step_vec(tm, _dt(aY), rf, _dt(aX), _dt(_mom(pr.tmpl), torch.float64),
                                _dt(_mom(pr.ref), torch.float64), gp, t, sg.pose_from_srt(pose.s, pose.R, pose.t),
                                want_wrench=True, want_f=True)
@@ -102,10 +106,15 @@ def _errors(so, wr, f, Y, mY=None):
     return e_f, e_F, e_K, e_U
 
 
-@pytest.mark.parametrize("D,kind,masses,eps", [(16, "uniform", False, 0.0), (30, "clustered", True, 0.02),
-                                                (5, "uniform", True, 0.0), (1, "clustered", False, 0.0),
-                                                (14, "clustered", False, 0.0)])
-def test_step_vec_matches_oracle(sg, ctx, D, kind, masses, eps):
+@pytest.mark.parametrize("D,kind,masses,eps,flags", [
+    (16, "uniform", False, 0.0, 0), (30, "clustered", True, 0.02, 0), (5, "uniform", True, 0.0, 0),
+    (1, "clustered", False, 0.0, 0), (14, "clustered", False, 0.0, 0),
+    (16, "uniform", False, 0.0, 4), (30, "clustered", True, 0.02, 4), (5, "uniform", True, 0.0, 4),
+    (9, "extreme", True, 0.0, 0)])
+def test_step_vec_matches_oracle(sg, ctx, D, kind, masses, eps, flags):
+    """flags 0: split-f16 products (the default), except for "extreme", whose
+    descriptors lie 500 spreads from the mean and select FP32 products by
+    themselves; flags 4: FP32 products."""
     pr, aX, aY = _vec_case(D, 40 + D, kind)
     rng = np.random.default_rng(D)
     wX = rng.uniform(0.5, 2.0, pr.N).astype(np.float32).astype(np.float64) if masses else None
@@ -113,9 +122,10 @@ def test_step_vec_matches_oracle(sg, ctx, D, kind, masses, eps):
     prm = O.Params(p=1.0, k=16, eps=eps, E=40)
     pose = O.Pose(1.1, rot_axis_angle([1, 2, 3], 20.0), np.array([0.1, -0.2, 0.05]))
     for t in (0, 39):
-        so, ora_pose, pout, wr, f, Y = _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX, mY)
+        so, ora_pose, pout, wr, f, Y = _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX, mY, flags)
         e = _errors(so, wr, f, Y, mY)
-        print(f"vector step D={D} {kind} t={t}: e_f={e[0]:.1e} e_F={e[1]:.1e} e_K={e[2]:.1e} e_U={e[3]:.1e}")
+        print(f"vector step D={D} {kind} flags={flags} t={t}: e_f={e[0]:.1e} e_F={e[1]:.1e} e_K={e[2]:.1e} "
+              f"e_U={e[3]:.1e}")
         assert max(e) <= F_TOL, e
         gp = O.Pose(pout[0], pout[1:10].reshape(3, 3), pout[10:13])
         d = gp.apply(pr.tmpl) - ora_pose.apply(pr.tmpl)
