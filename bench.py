@@ -311,9 +311,12 @@ def extra_pyramid(sg, ctx, E: int, k: int):
 def extra_vector(sg, ctx, E: int, k: int, D: int = 16):
     """Vector shape descriptors on the workload pair: the soft histograms of
     normals (D bins) of both clouds, then the registration whose pair
-    exponents are a K = 4 ceil((D + 2) / 4) contraction on the FP32 matrix
-    cores.  Matrix-core rate = 2 K M N E / registration time (a lower
-    bound: the time includes set-up and updates)."""
+    exponents are a contraction on the matrix cores, in its two forms: split
+    f16 (three 16x16x32 f16 products per 16 x 16 block, K = 32; peak 2.5
+    PFLOP/s) and FP32 products (K = 4 ceil((D + 2) / 4); peak 157.3
+    TFLOP/s).  Matrix rate = matrix flops of all pairs of all iterations /
+    registration time: a lower bound, since the time includes set-up and
+    updates."""
     import torch
 
     from synth import config2
@@ -327,15 +330,20 @@ def extra_vector(sg, ctx, E: int, k: int, D: int = 16):
     hY = ctx.descriptors_hn(tm, k, D)
     torch.cuda.synchronize()
     d_ms = (time.perf_counter() - t0) * 1e3
-    prm = sg.Params(p=1.0, k=k, E=E)
-    pose = sg.pose_identity()
-    ctx.register_vec(tm, hY, rf, hX, prm, pose=pose)
-    dt, _ = _timed(lambda: (pose.copy_(sg.pose_identity()), ctx.register_vec(tm, hY, rf, hX, prm, pose=pose)))
-    K = 4 * ((D + 2 + 3) // 4)
-    return {"D": D, "K": K, "M": pr.M, "N": pr.N, "iterations": E, "descriptors_ms_both_clouds": d_ms,
-            "ms_per_registration": dt * 1e3, "pairs_per_s": pr.M * pr.N * E / dt,
-            "matrix_tflops_lower_bound": 2 * K * pr.M * pr.N * E / dt / 1e12,
-            "pose_rmse_over_diameter": _pose_err(sg, pose, pr), "nn_rmse": float(ctx.residual(tm, rf, pose).item())}
+    out = {"D": D, "M": pr.M, "N": pr.N, "iterations": E, "descriptors_ms_both_clouds": d_ms}
+    pairs = pr.M * pr.N * E
+    for form, flags, fpp, peak in (("split_f16", 0, 3 * 2 * 32, 2500.0),
+                                   ("fp32", 4, 2 * 4 * ((D + 2 + 3) // 4), 157.3)):
+        prm = sg.Params(p=1.0, k=k, E=E, flags=flags)
+        pose = sg.pose_identity()
+        ctx.register_vec(tm, hY, rf, hX, prm, pose=pose)
+        dt, _ = _timed(lambda: (pose.copy_(sg.pose_identity()), ctx.register_vec(tm, hY, rf, hX, prm, pose=pose)))
+        out[form] = {"ms_per_registration": dt * 1e3, "pairs_per_s": pairs / dt, "matrix_flops_per_pair": fpp,
+                     "matrix_tflops_lower_bound": fpp * pairs / dt / 1e12,
+                     "matrix_peak_tflops": peak, "frac_lower_bound": fpp * pairs / dt / 1e12 / peak,
+                     "pose_rmse_over_diameter": _pose_err(sg, pose, pr),
+                     "nn_rmse": float(ctx.residual(tm, rf, pose).item())}
+    return out
 
 
 def extra_scene(sg, ctx, cpu_rows: int):
@@ -573,8 +581,8 @@ def main() -> int:
         log(f"pyramid: radius descriptors {out['pyramid']['radius_descriptors']['ms']:.3f} ms, registration "
             f"{out['pyramid']['pyramid']['ms_per_registration']:.1f} ms")
         out["vector"] = extra_vector(sg, ctx, E, k)
-        log(f"vector descriptors: {out['vector']['ms_per_registration']:.1f} ms/registration, "
-            f"{out['vector']['pairs_per_s']:.3g} pairs/s")
+        log(f"vector descriptors: split f16 {out['vector']['split_f16']['ms_per_registration']:.1f} ms, "
+            f"fp32 {out['vector']['fp32']['ms_per_registration']:.1f} ms per registration")
         out["scene"] = extra_scene(sg, ctx, cpu_rows=48)
         log(f"scene: fp32 {out['scene']['fp32']['ms_per_registration']:.1f} ms, "
             f"mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms")
