@@ -337,6 +337,47 @@ def forces(Y: np.ndarray, S: Setup, G: float, rows=None, block: int = 256):
     return f, U
 
 
+def force_vjp(Y: np.ndarray, S: Setup, G: float, gf: np.ndarray, gF: np.ndarray, gK: np.ndarray, block: int = 256):
+    """Gradient of L = sum_i gf_i . f_i + gF . F + sum_ab gK_ab K_ab, with
+    F = sum_i m_i f_i and K = sum_i f_i (y_i - ybar)^T (ybar the unweighted
+    mean), with respect to the template points, the template masses, sigma
+    and eps; the curvatures are held fixed.  Written from eqs. 3, 5, 11:
+    with lambda_i = dL/df_i = gf_i + m_i gF + gK (y_i - ybar) and
+    c_ij = w_j g_ij h_ij,
+      dL/dy_i = -(G/Z) sum_j c_ij [lambda_i + (p-1) (r_ij . lambda_i) r_ij / q_ij]
+                + gK^T (f_i - fbar)                   (K's lever arm),
+      dL/dm_i = gF . f_i,
+      dL/dsigma = -(G/Z) sum_ij c_ij (dln g/dsigma) (r_ij . lambda_i),
+                  dln g/dsigma = 2 (a_i - a_j)^2 / sigma^3 (0 when g = 1),
+      dL/deps = -(G/Z) sum_ij c_ij (p-1) eps / q_ij (r_ij . lambda_i).
+    FP64, blocks of template rows.  Returns (gY (M,3), gm (M,), gsigma, geps)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    prm = S.prm
+    p, eps = prm.p, prm.eps
+    f, _ = forces(Y, S, G, block=block)
+    ybar = Y.mean(axis=0)
+    lam = np.asarray(gf, np.float64) + S.mY[:, None] * np.asarray(gF, np.float64)[None, :] + \
+        (Y - ybar) @ np.asarray(gK, np.float64).T
+    gY = np.empty_like(Y)
+    gs = ge = 0.0
+    k = -(G / S.Z)
+    for b0 in range(0, len(Y), block):
+        rr = slice(b0, b0 + block)
+        r, q, c = pair_weights(Y[rr], S.aY[rr], S)
+        lr = np.einsum("bnk,bk->bn", r, lam[rr])                          # r_ij . lambda_i
+        gY[rr] = k * (c.sum(axis=1)[:, None] * lam[rr] + (p - 1) * np.einsum("bn,bnk->bk", c * lr / q, r))
+        if prm.g_mode != 2:
+            if S.aX.ndim == 2:
+                d2 = ((S.aY[rr][:, None, :] - S.aX[None, :, :]) ** 2).sum(axis=2)
+            else:
+                d2 = (S.aY[rr][:, None] - S.aX[None, :]) ** 2
+            gs += k * float(np.sum(c * lr * 2.0 * d2 / S.sigma ** 3))
+        ge += k * float(np.sum(c * lr * (p - 1) * eps / q))
+    gY += (f - f.mean(axis=0)) @ np.asarray(gK, np.float64)
+    gm = f @ np.asarray(gF, np.float64)
+    return gY, gm, gs, ge
+
+
 # ------------------------------------------------------------ rigid update
 def kabsch(Yc: np.ndarray, YD: np.ndarray):
     """eq. 6: C = Y_D^T Y = U S V^T, d = sign det(V U^T), R = V diag(1,1,d) U^T.

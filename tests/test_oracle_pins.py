@@ -150,6 +150,43 @@ def test_gravitational_mode_third_law_and_energy_gradient():
             assert -dU == pytest.approx(f[i, c], rel=1e-6, abs=1e-8)
 
 
+@pytest.mark.parametrize("p,g_mode,eps", [(1.0, 0, 0.0), (2.0, 0, 0.05), (2.0, 1, 0.02), (1.5, 0, 0.1),
+                                        (-2.0, 2, 0.05)])
+def test_force_vjp_matches_central_differences(p, g_mode, eps):
+    """The analytic FP64 adjoint against central differences of the force
+    itself, in every coordinate, mass, sigma and eps."""
+    pr = random_pair(9, 14, seed=19)
+    rng = np.random.default_rng(23)
+    X, Y = pr.ref.astype(np.float64), pr.tmpl.astype(np.float64)
+    aX, aY = rng.uniform(0.01, 0.3, 14), rng.uniform(0.01, 0.3, 9)
+    wX, m = rng.uniform(0.5, 2.0, 14), rng.uniform(0.5, 2.0, 9)
+    gf, gF, gK = rng.normal(size=(9, 3)), rng.normal(size=3), rng.normal(size=(3, 3))
+    sigma, G = 0.09, 3.0
+
+    def L(Yv=Y, mv=m, sv=sigma, ev=eps):
+        S = _setup(X, aX, aY, p=p, g_mode=g_mode, sigma=sv, eps=ev, L=0.8, wX=wX, mY=mv)
+        f, _ = O.forces(Yv, S, G)
+        return float(np.sum(gf * f) + gF @ (mv[:, None] * f).sum(0) + np.sum(gK * (f.T @ (Yv - Yv.mean(0)))))
+
+    S = _setup(X, aX, aY, p=p, g_mode=g_mode, sigma=sigma, eps=eps, L=0.8, wX=wX, mY=m)
+    gY, gm, gs, ge = O.force_vjp(Y, S, G, gf, gF, gK)
+    h = 1e-6
+    for i in range(9):
+        for c in range(3):
+            Yp, Ym = Y.copy(), Y.copy()
+            Yp[i, c] += h
+            Ym[i, c] -= h
+            assert gY[i, c] == pytest.approx((L(Yv=Yp) - L(Yv=Ym)) / (2 * h), rel=1e-6, abs=1e-8)
+        e = np.zeros(9)
+        e[i] = h
+        assert gm[i] == pytest.approx((L(mv=m + e) - L(mv=m - e)) / (2 * h), rel=1e-6, abs=1e-8)
+    assert gs == pytest.approx((L(sv=sigma + h) - L(sv=sigma - h)) / (2 * h), rel=1e-6, abs=1e-8)
+    if eps > 0:
+        assert ge == pytest.approx((L(ev=eps + h) - L(ev=eps - h)) / (2 * h), rel=1e-6, abs=1e-8)
+    if g_mode == 2:
+        assert gs == 0.0
+
+
 def test_force_equivariance():
     pr = random_pair(20, 35, seed=8)
     X = pr.ref.astype(np.float64)
