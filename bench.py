@@ -79,9 +79,10 @@ def log(msg: str) -> None:
 
 
 def cpu_baseline(pr, E: int, k: int, target_s: float):
-    """Time the FP64 C oracle force (one full M x N evaluation, repeated until
-    about target_s seconds have passed, or a row sample if one evaluation
-    alone is longer) on the host cores."""
+    """Time the FP64 C oracle force on the host cores: on all host threads
+    (one full M x N evaluation, repeated until about target_s seconds have
+    passed, or a row sample if one evaluation alone is longer), then on one
+    thread over a row sample of about target_s / 3 seconds."""
     import numpy as np
 
     from oracle import ref as O
@@ -92,29 +93,37 @@ def cpu_baseline(pr, E: int, k: int, target_s: float):
     aY = rng.uniform(0.0, 0.3, pr.M)
     S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX, aY=aY)
     Y = pr.tmpl.astype(np.float64)
-    rows = np.arange(min(512, pr.M))
-    t0 = time.perf_counter()
-    O.forces_c(Y, S, 1000.0, rows=rows)
-    t1 = time.perf_counter() - t0
-    per_row = t1 / len(rows)
-    if per_row * pr.M > target_s:
-        rows = np.arange(max(512, int(target_s / per_row)))
-        reps = 1
-    else:
-        rows = None
-        reps = max(1, int(round(target_s / (per_row * pr.M))))
-    nrows = pr.M if rows is None else len(rows)
-    t0 = time.perf_counter()
-    for _ in range(reps):
+
+    def timed_rate(budget_s):
+        rows = np.arange(min(512, pr.M))
+        t0 = time.perf_counter()
         O.forces_c(Y, S, 1000.0, rows=rows)
-    dt = time.perf_counter() - t0
-    pairs = reps * nrows * pr.N
-    rate = pairs / dt
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": rate, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+        per_row = (time.perf_counter() - t0) / len(rows)
+        if per_row * pr.M > budget_s:
+            rows = np.arange(max(64, min(pr.M, int(budget_s / per_row))))
+            reps = 1
+        else:
+            rows = None
+            reps = max(1, int(round(budget_s / (per_row * pr.M))))
+        nrows = pr.M if rows is None else len(rows)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            O.forces_c(Y, S, 1000.0, rows=rows)
+        dt = time.perf_counter() - t0
+        return reps * nrows * pr.N / dt, reps, nrows, dt
+
+    all_threads = O.c_threads()
+    rate, reps, nrows, dt = timed_rate(target_s)
+    O.c_threads(1)
+    rate1, _, nrows1, dt1 = timed_rate(target_s / 3)
+    O.c_threads(all_threads)
+    return {"value": rate, "unit": "pair-interactions/s", "cores": all_threads, "kind": "oracle",
             "sample": f"{reps} FP64 force evaluation(s) (eq. 5) of {nrows} template rows x {pr.N} reference "
-                      f"points (p = 1, g = s) by the C oracle in {dt:.1f} s; a {E}-iteration registration "
-                      f"would take {pr.M * pr.N * E / rate:.0f} s at this rate (extrapolated)"}
+                      f"points (p = 1, g = s) by the C oracle on {all_threads} threads in {dt:.1f} s; a "
+                      f"{E}-iteration registration would take {pr.M * pr.N * E / rate:.0f} s at this rate "
+                      f"(extrapolated)",
+            "single_thread": {"value": rate1, "unit": "pair-interactions/s", "cores": 1,
+                              "sample": f"{nrows1} template rows x {pr.N} reference points in {dt1:.1f} s"}}
 
 
 def _pose_err(sg, pose, pr):

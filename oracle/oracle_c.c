@@ -15,6 +15,7 @@
  *   file is compiled with -ffp-contract=off), ties broken by index.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 
@@ -91,3 +92,8 @@ void ora_knn(int64_t n, const float* P, int k, int64_t nq, const int64_t* querie
     free(bi);
   }
 }
+
+/* Thread count of the loops above (for timing the oracle on one thread and
+ * on all host threads). */
+int ora_threads(void) { return omp_get_max_threads(); }
+void ora_set_threads(int n) { omp_set_num_threads(n); }

@@ -557,7 +557,16 @@ def _clib():
         D = ctypes.c_double
         _LIB.ora_forces.argtypes = [I64, I64, P, P, P, P, P, D, ctypes.c_int, D, D, D, D, D, D, P, P]
         _LIB.ora_knn.argtypes = [I64, P, ctypes.c_int, I64, P, P]
+        _LIB.ora_threads.restype = ctypes.c_int
+        _LIB.ora_set_threads.argtypes = [ctypes.c_int]
     return _LIB
+
+
+def c_threads(n=None) -> int:
+    """Thread count of the C loops; sets it first when n is given."""
+    if n is not None:
+        _clib().ora_set_threads(int(n))
+    return int(_clib().ora_threads())
 
 
 def _ptr(a):
