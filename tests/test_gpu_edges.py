@@ -1,0 +1,127 @@
+"""Edge cases of the registration path against the oracle: clouds smaller
+than one wave and than one block (every tile ragged), a single reference
+tile, degenerate clouds (one point, non-finite coordinates) that must come
+back as errors, and the largest workload (the 250 000 x 307 200 depth-frame
+scene) on sampled rows."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref as O
+from synth import config5, random_pair, rot_axis_angle
+
+pytestmark = pytest.mark.gpu
+
+F_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def sg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1902_01061_amd as sg
+    return sg
+
+
+@pytest.fixture(scope="module")
+def ctx(sg):
+    c = sg.Context(0)
+    yield c
+    c.close()
+
+
+def _mom(P):
+    c, S, lam = O.moments(P)
+    return np.array([c[0], c[1], c[2], S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2], lam])
+
+
+def _dt(x, dtype=torch.float32):
+    return torch.as_tensor(np.asarray(x)).to(device="cuda", dtype=dtype).contiguous()
+
+
+@pytest.mark.parametrize("M,N,k,p", [(17, 23, 8, 1.0), (63, 65, 16, 2.0), (5, 300, 4, 1.0), (300, 5, 4, 1.0)])
+def test_tiny_clouds_step_and_register_match_oracle(sg, ctx, M, N, k, p):
+    pr = random_pair(M, N, seed=M * 100 + N)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    a_t, m_t = ctx.descriptors(tm, k)
+    a_r, m_r = ctx.descriptors(rf, k)
+    aY, aX = a_t.cpu().numpy().astype(np.float64), a_r.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(aY, O.descriptors(pr.tmpl, k), rtol=2e-6, atol=1e-9)
+    prm = O.Params(p=p, k=k, E=12)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX, aY=aY)
+    pose = O.Pose(0.9, rot_axis_angle([1, 0, 1], 10.0), np.array([0.1, 0.0, -0.1]))
+    Y = pose.apply(pr.tmpl)
+    so = O.step(Y, S, 5)
+    gp = sg.Params(p=p, k=k, E=12)
+    pout, wr, f = ctx.step(tm, a_t, rf, a_r, _dt(_mom(pr.tmpl), torch.float64), _dt(_mom(pr.ref), torch.float64),
+                           gp, 5, sg.pose_from_srt(pose.s, pose.R, pose.t), want_wrench=True, want_f=True)
+    f = f.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(f - so.f) <= F_TOL * np.linalg.norm(so.f)
+    po, _, _ = O.register(pr.tmpl, S)
+    pg, _ = ctx.register(tm, rf, gp)
+    s, R, t = sg.pose_to_srt(pg)
+    d = O.Pose(s, R, t).apply(pr.tmpl) - po.apply(pr.tmpl)
+    assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * O.diameter(pr.ref)
+
+
+def test_degenerate_clouds_are_errors(sg, ctx):
+    pr = random_pair(50, 60, seed=4)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    one = sg.Cloud(pr.tmpl[:1].copy())
+    with pytest.raises(sg.SgrError) as e:             # one template point: no spread, no rotation
+        ctx.register(one, rf, sg.Params(k=1, E=3))
+    assert e.value.code in (-2, -5)
+    bad = pr.tmpl.copy()
+    bad[7, 1] = np.nan
+    with pytest.raises(sg.SgrError) as e:             # a non-finite coordinate
+        ctx.register(sg.Cloud(bad), rf, sg.Params(k=8, E=3))
+    assert e.value.code in (-2, -5)
+    bad = pr.ref.copy()
+    bad[3, 0] = np.inf
+    with pytest.raises(sg.SgrError) as e:
+        ctx.register(tm, sg.Cloud(bad), sg.Params(k=8, E=3))
+    assert e.value.code in (-2, -5)
+    # the context stays usable after errors
+    ctx.register(tm, rf, sg.Params(k=8, E=3))
+
+
+def test_largest_workload_force_sampled(sg, ctx):
+    """The depth-frame scene (g = a a s): one force evaluation at the identity
+    pose and at a perturbed pose, on sampled rows against the C oracle."""
+    pr = config5()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    a_t, mom_t = ctx.descriptors(tm, 16)
+    a_r, mom_r = ctx.descriptors(rf, 16)
+    prm = O.Params(p=1.0, g_mode=1, k=16, E=100)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=a_r.cpu().numpy().astype(np.float64),
+                     aY=a_t.cpu().numpy().astype(np.float64))
+    plan = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, sg.Params(p=1.0, g_mode=1, k=16, E=100))
+    rows = np.random.default_rng(5).choice(pr.M, 64, replace=False)
+    for t, pose in ((0, O.Pose.identity()), (50, O.Pose(1.02, rot_axis_angle([0, 1, 0], 8.0), np.array([0.1, 0, 0.05])))):
+        _, f = plan.force(sg.pose_from_srt(pose.s, pose.R, pose.t), t=t, want_wrench=False, want_f=True)
+        f = f.cpu().numpy().astype(np.float64)[rows]
+        f_o, _ = O.forces_c(pose.apply(pr.tmpl), S, O.G_schedule(t, 100), rows=rows)
+        e = np.linalg.norm(f - f_o) / np.linalg.norm(f_o)
+        print(f"scene force t={t}: sampled error {e:.1e}")
+        assert e <= F_TOL
+    plan.close()
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_tiny_clouds_vector_step_matches_oracle(sg, ctx, flags):
+    """Vector descriptors with fewer points than one row tile and one LDS
+    stage (both product forms)."""
+    pr = random_pair(19, 37, seed=8)
+    rng = np.random.default_rng(8)
+    aX = rng.random((37, 7)).astype(np.float32)
+    aY = rng.random((19, 7)).astype(np.float32)
+    prm = O.Params(p=1.0, k=16, E=10)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64))
+    so = O.step(pr.tmpl.astype(np.float64), S, 3)
+    gp = sg.Params(p=1.0, k=16, E=10, flags=flags)
+    _, wr, f = ctx.step_vec(sg.Cloud(pr.tmpl), _dt(aY), sg.Cloud(pr.ref), _dt(aX), _dt(_mom(pr.tmpl), torch.float64),
+                            _dt(_mom(pr.ref), torch.float64), gp, 3, sg.pose_identity(), want_wrench=True,
+                            want_f=True)
+    f = f.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(f - so.f) <= F_TOL * np.linalg.norm(so.f)
+    assert np.linalg.norm(wr.cpu().numpy()[0:3] - so.F) <= F_TOL * np.abs(so.f).sum()
