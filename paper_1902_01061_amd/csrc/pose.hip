@@ -20,20 +20,34 @@ __device__ inline double G_sched(const Derived& D, int t) {
   return 0.1 * D.G1 + 0.9 * D.G1 / (1.0 + exp(-(((double)t - 1.0) - 0.5 * D.E)));
 }
 
-// Sum of `n` wrench partial rows starting at `wpart` (fixed order); result in
-// W[0..12], valid for thread 0 only.
+// Sum of `n` wrench partial rows (WR_STRIDE doubles each) starting at
+// `wpart`, in a fixed order; the result W[0..12] is valid in thread 0 only.
+// The rows are read as one contiguous array: thread t always takes component
+// t % 16 (BT is a multiple of 64 and WR_STRIDE is 16) of rows t / 16,
+// t / 16 + BT / 16, ..., so each wave load is 512 contiguous bytes; the four
+// lanes of a wave that hold the same component are added by shuffles, then
+// the waves in order through LDS (lds: BT / 4 doubles).  Components 13..15
+// are padding and are summed but not used.
+template <int BT>
 __device__ inline void sum_partials(const double* __restrict__ wpart, int n, double* lds, double W[13]) {
-  double v[13];
+  static_assert(WR_STRIDE == 16 && BT % 64 == 0, "one component per lane");
+  double v = 0.0;
+  const int64_t total = (int64_t)n * WR_STRIDE;
+#pragma unroll 4
+  for (int64_t e = threadIdx.x; e < total; e += BT) v += wpart[e];
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane < 16) lds[w * 16 + lane] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
 #pragma unroll
-  for (int e = 0; e < 13; ++e) v[e] = 0.0;
-  for (int b = threadIdx.x; b < n; b += 256) {
-    const double* src = wpart + (int64_t)b * WR_STRIDE;
-#pragma unroll
-    for (int e = 0; e < 13; ++e) v[e] += src[e];
+    for (int e = 0; e < 13; ++e) {
+      double a = 0.0;
+      for (int ww = 0; ww < BT / 64; ++ww) a += lds[ww * 16 + e];
+      W[e] = a;
+    }
   }
-  block_sum<13, 256>(v, lds);
-#pragma unroll
-  for (int e = 0; e < 13; ++e) W[e] = v[e];
 }
 
 // The update itself (one thread).
@@ -132,13 +146,13 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
   }
 }
 
-__global__ __launch_bounds__(256) void update_kernel(const double* __restrict__ wpart, int nblk,
-                                                     const double* __restrict__ pose_in, double* __restrict__ pose_out,
-                                                     Derived* __restrict__ dv, int t, double G_fixed, int do_update,
-                                                     double* __restrict__ wrench_out, double* __restrict__ stats_row) {
-  __shared__ double lds[4 * 13];
+__global__ __launch_bounds__(1024) void update_kernel(const double* __restrict__ wpart, int nblk,
+                                                      const double* __restrict__ pose_in, double* __restrict__ pose_out,
+                                                      Derived* __restrict__ dv, int t, double G_fixed, int do_update,
+                                                      double* __restrict__ wrench_out, double* __restrict__ stats_row) {
+  __shared__ double lds[1024 / 4];
   double W[13];
-  sum_partials(wpart, nblk, lds, W);
+  sum_partials<1024>(wpart, nblk, lds, W);
   if (threadIdx.x == 0) pose_update(W, pose_in, pose_out, dv, t, G_fixed, do_update, wrench_out, stats_row);
 }
 
@@ -149,11 +163,11 @@ __global__ __launch_bounds__(256) void update_batch_kernel(const double* __restr
                                                            Derived* __restrict__ dvs, int t, int do_update,
                                                            double* __restrict__ energy_out, double* __restrict__ stats,
                                                            int E) {
-  __shared__ double lds[4 * 13];
+  __shared__ double lds[256 / 4];
   const int r = blockIdx.x;
   const RegDesc& g = regs[r];
   double W[13];
-  sum_partials(wpart + (int64_t)g.wslot0 * WR_STRIDE, g.n_items, lds, W);
+  sum_partials<256>(wpart + (int64_t)g.wslot0 * WR_STRIDE, g.n_items, lds, W);
   if (threadIdx.x == 0) {
     double* pose = poses + 13 * (int64_t)r;
     pose_update(W, pose, pose, dvs + r, t, 0.0, do_update, nullptr,
@@ -244,7 +258,7 @@ hipError_t launch_identity_pose(double* pose, hipStream_t st) {
 
 hipError_t launch_update(const double* wpart, int nblk, const double* pose_in, double* pose_out, Derived* dv, int t,
                          double G_fixed, int do_update, double* wrench_out, double* stats_row, hipStream_t st) {
-  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(256), 0, st, wpart, nblk, pose_in, pose_out, dv, t, G_fixed,
+  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(1024), 0, st, wpart, nblk, pose_in, pose_out, dv, t, G_fixed,
                      do_update, wrench_out, stats_row);
   return hipGetLastError();
 }
