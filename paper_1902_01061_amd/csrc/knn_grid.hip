@@ -23,14 +23,35 @@ struct GridInfo {
   float h;
   int dims[3];
   int ncells;
+  double ext[3];  // bounding-box extents (for re-sizing the cells)
 };
 
+// Cell counts per axis for cell size h, grown by 10 % steps until the grid
+// has at most max_cells cells.
+__device__ inline void grid_dims(GridInfo& G, double h, int max_cells) {
+  int d[3];
+  for (int it = 0; it < 200; ++it) {
+    long long tot = 1;
+    for (int a = 0; a < 3; ++a) {
+      d[a] = (int)fmin(1024.0, floor(G.ext[a] / h) + 1.0);
+      tot *= d[a];
+    }
+    if (tot <= max_cells) break;
+    h *= 1.1;
+  }
+  G.h = (float)h;
+  for (int a = 0; a < 3; ++a) G.dims[a] = d[a];
+  G.ncells = d[0] * d[1] * d[2];
+}
+
 constexpr int GQ_BT = 256;
+constexpr int KNN_RCAP = 2;  // shells a lane searches alone before handing its query to a wave
 constexpr int SCAN_B = 1024;
 
 __global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                           const float* __restrict__ Zc, int n, int max_cells,
-                                                          GridInfo* __restrict__ gi) {
+                                                          GridInfo* __restrict__ gi, int* __restrict__ far) {
+  if (threadIdx.x == 0) far[0] = 0;  // count of queries handed to the wave-per-query pass
   __shared__ float red[16][6];
   float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   for (int i = threadIdx.x; i < n; i += 1024) {
@@ -68,7 +89,10 @@ __global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restric
         s[j] = s[j + 1];
         s[j + 1] = t;
       }
+  // first guess: 2 points per cell of the bounding box (a volume); for
+  // surfaces grid_refine_kernel then shrinks the cells
   const double rho = 2.0;
+  for (int a = 0; a < 3; ++a) G.ext[a] = e[a];
   double h;
   if (s[2] > 1e-6 * s[0])
     h = cbrt(s[0] * s[1] * s[2] * rho / n);
@@ -77,19 +101,34 @@ __global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restric
   else
     h = s[0] * rho / n;
   if (!(h > 0) || !isfinite(h)) h = 1.0;
-  int d[3];
-  for (int it = 0; it < 200; ++it) {
-    long long tot = 1;
-    for (int a = 0; a < 3; ++a) {
-      d[a] = (int)fmin(1024.0, floor(e[a] / h) + 1.0);
-      tot *= d[a];
-    }
-    if (tot <= max_cells) break;
-    h *= 1.1;
-  }
-  G.h = (float)h;
-  for (int a = 0; a < 3; ++a) G.dims[a] = d[a];
-  G.ncells = d[0] * d[1] * d[2];
+  grid_dims(G, h, max_cells);
+  *gi = G;
+}
+
+// Second look at the cell size, from the first count: scans are surfaces
+// (often with dense clusters), whose occupied cells hold many more points
+// than the 2 per cell of a volume, and a query inside them meets hundreds of
+// candidates.  With mu the mean count of the occupied cells, the cell side
+// is scaled by sqrt(6 / mu) when mu > 6 (surface scaling: counts go with
+// the side squared), and left as it is for volume-like clouds.  The caller
+// counts again with the new grid.  (Measured on the scan clouds: queries in
+// their clusters dominate the search time at 2 points per cell.)
+__global__ __launch_bounds__(1024) void grid_refine_kernel(const int* __restrict__ counts, int n, int max_cells,
+                                                           GridInfo* __restrict__ gi) {
+  __shared__ int red[16];
+  const GridInfo G0 = *gi;
+  int occ = 0;
+  for (int c = threadIdx.x; c < G0.ncells; c += 1024) occ += counts[c] > 0;
+  for (int off = 32; off > 0; off >>= 1) occ += __shfl_xor(occ, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = occ;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  occ = 0;
+  for (int w = 0; w < 16; ++w) occ += red[w];
+  const double mu = (double)n / (double)max(occ, 1);
+  if (!(mu > 6.0)) return;
+  GridInfo G = G0;
+  grid_dims(G, (double)G0.h * sqrt(6.0 / mu), max_cells);
   *gi = G;
 }
 
@@ -188,53 +227,96 @@ __device__ inline void span_points(const float4* __restrict__ spts, int p0, int 
   }
 }
 
-// The points of shell r around cell c (the cells with max(|dx|, |dy|, |dz|)
-// = r) as contiguous spans of the cell-sorted point array.  The cells of one
-// (z, y) row are adjacent in that array, so a row on the shell's boundary is
-// one span (two index loads, however many cells) and a row inside the shell
-// contributes its two end cells.  Calls f(p0, p1) per span, in the order in
-// which visiting the cells one by one would meet the points; far queries
-// (outliers in empty space) thus touch about 3x fewer index words.
+// The points of row (dz, dy) of shell r around cell c (the cells with
+// max(|dx|, |dy|, |dz|) = r in that row) as contiguous spans of the
+// cell-sorted point array.  The cells of one (z, y) row are adjacent in that
+// array, so a row on the shell's boundary is one span (two index loads,
+// however many cells) and a row inside the shell contributes its two end
+// cells.  Up to two spans are handed to a single call site (one inlined copy
+// of the caller's per-candidate code), in the order in which visiting the
+// cells one by one would meet the points.
+template <class F>
+__device__ inline void row_spans(const int* __restrict__ starts, const GridInfo& G, const int c[3], int r, int dz,
+                                 int dy, F&& f) {
+  const int cz = c[2] + dz, cy = c[1] + dy;
+  if (cz < 0 || cz >= G.dims[2] || cy < 0 || cy >= G.dims[1]) return;
+  const int row = (cz * G.dims[1] + cy) * G.dims[0];
+  int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+  if (r == 0 || abs(dz) == r || abs(dy) == r) {
+    a0 = starts[row + max(0, c[0] - r)];
+    a1 = starts[row + min(G.dims[0] - 1, c[0] + r) + 1];
+  } else {
+    if (c[0] - r >= 0) {
+      a0 = starts[row + c[0] - r];
+      a1 = starts[row + c[0] - r + 1];
+    }
+    if (c[0] + r < G.dims[0]) {
+      b0 = starts[row + c[0] + r];
+      b1 = starts[row + c[0] + r + 1];
+    }
+  }
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int q0 = h ? b0 : a0, q1 = h ? b1 : a1;
+    if (q0 < q1) f(q0, q1);
+  }
+}
+
+// Every point of shell r, row by row; far queries (outliers in empty space)
+// touch about 3x fewer index words than cell by cell.
 template <class F>
 __device__ inline void shell_spans(const int* __restrict__ starts, const GridInfo& G, const int c[3], int r, F&& f) {
-  for (int dz = -r; dz <= r; ++dz) {
-    const int cz = c[2] + dz;
-    if (cz < 0 || cz >= G.dims[2]) continue;
-    for (int dy = -r; dy <= r; ++dy) {
-      const int cy = c[1] + dy;
-      if (cy < 0 || cy >= G.dims[1]) continue;
-      const int row = (cz * G.dims[1] + cy) * G.dims[0];
-      // up to two spans per row, handed to the single call site below (one
-      // inlined copy of the caller's per-candidate code)
-      int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-      if (r == 0 || abs(dz) == r || abs(dy) == r) {
-        a0 = starts[row + max(0, c[0] - r)];
-        a1 = starts[row + min(G.dims[0] - 1, c[0] + r) + 1];
-      } else {
-        if (c[0] - r >= 0) {
-          a0 = starts[row + c[0] - r];
-          a1 = starts[row + c[0] - r + 1];
-        }
-        if (c[0] + r < G.dims[0]) {
-          b0 = starts[row + c[0] + r];
-          b1 = starts[row + c[0] + r + 1];
-        }
-      }
-#pragma unroll 1
-      for (int h = 0; h < 2; ++h) {
-        const int q0 = h ? b0 : a0, q1 = h ? b1 : a1;
-        if (q0 < q1) f(q0, q1);
-      }
+  for (int dz = -r; dz <= r; ++dz)
+    for (int dy = -r; dy <= r; ++dy) row_spans(starts, G, c, r, dz, dy, f);
+}
+
+// After shell r has been searched: true when nothing outside the searched
+// cube can beat the current k-th key (or no cell lies outside it).  Margin:
+// 1e-3 of a cell for the face, 1e-5 relative for the float32 key; an
+// incomplete list (key NaN) never stops the search.
+__device__ inline bool shell_done(const GridInfo& G, const int c[3], const float qv[3], int r, float kth) {
+  double lb = INFINITY;
+  bool all = true;
+  for (int a = 0; a < 3; ++a) {
+    if (c[a] - r > 0) {
+      lb = fmin(lb, (double)qv[a] - ((double)G.lo[a] + (double)(c[a] - r) * (double)G.h));
+      all = false;
     }
+    if (c[a] + r < G.dims[a] - 1) {
+      lb = fmin(lb, ((double)G.lo[a] + (double)(c[a] + r + 1) * (double)G.h) - (double)qv[a]);
+      all = false;
+    }
+  }
+  if (all) return true;
+  const double lbs = lb - 1e-3 * (double)G.h;
+  return lbs > 0.0 && (double)kth * 1.00001 < lbs * lbs;
+}
+
+__device__ inline float key_of(uint64_t w) { return __uint_as_float((uint32_t)(w >> 32)); }
+
+// Sorted insertion of a 64-bit (float32 key bits << 32 | index) word into
+// L[0..KC): one compare and two selects per slot.
+template <int KC>
+__device__ inline void insert_key(uint64_t (&L)[KC], uint64_t key) {
+  uint64_t ck = key;
+#pragma unroll
+  for (int s = 0; s < KC; ++s) {
+    const uint64_t t = L[s];
+    const bool sw = ck < t;
+    L[s] = sw ? ck : t;
+    ck = sw ? t : ck;
   }
 }
 
 // Writes the k neighbour indices of every point (row = original index,
-// sorted by key; -1 where fewer than k finite points exist).
+// sorted by key; -1 where fewer than k finite points exist).  With a far
+// list, a query whose search is not finished after shell rcap (an outlier in
+// empty space, whose lane would otherwise sweep many cells alone and hold up
+// its wave) is appended to it instead, for grid_knn_far_kernel.
 template <int KC>
 __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
-                                                         const GridInfo* __restrict__ gi, int n, int k,
-                                                         int32_t* __restrict__ idx_out) {
+                                                         const GridInfo* __restrict__ gi, int n, int k, int rcap,
+                                                         int* __restrict__ far, int32_t* __restrict__ idx_out) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
   float4* buf = s_buf + threadIdx.x;
   const int t = blockIdx.x * GQ_BT + threadIdx.x;
@@ -247,11 +329,11 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
   for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
   // The running top k as sorted 64-bit keys (float32 key bits << 32 |
   // index): for keys >= 0 the bit pattern orders like the value, so one
-  // unsigned compare gives the (key, index) order and an insertion step is
-  // one compare and two 64-bit selects.  Slots [0, KC - k) hold the sentinel
-  // 0, which no candidate undercuts, so slot KC - 1 is always the k-th best;
-  // empty slots hold all ones (key NaN, index -1).  Candidates whose key is
-  // not below +inf (non-finite points, overflowing distances) never enter.
+  // unsigned compare gives the (key, index) order.  Slots [0, KC - k) hold
+  // the sentinel 0, which no candidate undercuts, so slot KC - 1 is always
+  // the k-th best; empty slots hold all ones (key NaN, index -1).
+  // Candidates whose key is not below +inf (non-finite points, overflowing
+  // distances) never enter.
   uint64_t L[KC];
 #pragma unroll
   for (int s = 0; s < KC; ++s) L[s] = (s < KC - k) ? 0ull : ~0ull;
@@ -262,41 +344,103 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
         const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
         const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
         const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
-        if (d2 < INFINITY && key < L[KC - 1]) {
-          uint64_t ck = key;
-#pragma unroll
-          for (int s = 0; s < KC; ++s) {
-            const uint64_t t = L[s];
-            const bool sw = ck < t;
-            L[s] = sw ? ck : t;
-            ck = sw ? t : ck;
-          }
-        }
+        if (d2 < INFINITY && key < L[KC - 1]) insert_key(L, key);
       });
     });
-    // distance from the query to any cell outside the searched cube
-    double lb = INFINITY;
-    bool all = true;
-    for (int a = 0; a < 3; ++a) {
-      if (c[a] - r > 0) {
-        lb = fmin(lb, (double)qv[a] - ((double)G.lo[a] + (double)(c[a] - r) * (double)G.h));
-        all = false;
-      }
-      if (c[a] + r < G.dims[a] - 1) {
-        lb = fmin(lb, ((double)G.lo[a] + (double)(c[a] + r + 1) * (double)G.h) - (double)qv[a]);
-        all = false;
-      }
+    if (shell_done(G, c, qv, r, key_of(L[KC - 1]))) break;
+    if (far && r >= rcap) {
+      far[1 + atomicAdd(far, 1)] = t;
+      return;
     }
-    if (all) break;
-    // margin: 1e-3 of a cell for the face, 1e-5 relative for the float32 key
-    const double lbs = lb - 1e-3 * (double)G.h;
-    if (lbs > 0.0 && (double)__uint_as_float((uint32_t)(L[KC - 1] >> 32)) * 1.00001 < lbs * lbs) break;
   }
   // static slot indices only (a runtime index would put L in scratch memory)
   const int64_t o = (int64_t)qi * k;
 #pragma unroll
   for (int s = 0; s < KC; ++s)
     if (s >= KC - k) idx_out[o + (s - (KC - k))] = (int32_t)(uint32_t)L[s];
+}
+
+// The queries grid_knn_kernel left unfinished, one wave per query (a
+// wave-uniform loop over the far list).  Lane l scans rows l, l + 64, ... of
+// each shell into its own sorted list of the KC best keys it has met (every
+// slot real, no sentinels); after the shell the wave merges the 64 lists into
+// the KC best of their union by KC rounds of a wave-wide minimum (keys are
+// unique, so exactly the lanes holding the minimum pop it, and duplicates of
+// a merged entry are popped together), and every lane continues from the
+// merged list.  The stopping test is grid_knn_kernel's on the merged k-th
+// key, so the neighbour list is the same exact one.
+template <int KC>
+__global__ __launch_bounds__(GQ_BT) void grid_knn_far_kernel(const float4* __restrict__ spts,
+                                                             const int* __restrict__ starts,
+                                                             const GridInfo* __restrict__ gi, int n, int k,
+                                                             const int* __restrict__ far,
+                                                             int32_t* __restrict__ idx_out) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  float4* buf = s_buf + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * GQ_BT + threadIdx.x) >> 6;
+  const int n_waves = (gridDim.x * GQ_BT) >> 6;
+  const int cnt = far[0];
+  const GridInfo G = *gi;
+  const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
+  for (int f = wave; f < cnt; f += n_waves) {
+    const int t = far[1 + f];
+    const float4 q = spts[t];
+    const int qi = __float_as_int(q.w);
+    const float qv[3] = {q.x, q.y, q.z};
+    int c[3];
+    for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
+    uint64_t L[KC];
+#pragma unroll
+    for (int s = 0; s < KC; ++s) L[s] = ~0ull;
+    for (int r = 0; r <= rmax; ++r) {
+      const int side = 2 * r + 1;
+      for (int row = lane; row < side * side; row += 64) {
+        row_spans(starts, G, c, r, row / side - r, row % side - r, [&](int p0, int p1) {
+          span_points(spts, p0, p1, buf, [&](const float4& P) {
+            const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
+            const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+            const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
+            if (d2 < INFINITY && key < L[KC - 1]) insert_key(L, key);
+          });
+        });
+      }
+      // merge the 64 lists: M collects the successive wave minima in order
+      uint64_t M[KC];
+#pragma unroll
+      for (int s = 0; s < KC; ++s) M[s] = ~0ull;
+#pragma unroll 1
+      for (int round = 0; round < KC; ++round) {
+        const uint64_t h = L[0];
+        uint64_t m = h;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const uint64_t o = __shfl_xor(m, off, 64);
+          m = o < m ? o : m;
+        }
+        const bool pop = h == m;
+#pragma unroll
+        for (int s = 0; s < KC - 1; ++s) L[s] = pop ? L[s + 1] : L[s];
+        L[KC - 1] = pop ? ~0ull : L[KC - 1];
+#pragma unroll
+        for (int s = 0; s < KC - 1; ++s) M[s] = M[s + 1];
+        M[KC - 1] = m;
+      }
+      float kth = 0.f;
+#pragma unroll
+      for (int s = 0; s < KC; ++s) {
+        L[s] = M[s];
+        if (s == k - 1) kth = key_of(M[s]);
+      }
+      if (shell_done(G, c, qv, r, kth)) break;
+    }
+    if (lane == 0) {
+      const int64_t o = (int64_t)qi * k;
+#pragma unroll
+      for (int s = 0; s < KC; ++s)
+        if (s < k) idx_out[o + s] = (int32_t)(uint32_t)L[s];
+    }
+  }
 }
 
 // Curvature from the neighbour lists (FP64 covariance, 1/k, centred).
@@ -361,6 +505,7 @@ size_t grid_knn_workspace(int n, int k) {
   add(sizeof(int) * ((size_t)nb + 1));     // block sums
   add(sizeof(float4) * (size_t)n);         // sorted points
   add(sizeof(int32_t) * (size_t)n * k);    // neighbour lists
+  add(sizeof(int) * ((size_t)n + 1));      // far-query list
   return b;
 }
 
@@ -375,6 +520,7 @@ struct GridBufs {
   int* bsum;
   float4* spts;
   int32_t* nbr;
+  int* far;  // [0]: count, [1..n]: sorted positions of the queries left to the wave-per-query pass
 };
 
 GridBufs carve_grid(void* ws, int n, int k) {
@@ -395,6 +541,7 @@ GridBufs carve_grid(void* ws, int n, int k) {
   B.bsum = (int*)take(sizeof(int) * ((size_t)nb + 1));
   B.spts = (float4*)take(sizeof(float4) * (size_t)n);
   B.nbr = (int32_t*)take(sizeof(int32_t) * (size_t)n * k);
+  B.far = (int*)take(sizeof(int) * ((size_t)n + 1));
   return B;
 }
 
@@ -403,7 +550,10 @@ hipError_t build_grid(const float* x, const float* y, const float* z, int n, con
   const int max_cells = grid_max_cells(n);
   const int nb = (max_cells + SCAN_B - 1) / SCAN_B;
   const dim3 gn((n + 255) / 256), b256(256);
-  hipLaunchKernelGGL(grid_setup_kernel, dim3(1), dim3(1024), 0, st, x, y, z, n, max_cells, B.gi);
+  hipLaunchKernelGGL(grid_setup_kernel, dim3(1), dim3(1024), 0, st, x, y, z, n, max_cells, B.gi, B.far);
+  if (hipError_t e = launch_fill_i(B.counts, max_cells, st)) return e;
+  hipLaunchKernelGGL(grid_count_kernel, gn, b256, 0, st, x, y, z, n, B.gi, B.cell_of, B.counts);
+  hipLaunchKernelGGL(grid_refine_kernel, dim3(1), dim3(1024), 0, st, B.counts, n, max_cells, B.gi);
   if (hipError_t e = launch_fill_i(B.counts, max_cells, st)) return e;
   if (hipError_t e = launch_fill_i(B.cursor, max_cells, st)) return e;
   hipLaunchKernelGGL(grid_count_kernel, gn, b256, 0, st, x, y, z, n, B.gi, B.cell_of, B.counts);
@@ -423,14 +573,22 @@ hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n
   int32_t* lists = idx_out ? idx_out : B.nbr;
   const dim3 gn((n + 255) / 256), b256(256);
   const dim3 gq((n + GQ_BT - 1) / GQ_BT), bq(GQ_BT);
-  if (k <= 8)
-    hipLaunchKernelGGL(grid_knn_kernel<8>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
-  else if (k <= 16)
-    hipLaunchKernelGGL(grid_knn_kernel<16>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
-  else if (k <= 24)
-    hipLaunchKernelGGL(grid_knn_kernel<24>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
-  else
-    hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, lists);
+  // pass 1: one lane per query up to shell KNN_RCAP; pass 2: one wave per
+  // query left over (a fixed grid of waves loops over the device-side list)
+  const dim3 gf(512);
+  if (k <= 8) {
+    hipLaunchKernelGGL(grid_knn_kernel<8>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<8>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+  } else if (k <= 16) {
+    hipLaunchKernelGGL(grid_knn_kernel<16>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<16>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+  } else if (k <= 24) {
+    hipLaunchKernelGGL(grid_knn_kernel<24>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<24>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+  } else {
+    hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<32>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+  }
   if (a_out) hipLaunchKernelGGL(curvature_kernel, gn, b256, 0, st, x, y, z, n, k, lists, a_out);
   return hipGetLastError();
 }
