@@ -389,20 +389,32 @@ def extra_scene(sg, ctx, cpu_rows: int):
              for t in range(E)]
     out["mixed_vs_fp32_pose_diff_per_iter"] = {"t0..4": diffs[:5], "t10": diffs[10], "t50": diffs[50],
                                                  "t99": diffs[99]}
-    # one-step force against the FP64 oracle at the identity pose (sampled rows)
+    # one-step force against the FP64 oracle (sampled rows) at the poses the
+    # FP32 registration reaches before iterations 0-4, 10, 50 and 99
     a_t, mom_t = ctx.descriptors(tm, 16)
     a_r, mom_r = ctx.descriptors(rf, 16)
     rows = np.random.default_rng(0).choice(pr.M, cpu_rows, replace=False)
     aX = a_r.cpu().numpy().astype(np.float64)
     aY = a_t.cpu().numpy().astype(np.float64)
     S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=1.0, g_mode=1, k=16, E=E), aX=aX, aY=aY)
-    G = O.G_schedule(0, E)
-    f_ora, _ = O.forces_c(pr.tmpl.astype(np.float64), S, G, rows=rows)
+    traj = res["fp32"][2]
+    steps = (0, 1, 2, 3, 4, 10, 50, 99)
+    poses = {t: (np.concatenate([[1.0], np.eye(3).reshape(-1), np.zeros(3)]) if t == 0 else traj[t - 1][14:27])
+             for t in steps}
+    f_ora = {}
+    for t in steps:
+        P = poses[t]
+        Yt = P[0] * pr.tmpl.astype(np.float64) @ P[1:10].reshape(3, 3).T + P[10:13]
+        f_ora[t], _ = O.forces_c(Yt, S, O.G_schedule(t, E), rows=rows)
     for name, flags in (("fp32", 0), ("mixed", 2)):
         plan = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=flags))
-        _, f = plan.force(sg.pose_identity(), t=0, want_wrench=False, want_f=True)
-        f = f.cpu().numpy().astype(np.float64)[rows]
-        out[name]["one_step_force_rel_err_vs_oracle"] = float(np.linalg.norm(f - f_ora) / np.linalg.norm(f_ora))
+        errs = {}
+        for t in steps:
+            pt = torch.as_tensor(poses[t], dtype=torch.float64, device="cuda")
+            _, f = plan.force(pt, t=t, want_wrench=False, want_f=True)
+            f = f.cpu().numpy().astype(np.float64)[rows]
+            errs[f"t{t}"] = float(np.linalg.norm(f - f_ora[t]) / np.linalg.norm(f_ora[t]))
+        out[name]["one_step_force_rel_err_vs_oracle"] = errs
         plan.close()
     out["oracle_rows_sampled"] = int(cpu_rows)
 
