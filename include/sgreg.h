@@ -155,9 +155,14 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
  *   (1/n_i, centred at their mean), 0 if its trace is 0, NaN if i has no
  *   member (a non-finite point).
  * count_out[n] (int32, nullable): n_i.
- * Every point is scanned: the cost is n^2 key evaluations whatever r2.
+ * The points are visited in Morton order in tiles of 256; a tile whose
+ * bounding box is provably farther than sqrt(r2) from a block of 64 queries
+ * is skipped, so the cost falls with r2 (n^2 key evaluations at most) and the
+ * counts are exactly those of the full scan.  Uses the context workspace
+ * (64 bytes per point and the radix sort's temporaries); the call is
+ * asynchronous on stream.
  * Errors: SGR_EINVAL if r2 is negative or not finite, or both outputs are
- * NULL. */
+ * NULL; SGR_ENOMEM if the workspace cannot grow. */
 int sgr_descriptors_radius(sgr_ctx* ctx, const sgr_cloud* c, float r2, float* a_out, int32_t* count_out,
                            sgr_stream_t stream);
 

@@ -419,12 +419,13 @@ struct SingleWs {
 };
 
 // kmax: largest k of a nearest-neighbour search the call makes (0: none).
-int carve_single(sgr_ctx* ctx, int M, int N, const sgr_params* prm, int kmax, SingleWs& w) {
+int carve_single(sgr_ctx* ctx, int M, int N, const sgr_params* prm, int kmax, SingleWs& w, bool radius) {
   const int pm = pmode_of(prm->p);
   w.T = ctx->tiles.pick(M, N, pm);
   w.TM = tiles_for(ctx, M, N, prm);
   w.nslot = std::max(force_shape(ctx, M, N, w.T, pm).slots, w.TM.nblk);
-  const size_t gbytes = kmax > 0 ? std::max(grid_knn_workspace(N, kmax), grid_knn_workspace(M, kmax)) : 0;
+  size_t gbytes = kmax > 0 ? std::max(grid_knn_workspace(N, kmax), grid_knn_workspace(M, kmax)) : 0;
+  if (radius) gbytes = std::max({gbytes, radius_desc_workspace(N), radius_desc_workspace(M)});
   for (int pass = 0; pass < 2; ++pass) {
     Carve c{pass ? ctx->ws : nullptr};
     w.aX = c.take<float>(N);
@@ -826,7 +827,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
   SingleWs w;
-  if (int e = carve_single(ctx, M, N, prm, prm->k, w)) return e;
+  if (int e = carve_single(ctx, M, N, prm, prm->k, w, false)) return e;
   HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, prm->k, w.aX, nullptr, w.gws, st));
   HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, prm->k, w.aY, nullptr, w.gws, st));
   HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, w.mom + 10, st));
@@ -848,7 +849,9 @@ int sgr_descriptors_radius(sgr_ctx* ctx, const sgr_cloud* c, float r2, float* a_
   if (!(r2 >= 0.0f) || !std::isfinite(r2)) return fail(SGR_EINVAL, "r2 must be finite and >= 0");
   if (!a_out && !count_out) return fail(SGR_EINVAL, "nothing to compute");
   HIPCHK(hipSetDevice(ctx->device));
-  HIPCHK(launch_radius_desc(c->x, c->y, c->z, (int)c->n, nullptr, 0.0, r2, a_out, count_out, (hipStream_t)stream));
+  if (int e = ensure_ws(ctx, radius_desc_workspace((int)c->n))) return e;
+  HIPCHK(launch_radius_desc(c->x, c->y, c->z, (int)c->n, nullptr, 0.0, r2, a_out, count_out, ctx->ws,
+                            (hipStream_t)stream));
   return SGR_OK;
 }
 
@@ -862,11 +865,13 @@ int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* r
   if (n_levels < 1 || n_levels > 64) return fail(SGR_EINVAL, "n_levels must be in [1, 64]");
   int64_t total = 0;
   int kmax = 0;
+  bool radius = false;
   for (int l = 0; l < n_levels; ++l) {
     const sgr_level& v = levels[l];
     if (v.iters < 1) return fail(SGR_EINVAL, "every level needs iters >= 1");
     if (!std::isfinite(v.radius_scale) || v.radius_scale < 0) return fail(SGR_EINVAL, "radius_scale must be >= 0");
     if (!std::isfinite(v.sigma_scale) || !(v.sigma_scale > 0)) return fail(SGR_EINVAL, "sigma_scale must be > 0");
+    radius |= v.radius_scale > 0;
     if (v.radius_scale == 0) {
       if (v.k < 1 || v.k > 32) return fail(SGR_EINVAL, "a kNN level needs k in [1, 32]");
       if (tmpl->n < v.k || ref->n < v.k) return fail(SGR_EINVAL, "a cloud has fewer points than a level's k");
@@ -879,7 +884,7 @@ int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* r
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
   SingleWs w;
-  if (int e = carve_single(ctx, M, N, prm, kmax, w)) return e;
+  if (int e = carve_single(ctx, M, N, prm, kmax, w, radius)) return e;
   if ((int)ctx->gcp.size() < n_levels) ctx->gcp.resize(n_levels);
   HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, w.mom + 10, st));
   HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, w.mom, st));
@@ -889,8 +894,8 @@ int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* r
     const sgr_level& v = levels[l];
     if (v.radius_scale > 0) {
       const double s2 = v.radius_scale * v.radius_scale;
-      HIPCHK(launch_radius_desc(ref->x, ref->y, ref->z, N, w.mom + 10, s2, 0.f, w.aX, nullptr, st));
-      HIPCHK(launch_radius_desc(tmpl->x, tmpl->y, tmpl->z, M, w.mom, s2, 0.f, w.aY, nullptr, st));
+      HIPCHK(launch_radius_desc(ref->x, ref->y, ref->z, N, w.mom + 10, s2, 0.f, w.aX, nullptr, w.gws, st));
+      HIPCHK(launch_radius_desc(tmpl->x, tmpl->y, tmpl->z, M, w.mom, s2, 0.f, w.aY, nullptr, w.gws, st));
     } else {
       HIPCHK(launch_grid_knn(ref->x, ref->y, ref->z, N, v.k, w.aX, nullptr, w.gws, st));
       HIPCHK(launch_grid_knn(tmpl->x, tmpl->y, tmpl->z, M, v.k, w.aY, nullptr, w.gws, st));

@@ -202,9 +202,11 @@ hipError_t launch_normal_hist(const float* x, const float* y, const float* z, in
 // Curvature of the radius neighbourhood of every point: members have float32
 // key <= r2, where r2 = (float)(scale2 * mom[9]) when mom is given (mom[9] =
 // largest covariance eigenvalue, as launch_moments writes it), else r2_in.
-// a_out and cnt_out (member counts) may each be nullptr.
+// a_out and cnt_out (member counts) may each be nullptr.  ws: at least
+// radius_desc_workspace(n) bytes (Morton-ordered copy, tile boxes, sort).
+size_t radius_desc_workspace(int n);
 hipError_t launch_radius_desc(const float* x, const float* y, const float* z, int n, const double* mom, double scale2,
-                              float r2_in, float* a_out, int32_t* cnt_out, hipStream_t st);
+                              float r2_in, float* a_out, int32_t* cnt_out, void* ws, hipStream_t st);
 hipError_t launch_prepare(const float* aX, const float* wX, int64_t N, const float* aY, const float* mY, int64_t M,
                           const double* mom_t, const double* mom_r, const PrepParams& P, Derived* out, hipStream_t st);
 hipError_t launch_pack_ref(const float* x, const float* y, const float* z, const float* aX, const float* wX, int64_t N,

@@ -76,6 +76,35 @@ def test_radius_descriptors_edge_cases(sg, ctx):
     _check(sg, ctx, P[:37], 1.0)
 
 
+def test_radius_descriptors_tile_skipping(sg, ctx):
+    """Cases aimed at the tile test, which skips a tile of 64 Morton-ordered
+    points when its box is farther than r from the box of a block's queries:
+    it must never skip a member."""
+    rng = np.random.default_rng(11)
+    # offsets of 1e-30: every key underflows to 0 in float32, so with r2 = 0
+    # every point is a member of every neighbourhood, across all 16 tiles
+    T = (rng.normal(size=(1024, 3)) * 1e-30).astype(np.float32)
+    a, cnt = _check(sg, ctx, T, 0.0)
+    assert (cnt == 1024).all()
+    # a second such cluster 1e-20 away: keys of about 1e-40 are subnormal,
+    # not 0, so the clusters stay apart
+    T2 = np.concatenate([T, (rng.normal(size=(600, 3)) * 1e-30 + 1e-20).astype(np.float32)])
+    _, cnt = _check(sg, ctx, T2, 0.0)
+    assert sorted(set(cnt.tolist())) == [600, 1024]
+    # eight separated blobs: most tiles are skipped; r2 reaches across a
+    # blob but not between blobs
+    ctr = np.array([[i, j, k] for i in (0, 50) for j in (0, 50) for k in (0, 50)], np.float32)
+    B = (ctr[rng.integers(0, 8, 4000)] + rng.normal(size=(4000, 3)) * 2.0).astype(np.float32)
+    _check(sg, ctx, B, 4.0)
+    _check(sg, ctx, B, 400.0)
+    # an integer lattice with r2 = 1 and 2: many members lie exactly on the
+    # threshold, in other tiles than their query
+    g = np.stack(np.meshgrid(np.arange(16), np.arange(16), np.arange(8)), -1).reshape(-1, 3).astype(np.float32)
+    for r2 in (1.0, 2.0):
+        a, cnt = _check(sg, ctx, g[rng.permutation(len(g))], r2)
+        assert cnt.max() == (7 if r2 == 1.0 else 19)
+
+
 def test_radius_descriptors_full_size_sampled(sg, ctx):
     """The scan-sized reference (36 000 points) with the paper's radius
     sqrt(lambda_max): sampled rows against the oracle."""
