@@ -321,8 +321,8 @@ def extra_vector(sg, ctx, E: int, k: int, D: int = 16):
     """Vector shape descriptors on the workload pair: the soft histograms of
     normals (D bins) of both clouds, then the registration whose pair
     exponents are a contraction on the matrix cores, in its two forms: split
-    f16 (three 16x16x32 f16 products per 16 x 16 block, K = 32; peak 2.5
-    PFLOP/s) and FP32 products (K = 4 ceil((D + 2) / 4); peak 157.3
+    f16 (heads and tails as one contraction of length 3 (D + 2), two 16x16x32
+    f16 instructions per 16 x 16 block for D = 16; peak 2.5 PFLOP/s) and FP32 products (K = 4 ceil((D + 2) / 4); peak 157.3
     TFLOP/s).  Matrix rate = matrix flops of all pairs of all iterations /
     registration time: a lower bound, since the time includes set-up and
     updates."""
@@ -341,7 +341,7 @@ def extra_vector(sg, ctx, E: int, k: int, D: int = 16):
     d_ms = (time.perf_counter() - t0) * 1e3
     out = {"D": D, "M": pr.M, "N": pr.N, "iterations": E, "descriptors_ms_both_clouds": d_ms}
     pairs = pr.M * pr.N * E
-    for form, flags, fpp, peak in (("split_f16", 0, 3 * 2 * 32, 2500.0),
+    for form, flags, fpp, peak in (("split_f16", 0, 2 * 32 * ((3 * (D + 2) + 31) // 32), 2500.0),
                                    ("fp32", 4, 2 * 4 * ((D + 2 + 3) // 4), 157.3)):
         prm = sg.Params(p=1.0, k=k, E=E, flags=flags)
         pose = sg.pose_identity()

@@ -212,8 +212,9 @@ int sgr_descriptors_hn(sgr_ctx* ctx, const sgr_cloud* c, int k, int D, float* h_
  * sigma^2 = mean_j |a_j - abar|^2 over the reference (abar its mean; the std
  * of the scalar case when D = 1).  The similarity exponents of all pairs are
  * one dense contraction on the matrix cores: by default each entry of the
- * standardised operands is split into an f16 head and tail and three f16
- * products are accumulated in FP32 (about 2^-22 relative per product); FP32
+ * standardised operands is split into an f16 head and tail, and head.head +
+ * head.tail + tail.head is one f16 contraction of length 3 (D + 2)
+ * accumulated in FP32 (about 2^-22 relative per product); FP32
  * products (flags bit 2, and automatically when a standardised descriptor
  * lies more than about 140 spreads from the mean, beyond the f16 range) are
  * about 2^-24.  The set-up synchronises the stream once to make that choice.

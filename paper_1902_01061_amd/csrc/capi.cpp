@@ -542,9 +542,10 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
     Carve c{pass ? ctx->ws : nullptr};
     w.dv = c.take<Derived>(1);
     w.vd = c.take<double>(35);
-    // rows of K floats (FP32 form) or 64 halves = 32 floats (split f16)
-    w.At = c.take<float>((size_t)vforce_pad_rows(M) * std::max(w.K, 32));
-    w.Bt = c.take<float>((size_t)vforce_pad_refs(N) * std::max(w.K, 32));
+    // rows of K floats (FP32 form) or vforce_half_K(D) halves (split f16)
+    const size_t row_words = (size_t)std::max(w.K, vforce_half_K(D) / 2);
+    w.At = c.take<float>((size_t)vforce_pad_rows(M) * row_words);
+    w.Bt = c.take<float>((size_t)vforce_pad_refs(N) * row_words);
     w.ref4 = c.take<float4>((size_t)vforce_pad_refs(N));
     w.wpart = c.take<double>((size_t)w.slots * WR_STRIDE);
     w.fpart = with_f ? c.take<double>((size_t)w.n_chunks * M * 3) : nullptr;
@@ -570,7 +571,7 @@ int setup_vec(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, con
     HIPCHK(hipStreamSynchronize(st));
     w.half = vforce_half_ok(cmax);
   }
-  if (w.half) w.K = 32;
+  if (w.half) w.K = vforce_half_K(D);
   HIPCHK(launch_vpack(ref->x, ref->y, ref->z, a_r, ref->m, N, a_t, M, D, w.half, w.dv, w.vd, w.Bt, w.ref4, w.At,
                       st));
   return SGR_OK;

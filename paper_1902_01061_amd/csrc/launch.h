@@ -164,7 +164,7 @@ hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n
 hipError_t launch_moments(const float* x, const float* y, const float* z, int64_t n, double* out, hipStream_t st);
 // Force with vector descriptors (p = 1, g = s) on the matrix cores.
 struct VForceArgs {
-  const void* At;       // template augmented rows [Mpad]: K floats, or 64 halves (f16 head, tail)
+  const void* At;       // template augmented rows [Mpad]: K floats, or K halves (split f16)
   const void* Bt;       // reference augmented rows [Npad], same form
   const float4* ref4;   // reference x, y, z (centred at xbar), |x|^2 [Npad]
   const float* y0x;
@@ -174,12 +174,15 @@ struct VForceArgs {
   const double* pose;
   const Derived* dv;
   int M, N, K, n_chunks, t;
-  bool half;            // split-f16 rows and instructions (K = 32)
+  bool half;            // split-f16 rows and instructions (K = vforce_half_K(D))
   double G;             // > 0 overrides eq. 12
   double* wpart;        // [n_iblk * n_chunks][WR_STRIDE]
   double* fpart;        // [n_chunks][M][3] (WF only)
 };
 int vforce_K(int D);
+// Halves per split-f16 row: the contraction [h, h, l] . [h, l, h] of length
+// 3 (D + 2), padded to whole 16x16x32 instructions.
+int vforce_half_K(int D);
 int vforce_pad_rows(int M);
 int vforce_pad_refs(int N);
 int vforce_n_iblk(int M);
@@ -189,7 +192,8 @@ int vforce_chunks(int M, int N, int n_cu);
 hipError_t launch_vprep(const float* aX, int64_t N, const float* aY, int64_t M, int D, double sigma, Derived* dv,
                         double* vd, hipStream_t st);
 bool vforce_half_ok(double cmax);
-// Rows: K floats each (half = false) or 64 halves each (half = true).
+// Rows: vforce_K(D) floats each (half = false) or vforce_half_K(D) halves
+// each (half = true).
 hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const float* aX, const float* wX, int N,
                         const float* aY, int M, int D, bool half, const Derived* dv, const double* vd, void* Bt,
                         float4* ref4, void* At, hipStream_t st);

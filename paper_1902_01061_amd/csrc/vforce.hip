@@ -12,9 +12,12 @@
 // order one), and c_ij = exp2(At_i . Bt_j) for a 16 x 16 block of pairs
 // comes from the matrix cores in one of two forms:
 //  - split f16 (default): every entry is split into an f16 head and an f16
-//    tail (x = h + l + O(2^-22 |x|)), and h.h + h.l + l.h, three 16x16x32
-//    f16 instructions with FP32 accumulation (tails first), give the dot
-//    product to about 2^-22 of the size of its terms, K = 32;
+//    tail (x = h + l + O(2^-22 |x|)), and h.h + h.l + l.h gives the dot
+//    product to about 2^-22 of the size of its terms.  The three products
+//    are one contraction of length 3E (E = D + 2 entries per row): template
+//    rows [h, h, l], reference rows [h, l, h], zero-padded to 32 NB halves,
+//    NB = ceil(3E / 32) 16x16x32 f16 instructions with FP32 accumulation,
+//    the last block (all tails) first: 2 instructions for D = 16;
 //  - FP32: K/4 FP32 16x16x4 instructions, K = 4 ceil((D + 2) / 4); used when
 //    an entry would leave the f16 range (a descriptor more than about 140
 //    spreads from the mean) or when the caller asks for it.
@@ -121,16 +124,20 @@ __global__ __launch_bounds__(1024) void vprep_kernel(const float* __restrict__ a
 //   At_i = [2 log2(e) c_i, -log2(e) |c_i|^2, 1, 0...],
 //   Bt_j = [c_j, 1, lw_j - log2(e) |c_j|^2, 0...],
 // FP64 arithmetic, then either rounded once to FP32 (K entries per row) or
-// split into f16 head and tail (64 halves per row: 32 heads, then 32
-// tails).  Rows j >= N of the reference are zero-weight padding (exponent
-// -30000: exp2 gives 0, and the value is an f16 head with zero tail); rows
-// i >= M of the template are harmless padding (their sums are dropped).
-__device__ inline void put_entry(void* row, int c, double x, bool half) {
+// split into f16 head h and tail l and laid out as one contraction of length
+// 3E (K = 32 ceil(3E / 32) halves per row, E = D + 2): template [h, h, l],
+// reference [h, l, h].  Rows j >= N of the reference are zero-weight padding
+// (exponent -30000: exp2 gives 0, and the value is an f16 head with zero
+// tail); rows i >= M of the template are harmless padding (their sums are
+// dropped).
+__device__ inline void put_entry(void* row, int c, double x, bool half, int E, bool tmpl) {
   if (half) {
     _Float16* h = reinterpret_cast<_Float16*>(row);
     const _Float16 hi = (_Float16)x;
+    const _Float16 lo = (_Float16)(x - (double)hi);
     h[c] = hi;
-    h[32 + c] = (_Float16)(x - (double)hi);
+    h[E + c] = tmpl ? hi : lo;
+    h[2 * E + c] = tmpl ? lo : hi;
   } else {
     reinterpret_cast<float*>(row)[c] = (float)x;
   }
@@ -145,47 +152,48 @@ __global__ __launch_bounds__(256) void vpack_kernel(const float* __restrict__ X,
                                                     float4* __restrict__ ref4, void* __restrict__ At) {
   const int r = blockIdx.x * 256 + threadIdx.x;
   const double isig = 1.0 / vd[32];
-  const int Kr = half ? 32 : K;                        // entries per row
+  const int E = D + 2;  // entries per augmented row
   // exponent of zero-weight rows: exp2 of it is 0, and it is an f16 value
   // (the f16 form is only chosen when every other entry stays below 30000)
   const double pad_exp = half ? -30000.0 : -1e30;
-  const size_t rb = half ? 64 * sizeof(_Float16) : (size_t)K * sizeof(float);  // bytes per row
+  // K halves (split f16) or K floats per row
+  const size_t rb = half ? (size_t)K * sizeof(_Float16) : (size_t)K * sizeof(float);
   if (r < Npad) {
     void* b = reinterpret_cast<char*>(Bt) + (size_t)r * rb;
-    for (int c = 0; c < Kr; ++c) put_entry(b, c, 0.0, half);
+    for (size_t w = 0; w < rb / 4; ++w) reinterpret_cast<uint32_t*>(b)[w] = 0u;
     if (r < N) {
       double n2 = 0.0;
       for (int c = 0; c < D; ++c) {
         const double e = ((double)aX[(int64_t)r * D + c] - vd[c]) * isig;
-        put_entry(b, c, e, half);
+        put_entry(b, c, e, half, E, false);
         n2 += e * e;
       }
       const double lw = wX ? log2((double)wX[r]) : 0.0;
-      put_entry(b, D, 1.0, half);
-      put_entry(b, D + 1, fmax(lw - LOG2E * n2, pad_exp), half);
+      put_entry(b, D, 1.0, half, E, false);
+      put_entry(b, D + 1, fmax(lw - LOG2E * n2, pad_exp), half, E, false);
       const Derived& Dd = *dv;
       const float x = (float)((double)X[r] - Dd.xbar[0]), y = (float)((double)Y[r] - Dd.xbar[1]),
                   z = (float)((double)Zc[r] - Dd.xbar[2]);
       ref4[r] = make_float4(x, y, z, (float)((double)x * x + (double)y * y + (double)z * z));
     } else {
-      put_entry(b, D, 1.0, half);
-      put_entry(b, D + 1, pad_exp, half);
+      put_entry(b, D, 1.0, half, E, false);
+      put_entry(b, D + 1, pad_exp, half, E, false);
       ref4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   }
   if (r < Mpad) {
     void* a = reinterpret_cast<char*>(At) + (size_t)r * rb;
-    for (int c = 0; c < Kr; ++c) put_entry(a, c, 0.0, half);
+    for (size_t w = 0; w < rb / 4; ++w) reinterpret_cast<uint32_t*>(a)[w] = 0u;
     if (r < M) {
       double n2 = 0.0;
       for (int c = 0; c < D; ++c) {
         const double e = ((double)aY[(int64_t)r * D + c] - vd[c]) * isig;
-        put_entry(a, c, 2.0 * LOG2E * e, half);
+        put_entry(a, c, 2.0 * LOG2E * e, half, E, true);
         n2 += e * e;
       }
-      put_entry(a, D, -LOG2E * n2, half);
+      put_entry(a, D, -LOG2E * n2, half, E, true);
     }
-    put_entry(a, D + 1, 1.0, half);
+    put_entry(a, D + 1, 1.0, half, E, true);
   }
 }
 
@@ -196,8 +204,8 @@ __device__ inline double G_of(const Derived& D, int t) {
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 // H = false: FP32 rows of K = 4 VK entries, K/4 16x16x4 FP32 instructions.
-// H = true: f16 head/tail rows (64 halves), three 16x16x32 f16 instructions;
-// VK is unused.  Lane layouts (checked on the device): 16x16x4 f32 takes
+// H = true: split-f16 rows of K = 32 VK halves, VK 16x16x32 f16
+// instructions.  Lane layouts (checked on the device): 16x16x4 f32 takes
 // A[i = lane % 16][k = lane / 16] and B[k = lane / 16][j = lane % 16];
 // 16x16x32 f16 takes A[i = lane % 16][k = 8 (lane / 16) + e] and
 // B[k = 8 (lane / 16) + e][j = lane % 16], e = 0..7; both return
@@ -208,11 +216,12 @@ __global__ __launch_bounds__(VF_BT)
 __attribute__((amdgpu_waves_per_eu(SGR_VF_WAVES, SGR_VF_WAVES)))
 #endif
 void vforce_kernel(VForceArgs A) {
-  constexpr int K = H ? 32 : 4 * VK;
+  constexpr int K = H ? 32 * VK : 4 * VK;  // halves (H) or floats per row
+  constexpr int RW = H ? 16 * VK : K;       // 4-byte words per row
   // LDS words per staged reference row: FP32 rows use bt_stride(K); f16 rows
-  // (32 words) are padded to 36 words so that a 16-byte read per lane
-  // (16 rows x 4 quarter-rows) spreads over the banks
-  constexpr int KS = H ? 36 : bt_stride(K);
+  // (16 VK words) get 4 more, so that the 16-byte reads of one instruction
+  // (16 rows x 4 quarter-blocks) start on 64 distinct banks
+  constexpr int KS = H ? RW + 4 : bt_stride(K);
   constexpr int NQ = WU ? 5 : 4;
   constexpr int LDS_B = VF_TJ * KS > NQ * VF_ROWS ? VF_TJ * KS : NQ * VF_ROWS;  // tile, then the row sums
   __shared__ __attribute__((aligned(16))) float s_B[LDS_B];
@@ -229,14 +238,14 @@ void vforce_kernel(VForceArgs A) {
   const int j1 = (int)((int64_t)(chunk + 1) * n_t / A.n_chunks) * VF_TJ;
 
   float areg[VF_TI][H ? 1 : VK];
-  v8h ahi[H ? VF_TI : 1], alo[H ? VF_TI : 1];
+  v8h ah[H ? VF_TI : 1][H ? VK : 1];
   if constexpr (H) {
     const _Float16* At = reinterpret_cast<const _Float16*>(A.At);
 #pragma unroll
     for (int r = 0; r < VF_TI; ++r) {
-      const _Float16* row = At + (int64_t)(row0 + 16 * r + col) * 64;
-      ahi[r] = *reinterpret_cast<const v8h*>(row + 8 * kq);
-      alo[r] = *reinterpret_cast<const v8h*>(row + 32 + 8 * kq);
+      const _Float16* row = At + (int64_t)(row0 + 16 * r + col) * K;
+#pragma unroll
+      for (int k = 0; k < VK; ++k) ah[r][k] = *reinterpret_cast<const v8h*>(row + 32 * k + 8 * kq);
     }
   } else {
     const float* At = reinterpret_cast<const float*>(A.At);
@@ -256,8 +265,6 @@ void vforce_kernel(VForceArgs A) {
   for (int base = j0; base < j1; base += VF_TJ) {
     __syncthreads();
     {
-      // a staged row is RW words: K FP32 entries, or 64 halves = 32 words
-      constexpr int RW = H ? 32 : K;
       const float* Bt = reinterpret_cast<const float*>(A.Bt);
       for (int e = threadIdx.x; e < VF_TJ * (RW / 4); e += VF_BT) {
         const int jj = e / (RW / 4), s = e % (RW / 4);
@@ -271,10 +278,10 @@ void vforce_kernel(VForceArgs A) {
     for (int c = 0; c < VF_TJ / 16; ++c) {
       const int jl = 16 * c + col;
       float breg[H ? 1 : VK];
-      v8h bhi, blo;
+      v8h bh[H ? VK : 1];
       if constexpr (H) {
-        bhi = *reinterpret_cast<const v8h*>(&s_B[jl * KS + 4 * kq]);
-        blo = *reinterpret_cast<const v8h*>(&s_B[jl * KS + 16 + 4 * kq]);
+#pragma unroll
+        for (int k = 0; k < VK; ++k) bh[k] = *reinterpret_cast<const v8h*>(&s_B[jl * KS + 16 * k + 4 * kq]);
       } else {
 #pragma unroll
         for (int s = 0; s < VK; ++s) breg[s] = s_B[jl * KS + 4 * s + kq];
@@ -284,10 +291,10 @@ void vforce_kernel(VForceArgs A) {
       for (int r = 0; r < VF_TI; ++r) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
         if constexpr (H) {
-          // tails first: the small products are added before the large one
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo[r], bhi, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[r], blo, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi[r], bhi, acc, 0, 0, 0);
+          // the last block first: it holds only tail products, the first
+          // holds the head products, so small terms are added before large
+#pragma unroll
+          for (int k = VK - 1; k >= 0; --k) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r][k], bh[k], acc, 0, 0, 0);
         } else {
 #pragma unroll
           for (int s = 0; s < VK; ++s)
@@ -414,6 +421,7 @@ hipError_t launch_vk(const VForceArgs& A, bool wu, bool wf, hipStream_t st) {
 }  // namespace
 
 int vforce_K(int D) { return 4 * ((D + 2 + 3) / 4); }
+int vforce_half_K(int D) { return 32 * ((3 * (D + 2) + 31) / 32); }
 int vforce_pad_rows(int M) { return (M + VF_ROWS - 1) / VF_ROWS * VF_ROWS; }
 int vforce_pad_refs(int N) { return (N + VF_TJ - 1) / VF_TJ * VF_TJ; }
 int vforce_n_iblk(int M) { return (M + VF_ROWS - 1) / VF_ROWS; }
@@ -436,7 +444,7 @@ hipError_t launch_vprep(const float* aX, int64_t N, const float* aY, int64_t M, 
 hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const float* aX, const float* wX, int N,
                         const float* aY, int M, int D, bool half, const Derived* dv, const double* vd, void* Bt,
                         float4* ref4, void* At, hipStream_t st) {
-  const int Npad = vforce_pad_refs(N), Mpad = vforce_pad_rows(M), K = vforce_K(D);
+  const int Npad = vforce_pad_refs(N), Mpad = vforce_pad_rows(M), K = half ? vforce_half_K(D) : vforce_K(D);
   const int rows = std::max(Npad, Mpad);
   hipLaunchKernelGGL(vpack_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, X, Y, Z, aX, wX, N, Npad,
                      aY, M, Mpad, D, K, half, dv, vd, Bt, ref4, At);
@@ -444,7 +452,14 @@ hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const fl
 }
 
 hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st) {
-  if (A.half) return launch_vk<1, true>(A, wu, wf, st);
+  if (A.half) {
+    switch (A.K / 32) {
+      case 1: return launch_vk<1, true>(A, wu, wf, st);
+      case 2: return launch_vk<2, true>(A, wu, wf, st);
+      case 3: return launch_vk<3, true>(A, wu, wf, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (A.K / 4) {
     case 1: return launch_vk<1, false>(A, wu, wf, st);
     case 2: return launch_vk<2, false>(A, wu, wf, st);

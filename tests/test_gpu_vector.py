@@ -110,11 +110,13 @@ def _errors(so, wr, f, Y, mY=None):
     (16, "uniform", False, 0.0, 0), (30, "clustered", True, 0.02, 0), (5, "uniform", True, 0.0, 0),
     (1, "clustered", False, 0.0, 0), (14, "clustered", False, 0.0, 0),
     (16, "uniform", False, 0.0, 4), (30, "clustered", True, 0.02, 4), (5, "uniform", True, 0.0, 4),
-    (9, "extreme", True, 0.0, 0)])
+    (9, "extreme", True, 0.0, 0), (19, "uniform", True, 0.0, 0), (20, "clustered", False, 0.01, 0)])
 def test_step_vec_matches_oracle(sg, ctx, D, kind, masses, eps, flags):
     """flags 0: split-f16 products (the default), except for "extreme", whose
     descriptors lie 500 spreads from the mean and select FP32 products by
-    themselves; flags 4: FP32 products."""
+    themselves; flags 4: FP32 products.  The split form takes
+    ceil(3 (D + 2) / 32) 16x16x32 instructions: one for D = 1, 5; two for
+    D = 14, 16 and 19 (63 of 64 slots); three for D = 20 and 30."""
     pr, aX, aY = _vec_case(D, 40 + D, kind)
     rng = np.random.default_rng(D)
     wX = rng.uniform(0.5, 2.0, pr.N).astype(np.float32).astype(np.float64) if masses else None
