@@ -10,7 +10,10 @@ the registration including descriptors and the final status read-back).
 `roofline` describes the dominant kernel (the all-pairs force kernel),
 timed live with HIP events on the stream it is launched on.
 `cpu_baseline` times the FP64 C oracle on a bounded sample of the same
-force evaluation on the host cores.
+force evaluation on the host cores.  The extra leg `pose_independent_sums`
+is the same registration with flags bit 3 (the p = 1 pair sums formed once,
+O(M) per iteration); it is reported beside the headline, which keeps the
+per-iteration all-pairs work that the metric counts.
 """
 from __future__ import annotations
 
@@ -565,6 +568,20 @@ def main() -> int:
                         "pose_rmse_over_diameter": _pose_err(sg, pm_, pr),
                         "fp32_pose_rmse_over_diameter": pose_rmse / diam}
         log(f"mixed: {dtm * 1e3:.1f} ms/registration")
+        # p = 1: the pair weights do not depend on the pose, so the sums over
+        # the reference can be formed once per registration (flags bit 3)
+        prm_i = sg.Params(p=p, k=k, E=E, flags=8)
+        pi_ = ident.clone()
+        ctx.register(tm, rf, prm_i, pose=pi_)
+        dti, _ = _timed(lambda: (pi_.copy_(ident), ctx.register(tm, rf, prm_i, pose=pi_)), args.steps)
+        si, Ri, ti = sg.pose_to_srt(pi_)
+        Yall = pr.tmpl.astype(np.float64)
+        dpose = (si * Yall @ Ri.T + ti) - (s_ * Yall @ R_.T + t_)
+        out["pose_independent_sums"] = {
+            "ms_per_registration": dti * 1e3, "speedup_vs_all_pairs": ms_per_step / (dti * 1e3),
+            "pose_rmse_over_diameter": _pose_err(sg, pi_, pr),
+            "pose_difference_vs_all_pairs_over_diameter": float(np.sqrt(np.mean(np.sum(dpose ** 2, axis=1)))) / diam}
+        log(f"pose-independent sums: {dti * 1e3:.2f} ms/registration")
         out["batch"] = extra_batch(sg, ctx)
         log(f"batch: {out['batch']['ms_per_batch']:.1f} ms")
         out["adjoint"] = extra_adjoint(sg, ctx)

@@ -98,7 +98,18 @@ typedef struct {
                     the energy U is then reported as 0 except by the FP32 final
                     iteration of sgr_register; not for batch calls;
                     bit 2: vector descriptors (sgr_step_vec, sgr_register_vec)
-                    with FP32 matrix products instead of the split-f16 form. */
+                    with FP32 matrix products instead of the split-f16 form;
+                    bit 3: pose-independent pair sums (sgr_register and
+                    sgr_register_pyramid only; p = 1, g_mode 0 or 1, no mixed
+                    precision; SGR_EINVAL otherwise).  With p = 1 (eq. 11,
+                    h = 1) the pair weight of eq. 5 does not depend on the
+                    pose, so sum_j c_ij, sum_j c_ij x_j and sum_j c_ij |x_j|^2
+                    are formed once (one pass over all pairs, FP32 terms and
+                    FP64 sums) and every iteration costs O(M): f_i =
+                    -(G/Z) g_i (y_i sum_j c_ij - sum_j c_ij x_j).  Same
+                    results as the per-iteration all-pairs kernel up to
+                    rounding (workspace: about 48 bytes per template point
+                    per reference chunk). */
   double dt2;
 } sgr_params;
 

@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libsgreg.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["descriptors.hip", "force.hip", "pose.hip", "residual.hip", "adjoint.hip", "mixed.hip", "knn_grid.hip",
-           "sort.hip", "change.hip", "radius.hip", "vdesc.hip", "vforce.hip", "capi.cpp"]
+           "sort.hip", "change.hip", "radius.hip", "vdesc.hip", "vforce.hip", "psum.hip", "capi.cpp"]
 # Translation units whose results are integers decided by floating point
 # (neighbour ranks by the float32 key (dx*dx + dy*dy) + dz*dz, change flags)
 # are compiled without fused multiply-add, so that every operation is

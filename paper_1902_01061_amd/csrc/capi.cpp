@@ -87,7 +87,11 @@ int check_cloud(const sgr_cloud* c, const char* what) {
   return SGR_OK;
 }
 
-int check_params(const sgr_params* p) {
+constexpr int FLAG_PINV = 8;
+
+// allow_pinv: the caller (sgr_register, sgr_register_pyramid) implements
+// flags bit 3, the pose-independent pair sums of the p = 1 law.
+int check_params(const sgr_params* p, bool allow_pinv = false) {
   if (!p) return fail(SGR_EINVAL, "NULL params");
   if (!std::isfinite(p->p)) return fail(SGR_EINVAL, "p must be finite");
   if (p->p < 1.0 && !(p->eps > 0)) return fail(SGR_EINVAL, "p < 1 needs eps > 0 (the force would diverge at r = 0)");
@@ -95,7 +99,12 @@ int check_params(const sgr_params* p) {
   if (p->g_mode < 0 || p->g_mode > 2)
     return fail(SGR_EINVAL, "g_mode must be 0 (g = s), 1 (g = a a s) or 2 (g = 1, masses only)");
   if (!(p->G1 > 0) || !std::isfinite(p->G1)) return fail(SGR_EINVAL, "G1 must be positive");
-  if (p->flags & ~7) return fail(SGR_EINVAL, "unknown flag bits");
+  if (p->flags & ~15) return fail(SGR_EINVAL, "unknown flag bits");
+  if (p->flags & FLAG_PINV) {
+    if (!allow_pinv) return fail(SGR_EINVAL, "flags bit 3 applies to sgr_register and sgr_register_pyramid only");
+    if (p->p != 1.0 || p->g_mode > 1 || (p->flags & 2))
+      return fail(SGR_EINVAL, "flags bit 3 needs p = 1, g_mode 0 or 1 and no mixed precision");
+  }
   if (!std::isfinite(p->sigma) || !std::isfinite(p->eps) || p->eps < 0) return fail(SGR_EINVAL, "bad sigma/eps");
   if (!std::isfinite(p->dt2)) return fail(SGR_EINVAL, "bad dt2");
   return SGR_OK;
@@ -410,6 +419,9 @@ struct SingleWs {
   float* lw;
   double* wpart;
   char* gws;
+  double* ps_part;  // pose-independent pair sums (flags bit 3): per chunk, then reduced
+  double* ps_S;
+  int ps_chunks;
   int* perm;
   char* sws;
   float4* tm4;
@@ -421,9 +433,12 @@ struct SingleWs {
 // kmax: largest k of a nearest-neighbour search the call makes (0: none).
 int carve_single(sgr_ctx* ctx, int M, int N, const sgr_params* prm, int kmax, SingleWs& w, bool radius) {
   const int pm = pmode_of(prm->p);
+  const bool pinv = (prm->flags & FLAG_PINV) != 0;
   w.T = ctx->tiles.pick(M, N, pm);
   w.TM = tiles_for(ctx, M, N, prm);
   w.nslot = std::max(force_shape(ctx, M, N, w.T, pm).slots, w.TM.nblk);
+  if (pinv) w.nslot = std::max(w.nslot, pinv_blocks(M));
+  w.ps_chunks = pinv ? pinv_chunks(M, N, ctx->n_cu) : 0;
   size_t gbytes = kmax > 0 ? std::max(grid_knn_workspace(N, kmax), grid_knn_workspace(M, kmax)) : 0;
   if (radius) gbytes = std::max({gbytes, radius_desc_workspace(N), radius_desc_workspace(M)});
   for (int pass = 0; pass < 2; ++pass) {
@@ -440,6 +455,8 @@ int carve_single(sgr_ctx* ctx, int M, int N, const sgr_params* prm, int kmax, Si
     w.sws = c.take<char>(sort_perm_workspace(M, 1));
     w.tm4 = c.take<float4>(M);
     w.tmx = c.take<float2>(M);
+    w.ps_part = pinv ? c.take<double>((size_t)w.ps_chunks * M * 5) : nullptr;
+    w.ps_S = pinv ? c.take<double>((size_t)M * 5) : nullptr;
     if (!pass)
       if (int e = ensure_ws(ctx, c.off)) return e;
   }
@@ -454,6 +471,7 @@ int setup_single(const sgr_cloud* tmpl, const sgr_cloud* ref, const PrepParams& 
   HIPCHK(launch_pack_ref(ref->x, ref->y, ref->z, w.aX, ref->m, N, w.dv, w.ref4, w.lw, st));
   HIPCHK(launch_sort_perm(w.aY, M, w.perm, w.sws, st));
   HIPCHK(launch_pack_tmpl(tmpl->x, tmpl->y, tmpl->z, w.aY, tmpl->m, M, w.perm, w.dv, w.tm4, w.tmx, st));
+  if (w.ps_S) HIPCHK(launch_psum(w.tm4, M, w.ref4, w.lw, N, w.ps_chunks, w.ps_part, w.ps_S, st));
   return SGR_OK;
 }
 
@@ -475,7 +493,11 @@ int run_single_loop(sgr_ctx* ctx, GraphCache& gc, const sgr_cloud* tmpl, const s
       ForceArgs A{tmpl->x, tmpl->y, tmpl->z, w.aY, tmpl->m, w.ref4, w.lw, (const double*)inout, w.dv, M, N,
                   Tt.chunk_len, Tt.n_chunks, t, 0.0, w.wpart, nullptr, w.perm, w.tm4, w.tmx};
       int used = Tt.nblk;
-      if (mixed) {
+      if (w.ps_S) {
+        // p = 1 with the pair sums formed once by setup_single: O(M) per iteration
+        HIPCHK(launch_pinv(w.tm4, w.tmx, w.ps_S, M, (const double*)inout, w.dv, t, wu, w.wpart, s));
+        used = pinv_blocks(M);
+      } else if (mixed) {
         HIPCHK(launch_force_mixed(A, false, s));
       } else {
         const FLaunch L = force_shape(ctx, M, N, w.T, pm);
@@ -819,7 +841,7 @@ int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, cons
   if (!ctx || !inout) return fail(SGR_EINVAL, "NULL argument");
   if (int e = check_cloud(tmpl, "template")) return e;
   if (int e = check_cloud(ref, "reference")) return e;
-  if (int e = check_params(prm)) return e;
+  if (int e = check_params(prm, true)) return e;
   if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
   if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
   if (tmpl->n < prm->k || ref->n < prm->k) return fail(SGR_EINVAL, "a cloud has fewer points than k");
@@ -861,7 +883,7 @@ int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* r
   if (!ctx || !inout || !levels) return fail(SGR_EINVAL, "NULL argument");
   if (int e = check_cloud(tmpl, "template")) return e;
   if (int e = check_cloud(ref, "reference")) return e;
-  if (int e = check_params(prm)) return e;
+  if (int e = check_params(prm, true)) return e;
   if (int e = check_mixed(prm)) return e;
   if (n_levels < 1 || n_levels > 64) return fail(SGR_EINVAL, "n_levels must be in [1, 64]");
   int64_t total = 0;

@@ -203,6 +203,19 @@ size_t normal_hist_workspace(int n, int k);
 hipError_t launch_normal_hist(const float* x, const float* y, const float* z, int n, int k, int D, float* h_out,
                               void* ws, hipStream_t st);
 
+// Pose-independent pair sums of the p = 1 law: S[ip] = (sum_j c, sum_j c x_j
+// (3), sum_j c |x_j|^2) per template point in visiting order, c the pair
+// weight exp2(lw_j - (b_i - b_j)^2), from the packed template and reference;
+// part holds pinv_chunks(M, N, n_cu) * M * 5 doubles.  launch_pinv is the
+// per-iteration force from them: pinv_blocks(M) wrench partials in wpart
+// (the layout of the force kernel, for launch_update).
+int pinv_chunks(int M, int N, int n_cu);
+int pinv_blocks(int M);
+hipError_t launch_psum(const float4* tm4, int M, const float4* ref4, const float* lw, int N, int n_chunks,
+                       double* part, double* S, hipStream_t st);
+hipError_t launch_pinv(const float4* tm4, const float2* tmx, const double* S, int M, const double* pose,
+                       const Derived* dv, int t, bool wu, double* wpart, hipStream_t st);
+
 // Curvature of the radius neighbourhood of every point: members have float32
 // key <= r2, where r2 = (float)(scale2 * mom[9]) when mom is given (mom[9] =
 // largest covariance eigenvalue, as launch_moments writes it), else r2_in.
