@@ -388,6 +388,15 @@ def extra_scene(sg, ctx):
     def apply(row):
         s_, R_, t_ = row[14], row[15:24].reshape(3, 3), row[24:27]
         return s_ * sub @ R_.T + t_
+    # the same registration with the pair sums formed once (flags bit 3)
+    prm_i = sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=8)
+    ctx.register(tm, rf, prm_i)
+    dti, (pose_i, _) = _timed(lambda: ctx.register(tm, rf, prm_i))
+    s0, R0, t0 = sg.pose_to_srt(res["fp32"][1])
+    si, Ri, ti = sg.pose_to_srt(pose_i)
+    dpi = float(np.sqrt(np.mean(np.sum(((si * sub @ Ri.T + ti) - (s0 * sub @ R0.T + t0)) ** 2, 1)))) / diam
+    out["pose_independent_sums"] = {"ms_per_registration": dti * 1e3, "speedup_vs_fp32": res["fp32"][0] / dti,
+                                    "pose_difference_vs_fp32_over_diameter": dpi}
     diffs = [float(np.sqrt(np.mean(np.sum((apply(res["mixed"][2][t]) - apply(res["fp32"][2][t])) ** 2, 1)))) / diam
              for t in range(E)]
     out["mixed_vs_fp32_pose_diff_per_iter"] = {"t0..4": diffs[:5], "t10": diffs[10], "t50": diffs[50],
@@ -597,7 +606,8 @@ def main() -> int:
             f"fp32 {out['vector']['fp32']['ms_per_registration']:.1f} ms per registration")
         out["scene"] = extra_scene(sg, ctx)
         log(f"scene: fp32 {out['scene']['fp32']['ms_per_registration']:.1f} ms, "
-            f"mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms")
+            f"mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms, "
+            f"pose-independent sums {out['scene']['pose_independent_sums']['ms_per_registration']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(pr, E, k, args.cpu_seconds)
