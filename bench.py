@@ -175,13 +175,23 @@ def extra_batch(sg, ctx):
     ctx.multistart(tm, rf, prm, R0)
     dtm, (mposes, menergy, best) = _timed(lambda: ctx.multistart(tm, rf, prm, R0))
     start_err = [_pose_err(sg, mposes[s], ms_pr) for s in range(len(R0))]
+    # the same batch and sweep with the p = 1 pair sums formed once (flags bit 3)
+    prm_i = sg.Params(p=1.0, k=16, E=E, flags=8)
+    ctx.register_batch(tms, rfs, prm_i)
+    dti, (poses_i, _, _) = _timed(lambda: ctx.register_batch(tms, rfs, prm_i))
+    ctx.multistart(tm, rf, prm_i, R0)
+    dtmi, (mposes_i, _, best_i) = _timed(lambda: ctx.multistart(tm, rf, prm_i, R0))
+    dp = max(abs(_pose_err(sg, poses_i[r], pr) - errs[r]) for r, pr in enumerate(pairs))
     return {"registrations": len(pairs), "points_range": [min(p.N for p in pairs), max(p.N for p in pairs)],
             "iterations": E, "ms_per_batch": dt * 1e3, "pairs_per_s": pairs_total / dt,
             "pose_rmse_over_diameter_median": float(np.median(errs)),
             "multistart": {"starts": len(R0), "M": ms_pr.M, "N": ms_pr.N, "ms": dtm * 1e3,
                            "pairs_per_s": len(R0) * ms_pr.M * ms_pr.N * E / dtm, "best_start": best,
                            "best_pose_rmse_over_diameter": start_err[best],
-                           "min_pose_rmse_over_diameter": float(min(start_err))}}
+                           "min_pose_rmse_over_diameter": float(min(start_err))},
+            "pose_independent_sums": {"ms_per_batch": dti * 1e3, "speedup": dt / dti, "multistart_ms": dtmi * 1e3,
+                                      "multistart_speedup": dtm / dtmi, "multistart_best_start": best_i,
+                                      "max_pose_error_change_over_diameter": dp}}
 
 
 def extra_adjoint(sg, ctx):
@@ -592,7 +602,8 @@ def main() -> int:
             "pose_difference_vs_all_pairs_over_diameter": float(np.sqrt(np.mean(np.sum(dpose ** 2, axis=1)))) / diam}
         log(f"pose-independent sums: {dti * 1e3:.2f} ms/registration")
         out["batch"] = extra_batch(sg, ctx)
-        log(f"batch: {out['batch']['ms_per_batch']:.1f} ms")
+        log(f"batch: {out['batch']['ms_per_batch']:.1f} ms, pose-independent sums "
+            f"{out['batch']['pose_independent_sums']['ms_per_batch']:.1f} ms")
         out["adjoint"] = extra_adjoint(sg, ctx)
         log(f"adjoint: fwd {out['adjoint']['fwd_ms']:.3f} ms, bwd {out['adjoint']['bwd_ms']:.3f} ms")
         out["force_law"] = extra_force_law(sg, ctx, E, k)

@@ -89,8 +89,9 @@ int check_cloud(const sgr_cloud* c, const char* what) {
 
 constexpr int FLAG_PINV = 8;
 
-// allow_pinv: the caller (sgr_register, sgr_register_pyramid) implements
-// flags bit 3, the pose-independent pair sums of the p = 1 law.
+// allow_pinv: the caller (sgr_register, sgr_register_pyramid,
+// sgr_register_batch, sgr_multistart) implements flags bit 3, the
+// pose-independent pair sums of the p = 1 law.
 int check_params(const sgr_params* p, bool allow_pinv = false) {
   if (!p) return fail(SGR_EINVAL, "NULL params");
   if (!std::isfinite(p->p)) return fail(SGR_EINVAL, "p must be finite");
@@ -101,7 +102,9 @@ int check_params(const sgr_params* p, bool allow_pinv = false) {
   if (!(p->G1 > 0) || !std::isfinite(p->G1)) return fail(SGR_EINVAL, "G1 must be positive");
   if (p->flags & ~15) return fail(SGR_EINVAL, "unknown flag bits");
   if (p->flags & FLAG_PINV) {
-    if (!allow_pinv) return fail(SGR_EINVAL, "flags bit 3 applies to sgr_register and sgr_register_pyramid only");
+    if (!allow_pinv)
+      return fail(SGR_EINVAL, "flags bit 3 applies to sgr_register, sgr_register_pyramid, sgr_register_batch and "
+                              "sgr_multistart only");
     if (p->p != 1.0 || p->g_mode > 1 || (p->flags & 2))
       return fail(SGR_EINVAL, "flags bit 3 needs p = 1, g_mode 0 or 1 and no mixed precision");
   }
@@ -278,6 +281,19 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   };
   std::stable_sort(items.begin(), items.end(), [&](const int4& a, const int4& b) { return cost(a) > cost(b); });
   const int n_items = (int)items.size();
+  // flags bit 3 (p = 1): pair sums once, then one wrench slot per block of
+  // 256 template points in every iteration, described by regs_p
+  const bool pinv = (prm->flags & FLAG_PINV) != 0;
+  std::vector<int2> tblk;
+  std::vector<int> pslot0(B, 0), pslots(B, 0);
+  if (pinv)
+    for (int r = 0; r < B; ++r) {
+      pslot0[r] = (int)tblk.size();
+      pslots[r] = pinv_blocks((int)Ms[r]);
+      for (int b = 0; b < pslots[r]; ++b) tblk.push_back(make_int2(r, b));
+    }
+  const int n_tblk = (int)tblk.size();
+  const int n_slots = std::max(n_items, n_tblk);
 
   // workspace
   Carve cv{nullptr};
@@ -292,7 +308,7 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   cv.take<Derived>(B);
   cv.take<float4>(ref_total);
   cv.take<float>(ref_total);
-  cv.take<double>((size_t)n_items * WR_STRIDE);
+  cv.take<double>((size_t)n_slots * WR_STRIDE);
   cv.take<double>(B);
   int64_t perm_total = 0;
   for (int r = 0; r < B; ++r) perm_total += Ms[r];
@@ -301,6 +317,11 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   cv.take<float2>(perm_total);
   cv.take<int>(B + 1);
   cv.take<char>(sort_perm_workspace(perm_total, B));
+  if (pinv) {
+    cv.take<int2>(n_tblk);
+    cv.take<RegDesc>(B);
+    cv.take<double>((size_t)perm_total * 5);
+  }
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   CloudDesc* d_cds = w.take<CloudDesc>(ncl);
@@ -314,13 +335,16 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   Derived* d_dv = w.take<Derived>(B);
   float4* d_ref4 = w.take<float4>(ref_total);
   float* d_lw = w.take<float>(ref_total);
-  double* d_wpart = w.take<double>((size_t)n_items * WR_STRIDE);
+  double* d_wpart = w.take<double>((size_t)n_slots * WR_STRIDE);
   double* d_energy = w.take<double>(B);
   int* d_perm = w.take<int>(perm_total);
   float4* d_tm4 = w.take<float4>(perm_total);
   float2* d_tmx = w.take<float2>(perm_total);
   int* d_poff = w.take<int>(B + 1);
   char* d_sws = w.take<char>(sort_perm_workspace(perm_total, B));
+  int2* d_tblk = pinv ? w.take<int2>(n_tblk) : nullptr;
+  RegDesc* d_regs_p = pinv ? w.take<RegDesc>(B) : nullptr;
+  double* d_S = pinv ? w.take<double>((size_t)perm_total * 5) : nullptr;
 
   for (int c = 0; c < ncl; ++c)
     cds[c] = CloudDesc{in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, d_a + a_off[c], (int)in.clouds[c]->n, 0};
@@ -352,6 +376,16 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   HIPCHK(hipMemcpyAsync(d_regs, regs.data(), sizeof(RegDesc) * B, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_items, items.data(), sizeof(int4) * n_items, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_poff, poff.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, st));
+  std::vector<RegDesc> regs_p;
+  if (pinv) {
+    regs_p = regs;
+    for (int r = 0; r < B; ++r) {
+      regs_p[r].wslot0 = pslot0[r];
+      regs_p[r].n_items = pslots[r];
+    }
+    HIPCHK(hipMemcpyAsync(d_tblk, tblk.data(), sizeof(int2) * n_tblk, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_regs_p, regs_p.data(), sizeof(RegDesc) * B, hipMemcpyHostToDevice, st));
+  }
 
   // descriptors of every cloud in one brute-force launch: with hundreds of
   // small clouds a single launch keeps the chip busy, where one grid search
@@ -365,16 +399,21 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
     HIPCHK(launch_sort_perm_batch(d_regs, B, d_poff, perm_total, max_M, d_perm, d_sws, st));
     HIPCHK(launch_pack_tmpl_batch(d_regs, B, max_M, d_dv, st));
   }
+  if (pinv) HIPCHK(launch_psum_batch(d_regs, d_tblk, n_tblk, d_poff, d_ref4, d_lw, d_S, st));
   if (R0_multistart) HIPCHK(launch_init_multistart(R0_multistart, B, d_mom + 10 * in.tm_cloud[0], poses, st));
 
   const int grid = std::min(n_items, 8 * ctx->n_cu);
   auto loop = [&](hipStream_t s) -> int {
     for (int t = 0; t < prm->E; ++t) {
       const bool wu = stats != nullptr || t == prm->E - 1;
-      BatchArgs A{d_regs, d_items, n_items, d_ref4, d_lw, poses, d_dv, chunk_len, t, d_wpart};
-      HIPCHK(launch_force_batch(A, R, pm, wu, grid, s));
-      HIPCHK(launch_update_batch(d_wpart, d_regs, B, poses, d_dv, t, 1, t == prm->E - 1 ? d_energy : nullptr, stats,
-                                 prm->E, s));
+      if (pinv) {
+        HIPCHK(launch_pinv_batch(d_regs_p, d_tblk, n_tblk, d_poff, d_S, poses, d_dv, t, wu, d_wpart, s));
+      } else {
+        BatchArgs A{d_regs, d_items, n_items, d_ref4, d_lw, poses, d_dv, chunk_len, t, d_wpart};
+        HIPCHK(launch_force_batch(A, R, pm, wu, grid, s));
+      }
+      HIPCHK(launch_update_batch(d_wpart, pinv ? d_regs_p : d_regs, B, poses, d_dv, t, 1,
+                                 t == prm->E - 1 ? d_energy : nullptr, stats, prm->E, s));
     }
     return SGR_OK;
   };
@@ -1452,7 +1491,7 @@ int sgr_register_batch(sgr_ctx* ctx, int B, const sgr_cloud* tmpls, const sgr_cl
                        sgr_pose* poses, double* energy_out, double* stats, sgr_stream_t stream) {
   if (!ctx || !tmpls || !refs || !poses) return fail(SGR_EINVAL, "NULL argument");
   if (B < 1) return fail(SGR_EINVAL, "empty batch");
-  if (int e = check_params(prm)) return e;
+  if (int e = check_params(prm, true)) return e;
   if (is_mixed(prm)) return fail(SGR_EINVAL, "the batched form runs the FP32 force only");
   if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
   if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
@@ -1480,7 +1519,7 @@ int sgr_multistart(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, co
   if (S < 1) return fail(SGR_EINVAL, "no starts");
   if (int e = check_cloud(tmpl, "template")) return e;
   if (int e = check_cloud(ref, "reference")) return e;
-  if (int e = check_params(prm)) return e;
+  if (int e = check_params(prm, true)) return e;
   if (is_mixed(prm)) return fail(SGR_EINVAL, "the batched form runs the FP32 force only");
   if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
   if (prm->k < 1 || prm->k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");

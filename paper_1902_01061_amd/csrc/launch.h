@@ -215,6 +215,13 @@ hipError_t launch_psum(const float4* tm4, int M, const float4* ref4, const float
                        double* part, double* S, hipStream_t st);
 hipError_t launch_pinv(const float4* tm4, const float2* tmx, const double* S, int M, const double* pose,
                        const Derived* dv, int t, bool wu, double* wpart, hipStream_t st);
+// Batched forms: tblk lists (registration, block of 256 template points);
+// registration r's sums sit at template offset poff[r] of S.  regs_p is
+// regs with wslot0 / n_items describing one wrench slot per listed block.
+hipError_t launch_psum_batch(const RegDesc* regs, const int2* tblk, int n_tblk, const int* poff, const float4* ref4,
+                             const float* lw, double* S, hipStream_t st);
+hipError_t launch_pinv_batch(const RegDesc* regs_p, const int2* tblk, int n_tblk, const int* poff, const double* S,
+                             const double* poses, const Derived* dvs, int t, bool wu, double* wpart, hipStream_t st);
 
 // Curvature of the radius neighbourhood of every point: members have float32
 // key <= r2, where r2 = (float)(scale2 * mom[9]) when mom is given (mom[9] =

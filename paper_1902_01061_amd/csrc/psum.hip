@@ -30,23 +30,17 @@ namespace {
 constexpr int PS_BT = 256;
 constexpr int PS_NQ = 5;  // S0, S1 (3), S2
 
-__global__ __launch_bounds__(PS_BT) void psum_kernel(const float4* __restrict__ tm4, int M,
-                                                     const float4* __restrict__ ref4, const float* __restrict__ lw,
-                                                     int N, int chunk_len, double* __restrict__ part) {
-  __shared__ float4 s_x[PS_BT];
-  __shared__ float s_l[PS_BT], s_q[PS_BT];
-  const int n_iblk = (M + PS_BT - 1) / PS_BT;
-  const int iblk = blockIdx.x % n_iblk, chunk = blockIdx.x / n_iblk;
-  const int ip = iblk * PS_BT + threadIdx.x;
-  const float bi = ip < M ? tm4[ip].w : 0.f;
-  const int j0 = chunk * chunk_len, j1 = min(N, j0 + chunk_len);
-  double t[PS_NQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+// Sums of template point bi's pair weights over reference points [j0, j1)
+// into t (FP64), one LDS tile of PS_BT points at a time (every thread of the
+// block calls it with the same range).
+__device__ inline void pair_sums(float bi, const float4* __restrict__ ref4, const float* __restrict__ lw, int j0,
+                                 int j1, float4* s_x, float* s_l, float* s_q, double* t) {
   for (int base = j0; base < j1; base += PS_BT) {
     __syncthreads();
     {
       const int j = base + threadIdx.x;
       float4 X = make_float4(0.f, 0.f, 0.f, 0.f);
-      float l = -INFINITY;  // exp2(-inf) = 0: beyond the chunk
+      float l = -INFINITY;  // exp2(-inf) = 0: beyond the range
       if (j < j1) {
         X = ref4[j];
         l = lw[j];
@@ -74,8 +68,45 @@ __global__ __launch_bounds__(PS_BT) void psum_kernel(const float4* __restrict__ 
     t[3] += (double)az;
     t[4] += (double)aq;
   }
+}
+
+__global__ __launch_bounds__(PS_BT) void psum_kernel(const float4* __restrict__ tm4, int M,
+                                                     const float4* __restrict__ ref4, const float* __restrict__ lw,
+                                                     int N, int chunk_len, double* __restrict__ part) {
+  __shared__ float4 s_x[PS_BT];
+  __shared__ float s_l[PS_BT], s_q[PS_BT];
+  const int n_iblk = (M + PS_BT - 1) / PS_BT;
+  const int iblk = blockIdx.x % n_iblk, chunk = blockIdx.x / n_iblk;
+  const int ip = iblk * PS_BT + threadIdx.x;
+  const float bi = ip < M ? tm4[ip].w : 0.f;
+  const int j0 = chunk * chunk_len, j1 = min(N, j0 + chunk_len);
+  double t[PS_NQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  pair_sums(bi, ref4, lw, j0, j1, s_x, s_l, s_q, t);
   if (ip < M) {
     double* o = part + ((int64_t)chunk * M + ip) * PS_NQ;
+#pragma unroll
+    for (int q = 0; q < PS_NQ; ++q) o[q] = t[q];
+  }
+}
+
+// Batched form: block (r, b) of tblk takes template points [256 b, 256 b +
+// 256) of registration r against its whole reference, and writes their sums
+// at template offset poff[r].
+__global__ __launch_bounds__(PS_BT) void psum_batch_kernel(const RegDesc* __restrict__ regs,
+                                                           const int2* __restrict__ tblk,
+                                                           const int* __restrict__ poff,
+                                                           const float4* __restrict__ ref4,
+                                                           const float* __restrict__ lw, double* __restrict__ S) {
+  __shared__ float4 s_x[PS_BT];
+  __shared__ float s_l[PS_BT], s_q[PS_BT];
+  const int2 rb = tblk[blockIdx.x];
+  const RegDesc& g = regs[rb.x];
+  const int ip = rb.y * PS_BT + threadIdx.x;
+  const float bi = ip < g.M ? g.tm4[ip].w : 0.f;
+  double t[PS_NQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  pair_sums(bi, ref4 + g.ref_off, lw + g.ref_off, 0, g.N, s_x, s_l, s_q, t);
+  if (ip < g.M) {
+    double* o = S + ((int64_t)poff[rb.x] + ip) * PS_NQ;
 #pragma unroll
     for (int q = 0; q < PS_NQ; ++q) o[q] = t[q];
   }
@@ -90,65 +121,96 @@ __global__ __launch_bounds__(256) void psum_reduce_kernel(const double* __restri
   S[e] = s;
 }
 
+// Wrench terms of template point ip (visiting order) of one registration:
+// the posed point as the force kernel forms it (FP64 pose, rounded once to
+// FP32), then its force and energy from the pair sums s, in FP64.
+template <bool WU>
+__device__ inline void pinv_point(const float4* __restrict__ tm4, const float2* __restrict__ tmx, const double* s,
+                                  int ip, const double* __restrict__ pose, const Derived& D, int t, double* w) {
+  double sR[9], cv[3];
+  const double sc = pose[0];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) sR[e] = sc * pose[1 + e];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    cv[r] = sR[3 * r] * D.ybar0[0] + sR[3 * r + 1] * D.ybar0[1] + sR[3 * r + 2] * D.ybar0[2] + pose[10 + r] -
+            D.xbar[r];
+  // eq. (12), reading: iteration t uses 0.1 G1 + 0.9 G1 / (1 + exp(-(t - 1 - E/2)))
+  const double G = 0.1 * D.G1 + 0.9 * D.G1 / (1.0 + exp(-(((double)t - 1.0) - 0.5 * D.E)));
+  const double coef = -(G / D.Z) * D.coefL;
+  const double ucoef = (G / D.Z) * D.coefL / (D.p + 1.0);
+  const float4 T = tm4[ip];
+  const double ex = (double)T.x - D.ybar0[0], ey = (double)T.y - D.ybar0[1], ez = (double)T.z - D.ybar0[2];
+  // the posed point relative to xbar, rounded once to FP32
+  const float pxf = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);
+  const float pyf = (float)(sR[3] * ex + sR[4] * ey + sR[5] * ez + cv[1]);
+  const float pzf = (float)(sR[6] * ex + sR[7] * ey + sR[8] * ez + cv[2]);
+  const double px = pxf, py = pyf, pz = pzf;
+  const double tx = px * s[0] - s[1], ty = py * s[0] - s[2], tz = pz * s[0] - s[3];
+  const float2 A2 = tmx[ip];
+  const double gi = D.g_mode == 1.0 ? (double)A2.x / D.abar : 1.0;
+  const double mi = (double)A2.y;
+  const double fx = coef * gi * tx, fy = coef * gi * ty, fz = coef * gi * tz;
+  const double cx = px - cv[0], cy = py - cv[1], cz = pz - cv[2];
+  w[WR_F + 0] = mi * fx;
+  w[WR_F + 1] = mi * fy;
+  w[WR_F + 2] = mi * fz;
+  w[WR_K + 0] = fx * cx;
+  w[WR_K + 1] = fx * cy;
+  w[WR_K + 2] = fx * cz;
+  w[WR_K + 3] = fy * cx;
+  w[WR_K + 4] = fy * cy;
+  w[WR_K + 5] = fy * cz;
+  w[WR_K + 6] = fz * cx;
+  w[WR_K + 7] = fz * cy;
+  w[WR_K + 8] = fz * cz;
+  if constexpr (WU)
+    w[WR_U] = ucoef * gi * ((px * px + py * py + pz * pz + D.eps2) * s[0] - 2.0 * (px * s[1] + py * s[2] + pz * s[3]) +
+                            s[4]);
+}
+
 template <bool WU>
 __global__ __launch_bounds__(PS_BT) void pinv_kernel(const float4* __restrict__ tm4, const float2* __restrict__ tmx,
                                                      const double* __restrict__ S, int M,
                                                      const double* __restrict__ pose, const Derived* __restrict__ dv,
                                                      int t, double* __restrict__ wpart) {
   __shared__ double s_red[(PS_BT / 64) * 13];
-  const Derived& D = *dv;
-  double sR[9], cv[3];
-  {
-    const double s = pose[0];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) sR[e] = s * pose[1 + e];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-      cv[r] = sR[3 * r] * D.ybar0[0] + sR[3 * r + 1] * D.ybar0[1] + sR[3 * r + 2] * D.ybar0[2] + pose[10 + r] -
-              D.xbar[r];
-  }
-  // eq. (12), reading: iteration t uses 0.1 G1 + 0.9 G1 / (1 + exp(-(t - 1 - E/2)))
-  const double G = 0.1 * D.G1 + 0.9 * D.G1 / (1.0 + exp(-(((double)t - 1.0) - 0.5 * D.E)));
-  const double coef = -(G / D.Z) * D.coefL;
-  const double ucoef = (G / D.Z) * D.coefL / (D.p + 1.0);
   double w[13];
 #pragma unroll
   for (int e = 0; e < 13; ++e) w[e] = 0.0;
   const int ip = blockIdx.x * PS_BT + threadIdx.x;
-  if (ip < M) {
-    const float4 T = tm4[ip];
-    const double ex = (double)T.x - D.ybar0[0], ey = (double)T.y - D.ybar0[1], ez = (double)T.z - D.ybar0[2];
-    // the posed point relative to xbar, rounded once to FP32
-    const float pxf = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);
-    const float pyf = (float)(sR[3] * ex + sR[4] * ey + sR[5] * ez + cv[1]);
-    const float pzf = (float)(sR[6] * ex + sR[7] * ey + sR[8] * ez + cv[2]);
-    const double px = pxf, py = pyf, pz = pzf;
-    const double* s = S + (int64_t)ip * PS_NQ;
-    const double tx = px * s[0] - s[1], ty = py * s[0] - s[2], tz = pz * s[0] - s[3];
-    const float2 A2 = tmx[ip];
-    const double gi = D.g_mode == 1.0 ? (double)A2.x / D.abar : 1.0;
-    const double mi = (double)A2.y;
-    const double fx = coef * gi * tx, fy = coef * gi * ty, fz = coef * gi * tz;
-    const double cx = px - cv[0], cy = py - cv[1], cz = pz - cv[2];
-    w[WR_F + 0] = mi * fx;
-    w[WR_F + 1] = mi * fy;
-    w[WR_F + 2] = mi * fz;
-    w[WR_K + 0] = fx * cx;
-    w[WR_K + 1] = fx * cy;
-    w[WR_K + 2] = fx * cz;
-    w[WR_K + 3] = fy * cx;
-    w[WR_K + 4] = fy * cy;
-    w[WR_K + 5] = fy * cz;
-    w[WR_K + 6] = fz * cx;
-    w[WR_K + 7] = fz * cy;
-    w[WR_K + 8] = fz * cz;
-    if constexpr (WU)
-      w[WR_U] = ucoef * gi * ((px * px + py * py + pz * pz + D.eps2) * s[0] - 2.0 * (px * s[1] + py * s[2] + pz * s[3]) +
-                              s[4]);
-  }
+  if (ip < M) pinv_point<WU>(tm4, tmx, S + (int64_t)ip * PS_NQ, ip, pose, *dv, t, w);
   block_sum<13, PS_BT>(w, s_red);
   if (threadIdx.x == 0) {
     double* o = wpart + (int64_t)blockIdx.x * WR_STRIDE;
+#pragma unroll
+    for (int e = 0; e < 13; ++e) o[e] = w[e];
+  }
+}
+
+// Batched form: block (r, b) of tblk, wrench slot regs[r].wslot0 + b (regs
+// here describe the slot layout of this kernel: one slot per 256 points).
+template <bool WU>
+__global__ __launch_bounds__(PS_BT) void pinv_batch_kernel(const RegDesc* __restrict__ regs,
+                                                           const int2* __restrict__ tblk,
+                                                           const int* __restrict__ poff,
+                                                           const double* __restrict__ S,
+                                                           const double* __restrict__ poses,
+                                                           const Derived* __restrict__ dvs, int t,
+                                                           double* __restrict__ wpart) {
+  __shared__ double s_red[(PS_BT / 64) * 13];
+  const int2 rb = tblk[blockIdx.x];
+  const RegDesc& g = regs[rb.x];
+  double w[13];
+#pragma unroll
+  for (int e = 0; e < 13; ++e) w[e] = 0.0;
+  const int ip = rb.y * PS_BT + threadIdx.x;
+  if (ip < g.M)
+    pinv_point<WU>(g.tm4, g.tmx, S + ((int64_t)poff[rb.x] + ip) * PS_NQ, ip, poses + 13 * (int64_t)rb.x, dvs[rb.x],
+                   t, w);
+  block_sum<13, PS_BT>(w, s_red);
+  if (threadIdx.x == 0) {
+    double* o = wpart + ((int64_t)g.wslot0 + rb.y) * WR_STRIDE;
 #pragma unroll
     for (int e = 0; e < 13; ++e) o[e] = w[e];
   }
@@ -179,6 +241,24 @@ hipError_t launch_psum(const float4* tm4, int M, const float4* ref4, const float
   const int64_t ne = (int64_t)M * PS_NQ;
   hipLaunchKernelGGL(psum_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, (const double*)part, M,
                      nc, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_psum_batch(const RegDesc* regs, const int2* tblk, int n_tblk, const int* poff, const float4* ref4,
+                             const float* lw, double* S, hipStream_t st) {
+  if (n_tblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psum_batch_kernel, dim3((unsigned)n_tblk), dim3(PS_BT), 0, st, regs, tblk, poff, ref4, lw, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_pinv_batch(const RegDesc* regs_p, const int2* tblk, int n_tblk, const int* poff, const double* S,
+                             const double* poses, const Derived* dvs, int t, bool wu, double* wpart, hipStream_t st) {
+  if (n_tblk <= 0) return hipSuccess;
+  const dim3 grid((unsigned)n_tblk), block(PS_BT);
+  if (wu)
+    hipLaunchKernelGGL(pinv_batch_kernel<true>, grid, block, 0, st, regs_p, tblk, poff, S, poses, dvs, t, wpart);
+  else
+    hipLaunchKernelGGL(pinv_batch_kernel<false>, grid, block, 0, st, regs_p, tblk, poff, S, poses, dvs, t, wpart);
   return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from oracle import ref as O
-from synth import config1, config2
+from synth import config1, config2, config4, super_fibonacci_rotations
 
 pytestmark = pytest.mark.gpu
 
@@ -110,6 +110,43 @@ def test_register_pyramid_pinv(sg, ctx):
     assert _rmse(poses[PINV], poses[0], pr.tmpl) / O.diameter(pr.ref) <= 1e-6
 
 
+def test_batch_pinv_matches_all_pairs_batch(sg, ctx):
+    """Uneven registrations in one batched call: poses, final energies and
+    per-iteration statistics against the persistent all-pairs batch."""
+    pairs = config4(B=7, nmin=300, nmax=6000, iters=25)
+    tms = [sg.Cloud(p.tmpl) for p in pairs]
+    rfs = [sg.Cloud(p.ref) for p in pairs]
+    out = {}
+    for flags in (0, PINV):
+        poses, energy, st = ctx.register_batch(tms, rfs, sg.Params(p=1.0, k=16, E=25, flags=flags), stats=True)
+        out[flags] = (poses.cpu().numpy(), energy.cpu().numpy(), st.cpu().numpy())
+    for r, pr in enumerate(pairs):
+        pa, pb = _pose(sg, torch.as_tensor(out[0][0][r])), _pose(sg, torch.as_tensor(out[PINV][0][r]))
+        assert _rmse(pa, pb, pr.tmpl) <= 1e-6 * O.diameter(pr.ref), r
+    np.testing.assert_allclose(out[PINV][1], out[0][1], rtol=1e-5)
+    np.testing.assert_allclose(out[PINV][2][..., 0], out[0][2][..., 0], rtol=0, atol=0)   # G_t
+    # one registration of the batch against the oracle
+    pr = pairs[3]
+    S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=1.0, k=16, E=25))
+    po, _, _ = O.register(pr.tmpl, S)
+    assert _rmse(_pose(sg, torch.as_tensor(out[PINV][0][3])), po, pr.tmpl) <= 1e-4 * O.diameter(pr.ref)
+
+
+def test_multistart_pinv_matches_all_pairs_multistart(sg, ctx):
+    pr = config1(n=1500)
+    R0 = super_fibonacci_rotations(6)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    out = {}
+    for flags in (0, PINV):
+        poses, energy, best = ctx.multistart(tm, rf, sg.Params(p=1.0, k=16, E=20, flags=flags), R0)
+        out[flags] = (poses.cpu().numpy(), energy.cpu().numpy(), int(best))
+    for s in range(len(R0)):
+        pa, pb = _pose(sg, torch.as_tensor(out[0][0][s])), _pose(sg, torch.as_tensor(out[PINV][0][s]))
+        assert _rmse(pa, pb, pr.tmpl) <= 1e-6 * O.diameter(pr.ref), s
+    np.testing.assert_allclose(out[PINV][1], out[0][1], rtol=1e-5)
+    assert out[PINV][2] == out[0][2]
+
+
 def test_pinv_rejected_where_it_does_not_apply(sg, ctx):
     pr = config1(n=300)
     tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
@@ -118,5 +155,10 @@ def test_pinv_rejected_where_it_does_not_apply(sg, ctx):
                 sg.Params(p=1.0, k=16, E=5, flags=PINV | 2)):
         with pytest.raises(sg.SgrError):
             ctx.register(tm, rf, bad)
+        with pytest.raises(sg.SgrError):
+            ctx.register_batch([tm], [rf], bad)
+    # entry points without the O(M) iteration
+    a, mom = ctx.descriptors(tm, 16)
     with pytest.raises(sg.SgrError):
-        ctx.register_batch([tm], [rf], sg.Params(p=1.0, k=16, E=5, flags=PINV))
+        sg.Plan(ctx, tm, a, rf, ctx.descriptors(rf, 16)[0], mom, ctx.descriptors(rf, 16)[1],
+                sg.Params(p=1.0, k=16, E=5, flags=PINV))
