@@ -100,9 +100,9 @@ typedef struct {
                     bit 2: vector descriptors (sgr_step_vec, sgr_register_vec)
                     with FP32 matrix products instead of the split-f16 form;
                     bit 3: pose-independent pair sums (sgr_register,
-                    sgr_register_pyramid, sgr_register_batch, sgr_multistart;
-                    p = 1, g_mode 0 or 1, no mixed precision; SGR_EINVAL
-                    otherwise).  With p = 1 (eq. 11,
+                    sgr_register_pyramid, sgr_register_batch, sgr_multistart,
+                    sgr_register_vec; p = 1, g_mode 0 or 1, no mixed
+                    precision; SGR_EINVAL otherwise).  With p = 1 (eq. 11,
                     h = 1) the pair weight of eq. 5 does not depend on the
                     pose, so sum_j c_ij, sum_j c_ij x_j and sum_j c_ij |x_j|^2
                     are formed once (one pass over all pairs, FP32 terms and

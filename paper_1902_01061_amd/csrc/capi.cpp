@@ -90,8 +90,8 @@ int check_cloud(const sgr_cloud* c, const char* what) {
 constexpr int FLAG_PINV = 8;
 
 // allow_pinv: the caller (sgr_register, sgr_register_pyramid,
-// sgr_register_batch, sgr_multistart) implements flags bit 3, the
-// pose-independent pair sums of the p = 1 law.
+// sgr_register_batch, sgr_multistart, sgr_register_vec) implements flags
+// bit 3, the pose-independent pair sums of the p = 1 law.
 int check_params(const sgr_params* p, bool allow_pinv = false) {
   if (!p) return fail(SGR_EINVAL, "NULL params");
   if (!std::isfinite(p->p)) return fail(SGR_EINVAL, "p must be finite");
@@ -103,8 +103,8 @@ int check_params(const sgr_params* p, bool allow_pinv = false) {
   if (p->flags & ~15) return fail(SGR_EINVAL, "unknown flag bits");
   if (p->flags & FLAG_PINV) {
     if (!allow_pinv)
-      return fail(SGR_EINVAL, "flags bit 3 applies to sgr_register, sgr_register_pyramid, sgr_register_batch and "
-                              "sgr_multistart only");
+      return fail(SGR_EINVAL, "flags bit 3 applies to sgr_register, sgr_register_pyramid, sgr_register_batch, "
+                              "sgr_multistart and sgr_register_vec only");
     if (p->p != 1.0 || p->g_mode > 1 || (p->flags & 2))
       return fail(SGR_EINVAL, "flags bit 3 needs p = 1, g_mode 0 or 1 and no mixed precision");
   }
@@ -593,12 +593,18 @@ struct VecWs {
   double* mom;
   int K, n_chunks, slots;
   bool half;  // split-f16 products (decided by setup_vec)
+  // flags bit 3: the template in its own order, the pair sums per chunk, reduced
+  float4* tm4 = nullptr;
+  float2* tmx = nullptr;
+  double* ps_part = nullptr;
+  double* ps_S = nullptr;
 };
 
-int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, VecWs& w) {
+int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, VecWs& w, bool pinv = false) {
   w.K = vforce_K(D);
   w.n_chunks = vforce_chunks(M, N, ctx->n_cu);
   w.slots = vforce_n_iblk(M) * w.n_chunks;
+  const int wslots = pinv ? std::max(w.slots, pinv_blocks(M)) : w.slots;
   for (int pass = 0; pass < 2; ++pass) {
     Carve c{pass ? ctx->ws : nullptr};
     w.dv = c.take<Derived>(1);
@@ -608,9 +614,15 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
     w.At = c.take<float>((size_t)vforce_pad_rows(M) * row_words);
     w.Bt = c.take<float>((size_t)vforce_pad_refs(N) * row_words);
     w.ref4 = c.take<float4>((size_t)vforce_pad_refs(N));
-    w.wpart = c.take<double>((size_t)w.slots * WR_STRIDE);
+    w.wpart = c.take<double>((size_t)wslots * WR_STRIDE);
     w.fpart = with_f ? c.take<double>((size_t)w.n_chunks * M * 3) : nullptr;
     w.mom = with_mom ? c.take<double>(20) : nullptr;
+    if (pinv) {
+      w.tm4 = c.take<float4>(M);
+      w.tmx = c.take<float2>(M);
+      w.ps_part = c.take<double>((size_t)w.n_chunks * M * 5);
+      w.ps_S = c.take<double>((size_t)M * 5);
+    }
     if (!pass)
       if (int e = ensure_ws(ctx, c.off)) return e;
   }
@@ -1019,22 +1031,37 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
   if (!ctx || !inout || !a_t || !a_r) return fail(SGR_EINVAL, "NULL argument");
   if (int e = check_cloud(tmpl, "template")) return e;
   if (int e = check_cloud(ref, "reference")) return e;
-  if (int e = check_params(prm)) return e;
+  if (int e = check_params(prm, true)) return e;
   if (int e = check_vec(prm, D)) return e;
   if (prm->E < 1) return fail(SGR_EINVAL, "E must be >= 1");
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
+  const bool pinv = (prm->flags & FLAG_PINV) != 0;
   VecWs w;
-  if (int e = carve_vec(ctx, M, N, D, false, true, w)) return e;
+  if (int e = carve_vec(ctx, M, N, D, false, true, w, pinv)) return e;
   HIPCHK(launch_moments(ref->x, ref->y, ref->z, N, w.mom + 10, st));
   HIPCHK(launch_moments(tmpl->x, tmpl->y, tmpl->z, M, w.mom, st));
   if (int e = setup_vec(tmpl, a_t, ref, a_r, D, w.mom, w.mom + 10, prm, w, st)) return e;
+  if (pinv) {
+    // the pair sums once: one pass of the vector kernel writing them per chunk
+    VForceArgs A = vargs(tmpl, ref, w, (const double*)inout, 0);
+    A.spart = w.ps_part;
+    HIPCHK(launch_vforce(A, true, false, st));
+    HIPCHK(launch_psum_reduce(w.ps_part, M, w.n_chunks, w.ps_S, st));
+    HIPCHK(launch_pack_plain(tmpl->x, tmpl->y, tmpl->z, tmpl->m, M, w.tm4, w.tmx, st));
+  }
   auto loop = [&](hipStream_t s) -> int {
     for (int t = 0; t < prm->E; ++t) {
       const bool wu = stats != nullptr || t == prm->E - 1;
-      HIPCHK(launch_vforce(vargs(tmpl, ref, w, (const double*)inout, t), wu, false, s));
-      HIPCHK(launch_update(w.wpart, w.slots, (const double*)inout, (double*)inout, w.dv, t, 0.0, 1, nullptr,
+      int used = w.slots;
+      if (pinv) {
+        HIPCHK(launch_pinv(w.tm4, w.tmx, w.ps_S, M, (const double*)inout, w.dv, t, wu, w.wpart, s));
+        used = pinv_blocks(M);
+      } else {
+        HIPCHK(launch_vforce(vargs(tmpl, ref, w, (const double*)inout, t), wu, false, s));
+      }
+      HIPCHK(launch_update(w.wpart, used, (const double*)inout, (double*)inout, w.dv, t, 0.0, 1, nullptr,
                            stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
     }
     return SGR_OK;

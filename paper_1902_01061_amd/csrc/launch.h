@@ -178,6 +178,7 @@ struct VForceArgs {
   double G;             // > 0 overrides eq. 12
   double* wpart;        // [n_iblk * n_chunks][WR_STRIDE]
   double* fpart;        // [n_chunks][M][3] (WF only)
+  double* spart = nullptr;  // with WU: [n_chunks][M][5] pair sums instead of forces and wrench
 };
 int vforce_K(int D);
 // Halves per split-f16 row: the contraction [h, h, l] . [h, l, h] of length
@@ -215,6 +216,11 @@ hipError_t launch_psum(const float4* tm4, int M, const float4* ref4, const float
                        double* part, double* S, hipStream_t st);
 hipError_t launch_pinv(const float4* tm4, const float2* tmx, const double* S, int M, const double* pose,
                        const Derived* dv, int t, bool wu, double* wpart, hipStream_t st);
+// S[i] = sum over n_chunks of part[chunk][i] (5 values per point, fixed order).
+hipError_t launch_psum_reduce(const double* part, int M, int n_chunks, double* S, hipStream_t st);
+// Template in its own order for launch_pinv: (x0, y0, z0, 0) and (0, m).
+hipError_t launch_pack_plain(const float* x, const float* y, const float* z, const float* mY, int M, float4* tm4,
+                             float2* tmx, hipStream_t st);
 // Batched forms: tblk lists (registration, block of 256 template points);
 // registration r's sums sit at template offset poff[r] of S.  regs_p is
 // regs with wslot0 / n_items describing one wrench slot per listed block.

@@ -9,7 +9,8 @@
 // g_i ((|y_i|^2 + eps^2) S0_i - 2 y_i . S1_i + S2_i) with S2_i = sum_j c_ij
 // |x_j|^2 (x_j relative to the reference centroid, as everywhere).
 //
-// psum_kernel forms S0, S1, S2 once per registration, one pass over all
+// psum_kernel forms S0, S1, S2 once per registration (scalar descriptors;
+// the vector-descriptor kernel writes the same sums itself), one pass over all
 // pairs: a block of 256 template points (visiting order) against one chunk of
 // the reference, staged through LDS 256 points at a time; every lane sums a
 // tile's 256 terms in FP32 and adds them to FP64 sums, as the force kernel
@@ -169,6 +170,15 @@ __device__ inline void pinv_point(const float4* __restrict__ tm4, const float2* 
                             s[4]);
 }
 
+__global__ __launch_bounds__(256) void pack_plain_kernel(const float* __restrict__ x, const float* __restrict__ y,
+                                                         const float* __restrict__ z, const float* __restrict__ mY, int M,
+                                                         float4* __restrict__ tm4, float2* __restrict__ tmx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  tm4[i] = make_float4(x[i], y[i], z[i], 0.f);
+  tmx[i] = make_float2(0.f, mY ? mY[i] : 1.f);
+}
+
 template <bool WU>
 __global__ __launch_bounds__(PS_BT) void pinv_kernel(const float4* __restrict__ tm4, const float2* __restrict__ tmx,
                                                      const double* __restrict__ S, int M,
@@ -238,9 +248,20 @@ hipError_t launch_psum(const float4* tm4, int M, const float4* ref4, const float
                      part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_psum_reduce(part, M, nc, S, st);
+}
+
+hipError_t launch_psum_reduce(const double* part, int M, int n_chunks, double* S, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
   const int64_t ne = (int64_t)M * PS_NQ;
-  hipLaunchKernelGGL(psum_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, (const double*)part, M,
-                     nc, S);
+  hipLaunchKernelGGL(psum_reduce_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, part, M, n_chunks, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_plain(const float* x, const float* y, const float* z, const float* mY, int M, float4* tm4,
+                             float2* tmx, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_plain_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, x, y, z, mY, M, tm4, tmx);
   return hipGetLastError();
 }
 

@@ -362,6 +362,16 @@ void vforce_kernel(VForceArgs A) {
     double t[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) t[q] = (double)s_S[q * VF_ROWS + threadIdx.x];
+    if constexpr (WU) {
+      if (A.spart) {
+        // the sums themselves (pose-independent for p = 1): sum_j c, sum_j c x_j
+        // (3), sum_j c |x_j|^2 of this chunk
+        double* o = A.spart + ((int64_t)chunk * A.M + ip) * 5;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[q] = t[q];
+        goto done;
+      }
+    }
     const double ex = (double)A.y0x[ip] - D.ybar0[0], ey = (double)A.y0y[ip] - D.ybar0[1],
                  ez = (double)A.y0z[ip] - D.ybar0[2];
     const float pxf = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);

@@ -147,6 +147,32 @@ def test_multistart_pinv_matches_all_pairs_multistart(sg, ctx):
     assert out[PINV][2] == out[0][2]
 
 
+@pytest.mark.parametrize("flags", [0, 4])
+def test_register_vec_pinv(sg, ctx, flags):
+    """Vector descriptors (16-bin histograms of normals): the sums come from
+    one pass of the matrix-core kernel (split f16, or FP32 products with
+    flags bit 2); against the oracle and the per-iteration kernel."""
+    pr = config1()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    hX = ctx.descriptors_hn(rf, 16, 16)
+    hY = ctx.descriptors_hn(tm, 16, 16)
+    prm = O.Params(p=1.0, k=16, E=60)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=hX.cpu().numpy().astype(np.float64),
+                     aY=hY.cpu().numpy().astype(np.float64))
+    po, _, _ = O.register(pr.tmpl, S)
+    poses = {}
+    for f in (flags, flags | PINV):
+        pose, _ = ctx.register_vec(tm, hY, rf, hX, sg.Params(p=1.0, k=16, E=60, flags=f))
+        poses[f] = _pose(sg, pose)
+    D = O.diameter(pr.ref)
+    e_o = _rmse(poses[flags | PINV], po, pr.tmpl) / D
+    e_k = _rmse(poses[flags | PINV], poses[flags], pr.tmpl) / D
+    print(f"vector registration with pose-independent sums (flags {flags}): vs oracle {e_o:.1e} D, "
+          f"vs per-iteration kernel {e_k:.1e} D")
+    assert e_o <= 1e-4
+    assert e_k <= 1e-6
+
+
 def test_pinv_rejected_where_it_does_not_apply(sg, ctx):
     pr = config1(n=300)
     tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
