@@ -105,6 +105,18 @@ def test_radius_descriptors_tile_skipping(sg, ctx):
         assert cnt.max() == (7 if r2 == 1.0 else 19)
 
 
+def test_radius_descriptors_two_list_passes(sg, ctx):
+    """70 000 points = 1 094 tiles of 64: the per-block list of tiles within
+    r is built in two passes of 1 024 tiles; sampled rows, including the
+    first and last points of the Morton order's extremes."""
+    P = ellipsoid_patch(70000, 9).astype(np.float32)
+    lam = O.moments(P)[2]
+    rows = np.concatenate([np.random.default_rng(2).choice(len(P), 60, replace=False),
+                           [int(np.argmin(P[:, 0])), int(np.argmax(P[:, 0])), len(P) - 1]])
+    a, cnt = _check(sg, ctx, P, np.float32(0.3 * 0.3 * lam), rows)
+    assert cnt[rows].min() >= 1
+
+
 def test_radius_descriptors_full_size_sampled(sg, ctx):
     """The scan-sized reference (36 000 points) with the paper's radius
     sqrt(lambda_max): sampled rows against the oracle."""
