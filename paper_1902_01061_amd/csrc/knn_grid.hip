@@ -235,13 +235,12 @@ __device__ inline void span_points(const float4* __restrict__ spts, int p0, int 
 // cells.  Up to two spans are handed to a single call site (one inlined copy
 // of the caller's per-candidate code), in the order in which visiting the
 // cells one by one would meet the points.
-template <class F>
-__device__ inline void row_spans(const int* __restrict__ starts, const GridInfo& G, const int c[3], int r, int dz,
-                                 int dy, F&& f) {
+__device__ inline void row_bounds(const int* __restrict__ starts, const GridInfo& G, const int c[3], int r, int dz,
+                                  int dy, int& a0, int& a1, int& b0, int& b1) {
+  a0 = a1 = b0 = b1 = 0;
   const int cz = c[2] + dz, cy = c[1] + dy;
   if (cz < 0 || cz >= G.dims[2] || cy < 0 || cy >= G.dims[1]) return;
   const int row = (cz * G.dims[1] + cy) * G.dims[0];
-  int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
   if (r == 0 || abs(dz) == r || abs(dy) == r) {
     a0 = starts[row + max(0, c[0] - r)];
     a1 = starts[row + min(G.dims[0] - 1, c[0] + r) + 1];
@@ -255,6 +254,13 @@ __device__ inline void row_spans(const int* __restrict__ starts, const GridInfo&
       b1 = starts[row + c[0] + r + 1];
     }
   }
+}
+
+template <class F>
+__device__ inline void row_spans(const int* __restrict__ starts, const GridInfo& G, const int c[3], int r, int dz,
+                                 int dy, F&& f) {
+  int a0, a1, b0, b1;
+  row_bounds(starts, G, c, r, dz, dy, a0, a1, b0, b1);
 #pragma unroll 1
   for (int h = 0; h < 2; ++h) {
     const int q0 = h ? b0 : a0, q1 = h ? b1 : a1;
@@ -313,12 +319,24 @@ __device__ inline void insert_key(uint64_t (&L)[KC], uint64_t key) {
 // list, a query whose search is not finished after shell rcap (an outlier in
 // empty space, whose lane would otherwise sweep many cells alone and hold up
 // its wave) is appended to it instead, for grid_knn_far_kernel.
+// Candidates a lane buffers before they are inserted.  A candidate is
+// buffered when its key is below the k-th key of the list as it stood at the
+// last insertion; that key only decreases, so a rejected candidate could never
+// have entered.  Each lane's buffer is its own LDS column.  The active lanes
+// of a wave insert their buffers together as soon as one of them is full (and
+// at the end of every shell, before the stopping test): in a dense cluster
+// some lane accepts a candidate at almost every step, and inserting at once
+// would make the wave run the 5 KC-operation insertion at almost every step.
+constexpr int KNN_CB = 8;
+
 template <int KC>
 __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
                                                          const GridInfo* __restrict__ gi, int n, int k, int rcap,
                                                          int* __restrict__ far, int32_t* __restrict__ idx_out) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
   float4* buf = s_buf + threadIdx.x;
+  uint64_t* cand = s_cand + threadIdx.x;
   const int t = blockIdx.x * GQ_BT + threadIdx.x;
   if (t >= n) return;  // no barriers below
   const GridInfo G = *gi;
@@ -337,16 +355,49 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
   uint64_t L[KC];
 #pragma unroll
   for (int s = 0; s < KC; ++s) L[s] = (s < KC - k) ? 0ull : ~0ull;
+  int cnt = 0;  // buffered candidates of this lane
   const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
   for (int r = 0; r <= rmax; ++r) {
-    shell_spans(starts, G, c, r, [&](int p0, int p1) {
-      span_points(spts, p0, p1, buf, [&](const float4& P) {
-        const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
-        const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
-        const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
-        if (d2 < INFINITY && key < L[KC - 1]) insert_key(L, key);
-      });
-    });
+    // the rows of shell r (see row_spans), then one end row that visits no
+    // point and empties the buffers through the same insertion code, so that
+    // this code exists once
+    const int w = 2 * r + 1, nrow = w * w;
+#pragma unroll 1
+    for (int ri = 0; ri <= nrow; ++ri) {
+      const bool end = ri == nrow;
+      int a0 = 0, a1 = 1, b0 = 0, b1 = 0;
+      if (!end) row_bounds(starts, G, c, r, ri / w - r, ri % w - r, a0, a1, b0, b1);
+#pragma unroll 1
+      for (int h = 0; h < 2; ++h) {
+        const int q0 = h ? b0 : a0, q1 = h ? b1 : a1;
+#pragma unroll 1
+        for (int p = q0; p < q1; p += SPAN_U) {
+          if (!end) {
+#pragma unroll
+            for (int u = 0; u < SPAN_U; ++u) buf[u * GQ_BT] = spts[min(p + u, q1 - 1)];
+          }
+          const int nu = min(SPAN_U, q1 - p);
+#pragma unroll 1
+          for (int u = 0; u < nu; ++u) {
+            if (!end) {
+              const float4 P = buf[u * GQ_BT];
+              const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
+              const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+              const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
+              if (d2 < INFINITY && key < L[KC - 1]) {
+                cand[cnt * GQ_BT] = key;
+                ++cnt;
+              }
+            }
+            if (__any(cnt == KNN_CB || (end && cnt > 0))) {
+#pragma unroll 1
+              for (int e = 0; e < cnt; ++e) insert_key(L, cand[e * GQ_BT]);
+              cnt = 0;
+            }
+          }
+        }
+      }
+    }
     if (shell_done(G, c, qv, r, key_of(L[KC - 1]))) break;
     if (far && r >= rcap) {
       far[1 + atomicAdd(far, 1)] = t;
