@@ -58,10 +58,12 @@ def test_tiny_clouds_step_and_register_match_oracle(sg, ctx, M, N, k, p):
     f = f.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(f - so.f) <= F_TOL * np.linalg.norm(so.f)
     po, _, _ = O.register(pr.tmpl, S)
-    pg, _ = ctx.register(tm, rf, gp)
-    s, R, t = sg.pose_to_srt(pg)
-    d = O.Pose(s, R, t).apply(pr.tmpl) - po.apply(pr.tmpl)
-    assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * O.diameter(pr.ref)
+    # p = 1 also with the pair sums formed once (flags bit 3)
+    for flags in ((0, 8) if p == 1.0 else (0,)):
+        pg, _ = ctx.register(tm, rf, sg.Params(p=p, k=k, E=12, flags=flags))
+        s, R, t = sg.pose_to_srt(pg)
+        d = O.Pose(s, R, t).apply(pr.tmpl) - po.apply(pr.tmpl)
+        assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * O.diameter(pr.ref), flags
 
 
 def test_degenerate_clouds_are_errors(sg, ctx):
@@ -134,3 +136,11 @@ def test_tiny_clouds_vector_step_matches_oracle(sg, ctx, flags):
     f = f.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(f - so.f) <= F_TOL * np.linalg.norm(so.f)
     assert np.linalg.norm(wr.cpu().numpy()[0:3] - so.F) <= F_TOL * np.abs(so.f).sum()
+    # the registration, per-iteration kernel and pair sums formed once
+    po, _, _ = O.register(pr.tmpl, S)
+    for fl in (flags, flags | 8):
+        pg, _ = ctx.register_vec(sg.Cloud(pr.tmpl), _dt(aY), sg.Cloud(pr.ref), _dt(aX),
+                                 sg.Params(p=1.0, k=16, E=10, flags=fl))
+        s_, R_, t_ = sg.pose_to_srt(pg)
+        d = O.Pose(s_, R_, t_).apply(pr.tmpl) - po.apply(pr.tmpl)
+        assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * O.diameter(pr.ref), fl
