@@ -29,6 +29,9 @@ if ROOT not in sys.path:
 
 METRIC = "shape-weighted pair interactions/sec per iteration; ms/registration at fixed RMSE"
 PEAK_FP32_TFLOPS = 157.3        # MI355X published FP32 vector peak
+# Without packed FP32 (disabled for every HIP unit of this build) a lane
+# retires one FP32 FMA per clock: 256 CU x 64 lanes x 2 flops x 2.4 GHz.
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one VALU issue slot per lane per clock
 # Algorithmic FP32 flops per pair (FMA = 2, transcendentals not counted):
 # p = 1: r (3) + similarity exponent (3) + weight (1) + accumulate (6) = 13;
@@ -583,6 +586,8 @@ def main() -> int:
                      "flops_per_pair": fpp, "pairs_per_s": k_pairs},
     }
     out["roofline"]["launch"] = launch
+    out["roofline"]["peak_unpacked"] = PEAK_FP32_UNPACKED_TFLOPS
+    out["roofline"]["frac_unpacked"] = achieved / PEAK_FP32_UNPACKED_TFLOPS
     out["roofline"]["traffic"] = _traffic(launch)
     if not args.no_extras:
         # the same registration with the mixed-precision force (bf16 matrix cores)
