@@ -50,6 +50,12 @@ passages the paper leaves open (each is repeated where it is used):
 * Update (eq. 9): Y(t+1) = c (Y - ybar) R + ybar + d (row vectors).
 * G schedule (eq. 12): iteration t (0-based) uses
   G_t = 0.1 G1 + 0.9 G1 / (1 + exp(-(t - 1 - E/2))).
+* Local polynomial coefficients (Sec. III-A names them among the features
+  evaluated, without a definition): a quadratic height function fitted by
+  least squares in the neighbourhood's covariance frame, coordinates divided
+  by the neighbourhood's RMS spread, reduced to quantities that no rotation,
+  scale or frame sign changes: the fitted Hessian's eigenvalues (sign fixed
+  by their sum) and the RMS residual (poly_fit).
 """
 from __future__ import annotations
 
@@ -193,6 +199,50 @@ def normal_histograms(P: np.ndarray, k: int, D: int, queries=None):
     u = np.abs(np.einsum("qc,qkc->qk", n_all[q], n_all[nbr]))
     h = tent_weights(np.minimum(u, 1.0).reshape(-1), D).reshape(len(q), k, D).mean(axis=1)
     return h, lam_all[q]
+
+
+def poly_fit(Q: np.ndarray) -> np.ndarray:
+    """Local polynomial descriptor of one neighbourhood (Sec. III-A names local
+    polynomial coefficients among the features evaluated), as read here: the
+    points Q (k x 3, k >= 6) in the frame of their covariance (1/k, centred at
+    their mean; tangent axes t1, t2 of the two largest eigenvalues, normal n of
+    the smallest), every coordinate divided by rho = sqrt(trace), so that
+    u = (q - qbar).t1 / rho, v = (q - qbar).t2 / rho, h = (q - qbar).n / rho;
+    the least-squares fit h ~ c0 + c1 u + c2 v + c3 u^2 + c4 u v + c5 v^2; and
+    the descriptor [mu1, mu2, r]: mu1 >= mu2 the eigenvalues of the fitted
+    Hessian [[2 c3, c4], [c4, 2 c5]], negated and swapped when their sum is
+    negative (the sign of n is arbitrary), and r the RMS residual of the fit.
+    It does not change under rotation, translation, uniform scale, a change of
+    sign of any axis or a rotation of the tangent axes.  rho = 0 (all points
+    equal) gives NaN."""
+    Q = np.asarray(Q, dtype=np.float64)
+    qc = Q - Q.mean(axis=0)
+    C = qc.T @ qc / len(Q)
+    lam, vec = np.linalg.eigh(C)                    # ascending: n = vec[:, 0]
+    rho = np.sqrt(lam.sum())
+    if not rho > 0:
+        return np.full(3, np.nan)
+    u, v, h = qc @ vec[:, 2] / rho, qc @ vec[:, 1] / rho, qc @ vec[:, 0] / rho
+    A = np.stack([np.ones_like(u), u, v, u * u, u * v, v * v], axis=1)
+    c = np.linalg.lstsq(A, h, rcond=None)[0]
+    mu = np.linalg.eigvalsh(np.array([[2 * c[3], c[4]], [c[4], 2 * c[5]]]))[::-1]
+    if mu.sum() < 0:
+        mu = -mu[::-1]
+    r = np.sqrt(np.mean((h - A @ c) ** 2))
+    return np.array([mu[0], mu[1], r])
+
+
+def poly_descriptors(P: np.ndarray, k: int, queries=None):
+    """poly_fit over every point's k nearest neighbours (self included, the
+    neighbour lists of the curvature).  Returns (descriptors (nq, 3),
+    covariance eigenvalues (nq, 3) ascending): the normal, and so the
+    descriptor, is determined only where lambda_0 < lambda_1."""
+    P = np.ascontiguousarray(P, dtype=np.float32)
+    q = np.arange(len(P)) if queries is None else np.asarray(queries)
+    nbr = knn(P, k, q)
+    _, lam = normals(P, nbr)
+    out = np.stack([poly_fit(P[nb]) for nb in nbr]) if len(q) else np.zeros((0, 3))
+    return out, lam
 
 
 def radius_descriptors(P: np.ndarray, r2, queries=None):

@@ -596,3 +596,80 @@ def test_change_flags_self_pair_added_object_and_shape_change():
     assert (f[:50] == 2).all() and not f[50:].any()
     f, _, _ = O.change_flags(X, aY2, X, aX, ident, tau, sigma, 0.0)   # shape test off
     assert not f.any()
+
+
+# ------------------------------------------------- local polynomial descriptor
+def _quadric_grid(a, b, c, n=7):
+    g = np.array([[x, y] for x in np.linspace(-1, 1, n) for y in np.linspace(-1, 1, n)])
+    return np.column_stack([g[:, 0], g[:, 1], a * g[:, 0] ** 2 + b * g[:, 0] * g[:, 1] + c * g[:, 1] ** 2])
+
+
+def _rho(Q):
+    qc = Q - Q.mean(axis=0)
+    return np.sqrt(np.mean(np.sum(qc * qc, axis=1)))
+
+
+@pytest.mark.parametrize("a,b,c", [(0.05, 0.0, -0.02), (0.03, 0.0, 0.03), (-0.04, 0.0, -0.01), (0.02, 0.0, -0.05)])
+def test_poly_fit_exact_quadric(a, b, c):
+    """Points exactly on h = a u^2 + c v^2 over a grid symmetric in u and v:
+    the covariance frame is the (u, v, h) frame, the fit is exact, and the
+    descriptor is the Hessian's eigenvalues 2 a rho and 2 c rho, sorted, with
+    both negated and swapped when their sum is negative; residual 0."""
+    Q = _quadric_grid(a, b, c)
+    rho = _rho(Q)
+    mu = np.sort([2 * a * rho, 2 * c * rho])[::-1]
+    if mu.sum() < 0:
+        mu = -mu[::-1]
+    d = O.poly_fit(Q)
+    np.testing.assert_allclose(d[:2], mu, rtol=1e-12, atol=1e-14)
+    assert d[2] < 1e-14
+
+
+def test_poly_fit_plane_and_degenerate():
+    g = _quadric_grid(0.0, 0.0, 0.0)
+    np.testing.assert_allclose(O.poly_fit(g), 0.0, atol=1e-14)
+    assert np.isnan(O.poly_fit(np.ones((8, 3)))).all()
+
+
+def test_poly_fit_sphere_cap_is_umbilic_and_convex():
+    """A cap of a sphere sampled symmetrically under a quarter turn about its
+    axis: mu1 = mu2 (an umbilic), positive by the sign convention, close to
+    rho / R."""
+    R = 3.0
+    g = _quadric_grid(0.0, 0.0, 0.0, n=9)[:, :2] * 0.4
+    Q = np.column_stack([g, np.sqrt(R * R - np.sum(g * g, axis=1))])
+    d = O.poly_fit(Q)
+    assert d[0] == pytest.approx(d[1], rel=1e-9)
+    assert d[0] > 0
+    assert d[0] == pytest.approx(_rho(Q) / R, rel=2e-2)
+
+
+def test_poly_fit_residual_of_a_cubic():
+    """h = u^3 is not in the fitted space: the residual is the RMS of the
+    part of u^3 orthogonal to {1, u, v, u^2, u v, v^2} over the samples."""
+    g = _quadric_grid(0.0, 0.0, 0.0, n=9)[:, :2]
+    Q = np.column_stack([g, 0.05 * g[:, 0] ** 3])
+    d = O.poly_fit(Q)
+    qc = Q - Q.mean(axis=0)
+    lam, vec = np.linalg.eigh(qc.T @ qc / len(Q))
+    rho = np.sqrt(lam.sum())
+    u, v, h = qc @ vec[:, 2] / rho, qc @ vec[:, 1] / rho, qc @ vec[:, 0] / rho
+    A = np.stack([np.ones_like(u), u, v, u * u, u * v, v * v], axis=1)
+    resid = h - A @ np.linalg.pinv(A) @ h             # projection residual, another route
+    assert d[2] == pytest.approx(np.sqrt(np.mean(resid ** 2)), rel=1e-9)
+    assert d[2] > 1e-4
+
+
+def test_poly_fit_invariances():
+    rng = np.random.default_rng(4)
+    base = _quadric_grid(0.08, 0.03, -0.05, n=5) + rng.normal(0, 0.01, (25, 3))
+    d0 = O.poly_fit(base)
+    Rm = rot_axis_angle([1.0, -2.0, 0.5], 73.0)
+    t = np.array([3.0, -1.0, 2.0])
+    for Q in (base @ Rm.T + t,                        # rotation + translation
+              2.7 * base,                             # uniform scale
+              base * np.array([1.0, 1.0, -1.0]),      # reflection of the normal axis
+              base * np.array([-1.0, 1.0, 1.0]),      # reflection of a tangent axis
+              base[rng.permutation(len(base))],       # order of the neighbours
+              base @ rot_axis_angle([0.0, 0.0, 1.0], 30.0).T):   # rotation of the tangent frame
+        np.testing.assert_allclose(O.poly_fit(Q), d0, rtol=1e-9, atol=1e-12)
