@@ -368,6 +368,20 @@ def extra_vector(sg, ctx, E: int, k: int, D: int = 16):
                      "matrix_peak_tflops": peak, "frac_lower_bound": fpp * pairs / dt / 1e12 / peak,
                      "pose_rmse_over_diameter": _pose_err(sg, pose, pr),
                      "nn_rmse": float(ctx.residual(tm, rf, pose).item())}
+    # local polynomial descriptors (D = 3: fitted Hessian eigenvalues, residual)
+    ctx.descriptors_poly(rf, k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pX = ctx.descriptors_poly(rf, k)
+    pY = ctx.descriptors_poly(tm, k)
+    torch.cuda.synchronize()
+    dp_ms = (time.perf_counter() - t0) * 1e3
+    prm = sg.Params(p=1.0, k=k, E=E)
+    pose = sg.pose_identity()
+    ctx.register_vec(tm, pY, rf, pX, prm, pose=pose)
+    dt, _ = _timed(lambda: (pose.copy_(sg.pose_identity()), ctx.register_vec(tm, pY, rf, pX, prm, pose=pose)))
+    out["poly_descriptors"] = {"D": 3, "descriptors_ms_both_clouds": dp_ms, "ms_per_registration": dt * 1e3,
+                               "pose_rmse_over_diameter": _pose_err(sg, pose, pr)}
     # split f16 with the pair sums formed by one pass of the kernel (flags bit 3)
     prm = sg.Params(p=1.0, k=k, E=E, flags=8)
     pose = sg.pose_identity()

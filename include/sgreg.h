@@ -218,6 +218,29 @@ int sgr_register_pyramid(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* r
  * Errors: SGR_EINVAL if k < 1, k > 32, n < k, or D outside [2, 30]. */
 int sgr_descriptors_hn(sgr_ctx* ctx, const sgr_cloud* c, int k, int D, float* h_out, sgr_stream_t stream);
 
+/* Vector shape descriptor from local polynomial coefficients (Sec. III-A
+ * lists them among the local shape features; the paper gives no definition,
+ * this is the reading used).  For every point, its k nearest neighbours (the
+ * neighbour lists of sgr_knn) are expressed in the frame of their covariance
+ * (1/k, centred at their mean: tangent axes of the two largest eigenvalues,
+ * normal of the smallest), every coordinate divided by rho = sqrt(trace);
+ * a quadric h = c0 + c1 u + c2 v + c3 u^2 + c4 u v + c5 v^2 is fitted by least
+ * squares (FP64 normal equations), and
+ *   out[i][0..2] = (mu1, mu2, r): mu1 >= mu2 the eigenvalues of the fitted
+ *   Hessian [[2 c3, c4], [c4, 2 c5]] (both negated and swapped when their
+ *   sum is negative, since the normal's sign is arbitrary) and r the RMS
+ *   residual of the fit,
+ * float32, row-major [n][3], device, caller-owned.  The three numbers do not
+ * change under rotation, translation, uniform scale, or a change of sign or
+ * an in-plane rotation of the frame; they feed sgr_step_vec /
+ * sgr_register_vec with D = 3.  NaN for a point whose neighbours coincide
+ * (rho = 0) or lie on a line (singular normal equations).  The frame, and so
+ * the descriptor, is determined only where the smallest covariance
+ * eigenvalue is below the middle one.  Uses the context workspace;
+ * asynchronous on stream.
+ * Errors: SGR_EINVAL for NULL arguments, k outside [6, 32] or n < k. */
+int sgr_descriptors_poly(sgr_ctx* ctx, const sgr_cloud* c, int k, float* out, sgr_stream_t stream);
+
 /* sgr_step and sgr_register with vector descriptors: eq. (3) with
  * |a_i - a_j|^2 summed over D dimensions, a_t[M][D] and a_r[N][D] (device,
  * float32, row-major; e.g. from sgr_descriptors_hn).  sigma <= 0 selects

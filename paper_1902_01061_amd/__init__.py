@@ -287,6 +287,13 @@ class Context:
         check(lib().sgr_descriptors_hn(self._h, ctypes.byref(c), int(k), int(D), _ptr(h), _stream(self.device)))
         return h
 
+    def descriptors_poly(self, cloud: Cloud, k: int) -> torch.Tensor:
+        """Local polynomial descriptor (mu1, mu2, residual), (n, 3) float32."""
+        out = torch.empty((cloud.n, 3), dtype=torch.float32, device=self.device)
+        c = cloud.c()
+        check(lib().sgr_descriptors_poly(self._h, ctypes.byref(c), int(k), _ptr(out), _stream(self.device)))
+        return out
+
     def step_vec(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params, t: int, pose_in,
                  want_wrench=False, want_f=False):
         """step() with vector descriptors a_t (M, D), a_r (N, D)."""

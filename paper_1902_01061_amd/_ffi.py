@@ -72,6 +72,7 @@ SIGNATURES = {
     "sgr_descriptors_radius": [P, CP, ctypes.c_float, P, P, P],
     "sgr_register_pyramid": [P, CP, CP, PP, ctypes.POINTER(SgrLevel), I, P, P, P],
     "sgr_descriptors_hn": [P, CP, I, I, P, P],
+    "sgr_descriptors_poly": [P, CP, I, P, P],
     "sgr_step_vec": [P, CP, P, CP, P, I, P, P, PP, I, P, P, P, P, P],
     "sgr_register_vec": [P, CP, P, CP, P, I, PP, P, P, P],
 }

@@ -1005,6 +1005,17 @@ int sgr_descriptors_hn(sgr_ctx* ctx, const sgr_cloud* c, int k, int D, float* h_
   return SGR_OK;
 }
 
+int sgr_descriptors_poly(sgr_ctx* ctx, const sgr_cloud* c, int k, float* out, sgr_stream_t stream) {
+  if (!ctx || !out) return fail(SGR_EINVAL, "NULL argument");
+  if (int e = check_cloud(c, "cloud")) return e;
+  if (k < 6 || k > 32) return fail(SGR_EINVAL, "k must be in [6, 32] (six fitted coefficients)");
+  if (c->n < k) return fail(SGR_EINVAL, "cloud has fewer points than k");
+  HIPCHK(hipSetDevice(ctx->device));
+  if (int e = ensure_ws(ctx, poly_workspace((int)c->n, k))) return e;
+  HIPCHK(launch_poly(c->x, c->y, c->z, (int)c->n, k, out, ctx->ws, (hipStream_t)stream));
+  return SGR_OK;
+}
+
 int sgr_step_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r, int D,
                  const double* mom_t, const double* mom_r, const sgr_params* prm, int t, const sgr_pose* in,
                  sgr_pose* out, double* wrench_out, float* f_out, sgr_stream_t stream) {

@@ -199,6 +199,11 @@ hipError_t launch_vpack(const float* X, const float* Y, const float* Z, const fl
                         const float* aY, int M, int D, bool half, const Derived* dv, const double* vd, void* Bt,
                         float4* ref4, void* At, hipStream_t st);
 hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st);
+// Local polynomial descriptor: out[n][3] = (mu1, mu2, residual) of a quadric
+// fitted to the k nearest neighbours (k >= 6).
+size_t poly_workspace(int n, int k);
+hipError_t launch_poly(const float* x, const float* y, const float* z, int n, int k, float* out, void* ws,
+                       hipStream_t st);
 // Soft histogram of normals: h_out[n][D] from the k nearest neighbours.
 size_t normal_hist_workspace(int n, int k);
 hipError_t launch_normal_hist(const float* x, const float* y, const float* z, int n, int k, int D, float* h_out,

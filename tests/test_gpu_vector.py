@@ -63,6 +63,57 @@ def test_normal_histograms_match_oracle(sg, ctx, n, k, D):
     np.testing.assert_allclose(h.sum(axis=1), 1.0, rtol=1e-5)
 
 
+@pytest.mark.parametrize("n,k", [(3001, 16), (2000, 8), (700, 24)])
+def test_poly_descriptors_match_oracle(sg, ctx, n, k):
+    """Local polynomial descriptors (quadric fit in the covariance frame)
+    against the oracle on the points whose normal is determined.  The GPU
+    solves the FP64 normal equations, the oracle an SVD least-squares
+    problem; both round once to float32."""
+    P = ellipsoid_patch(n, 17).astype(np.float32)
+    d = ctx.descriptors_poly(sg.Cloud(P), k).cpu().numpy()
+    d_o, lam = O.poly_descriptors(P, k)
+    ok = (lam[:, 1] - lam[:, 0]) > 1e-3 * lam.sum(axis=1)
+    assert ok.mean() > 0.9
+    err = np.abs(d[ok] - d_o[ok]).max()
+    scale = np.abs(d_o[ok]).max()
+    print(f"poly descriptors n={n} k={k}: max abs error {err:.1e} (values up to {scale:.2f}) on {ok.mean():.1%}")
+    np.testing.assert_allclose(d[ok], d_o[ok].astype(np.float32), rtol=1e-5, atol=1e-6)
+
+
+def test_poly_descriptors_plane_full_size_and_bad_arguments(sg, ctx):
+    g = np.stack(np.meshgrid(np.arange(30), np.arange(20)), -1).reshape(-1, 2).astype(np.float32)
+    plane = np.concatenate([g, np.zeros((len(g), 1), np.float32)], axis=1)
+    d = ctx.descriptors_poly(sg.Cloud(plane), 12).cpu().numpy()
+    assert np.abs(d).max() <= 1e-6
+    pr = config2()
+    rows = np.random.default_rng(3).choice(pr.N, 80, replace=False)
+    d = ctx.descriptors_poly(sg.Cloud(pr.ref), 24).cpu().numpy()[rows]
+    d_o, lam = O.poly_descriptors(pr.ref, 24, rows)
+    ok = (lam[:, 1] - lam[:, 0]) > 1e-3 * lam.sum(axis=1)
+    np.testing.assert_allclose(d[ok], d_o[ok].astype(np.float32), rtol=1e-5, atol=1e-6)
+    for k in (5, 33):
+        with pytest.raises(sg.SgrError):
+            ctx.descriptors_poly(sg.Cloud(pr.ref), k)
+
+
+def test_register_vec_with_poly_descriptors_matches_oracle(sg, ctx):
+    pr = config1()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    aX = ctx.descriptors_poly(rf, 16)
+    aY = ctx.descriptors_poly(tm, 16)
+    prm = O.Params(p=1.0, k=16, E=60)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.cpu().numpy().astype(np.float64),
+                     aY=aY.cpu().numpy().astype(np.float64))
+    po, _, _ = O.register(pr.tmpl, S)
+    pose, _ = ctx.register_vec(tm, aY, rf, aX, sg.Params(p=1.0, k=16, E=60))
+    s, R, t = sg.pose_to_srt(pose)
+    d = O.Pose(s, R, t).apply(pr.tmpl) - po.apply(pr.tmpl)
+    err = np.sqrt(np.mean(np.sum(d * d, axis=1))) / O.diameter(pr.ref)
+    gt = O.pose_rmse(po, pr.tmpl, pr.gt_s, pr.gt_R, pr.gt_t) / O.diameter(pr.ref)
+    print(f"registration with polynomial descriptors: parity {err:.2e} D (oracle pose error {gt:.3f} D)")
+    assert err <= 1e-4
+
+
 def _vec_case(D, seed, kind):
     pr = random_pair(1300, 2900, seed=seed)         # several tiles and chunks, ragged tails
     rng = np.random.default_rng(seed)
