@@ -78,6 +78,7 @@ class Params:
     G1: float = G1_DEFAULT   # eq. 12
     E: int = 100             # number of iterations
     dt2: float = 0.0         # <= 0: 1 / G1
+    momentum: float = 0.0    # mu in [0, 1): share of the previous translation carried (0: v = 0)
 
 
 # -------------------------------------------------------------- kNN (fp32)
@@ -453,17 +454,23 @@ class StepOut:
     C: np.ndarray       # cross-covariance
 
 
-def step(Y: np.ndarray, S: Setup, t: int) -> StepOut:
+def step(Y: np.ndarray, S: Setup, t: int, d_prev=None) -> StepOut:
     """One iteration of Sec. III: forces (eq. 5), Newtonian translation
     (eq. 5.5), Kabsch rotation (eq. 6), eigenvalue scale (eq. 8), update
-    (eq. 9), with G from eq. 12."""
+    (eq. 9), with G from eq. 12.  Velocity (eq. 5.5's v^X, eq. 1's friction
+    -eta v): the template's velocity in the previous iteration is its
+    translation then, d_prev, of which the share mu = prm.momentum is carried
+    (mu = 1 - the friction's share); every point moves by it, so it shifts Y_D
+    as a whole and leaves the rotation unchanged.  mu = 0 or d_prev None is
+    the paper's v = 0."""
     prm = S.prm
     G = G_schedule(t, prm.E, prm.G1)
     dt2 = prm.dt2 if prm.dt2 > 0 else 1.0 / prm.G1
     f, U = forces(Y, S, G)
-    delta = dt2 * f                                   # per-point displacement, v = 0
+    carry = prm.momentum * np.asarray(d_prev, np.float64) if d_prev is not None else np.zeros(3)
+    delta = dt2 * f + carry                           # per-point displacement
     F = (S.mY[:, None] * f).sum(axis=0)
-    d = dt2 * F / S.mY.sum()                          # eq. 5.5
+    d = dt2 * F / S.mY.sum() + carry                  # eq. 5.5
     ybar = Y.mean(axis=0)
     Yc = Y - ybar
     YD = (Y + delta) - (Y + delta).mean(axis=0)
@@ -507,11 +514,13 @@ def register(Y0, S: Setup, E=None, pose0: Pose | None = None, t0: int = 0, keep=
     pose = Pose.identity() if pose0 is None else pose0
     Y = pose.apply(Y0)
     hist = []
+    d_prev = None                                     # the template starts at rest
     for t in range(t0, t0 + E):
         ybar = Y.mean(axis=0)
-        so = step(Y, S, t)
+        so = step(Y, S, t, d_prev)
         pose = compose(pose, so, ybar)
         Y = so.Y
+        d_prev = so.d
         if keep:
             hist.append(so)
     return pose, Y, hist

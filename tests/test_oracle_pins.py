@@ -27,6 +27,31 @@ def _setup(X, aX, aY, p=1.0, g_mode=0, sigma=0.2, eps=0.0, L=None, wX=None, mY=N
 
 
 # ------------------------------------------------------------ eqs. 3, 5, 10, 11
+@pytest.mark.parametrize("mu", [0.0, 0.5, 0.9])
+def test_velocity_state_closed_form(mu):
+    """Eq. 5.5 with the template's previous velocity (and eq. 1's friction,
+    mu = 1 - its share): with s = 1, p = 1 and unit masses the translation is
+    d_t = -G_t dt2 (ybar_t - xbar) + mu d_(t-1) (d_(-1) = 0, the template
+    starts at rest) and the centroid moves by d_t, whatever the rotation and
+    scale do, so ybar - xbar follows a scalar recurrence per axis."""
+    pr = random_pair(40, 60, seed=3)
+    X, Y0 = pr.ref.astype(np.float64), pr.tmpl.astype(np.float64)
+    rng = np.random.default_rng(0)
+    prm = O.Params(p=1.0, sigma=1e30, E=20, momentum=mu)
+    S = O.make_setup(X, Y0, prm, aX=rng.uniform(0, 0.3, 60), aY=rng.uniform(0, 0.3, 40))
+    _, _, hist = O.register(Y0, S, keep=True)
+    dt2 = 1.0 / prm.G1
+    e, d_prev = Y0.mean(0) - X.mean(0), np.zeros(3)
+    for t, so in enumerate(hist):
+        d = -O.G_schedule(t, prm.E, prm.G1) * dt2 * e + mu * d_prev
+        np.testing.assert_allclose(so.d, d, rtol=1e-9, atol=1e-12)
+        e, d_prev = e + d, d
+        np.testing.assert_allclose(so.Y.mean(0) - X.mean(0), e, rtol=1e-9, atol=1e-12)
+    if mu > 0:   # the carried velocity changes the path, not only the last digits
+        _, _, h0 = O.register(Y0, O.make_setup(X, Y0, O.Params(p=1.0, sigma=1e30, E=20), aX=S.aX, aY=S.aY), keep=True)
+        assert np.abs(h0[5].d - hist[5].d).max() > 1e-6
+
+
 def test_hand_worked_force():
     gold = json.load(open(os.path.join(HERE, "golden", "hand_force.json")))
     X = np.array(gold["reference"])
