@@ -112,6 +112,17 @@ typedef struct {
                     rounding (workspace: about 48 bytes per template point
                     per reference chunk). */
   double dt2;
+  double momentum; /* mu in [0, 1): the template's velocity state (eq. 5.5's
+                      v^X, damped by eq. 1's friction -eta v, mu = 1 - the
+                      friction's share).  Its velocity in the previous
+                      iteration is its translation d then, and every point
+                      carries mu d on top of dt2 f_i: d(t) = dt2 F / sum m +
+                      mu d(t-1); the rotation is unchanged (a shift common
+                      to all points).  The template starts at rest in every
+                      registration (and every pyramid level).  0 (default) is
+                      the paper's v = 0; calls without an iteration loop
+                      (sgr_step, plans, the adjoint, sgr_step_vec) reject
+                      mu != 0 with SGR_EINVAL. */
 } sgr_params;
 
 /* Context on HIP device `device`: owns the workspace, captured graphs and the

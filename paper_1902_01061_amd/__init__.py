@@ -34,10 +34,11 @@ class Params:
     E: int = 100
     flags: int = 0
     dt2: float = 0.0
+    momentum: float = 0.0
 
     def c(self) -> SgrParams:
         return SgrParams(float(self.p), int(self.g_mode), int(self.k), float(self.sigma), float(self.eps),
-                         float(self.G1), int(self.E), int(self.flags), float(self.dt2))
+                         float(self.G1), int(self.E), int(self.flags), float(self.dt2), float(self.momentum))
 
 
 @dataclasses.dataclass

@@ -23,7 +23,8 @@ class SgrCloud(ctypes.Structure):
 class SgrParams(ctypes.Structure):
     _fields_ = [("p", ctypes.c_double), ("g_mode", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("sigma", ctypes.c_double), ("eps", ctypes.c_double), ("G1", ctypes.c_double),
-                ("E", ctypes.c_int32), ("flags", ctypes.c_int32), ("dt2", ctypes.c_double)]
+                ("E", ctypes.c_int32), ("flags", ctypes.c_int32), ("dt2", ctypes.c_double),
+                ("momentum", ctypes.c_double)]
 
 
 class SgrLevel(ctypes.Structure):

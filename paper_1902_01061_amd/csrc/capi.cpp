@@ -90,8 +90,9 @@ int check_cloud(const sgr_cloud* c, const char* what) {
 constexpr int FLAG_PINV = 8;
 
 // allow_pinv: the caller (sgr_register, sgr_register_pyramid,
-// sgr_register_batch, sgr_multistart, sgr_register_vec) implements flags
-// bit 3, the pose-independent pair sums of the p = 1 law.
+// sgr_register_batch, sgr_multistart, sgr_register_vec) runs an iteration
+// loop: it implements flags bit 3 (the pose-independent pair sums of the
+// p = 1 law) and a velocity state (momentum).
 int check_params(const sgr_params* p, bool allow_pinv = false) {
   if (!p) return fail(SGR_EINVAL, "NULL params");
   if (!std::isfinite(p->p)) return fail(SGR_EINVAL, "p must be finite");
@@ -110,6 +111,10 @@ int check_params(const sgr_params* p, bool allow_pinv = false) {
   }
   if (!std::isfinite(p->sigma) || !std::isfinite(p->eps) || p->eps < 0) return fail(SGR_EINVAL, "bad sigma/eps");
   if (!std::isfinite(p->dt2)) return fail(SGR_EINVAL, "bad dt2");
+  if (!(p->momentum >= 0.0 && p->momentum < 1.0)) return fail(SGR_EINVAL, "momentum must be in [0, 1)");
+  if (p->momentum != 0.0 && !allow_pinv)
+    return fail(SGR_EINVAL, "a velocity state (momentum != 0) needs an iteration loop: sgr_register, "
+                            "sgr_register_pyramid, sgr_register_batch, sgr_multistart or sgr_register_vec");
   return SGR_OK;
 }
 
@@ -122,6 +127,7 @@ PrepParams prep_of(const sgr_params* p) {
   P.dt2 = p->dt2;
   P.E = p->E;
   P.g_mode = p->g_mode;
+  P.momentum = p->momentum;
   return P;
 }
 

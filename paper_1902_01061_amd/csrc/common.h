@@ -44,6 +44,8 @@ struct Derived {
   int32_t pad2;
   int32_t status;    // 0 ok; bit flags set by the update kernel
   int32_t pad;
+  double momentum;   // share of the previous translation carried (eq. 5.5's v^X); 0: v = 0
+  double dprev[3];   // the previous iteration's translation (0 at the start)
 };
 
 enum : int32_t {

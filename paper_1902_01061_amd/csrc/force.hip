@@ -108,6 +108,8 @@ __device__ inline void prepare_body(const float* __restrict__ aX, const float* _
   D.G1 = P.G1;
   D.E = (double)P.E;
   D.dt2 = P.dt2 > 0 ? P.dt2 : 1.0 / P.G1;
+  D.momentum = P.momentum;
+  D.dprev[0] = D.dprev[1] = D.dprev[2] = 0.0;
   D.p = P.p;
   D.g_mode = (double)P.g_mode;
   {

@@ -18,6 +18,7 @@ struct PrepParams {
   int32_t g_mode;
   int32_t cold_svd = 0;  // 1: the update's SVD starts cold (a deterministic function of C)
   double sigma_scale = 1.0;  // multiplies sigma (explicit or the std of the reference curvatures)
+  double momentum = 0.0;     // share of the previous translation carried by the update
 };
 
 struct ForceArgs {

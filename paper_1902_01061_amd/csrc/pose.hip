@@ -96,6 +96,9 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
       c = sqrt(D.lamX / (s * s * D.lamY0));
       double d[3];
       for (int r = 0; r < 3; ++r) d[r] = D.dt2 * W[WR_F + r] / D.Mtot;
+      // velocity state: the share D.momentum of the previous translation
+      if (D.momentum != 0.0)
+        for (int r = 0; r < 3; ++r) d[r] += D.momentum * D.dprev[r];
       // column form: y' = c Rk^T (y - ybar) + ybar + d
       double Rn[9];
       for (int r = 0; r < 3; ++r)
@@ -128,6 +131,7 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
         Pn[0] = sn;
         for (int e = 0; e < 9; ++e) Pn[1 + e] = Ro[e];
         for (int e = 0; e < 3; ++e) Pn[10 + e] = tn[e];
+        for (int e = 0; e < 3; ++e) D.dprev[e] = d[e];
       }
     }
     D.status = st;

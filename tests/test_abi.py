@@ -35,9 +35,34 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def test_binding_mirrors_header_structs():
+def test_binding_mirrors_header_structs(tmp_path):
+    """Every field offset and the size of the header's structs, as a C
+    compiler lays them out, against the ctypes mirrors."""
+    import shutil
+    import subprocess
+
     from paper_1902_01061_amd import _ffi
-    assert ctypes.sizeof(_ffi.SgrCloud) == 40
-    assert ctypes.sizeof(_ffi.SgrParams) == 56
     for n in _ffi.SIGNATURES:
         assert n in _declared()
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"sgr_cloud": _ffi.SgrCloud, "sgr_params": _ffi.SgrParams, "sgr_level": _ffi.SgrLevel}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sgreg.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
