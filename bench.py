@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 METRIC = "shape-weighted pair interactions/sec per iteration; ms/registration at fixed RMSE"
 PEAK_FP32_TFLOPS = 157.3        # MI355X published FP32 vector peak
-# Without packed FP32 (disabled for every HIP unit of this build) a lane
+# Without packed FP32 (every HIP unit of the library is compiled without it) a lane
 # retires one FP32 FMA per clock: 256 CU x 64 lanes x 2 flops x 2.4 GHz.
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one VALU issue slot per lane per clock
@@ -488,7 +488,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only: the registration hot path runs on a single "
+        print(json.dumps({"error": "bench.py measures one GPU only: the registration hot path runs on a single "
                                    "MI355X (multi-GPU sharding is a design note, not implemented)",
                           "n_gpus": args.gpus}))
         return 2

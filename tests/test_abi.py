@@ -29,7 +29,7 @@ def test_headers_declare_the_api():
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(LIB):
-        pytest.fail("libsgreg.so is not built (run __graft_entry__.build())")
+        pytest.fail("libsgreg.so is not built (run build.py)")
     lib = ctypes.CDLL(LIB)
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
