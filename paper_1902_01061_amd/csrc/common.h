@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #define SGR_HD __host__ __device__ inline
+#define SGR_HDI __host__ __device__ inline __attribute__((always_inline))
 
 namespace sgr {
 
@@ -72,12 +73,59 @@ SGR_HD void cross3(const double a[3], const double b[3], double o[3]) {
   o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// One Jacobi rotation of the column pair (p, q) of a (and of v): makes the
+// two columns orthogonal.  off receives the largest relative
+// non-orthogonality met.  Every index is a constant at its call sites, so the
+// columns stay in registers.
+SGR_HDI void jacobi_pair(double (&ap)[3], double (&aq)[3], double (&vp)[3], double (&vq)[3], double& off) {
+  double al = 0, be = 0, ga = 0;
+  for (int r = 0; r < 3; ++r) {
+    al += ap[r] * ap[r];
+    be += aq[r] * aq[r];
+    ga += ap[r] * aq[r];
+  }
+  if (ga == 0.0) return;
+  const double rel = fabs(ga) / sqrt(al * be);
+  if (!(rel > 1e-17)) return;
+  off = fmax(off, rel);
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+  for (int r = 0; r < 3; ++r) {
+    const double a0 = ap[r], a1 = aq[r];
+    ap[r] = c * a0 - s * a1;
+    aq[r] = s * a0 + c * a1;
+    const double v0 = vp[r], v1 = vq[r];
+    vp[r] = c * v0 - s * v1;
+    vq[r] = s * v0 + c * v1;
+  }
+}
+
+// Swap columns i and j (and their norms) when n[i] < n[j].
+SGR_HDI void order_pair(double (&ni)[1], double (&nj)[1], double (&ai)[3], double (&aj)[3], double (&vi)[3],
+                        double (&vj)[3]) {
+  if (ni[0] < nj[0]) {
+    const double t = ni[0];
+    ni[0] = nj[0];
+    nj[0] = t;
+    for (int r = 0; r < 3; ++r) {
+      const double x = ai[r];
+      ai[r] = aj[r];
+      aj[r] = x;
+      const double y = vi[r];
+      vi[r] = vj[r];
+      vj[r] = y;
+    }
+  }
+}
+
 // One-sided (Hestenes) Jacobi SVD of a 3x3 matrix A (row-major):
 // A = U diag(sv) V^T with sv sorted descending.  U and V are returned
 // column-major in the sense u[k][*] = k-th left singular vector.  A column of
 // A that collapses to zero leaves its u[k] undefined (set to 0); callers
 // only use the vectors of non-zero singular values.
-SGR_HD void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3][3], const double* V0 = nullptr) {
+SGR_HDI void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3][3], const double* V0 = nullptr) {
   double a[3][3];  // a[col][row]
   double vv[3][3]; // vv[col][row]
   // start from V0 (row-major, columns = right singular vectors of a nearby
@@ -90,47 +138,23 @@ SGR_HD void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3]
       a[c][r] = A_in[r * 3 + 0] * vv[c][0] + A_in[r * 3 + 1] * vv[c][1] + A_in[r * 3 + 2] * vv[c][2];
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0;
-    for (int pq = 0; pq < 3; ++pq) {
-      const int p = (pq == 2) ? 1 : 0;
-      const int q = (pq == 0) ? 1 : 2;
-      double al = 0, be = 0, ga = 0;
-      for (int r = 0; r < 3; ++r) {
-        al += a[p][r] * a[p][r];
-        be += a[q][r] * a[q][r];
-        ga += a[p][r] * a[q][r];
-      }
-      if (ga == 0.0) continue;
-      const double rel = fabs(ga) / sqrt(al * be);
-      if (!(rel > 1e-17)) continue;
-      off = fmax(off, rel);
-      const double zeta = (be - al) / (2.0 * ga);
-      const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double c = 1.0 / sqrt(1.0 + t * t);
-      const double s = c * t;
-      for (int r = 0; r < 3; ++r) {
-        const double ap = a[p][r], aq = a[q][r];
-        a[p][r] = c * ap - s * aq;
-        a[q][r] = s * ap + c * aq;
-        const double vp = vv[p][r], vq = vv[q][r];
-        vv[p][r] = c * vp - s * vq;
-        vv[q][r] = s * vp + c * vq;
-      }
-    }
+    // cyclic order (0, 1), (0, 2), (1, 2)
+    jacobi_pair(a[0], a[1], vv[0], vv[1], off);
+    jacobi_pair(a[0], a[2], vv[0], vv[2], off);
+    jacobi_pair(a[1], a[2], vv[1], vv[2], off);
     if (off < 1e-15) break;
   }
-  double n[3];
-  for (int c = 0; c < 3; ++c) n[c] = sqrt(a[c][0] * a[c][0] + a[c][1] * a[c][1] + a[c][2] * a[c][2]);
-  int o[3] = {0, 1, 2};
-  // sort descending (3 elements)
-  if (n[o[0]] < n[o[1]]) { int t = o[0]; o[0] = o[1]; o[1] = t; }
-  if (n[o[1]] < n[o[2]]) { int t = o[1]; o[1] = o[2]; o[2] = t; }
-  if (n[o[0]] < n[o[1]]) { int t = o[0]; o[0] = o[1]; o[1] = t; }
+  double n[3][1];
+  for (int c = 0; c < 3; ++c) n[c][0] = sqrt(a[c][0] * a[c][0] + a[c][1] * a[c][1] + a[c][2] * a[c][2]);
+  // sort descending (3 elements): the columns themselves are exchanged
+  order_pair(n[0], n[1], a[0], a[1], vv[0], vv[1]);
+  order_pair(n[1], n[2], a[1], a[2], vv[1], vv[2]);
+  order_pair(n[0], n[1], a[0], a[1], vv[0], vv[1]);
   for (int k = 0; k < 3; ++k) {
-    const int c = o[k];
-    sv[k] = n[c];
+    sv[k] = n[k][0];
     for (int r = 0; r < 3; ++r) {
-      u[k][r] = n[c] > 0 ? a[c][r] / n[c] : 0.0;
-      v[k][r] = vv[c][r];
+      u[k][r] = n[k][0] > 0 ? a[k][r] / n[k][0] : 0.0;
+      v[k][r] = vv[k][r];
     }
   }
 }
@@ -138,7 +162,7 @@ SGR_HD void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3]
 // Eigenvalues of a symmetric positive semi-definite 3x3 matrix given as
 // (xx, yy, zz, xy, xz, yz): for such matrices the singular values are the
 // eigenvalues.  Returns them descending.
-SGR_HD void eig_psd3(const double S6[6], double lam[3]) {
+SGR_HDI void eig_psd3(const double S6[6], double lam[3]) {
   const double A[9] = {S6[0], S6[3], S6[4], S6[3], S6[1], S6[5], S6[4], S6[5], S6[2]};
   double u[3][3], v[3][3];
   svd3(A, lam, u, v);
@@ -149,7 +173,7 @@ SGR_HD void eig_psd3(const double S6[6], double lam[3]) {
 // singular pairs: R = v1 u1^T + v2 u2^T + (v1 x v2)(u1 x u2)^T, which is
 // the same matrix and needs no sign bookkeeping.  Returns false if C has
 // rank < 2 (the rotation is then not determined).
-SGR_HD bool kabsch_rot(const double C[9], double R[9], double* Vwarm = nullptr) {
+SGR_HDI bool kabsch_rot(const double C[9], double R[9], double* Vwarm = nullptr) {
   double sv[3], u[3][3], v[3][3];
   svd3(C, sv, u, v, Vwarm);
   if (Vwarm) {

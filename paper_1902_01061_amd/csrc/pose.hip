@@ -21,41 +21,73 @@ __device__ inline double G_sched(const Derived& D, int t) {
 }
 
 // Sum of `n` wrench partial rows (WR_STRIDE doubles each) starting at
-// `wpart`, in a fixed order; the result W[0..12] is valid in thread 0 only.
-// The rows are read as one contiguous array: thread t always takes component
-// t % 16 (BT is a multiple of 64 and WR_STRIDE is 16) of rows t / 16,
-// t / 16 + BT / 16, ..., so each wave load is 512 contiguous bytes; the four
-// lanes of a wave that hold the same component are added by shuffles, then
-// the waves in order through LDS (lds: BT / 4 doubles).  Components 13..15
-// are padding and are summed but not used.
-template <int BT>
+// `wpart` (16-byte aligned), in a fixed order; the result W[0..12] is valid
+// in thread 0 only.  The rows are read as one contiguous array of double
+// pairs: thread t always takes the pair 2 (t % 8), 2 (t % 8) + 1 (BT is a
+// multiple of 64 and WR_STRIDE is 16) of rows t / 8, t / 8 + BT / 8, ...,
+// U loads in flight per thread, since the rows were written by blocks on
+// every XCD and each round trip is long.  The eight lanes of a wave that
+// hold the same pair are added by shuffles, then the waves in order through
+// LDS (lds: BT / 4 doubles).  Components 13..15 are padding and are summed
+// but not used.
+template <int BT, int U>
 __device__ inline void sum_partials(const double* __restrict__ wpart, int n, double* lds, double W[13]) {
-  static_assert(WR_STRIDE == 16 && BT % 64 == 0, "one component per lane");
-  double v = 0.0;
-  const int64_t total = (int64_t)n * WR_STRIDE;
-#pragma unroll 4
-  for (int64_t e = threadIdx.x; e < total; e += BT) v += wpart[e];
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
+  static_assert(WR_STRIDE == 16 && BT % 64 == 0, "one component pair per lane");
+  const double2* __restrict__ p = reinterpret_cast<const double2*>(wpart);
+  const int total = n * (WR_STRIDE / 2);
+  double a = 0.0, b = 0.0;
+  for (int base = threadIdx.x; base < total; base += U * BT) {
+    double2 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int e = base + k * BT;
+      v[k] = e < total ? p[e] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      a += v[k].x;
+      b += v[k].y;
+    }
+  }
+#pragma unroll
+  for (int off = 8; off < 64; off <<= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane < 16) lds[w * 16 + lane] = v;
+  if (lane < 8) {
+    lds[w * 16 + 2 * lane] = a;
+    lds[w * 16 + 2 * lane + 1] = b;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int e = 0; e < 13; ++e) {
-      double a = 0.0;
-      for (int ww = 0; ww < BT / 64; ++ww) a += lds[ww * 16 + e];
-      W[e] = a;
+      double s = 0.0;
+      for (int ww = 0; ww < BT / 64; ++ww) s += lds[ww * 16 + e];
+      W[e] = s;
     }
   }
 }
 
-// The update itself (one thread).
+// The update itself (one thread).  Every field of the constant block it
+// reads is loaded into registers first, and the three it changes (status,
+// warm-start vectors, previous translation) are stored at the end: reading
+// them in place would order each later load behind those stores.
 __device__ void pose_update(const double W[13], const double* __restrict__ pose_in, double* __restrict__ pose_out,
                             Derived* __restrict__ dv, int t, double G_fixed, int do_update,
                             double* __restrict__ wrench_out, double* __restrict__ stats_row) {
-  Derived& D = *dv;
-  const double G = G_fixed > 0 ? G_fixed : G_sched(D, t);
+  const double G = G_fixed > 0 ? G_fixed : G_sched(*dv, t);
+  const bool cold = dv->cold_svd != 0;
+  double ybar0[3], SigY0[6], Vw[9], dprev[3];
+  for (int e = 0; e < 3; ++e) ybar0[e] = dv->ybar0[e];
+  for (int e = 0; e < 6; ++e) SigY0[e] = dv->SigY0[e];
+  // cold: the SVD starts from the identity, which is what it does without a
+  // warm start, to the bit
+  for (int e = 0; e < 9; ++e) Vw[e] = cold ? ((e % 4 == 0) ? 1.0 : 0.0) : dv->Vw[e];
+  for (int e = 0; e < 3; ++e) dprev[e] = dv->dprev[e];
+  const double Mcount = dv->Mcount, dt2 = dv->dt2, lamX = dv->lamX, lamY0 = dv->lamY0, Mtot = dv->Mtot,
+               momentum = dv->momentum;
   if (wrench_out) {
     for (int e = 0; e < 13; ++e) wrench_out[e] = W[e];
   }
@@ -64,7 +96,7 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
   double Pn[13];
   for (int e = 0; e < 13; ++e) Pn[e] = P[e];
   double c = 1.0;
-  int32_t st = D.status;
+  int32_t st = dv->status;
   if (do_update && st == 0) {
     const double s = P[0];
     const double* R = P + 1;
@@ -74,9 +106,9 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
     // ybar = s R ybar0 + t ; Sigma_Y = s^2 R Sigma_Y0 R^T
     double yb[3];
     for (int r = 0; r < 3; ++r)
-      yb[r] = s * (R[3 * r] * D.ybar0[0] + R[3 * r + 1] * D.ybar0[1] + R[3 * r + 2] * D.ybar0[2]) + tv[r];
-    const double S0[9] = {D.SigY0[0], D.SigY0[3], D.SigY0[4], D.SigY0[3], D.SigY0[1],
-                          D.SigY0[5], D.SigY0[4], D.SigY0[5], D.SigY0[2]};
+      yb[r] = s * (R[3 * r] * ybar0[0] + R[3 * r + 1] * ybar0[1] + R[3 * r + 2] * ybar0[2]) + tv[r];
+    const double S0[9] = {SigY0[0], SigY0[3], SigY0[4], SigY0[3], SigY0[1],
+                          SigY0[5], SigY0[4], SigY0[5], SigY0[2]};
     double RS[9];
     for (int r = 0; r < 3; ++r)
       for (int q = 0; q < 3; ++q) RS[3 * r + q] = R[3 * r] * S0[q] + R[3 * r + 1] * S0[3 + q] + R[3 * r + 2] * S0[6 + q];
@@ -84,21 +116,21 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
     for (int r = 0; r < 3; ++r)
       for (int q = 0; q < 3; ++q) {
         const double sig = s * s * (RS[3 * r] * R[3 * q] + RS[3 * r + 1] * R[3 * q + 1] + RS[3 * r + 2] * R[3 * q + 2]);
-        C[3 * r + q] = D.Mcount * sig + D.dt2 * W[WR_K + 3 * r + q];
+        C[3 * r + q] = Mcount * sig + dt2 * W[WR_K + 3 * r + q];
       }
     for (int e = 0; e < 9; ++e) ok &= isfinite(C[e]);
     double Rk[9];
     if (!ok) {
       st |= ST_NONFINITE;
-    } else if (!kabsch_rot(C, Rk, D.cold_svd ? nullptr : D.Vw)) {
+    } else if (!kabsch_rot(C, Rk, Vw)) {
       st |= ST_SINGULAR;
     } else {
-      c = sqrt(D.lamX / (s * s * D.lamY0));
+      c = sqrt(lamX / (s * s * lamY0));
       double d[3];
-      for (int r = 0; r < 3; ++r) d[r] = D.dt2 * W[WR_F + r] / D.Mtot;
-      // velocity state: the share D.momentum of the previous translation
-      if (D.momentum != 0.0)
-        for (int r = 0; r < 3; ++r) d[r] += D.momentum * D.dprev[r];
+      for (int r = 0; r < 3; ++r) d[r] = dt2 * W[WR_F + r] / Mtot;
+      // velocity state: the share momentum of the previous translation
+      if (momentum != 0.0)
+        for (int r = 0; r < 3; ++r) d[r] += momentum * dprev[r];
       // column form: y' = c Rk^T (y - ybar) + ybar + d
       double Rn[9];
       for (int r = 0; r < 3; ++r)
@@ -131,10 +163,13 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
         Pn[0] = sn;
         for (int e = 0; e < 9; ++e) Pn[1 + e] = Ro[e];
         for (int e = 0; e < 3; ++e) Pn[10 + e] = tn[e];
-        for (int e = 0; e < 3; ++e) D.dprev[e] = d[e];
+        for (int e = 0; e < 3; ++e) dprev[e] = d[e];
       }
     }
-    D.status = st;
+    dv->status = st;
+    if (!cold)
+      for (int e = 0; e < 9; ++e) dv->Vw[e] = Vw[e];
+    for (int e = 0; e < 3; ++e) dv->dprev[e] = dprev[e];
   }
   if (pose_out) {
     for (int e = 0; e < 13; ++e) pose_out[e] = Pn[e];
@@ -150,13 +185,16 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
   }
 }
 
-__global__ __launch_bounds__(1024) void update_kernel(const double* __restrict__ wpart, int nblk,
+// 512 threads: the single-thread update keeps its FP64 state in registers
+// (a 1024-thread block would cap it at 128 VGPRs and spill), and 32 loads in
+// flight per thread still read up to 2048 partial rows in one round.
+__global__ __launch_bounds__(512) void update_kernel(const double* __restrict__ wpart, int nblk,
                                                       const double* __restrict__ pose_in, double* __restrict__ pose_out,
                                                       Derived* __restrict__ dv, int t, double G_fixed, int do_update,
                                                       double* __restrict__ wrench_out, double* __restrict__ stats_row) {
-  __shared__ double lds[1024 / 4];
+  __shared__ double lds[512 / 4];
   double W[13];
-  sum_partials<1024>(wpart, nblk, lds, W);
+  sum_partials<512, 32>(wpart, nblk, lds, W);
   if (threadIdx.x == 0) pose_update(W, pose_in, pose_out, dv, t, G_fixed, do_update, wrench_out, stats_row);
 }
 
@@ -171,7 +209,7 @@ __global__ __launch_bounds__(256) void update_batch_kernel(const double* __restr
   const int r = blockIdx.x;
   const RegDesc& g = regs[r];
   double W[13];
-  sum_partials<256>(wpart + (int64_t)g.wslot0 * WR_STRIDE, g.n_items, lds, W);
+  sum_partials<256, 16>(wpart + (int64_t)g.wslot0 * WR_STRIDE, g.n_items, lds, W);
   if (threadIdx.x == 0) {
     double* pose = poses + 13 * (int64_t)r;
     pose_update(W, pose, pose, dvs + r, t, 0.0, do_update, nullptr,
@@ -262,7 +300,7 @@ hipError_t launch_identity_pose(double* pose, hipStream_t st) {
 
 hipError_t launch_update(const double* wpart, int nblk, const double* pose_in, double* pose_out, Derived* dv, int t,
                          double G_fixed, int do_update, double* wrench_out, double* stats_row, hipStream_t st) {
-  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(1024), 0, st, wpart, nblk, pose_in, pose_out, dv, t, G_fixed,
+  hipLaunchKernelGGL(update_kernel, dim3(1), dim3(512), 0, st, wpart, nblk, pose_in, pose_out, dv, t, G_fixed,
                      do_update, wrench_out, stats_row);
   return hipGetLastError();
 }
