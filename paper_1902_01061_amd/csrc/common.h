@@ -74,20 +74,21 @@ SGR_HD void cross3(const double a[3], const double b[3], double o[3]) {
 }
 
 // One Jacobi rotation of the column pair (p, q) of a (and of v): makes the
-// two columns orthogonal.  off receives the largest relative
-// non-orthogonality met.  Every index is a constant at its call sites, so the
-// columns stay in registers.
-SGR_HDI void jacobi_pair(double (&ap)[3], double (&aq)[3], double (&vp)[3], double (&vq)[3], double& off) {
+// two columns orthogonal.  The relative non-orthogonality |ga| / sqrt(al be)
+// is compared with its thresholds in squares (no square root or division):
+// below 1e-17 the pair is left alone, at 1e-15 or above `more` is set (the
+// sweeps have not converged).  Every index is a constant at its call sites,
+// so the columns stay in registers.
+SGR_HDI void jacobi_pair(double (&ap)[3], double (&aq)[3], double (&vp)[3], double (&vq)[3], bool& more) {
   double al = 0, be = 0, ga = 0;
   for (int r = 0; r < 3; ++r) {
     al += ap[r] * ap[r];
     be += aq[r] * aq[r];
     ga += ap[r] * aq[r];
   }
-  if (ga == 0.0) return;
-  const double rel = fabs(ga) / sqrt(al * be);
-  if (!(rel > 1e-17)) return;
-  off = fmax(off, rel);
+  const double g2 = ga * ga, ab = al * be;
+  if (!(g2 > 1e-34 * ab)) return;
+  if (g2 >= 1e-30 * ab) more = true;
   const double zeta = (be - al) / (2.0 * ga);
   const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double c = 1.0 / sqrt(1.0 + t * t);
@@ -137,12 +138,12 @@ SGR_HDI void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3
     for (int r = 0; r < 3; ++r)
       a[c][r] = A_in[r * 3 + 0] * vv[c][0] + A_in[r * 3 + 1] * vv[c][1] + A_in[r * 3 + 2] * vv[c][2];
   for (int sweep = 0; sweep < 30; ++sweep) {
-    double off = 0.0;
+    bool more = false;
     // cyclic order (0, 1), (0, 2), (1, 2)
-    jacobi_pair(a[0], a[1], vv[0], vv[1], off);
-    jacobi_pair(a[0], a[2], vv[0], vv[2], off);
-    jacobi_pair(a[1], a[2], vv[1], vv[2], off);
-    if (off < 1e-15) break;
+    jacobi_pair(a[0], a[1], vv[0], vv[1], more);
+    jacobi_pair(a[0], a[2], vv[0], vv[2], more);
+    jacobi_pair(a[1], a[2], vv[1], vv[2], more);
+    if (!more) break;
   }
   double n[3][1];
   for (int c = 0; c < 3; ++c) n[c][0] = sqrt(a[c][0] * a[c][0] + a[c][1] * a[c][1] + a[c][2] * a[c][2]);
