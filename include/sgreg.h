@@ -158,9 +158,12 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
              int t, const sgr_pose* in, sgr_pose* out, double* wrench_out, float* f_out,
              sgr_stream_t stream);
 
-/* "register(template, reference, params) -> pose": descriptors of both
- * clouds, then E iterations from the pose in `inout` (device), written back
- * in place.  stats (nullable, device float64 [E][32]): per iteration G_t,
+/* "register(template, reference, params) -> pose" (Sec. I's problem: the
+ * translation, rotation and scale that align the template to the
+ * reference): curvature descriptors of both clouds (Sec. III-A), then E
+ * iterations of Sec. III from the pose in `inout` (device), written back in
+ * place: the shape-weighted force (eqs. 3, 5, 10, 11), translation (eq.
+ * 5.5), rotation (eq. 6), scale (eq. 8), update (eq. 9), G from eq. 12.  stats (nullable, device float64 [E][32]): per iteration G_t,
  * F[3], K[9], U, the pose after the update (13), the scale factor c and the
  * status word.  Synchronises the stream at the end to read the device
  * status word; SGR_ENUMERIC if an update went non-finite or rank deficient
@@ -275,7 +278,10 @@ int sgr_step_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
 int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
                      int D, const sgr_params* prm, sgr_pose* inout, double* stats, sgr_stream_t stream);
 
-/* "residual": with corr (int32[M], -1 = none): sqrt(mean |T(y_i) - x_corr(i)|^2)
+/* "residual": the root mean square error by which Sec. V scores a
+ * registration (its protocol follows a reference that is not given, so the
+ * two usual forms are offered).
+ * With corr (int32[M], -1 = none): sqrt(mean |T(y_i) - x_corr(i)|^2)
  * over i with corr >= 0; with corr == NULL: one-sided nearest-neighbour RMSE
  * template -> reference (nearest by float32 distance of the float32-rounded
  * transformed point, the distance itself in float64).  rmse_out: device

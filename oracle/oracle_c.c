@@ -9,7 +9,9 @@
  *   Sec. IV / eq. (10), s from eq. (3) and the distance law of eqs. (4),
  *   (11): f_i = coef * sum_j w_j g_ij ((|r|^2+eps^2)/L^2)^((p-1)/2) r_ij,
  *   r_ij = y_i - x_j, coef = -(G/Z); the energy
- *   U = (G/Z) sum_ij w_j g_ij L^(1-p) q^((p+1)/2) / (p+1).
+ *   U = (G/Z) sum_ij w_j g_ij L^(1-p) q^((p+1)/2) / (p+1);
+ *   optionally (s_out != NULL) the absolute-sum scale of each force,
+ *   s_i = (G/Z) sum_j |w_j g_ij h_ij| |r_ij|.
  * ora_knn: k nearest neighbours in float32 squared distance, evaluated as
  *   ((dx*dx + dy*dy) + dz*dz) with every operation rounded to float32 (the
  *   file is compiled with -ffp-contract=off), ties broken by index.
@@ -22,12 +24,12 @@
 void ora_forces(int64_t M, int64_t N, const double* Y, const double* aY, const double* X,
                 const double* aX, const double* wX, double p, int g_mode, double sigma,
                 double eps, double L, double abar, double G, double Z, double* f_out,
-                double* U_out) {
+                double* U_out, double* s_out) {
   double Utot = 0.0;
   const double hp = 0.5 * (p - 1.0);
 #pragma omp parallel for schedule(static) reduction(+ : Utot)
   for (int64_t i = 0; i < M; ++i) {
-    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, u = 0.0, sa = 0.0;
     for (int64_t j = 0; j < N; ++j) {
       double rx = Y[3 * i + 0] - X[3 * j + 0];
       double ry = Y[3 * i + 1] - X[3 * j + 1];
@@ -42,7 +44,9 @@ void ora_forces(int64_t M, int64_t N, const double* Y, const double* aY, const d
       fy += c * ry;
       fz += c * rz;
       u += c * q;
+      if (s_out) sa += fabs(c) * sqrt(rx * rx + ry * ry + rz * rz);
     }
+    if (s_out) s_out[i] = (G / Z) * sa;
     f_out[3 * i + 0] = -(G / Z) * fx;
     f_out[3 * i + 1] = -(G / Z) * fy;
     f_out[3 * i + 2] = -(G / Z) * fz;

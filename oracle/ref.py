@@ -388,6 +388,22 @@ def forces(Y: np.ndarray, S: Setup, G: float, rows=None, block: int = 256):
     return f, U
 
 
+def force_scale(Y: np.ndarray, S: Setup, G: float, rows=None, block: int = 256) -> np.ndarray:
+    """Absolute-sum scale of each force of eq. 5: S_i = (G/Z) sum_j
+    |w_j g_ij h_ij| |y_i - x_j|, the sum of the norms of the terms whose
+    vector sum is f_i, so |f_i| <= S_i, with equality when all r_ij point the
+    same way.  Rounding in any evaluation of f_i that adds the terms in
+    another order is bounded relative to S_i, not to |f_i| (which cancels)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    rows = np.arange(len(Y)) if rows is None else np.asarray(rows)
+    out = np.empty(len(rows))
+    for b0 in range(0, len(rows), block):
+        rr = rows[b0:b0 + block]
+        r, _, c = pair_weights(Y[rr], S.aY[rr], S)
+        out[b0:b0 + block] = (G / S.Z) * np.sum(np.abs(c) * np.sqrt(np.einsum("bnk,bnk->bn", r, r)), axis=1)
+    return out
+
+
 def force_vjp(Y: np.ndarray, S: Setup, G: float, gf: np.ndarray, gF: np.ndarray, gK: np.ndarray, block: int = 256):
     """Gradient of L = sum_i gf_i . f_i + gF . F + sum_ab gK_ab K_ab, with
     F = sum_i m_i f_i and K = sum_i f_i (y_i - ybar)^T (ybar the unweighted
@@ -614,7 +630,7 @@ def _clib():
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         D = ctypes.c_double
-        _LIB.ora_forces.argtypes = [I64, I64, P, P, P, P, P, D, ctypes.c_int, D, D, D, D, D, D, P, P]
+        _LIB.ora_forces.argtypes = [I64, I64, P, P, P, P, P, D, ctypes.c_int, D, D, D, D, D, D, P, P, P]
         _LIB.ora_knn.argtypes = [I64, P, ctypes.c_int, I64, P, P]
         _LIB.ora_threads.restype = ctypes.c_int
         _LIB.ora_set_threads.argtypes = [ctypes.c_int]
@@ -634,8 +650,9 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def forces_c(Y: np.ndarray, S: Setup, G: float, rows=None):
-    """forces() evaluated by the plain C loops (OpenMP); same definition."""
+def forces_c(Y: np.ndarray, S: Setup, G: float, rows=None, want_scale: bool = False):
+    """forces() evaluated by the plain C loops (OpenMP); same definition.
+    With want_scale, also force_scale() of the same rows: (f, U, scale)."""
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     aY = np.ascontiguousarray(S.aY)
     if rows is not None:
@@ -645,10 +662,14 @@ def forces_c(Y: np.ndarray, S: Setup, G: float, rows=None):
     X = np.ascontiguousarray(S.X)
     f = np.empty((len(Y), 3))
     U = np.zeros(1)
+    sc = np.empty(len(Y)) if want_scale else None
     prm = S.prm
     _clib().ora_forces(len(Y), len(X), _ptr(Y), _ptr(aY), _ptr(X), _ptr(np.ascontiguousarray(S.aX)),
                        _ptr(np.ascontiguousarray(S.wX)), float(prm.p), int(prm.g_mode), S.sigma,
-                       float(prm.eps), S.L, S.abar, float(G), S.Z, _ptr(f), _ptr(U))
+                       float(prm.eps), S.L, S.abar, float(G), S.Z, _ptr(f), _ptr(U),
+                       _ptr(sc) if want_scale else None)
+    if want_scale:
+        return f, float(U[0]), sc
     return f, float(U[0])
 
 

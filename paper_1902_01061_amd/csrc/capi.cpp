@@ -555,24 +555,29 @@ int run_single_loop(sgr_ctx* ctx, GraphCache& gc, const sgr_cloud* tmpl, const s
     return SGR_OK;
   };
   if ((prm->flags & FLAG_NO_GRAPH) || t1 - t0 < 2) return loop(st);
+  // The captured kernels read every buffer below at a fixed address, so the
+  // key holds all of them: the workspace layout depends on more than the
+  // clouds and parameters (the neighbour search's k, radius levels).
   struct Key {
     const void* p[10];
+    const void* wsp[11];
     int64_t n[2];
     int32_t t[2];
     sgr_params prm;
-    Tiles T;
-    void* ws;
+    Tiles T, TM;
   } key;
   std::memset(&key, 0, sizeof(key));
   const void* ptrs[10] = {tmpl->x, tmpl->y, tmpl->z, tmpl->m, ref->x, ref->y, ref->z, ref->m, inout, stats};
   std::memcpy(key.p, ptrs, sizeof(ptrs));
+  const void* wptrs[11] = {w.aY, w.dv, w.ref4, w.lw, w.wpart, w.perm, w.tm4, w.tmx, w.ps_S, w.aX, w.mom};
+  std::memcpy(key.wsp, wptrs, sizeof(wptrs));
   key.n[0] = M;
   key.n[1] = N;
   key.t[0] = t0;
   key.t[1] = t1;
   key.prm = *prm;
   key.T = w.T;
-  key.ws = ctx->ws;
+  key.TM = w.TM;
   std::vector<uint8_t> kb((uint8_t*)&key, (uint8_t*)&key + sizeof(key));
   return run_graph(ctx, gc, kb, loop, st);
 }

@@ -129,6 +129,19 @@ SGR_HDI void order_pair(double (&ni)[1], double (&nj)[1], double (&ai)[3], doubl
 SGR_HDI void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3][3], const double* V0 = nullptr) {
   double a[3][3];  // a[col][row]
   double vv[3][3]; // vv[col][row]
+  // The rotation tests compare products of squared column norms, which
+  // under- or overflow for entries far from 1 (below about 1e-77 or above
+  // 1e77).  A is therefore scaled by an exact power of two that brings its
+  // largest |entry| into [0.5, 1); the singular values are scaled back at
+  // the end, and the singular vectors do not change.
+  int ex = 0;
+  {
+    double amax = 0.0;
+    for (int e = 0; e < 9; ++e) amax = fmax(amax, fabs(A_in[e]));
+    if (amax > 0.0 && amax <= 1.7976931348623157e308) (void)frexp(amax, &ex);
+  }
+  double As[9];
+  for (int e = 0; e < 9; ++e) As[e] = ldexp(A_in[e], -ex);
   // start from V0 (row-major, columns = right singular vectors of a nearby
   // matrix) when given: A V0 is then nearly column-orthogonal and the
   // rotations below converge in one or two sweeps
@@ -136,7 +149,7 @@ SGR_HDI void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3
     for (int r = 0; r < 3; ++r) vv[c][r] = V0 ? V0[r * 3 + c] : ((r == c) ? 1.0 : 0.0);
   for (int c = 0; c < 3; ++c)
     for (int r = 0; r < 3; ++r)
-      a[c][r] = A_in[r * 3 + 0] * vv[c][0] + A_in[r * 3 + 1] * vv[c][1] + A_in[r * 3 + 2] * vv[c][2];
+      a[c][r] = As[r * 3 + 0] * vv[c][0] + As[r * 3 + 1] * vv[c][1] + As[r * 3 + 2] * vv[c][2];
   for (int sweep = 0; sweep < 30; ++sweep) {
     bool more = false;
     // cyclic order (0, 1), (0, 2), (1, 2)
@@ -152,7 +165,7 @@ SGR_HDI void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3
   order_pair(n[1], n[2], a[1], a[2], vv[1], vv[2]);
   order_pair(n[0], n[1], a[0], a[1], vv[0], vv[1]);
   for (int k = 0; k < 3; ++k) {
-    sv[k] = n[k][0];
+    sv[k] = ldexp(n[k][0], ex);
     for (int r = 0; r < 3; ++r) {
       u[k][r] = n[k][0] > 0 ? a[k][r] / n[k][0] : 0.0;
       v[k][r] = vv[k][r];

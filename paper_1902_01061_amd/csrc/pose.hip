@@ -73,8 +73,11 @@ __device__ inline void sum_partials(const double* __restrict__ wpart, int n, dou
 // The update itself (one thread).  Every field of the constant block it
 // reads is loaded into registers first, and the three it changes (status,
 // warm-start vectors, previous translation) are stored at the end: reading
-// them in place would order each later load behind those stores.
-__device__ void pose_update(const double W[13], const double* __restrict__ pose_in, double* __restrict__ pose_out,
+// them in place would order each later load behind those stores.  pose_in
+// and pose_out may be the same array (the pose is updated in place), so
+// neither is declared __restrict__; the pose is read into registers before
+// anything is stored.
+__device__ void pose_update(const double W[13], const double* pose_in, double* pose_out,
                             Derived* __restrict__ dv, int t, double G_fixed, int do_update,
                             double* __restrict__ wrench_out, double* __restrict__ stats_row) {
   const double G = G_fixed > 0 ? G_fixed : G_sched(*dv, t);
@@ -189,7 +192,7 @@ __device__ void pose_update(const double W[13], const double* __restrict__ pose_
 // (a 1024-thread block would cap it at 128 VGPRs and spill), and 32 loads in
 // flight per thread still read up to 2048 partial rows in one round.
 __global__ __launch_bounds__(512) void update_kernel(const double* __restrict__ wpart, int nblk,
-                                                      const double* __restrict__ pose_in, double* __restrict__ pose_out,
+                                                      const double* pose_in, double* pose_out,
                                                       Derived* __restrict__ dv, int t, double G_fixed, int do_update,
                                                       double* __restrict__ wrench_out, double* __restrict__ stats_row) {
   __shared__ double lds[512 / 4];
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(512) void update_kernel(const double* __restrict__ 
 // One block per registration of a batch; its items own the wrench slots
 // [wslot0, wslot0 + n_items).  energy_out[r] (nullable) receives U.
 __global__ __launch_bounds__(256) void update_batch_kernel(const double* __restrict__ wpart,
-                                                           const RegDesc* __restrict__ regs, double* __restrict__ poses,
+                                                           const RegDesc* __restrict__ regs, double* poses,
                                                            Derived* __restrict__ dvs, int t, int do_update,
                                                            double* __restrict__ energy_out, double* __restrict__ stats,
                                                            int E) {

@@ -173,3 +173,30 @@ def test_pyramid_and_radius_reject_bad_arguments(sg, ctx):
     for r2 in (-1.0, float("inf"), float("nan")):
         with pytest.raises(sg.SgrError):
             ctx.descriptors_radius(tm, r2)
+
+
+def test_pyramid_graph_cache_follows_the_workspace_layout(sg):
+    """One context and one pose buffer reused across pyramids whose levels
+    differ only in the neighbourhood (k nearest with k = 16, a radius level,
+    k = 8): the workspace layout differs between them while clouds,
+    parameters and pose address do not, so a cached graph must not be
+    replayed.  Each result equals a fresh context's, bit for bit."""
+    pr = config1(n=1200)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    prm = sg.Params(p=1.0, k=16, E=30)
+    schedules = [[sg.Level(0.0, 1.0, 30, 16)], [sg.Level(1.0, 1.0, 30)], [sg.Level(0.0, 1.0, 30, 8)]]
+    shared = sg.Context(0)
+    pose = sg.pose_identity()
+    try:
+        for lv in schedules:
+            pose.copy_(sg.pose_identity())
+            got, _ = shared.register_pyramid(tm, rf, prm, lv, pose=pose)
+            fresh = sg.Context(0)
+            try:
+                want, _ = fresh.register_pyramid(tm, rf, prm, lv)
+            finally:
+                fresh.close()
+            torch.cuda.synchronize()
+            assert torch.equal(got, want), lv
+    finally:
+        shared.close()

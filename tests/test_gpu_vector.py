@@ -18,6 +18,7 @@ import pytest
 import torch
 
 from oracle import ref as O
+from parity_bars import row_error
 from synth import config1, config2, random_pair, rot_axis_angle
 from synth.clouds import ellipsoid_patch
 
@@ -136,6 +137,7 @@ def _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX=None, mY=None, flags=0):
     S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64), wX=wX, mY=mY)
     Y = pose.apply(pr.tmpl)
     so = O.step(Y, S, t)
+    so.scale = O.force_scale(Y, S, so.G)
     ora_pose = O.compose(pose, so, Y.mean(axis=0))
     tm = sg.Cloud(pr.tmpl, masses=mY)
     rf = sg.Cloud(pr.ref, masses=wX)
@@ -147,8 +149,10 @@ def _step_both(sg, ctx, pr, aX, aY, prm, pose, t, wX=None, mY=None, flags=0):
 
 
 def _errors(so, wr, f, Y, mY=None):
+    """Per-point bar (parity_bars) on every row; F, K against their
+    absolute-sum scales; U relatively."""
     m = np.ones(len(f)) if mY is None else np.asarray(mY, np.float64)
-    e_f = np.linalg.norm(f - so.f) / np.linalg.norm(so.f)
+    e_f = row_error(f, so.f, so.scale)
     e_F = np.linalg.norm(wr[0:3] - so.F) / np.sum(m * np.linalg.norm(so.f, axis=1))
     Yc = Y - Y.mean(axis=0)
     e_K = np.linalg.norm(wr[3:12].reshape(3, 3) - so.K) / np.sum(np.linalg.norm(so.f, axis=1) *
@@ -238,10 +242,11 @@ def test_step_vec_full_size_sampled(sg, ctx):
     prm = O.Params(p=1.0, k=24, E=300)
     S = O.make_setup(pr.ref, pr.tmpl, prm, aX=hX.cpu().numpy().astype(np.float64),
                      aY=hY.cpu().numpy().astype(np.float64))
-    rows = np.random.default_rng(1).choice(pr.M, 150, replace=False)
-    f_o, _ = O.forces(pr.tmpl.astype(np.float64), S, O.G_schedule(0, 300), rows=rows, block=50)
+    rows = np.random.default_rng(1).choice(pr.M, 256, replace=False)
+    f_o, _ = O.forces(pr.tmpl.astype(np.float64), S, O.G_schedule(0, 300), rows=rows, block=32)
+    sc = O.force_scale(pr.tmpl.astype(np.float64), S, O.G_schedule(0, 300), rows=rows, block=32)
     f = f.cpu().numpy().astype(np.float64)[rows]
-    e = np.linalg.norm(f - f_o) / np.linalg.norm(f_o)
+    e = row_error(f, f_o, sc)
     print(f"full-size vector step: sampled force error {e:.1e}")
     assert e <= F_TOL
 

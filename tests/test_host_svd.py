@@ -122,3 +122,23 @@ def test_rank_cases_and_psd_eigenvalues(harness):
     np.testing.assert_allclose(eye["R"], np.eye(3), atol=1e-15)
     lam_np = np.sort(np.linalg.eigvalsh(psd))[::-1]
     np.testing.assert_allclose(ps["lam"], lam_np, rtol=0, atol=1e-13 * lam_np[0])
+
+
+def test_extreme_scales(harness):
+    """Entries near 1e-100 or 1e100 (and subnormal or near-overflow ones):
+    products of squared column norms would under- or overflow in the
+    rotation tests, so the routine works on an exactly rescaled copy.
+    Singular values scale with A, vectors and the rotation do not."""
+    rng = np.random.default_rng(10)
+    base = _cases(rng, 6)
+    scales = [1e-100, 1e100, 1e-300, 1e300, 2.0 ** -1060, 1e-160]
+    cases = [(A / np.abs(A).max() * sc, None) for A in base for sc in scales]
+    res = harness(cases)
+    for (A, _), r in zip(cases, res):
+        sv_np = np.linalg.svd(A, compute_uv=False)
+        # subnormal inputs carry fewer significant bits
+        tol = 1e-13 if sv_np[0] > 1e-290 else 1e-3
+        np.testing.assert_allclose(r["sv"], sv_np, rtol=tol)
+        assert r["ok"] == 1
+        np.testing.assert_allclose(r["R"], _kabsch(A), atol=1e-11 if tol < 1e-6 else 1e-2)
+        assert abs(np.linalg.det(r["R"]) - 1.0) < 1e-12

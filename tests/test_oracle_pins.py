@@ -698,3 +698,162 @@ def test_poly_fit_invariances():
               base[rng.permutation(len(base))],       # order of the neighbours
               base @ rot_axis_angle([0.0, 0.0, 1.0], 30.0).T):   # rotation of the tangent frame
         np.testing.assert_allclose(O.poly_fit(Q), d0, rtol=1e-9, atol=1e-12)
+
+
+# ------------------------------------------- Sec. III-B moments, set-up defaults
+def _box_corners(hx, hy, hz):
+    return np.array([[sx * hx, sy * hy, sz * hz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], float)
+
+
+def test_moments_box_corners():
+    """The 8 corners (+-1, +-2, +-3): centroid 0 and, with the 1/n
+    normalisation, covariance diag(1, 4, 9) exactly, whose LARGEST eigenvalue
+    (eX of Sec. III-B) is 9.  Fails for eigvalsh()[0] (gives 1), for a
+    1/(n-1) covariance (9 * 8/7) and for a centroid that is not subtracted."""
+    X = _box_corners(1.0, 2.0, 3.0) + 0.0
+    c, S, lam = O.moments(X)
+    np.testing.assert_array_equal(c, np.zeros(3))
+    np.testing.assert_array_equal(S, np.diag([1.0, 4.0, 9.0]))
+    assert lam == 9.0
+    c2, S2, lam2 = O.moments(X + np.array([5.0, -1.0, 0.5]))
+    np.testing.assert_allclose(c2, [5.0, -1.0, 0.5], atol=1e-15)
+    assert lam2 == pytest.approx(9.0, rel=1e-14)
+
+
+def test_step_scale_is_sqrt_of_largest_eigenvalue_ratio():
+    """Eq. 8 as read: c = sqrt(lambda_max(Sigma_X) / lambda_max(Sigma_Y)),
+    both covariances 1/count.  Reference: the 8 corners (+-1, +-2, +-3)
+    (lambda_max 9, lambda_min 1); template: the corners stretched 5x along x,
+    each taken twice (16 points; lambda_max 25, lambda_min 4).  c = 0.6
+    exactly.  The smallest eigenvalues would give 0.5; 1/(n-1) covariances,
+    with n = 8 and 16, would give sqrt((72/7) / (400/15)) = 0.621."""
+    X = _box_corners(1.0, 2.0, 3.0)
+    Y = np.concatenate([_box_corners(5.0, 2.0, 3.0)] * 2)
+    rng = np.random.default_rng(2)
+    S = O.make_setup(X, Y, O.Params(p=1.0, E=10), aX=np.array([0.1, 0.3] * 4), aY=rng.uniform(0.1, 0.3, 16))
+    so = O.step(Y, S, 0)
+    assert so.c == pytest.approx(0.6, rel=1e-13)
+    assert abs(so.c - 0.5) > 0.05 and abs(so.c - math.sqrt((72 / 7) / (400 / 15))) > 0.01
+
+
+def test_setup_defaults_and_p2_force_by_hand():
+    """Defaults of make_setup written out by hand.  Reference x1 = (-2, 0, 0),
+    x2 = (2, 0, 0) with curvatures 0.1, 0.3: abar = 0.2, sigma = population
+    std = 0.1 (the sample std would be 0.1414), lambda_max = 4 and L =
+    sqrt(lambda_max) = 2 (L = lambda_max would be 4; a 1/(n-1) covariance
+    2 sqrt(2); lambda_min = 0 would make the p = 2 law infinite).  Template
+    point y = (0, 1, 0) with a = 0.2: s_1 = s_2 = exp(-(0.1/0.1)^2) = 1/e,
+    r_1 = (2, 1, 0), r_2 = (-2, 1, 0), |r| = sqrt(5), and for p = 2, eps = 0
+    the distance factor (|r|^2 / L^2)^(1/2) = sqrt(5)/2.  With G = 1, Z = 2:
+      g = s:      f = -(1/2)(sqrt(5)/2)(1/e)(r_1 + r_2) = (0, -sqrt(5)/(2e), 0)
+      g = a a s:  weights (a_j/abar) = 1/2, 3/2:
+                  f = -(1/2)(sqrt(5)/2)(1/e)(r_1/2 + 3 r_2/2) = (sqrt(5)/(2e), -sqrt(5)/(2e), 0)
+    Neither sigma nor L is overridden."""
+    X = np.array([[-2.0, 0.0, 0.0], [2.0, 0.0, 0.0]])
+    aX = np.array([0.1, 0.3])
+    Y = np.array([[0.0, 1.0, 0.0]])
+    v = math.sqrt(5.0) / (2.0 * math.e)
+    for g_mode, want in ((0, [0.0, -v, 0.0]), (1, [v, -v, 0.0])):
+        S = O.make_setup(X, Y, O.Params(p=2.0, g_mode=g_mode), aX=aX, aY=np.array([0.2]))
+        assert S.sigma == pytest.approx(0.1, rel=1e-14)
+        assert S.abar == pytest.approx(0.2, rel=1e-15)
+        assert S.lamX == 4.0 and S.L == 2.0
+        for fn in (O.forces, O.forces_c):
+            f, _ = fn(Y, S, 1.0)
+            np.testing.assert_allclose(f[0], want, rtol=1e-14, atol=1e-15)
+
+
+def _labelled_pair(n=40, seed=8):
+    """A 3-D cloud whose points carry distinct labels (curvatures 0.01 i),
+    with a similarity spread that couples every template point to its own
+    counterpart only (other pairs: exp(-100) or less)."""
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, 3)) * np.array([1.0, 0.6, 0.3])
+    X -= X.mean(0)
+    a = 0.01 * np.arange(n)
+    return X, a, 0.001
+
+
+def _angle_about_z(A, B):
+    """Mean signed angle (about z, through the centroids) that carries the
+    rows of A to the rows of B, weighted by squared radius in the xy plane."""
+    A = A - A.mean(0)
+    B = B - B.mean(0)
+    cr = A[:, 0] * B[:, 1] - A[:, 1] * B[:, 0]
+    dt = A[:, 0] * B[:, 0] + A[:, 1] * B[:, 1]
+    return math.atan2(cr.sum(), dt.sum())
+
+
+def test_step_rotates_toward_the_reference():
+    """Direction of eq. 6 as eq. 9 applies it.  The template is the
+    reference turned by +10 degrees about z (through the centroid), every
+    point coupled only to its counterpart, p = 1, so f_i = -(G/N)(y_i - x_i);
+    dt2 is chosen so that G dt2 / N = 1/2, i.e. "after" is the midpoint
+    cloud.  The Kabsch rotation from the template to the midpoints turns by
+    about -5 degrees, so one step must leave about +5 degrees (between 4 and
+    6).  Passing the Kabsch arguments in the wrong order (kabsch(YD, Yc), a
+    transposed R) or applying R^T in eq. 9 would leave about +15 degrees."""
+    X, a, sig = _labelled_pair()
+    th = math.radians(10.0)
+    Q = rot_axis_angle([0.0, 0.0, 1.0], 10.0)
+    Y = X @ Q.T
+    assert _angle_about_z(X, Y) == pytest.approx(th, rel=1e-12)
+    t, E = 3, 50
+    G = O.G_schedule(t, E)
+    prm = O.Params(p=1.0, sigma=sig, E=E, dt2=0.5 * len(X) / G)
+    S = O.make_setup(X, Y, prm, aX=a, aY=a)
+    so = O.step(Y, S, t)
+    assert so.c == pytest.approx(1.0, rel=1e-12)                      # same eigenvalues
+    left = _angle_about_z(X, so.Y)
+    assert 0.4 * th < left < 0.6 * th, math.degrees(left)
+
+
+def test_exact_recovery_of_a_similarity_transform():
+    """Noise-free template y = s Q x + t (40 degrees about an oblique axis,
+    s = 1.3) whose points are coupled only to their counterparts, p = 1,
+    dt2 = N/G1 so that the displacement G_t dt2 / N = G_t/G1 reaches 1 at
+    the end of eq. 12's schedule (the midpoint becomes the reference point
+    itself).  Registration must recover rotation, scale and translation to
+    rounding: pose-RMSE <= 1e-9 of the diameter."""
+    X, a, sig = _labelled_pair(n=60, seed=9)
+    Q = rot_axis_angle([0.3, -0.8, 0.5], 40.0)
+    s, t = 1.3, np.array([0.5, -0.2, 0.3])
+    Y0 = s * X @ Q.T + t
+    prm = O.Params(p=1.0, sigma=sig, E=60, dt2=len(X) / O.G1_DEFAULT)
+    S = O.make_setup(X, Y0, prm, aX=a, aY=a)
+    pose, Y, _ = O.register(Y0, S)
+    assert O.pose_rmse(pose, Y0, s, Q, t) <= 1e-9 * O.diameter(X)
+    np.testing.assert_allclose(pose.R, Q.T, atol=1e-10)
+    assert pose.s == pytest.approx(1.0 / s, rel=1e-10)
+
+
+def test_force_scale_bounds_and_equality():
+    """S_i = (G/Z) sum_j |c_ij| |r_ij| bounds |f_i| (triangle inequality),
+    with equality for a single reference point and for reference points that
+    all lie on one side of y_i along one line; rows subset equals full."""
+    pr = random_pair(30, 50, seed=4)
+    rng = np.random.default_rng(3)
+    S = _setup(pr.ref.astype(np.float64), rng.uniform(0, 0.3, 50), rng.uniform(0, 0.3, 30), p=2.0, sigma=0.1,
+               eps=0.02, L=0.9)
+    f, _ = O.forces(pr.tmpl, S, 5.0)
+    sc = O.force_scale(pr.tmpl, S, 5.0)
+    assert np.all(np.linalg.norm(f, axis=1) <= sc * (1 + 1e-14))
+    assert np.all(np.linalg.norm(f, axis=1) < 0.999 * sc)            # generic rows cancel
+    np.testing.assert_array_equal(O.force_scale(pr.tmpl, S, 5.0, rows=[3, 7]), sc[[3, 7]])
+    X1 = np.array([[1.0, 2.0, 3.0], [2.0, 4.0, 6.0], [4.0, 8.0, 12.0]])    # one ray from the origin
+    S1 = _setup(X1, np.array([0.1, 0.2, 0.15]), np.array([0.12]), p=1.5, sigma=0.1, L=1.3)
+    Y1 = np.zeros((1, 3))
+    f1, _ = O.forces(Y1, S1, 2.0)
+    assert np.linalg.norm(f1[0]) == pytest.approx(O.force_scale(Y1, S1, 2.0)[0], rel=1e-14)
+
+
+def test_force_scale_c_matches_numpy():
+    pr = random_pair(40, 70, seed=13)
+    rng = np.random.default_rng(14)
+    for p, g_mode, eps in ((1.0, 0, 0.0), (2.0, 1, 0.03), (-2.0, 2, 0.05)):
+        S = _setup(pr.ref.astype(np.float64), rng.uniform(0.01, 0.3, 70), rng.uniform(0.01, 0.3, 40), p=p,
+                   g_mode=g_mode, sigma=0.08, eps=eps, L=0.7, wX=rng.uniform(0.5, 2, 70))
+        rows = [0, 5, 39]
+        f, U, sc = O.forces_c(pr.tmpl, S, 3.0, rows=rows, want_scale=True)
+        np.testing.assert_allclose(sc, O.force_scale(pr.tmpl, S, 3.0, rows=rows), rtol=1e-12)
+        np.testing.assert_allclose(f, O.forces(pr.tmpl, S, 3.0)[0][rows], rtol=1e-12, atol=1e-14)
