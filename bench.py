@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark: one step = one whole registration of the scan-sized workload
-(spherical-harmonic surface, template 32,400 points with a cropped cap and
-outliers, reference 36,000 points, k = 24 descriptors, 300 iterations of
+"""Benchmark: one step = one whole registration of the largest single-GPU
+workload, the depth-frame scene (reference 307,200 points: a 640 x 480
+frame of a room with 20 boxes; template 250,000 points of the same room
+after one box is removed and two are added, seen from a camera turned
+30 degrees; k = 16 curvature, g = a a s (eq. 10), p = 1, 100 iterations of
 the shape-weighted gravitational update), on one MI355X.
 
 Prints one JSON line.  `value` is pair interactions per second over the
 whole registration (sum over iterations of M*N, divided by the wall time of
 the registration including descriptors and the final status read-back).
 `roofline` describes the dominant kernel (the all-pairs force kernel),
-timed live with HIP events on the stream it is launched on.
-`cpu_baseline` times the FP64 C oracle on a bounded sample of the same
-force evaluation on the host cores.  The extra leg `pose_independent_sums`
-is the same registration with flags bit 3 (the p = 1 pair sums formed once,
-O(M) per iteration); it is reported beside the headline, which keeps the
-per-iteration all-pairs work that the metric counts.
+timed live with HIP events on the stream it is launched on; `roofline_rform`
+is the same kernel with the distance law of p = 2 (eq. 11: one log2 and one
+exp2 per pair) at the same size.  `cpu_baseline` times the FP64 C oracle on
+a bounded sample of rows of the same force evaluation on the host cores.
+The scan-sized pair (32,400 x 36,000, 300 iterations) and the other
+workloads are extra legs.  Every pose error is printed beside the error of
+the identity pose and of the scale-only update (the pose after a first
+iteration with no force) for the same pair.
 """
 from __future__ import annotations
 
@@ -38,7 +42,10 @@ LANE_SLOTS_PER_S = 256 * 64 * 2.4e9   # CUs x lanes x clock: one VALU issue slot
 # p = 2: adds q = |r|^2 + eps^2 (6) and the distance factor (1) = 20.
 FLOPS_PER_PAIR = {1.0: 13, 2.0: 20}
 TILES = os.path.join(ROOT, "paper_1902_01061_amd", "tiles_gfx950.json")
-COUNTERS = os.path.join(ROOT, "profiles", "force_kernel_scan_32400x36000_counters.json")
+# Counter summaries (FETCH_SIZE, WRITE_SIZE) of the force kernel, by (M, N, p).
+COUNTERS = {(250000, 307200, 1.0): os.path.join(ROOT, "profiles", "force_kernel_scene_250000x307200_counters.json"),
+            (250000, 307200, 2.0): os.path.join(ROOT, "profiles",
+                                                "force_kernel_rform_scene_250000x307200_counters.json")}
 FORCE_SOURCES = ["paper_1902_01061_amd/csrc/force.hip", "paper_1902_01061_amd/csrc/common.h"]
 
 
@@ -67,13 +74,15 @@ def _sources_digest():
     return h.hexdigest()
 
 
-def _traffic(launch):
+def _traffic(launch, M, N, p):
     """HBM bytes per launch of the force kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or
-    None when the kernel source or its launch shape changed since."""
-    if launch is None or not os.path.exists(COUNTERS):
+    None when there is none for this workload, or the kernel source or its
+    launch shape changed since."""
+    path = COUNTERS.get((M, N, p))
+    if launch is None or path is None or not os.path.exists(path):
         return None
-    with open(COUNTERS) as f:
+    with open(path) as f:
         c = json.load(f)
     if c.get("sources_sha256") != _sources_digest() or c.get("launch") != launch:
         return None
@@ -84,7 +93,7 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(pr, E: int, k: int, target_s: float):
+def cpu_baseline(pr, E: int, k: int, target_s: float, g_mode: int = 0):
     """Time the FP64 C oracle force on the host cores: on all host threads
     (one full M x N evaluation, repeated until about target_s seconds have
     passed, or a row sample if one evaluation alone is longer), then on one
@@ -93,7 +102,7 @@ def cpu_baseline(pr, E: int, k: int, target_s: float):
 
     from oracle import ref as O
 
-    prm = O.Params(p=1.0, k=k, E=E)
+    prm = O.Params(p=1.0, g_mode=g_mode, k=k, E=E)
     rng = np.random.default_rng(0)
     aX = rng.uniform(0.0, 0.3, pr.N)     # descriptor values do not change the cost
     aY = rng.uniform(0.0, 0.3, pr.M)
@@ -125,7 +134,8 @@ def cpu_baseline(pr, E: int, k: int, target_s: float):
     O.c_threads(all_threads)
     return {"value": rate, "unit": "pair-interactions/s", "cores": all_threads, "kind": "oracle",
             "sample": f"{reps} FP64 force evaluation(s) (eq. 5) of {nrows} template rows x {pr.N} reference "
-                      f"points (p = 1, g = s) by the C oracle on {all_threads} threads in {dt:.1f} s; a "
+                      f"points (p = 1, g = {'a a s' if g_mode == 1 else 's'}) by the C oracle on {all_threads} "
+                      f"threads in {dt:.1f} s; a "
                       f"{E}-iteration registration would take {pr.M * pr.N * E / rate:.0f} s at this rate "
                       f"(extrapolated)",
             "single_thread": {"value": rate1, "unit": "pair-interactions/s", "cores": 1,
@@ -145,6 +155,36 @@ def _pose_err(sg, pose, pr):
     truth = (Y0 - pr.gt_t) @ pr.gt_R / pr.gt_s
     diam = float(np.linalg.norm(pr.ref.max(0) - pr.ref.min(0)))
     return float(np.sqrt(np.mean(np.sum((est - truth) ** 2, axis=1)))) / diam
+
+
+def _pose_err_srt(s_, R_, t_, pr):
+    """_pose_err for a pose given as (s, R, t) on the host."""
+    import numpy as np
+
+    inl = pr.corr >= 0
+    Y0 = (pr.tmpl[inl] if inl.any() else pr.tmpl).astype(np.float64)
+    est = s_ * Y0 @ np.asarray(R_).T + t_
+    truth = (Y0 - pr.gt_t) @ pr.gt_R / pr.gt_s
+    diam = float(np.linalg.norm(pr.ref.max(0) - pr.ref.min(0)))
+    return float(np.sqrt(np.mean(np.sum((est - truth) ** 2, axis=1)))) / diam
+
+
+def _reference_errors(pr):
+    """Pose errors that frame a registration's: the identity pose, and the
+    scale-only update (what the first iteration does when every force is
+    zero: the template scaled about its centroid by sqrt(lambda_max(Sigma_X)
+    / lambda_max(Sigma_Y)), eq. 8)."""
+    import numpy as np
+
+    def lam(P):
+        Q = P.astype(np.float64)
+        Q = Q - Q.mean(0)
+        return float(np.linalg.eigvalsh(Q.T @ Q / len(Q))[-1])
+
+    c = float(np.sqrt(lam(pr.ref) / lam(pr.tmpl)))
+    yb = pr.tmpl.astype(np.float64).mean(0)
+    return {"identity_pose_rmse_over_diameter": _pose_err_srt(1.0, np.eye(3), np.zeros(3), pr),
+            "scale_only_pose_rmse_over_diameter": _pose_err_srt(c, np.eye(3), yb - c * yb, pr)}
 
 
 def _timed(fn, reps=1):
@@ -393,29 +433,27 @@ def extra_vector(sg, ctx, E: int, k: int, D: int = 16):
     return out
 
 
-def extra_scene(sg, ctx):
-    """Depth-frame scene (307,200 x 250,000, g = a a s): FP32 and mixed
-    registrations, their pose difference per iteration, and change detection
-    (their force parity with the oracle along the FP32 trajectory is a test:
-    tests/test_gpu_edges.py)."""
+def extra_scene(sg, ctx, pr, fp32_dt, fp32_pose):
+    """The headline scene's other forms: the mixed-precision registration,
+    its pose difference from the FP32 one per iteration, the pose-independent
+    pair sums, and change detection (their force parity with the oracle along
+    the FP32 trajectory is a test: tests/test_gpu_edges.py)."""
     import numpy as np
     import torch
 
-    from synth import config5
-
-    pr = config5()
     E = 100
     tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
     out = {"M": pr.M, "N": pr.N, "iterations": E, "g_mode": 1}
-    res = {}
+    res = {"fp32": (fp32_dt, fp32_pose, None)}
+    prm_m = sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=2)
+    ctx.register(tm, rf, prm_m)
+    dt, (pose, _) = _timed(lambda: ctx.register(tm, rf, prm_m))
+    res["mixed"] = (dt, pose, None)
+    out["mixed"] = {"ms_per_registration": dt * 1e3, "pairs_per_s": pr.M * pr.N * E / dt,
+                    "pose_rmse_over_diameter": _pose_err(sg, pose, pr)}
     for name, flags in (("fp32", 0), ("mixed", 2)):
-        prm = sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=flags)
-        ctx.register(tm, rf, prm)
-        dt, (pose, _) = _timed(lambda: ctx.register(tm, rf, prm))
-        _, st = ctx.register(tm, rf, prm, stats=True)     # trajectory for the comparison (untimed)
-        res[name] = (dt, pose, st.cpu().numpy())
-        out[name] = {"ms_per_registration": dt * 1e3, "pairs_per_s": pr.M * pr.N * E / dt,
-                     "pose_rmse_over_diameter": _pose_err(sg, pose, pr)}
+        _, st = ctx.register(tm, rf, sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=flags), stats=True)  # untimed
+        res[name] = (res[name][0], res[name][1], st.cpu().numpy())
     out["mixed_speedup"] = res["fp32"][0] / res["mixed"][0]
     # per-iteration pose difference, mixed vs FP32, as RMSE of transformed template points / diameter
     diam = float(np.linalg.norm(pr.ref.max(0) - pr.ref.min(0)))
@@ -471,15 +509,96 @@ def extra_scene(sg, ctx):
     return out
 
 
+def extra_scan(sg, ctx, steps: int, kernel_reps: int):
+    """The scan-sized pair (32,400 x 36,000, k = 24, g = s, 300 iterations):
+    registration time and pose error beside the identity and scale-only
+    errors, the number of template rows whose force is not negligible at the
+    first iterate (with the default sigma, the smooth reference's curvatures
+    lie far below the noisy template's, and most rows' weights underflow),
+    the force kernel alone, and the mixed-precision and pose-independent
+    forms."""
+    import numpy as np
+    import torch
+
+    from synth import config2
+
+    pr = config2()
+    E, k = 300, 24
+    prm = sg.Params(p=1.0, k=k, E=E)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    ident = sg.pose_identity()
+    out = {"M": pr.M, "N": pr.N, "iterations": E, "k": k}
+    forms = {}
+    for name, flags in (("fp32", 0), ("mixed", 2), ("pose_independent_sums", 8)):
+        pp = sg.Params(p=1.0, k=k, E=E, flags=flags)
+        pose = ident.clone()
+        ctx.register(tm, rf, pp, pose=pose)
+        dt, _ = _timed(lambda: (pose.copy_(ident), ctx.register(tm, rf, pp, pose=pose)), steps)
+        forms[name] = (dt, pose)
+        out[name] = {"ms_per_registration": dt * 1e3, "pairs_per_s": pr.M * pr.N * E / dt,
+                     "pose_rmse_over_diameter": _pose_err(sg, pose, pr)}
+    out["fp32"]["nn_rmse"] = float(ctx.residual(tm, rf, forms["fp32"][1]).item())
+    out["mixed"]["speedup_vs_fp32"] = forms["fp32"][0] / forms["mixed"][0]
+    out["pose_independent_sums"]["speedup_vs_all_pairs"] = forms["fp32"][0] / forms["pose_independent_sums"][0]
+    out.update(_reference_errors(pr))
+    a_t, mom_t = ctx.descriptors(tm, k)
+    a_r, mom_r = ctx.descriptors(rf, k)
+    plan = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, prm)
+    _, f = plan.force(ident, t=0, want_wrench=False, want_f=True)
+    fn = torch.linalg.vector_norm(f.double(), dim=1)
+    out["rows_with_force_at_t0"] = int((fn > 1e-6 * fn.max()).sum().item())
+    for _ in range(3):
+        plan.force(forms["fp32"][1], t=E - 1, want_wrench=False)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(kernel_reps):
+        plan.force(forms["fp32"][1], t=E - 1, want_wrench=False)
+    e1.record(stream)
+    e1.synchronize()
+    k_ms = e0.elapsed_time(e1) / kernel_reps
+    plan.close()
+    out["force_kernel"] = {"ms_per_launch": k_ms, "pairs_per_s": pr.M * pr.N / (k_ms * 1e-3),
+                           "tflops_13_per_pair": 13 * pr.M * pr.N / (k_ms * 1e-3) / 1e12}
+    return out
+
+
+def _kernel_ms(plan, pose, t, reps):
+    """Average duration of the force kernel alone: HIP events around `reps`
+    back-to-back launches on the stream the plan launches on (torch's
+    current stream)."""
+    import torch
+
+    for _ in range(2):
+        plan.force(pose, t=t, want_wrench=False)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        plan.force(pose, t=t, want_wrench=False)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _roofline(fpp, pairs, k_ms, launch, traffic, kernel):
+    achieved = fpp * pairs / (k_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic, "kernel": kernel, "ms_per_launch": k_ms,
+            "pairs_per_launch": pairs, "flops_per_pair": fpp, "pairs_per_s": pairs / (k_ms * 1e-3),
+            "launch": launch, "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+            "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--kernel-reps", type=int, default=40)
+    ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batch / adjoint / mixed / scene legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the scan, batch, adjoint, mixed ... legs")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the force kernel launch shape instead of loading the committed tile table")
     ap.add_argument("--save-tiles", default="", help="write the tile table here after tuning")
@@ -507,13 +626,13 @@ def main() -> int:
         return 0
 
     import paper_1902_01061_amd as sg
-    from synth import config2
+    from synth import config5
 
-    pr = config2()
-    E, k, p = 300, 24, 1.0
-    prm = sg.Params(p=p, k=k, E=E)
+    pr = config5()
+    E, k, p, g_mode = 100, 16, 1.0, 1
+    prm = sg.Params(p=p, g_mode=g_mode, k=k, E=E)
     M, N = pr.M, pr.N
-    log(f"workload: template {M} x reference {N}, k={k}, E={E}, p={p}")
+    log(f"workload: depth-frame scene, template {M} x reference {N}, k={k}, E={E}, p={p}, g=a a s")
     ctx = sg.Context(0)
     tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
     ident = sg.pose_identity()
@@ -522,7 +641,7 @@ def main() -> int:
     a_t, mom_t = ctx.descriptors(tm, k)
     a_r, mom_r = ctx.descriptors(rf, k)
     if args.autotune or not os.path.exists(TILES):
-        tuned, tuned_ms = ctx.autotune(tm, a_t, rf, a_r, mom_t, mom_r, prm, reps=10)
+        tuned, tuned_ms = ctx.autotune(tm, a_t, rf, a_r, mom_t, mom_r, prm, reps=5)
         log(f"autotuned force kernel launch: R={tuned[0]} blocks/CU={tuned[1]} variant={tuned[2]} ({tuned_ms:.4f} ms)")
         if args.save_tiles:
             ctx.save_tiles(args.save_tiles)
@@ -540,39 +659,30 @@ def main() -> int:
     for s in range(args.steps):
         pose.copy_(ident)
         ctx.register(tm, rf, prm, pose=pose)
+        log(f"timed registration {s + 1}/{args.steps} launched")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"timed {args.steps} registrations: {dt:.3f} s")
     ms_per_step = dt / args.steps * 1e3
     value = M * N * E * args.steps / dt
-
-    # registration quality (pose error against the generating transform, inlier points)
-    s_, R_, t_ = sg.pose_to_srt(pose)
-    inl = pr.corr >= 0
-    Y0 = pr.tmpl[inl].astype(np.float64)
-    est = s_ * Y0 @ R_.T + t_
-    truth = (Y0 - pr.gt_t) @ pr.gt_R / pr.gt_s
-    diam = float(np.linalg.norm(pr.ref.max(0) - pr.ref.min(0)))
-    pose_rmse = float(np.sqrt(np.mean(np.sum((est - truth) ** 2, axis=1))))
+    pose_err = _pose_err(sg, pose, pr)
     nn_rmse = float(ctx.residual(tm, rf, pose).item())
 
     # dominant kernel: the all-pairs force kernel alone, on the final pose
     plan = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, prm)
-    for _ in range(3):
-        plan.force(pose, t=E - 1, want_wrench=False)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.kernel_reps):
-        plan.force(pose, t=E - 1, want_wrench=False)
-    e1.record(stream)
-    e1.synchronize()
-    k_ms = e0.elapsed_time(e1) / args.kernel_reps
-    k_pairs = M * N / (k_ms * 1e-3)
-    fpp = FLOPS_PER_PAIR[p]
-    achieved = fpp * k_pairs / 1e12
-    log(f"force kernel: {k_ms:.4f} ms/launch, {k_pairs:.3e} pairs/s, {achieved:.2f} TFLOP/s")
+    k_ms = _kernel_ms(plan, pose, E - 1, args.kernel_reps)
     plan.close()
+    roof = _roofline(FLOPS_PER_PAIR[1.0], M * N, k_ms, launch, _traffic(launch, M, N, p), "force_kernel (p = 1)")
+    log(f"force kernel: {k_ms:.4f} ms/launch, {roof['pairs_per_s']:.3e} pairs/s, {roof['achieved']:.2f} TFLOP/s")
+    # the same kernel with the p = 2 distance law (one log2 + one exp2 per pair)
+    prm2 = sg.Params(p=2.0, g_mode=g_mode, k=k, E=E)
+    plan2 = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, prm2)
+    k2_ms = _kernel_ms(plan2, pose, E - 1, max(3, args.kernel_reps // 2))
+    plan2.close()
+    launch2 = _launch_of(TILES, M, N, 2.0) if os.path.exists(TILES) else None
+    roof2 = _roofline(FLOPS_PER_PAIR[2.0], M * N, k2_ms, launch2, _traffic(launch2, M, N, 2.0),
+                      "force_kernel (p = 2, r-form)")
+    log(f"force kernel p=2: {k2_ms:.4f} ms/launch, {roof2['pairs_per_s']:.3e} pairs/s")
 
     out = {
         "metric": METRIC,
@@ -587,69 +697,43 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"scan-sized registration: spherical-harmonic surface, template {M} (25% cap "
-                               f"cropped, 15% blob + 5% uniform outliers, 0.8 x 60 deg rotation, noise 0.003) "
-                               f"vs reference {N}, k={k} curvature, p={p:g}, g=s, {E} iterations",
-                   "M": M, "N": N, "iterations": E, "k": k, "p": p, "g_mode": 0},
+        "config": {"workload": f"depth-frame scene registration: reference {N} points (640x480 frame of a 5x3x4 m "
+                               f"room with 20 boxes, depth noise 0.001 z^2), template {M} points (one box removed, "
+                               f"two added, camera turned 30 deg), k={k} curvature, p={p:g}, g=a a s (eq. 10), "
+                               f"{E} iterations",
+                   "M": M, "N": N, "iterations": E, "k": k, "p": p, "g_mode": g_mode},
         "ms_per_registration": ms_per_step,
-        "pose_rmse_over_diameter": pose_rmse / diam,
+        "pose_rmse_over_diameter": pose_err,
         "nn_rmse": nn_rmse,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "force_kernel", "ms_per_launch": k_ms, "pairs_per_launch": M * N,
-                     "flops_per_pair": fpp, "pairs_per_s": k_pairs},
+        "roofline": roof,
+        "roofline_rform": roof2,
     }
-    out["roofline"]["launch"] = launch
-    out["roofline"]["peak_unpacked"] = PEAK_FP32_UNPACKED_TFLOPS
-    out["roofline"]["frac_unpacked"] = achieved / PEAK_FP32_UNPACKED_TFLOPS
-    out["roofline"]["traffic"] = _traffic(launch)
+    out.update(_reference_errors(pr))
     if not args.no_extras:
-        # the same registration with the mixed-precision force (bf16 matrix cores)
-        prm_m = sg.Params(p=p, k=k, E=E, flags=2)
-        pm_ = ident.clone()
-        ctx.register(tm, rf, prm_m, pose=pm_)
-        dtm, _ = _timed(lambda: (pm_.copy_(ident), ctx.register(tm, rf, prm_m, pose=pm_)), args.steps)
-        out["mixed"] = {"ms_per_registration": dtm * 1e3, "pairs_per_s": M * N * E / dtm,
-                        "speedup_vs_fp32": ms_per_step / (dtm * 1e3),
-                        "pose_rmse_over_diameter": _pose_err(sg, pm_, pr),
-                        "fp32_pose_rmse_over_diameter": pose_rmse / diam}
-        log(f"mixed: {dtm * 1e3:.1f} ms/registration")
-        # p = 1: the pair weights do not depend on the pose, so the sums over
-        # the reference can be formed once per registration (flags bit 3)
-        prm_i = sg.Params(p=p, k=k, E=E, flags=8)
-        pi_ = ident.clone()
-        ctx.register(tm, rf, prm_i, pose=pi_)
-        dti, _ = _timed(lambda: (pi_.copy_(ident), ctx.register(tm, rf, prm_i, pose=pi_)), args.steps)
-        si, Ri, ti = sg.pose_to_srt(pi_)
-        Yall = pr.tmpl.astype(np.float64)
-        dpose = (si * Yall @ Ri.T + ti) - (s_ * Yall @ R_.T + t_)
-        out["pose_independent_sums"] = {
-            "ms_per_registration": dti * 1e3, "speedup_vs_all_pairs": ms_per_step / (dti * 1e3),
-            "pose_rmse_over_diameter": _pose_err(sg, pi_, pr),
-            "pose_difference_vs_all_pairs_over_diameter": float(np.sqrt(np.mean(np.sum(dpose ** 2, axis=1)))) / diam}
-        log(f"pose-independent sums: {dti * 1e3:.2f} ms/registration")
+        out["scene"] = extra_scene(sg, ctx, pr, dt / args.steps, pose)
+        log(f"scene: mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms, "
+            f"pose-independent sums {out['scene']['pose_independent_sums']['ms_per_registration']:.1f} ms")
+        out["scan"] = extra_scan(sg, ctx, args.steps, 20)
+        log(f"scan: fp32 {out['scan']['fp32']['ms_per_registration']:.1f} ms, "
+            f"{out['scan']['rows_with_force_at_t0']} rows with a force")
         out["batch"] = extra_batch(sg, ctx)
         log(f"batch: {out['batch']['ms_per_batch']:.1f} ms, pose-independent sums "
             f"{out['batch']['pose_independent_sums']['ms_per_batch']:.1f} ms")
         out["adjoint"] = extra_adjoint(sg, ctx)
         log(f"adjoint: fwd {out['adjoint']['fwd_ms']:.3f} ms, bwd {out['adjoint']['bwd_ms']:.3f} ms")
-        out["force_law"] = extra_force_law(sg, ctx, E, k)
+        out["force_law"] = extra_force_law(sg, ctx, 300, 24)
         log(f"force law: workload pose error p=1 {out['force_law']['workload']['shape_p1']['pose_rmse_over_diameter']:.2e}"
             f", gravitational {out['force_law']['workload']['gravitational_p-2']['pose_rmse_over_diameter']:.2e}")
-        out["pyramid"] = extra_pyramid(sg, ctx, E, k)
+        out["pyramid"] = extra_pyramid(sg, ctx, 300, 24)
         log(f"pyramid: radius descriptors {out['pyramid']['radius_descriptors']['ms']:.3f} ms, registration "
             f"{out['pyramid']['pyramid']['ms_per_registration']:.1f} ms")
-        out["vector"] = extra_vector(sg, ctx, E, k)
+        out["vector"] = extra_vector(sg, ctx, 300, 24)
         log(f"vector descriptors: split f16 {out['vector']['split_f16']['ms_per_registration']:.1f} ms, "
             f"fp32 {out['vector']['fp32']['ms_per_registration']:.1f} ms, pose-independent sums "
             f"{out['vector']['split_f16_pose_independent_sums']['ms_per_registration']:.1f} ms per registration")
-        out["scene"] = extra_scene(sg, ctx)
-        log(f"scene: fp32 {out['scene']['fp32']['ms_per_registration']:.1f} ms, "
-            f"mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms, "
-            f"pose-independent sums {out['scene']['pose_independent_sums']['ms_per_registration']:.1f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(pr, E, k, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(pr, E, k, args.cpu_seconds, g_mode=g_mode)
     print(json.dumps(out), flush=True)
     ctx.close()
     return 0

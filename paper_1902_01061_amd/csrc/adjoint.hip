@@ -22,6 +22,7 @@ namespace sgr {
 
 constexpr int A_BT = 256;
 constexpr int A_TJ = 256;
+constexpr int A_GRAN = 16;  // balanced reference chunks are cut at multiples of this
 
 // lambda_i for every template point; also the sum of f (for the K term).
 __global__ __launch_bounds__(A_BT) void adj_lambda_kernel(AdjArgs A) {
@@ -71,9 +72,18 @@ __global__ __launch_bounds__(A_BT) void adj_pair_kernel(AdjArgs A) {
 #pragma unroll
   for (int r = 0; r < R; ++r) S0[r] = Sx[r] = Sy[r] = Sz[r] = Ss[r] = Se[r] = 0.0;
 
-  const int j0 = chunk * A.chunk_len;
-  const int j1 = min(A.N, j0 + A.chunk_len);
+  int j0, j1;
+  if (A.chunk_len > 0) {
+    j0 = chunk * A.chunk_len;
+    j1 = min(A.N, j0 + A.chunk_len);
+  } else {
+    // balanced chunks: chunk c covers the A_GRAN-point groups [c n / C, (c + 1) n / C)
+    const int64_t n_sub = (A.N + A_GRAN - 1) / A_GRAN;
+    j0 = (int)(chunk * n_sub / A.n_chunks) * A_GRAN;
+    j1 = min(A.N, (int)((chunk + 1) * n_sub / A.n_chunks) * A_GRAN);
+  }
   for (int base = j0; base < j1; base += A_TJ) {
+    const int tn = min(A_TJ, j1 - base);
     __syncthreads();
     {
       const int j = base + threadIdx.x;
@@ -89,7 +99,7 @@ __global__ __launch_bounds__(A_BT) void adj_pair_kernel(AdjArgs A) {
     float a0[R], ax[R], ay[R], az[R], as[R], ae[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a0[r] = ax[r] = ay[r] = az[r] = as[r] = ae[r] = 0.f;
-    for (int jj = 0; jj < A_TJ; ++jj) {
+    for (int jj = 0; jj < tn; ++jj) {
       const float4 X = s_ref[jj];
       const float lw = s_lw[jj];
 #pragma unroll
@@ -202,6 +212,27 @@ __global__ __launch_bounds__(A_BT) void adj_final_kernel(AdjArgs A, const double
     }
   }
 }
+
+// Resident blocks per CU of the pair kernel (cached per instantiation).
+template <int R, bool P1>
+static int adj_occ() {
+  static int occ = 0;
+  if (occ == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adj_pair_kernel<R, P1>, A_BT, 0) != hipSuccess || n < 1)
+      n = 1;
+    occ = n;
+  }
+  return occ;
+}
+
+int adj_blocks_per_cu(int R, bool p1) {
+  if (R == 1) return p1 ? adj_occ<1, true>() : adj_occ<1, false>();
+  if (R == 2) return p1 ? adj_occ<2, true>() : adj_occ<2, false>();
+  return p1 ? adj_occ<4, true>() : adj_occ<4, false>();
+}
+
+int adj_chunk_gran() { return A_GRAN; }
 
 hipError_t launch_adjoint(const AdjArgs& A, int R, double* fsum_tmp, hipStream_t st) {
   const int gi = (A.M + A_BT - 1) / A_BT;

@@ -151,11 +151,12 @@ Tiles tiles_for(const sgr_ctx* ctx, int M, int N, const sgr_params* p) {
 }
 
 // Shape of one FP32 force launch for a single registration: every template
-// block gets n_chunks reference chunks cut at multiples of 64 points, with
-// n_chunks chosen so that the launch is about T.bpc blocks per CU (by
-// default one wave of resident blocks, from the kernel's occupancy).
+// block gets n_chunks reference chunks cut at multiples of force_chunk_gran()
+// points, with n_chunks chosen so that the launch is about T.bpc blocks per
+// CU (by default one wave of resident blocks, from the kernel's occupancy).
 // Whole-tile chunks would leave the last wave of blocks partly empty
-// whenever the work is not a multiple of the resident block count.
+// whenever the work is not a multiple of the resident block count, and a
+// small pair (a few thousand points) would occupy a few CUs only.
 // `slots` is the number of wrench slots the launch writes.
 struct FLaunch {
   int n_chunks = 0, slots = 0;
@@ -163,13 +164,30 @@ struct FLaunch {
 
 FLaunch force_shape(const sgr_ctx* ctx, int M, int N, const Tiles& T, int pm) {
   const int64_t n_iblk = (M + 256 * T.R - 1) / (256 * T.R);
-  const int64_t n_tiles = (N + 255) / 256;  // at least one LDS tile per chunk
+  const int64_t n_sub = (N + force_chunk_gran() - 1) / force_chunk_gran();  // smallest chunks
   const int bpc = T.bpc > 0 ? T.bpc : force_blocks_per_cu(T.R, pm, T.sm != 0);
-  const int64_t nc = std::max<int64_t>(1, std::min<int64_t>(n_tiles, (int64_t)bpc * ctx->n_cu / n_iblk));
+  const int64_t nc = std::max<int64_t>(1, std::min<int64_t>(n_sub, (int64_t)bpc * ctx->n_cu / n_iblk));
   FLaunch L;
   L.n_chunks = (int)nc;
   L.slots = (int)(n_iblk * nc);
   return L;
+}
+
+// Launch shape of the adjoint pair kernel: R template points per lane from
+// the tile choice (at most 4), n_chunks balanced reference chunks so that
+// the launch is one wave of resident blocks.
+Tiles adj_shape(const sgr_ctx* ctx, int M, int N, int R, bool p1) {
+  if (R > 4) R = 4;
+  Tiles T{};
+  T.R = R;
+  T.n_iblk = (M + 256 * R - 1) / (256 * R);
+  const int64_t n_sub = (N + adj_chunk_gran() - 1) / adj_chunk_gran();
+  const int64_t nc = std::max<int64_t>(
+      1, std::min<int64_t>(n_sub, (int64_t)adj_blocks_per_cu(R, p1) * ctx->n_cu / T.n_iblk));
+  T.n_chunks = (int)nc;
+  T.chunk_len = 0;
+  T.nblk = T.n_iblk * T.n_chunks;
+  return T;
 }
 
 hipError_t run_force(ForceArgs A, const Tiles& T, const FLaunch& L, int pm, bool wu, bool wf, hipStream_t st) {
@@ -1358,8 +1376,7 @@ int sgr_force_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const s
   hipStream_t st = (hipStream_t)stream;
   const int M = (int)tmpl->n, N = (int)ref->n;
   const int pm = pmode_of(prm->p);
-  Tiles T = ctx->tiles.pick(M, N, pm);
-  if (T.R > 4) T = TileTable::make(M, N, 4, 8 * ctx->n_cu);
+  const Tiles T = adj_shape(ctx, M, N, ctx->tiles.pick(M, N, pm).R, pm == 1);
   Carve cv{nullptr};
   cv.take<double>(16);
   cv.take<double>(16);
@@ -1623,8 +1640,7 @@ int sgr_unrolled_bwd(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
   unrolled_shape(ctx, tmpl, ref, prm, U);
   const int M = U.M, N = U.N, E = prm->E;
   // the adjoint kernels use tile-multiple chunks (at most 4 points per lane)
-  Tiles TA = U.T;
-  if (TA.R > 4) TA = TileTable::make(M, N, 4, 8 * ctx->n_cu);
+  const Tiles TA = adj_shape(ctx, M, N, U.T.R, U.pm == 1);
   const int nseg = (E + K - 1) / K;
   const int npg = pose_grad_blocks(M);
   auto carve_rest = [&](Carve& c, double** seg, double** W, double** g0, double** g1, double** gW, double** gse_t,

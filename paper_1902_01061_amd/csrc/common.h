@@ -283,7 +283,10 @@ __device__ inline void block_range(float& lo, float& hi, double* lds) {
 // the block end nearest to the range for a block entirely outside it (which
 // makes the bound lw_max).  The template order sorted by curvature keeps
 // block ranges narrow.
-__device__ inline bool expanded_centre(float lo, float hi, const Derived& D, bool fixed, float& beta) {
+// `extra` bounds any further term of the FP32 exponent (the distance law of
+// the r-form, hp log2(q), whose largest value for hp < 0 is hp log2(eps^2)).
+__device__ inline bool expanded_centre(float lo, float hi, const Derived& D, bool fixed, float& beta,
+                                       double extra = 0.0) {
   beta = 0.f;
   if (!(lo <= hi)) return false;
   const float rlo = (float)D.bref_lo, rhi = (float)D.bref_hi;
@@ -302,7 +305,7 @@ __device__ inline bool expanded_centre(float lo, float hi, const Derived& D, boo
   double e = fmax(bound(lo), bound(hi));
   if (rlo > lo && rlo < hi) e = fmax(e, bound(rlo));
   if (rhi > lo && rhi < hi) e = fmax(e, bound(rhi));
-  return e + D.lw_max <= 64.0;
+  return e + D.lw_max + extra <= 64.0;
 }
 
 }  // namespace sgr

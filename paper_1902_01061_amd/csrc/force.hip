@@ -7,9 +7,9 @@
 //   lw_j = log2(w_j) [+ log2(a_j/abar) for g = a a s],  g'_i = 1 [or a_i/abar].
 //
 // All similarity, mass and distance-law factors of one pair fold into a
-// single exponent, so a pair costs 3 sub + 3 fma (q) + 1 sub + 2 fma + one
-// log2 + one exp2 + 3 fma (accumulate) on the FP32 VALU for p != 1, and no
-// log2 / q for p = 1.  Each lane holds R template points in registers (R
+// single exponent, so a pair costs 3 sub + 3 fma (q) + 2 fma + one log2 + one
+// exp2 + 3 fma (accumulate) on the FP32 VALU for p != 1 (the similarity term
+// in the block-centred expanded form below), and no log2 / q for p = 1.  Each lane holds R template points in registers (R
 // independent dependency chains hide transcendental latency); the
 // reference streams through LDS in tiles of 256 points that every lane reads
 // by broadcast.  Per-tile FP32 partial sums (256 terms) are flushed into
@@ -27,6 +27,7 @@ namespace sgr {
 
 constexpr int F_BT = 256;  // threads per block
 constexpr int F_TJ = 256;  // reference points per LDS tile
+constexpr int F_GRAN = 16; // balanced reference chunks are cut at multiples of this
 
 __device__ inline double G_at(const Derived& D, int t) {
   // eq. (12): G(t+1) = 0.1 G1 + 0.9 G1 / (1 + exp(-(t - E/2))); iteration t uses G(t).
@@ -340,7 +341,7 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int j0, int j1,
   // tile, the scalar form keeps beta = 0 and reads the packed reference.
   float beta = 0.f;
   bool expd = false;
-  if constexpr (MOM) {
+  {
     float lo = INFINITY, hi = -INFINITY;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -349,7 +350,11 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int j0, int j1,
         hi = fmaxf(hi, bi[r]);
       }
     block_range<F_BT>(lo, hi, s_red);
-    expd = expanded_centre(lo, hi, D, SM, beta);
+    // r-form: the distance law adds hp log2(q) to the exponent; for hp < 0 it
+    // is largest at q = eps^2 (p < 1 needs eps > 0); p = 3 multiplies by q
+    // outside the exponent
+    const double extra = (!MOM && PM != 3 && D.hp < 0.0 && D.eps2 > 0.0) ? D.hp * log2(D.eps2) : 0.0;
+    expd = expanded_centre(lo, hi, D, SM, beta, extra);
   }
   float al[R];
 #pragma unroll
@@ -458,19 +463,44 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int j0, int j1,
       float ax[R], ay[R], az[R], au[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) ax[r] = ay[r] = az[r] = au[r] = 0.f;
+      if (expd) {
+        // block-centred expanded similarity exponent: one FMA, the factor
+        // exp2(-d_i^2) is applied in FP64 after the loop
 #pragma unroll 2
-      for (int jj = 0; jj < tn; ++jj) {
-        const float4 X = SM ? gref[jj] : s_ref[jj];
-        const float lw = SM ? glw[jj] : s_lw[jj];
+        for (int jj = 0; jj < tn; ++jj) {
+          const float4 X = SM ? gref[jj] : s_ref[jj];
+          const float cj = SM ? __builtin_fmaf(-X.w, X.w, glw[jj]) : s_lw[jj];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const float rx = yx[r] - X.x, ry = yy[r] - X.y, rz = yz[r] - X.z;
-          float q;
-          const float c = pair_coef<PM>(rx, ry, rz, bi[r] - X.w, lw, eps2, hp, q);
-          ax[r] = __builtin_fmaf(c, rx, ax[r]);
-          ay[r] = __builtin_fmaf(c, ry, ay[r]);
-          az[r] = __builtin_fmaf(c, rz, az[r]);
-          if constexpr (WU) au[r] = __builtin_fmaf(c, q, au[r]);
+          for (int r = 0; r < R; ++r) {
+            const float rx = yx[r] - X.x, ry = yy[r] - X.y, rz = yz[r] - X.z;
+            const float q = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, __builtin_fmaf(rz, rz, eps2)));
+            const float e = __builtin_fmaf(al[r], X.w, cj);
+            float c;
+            if constexpr (PM == 3)
+              c = __builtin_amdgcn_exp2f(e) * q;
+            else
+              c = __builtin_amdgcn_exp2f(__builtin_fmaf(hp, __builtin_amdgcn_logf(q), e));
+            ax[r] = __builtin_fmaf(c, rx, ax[r]);
+            ay[r] = __builtin_fmaf(c, ry, ay[r]);
+            az[r] = __builtin_fmaf(c, rz, az[r]);
+            if constexpr (WU) au[r] = __builtin_fmaf(c, q, au[r]);
+          }
+        }
+      } else {
+#pragma unroll 2
+        for (int jj = 0; jj < tn; ++jj) {
+          const float4 X = SM ? gref[jj] : s_ref[jj];
+          const float lw = SM ? glw[jj] : s_lw[jj];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const float rx = yx[r] - X.x, ry = yy[r] - X.y, rz = yz[r] - X.z;
+            float q;
+            const float c = pair_coef<PM>(rx, ry, rz, bi[r] - X.w, lw, eps2, hp, q);
+            ax[r] = __builtin_fmaf(c, rx, ax[r]);
+            ay[r] = __builtin_fmaf(c, ry, ay[r]);
+            az[r] = __builtin_fmaf(c, rz, az[r]);
+            if constexpr (WU) au[r] = __builtin_fmaf(c, q, au[r]);
+          }
         }
       }
 #pragma unroll
@@ -500,6 +530,16 @@ __device__ inline void force_block(const ForceArgs& A, int iblk, int j0, int j1,
   for (int r = 0; r < R; ++r) {
     const int ip = ip0 + r * F_BT;
     if (ip >= A.M) continue;
+    if constexpr (!MOM) {
+      if (expd) {
+        const double dl = (double)(bi[r] - beta);
+        const double sc = exp2(-dl * dl);
+        tx[r] *= sc;
+        ty[r] *= sc;
+        tz[r] *= sc;
+        if constexpr (WU) tu[r] *= sc;
+      }
+    }
     if constexpr (MOM) {
       yx[r] = s_y[r * F_BT + threadIdx.x];
       yy[r] = s_y[(R + r) * F_BT + threadIdx.x];
@@ -570,10 +610,10 @@ __global__ __launch_bounds__(F_BT) void force_kernel(ForceArgs A) {
     j0 = chunk * A.chunk_len;
     j1 = min(A.N, j0 + A.chunk_len);
   } else {
-    // balanced chunks: chunk c covers the 64-point groups [c n / C, (c + 1) n / C)
-    const int64_t n_sub = (A.N + 63) / 64;
-    j0 = (int)(chunk * n_sub / A.n_chunks) * 64;
-    j1 = min(A.N, (int)((chunk + 1) * n_sub / A.n_chunks) * 64);
+    // balanced chunks: chunk c covers the F_GRAN-point groups [c n / C, (c + 1) n / C)
+    const int64_t n_sub = (A.N + F_GRAN - 1) / F_GRAN;
+    j0 = (int)(chunk * n_sub / A.n_chunks) * F_GRAN;
+    j1 = min(A.N, (int)((chunk + 1) * n_sub / A.n_chunks) * F_GRAN);
   }
   force_block<R, PM, WU, WF, SM>(A, blockIdx.x % n_iblk, j0, j1, chunk, blockIdx.x, s_ref, s_lw, s_red, s_y);
 }
@@ -713,6 +753,7 @@ int force_blocks_per_cu(int R, int pm, bool sm) {
 }
 
 int force_points_per_block(int R) { return F_BT * R; }
+int force_chunk_gran() { return F_GRAN; }
 int force_tile_j() { return F_TJ; }
 
 hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool want_f, hipStream_t st, bool sm) {

@@ -112,7 +112,7 @@ struct AdjArgs {
   const float* reflw;
   const Derived* dv;
   int M, N;
-  int chunk_len, n_chunks, nblk;
+  int chunk_len, n_chunks, nblk;  // chunk_len 0: n_chunks balanced chunks
   bool p1;              // p == 1: no distance-law derivative terms
   double G;             // force constant
   const float* f;       // forces of the forward pass [M][3]
@@ -127,6 +127,10 @@ struct AdjArgs {
 };
 
 hipError_t launch_adjoint(const AdjArgs& A, int R, double* fsum_tmp, hipStream_t st);
+// Resident blocks per CU of the adjoint pair kernel; granularity of its
+// balanced reference chunks (AdjArgs.chunk_len = 0).
+int adj_blocks_per_cu(int R, bool p1);
+int adj_chunk_gran();
 // Adjoint of one rigid update: gpose_in[13] and gW[16] from gpose_out[13]
 // (pose_in the pose the update started from, W its wrench).
 hipError_t launch_update_bwd(const double* pose_in, const double* W, const double* gpose_out, const Derived* dv,
@@ -277,6 +281,7 @@ int mixed_points_per_block();
 // f_out[perm[ip]] (perm nullable) = sum over chunks of fpart[chunk][ip] (visiting order).
 hipError_t launch_reduce_f(const double* fpart, int n_chunks, int M, const int* perm, float* f_out, hipStream_t st);
 int force_points_per_block(int R);
+int force_chunk_gran();
 int force_tile_j();
 hipError_t launch_update(const double* wpart, int nblk, const double* pose_in, double* pose_out, Derived* dv, int t,
                          double G_fixed, int do_update, double* wrench_out, double* stats_row, hipStream_t st);
