@@ -146,6 +146,17 @@ int sgr_descriptors(sgr_ctx* ctx, const sgr_cloud* c, int k, float* a_out, doubl
  * (int32), row i sorted by (float32 squared distance, index). */
 int sgr_knn(sgr_ctx* ctx, const sgr_cloud* c, int k, int32_t* idx_out, sgr_stream_t stream);
 
+/* "descriptors(cloud)" for many clouds at once (the batched registrations'
+ * descriptors): the same exact k nearest neighbours and curvature (Sec.
+ * III-A) as sgr_knn / sgr_descriptors on each cloud, with one launch per
+ * phase of the grid search for all clouds.  a_out[c] (device float32
+ * [n_c], or a_out NULL) receives cloud c's curvatures; idx_out (nullable;
+ * entries nullable) its neighbour lists int32 [n_c][k] as sgr_knn writes
+ * them.  Synchronises the stream once.  SGR_EINVAL for k outside [1, 32], a
+ * cloud with fewer than k points, or no output. */
+int sgr_descriptors_batch(sgr_ctx* ctx, int n_clouds, const sgr_cloud* clouds, int k, float* const* a_out,
+                          int32_t* const* idx_out, sgr_stream_t stream);
+
 /* "step(template, reference, pose)": exactly one iteration t of Sec. III
  * from pose `in`, writing `out` (device; may alias `in`).
  * a_t[M], a_r[N]: curvatures (e.g. from sgr_descriptors); mom_t, mom_r: the

@@ -55,6 +55,35 @@ void ora_forces(int64_t M, int64_t N, const double* Y, const double* aY, const d
   *U_out = (G / Z) * Utot / (p + 1.0);
 }
 
+/* ora_pair_sums (p = 1 only, where h = 1 and the pair weight
+ * c_ij = w_j g_ij does not depend on the pose): per template row i the sums
+ * over the reference S0_i = sum_j c_ij, Sx_i = sum_j c_ij x_j (3) and
+ * Sxx_i = sum_j c_ij |x_j|^2, out[5 i ...].  With them eq. 5 reads
+ * f_i = -(G/Z) (y_i S0_i - Sx_i) for any pose. */
+void ora_pair_sums(int64_t M, int64_t N, const double* aY, const double* X, const double* aX,
+                   const double* wX, int g_mode, double sigma, double abar, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < M; ++i) {
+    double s0 = 0.0, sx = 0.0, sy = 0.0, sz = 0.0, sq = 0.0;
+    for (int64_t j = 0; j < N; ++j) {
+      double da = aY[i] - aX[j];
+      double s = exp(-(da * da) / (sigma * sigma));
+      double g = (g_mode == 1) ? (aY[i] / abar) * (aX[j] / abar) * s : (g_mode == 2 ? 1.0 : s);
+      double c = wX[j] * g;
+      s0 += c;
+      sx += c * X[3 * j + 0];
+      sy += c * X[3 * j + 1];
+      sz += c * X[3 * j + 2];
+      sq += c * (X[3 * j + 0] * X[3 * j + 0] + X[3 * j + 1] * X[3 * j + 1] + X[3 * j + 2] * X[3 * j + 2]);
+    }
+    out[5 * i + 0] = s0;
+    out[5 * i + 1] = sx;
+    out[5 * i + 2] = sy;
+    out[5 * i + 3] = sz;
+    out[5 * i + 4] = sq;
+  }
+}
+
 static float sq32(const float* P, int64_t a, int64_t b) {
   float dx = P[3 * a + 0] - P[3 * b + 0];
   float dy = P[3 * a + 1] - P[3 * b + 1];

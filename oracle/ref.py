@@ -470,7 +470,7 @@ class StepOut:
     C: np.ndarray       # cross-covariance
 
 
-def step(Y: np.ndarray, S: Setup, t: int, d_prev=None) -> StepOut:
+def step(Y: np.ndarray, S: Setup, t: int, d_prev=None, force_fn=None) -> StepOut:
     """One iteration of Sec. III: forces (eq. 5), Newtonian translation
     (eq. 5.5), Kabsch rotation (eq. 6), eigenvalue scale (eq. 8), update
     (eq. 9), with G from eq. 12.  Velocity (eq. 5.5's v^X, eq. 1's friction
@@ -478,11 +478,12 @@ def step(Y: np.ndarray, S: Setup, t: int, d_prev=None) -> StepOut:
     translation then, d_prev, of which the share mu = prm.momentum is carried
     (mu = 1 - the friction's share); every point moves by it, so it shifts Y_D
     as a whole and leaves the rotation unchanged.  mu = 0 or d_prev None is
-    the paper's v = 0."""
+    the paper's v = 0.  force_fn(Y, S, G) -> (f, U) replaces forces() (the
+    same quantities evaluated another way, e.g. forces_from_sums)."""
     prm = S.prm
     G = G_schedule(t, prm.E, prm.G1)
     dt2 = prm.dt2 if prm.dt2 > 0 else 1.0 / prm.G1
-    f, U = forces(Y, S, G)
+    f, U = forces(Y, S, G) if force_fn is None else force_fn(Y, S, G)
     carry = prm.momentum * np.asarray(d_prev, np.float64) if d_prev is not None else np.zeros(3)
     delta = dt2 * f + carry                           # per-point displacement
     F = (S.mY[:, None] * f).sum(axis=0)
@@ -522,10 +523,10 @@ def compose(pose: Pose, so: StepOut, ybar: np.ndarray) -> Pose:
     return Pose(so.c * pose.s, Rt @ pose.R, so.c * Rt @ (pose.t - ybar) + ybar + so.d)
 
 
-def register(Y0, S: Setup, E=None, pose0: Pose | None = None, t0: int = 0, keep=False):
+def register(Y0, S: Setup, E=None, pose0: Pose | None = None, t0: int = 0, keep=False, force_fn=None):
     """E iterations from Y0 (optionally pre-posed).  Returns the final pose
     (mapping the input template onto the registered one), the final points,
-    and (if keep) the per-iteration StepOut list."""
+    and (if keep) the per-iteration StepOut list.  force_fn: as in step()."""
     E = S.prm.E if E is None else E
     pose = Pose.identity() if pose0 is None else pose0
     Y = pose.apply(Y0)
@@ -533,13 +534,23 @@ def register(Y0, S: Setup, E=None, pose0: Pose | None = None, t0: int = 0, keep=
     d_prev = None                                     # the template starts at rest
     for t in range(t0, t0 + E):
         ybar = Y.mean(axis=0)
-        so = step(Y, S, t, d_prev)
+        so = step(Y, S, t, d_prev, force_fn=force_fn)
         pose = compose(pose, so, ybar)
         Y = so.Y
         d_prev = so.d
         if keep:
             hist.append(so)
     return pose, Y, hist
+
+
+def register_p1(Y0, S: Setup, E=None, pose0: Pose | None = None, keep=False, sums=None):
+    """register() for p = 1 with the forces from the pose-independent pair
+    sums (pair_sums_c, formed once): the same iteration, O(M) per step
+    after an O(MN) start.  Returns (pose, Y, hist, sums)."""
+    sums = pair_sums_c(S) if sums is None else sums
+    pose, Y, hist = register(Y0, S, E=E, pose0=pose0, keep=keep,
+                             force_fn=lambda Yt, S_, G: forces_from_sums(Yt, S_, G, sums))
+    return pose, Y, hist, sums
 
 
 # ------------------------------------------------------- pyramidal schedule
@@ -632,6 +643,7 @@ def _clib():
         D = ctypes.c_double
         _LIB.ora_forces.argtypes = [I64, I64, P, P, P, P, P, D, ctypes.c_int, D, D, D, D, D, D, P, P, P]
         _LIB.ora_knn.argtypes = [I64, P, ctypes.c_int, I64, P, P]
+        _LIB.ora_pair_sums.argtypes = [I64, I64, P, P, P, P, ctypes.c_int, D, D, P]
         _LIB.ora_threads.restype = ctypes.c_int
         _LIB.ora_set_threads.argtypes = [ctypes.c_int]
     return _LIB
@@ -671,6 +683,32 @@ def forces_c(Y: np.ndarray, S: Setup, G: float, rows=None, want_scale: bool = Fa
     if want_scale:
         return f, float(U[0]), sc
     return f, float(U[0])
+
+
+def pair_sums_c(S: Setup) -> np.ndarray:
+    """For p = 1 (h = 1) the pair weights c_ij = w_j g_ij of eq. 5 do not
+    depend on the pose, so per template row the sums S0 = sum_j c_ij,
+    Sx = sum_j c_ij x_j (3) and Sxx = sum_j c_ij |x_j|^2 hold for every
+    iterate (C loops).  Returns (M, 5)."""
+    if S.prm.p != 1.0:
+        raise ValueError("pose-independent pair sums need p = 1")
+    aY = np.ascontiguousarray(S.aY, dtype=np.float64)
+    X = np.ascontiguousarray(S.X, dtype=np.float64)
+    out = np.empty((len(aY), 5))
+    _clib().ora_pair_sums(len(aY), len(X), _ptr(aY), _ptr(X), _ptr(np.ascontiguousarray(S.aX, dtype=np.float64)),
+                          _ptr(np.ascontiguousarray(S.wX, dtype=np.float64)), int(S.prm.g_mode), float(S.sigma),
+                          float(S.abar), _ptr(out))
+    return out
+
+
+def forces_from_sums(Y: np.ndarray, S: Setup, G: float, sums: np.ndarray):
+    """forces() at p = 1 from pair_sums_c: f_i = -(G/Z) (y_i S0_i - Sx_i)
+    and U = (G/Z) sum_i [(|y_i|^2 + eps^2) S0_i - 2 y_i . Sx_i + Sxx_i] / 2,
+    i.e. eq. 5 and its energy with the sum over the reference taken first."""
+    Y = np.asarray(Y, np.float64)
+    f = -(G / S.Z) * (Y * sums[:, 0:1] - sums[:, 1:4])
+    q = (np.sum(Y * Y, axis=1) + S.prm.eps ** 2) * sums[:, 0] - 2.0 * np.sum(Y * sums[:, 1:4], axis=1) + sums[:, 4]
+    return f, (G / S.Z) * float(np.sum(q)) / 2.0
 
 
 def knn_c(P: np.ndarray, k: int, queries=None) -> np.ndarray:

@@ -173,6 +173,18 @@ class Context:
         check(lib().sgr_descriptors(self._h, ctypes.byref(c), int(k), _ptr(a), _ptr(mom), _stream(self.device)))
         return a, mom
 
+    def descriptors_batch(self, clouds, k: int, want_idx=False):
+        """Curvatures (and neighbour lists) of many clouds in one call:
+        ([a_c float32 [n_c]], [idx_c int32 [n_c, k]] or None)."""
+        B = len(clouds)
+        a = [torch.empty(c.n, dtype=torch.float32, device=self.device) for c in clouds]
+        idx = [torch.empty((c.n, k), dtype=torch.int32, device=self.device) for c in clouds] if want_idx else None
+        cc = (SgrCloud * B)(*[c.c() for c in clouds])
+        pa = (ctypes.c_void_p * B)(*[t.data_ptr() for t in a])
+        pi = (ctypes.c_void_p * B)(*[t.data_ptr() for t in idx]) if want_idx else None
+        check(lib().sgr_descriptors_batch(self._h, B, cc, int(k), pa, pi, _stream(self.device)))
+        return a, idx
+
     def knn(self, cloud: Cloud, k: int) -> torch.Tensor:
         idx = torch.empty((cloud.n, k), dtype=torch.int32, device=self.device)
         c = cloud.c()

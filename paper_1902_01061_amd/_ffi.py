@@ -52,6 +52,7 @@ SIGNATURES = {
     "sgr_destroy": [P],
     "sgr_descriptors": [P, CP, I, P, P, P],
     "sgr_knn": [P, CP, I, P, P],
+    "sgr_descriptors_batch": [P, I, CP, I, P, P, P],
     "sgr_step": [P, CP, P, CP, P, P, P, PP, I, P, P, P, P, P],
     "sgr_register": [P, CP, CP, PP, P, P, P],
     "sgr_residual": [P, CP, CP, P, P, P, P],

@@ -174,16 +174,18 @@ FLaunch force_shape(const sgr_ctx* ctx, int M, int N, const Tiles& T, int pm) {
 }
 
 // Launch shape of the adjoint pair kernel: R template points per lane from
-// the tile choice (at most 4), n_chunks balanced reference chunks so that
-// the launch is one wave of resident blocks.
+// the tile choice (at most 4), n_chunks balanced reference chunks for about
+// two blocks per CU (fewer for a small pair: chunks of at least 16 points).
+// Every chunk writes 32 bytes per template point of partial sums, so more,
+// shorter chunks cost traffic as well as per-block overhead.
 Tiles adj_shape(const sgr_ctx* ctx, int M, int N, int R, bool p1) {
+  (void)p1;
   if (R > 4) R = 4;
   Tiles T{};
   T.R = R;
   T.n_iblk = (M + 256 * R - 1) / (256 * R);
   const int64_t n_sub = (N + adj_chunk_gran() - 1) / adj_chunk_gran();
-  const int64_t nc = std::max<int64_t>(
-      1, std::min<int64_t>(n_sub, (int64_t)adj_blocks_per_cu(R, p1) * ctx->n_cu / T.n_iblk));
+  const int64_t nc = std::max<int64_t>(1, std::min<int64_t>(n_sub, (int64_t)2 * ctx->n_cu / T.n_iblk));
   T.n_chunks = (int)nc;
   T.chunk_len = 0;
   T.nblk = T.n_iblk * T.n_chunks;
@@ -346,6 +348,10 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
     cv.take<RegDesc>(B);
     cv.take<double>((size_t)perm_total * 5);
   }
+  std::vector<int> cl_n(ncl);
+  for (int c = 0; c < ncl; ++c) cl_n[c] = (int)in.clouds[c]->n;
+  const size_t gws_bytes = grid_knn_batch_workspace(cl_n.data(), ncl, prm->k);
+  cv.take<char>(gws_bytes);
   if (int e = ensure_ws(ctx, cv.off)) return e;
   Carve w{ctx->ws};
   CloudDesc* d_cds = w.take<CloudDesc>(ncl);
@@ -369,6 +375,7 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
   int2* d_tblk = pinv ? w.take<int2>(n_tblk) : nullptr;
   RegDesc* d_regs_p = pinv ? w.take<RegDesc>(B) : nullptr;
   double* d_S = pinv ? w.take<double>((size_t)perm_total * 5) : nullptr;
+  char* d_gws = w.take<char>(gws_bytes);
 
   for (int c = 0; c < ncl; ++c)
     cds[c] = CloudDesc{in.clouds[c]->x, in.clouds[c]->y, in.clouds[c]->z, d_a + a_off[c], (int)in.clouds[c]->n, 0};
@@ -411,10 +418,21 @@ int run_batch(sgr_ctx* ctx, const BatchIn& in, const sgr_params* prm, double* po
     HIPCHK(hipMemcpyAsync(d_regs_p, regs_p.data(), sizeof(RegDesc) * B, hipMemcpyHostToDevice, st));
   }
 
-  // descriptors of every cloud in one brute-force launch: with hundreds of
-  // small clouds a single launch keeps the chip busy, where one grid search
-  // per cloud would be a long chain of small launches
-  HIPCHK(launch_knn_desc_batch(d_cds, d_kb, (int)kblocks.size(), prm->k, st));
+  // descriptors of every cloud: the exact grid search for all clouds at
+  // once, one launch per phase (a grid search per cloud would be a long
+  // chain of small launches, brute force n^2 work per cloud)
+  {
+    std::vector<const float*> cx(ncl), cy(ncl), cz(ncl);
+    std::vector<float*> ca(ncl);
+    for (int c = 0; c < ncl; ++c) {
+      cx[c] = in.clouds[c]->x;
+      cy[c] = in.clouds[c]->y;
+      cz[c] = in.clouds[c]->z;
+      ca[c] = d_a + a_off[c];
+    }
+    HIPCHK(launch_grid_knn_batch(cx.data(), cy.data(), cz.data(), cl_n.data(), ca.data(), nullptr, ncl, prm->k,
+                                 d_gws, st));
+  }
   HIPCHK(launch_moments_batch(d_cds, ncl, d_mom, st));
   HIPCHK(launch_prepare_batch(d_prep, B, prep_of(prm), d_dv, st));
   HIPCHK(launch_pack_batch(d_prep, d_b2r, (int)blk2reg.size(), d_dv, d_ref4, d_lw, st));
@@ -622,6 +640,8 @@ struct VecWs {
   double* mom;
   int K, n_chunks, slots;
   bool half;  // split-f16 products (decided by setup_vec)
+  int* far_idx;  // far template rows (M + 1 ints: the list, then its length)
+  int n_far;     // number of far rows (read back by setup_vec)
   // flags bit 3: the template in its own order, the pair sums per chunk, reduced
   float4* tm4 = nullptr;
   float2* tmx = nullptr;
@@ -633,7 +653,8 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
   w.K = vforce_K(D);
   w.n_chunks = vforce_chunks(M, N, ctx->n_cu);
   w.slots = vforce_n_iblk(M) * w.n_chunks;
-  const int wslots = pinv ? std::max(w.slots, pinv_blocks(M)) : w.slots;
+  // every template row may be a far row, with a wrench slot of its own
+  const int wslots = pinv ? std::max(w.slots + M, pinv_blocks(M)) : w.slots + M;
   for (int pass = 0; pass < 2; ++pass) {
     Carve c{pass ? ctx->ws : nullptr};
     w.dv = c.take<Derived>(1);
@@ -646,6 +667,7 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
     w.wpart = c.take<double>((size_t)wslots * WR_STRIDE);
     w.fpart = with_f ? c.take<double>((size_t)w.n_chunks * M * 3) : nullptr;
     w.mom = with_mom ? c.take<double>(20) : nullptr;
+    w.far_idx = c.take<int>((size_t)M + 1);
     if (pinv) {
       w.tm4 = c.take<float4>(M);
       w.tmx = c.take<float2>(M);
@@ -666,17 +688,28 @@ int setup_vec(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, con
   const int M = (int)tmpl->n, N = (int)ref->n;
   HIPCHK(launch_prepare(nullptr, ref->m, N, nullptr, tmpl->m, M, mom_t, mom_r, prep_of(prm), w.dv, st));
   HIPCHK(launch_vprep(a_r, N, a_t, M, D, prm->sigma, w.dv, w.vd, st));
-  w.half = false;
-  if (!(prm->flags & FLAG_VEC_FP32)) {
-    double cmax = 0.0;
-    HIPCHK(hipMemcpyAsync(&cmax, w.vd + 34, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    w.half = vforce_half_ok(cmax);
-  }
+  HIPCHK(launch_vfar_list(a_t, M, D, w.vd, w.far_idx, st));
+  double cmax = 0.0;
+  int n_far = 0;
+  HIPCHK(hipMemcpyAsync(&cmax, w.vd + 34, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&n_far, w.far_idx + M, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  w.n_far = n_far;
+  w.half = !(prm->flags & FLAG_VEC_FP32) && vforce_half_ok(cmax);
   if (w.half) w.K = vforce_half_K(D);
   HIPCHK(launch_vpack(ref->x, ref->y, ref->z, a_r, ref->m, N, a_t, M, D, w.half, w.dv, w.vd, w.Bt, w.ref4, w.At,
                       st));
   return SGR_OK;
+}
+
+// The vector-descriptor force of one iteration: the contraction kernel,
+// then the far rows; returns through `used` the wrench slots written.
+hipError_t run_vforce(const VForceArgs& A, const sgr_cloud* ref, const float* a_r, const float* a_t, int D,
+                      const VecWs& w, bool wu, bool wf, int* used, hipStream_t st) {
+  hipError_t e = launch_vforce(A, wu, wf, st);
+  if (e != hipSuccess) return e;
+  if (used) *used = w.slots + w.n_far;
+  return launch_vfar(A, a_r, ref->m, a_t, D, w.vd, w.far_idx, w.n_far, w.slots, wu, wf, st);
 }
 
 VForceArgs vargs(const sgr_cloud* tmpl, const sgr_cloud* ref, const VecWs& w, const double* pose, int t) {
@@ -916,6 +949,29 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   return SGR_OK;
 }
 
+int sgr_descriptors_batch(sgr_ctx* ctx, int n_clouds, const sgr_cloud* clouds, int k, float* const* a_out,
+                          int32_t* const* idx_out, sgr_stream_t stream) {
+  if (!ctx || !clouds || (!a_out && !idx_out)) return fail(SGR_EINVAL, "NULL argument");
+  if (n_clouds < 1) return fail(SGR_EINVAL, "n_clouds must be >= 1");
+  if (k < 1 || k > 32) return fail(SGR_EINVAL, "k must be in [1, 32]");
+  std::vector<const float*> cx(n_clouds), cy(n_clouds), cz(n_clouds);
+  std::vector<int> cn(n_clouds);
+  for (int c = 0; c < n_clouds; ++c) {
+    if (int e = check_cloud(&clouds[c], "cloud")) return e;
+    if (clouds[c].n < k) return fail(SGR_EINVAL, "a cloud has fewer points than k");
+    if ((a_out && !a_out[c]) || (!a_out && !idx_out[c])) return fail(SGR_EINVAL, "NULL output array");
+    cx[c] = clouds[c].x;
+    cy[c] = clouds[c].y;
+    cz[c] = clouds[c].z;
+    cn[c] = (int)clouds[c].n;
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  if (int e = ensure_ws(ctx, grid_knn_batch_workspace(cn.data(), n_clouds, k))) return e;
+  HIPCHK(launch_grid_knn_batch(cx.data(), cy.data(), cz.data(), cn.data(), a_out, idx_out, n_clouds, k, ctx->ws,
+                               (hipStream_t)stream));
+  return SGR_OK;
+}
+
 int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm, sgr_pose* inout,
                  double* stats, sgr_stream_t stream) {
   if (!ctx || !inout) return fail(SGR_EINVAL, "NULL argument");
@@ -1060,9 +1116,11 @@ int sgr_step_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   VecWs w;
   if (int e = carve_vec(ctx, M, (int)ref->n, D, f_out != nullptr, false, w)) return e;
   if (int e = setup_vec(tmpl, a_t, ref, a_r, D, mom_t, mom_r, prm, w, st)) return e;
-  HIPCHK(launch_vforce(vargs(tmpl, ref, w, (const double*)in, t), wrench_out != nullptr, f_out != nullptr, st));
+  int used = w.slots;
+  HIPCHK(run_vforce(vargs(tmpl, ref, w, (const double*)in, t), ref, a_r, a_t, D, w, wrench_out != nullptr,
+                    f_out != nullptr, &used, st));
   if (f_out) HIPCHK(launch_reduce_f(w.fpart, w.n_chunks, M, nullptr, f_out, st));
-  HIPCHK(launch_update(w.wpart, w.slots, (const double*)in, (double*)out, w.dv, t, 0.0, 1, wrench_out, nullptr, st));
+  HIPCHK(launch_update(w.wpart, used, (const double*)in, (double*)out, w.dv, t, 0.0, 1, wrench_out, nullptr, st));
   return SGR_OK;
 }
 
@@ -1087,7 +1145,7 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
     // the pair sums once: one pass of the vector kernel writing them per chunk
     VForceArgs A = vargs(tmpl, ref, w, (const double*)inout, 0);
     A.spart = w.ps_part;
-    HIPCHK(launch_vforce(A, true, false, st));
+    HIPCHK(run_vforce(A, ref, a_r, a_t, D, w, true, false, nullptr, st));
     HIPCHK(launch_psum_reduce(w.ps_part, M, w.n_chunks, w.ps_S, st));
     HIPCHK(launch_pack_plain(tmpl->x, tmpl->y, tmpl->z, tmpl->m, M, w.tm4, w.tmx, st));
   }
@@ -1099,7 +1157,7 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
         HIPCHK(launch_pinv(w.tm4, w.tmx, w.ps_S, M, (const double*)inout, w.dv, t, wu, w.wpart, s));
         used = pinv_blocks(M);
       } else {
-        HIPCHK(launch_vforce(vargs(tmpl, ref, w, (const double*)inout, t), wu, false, s));
+        HIPCHK(run_vforce(vargs(tmpl, ref, w, (const double*)inout, t), ref, a_r, a_t, D, w, wu, false, &used, s));
       }
       HIPCHK(launch_update(w.wpart, used, (const double*)inout, (double*)inout, w.dv, t, 0.0, 1, nullptr,
                            stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));
@@ -1112,8 +1170,8 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
     std::vector<uint8_t> key;
     const void* ptrs[12] = {tmpl->x, tmpl->y, tmpl->z, tmpl->m, ref->x, ref->y, ref->z, ref->m, inout, stats, a_t, a_r};
     key_add(key, ptrs, 12);
-    const int64_t dims[4] = {M, N, D, w.half ? 1 : 0};
-    key_add(key, dims, 4);
+    const int64_t dims[5] = {M, N, D, w.half ? 1 : 0, w.n_far};
+    key_add(key, dims, 5);
     key_add(key, prm, 1);
     const void* wsp = ctx->ws;
     key_add(key, &wsp, 1);
@@ -1174,7 +1232,9 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   const int pm = pmode_of(prm->p);
   const auto key = std::make_tuple(log2_bucket(M), log2_bucket(N), pm);
   // Candidates: template points per lane, the reference load variant, and
-  // one or two waves of resident blocks (from the kernel's occupancy).
+  // the blocks per CU of the launch: 1 to 4 (long reference chunks, a few
+  // resident blocks), one or two waves of resident blocks (from the
+  // kernel's occupancy).
   const int cand_R[4] = {1, 2, 4, 8};
   // size the workspace for the largest candidate
   size_t need = 0;
@@ -1217,9 +1277,12 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   int bR = 4, bB = 8, bV = 0;
   for (int v : {0, 1})
     for (int R : cand_R)
-      for (int waves : {1, 2}) {
+      for (int c = 0; c < 6; ++c) {
+        const int occ = force_blocks_per_cu(R, pm, v != 0);
+        const int bpc = c < 4 ? c + 1 : (c - 3) * occ;
+        if (c < 4 && bpc >= occ) continue;  // covered by the occupancy targets
         Tiles T = TileTable::make(M, N, R, 8 * ctx->n_cu, v);
-        T.bpc = waves * force_blocks_per_cu(R, pm, v != 0);
+        T.bpc = bpc;
         const FLaunch L = force_shape(ctx, M, N, T, pm);
         Carve wc{ctx->ws, wp_off};
         double* wpart = wc.take<double>((size_t)L.slots * WR_STRIDE);

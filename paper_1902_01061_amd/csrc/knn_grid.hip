@@ -13,6 +13,8 @@
 //    until the current k-th distance is below the distance from the query to
 //    the unsearched region (with a margin that covers the float32 rounding
 //    of cell assignment and of the key), so no closer point can be missed.
+#include <vector>
+
 #include "common.h"
 #include "launch.h"
 
@@ -48,9 +50,11 @@ constexpr int GQ_BT = 256;
 constexpr int KNN_RCAP = 2;  // shells a lane searches alone before handing its query to a wave
 constexpr int SCAN_B = 1024;
 
-__global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                          const float* __restrict__ Zc, int n, int max_cells,
-                                                          GridInfo* __restrict__ gi, int* __restrict__ far) {
+// Bodies of the grid kernels, shared by the one-cloud kernels and their
+// batched forms (a table of clouds, one launch per phase for all of them).
+__device__ inline void grid_setup_body(const float* __restrict__ X, const float* __restrict__ Y,
+                                       const float* __restrict__ Zc, int n, int max_cells, GridInfo* __restrict__ gi,
+                                       int* __restrict__ far) {
   if (threadIdx.x == 0) far[0] = 0;  // count of queries handed to the wave-per-query pass
   __shared__ float red[16][6];
   float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -105,6 +109,12 @@ __global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restric
   *gi = G;
 }
 
+__global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                          const float* __restrict__ Zc, int n, int max_cells,
+                                                          GridInfo* __restrict__ gi, int* __restrict__ far) {
+  grid_setup_body(X, Y, Zc, n, max_cells, gi, far);
+}
+
 // Second look at the cell size, from the first count: scans are surfaces
 // (often with dense clusters), whose occupied cells hold many more points
 // than the 2 per cell of a volume, and a query inside them meets hundreds of
@@ -113,8 +123,8 @@ __global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restric
 // the side squared), and left as it is for volume-like clouds.  The caller
 // counts again with the new grid.  (Measured on the scan clouds: queries in
 // their clusters dominate the search time at 2 points per cell.)
-__global__ __launch_bounds__(1024) void grid_refine_kernel(const int* __restrict__ counts, int n, int max_cells,
-                                                           GridInfo* __restrict__ gi) {
+__device__ inline void grid_refine_body(const int* __restrict__ counts, int n, int max_cells,
+                                        GridInfo* __restrict__ gi) {
   __shared__ int red[16];
   const GridInfo G0 = *gi;
   int occ = 0;
@@ -132,6 +142,11 @@ __global__ __launch_bounds__(1024) void grid_refine_kernel(const int* __restrict
   *gi = G;
 }
 
+__global__ __launch_bounds__(1024) void grid_refine_kernel(const int* __restrict__ counts, int n, int max_cells,
+                                                           GridInfo* __restrict__ gi) {
+  grid_refine_body(counts, n, max_cells, gi);
+}
+
 // Cell coordinates and cell faces are computed in FP64 so that rounding
 // cannot move a point across a face by more than a negligible fraction of a
 // cell, whatever the offset of the cloud from the origin.
@@ -141,11 +156,9 @@ __device__ inline int cell_coord(float p, float lo, float h, int dim) {
   return c;
 }
 
-__global__ __launch_bounds__(256) void grid_count_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                         const float* __restrict__ Zc, int n,
-                                                         const GridInfo* __restrict__ gi, int* __restrict__ cell_of,
-                                                         int* __restrict__ counts) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+__device__ inline void grid_count_point(const float* __restrict__ X, const float* __restrict__ Y,
+                                        const float* __restrict__ Zc, int n, const GridInfo* __restrict__ gi,
+                                        int* __restrict__ cell_of, int* __restrict__ counts, int i) {
   if (i >= n) return;
   const GridInfo& G = *gi;
   const int cx = cell_coord(X[i], G.lo[0], G.h, G.dims[0]);
@@ -154,6 +167,13 @@ __global__ __launch_bounds__(256) void grid_count_kernel(const float* __restrict
   const int c = (cz * G.dims[1] + cy) * G.dims[0] + cx;
   cell_of[i] = c;
   atomicAdd(&counts[c], 1);
+}
+
+__global__ __launch_bounds__(256) void grid_count_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                         const float* __restrict__ Zc, int n,
+                                                         const GridInfo* __restrict__ gi, int* __restrict__ cell_of,
+                                                         int* __restrict__ counts) {
+  grid_count_point(X, Y, Zc, n, gi, cell_of, counts, blockIdx.x * 256 + threadIdx.x);
 }
 
 // Exclusive scan of counts[0, m) into starts[0, m], in three passes.
@@ -193,16 +213,22 @@ __global__ __launch_bounds__(SCAN_B) void scan_add_kernel(int* __restrict__ out,
   if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = bsum[nb];
 }
 
+__device__ inline void grid_scatter_point(const float* __restrict__ X, const float* __restrict__ Y,
+                                          const float* __restrict__ Zc, int n, const int* __restrict__ cell_of,
+                                          const int* __restrict__ starts, int* __restrict__ cursor,
+                                          float4* __restrict__ spts, int i) {
+  if (i >= n) return;
+  const int c = cell_of[i];
+  const int pos = starts[c] + atomicAdd(&cursor[c], 1);
+  spts[pos] = make_float4(X[i], Y[i], Zc[i], __int_as_float(i));
+}
+
 __global__ __launch_bounds__(256) void grid_scatter_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                            const float* __restrict__ Zc, int n,
                                                            const int* __restrict__ cell_of,
                                                            const int* __restrict__ starts, int* __restrict__ cursor,
                                                            float4* __restrict__ spts) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int c = cell_of[i];
-  const int pos = starts[c] + atomicAdd(&cursor[c], 1);
-  spts[pos] = make_float4(X[i], Y[i], Zc[i], __int_as_float(i));
+  grid_scatter_point(X, Y, Zc, n, cell_of, starts, cursor, spts, blockIdx.x * 256 + threadIdx.x);
 }
 
 __device__ inline bool key_less(float d, int i, float bd, int bi) { return d < bd || (d == bd && i < bi); }
@@ -329,16 +355,13 @@ __device__ inline void insert_key(uint64_t (&L)[KC], uint64_t key) {
 // would make the wave run the 5 KC-operation insertion at almost every step.
 constexpr int KNN_CB = 8;
 
+// Query t (a position in the cell-sorted array); buf and cand are the lane's
+// LDS columns (stride GQ_BT).  No barriers.
 template <int KC>
-__global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
-                                                         const GridInfo* __restrict__ gi, int n, int k, int rcap,
-                                                         int* __restrict__ far, int32_t* __restrict__ idx_out) {
-  __shared__ float4 s_buf[SPAN_U * GQ_BT];
-  __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
-  float4* buf = s_buf + threadIdx.x;
-  uint64_t* cand = s_cand + threadIdx.x;
-  const int t = blockIdx.x * GQ_BT + threadIdx.x;
-  if (t >= n) return;  // no barriers below
+__device__ inline void grid_knn_query(const float4* __restrict__ spts, const int* __restrict__ starts,
+                                      const GridInfo* __restrict__ gi, int n, int k, int rcap, int* __restrict__ far,
+                                      int32_t* __restrict__ idx_out, int t, float4* buf, uint64_t* cand) {
+  if (t >= n) return;
   const GridInfo G = *gi;
   const float4 q = spts[t];
   const int qi = __float_as_int(q.w);
@@ -411,6 +434,16 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
     if (s >= KC - k) idx_out[o + (s - (KC - k))] = (int32_t)(uint32_t)L[s];
 }
 
+template <int KC>
+__global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restrict__ spts, const int* __restrict__ starts,
+                                                         const GridInfo* __restrict__ gi, int n, int k, int rcap,
+                                                         int* __restrict__ far, int32_t* __restrict__ idx_out) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
+  grid_knn_query<KC>(spts, starts, gi, n, k, rcap, far, idx_out, blockIdx.x * GQ_BT + threadIdx.x,
+                     s_buf + threadIdx.x, s_cand + threadIdx.x);
+}
+
 // The queries grid_knn_kernel left unfinished, one wave per query (a
 // wave-uniform loop over the far list).  Lane l scans rows l, l + 64, ... of
 // each shell into its own sorted list of the KC best keys it has met (every
@@ -420,17 +453,12 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
 // a merged entry are popped together), and every lane continues from the
 // merged list.  The stopping test is grid_knn_kernel's on the merged k-th
 // key, so the neighbour list is the same exact one.
+// Wave `wave` of n_waves takes the far queries wave, wave + n_waves, ...
 template <int KC>
-__global__ __launch_bounds__(GQ_BT) void grid_knn_far_kernel(const float4* __restrict__ spts,
-                                                             const int* __restrict__ starts,
-                                                             const GridInfo* __restrict__ gi, int n, int k,
-                                                             const int* __restrict__ far,
-                                                             int32_t* __restrict__ idx_out) {
-  __shared__ float4 s_buf[SPAN_U * GQ_BT];
-  float4* buf = s_buf + threadIdx.x;
+__device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const int* __restrict__ starts,
+                                          const GridInfo* __restrict__ gi, int k, const int* __restrict__ far,
+                                          int32_t* __restrict__ idx_out, int wave, int n_waves, float4* buf) {
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * GQ_BT + threadIdx.x) >> 6;
-  const int n_waves = (gridDim.x * GQ_BT) >> 6;
   const int cnt = far[0];
   const GridInfo G = *gi;
   const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
@@ -494,11 +522,22 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_far_kernel(const float4* __res
   }
 }
 
+template <int KC>
+__global__ __launch_bounds__(GQ_BT) void grid_knn_far_kernel(const float4* __restrict__ spts,
+                                                             const int* __restrict__ starts,
+                                                             const GridInfo* __restrict__ gi, int n, int k,
+                                                             const int* __restrict__ far,
+                                                             int32_t* __restrict__ idx_out) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  (void)n;
+  grid_knn_far_waves<KC>(spts, starts, gi, k, far, idx_out, (blockIdx.x * GQ_BT + threadIdx.x) >> 6,
+                         (gridDim.x * GQ_BT) >> 6, s_buf + threadIdx.x);
+}
+
 // Curvature from the neighbour lists (FP64 covariance, 1/k, centred).
-__global__ __launch_bounds__(256) void curvature_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                        const float* __restrict__ Zc, int n, int k,
-                                                        const int32_t* __restrict__ idx, float* __restrict__ a_out) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
+__device__ inline void curvature_point(const float* __restrict__ X, const float* __restrict__ Y,
+                                       const float* __restrict__ Zc, int n, int k, const int32_t* __restrict__ idx,
+                                       float* __restrict__ a_out, int q) {
   if (q >= n) return;
   const int32_t* nb = idx + (int64_t)q * k;
   bool missing = false;
@@ -535,6 +574,12 @@ __global__ __launch_bounds__(256) void curvature_kernel(const float* __restrict_
   eig_psd3(C, lam);
   const double tr = C[0] + C[1] + C[2];
   a_out[q] = (tr > 0.0) ? (float)(lam[2] / tr) : 0.f;
+}
+
+__global__ __launch_bounds__(256) void curvature_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                        const float* __restrict__ Zc, int n, int k,
+                                                        const int32_t* __restrict__ idx, float* __restrict__ a_out) {
+  curvature_point(X, Y, Zc, n, k, idx, a_out, blockIdx.x * 256 + threadIdx.x);
 }
 
 int grid_max_cells(int n) {
@@ -703,6 +748,184 @@ __global__ __launch_bounds__(GQ_BT) void grid_nn_kernel(const float4* __restrict
   }
   nn[t] = bi;
   key[t] = bd;
+}
+
+// ---------------------------------------------------------------- batches
+// The same exact search for many clouds (one launch per phase for all of
+// them): every cloud has its own grid and workspace region, and blocks are
+// mapped to clouds through a job table and a (cloud, block) list.
+struct GridJob {
+  const float* x;
+  const float* y;
+  const float* z;
+  float* a_out;
+  int n, max_cells;
+  GridInfo* gi;
+  int* cell_of;
+  int* counts;
+  int* cursor;
+  int* starts;
+  float4* spts;
+  int32_t* nbr;
+  int* far;
+};
+
+__global__ __launch_bounds__(1024) void grid_setup_batch_kernel(const GridJob* __restrict__ jobs) {
+  const GridJob& J = jobs[blockIdx.x];
+  grid_setup_body(J.x, J.y, J.z, J.n, J.max_cells, J.gi, J.far);
+}
+
+__global__ __launch_bounds__(1024) void grid_refine_batch_kernel(const GridJob* __restrict__ jobs) {
+  const GridJob& J = jobs[blockIdx.x];
+  grid_refine_body(J.counts, J.n, J.max_cells, J.gi);
+}
+
+// counts (and, with both, cursor) of every cell set to 0; grid (clouds, splits)
+__global__ __launch_bounds__(1024) void grid_clear_batch_kernel(const GridJob* __restrict__ jobs, int both) {
+  const GridJob& J = jobs[blockIdx.x];
+  for (int c = blockIdx.y * 1024 + threadIdx.x; c < J.max_cells; c += gridDim.y * 1024) {
+    J.counts[c] = 0;
+    if (both) J.cursor[c] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void grid_count_batch_kernel(const GridJob* __restrict__ jobs,
+                                                               const int2* __restrict__ bmap) {
+  const int2 cb = bmap[blockIdx.x];
+  const GridJob& J = jobs[cb.x];
+  grid_count_point(J.x, J.y, J.z, J.n, J.gi, J.cell_of, J.counts, cb.y * 256 + threadIdx.x);
+}
+
+// Exclusive scan of one cloud's cell counts into starts[0, max_cells], one
+// block per cloud, 1024 cells per step: wave scans by shuffles, then the
+// wave totals, then the running carry.
+__global__ __launch_bounds__(1024) void grid_scan_batch_kernel(const GridJob* __restrict__ jobs) {
+  __shared__ int s_w[16];
+  __shared__ int s_carry;
+  const GridJob& J = jobs[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < J.max_cells; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v = i < J.max_cells ? J.counts[i] : 0;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(x, off, 64);
+      if (lane >= off) x += o;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int before = s_carry;
+    for (int u = 0; u < w; ++u) before += s_w[u];
+    if (i < J.max_cells) J.starts[i] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int u = 0; u < 16; ++u) tot += s_w[u];
+      s_carry += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) J.starts[J.max_cells] = s_carry;
+}
+
+__global__ __launch_bounds__(256) void grid_scatter_batch_kernel(const GridJob* __restrict__ jobs,
+                                                                 const int2* __restrict__ bmap) {
+  const int2 cb = bmap[blockIdx.x];
+  const GridJob& J = jobs[cb.x];
+  grid_scatter_point(J.x, J.y, J.z, J.n, J.cell_of, J.starts, J.cursor, J.spts, cb.y * 256 + threadIdx.x);
+}
+
+template <int KC>
+__global__ __launch_bounds__(GQ_BT) void grid_knn_batch_kernel(const GridJob* __restrict__ jobs,
+                                                               const int2* __restrict__ bmap, int k) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
+  const int2 cb = bmap[blockIdx.x];
+  const GridJob& J = jobs[cb.x];
+  grid_knn_query<KC>(J.spts, J.starts, J.gi, J.n, k, KNN_RCAP, J.far, J.nbr, cb.y * GQ_BT + threadIdx.x,
+                     s_buf + threadIdx.x, s_cand + threadIdx.x);
+}
+
+// grid (clouds, splits): the far queries of cloud blockIdx.x over its
+// splits x 4 waves
+template <int KC>
+__global__ __launch_bounds__(GQ_BT) void grid_knn_far_batch_kernel(const GridJob* __restrict__ jobs, int k) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  const GridJob& J = jobs[blockIdx.x];
+  grid_knn_far_waves<KC>(J.spts, J.starts, J.gi, k, J.far, J.nbr, (blockIdx.y * GQ_BT + threadIdx.x) >> 6,
+                         (gridDim.y * GQ_BT) >> 6, s_buf + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void curvature_batch_kernel(const GridJob* __restrict__ jobs,
+                                                              const int2* __restrict__ bmap, int k) {
+  const int2 cb = bmap[blockIdx.x];
+  const GridJob& J = jobs[cb.x];
+  if (J.a_out) curvature_point(J.x, J.y, J.z, J.n, k, J.nbr, J.a_out, cb.y * 256 + threadIdx.x);
+}
+
+size_t grid_knn_batch_workspace(const int* n, int n_clouds, int k) {
+  size_t b = 0;
+  int64_t blocks = 0;
+  for (int c = 0; c < n_clouds; ++c) {
+    b += grid_knn_workspace(n[c], k);
+    blocks += (n[c] + 255) / 256;
+  }
+  b += ((sizeof(GridJob) * (size_t)n_clouds + 255) & ~size_t(255)) + ((sizeof(int2) * (size_t)blocks + 255) & ~size_t(255));
+  return b;
+}
+
+hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, const float* const* z, const int* n,
+                                 float* const* a_out, int32_t* const* idx_out, int n_clouds, int k, void* ws,
+                                 hipStream_t st) {
+  if (n_clouds < 1) return hipSuccess;
+  std::vector<GridJob> jobs(n_clouds);
+  std::vector<int2> bmap;
+  char* p = (char*)ws;
+  for (int c = 0; c < n_clouds; ++c) {
+    const GridBufs B = carve_grid(p, n[c], k);
+    p += grid_knn_workspace(n[c], k);
+    int32_t* lists = (idx_out && idx_out[c]) ? idx_out[c] : B.nbr;
+    jobs[c] = GridJob{x[c], y[c], z[c], a_out ? a_out[c] : nullptr, n[c], grid_max_cells(n[c]), B.gi, B.cell_of,
+                      B.counts, B.cursor, B.starts, B.spts, lists, B.far};
+    for (int b = 0; b < (n[c] + 255) / 256; ++b) bmap.push_back(make_int2(c, b));
+  }
+  GridJob* d_jobs = (GridJob*)p;
+  p += (sizeof(GridJob) * (size_t)n_clouds + 255) & ~size_t(255);
+  int2* d_bmap = (int2*)p;
+  hipError_t e = hipMemcpyAsync(d_jobs, jobs.data(), sizeof(GridJob) * jobs.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(d_bmap, bmap.data(), sizeof(int2) * bmap.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  // the copies read host vectors that go out of scope below
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  const dim3 gc((unsigned)n_clouds), gcs((unsigned)n_clouds, 16), gb((unsigned)bmap.size());
+  hipLaunchKernelGGL(grid_setup_batch_kernel, gc, dim3(1024), 0, st, d_jobs);
+  hipLaunchKernelGGL(grid_clear_batch_kernel, gcs, dim3(1024), 0, st, d_jobs, 0);
+  hipLaunchKernelGGL(grid_count_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
+  hipLaunchKernelGGL(grid_refine_batch_kernel, gc, dim3(1024), 0, st, d_jobs);
+  hipLaunchKernelGGL(grid_clear_batch_kernel, gcs, dim3(1024), 0, st, d_jobs, 1);
+  hipLaunchKernelGGL(grid_count_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
+  hipLaunchKernelGGL(grid_scan_batch_kernel, gc, dim3(1024), 0, st, d_jobs);
+  hipLaunchKernelGGL(grid_scatter_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
+  const dim3 gf((unsigned)n_clouds, 16);
+  if (k <= 8) {
+    hipLaunchKernelGGL(grid_knn_batch_kernel<8>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
+    hipLaunchKernelGGL(grid_knn_far_batch_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+  } else if (k <= 16) {
+    hipLaunchKernelGGL(grid_knn_batch_kernel<16>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
+    hipLaunchKernelGGL(grid_knn_far_batch_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+  } else if (k <= 24) {
+    hipLaunchKernelGGL(grid_knn_batch_kernel<24>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
+    hipLaunchKernelGGL(grid_knn_far_batch_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+  } else {
+    hipLaunchKernelGGL(grid_knn_batch_kernel<32>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
+    hipLaunchKernelGGL(grid_knn_far_batch_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+  }
+  hipLaunchKernelGGL(curvature_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap, k);
+  return hipGetLastError();
 }
 
 hipError_t launch_grid_nn(const float* x, const float* y, const float* z, int n, const float* qx, const float* qy,

@@ -150,6 +150,16 @@ hipError_t launch_identity_pose(double* pose, hipStream_t st);
 hipError_t launch_fill_i(int* p, int n, hipStream_t st);
 int grid_max_cells(int n);
 size_t grid_knn_workspace(int n, int k);
+// The grid search (launch_grid_knn) for many clouds at once: cloud c has
+// n[c] points at x[c], y[c], z[c] and receives its curvatures in a_out[c]
+// (a_out nullable) and, when idx_out and idx_out[c] are given, its
+// neighbour lists there.  One launch per phase for all clouds; neighbour
+// lists and curvatures equal those of launch_grid_knn on each cloud.
+// Synchronises the stream once (the job table is copied from host memory).
+size_t grid_knn_batch_workspace(const int* n, int n_clouds, int k);
+hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, const float* const* z, const int* n,
+                                 float* const* a_out, int32_t* const* idx_out, int n_clouds, int k, void* ws,
+                                 hipStream_t st);
 hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n, int k, float* a_out,
                            int32_t* idx_out, void* ws, hipStream_t st);
 // Nearest point of the cloud (x, y, z, n) to each query among those with
@@ -185,6 +195,13 @@ struct VForceArgs {
   double* fpart;        // [n_chunks][M][3] (WF only)
   double* spart = nullptr;  // with WU: [n_chunks][M][5] pair sums instead of forces and wrench
 };
+// Far template rows (standardised descriptor more than 8 spreads from the
+// mean), listed in increasing order into far_idx[0..n), n in far_idx[M]
+// (far_idx holds M + 1 ints); and their exact evaluation after the
+// contraction, one wrench slot each from slot0.
+hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, int* far_idx, hipStream_t st);
+hipError_t launch_vfar(const VForceArgs& A, const float* aX, const float* wX, const float* aY, int D,
+                       const double* vd, const int* far_idx, int n_far, int slot0, bool wu, bool wf, hipStream_t st);
 int vforce_K(int D);
 // Halves per split-f16 row: the contraction [h, h, l] . [h, l, h] of length
 // 3 (D + 2), padded to whole 16x16x32 instructions.

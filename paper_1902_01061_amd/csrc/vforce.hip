@@ -25,6 +25,14 @@
 // needs, per template point, sum_j c, sum_j c x_j (and sum_j c |x_j|^2 for
 // the energy) over the reference, accumulated in FP32 by the vector ALU.
 //
+// Far rows: the products lose accuracy as |c| grows (each entry carries a
+// rounding of about 2^-24 of log2(e) |c|^2 in FP32, 2^-22 in split f16, and
+// the exponent of a pair is their difference), so a template row whose
+// standardised descriptor lies more than VF_FAR spreads from the mean is
+// left out of the contraction (its exponent is set to the padding value)
+// and evaluated by vfar_kernel instead: exact differences a_i - a_j in FP64
+// for each pair, FP64 sums, the same epilogue and its own wrench slot.
+//
 // Work decomposition: a block of 256 threads (4 waves) owns 256 template
 // points; wave w holds 4 row tiles of 16 points, their At rows resident in
 // registers for the whole chunk.  Reference chunks of at most 2048 points
@@ -55,6 +63,19 @@ constexpr int VF_ROWS = 64 * VF_TI;  // template points per block
 static_assert(VF_TI == 1 || VF_TI == 2 || VF_TI == 4, "row tiles per wave");
 constexpr int VF_TJ = 64;    // reference points per LDS stage
 constexpr double LOG2E = 1.4426950408889634;
+constexpr double VF_FAR2 = 64.0;  // |c|^2 beyond which a template row is a far row (8 spreads)
+
+// |c_r|^2 = |a_r - abar|^2 / sigma^2 of descriptor row r, in FP64 (the same
+// expression decides far rows in vfar_list_kernel and vpack_kernel).
+__device__ inline double std_norm2(const float* __restrict__ a, int64_t r, int D, const double* __restrict__ vd) {
+  const double isig = 1.0 / vd[32];
+  double n2 = 0.0;
+  for (int c = 0; c < D; ++c) {
+    const double e = ((double)a[r * D + c] - vd[c]) * isig;
+    n2 += e * e;
+  }
+  return n2;
+}
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -184,16 +205,22 @@ __global__ __launch_bounds__(256) void vpack_kernel(const float* __restrict__ X,
   if (r < Mpad) {
     void* a = reinterpret_cast<char*>(At) + (size_t)r * rb;
     for (size_t w = 0; w < rb / 4; ++w) reinterpret_cast<uint32_t*>(a)[w] = 0u;
-    if (r < M) {
-      double n2 = 0.0;
-      for (int c = 0; c < D; ++c) {
-        const double e = ((double)aY[(int64_t)r * D + c] - vd[c]) * isig;
-        put_entry(a, c, 2.0 * LOG2E * e, half, E, true);
-        n2 += e * e;
+    if (r < M && std_norm2(aY, r, D, vd) > VF_FAR2) {
+      // far row (vfar_kernel): every pair exponent is the padding value
+      put_entry(a, D, pad_exp, half, E, true);
+      put_entry(a, D + 1, 0.0, half, E, true);
+    } else {
+      if (r < M) {
+        double n2 = 0.0;
+        for (int c = 0; c < D; ++c) {
+          const double e = ((double)aY[(int64_t)r * D + c] - vd[c]) * isig;
+          put_entry(a, c, 2.0 * LOG2E * e, half, E, true);
+          n2 += e * e;
+        }
+        put_entry(a, D, -LOG2E * n2, half, E, true);
       }
-      put_entry(a, D, -LOG2E * n2, half, E, true);
+      put_entry(a, D + 1, 1.0, half, E, true);
     }
-    put_entry(a, D + 1, 1.0, half, E, true);
   }
 }
 
@@ -413,6 +440,133 @@ done:
   }
 }
 
+// The far rows in increasing order: far_idx[0..n) and n in far_idx[M].
+// One block; thread t scans a contiguous range of rows, so that an exclusive
+// scan of the per-thread counts places every index deterministically.
+__global__ __launch_bounds__(1024) void vfar_list_kernel(const float* __restrict__ aY, int M, int D,
+                                                         const double* __restrict__ vd, int* __restrict__ far_idx) {
+  __shared__ int cnt[1024];
+  const int per = (M + 1023) / 1024;
+  const int r0 = min(M, (int)threadIdx.x * per), r1 = min(M, r0 + per);
+  int c = 0;
+  for (int r = r0; r < r1; ++r) c += std_norm2(aY, r, D, vd) > VF_FAR2;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const int v = cnt[t];
+      cnt[t] = acc;
+      acc += v;
+    }
+    far_idx[M] = acc;
+  }
+  __syncthreads();
+  int o = cnt[threadIdx.x];
+  for (int r = r0; r < r1; ++r)
+    if (std_norm2(aY, r, D, vd) > VF_FAR2) far_idx[o++] = r;
+}
+
+// One block per far row k (template point far_idx[k]): the pair weights
+// c_j = w_j exp(-|a_i - a_j|^2 / sigma^2) from exact FP64 differences, the
+// moment sums in FP64, then the epilogue of vforce_kernel; the wrench
+// partial goes to slot slot0 + k, the per-point force (WF) and the pair sums
+// (WU with spart) to chunk 0 (vforce_kernel wrote zeros for this row in
+// every chunk).
+template <bool WU, bool WF>
+__global__ __launch_bounds__(256) void vfar_kernel(VForceArgs A, const float* __restrict__ aX,
+                                                   const float* __restrict__ wX, const float* __restrict__ aY, int D,
+                                                   const double* __restrict__ vd, const int* __restrict__ far_idx,
+                                                   int slot0) {
+  __shared__ double s_red[4 * 13];
+  const int k = blockIdx.x;
+  const int ip = far_idx[k];
+  const double kap = vd[33];  // log2(e) / sigma^2
+  double ai[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) ai[c] = c < D ? (double)aY[(int64_t)ip * D + c] : 0.0;
+  double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < A.N; j += 256) {
+    double d2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 32; ++c)
+      if (c < D) {
+        const double d = ai[c] - (double)aX[(int64_t)j * D + c];
+        d2 += d * d;
+      }
+    const double lw = wX ? log2((double)wX[j]) : 0.0;
+    const double cj = exp2(lw - kap * d2);
+    const float4 X = A.ref4[j];
+    sums[0] += cj;
+    sums[1] += cj * (double)X.x;
+    sums[2] += cj * (double)X.y;
+    sums[3] += cj * (double)X.z;
+    sums[4] += cj * (double)X.w;
+  }
+  block_sum<5, 256>(sums, s_red);
+  double wr[13];
+#pragma unroll
+  for (int e = 0; e < 13; ++e) wr[e] = 0.0;
+  if (threadIdx.x == 0) {
+    const Derived& D_ = *A.dv;
+    bool sums_only = false;
+    if constexpr (WU) {
+      if (A.spart) {
+        double* o = A.spart + (int64_t)ip * 5;  // chunk 0
+#pragma unroll
+        for (int q = 0; q < 5; ++q) o[q] = sums[q];
+        sums_only = true;
+      }
+    }
+    if (!sums_only) {
+      double sR[9], cv[3];
+      const double s = A.pose[0];
+#pragma unroll
+      for (int e = 0; e < 9; ++e) sR[e] = s * A.pose[1 + e];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        cv[r] = sR[3 * r] * D_.ybar0[0] + sR[3 * r + 1] * D_.ybar0[1] + sR[3 * r + 2] * D_.ybar0[2] +
+                A.pose[10 + r] - D_.xbar[r];
+      const double G = A.G > 0 ? A.G : G_of(D_, A.t);
+      const double coef = -(G / D_.Z);
+      const double ucoef = 0.5 * (G / D_.Z);
+      const double ex = (double)A.y0x[ip] - D_.ybar0[0], ey = (double)A.y0y[ip] - D_.ybar0[1],
+                   ez = (double)A.y0z[ip] - D_.ybar0[2];
+      const double px = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);
+      const double py = (float)(sR[3] * ex + sR[4] * ey + sR[5] * ez + cv[1]);
+      const double pz = (float)(sR[6] * ex + sR[7] * ey + sR[8] * ez + cv[2]);
+      const double tx = px * sums[0] - sums[1], ty = py * sums[0] - sums[2], tz = pz * sums[0] - sums[3];
+      const double mi = A.mY ? (double)A.mY[ip] : 1.0;
+      const double fx = coef * tx, fy = coef * ty, fz = coef * tz;
+      const double cx = px - cv[0], cy = py - cv[1], cz = pz - cv[2];
+      wr[WR_F + 0] = mi * fx;
+      wr[WR_F + 1] = mi * fy;
+      wr[WR_F + 2] = mi * fz;
+      wr[WR_K + 0] = fx * cx;
+      wr[WR_K + 1] = fx * cy;
+      wr[WR_K + 2] = fx * cz;
+      wr[WR_K + 3] = fy * cx;
+      wr[WR_K + 4] = fy * cy;
+      wr[WR_K + 5] = fy * cz;
+      wr[WR_K + 6] = fz * cx;
+      wr[WR_K + 7] = fz * cy;
+      wr[WR_K + 8] = fz * cz;
+      if constexpr (WU)
+        wr[WR_U] = ucoef * ((px * px + py * py + pz * pz + D_.eps2) * sums[0] -
+                            2.0 * (px * sums[1] + py * sums[2] + pz * sums[3]) + sums[4]);
+      if constexpr (WF) {
+        double* fp = A.fpart + (int64_t)ip * 3;  // chunk 0
+        fp[0] = fx;
+        fp[1] = fy;
+        fp[2] = fz;
+      }
+    }
+    double* o = A.wpart + (int64_t)(slot0 + k) * WR_STRIDE;
+#pragma unroll
+    for (int e = 0; e < 13; ++e) o[e] = wr[e];
+  }
+}
+
 template <int VK, bool H>
 hipError_t launch_vk(const VForceArgs& A, bool wu, bool wf, hipStream_t st) {
   const int n_iblk = (A.M + VF_ROWS - 1) / VF_ROWS;
@@ -481,6 +635,26 @@ hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st) 
     case 8: return launch_vk<8, false>(A, wu, wf, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, int* far_idx, hipStream_t st) {
+  hipLaunchKernelGGL(vfar_list_kernel, dim3(1), dim3(1024), 0, st, aY, M, D, vd, far_idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_vfar(const VForceArgs& A, const float* aX, const float* wX, const float* aY, int D,
+                       const double* vd, const int* far_idx, int n_far, int slot0, bool wu, bool wf, hipStream_t st) {
+  if (n_far <= 0) return hipSuccess;
+  const dim3 grid((unsigned)n_far), block(256);
+  if (wu && wf)
+    hipLaunchKernelGGL((vfar_kernel<true, true>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+  else if (wu)
+    hipLaunchKernelGGL((vfar_kernel<true, false>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+  else if (wf)
+    hipLaunchKernelGGL((vfar_kernel<false, true>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+  else
+    hipLaunchKernelGGL((vfar_kernel<false, false>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+  return hipGetLastError();
 }
 
 // f16 form possible: every augmented entry below 30000 in magnitude (the

@@ -82,3 +82,86 @@ def test_multistart_matches_single_starts_and_picks_lowest_energy(sg, ctx):
         assert _prmse(_pose(sg, torch.as_tensor(poses[s])), _pose(sg, single), pr.tmpl) <= 1e-5 * O.diameter(pr.ref)
     assert best == int(np.argmin(energy))
     assert np.isfinite(energy).all()
+
+
+def test_batch_at_bench_size_matches_oracle(sg, ctx):
+    """The 256-registration batch of the bench (2 000 to 40 000 points, 100
+    iterations): the smallest, median and largest registration's final pose
+    against the oracle (the p = 1 iteration with the sums over the reference
+    formed once, register_p1, itself pinned to register()), and its final
+    energy."""
+    from synth import config4 as c4
+
+    pairs = c4()
+    E = 100
+    prm = sg.Params(p=1.0, k=16, E=E)
+    tms = [sg.Cloud(p.tmpl) for p in pairs]
+    rfs = [sg.Cloud(p.ref) for p in pairs]
+    poses, energy, _ = ctx.register_batch(tms, rfs, prm)
+    poses, energy = poses.cpu().numpy(), energy.cpu().numpy()
+    order = np.argsort([p.N for p in pairs], kind="stable")
+    for r in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        pr = pairs[r]
+        S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=1.0, k=16, E=E))
+        po, _, hist, _ = O.register_p1(pr.tmpl, S, keep=True)
+        err = _prmse(_pose(sg, torch.as_tensor(poses[r])), po, pr.tmpl) / O.diameter(pr.ref)
+        print(f"batch member {r} ({pr.M} x {pr.N}): pose parity {err:.2e} D, energy {energy[r]:.6e} vs "
+              f"{hist[-1].U:.6e}", flush=True)
+        assert err <= 1e-4
+        assert energy[r] == pytest.approx(hist[-1].U, rel=1e-4)
+
+
+def test_multistart_at_bench_size_matches_oracle(sg, ctx):
+    """The 32-start sweep of the bench (22 000 x 20 000, 100 iterations): two
+    starts' final poses and energies (the selection criterion) against the
+    oracle, which forms the pose-independent sums once for both."""
+    from synth import config4_multistart
+
+    pr, R0 = config4_multistart()
+    E = 100
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    poses, energy, best = ctx.multistart(tm, rf, sg.Params(p=1.0, k=16, E=E), R0)
+    poses, energy = poses.cpu().numpy(), energy.cpu().numpy()
+    S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=1.0, k=16, E=E))
+    ybar = pr.tmpl.astype(np.float64).mean(axis=0)
+    sums = None
+    for s in sorted({best, (best + 16) % len(R0)}):
+        p0 = O.Pose(1.0, R0[s], ybar - R0[s] @ ybar)
+        po, _, hist, sums = O.register_p1(pr.tmpl, S, pose0=p0, keep=True, sums=sums)
+        err = _prmse(_pose(sg, torch.as_tensor(poses[s])), po, pr.tmpl) / O.diameter(pr.ref)
+        print(f"start {s}: pose parity {err:.2e} D, energy {energy[s]:.6e} vs {hist[-1].U:.6e}", flush=True)
+        assert err <= 1e-4
+        assert energy[s] == pytest.approx(hist[-1].U, rel=1e-4)
+
+
+def test_batch_descriptors_match_oracle_and_single_clouds(sg, ctx):
+    """The batch's descriptors come from one grid search over all its clouds
+    (sgr_descriptors_batch).  On all 512 clouds of the bench's batch: the
+    neighbour lists of the smallest, median and largest registration's two
+    clouds bit-exact against the oracle on 300 sampled rows each, their
+    curvatures to float32 rounding; every cloud's lists and curvatures equal
+    the one-cloud grid search's (sgr_knn / sgr_descriptors), bit for bit, on
+    a spread of 12 clouds."""
+    from synth import config4 as c4
+
+    pairs = c4()
+    clouds = []
+    for p in pairs:
+        clouds += [p.ref, p.tmpl]
+    cls = [sg.Cloud(P) for P in clouds]
+    a, idx = ctx.descriptors_batch(cls, 16, want_idx=True)
+    torch.cuda.synchronize()
+    order = np.argsort([p.N for p in pairs], kind="stable")
+    rng = np.random.default_rng(11)
+    for r in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        for c in (2 * r, 2 * r + 1):
+            P = clouds[c]
+            q = rng.choice(len(P), 300, replace=False)
+            ref_idx = O.knn_c(P, 16, q)
+            assert np.array_equal(idx[c].cpu().numpy()[q], ref_idx), c
+            np.testing.assert_allclose(a[c].cpu().numpy()[q], O.surface_variation(P, ref_idx).astype(np.float32),
+                                       rtol=2e-6, atol=1e-9)
+    for c in np.linspace(0, len(clouds) - 1, 12).astype(int):
+        i1 = ctx.knn(cls[c], 16)
+        a1, _ = ctx.descriptors(cls[c], 16)
+        assert torch.equal(i1, idx[c]) and torch.equal(a1, a[c]), c

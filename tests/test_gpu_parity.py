@@ -237,6 +237,29 @@ def test_config2_force_along_gpu_trajectory(sg, ctx, sigma_kind):
         plan.close()
 
 
+@pytest.mark.parametrize("sigma_kind", ["default", "wide"])
+def test_register_config2_final_pose_matches_oracle(sg, ctx, sigma_kind):
+    """The bench's scan registration (32 400 x 36 000, k = 24, 300
+    iterations) end to end on the GPU, against the oracle's registration
+    from the same curvatures (its p = 1 iteration with the sums over the
+    reference formed once, register_p1, pinned to register()): final pose
+    parity <= 1e-4 of the diameter, at the default sigma and at the wide one
+    under which nearly every row carries a force."""
+    pr, aX, aY, prm, S = _config2_setup(sigma_kind)
+    po, _, _, _ = O.register_p1(pr.tmpl, S)
+    pose, _ = ctx.register(sg.Cloud(pr.tmpl), sg.Cloud(pr.ref), sg.Params(p=1.0, k=24, E=300, sigma=prm.sigma))
+    s, R, t = sg.pose_to_srt(pose)
+    pg = O.Pose(s, R, t)
+    D = O.diameter(pr.ref)
+    d = pg.apply(pr.tmpl) - po.apply(pr.tmpl)
+    err = np.sqrt(np.mean(np.sum(d * d, axis=1))) / D
+    q_gpu = O.pose_rmse(pg, pr.tmpl, pr.gt_s, pr.gt_R, pr.gt_t, pr.corr) / D
+    q_id = O.pose_rmse(O.Pose.identity(), pr.tmpl, pr.gt_s, pr.gt_R, pr.gt_t, pr.corr) / D
+    print(f"config 2 registration ({sigma_kind} sigma): parity {err:.2e} D; pose error {q_gpu:.4f} D "
+          f"(identity {q_id:.4f} D)", flush=True)
+    assert err <= 1e-4
+
+
 # ------------------------------------------------------------ registration
 def _register_both(sg, ctx, pr, prm):
     S = O.make_setup(pr.ref, pr.tmpl, prm)

@@ -130,6 +130,12 @@ def _vec_case(D, seed, kind):
             sd = np.sqrt(np.mean(np.sum((aX - aX.mean(0)) ** 2, axis=1)))
             aY[20:23] = aX.mean(0) + 500.0 * sd / np.sqrt(D)
             aX[:2] = aY[20]
+        elif kind == "far":                          # far rows within the f16 range, with close partners
+            sd = np.sqrt(np.mean(np.sum((aX - aX.mean(0)) ** 2, axis=1)))
+            u = rng.normal(size=(10, D))
+            u /= np.linalg.norm(u, axis=1, keepdims=True)
+            aY[20:30] = aX.mean(0) + 20.0 * sd * u
+            aX[:10] = aY[20:30] + 0.1 * sd * rng.normal(size=(10, D))
     return pr, aX, aY
 
 
@@ -165,11 +171,15 @@ def _errors(so, wr, f, Y, mY=None):
     (16, "uniform", False, 0.0, 0), (30, "clustered", True, 0.02, 0), (5, "uniform", True, 0.0, 0),
     (1, "clustered", False, 0.0, 0), (14, "clustered", False, 0.0, 0),
     (16, "uniform", False, 0.0, 4), (30, "clustered", True, 0.02, 4), (5, "uniform", True, 0.0, 4),
-    (9, "extreme", True, 0.0, 0), (19, "uniform", True, 0.0, 0), (20, "clustered", False, 0.01, 0)])
+    (9, "extreme", True, 0.0, 0), (19, "uniform", True, 0.0, 0), (20, "clustered", False, 0.01, 0),
+    (5, "far", True, 0.0, 0), (5, "far", False, 0.0, 4)])
 def test_step_vec_matches_oracle(sg, ctx, D, kind, masses, eps, flags):
     """flags 0: split-f16 products (the default), except for "extreme", whose
     descriptors lie 500 spreads from the mean and select FP32 products by
-    themselves; flags 4: FP32 products.  The split form takes
+    themselves; flags 4: FP32 products.  Template rows more than 8 spreads
+    from the mean ("extreme": 3 rows at 500 spreads; "far": 10 rows at 20
+    spreads, each with a close reference partner) are evaluated exactly
+    outside the contraction, so every row meets the per-point bar.  The split form takes
     ceil(3 (D + 2) / 32) 16x16x32 instructions: one for D = 1, 5; two for
     D = 14, 16 and 19 (63 of 64 slots); three for D = 20 and 30."""
     pr, aX, aY = _vec_case(D, 40 + D, kind)

@@ -857,3 +857,35 @@ def test_force_scale_c_matches_numpy():
         f, U, sc = O.forces_c(pr.tmpl, S, 3.0, rows=rows, want_scale=True)
         np.testing.assert_allclose(sc, O.force_scale(pr.tmpl, S, 3.0, rows=rows), rtol=1e-12)
         np.testing.assert_allclose(f, O.forces(pr.tmpl, S, 3.0)[0][rows], rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------- p = 1: sums over the reference first
+@pytest.mark.parametrize("g_mode,masses,eps", [(0, False, 0.0), (1, True, 0.05)])
+def test_forces_from_pair_sums_equal_eq5(g_mode, masses, eps):
+    """At p = 1, f_i = -(G/Z) sum_j c_ij (y_i - x_j) = -(G/Z)(y_i S0_i - Sx_i)
+    with c_ij independent of the pose: forces_from_sums must equal forces()
+    (eq. 5 summed pair by pair) at arbitrary poses, energy included."""
+    pr = random_pair(70, 110, seed=31)
+    rng = np.random.default_rng(32)
+    wX = rng.uniform(0.5, 2.0, 110) if masses else None
+    S = _setup(pr.ref.astype(np.float64), rng.uniform(0.01, 0.3, 110), rng.uniform(0.01, 0.3, 70), p=1.0,
+               g_mode=g_mode, sigma=0.08, eps=eps, wX=wX)
+    sums = O.pair_sums_c(S)
+    for pose in (O.Pose.identity(), O.Pose(0.8, rot_axis_angle([1, 1, 0], 70.0), np.array([0.3, -1.0, 2.0]))):
+        Y = pose.apply(pr.tmpl)
+        f1, U1 = O.forces(Y, S, 9.0)
+        f2, U2 = O.forces_from_sums(Y, S, 9.0, sums)
+        np.testing.assert_allclose(f2, f1, rtol=1e-11, atol=1e-12 * np.abs(f1).max())
+        assert U2 == pytest.approx(U1, rel=1e-11)
+
+
+def test_register_p1_equals_register():
+    """The registration with the sums formed once follows register() (eq.
+    5 summed pair by pair at every iterate) to rounding."""
+    pr = config1(n=400)
+    S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=1.0, k=16, E=40))
+    po, Y1, _ = O.register(pr.tmpl, S)
+    pq, Y2, _, _ = O.register_p1(pr.tmpl, S)
+    assert np.sqrt(np.mean(np.sum((Y1 - Y2) ** 2, axis=1))) <= 1e-12 * O.diameter(pr.ref)
+    with pytest.raises(ValueError):
+        O.pair_sums_c(O.make_setup(pr.ref, pr.tmpl, O.Params(p=2.0, k=16, E=5), aX=S.aX, aY=S.aY))
