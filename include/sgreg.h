@@ -169,6 +169,28 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
              int t, const sgr_pose* in, sgr_pose* out, double* wrench_out, float* f_out,
              sgr_stream_t stream);
 
+/* sgr_step for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and kernels as sgr_step, bit for bit;
+ * the step's intermediate buffers (set-up constants, packed clouds, visiting
+ * order and its sort temporaries, wrench partials, per-chunk forces) come
+ * from a static 64 MiB device array per GPU (SGR_STATIC_SCRATCH_BYTES)
+ * instead of the context workspace, and nothing is allocated or freed.
+ * The array is held from the library's loading on that GPU until the process
+ * ends; its device address is taken by sgr_create.  Limit: a pair needs
+ * roughly 20 N + 60 M bytes plus, with f_out, 24 M bytes per reference chunk;
+ * SGR_EINVAL with the byte count when a call needs more than the array (the
+ * depth-frame scene, 250 000 x 307 200, fits).  No part of the array needs
+ * to start at any value.  Every call on one GPU uses the same array: calls
+ * that overlap in time on one GPU (from several threads, or on several
+ * streams without ordering) race and give wrong results; calls ordered on
+ * one stream are safe. */
+#define SGR_STATIC_SCRATCH_BYTES (64u << 20)
+int sgr_step_static(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref,
+                    const float* a_r, const double* mom_t, const double* mom_r, const sgr_params* prm,
+                    int t, const sgr_pose* in, sgr_pose* out, double* wrench_out, float* f_out,
+                    sgr_stream_t stream);
+
 /* "register(template, reference, params) -> pose" (Sec. I's problem: the
  * translation, rotation and scale that align the template to the
  * reference): curvature descriptors of both clouds (Sec. III-A), then E

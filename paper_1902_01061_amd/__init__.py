@@ -192,14 +192,19 @@ class Context:
         return idx
 
     def step(self, tmpl: Cloud, a_t, ref: Cloud, a_r, mom_t, mom_r, params: Params, t: int, pose_in,
-             pose_out=None, want_wrench=True, want_f=False):
+             pose_out=None, want_wrench=True, want_f=False, static_scratch=False, wrench=None, f=None):
+        """One iteration.  static_scratch: through sgr_step_static (no device
+        allocation; the caller may also pass the output buffers)."""
         pose_out = torch.empty(13, dtype=torch.float64, device=self.device) if pose_out is None else pose_out
-        wrench = torch.empty(13, dtype=torch.float64, device=self.device) if want_wrench else None
-        f = torch.empty((tmpl.n, 3), dtype=torch.float32, device=self.device) if want_f else None
+        if wrench is None and want_wrench:
+            wrench = torch.empty(13, dtype=torch.float64, device=self.device)
+        if f is None and want_f:
+            f = torch.empty((tmpl.n, 3), dtype=torch.float32, device=self.device)
         ct, cr, pr = tmpl.c(), ref.c(), params.c()
-        check(lib().sgr_step(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_t),
-                             _ptr(mom_r), ctypes.byref(pr), int(t), _ptr(pose_in), _ptr(pose_out), _ptr(wrench),
-                             _ptr(f), _stream(self.device)))
+        fn = lib().sgr_step_static if static_scratch else lib().sgr_step
+        check(fn(self._h, ctypes.byref(ct), _ptr(a_t), ctypes.byref(cr), _ptr(a_r), _ptr(mom_t), _ptr(mom_r),
+                 ctypes.byref(pr), int(t), _ptr(pose_in), _ptr(pose_out), _ptr(wrench), _ptr(f),
+                 _stream(self.device)))
         return pose_out, wrench, f
 
     def register(self, tmpl: Cloud, ref: Cloud, params: Params, pose=None, stats=False):

@@ -54,6 +54,7 @@ SIGNATURES = {
     "sgr_knn": [P, CP, I, P, P],
     "sgr_descriptors_batch": [P, I, CP, I, P, P, P],
     "sgr_step": [P, CP, P, CP, P, P, P, PP, I, P, P, P, P, P],
+    "sgr_step_static": [P, CP, P, CP, P, P, P, PP, I, P, P, P, P, P],
     "sgr_register": [P, CP, CP, PP, P, P, P],
     "sgr_residual": [P, CP, CP, P, P, P, P],
     "sgr_plan_create": [P, CP, P, CP, P, P, P, PP, ctypes.POINTER(P), P],

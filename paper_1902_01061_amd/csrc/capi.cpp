@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -823,6 +824,39 @@ int unrolled_force(const sgr_cloud* tmpl, const float* a_t, const Unrolled& U, i
 
 extern "C" {
 
+// ------------------------------------------------- allocation-free step
+// sgr_step_static carves its buffers from this array instead of the
+// context workspace.  Each device holds its own copy (at its own address)
+// from the loading of the library's code on it until the process ends.  The
+// name is a host-side stand-in in host code: its device address is taken
+// once per device with hipGetSymbolAddress (in sgr_create) and only that
+// address is handed to kernels.
+constexpr size_t SGR_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) char scratch[SGR_SCRATCH_BYTES];
+constexpr int SGR_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[SGR_MAX_DEVICES];
+
+// Called with `device` current.
+static int scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= SGR_MAX_DEVICES) return fail(SGR_EINVAL, "device index beyond 63");
+  if (g_scratch_ptr[device]) return SGR_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(SGR_EHIP, std::string("device address of the static scratch: ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = static_cast<char*>(p);
+  return SGR_OK;
+}
+
+static char* scratch_of(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < SGR_MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
+}
+
 const char* sgr_last_error(void) { return g_err.c_str(); }
 
 int sgr_create(sgr_ctx** out, int device) {
@@ -845,6 +879,11 @@ int sgr_create(sgr_ctx** out, int device) {
     return fail(SGR_EHIP, "stream creation failed");
   }
   c->tiles.init(c->n_cu);
+  if (int e = scratch_init(device)) {
+    (void)hipStreamDestroy(c->cap);
+    delete c;
+    return e;
+  }
   *out = c;
   return SGR_OK;
 }
@@ -892,9 +931,12 @@ int sgr_knn(sgr_ctx* ctx, const sgr_cloud* c, int k, int32_t* idx_out, sgr_strea
   return SGR_OK;
 }
 
-int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
-             const double* mom_t, const double* mom_r, const sgr_params* prm, int t, const sgr_pose* in,
-             sgr_pose* out, double* wrench_out, float* f_out, sgr_stream_t stream) {
+// One iteration (sgr_step); the buffers come from the context workspace
+// (grown with hipMalloc on demand) or, with use_static, from the device's
+// static scratch, with no allocation at all.
+static int step_impl(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                     const double* mom_t, const double* mom_r, const sgr_params* prm, int t, const sgr_pose* in,
+                     sgr_pose* out, double* wrench_out, float* f_out, sgr_stream_t stream, bool use_static) {
   if (!ctx) return fail(SGR_EINVAL, "NULL ctx");
   if (int e = check_cloud(tmpl, "template")) return e;
   if (int e = check_cloud(ref, "reference")) return e;
@@ -918,8 +960,18 @@ int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cl
   cv.take<char>(sort_perm_workspace(M, 1));
   cv.take<float4>(M);
   cv.take<float2>(M);
-  if (int e = ensure_ws(ctx, cv.off)) return e;
-  Carve w{ctx->ws};
+  char* base = nullptr;
+  if (use_static) {
+    base = scratch_of(ctx->device);
+    if (!base) return fail(SGR_EHIP, "the static scratch of this device has no device address");
+    if (cv.off > SGR_SCRATCH_BYTES)
+      return fail(SGR_EINVAL, "this step needs " + std::to_string(cv.off) + " bytes of scratch, more than the " +
+                                  std::to_string(SGR_SCRATCH_BYTES) + " bytes of the static scratch");
+  } else {
+    if (int e = ensure_ws(ctx, cv.off)) return e;
+    base = ctx->ws;
+  }
+  Carve w{base};
   Derived* dv = w.take<Derived>(1);
   float4* ref4 = w.take<float4>(pad_n(N));
   float* lw = w.take<float>(pad_n(N));
@@ -970,6 +1022,18 @@ int sgr_descriptors_batch(sgr_ctx* ctx, int n_clouds, const sgr_cloud* clouds, i
   HIPCHK(launch_grid_knn_batch(cx.data(), cy.data(), cz.data(), cn.data(), a_out, idx_out, n_clouds, k, ctx->ws,
                                (hipStream_t)stream));
   return SGR_OK;
+}
+
+int sgr_step(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+             const double* mom_t, const double* mom_r, const sgr_params* prm, int t, const sgr_pose* in,
+             sgr_pose* out, double* wrench_out, float* f_out, sgr_stream_t stream) {
+  return step_impl(ctx, tmpl, a_t, ref, a_r, mom_t, mom_r, prm, t, in, out, wrench_out, f_out, stream, false);
+}
+
+int sgr_step_static(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, const float* a_r,
+                    const double* mom_t, const double* mom_r, const sgr_params* prm, int t, const sgr_pose* in,
+                    sgr_pose* out, double* wrench_out, float* f_out, sgr_stream_t stream) {
+  return step_impl(ctx, tmpl, a_t, ref, a_r, mom_t, mom_r, prm, t, in, out, wrench_out, f_out, stream, true);
 }
 
 int sgr_register(sgr_ctx* ctx, const sgr_cloud* tmpl, const sgr_cloud* ref, const sgr_params* prm, sgr_pose* inout,
