@@ -560,6 +560,15 @@ def extra_scan(sg, ctx, steps: int, kernel_reps: int):
     plan.close()
     out["force_kernel"] = {"ms_per_launch": k_ms, "pairs_per_s": pr.M * pr.N / (k_ms * 1e-3),
                            "tflops_13_per_pair": 13 * pr.M * pr.N / (k_ms * 1e-3) / 1e12}
+    # the r-form of the same kernel on this pair: the p = 2 law (20 flops per
+    # pair) and eq. 1's gravitational law (p = -2, eps = 0.05 L, g = 1)
+    L = float(np.sqrt(mom_r[9].item()))
+    for name, pp in (("force_kernel_p2", sg.Params(p=2.0, k=k, E=E)),
+                     ("force_kernel_gravitational_p-2", sg.Params(p=-2.0, g_mode=2, eps=0.05 * L, k=k, E=E))):
+        pl = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, pp)
+        ms = _kernel_ms(pl, forms["fp32"][1], E - 1, kernel_reps)
+        pl.close()
+        out[name] = {"ms_per_launch": ms, "pairs_per_s": pr.M * pr.N / (ms * 1e-3)}
     return out
 
 
@@ -599,6 +608,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the scan, batch, adjoint, mixed ... legs")
+    ap.add_argument("--legs", default="scene,scan,batch,adjoint,force_law,pyramid,vector",
+                    help="comma-separated extra legs to run (default: all)")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the force kernel launch shape instead of loading the committed tile table")
     ap.add_argument("--save-tiles", default="", help="write the tile table here after tuning")
@@ -709,24 +720,31 @@ def main() -> int:
         "roofline_rform": roof2,
     }
     out.update(_reference_errors(pr))
-    if not args.no_extras:
+    legs = set() if args.no_extras else set(args.legs.split(","))
+    if "scene" in legs:
         out["scene"] = extra_scene(sg, ctx, pr, dt / args.steps, pose)
         log(f"scene: mixed {out['scene']['mixed']['ms_per_registration']:.1f} ms, "
             f"pose-independent sums {out['scene']['pose_independent_sums']['ms_per_registration']:.1f} ms")
+    if "scan" in legs:
         out["scan"] = extra_scan(sg, ctx, args.steps, 20)
         log(f"scan: fp32 {out['scan']['fp32']['ms_per_registration']:.1f} ms, "
             f"{out['scan']['rows_with_force_at_t0']} rows with a force")
+    if "batch" in legs:
         out["batch"] = extra_batch(sg, ctx)
         log(f"batch: {out['batch']['ms_per_batch']:.1f} ms, pose-independent sums "
             f"{out['batch']['pose_independent_sums']['ms_per_batch']:.1f} ms")
+    if "adjoint" in legs:
         out["adjoint"] = extra_adjoint(sg, ctx)
         log(f"adjoint: fwd {out['adjoint']['fwd_ms']:.3f} ms, bwd {out['adjoint']['bwd_ms']:.3f} ms")
+    if "force_law" in legs:
         out["force_law"] = extra_force_law(sg, ctx, 300, 24)
         log(f"force law: workload pose error p=1 {out['force_law']['workload']['shape_p1']['pose_rmse_over_diameter']:.2e}"
             f", gravitational {out['force_law']['workload']['gravitational_p-2']['pose_rmse_over_diameter']:.2e}")
+    if "pyramid" in legs:
         out["pyramid"] = extra_pyramid(sg, ctx, 300, 24)
         log(f"pyramid: radius descriptors {out['pyramid']['radius_descriptors']['ms']:.3f} ms, registration "
             f"{out['pyramid']['pyramid']['ms_per_registration']:.1f} ms")
+    if "vector" in legs:
         out["vector"] = extra_vector(sg, ctx, 300, 24)
         log(f"vector descriptors: split f16 {out['vector']['split_f16']['ms_per_registration']:.1f} ms, "
             f"fp32 {out['vector']['fp32']['ms_per_registration']:.1f} ms, pose-independent sums "
