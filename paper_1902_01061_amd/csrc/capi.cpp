@@ -643,6 +643,8 @@ struct VecWs {
   bool half;  // split-f16 products (decided by setup_vec)
   int* far_idx;  // far template rows (M + 1 ints: the list, then its length)
   int n_far;     // number of far rows (read back by setup_vec)
+  double* far_ref;   // reference records of the far-row evaluation
+  double* far_part;  // its per-segment sums
   // flags bit 3: the template in its own order, the pair sums per chunk, reduced
   float4* tm4 = nullptr;
   float2* tmx = nullptr;
@@ -659,7 +661,7 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
   for (int pass = 0; pass < 2; ++pass) {
     Carve c{pass ? ctx->ws : nullptr};
     w.dv = c.take<Derived>(1);
-    w.vd = c.take<double>(35);
+    w.vd = c.take<double>(36);
     // rows of K floats (FP32 form) or vforce_half_K(D) halves (split f16)
     const size_t row_words = (size_t)std::max(w.K, vforce_half_K(D) / 2);
     w.At = c.take<float>((size_t)vforce_pad_rows(M) * row_words);
@@ -669,6 +671,8 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
     w.fpart = with_f ? c.take<double>((size_t)w.n_chunks * M * 3) : nullptr;
     w.mom = with_mom ? c.take<double>(20) : nullptr;
     w.far_idx = c.take<int>((size_t)M + 1);
+    w.far_ref = c.take<double>((size_t)N * vfar_stride(D));
+    w.far_part = c.take<double>(vfar_part_doubles(M));
     if (pinv) {
       w.tm4 = c.take<float4>(M);
       w.tmx = c.take<float2>(M);
@@ -689,7 +693,7 @@ int setup_vec(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, con
   const int M = (int)tmpl->n, N = (int)ref->n;
   HIPCHK(launch_prepare(nullptr, ref->m, N, nullptr, tmpl->m, M, mom_t, mom_r, prep_of(prm), w.dv, st));
   HIPCHK(launch_vprep(a_r, N, a_t, M, D, prm->sigma, w.dv, w.vd, st));
-  HIPCHK(launch_vfar_list(a_t, M, D, w.vd, w.far_idx, st));
+  HIPCHK(launch_vfar_list(a_t, M, D, w.vd, w.dv, w.far_idx, st));
   double cmax = 0.0;
   int n_far = 0;
   HIPCHK(hipMemcpyAsync(&cmax, w.vd + 34, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -700,17 +704,18 @@ int setup_vec(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, con
   if (w.half) w.K = vforce_half_K(D);
   HIPCHK(launch_vpack(ref->x, ref->y, ref->z, a_r, ref->m, N, a_t, M, D, w.half, w.dv, w.vd, w.Bt, w.ref4, w.At,
                       st));
+  if (n_far > 0) HIPCHK(launch_vfar_ref(a_r, ref->m, N, D, w.vd, w.ref4, w.far_ref, st));
   return SGR_OK;
 }
 
 // The vector-descriptor force of one iteration: the contraction kernel,
 // then the far rows; returns through `used` the wrench slots written.
-hipError_t run_vforce(const VForceArgs& A, const sgr_cloud* ref, const float* a_r, const float* a_t, int D,
-                      const VecWs& w, bool wu, bool wf, int* used, hipStream_t st) {
+hipError_t run_vforce(const VForceArgs& A, const float* a_t, int D, const VecWs& w, bool wu, bool wf, int* used,
+                      hipStream_t st) {
   hipError_t e = launch_vforce(A, wu, wf, st);
   if (e != hipSuccess) return e;
   if (used) *used = w.slots + w.n_far;
-  return launch_vfar(A, a_r, ref->m, a_t, D, w.vd, w.far_idx, w.n_far, w.slots, wu, wf, st);
+  return launch_vfar(A, a_t, D, w.vd, w.far_ref, w.far_idx, w.n_far, w.far_part, w.slots, wu, wf, st);
 }
 
 VForceArgs vargs(const sgr_cloud* tmpl, const sgr_cloud* ref, const VecWs& w, const double* pose, int t) {
@@ -1181,7 +1186,7 @@ int sgr_step_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   if (int e = carve_vec(ctx, M, (int)ref->n, D, f_out != nullptr, false, w)) return e;
   if (int e = setup_vec(tmpl, a_t, ref, a_r, D, mom_t, mom_r, prm, w, st)) return e;
   int used = w.slots;
-  HIPCHK(run_vforce(vargs(tmpl, ref, w, (const double*)in, t), ref, a_r, a_t, D, w, wrench_out != nullptr,
+  HIPCHK(run_vforce(vargs(tmpl, ref, w, (const double*)in, t), a_t, D, w, wrench_out != nullptr,
                     f_out != nullptr, &used, st));
   if (f_out) HIPCHK(launch_reduce_f(w.fpart, w.n_chunks, M, nullptr, f_out, st));
   HIPCHK(launch_update(w.wpart, used, (const double*)in, (double*)out, w.dv, t, 0.0, 1, wrench_out, nullptr, st));
@@ -1209,7 +1214,7 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
     // the pair sums once: one pass of the vector kernel writing them per chunk
     VForceArgs A = vargs(tmpl, ref, w, (const double*)inout, 0);
     A.spart = w.ps_part;
-    HIPCHK(run_vforce(A, ref, a_r, a_t, D, w, true, false, nullptr, st));
+    HIPCHK(run_vforce(A, a_t, D, w, true, false, nullptr, st));
     HIPCHK(launch_psum_reduce(w.ps_part, M, w.n_chunks, w.ps_S, st));
     HIPCHK(launch_pack_plain(tmpl->x, tmpl->y, tmpl->z, tmpl->m, M, w.tm4, w.tmx, st));
   }
@@ -1221,7 +1226,7 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
         HIPCHK(launch_pinv(w.tm4, w.tmx, w.ps_S, M, (const double*)inout, w.dv, t, wu, w.wpart, s));
         used = pinv_blocks(M);
       } else {
-        HIPCHK(run_vforce(vargs(tmpl, ref, w, (const double*)inout, t), ref, a_r, a_t, D, w, wu, false, &used, s));
+        HIPCHK(run_vforce(vargs(tmpl, ref, w, (const double*)inout, t), a_t, D, w, wu, false, &used, s));
       }
       HIPCHK(launch_update(w.wpart, used, (const double*)inout, (double*)inout, w.dv, t, 0.0, 1, nullptr,
                            stats ? stats + (size_t)t * STATS_STRIDE : nullptr, s));

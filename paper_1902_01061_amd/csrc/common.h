@@ -89,8 +89,11 @@ SGR_HDI void jacobi_pair(double (&ap)[3], double (&aq)[3], double (&vp)[3], doub
   const double g2 = ga * ga, ab = al * be;
   if (!(g2 > 1e-34 * ab)) return;
   if (g2 >= 1e-30 * ab) more = true;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  // tangent of the rotation angle, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2))
+  // with zeta = (be - al) / (2 ga), multiplied through by |2 ga| (one
+  // division fewer)
+  const double d = be - al, g = 2.0 * ga;
+  const double t = (d * g >= 0.0 ? fabs(g) : -fabs(g)) / (fabs(d) + sqrt(d * d + g * g));
   const double c = 1.0 / sqrt(1.0 + t * t);
   const double s = c * t;
   for (int r = 0; r < 3; ++r) {
@@ -166,8 +169,9 @@ SGR_HDI void svd3(const double A_in[9], double sv[3], double u[3][3], double v[3
   order_pair(n[0], n[1], a[0], a[1], vv[0], vv[1]);
   for (int k = 0; k < 3; ++k) {
     sv[k] = ldexp(n[k][0], ex);
+    const double inv = n[k][0] > 0 ? 1.0 / n[k][0] : 0.0;
     for (int r = 0; r < 3; ++r) {
-      u[k][r] = n[k][0] > 0 ? a[k][r] / n[k][0] : 0.0;
+      u[k][r] = a[k][r] * inv;
       v[k][r] = vv[k][r];
     }
   }

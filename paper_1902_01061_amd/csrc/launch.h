@@ -196,12 +196,21 @@ struct VForceArgs {
   double* spart = nullptr;  // with WU: [n_chunks][M][5] pair sums instead of forces and wrench
 };
 // Far template rows (standardised descriptor more than 8 spreads from the
-// mean), listed in increasing order into far_idx[0..n), n in far_idx[M]
-// (far_idx holds M + 1 ints); and their exact evaluation after the
-// contraction, one wrench slot each from slot0.
-hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, int* far_idx, hipStream_t st);
-hipError_t launch_vfar(const VForceArgs& A, const float* aX, const float* wX, const float* aY, int D,
-                       const double* vd, const int* far_idx, int n_far, int slot0, bool wu, bool wf, hipStream_t st);
+// mean, within reach of a reference descriptor), listed in increasing order
+// into far_idx[0..n), n in far_idx[M] (far_idx holds M + 1 ints).  Their
+// evaluation after the contraction reads reference records built once per
+// registration (launch_vfar_ref: N records of vfar_stride(D) doubles) and
+// leaves per-segment sums in part (vfar_part_doubles(M) doubles); one wrench
+// slot per far row from slot0.
+__host__ __device__ inline int vfar_db(int D) { return 8 * ((D + 7) / 8); }
+__host__ __device__ inline int vfar_stride(int D) { return vfar_db(D) + 6; }
+size_t vfar_part_doubles(int M);
+hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, const Derived* dv, int* far_idx,
+                            hipStream_t st);
+hipError_t launch_vfar_ref(const float* aX, const float* wX, int N, int D, const double* vd, const float4* ref4,
+                           double* refd, hipStream_t st);
+hipError_t launch_vfar(const VForceArgs& A, const float* aY, int D, const double* vd, const double* refd,
+                       const int* far_idx, int n_far, double* part, int slot0, bool wu, bool wf, hipStream_t st);
 int vforce_K(int D);
 // Halves per split-f16 row: the contraction [h, h, l] . [h, l, h] of length
 // 3 (D + 2), padded to whole 16x16x32 instructions.
@@ -210,8 +219,9 @@ int vforce_pad_rows(int M);
 int vforce_pad_refs(int N);
 int vforce_n_iblk(int M);
 int vforce_chunks(int M, int N, int n_cu);
-// vd: [35] doubles: reference mean (32), sigma, log2(e) / sigma^2, and the
-// largest |a - abar|^2 / sigma^2 over both clouds (for vforce_half_ok)
+// vd: [36] doubles: reference mean (32), sigma, log2(e) / sigma^2, the
+// largest |a - abar|^2 / sigma^2 over the reference and the template rows
+// that enter the contraction (for vforce_half_ok), and over the reference
 hipError_t launch_vprep(const float* aX, int64_t N, const float* aY, int64_t M, int D, double sigma, Derived* dv,
                         double* vd, hipStream_t st);
 bool vforce_half_ok(double cmax);

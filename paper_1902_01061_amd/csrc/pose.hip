@@ -18,16 +18,19 @@
 namespace sgr {
 
 // 512 threads: the single-thread update keeps its FP64 state in registers
-// (a 1024-thread block would cap it at 128 VGPRs and spill), and 32 loads in
-// flight per thread still read up to 2048 partial rows in one round.
+// (a 1024-thread block would cap it at 128 VGPRs and spill); its other inputs
+// are loaded before the partial rows are summed, with 16 loads in flight per
+// thread (up to 1024 rows per round).
 __global__ __launch_bounds__(512) void update_kernel(const double* __restrict__ wpart, int nblk,
                                                       const double* pose_in, double* pose_out,
                                                       Derived* __restrict__ dv, int t, double G_fixed, int do_update,
                                                       double* __restrict__ wrench_out, double* __restrict__ stats_row) {
   __shared__ double lds[512 / 4];
+  UpdateIn u;
+  if (threadIdx.x == 0) update_load(dv, pose_in, t, G_fixed, u);
   double W[13];
-  sum_partials<512, 32>(wpart, nblk, lds, W);
-  if (threadIdx.x == 0) pose_update(W, pose_in, pose_out, dv, t, G_fixed, do_update, wrench_out, stats_row);
+  sum_partials<512, 16>(wpart, nblk, lds, W);
+  if (threadIdx.x == 0) update_apply(W, u, pose_out, dv, do_update, wrench_out, stats_row);
 }
 
 // One block per registration of a batch; its items own the wrench slots
@@ -40,12 +43,13 @@ __global__ __launch_bounds__(256) void update_batch_kernel(const double* __restr
   __shared__ double lds[256 / 4];
   const int r = blockIdx.x;
   const RegDesc& g = regs[r];
+  double* pose = poses + 13 * (int64_t)r;
+  UpdateIn u;
+  if (threadIdx.x == 0) update_load(dvs + r, pose, t, 0.0, u);
   double W[13];
   sum_partials<256, 16>(wpart + (int64_t)g.wslot0 * WR_STRIDE, g.n_items, lds, W);
   if (threadIdx.x == 0) {
-    double* pose = poses + 13 * (int64_t)r;
-    pose_update(W, pose, pose, dvs + r, t, 0.0, do_update, nullptr,
-                stats ? stats + ((int64_t)r * E + t) * STATS_STRIDE : nullptr);
+    update_apply(W, u, pose, dvs + r, do_update, nullptr, stats ? stats + ((int64_t)r * E + t) * STATS_STRIDE : nullptr);
     if (energy_out) energy_out[r] = W[WR_U];
   }
 }

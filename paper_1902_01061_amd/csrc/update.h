@@ -67,29 +67,59 @@ __device__ inline void sum_partials(const double* __restrict__ wpart, int n, dou
 // and pose_out may be the same array (the pose is updated in place), so
 // neither is declared __restrict__; the pose is read into registers before
 // anything is stored.
-__device__ inline void pose_update(const double W[13], const double* pose_in, double* pose_out,
-                            Derived* __restrict__ dv, int t, double G_fixed, int do_update,
-                            double* __restrict__ wrench_out, double* __restrict__ stats_row) {
-  const double G = G_fixed > 0 ? G_fixed : G_sched(*dv, t);
-  const bool cold = dv->cold_svd != 0;
+// Everything the update reads besides the wrench.  The thread that runs
+// the update loads it before the wrench rows are summed (update_load), so
+// that both sets of loads are in flight together, then applies the update
+// (update_apply).
+struct UpdateIn {
+  double G;
   double ybar0[3], SigY0[6], Vw[9], dprev[3];
-  for (int e = 0; e < 3; ++e) ybar0[e] = dv->ybar0[e];
-  for (int e = 0; e < 6; ++e) SigY0[e] = dv->SigY0[e];
+  double Mcount, dt2, lamX, lamY0, Mtot, momentum;
+  double P[13];
+  int32_t status;
+  bool cold;
+};
+
+__device__ inline void update_load(const Derived* __restrict__ dv, const double* pose_in, int t, double G_fixed,
+                                   UpdateIn& u) {
+  u.G = G_fixed > 0 ? G_fixed : G_sched(*dv, t);
+  u.cold = dv->cold_svd != 0;
+  for (int e = 0; e < 3; ++e) u.ybar0[e] = dv->ybar0[e];
+  for (int e = 0; e < 6; ++e) u.SigY0[e] = dv->SigY0[e];
   // cold: the SVD starts from the identity, which is what it does without a
   // warm start, to the bit
-  for (int e = 0; e < 9; ++e) Vw[e] = cold ? ((e % 4 == 0) ? 1.0 : 0.0) : dv->Vw[e];
-  for (int e = 0; e < 3; ++e) dprev[e] = dv->dprev[e];
-  const double Mcount = dv->Mcount, dt2 = dv->dt2, lamX = dv->lamX, lamY0 = dv->lamY0, Mtot = dv->Mtot,
-               momentum = dv->momentum;
+  for (int e = 0; e < 9; ++e) u.Vw[e] = u.cold ? ((e % 4 == 0) ? 1.0 : 0.0) : dv->Vw[e];
+  for (int e = 0; e < 3; ++e) u.dprev[e] = dv->dprev[e];
+  u.Mcount = dv->Mcount;
+  u.dt2 = dv->dt2;
+  u.lamX = dv->lamX;
+  u.lamY0 = dv->lamY0;
+  u.Mtot = dv->Mtot;
+  u.momentum = dv->momentum;
+  for (int e = 0; e < 13; ++e) u.P[e] = pose_in[e];
+  u.status = dv->status;
+}
+
+__device__ inline void update_apply(const double W[13], const UpdateIn& u, double* pose_out,
+                                    Derived* __restrict__ dv, int do_update, double* __restrict__ wrench_out,
+                                    double* __restrict__ stats_row) {
+  const double G = u.G;
+  const bool cold = u.cold;
+  double ybar0[3], SigY0[6], Vw[9], dprev[3];
+  for (int e = 0; e < 3; ++e) ybar0[e] = u.ybar0[e];
+  for (int e = 0; e < 6; ++e) SigY0[e] = u.SigY0[e];
+  for (int e = 0; e < 9; ++e) Vw[e] = u.Vw[e];
+  for (int e = 0; e < 3; ++e) dprev[e] = u.dprev[e];
+  const double Mcount = u.Mcount, dt2 = u.dt2, lamX = u.lamX, lamY0 = u.lamY0, Mtot = u.Mtot, momentum = u.momentum;
   if (wrench_out) {
     for (int e = 0; e < 13; ++e) wrench_out[e] = W[e];
   }
   double P[13];
-  for (int e = 0; e < 13; ++e) P[e] = pose_in[e];
+  for (int e = 0; e < 13; ++e) P[e] = u.P[e];
   double Pn[13];
   for (int e = 0; e < 13; ++e) Pn[e] = P[e];
   double c = 1.0;
-  int32_t st = dv->status;
+  int32_t st = u.status;
   if (do_update && st == 0) {
     const double s = P[0];
     const double* R = P + 1;
@@ -120,7 +150,8 @@ __device__ inline void pose_update(const double W[13], const double* pose_in, do
     } else {
       c = sqrt(lamX / (s * s * lamY0));
       double d[3];
-      for (int r = 0; r < 3; ++r) d[r] = dt2 * W[WR_F + r] / Mtot;
+      const double dt2_m = dt2 / Mtot;
+      for (int r = 0; r < 3; ++r) d[r] = dt2_m * W[WR_F + r];
       // velocity state: the share momentum of the previous translation
       if (momentum != 0.0)
         for (int r = 0; r < 3; ++r) d[r] += momentum * dprev[r];
@@ -176,6 +207,14 @@ __device__ inline void pose_update(const double W[13], const double* pose_in, do
     stats_row[ST_STATUS] = (double)st;
     for (int e = ST_STATUS + 1; e < STATS_STRIDE; ++e) stats_row[e] = 0.0;
   }
+}
+
+__device__ inline void pose_update(const double W[13], const double* pose_in, double* pose_out,
+                                   Derived* __restrict__ dv, int t, double G_fixed, int do_update,
+                                   double* __restrict__ wrench_out, double* __restrict__ stats_row) {
+  UpdateIn u;
+  update_load(dv, pose_in, t, G_fixed, u);
+  update_apply(W, u, pose_out, dv, do_update, wrench_out, stats_row);
 }
 
 }  // namespace sgr

@@ -30,8 +30,10 @@
 // the exponent of a pair is their difference), so a template row whose
 // standardised descriptor lies more than VF_FAR spreads from the mean is
 // left out of the contraction (its exponent is set to the padding value)
-// and evaluated by vfar_kernel instead: exact differences a_i - a_j in FP64
-// for each pair, FP64 sums, the same epilogue and its own wrench slot.
+// and evaluated after it instead, in FP64 from the standardised descriptors
+// (vfar_pairs_kernel), with FP64 sums, the same epilogue and a wrench slot
+// of its own (a far row beyond the reach of every reference descriptor has
+// no weight above 2^-150 and is left at zero force: far_reachable).
 //
 // Work decomposition: a block of 256 threads (4 waves) owns 256 template
 // points; wave w holds 4 row tiles of 16 points, their At rows resident in
@@ -113,9 +115,11 @@ __global__ __launch_bounds__(1024) void vprep_kernel(const float* __restrict__ a
   if (threadIdx.x == 0) sig_s = sigma_in > 0 ? sigma_in : sqrt(v[0] / (double)N);
   __syncthreads();
   const double sigma = sig_s;
-  // largest |a - abar|^2 / sigma^2 over both clouds (NaN-propagating): the
-  // host picks the f16 form only if every augmented entry fits its range
-  double mx = 0.0;
+  // largest |a - abar|^2 / sigma^2 (NaN-propagating) over the reference
+  // (mr), and over the reference and the template rows that enter the
+  // contraction (mx: far rows do not): the host picks the f16 form only if
+  // every augmented entry fits its range
+  double mx = 0.0, mr = 0.0;
   for (int64_t r = threadIdx.x; r < N + M; r += 1024) {
     const float* a = r < N ? aX + r * D : aY + (r - N) * D;
     double n2 = 0.0;
@@ -123,20 +127,30 @@ __global__ __launch_bounds__(1024) void vprep_kernel(const float* __restrict__ a
       const double e = ((double)a[c] - mean[c]) / sigma;
       n2 += e * e;
     }
-    mx = (n2 > mx || n2 != n2) ? n2 : mx;
+    if (r < N) mr = (n2 > mr || n2 != n2) ? n2 : mr;
+    if (r < N || !(n2 > VF_FAR2)) mx = (n2 > mx || n2 != n2) ? n2 : mx;
   }
   for (int off = 32; off > 0; off >>= 1) {
     const double o = __shfl_xor(mx, off, 64);
     mx = (o > mx || o != o) ? o : mx;
+    const double q = __shfl_xor(mr, off, 64);
+    mr = (q > mr || q != q) ? q : mr;
   }
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6] = mx;
+    lds[16 + (threadIdx.x >> 6)] = mr;
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int w = 1; w < 16; ++w) mx = (lds[w] > mx || lds[w] != lds[w]) ? lds[w] : mx;
+  for (int w = 1; w < 16; ++w) {
+    mx = (lds[w] > mx || lds[w] != lds[w]) ? lds[w] : mx;
+    mr = (lds[16 + w] > mr || lds[16 + w] != lds[16 + w]) ? lds[16 + w] : mr;
+  }
   for (int c = 0; c < 32; ++c) vd[c] = mean[c];
   vd[32] = sigma;
   vd[33] = LOG2E / (sigma * sigma);
   vd[34] = mx;
+  vd[35] = mr;
   dv->sigma = sigma;
   if (!(sigma > 0) || !isfinite(vd[33])) dv->status |= ST_DEGENERATE;
 }
@@ -440,16 +454,32 @@ done:
   }
 }
 
-// The far rows in increasing order: far_idx[0..n) and n in far_idx[M].
-// One block; thread t scans a contiguous range of rows, so that an exclusive
-// scan of the per-thread counts places every index deterministically.
+// A far row whose standardised distance from every reference descriptor is
+// at least |c_i| - max_j |c_j| (triangle inequality) has no pair weight above
+// 2^(lw_max - log2(e) (|c_i| - max_j |c_j|)^2); when that is below 2^-150 its
+// force is zero in FP32 and far below any other row's, and it needs no
+// evaluation (the contraction already gives it zero weight).
+__device__ inline bool far_reachable(double n2, const double* __restrict__ vd, const Derived* __restrict__ dv) {
+  const double gap = sqrt(n2) - sqrt(vd[35]);
+  return !(gap > 0.0 && gap * gap * LOG2E > dv->lw_max + 150.0);
+}
+
+// The far rows that can carry a force, in increasing order: far_idx[0..n)
+// and n in far_idx[M].  One block; thread t scans a contiguous range of rows,
+// so that an exclusive scan of the per-thread counts places every index
+// deterministically.
 __global__ __launch_bounds__(1024) void vfar_list_kernel(const float* __restrict__ aY, int M, int D,
-                                                         const double* __restrict__ vd, int* __restrict__ far_idx) {
+                                                         const double* __restrict__ vd,
+                                                         const Derived* __restrict__ dv, int* __restrict__ far_idx) {
   __shared__ int cnt[1024];
   const int per = (M + 1023) / 1024;
   const int r0 = min(M, (int)threadIdx.x * per), r1 = min(M, r0 + per);
+  auto is_far = [&](int r) {
+    const double n2 = std_norm2(aY, r, D, vd);
+    return n2 > VF_FAR2 && far_reachable(n2, vd, dv);
+  };
   int c = 0;
-  for (int r = r0; r < r1; ++r) c += std_norm2(aY, r, D, vd) > VF_FAR2;
+  for (int r = r0; r < r1; ++r) c += is_far(r);
   cnt[threadIdx.x] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -464,107 +494,266 @@ __global__ __launch_bounds__(1024) void vfar_list_kernel(const float* __restrict
   __syncthreads();
   int o = cnt[threadIdx.x];
   for (int r = r0; r < r1; ++r)
-    if (std_norm2(aY, r, D, vd) > VF_FAR2) far_idx[o++] = r;
+    if (is_far(r)) far_idx[o++] = r;
 }
 
-// One block per far row k (template point far_idx[k]): the pair weights
-// c_j = w_j exp(-|a_i - a_j|^2 / sigma^2) from exact FP64 differences, the
-// moment sums in FP64, then the epilogue of vforce_kernel; the wrench
-// partial goes to slot slot0 + k, the per-point force (WF) and the pair sums
-// (WU with spart) to chunk 0 (vforce_kernel wrote zeros for this row in
-// every chunk).
-template <bool WU, bool WF>
-__global__ __launch_bounds__(256) void vfar_kernel(VForceArgs A, const float* __restrict__ aX,
-                                                   const float* __restrict__ wX, const float* __restrict__ aY, int D,
-                                                   const double* __restrict__ vd, const int* __restrict__ far_idx,
-                                                   int slot0) {
-  __shared__ double s_red[4 * 13];
-  const int k = blockIdx.x;
-  const int ip = far_idx[k];
-  const double kap = vd[33];  // log2(e) / sigma^2
-  double ai[32];
-#pragma unroll
-  for (int c = 0; c < 32; ++c) ai[c] = c < D ? (double)aY[(int64_t)ip * D + c] : 0.0;
-  double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int j = threadIdx.x; j < A.N; j += 256) {
-    double d2 = 0.0;
-#pragma unroll
-    for (int c = 0; c < 32; ++c)
-      if (c < D) {
-        const double d = ai[c] - (double)aX[(int64_t)j * D + c];
-        d2 += d * d;
-      }
-    const double lw = wX ? log2((double)wX[j]) : 0.0;
-    const double cj = exp2(lw - kap * d2);
-    const float4 X = A.ref4[j];
-    sums[0] += cj;
-    sums[1] += cj * (double)X.x;
-    sums[2] += cj * (double)X.y;
-    sums[3] += cj * (double)X.z;
-    sums[4] += cj * (double)X.w;
+// Far-row evaluation.  The pair exponent t_ij = lw_j - log2(e) |c_i - c_j|^2
+// is formed in FP64 from the standardised descriptors themselves,
+//   t_ij = b_j - n_i + w_i . c_j,  b_j = lw_j - log2(e) |c_j|^2,
+//   w_i = 2 log2(e) c_i,  n_i = log2(e) |c_i|^2,
+// whose terms carry a rounding of 2^-53 of their size (the contraction's
+// 2^-22 or 2^-24 is what made these rows far); the pair weight is then
+// exp2 of t rounded to FP32, as in the contraction, and the moment sums are
+// FP64.  Work: a block takes a tile of 64 far rows and a segment of the
+// reference, staged through LDS VFAR_CH records at a time; a lane holds the
+// w_i of RPL rows in registers and meets one reference record per step
+// (RPL pairs), the Q = RPL lanes of a row group taking consecutive records.
+
+constexpr int VFAR_CH = 256;      // reference records staged per chunk
+constexpr int VFAR_BLOCKS = 2048;  // pair blocks aimed at (tiles x segments)
+
+// Reference record of the far-row evaluation, vfar_stride(D) doubles: c_j
+// zero-padded to vfar_db(D) entries, b_j, x, y, z, |x|^2 of ref4, and a
+// zero (an even stride whose LDS copies of 4 consecutive records start in
+// distinct bank groups).
+__global__ __launch_bounds__(256) void vfar_ref_kernel(const float* __restrict__ aX, const float* __restrict__ wX,
+                                                       int N, int D, const double* __restrict__ vd,
+                                                       const float4* __restrict__ ref4, double* __restrict__ refd) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const int DB = vfar_db(D), RS = vfar_stride(D);
+  const double isig = 1.0 / vd[32];
+  double* r = refd + (int64_t)j * RS;
+  double n2 = 0.0;
+  for (int c = 0; c < DB; ++c) {
+    const double e = c < D ? ((double)aX[(int64_t)j * D + c] - vd[c]) * isig : 0.0;
+    r[c] = e;
+    n2 += e * e;
   }
-  block_sum<5, 256>(sums, s_red);
+  r[DB] = (wX ? log2((double)wX[j]) : 0.0) - LOG2E * n2;
+  const float4 X = ref4[j];
+  r[DB + 1] = X.x;
+  r[DB + 2] = X.y;
+  r[DB + 3] = X.z;
+  r[DB + 4] = X.w;
+  r[DB + 5] = 0.0;
+}
+
+// Segments of the reference: about VFAR_BLOCKS pair blocks in all, whole
+// chunks each; part holds n_seg x 5 x (64 row tiles) sums, at most
+// max(VFAR_BLOCKS, row tiles) x 320 doubles.
+struct VfarGrid {
+  int n_rt, n_seg, cps;  // row tiles, segments, chunks per segment
+};
+inline VfarGrid vfar_grid(int n_far, int N) {
+  VfarGrid g;
+  g.n_rt = (n_far + 63) / 64;
+  const int n_ch = std::max(1, (N + VFAR_CH - 1) / VFAR_CH);
+  const int s = std::max(1, std::min(n_ch, VFAR_BLOCKS / g.n_rt));
+  g.cps = (n_ch + s - 1) / s;
+  g.n_seg = (n_ch + g.cps - 1) / g.cps;
+  return g;
+}
+
+// Block (row tile rt, segment sg): 64 far rows 64 rt + g + G rr (row group
+// g = lane % G, rr < RPL) against the chunks [cps sg, cps (sg + 1)); wave w
+// takes records [w CH/4, (w + 1) CH/4) of a staged chunk, lane q = lane / G
+// of a row group every Q-th of them.  Sums: over the records of a lane, over
+// q (a butterfly), then over the 4 waves in order, into
+// part[(sg * 5 + e) * 64 n_rt + row].
+template <int DB>
+__global__ __launch_bounds__(256) void vfar_pairs_kernel(const double* __restrict__ refd, int N, int cps,
+                                                         const float* __restrict__ aY, int D,
+                                                         const double* __restrict__ vd,
+                                                         const int* __restrict__ far_idx, int n_far,
+                                                         double* __restrict__ part) {
+  constexpr int RS = DB + 6, RPL = DB <= 16 ? 4 : 2, G = 64 / RPL, Q = RPL, CW = VFAR_CH / 4;
+  static_assert(VFAR_CH == 256, "one staged record per thread");
+  static_assert(VFAR_CH * RS >= 4 * 64 * 5, "LDS also holds the wave sums");
+  __shared__ __align__(16) double lds[VFAR_CH * RS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane % G, q = lane / G;
+  const int64_t nfp = (int64_t)gridDim.x * 64;
+  const double isig = 1.0 / vd[32];
+  double wi[RPL][DB], ni[RPL];
+#pragma unroll
+  for (int rr = 0; rr < RPL; ++rr) {
+    const int k = (int)blockIdx.x * 64 + g + G * rr;
+    const int ip = far_idx[k < n_far ? k : n_far - 1];
+    double n2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < DB; ++c) {
+      const double e = c < D ? ((double)aY[(int64_t)ip * D + c] - vd[c]) * isig : 0.0;
+      wi[rr][c] = 2.0 * LOG2E * e;
+      n2 += e * e;
+    }
+    ni[rr] = LOG2E * n2;
+  }
+  double s[RPL][5];
+#pragma unroll
+  for (int rr = 0; rr < RPL; ++rr)
+#pragma unroll
+    for (int e = 0; e < 5; ++e) s[rr][e] = 0.0;
+  const int n_ch = (N + VFAR_CH - 1) / VFAR_CH;
+  const int c0 = (int)blockIdx.y * cps, c1 = min(n_ch, c0 + cps);
+  for (int ch = c0; ch < c1; ++ch) {
+    __syncthreads();  // the previous chunk is consumed
+    const int64_t base = (int64_t)ch * VFAR_CH;
+    const int nrec = (int)min((int64_t)VFAR_CH, (int64_t)N - base);
+    // RS / 2 granules of 16 bytes per thread, all loads issued before the
+    // LDS writes; records past N get zero weight (exp2 of -1e300 in FP32 is 0)
+    const double2* src = reinterpret_cast<const double2*>(refd + base * RS);
+    double2 buf[RS / 2];
+    if (nrec == VFAR_CH) {
+#pragma unroll
+      for (int i = 0; i < RS / 2; ++i) buf[i] = src[threadIdx.x + 256 * i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < RS / 2; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        buf[i] = (2 * e) / RS < nrec ? src[e] : make_double2((2 * e) % RS == DB ? -1e300 : 0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RS / 2; ++i) reinterpret_cast<double2*>(lds)[threadIdx.x + 256 * i] = buf[i];
+    __syncthreads();
+#pragma unroll 2
+    for (int st = 0; st < CW / Q; ++st) {
+      const double2* r = reinterpret_cast<const double2*>(lds + (wave * CW + st * Q + q) * RS);
+      double v[DB + 6];
+#pragma unroll
+      for (int c = 0; c < (DB + 6) / 2; ++c) {
+        const double2 x = r[c];
+        v[2 * c] = x.x;
+        v[2 * c + 1] = x.y;
+      }
+#pragma unroll
+      for (int rr = 0; rr < RPL; ++rr) {
+        double t = v[DB] - ni[rr];
+#pragma unroll
+        for (int c = 0; c < DB; ++c) t = fma(wi[rr][c], v[c], t);
+        const double cw = (double)__builtin_amdgcn_exp2f((float)t);
+        s[rr][0] += cw;
+        s[rr][1] = fma(cw, v[DB + 1], s[rr][1]);
+        s[rr][2] = fma(cw, v[DB + 2], s[rr][2]);
+        s[rr][3] = fma(cw, v[DB + 3], s[rr][3]);
+        s[rr][4] = fma(cw, v[DB + 4], s[rr][4]);
+      }
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < RPL; ++rr)
+#pragma unroll
+    for (int e = 0; e < 5; ++e)
+#pragma unroll
+      for (int off = G; off < 64; off <<= 1) s[rr][e] += __shfl_xor(s[rr][e], off, 64);
+  __syncthreads();  // LDS now holds the wave sums [wave][row][e]
+  if (q == 0) {
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr)
+#pragma unroll
+      for (int e = 0; e < 5; ++e) lds[(wave * 64 + g + G * rr) * 5 + e] = s[rr][e];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int k = (int)blockIdx.x * 64 + threadIdx.x;
+    if (k < n_far) {
+      const int t = threadIdx.x;
+#pragma unroll
+      for (int e = 0; e < 5; ++e)
+        part[((int64_t)blockIdx.y * 5 + e) * nfp + k] =
+            ((lds[t * 5 + e] + lds[(64 + t) * 5 + e]) + lds[(128 + t) * 5 + e]) + lds[(192 + t) * 5 + e];
+    }
+  }
+}
+
+// One block per tile of 64 far rows: wave w adds the segments w, w + 4, ...
+// of a row in order, the 4 waves' sums are added in order, then lane l of
+// wave 0 runs the epilogue of vforce_kernel for far row k = 64 tile + l
+// (template point far_idx[k]); the wrench partial goes to slot slot0 + k,
+// the per-point force (WF) and the pair sums (WU with spart) to chunk 0
+// (vforce_kernel wrote zeros for this row in every chunk).
+template <bool WU, bool WF>
+__global__ __launch_bounds__(256) void vfar_epi_kernel(VForceArgs A, const int* __restrict__ far_idx, int n_far,
+                                                       int n_seg, const double* __restrict__ part, int slot0) {
+  __shared__ double red[4][5][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = (int)blockIdx.x * 64 + lane;
+  const int64_t nfp = (int64_t)gridDim.x * 64;
+  double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (k < n_far) {
+#pragma unroll 4
+    for (int sg = wave; sg < n_seg; sg += 4) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sums[q] += part[((int64_t)sg * 5 + q) * nfp + k];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) red[wave][q][lane] = sums[q];
+  __syncthreads();
+  if (wave != 0 || k >= n_far) return;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) sums[q] = ((red[0][q][lane] + red[1][q][lane]) + red[2][q][lane]) + red[3][q][lane];
+  const int ip = far_idx[k];
   double wr[13];
 #pragma unroll
   for (int e = 0; e < 13; ++e) wr[e] = 0.0;
-  if (threadIdx.x == 0) {
-    const Derived& D_ = *A.dv;
-    bool sums_only = false;
-    if constexpr (WU) {
-      if (A.spart) {
-        double* o = A.spart + (int64_t)ip * 5;  // chunk 0
+  const Derived& D_ = *A.dv;
+  bool sums_only = false;
+  if constexpr (WU) {
+    if (A.spart) {
+      double* o = A.spart + (int64_t)ip * 5;  // chunk 0
 #pragma unroll
-        for (int q = 0; q < 5; ++q) o[q] = sums[q];
-        sums_only = true;
-      }
+      for (int q = 0; q < 5; ++q) o[q] = sums[q];
+      sums_only = true;
     }
-    if (!sums_only) {
-      double sR[9], cv[3];
-      const double s = A.pose[0];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) sR[e] = s * A.pose[1 + e];
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-        cv[r] = sR[3 * r] * D_.ybar0[0] + sR[3 * r + 1] * D_.ybar0[1] + sR[3 * r + 2] * D_.ybar0[2] +
-                A.pose[10 + r] - D_.xbar[r];
-      const double G = A.G > 0 ? A.G : G_of(D_, A.t);
-      const double coef = -(G / D_.Z);
-      const double ucoef = 0.5 * (G / D_.Z);
-      const double ex = (double)A.y0x[ip] - D_.ybar0[0], ey = (double)A.y0y[ip] - D_.ybar0[1],
-                   ez = (double)A.y0z[ip] - D_.ybar0[2];
-      const double px = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);
-      const double py = (float)(sR[3] * ex + sR[4] * ey + sR[5] * ez + cv[1]);
-      const double pz = (float)(sR[6] * ex + sR[7] * ey + sR[8] * ez + cv[2]);
-      const double tx = px * sums[0] - sums[1], ty = py * sums[0] - sums[2], tz = pz * sums[0] - sums[3];
-      const double mi = A.mY ? (double)A.mY[ip] : 1.0;
-      const double fx = coef * tx, fy = coef * ty, fz = coef * tz;
-      const double cx = px - cv[0], cy = py - cv[1], cz = pz - cv[2];
-      wr[WR_F + 0] = mi * fx;
-      wr[WR_F + 1] = mi * fy;
-      wr[WR_F + 2] = mi * fz;
-      wr[WR_K + 0] = fx * cx;
-      wr[WR_K + 1] = fx * cy;
-      wr[WR_K + 2] = fx * cz;
-      wr[WR_K + 3] = fy * cx;
-      wr[WR_K + 4] = fy * cy;
-      wr[WR_K + 5] = fy * cz;
-      wr[WR_K + 6] = fz * cx;
-      wr[WR_K + 7] = fz * cy;
-      wr[WR_K + 8] = fz * cz;
-      if constexpr (WU)
-        wr[WR_U] = ucoef * ((px * px + py * py + pz * pz + D_.eps2) * sums[0] -
-                            2.0 * (px * sums[1] + py * sums[2] + pz * sums[3]) + sums[4]);
-      if constexpr (WF) {
-        double* fp = A.fpart + (int64_t)ip * 3;  // chunk 0
-        fp[0] = fx;
-        fp[1] = fy;
-        fp[2] = fz;
-      }
-    }
-    double* o = A.wpart + (int64_t)(slot0 + k) * WR_STRIDE;
-#pragma unroll
-    for (int e = 0; e < 13; ++e) o[e] = wr[e];
   }
+  if (!sums_only) {
+    double sR[9], cv[3];
+    const double s = A.pose[0];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) sR[e] = s * A.pose[1 + e];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      cv[r] = sR[3 * r] * D_.ybar0[0] + sR[3 * r + 1] * D_.ybar0[1] + sR[3 * r + 2] * D_.ybar0[2] + A.pose[10 + r] -
+              D_.xbar[r];
+    const double G = A.G > 0 ? A.G : G_of(D_, A.t);
+    const double coef = -(G / D_.Z);
+    const double ucoef = 0.5 * (G / D_.Z);
+    const double ex = (double)A.y0x[ip] - D_.ybar0[0], ey = (double)A.y0y[ip] - D_.ybar0[1],
+                 ez = (double)A.y0z[ip] - D_.ybar0[2];
+    const double px = (float)(sR[0] * ex + sR[1] * ey + sR[2] * ez + cv[0]);
+    const double py = (float)(sR[3] * ex + sR[4] * ey + sR[5] * ez + cv[1]);
+    const double pz = (float)(sR[6] * ex + sR[7] * ey + sR[8] * ez + cv[2]);
+    const double tx = px * sums[0] - sums[1], ty = py * sums[0] - sums[2], tz = pz * sums[0] - sums[3];
+    const double mi = A.mY ? (double)A.mY[ip] : 1.0;
+    const double fx = coef * tx, fy = coef * ty, fz = coef * tz;
+    const double cx = px - cv[0], cy = py - cv[1], cz = pz - cv[2];
+    wr[WR_F + 0] = mi * fx;
+    wr[WR_F + 1] = mi * fy;
+    wr[WR_F + 2] = mi * fz;
+    wr[WR_K + 0] = fx * cx;
+    wr[WR_K + 1] = fx * cy;
+    wr[WR_K + 2] = fx * cz;
+    wr[WR_K + 3] = fy * cx;
+    wr[WR_K + 4] = fy * cy;
+    wr[WR_K + 5] = fy * cz;
+    wr[WR_K + 6] = fz * cx;
+    wr[WR_K + 7] = fz * cy;
+    wr[WR_K + 8] = fz * cz;
+    if constexpr (WU)
+      wr[WR_U] = ucoef * ((px * px + py * py + pz * pz + D_.eps2) * sums[0] -
+                          2.0 * (px * sums[1] + py * sums[2] + pz * sums[3]) + sums[4]);
+    if constexpr (WF) {
+      double* fp = A.fpart + (int64_t)ip * 3;  // chunk 0
+      fp[0] = fx;
+      fp[1] = fy;
+      fp[2] = fz;
+    }
+  }
+  double* o = A.wpart + (int64_t)(slot0 + k) * WR_STRIDE;
+#pragma unroll
+  for (int e = 0; e < 13; ++e) o[e] = wr[e];
 }
 
 template <int VK, bool H>
@@ -637,23 +826,55 @@ hipError_t launch_vforce(const VForceArgs& A, bool wu, bool wf, hipStream_t st) 
   }
 }
 
-hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, int* far_idx, hipStream_t st) {
-  hipLaunchKernelGGL(vfar_list_kernel, dim3(1), dim3(1024), 0, st, aY, M, D, vd, far_idx);
+hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, const Derived* dv, int* far_idx,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(vfar_list_kernel, dim3(1), dim3(1024), 0, st, aY, M, D, vd, dv, far_idx);
   return hipGetLastError();
 }
 
-hipError_t launch_vfar(const VForceArgs& A, const float* aX, const float* wX, const float* aY, int D,
-                       const double* vd, const int* far_idx, int n_far, int slot0, bool wu, bool wf, hipStream_t st) {
+size_t vfar_part_doubles(int M) { return (size_t)std::max(VFAR_BLOCKS, (M + 63) / 64) * 64 * 5; }
+
+hipError_t launch_vfar_ref(const float* aX, const float* wX, int N, int D, const double* vd, const float4* ref4,
+                           double* refd, hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vfar_ref_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, aX, wX, N, D, vd, ref4,
+                     refd);
+  return hipGetLastError();
+}
+
+hipError_t launch_vfar(const VForceArgs& A, const float* aY, int D, const double* vd, const double* refd,
+                       const int* far_idx, int n_far, double* part, int slot0, bool wu, bool wf, hipStream_t st) {
   if (n_far <= 0) return hipSuccess;
-  const dim3 grid((unsigned)n_far), block(256);
+  const int N = A.N;
+  const VfarGrid vg = vfar_grid(n_far, N);
+  const dim3 grid((unsigned)vg.n_rt, (unsigned)vg.n_seg), block(256);
+  switch (vfar_db(D)) {
+    case 8:
+      hipLaunchKernelGGL((vfar_pairs_kernel<8>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far, part);
+      break;
+    case 16:
+      hipLaunchKernelGGL((vfar_pairs_kernel<16>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far,
+                         part);
+      break;
+    case 24:
+      hipLaunchKernelGGL((vfar_pairs_kernel<24>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far,
+                         part);
+      break;
+    case 32:
+      hipLaunchKernelGGL((vfar_pairs_kernel<32>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far,
+                         part);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  const dim3 eg((unsigned)vg.n_rt);
   if (wu && wf)
-    hipLaunchKernelGGL((vfar_kernel<true, true>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+    hipLaunchKernelGGL((vfar_epi_kernel<true, true>), eg, block, 0, st, A, far_idx, n_far, vg.n_seg, part, slot0);
   else if (wu)
-    hipLaunchKernelGGL((vfar_kernel<true, false>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+    hipLaunchKernelGGL((vfar_epi_kernel<true, false>), eg, block, 0, st, A, far_idx, n_far, vg.n_seg, part, slot0);
   else if (wf)
-    hipLaunchKernelGGL((vfar_kernel<false, true>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+    hipLaunchKernelGGL((vfar_epi_kernel<false, true>), eg, block, 0, st, A, far_idx, n_far, vg.n_seg, part, slot0);
   else
-    hipLaunchKernelGGL((vfar_kernel<false, false>), grid, block, 0, st, A, aX, wX, aY, D, vd, far_idx, slot0);
+    hipLaunchKernelGGL((vfar_epi_kernel<false, false>), eg, block, 0, st, A, far_idx, n_far, vg.n_seg, part, slot0);
   return hipGetLastError();
 }
 
