@@ -640,6 +640,7 @@ struct VecWs {
   double* fpart;
   double* mom;
   int K, n_chunks, slots;
+  int n_cu;   // compute units (the far-row grid is one round of blocks)
   bool half;  // split-f16 products (decided by setup_vec)
   int* far_idx;  // far template rows (M + 1 ints: the list, then its length)
   int n_far;     // number of far rows (read back by setup_vec)
@@ -654,6 +655,7 @@ struct VecWs {
 
 int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, VecWs& w, bool pinv = false) {
   w.K = vforce_K(D);
+  w.n_cu = ctx->n_cu;
   w.n_chunks = vforce_chunks(M, N, ctx->n_cu);
   w.slots = vforce_n_iblk(M) * w.n_chunks;
   // every template row may be a far row, with a wrench slot of its own
@@ -671,7 +673,7 @@ int carve_vec(sgr_ctx* ctx, int M, int N, int D, bool with_f, bool with_mom, Vec
     w.fpart = with_f ? c.take<double>((size_t)w.n_chunks * M * 3) : nullptr;
     w.mom = with_mom ? c.take<double>(20) : nullptr;
     w.far_idx = c.take<int>((size_t)M + 1);
-    w.far_ref = c.take<double>((size_t)N * vfar_stride(D));
+    w.far_ref = c.take<double>((size_t)vfar_pad_refs(N) * vfar_stride(D));
     w.far_part = c.take<double>(vfar_part_doubles(M));
     if (pinv) {
       w.tm4 = c.take<float4>(M);
@@ -704,7 +706,10 @@ int setup_vec(const sgr_cloud* tmpl, const float* a_t, const sgr_cloud* ref, con
   if (w.half) w.K = vforce_half_K(D);
   HIPCHK(launch_vpack(ref->x, ref->y, ref->z, a_r, ref->m, N, a_t, M, D, w.half, w.dv, w.vd, w.Bt, w.ref4, w.At,
                       st));
-  if (n_far > 0) HIPCHK(launch_vfar_ref(a_r, ref->m, N, D, w.vd, w.ref4, w.far_ref, st));
+  if (n_far > 0) {
+    HIPCHK(launch_vfar_ref(a_r, ref->m, N, D, w.vd, w.ref4, w.far_ref, st));
+    vfar_prepare(D);
+  }
   return SGR_OK;
 }
 
@@ -715,7 +720,7 @@ hipError_t run_vforce(const VForceArgs& A, const float* a_t, int D, const VecWs&
   hipError_t e = launch_vforce(A, wu, wf, st);
   if (e != hipSuccess) return e;
   if (used) *used = w.slots + w.n_far;
-  return launch_vfar(A, a_t, D, w.vd, w.far_ref, w.far_idx, w.n_far, w.far_part, w.slots, wu, wf, st);
+  return launch_vfar(A, a_t, D, w.vd, w.far_ref, w.far_idx, w.n_far, w.far_part, w.slots, wu, wf, w.n_cu, st);
 }
 
 VForceArgs vargs(const sgr_cloud* tmpl, const sgr_cloud* ref, const VecWs& w, const double* pose, int t) {

@@ -199,18 +199,21 @@ struct VForceArgs {
 // mean, within reach of a reference descriptor), listed in increasing order
 // into far_idx[0..n), n in far_idx[M] (far_idx holds M + 1 ints).  Their
 // evaluation after the contraction reads reference records built once per
-// registration (launch_vfar_ref: N records of vfar_stride(D) doubles) and
-// leaves per-segment sums in part (vfar_part_doubles(M) doubles); one wrench
-// slot per far row from slot0.
-__host__ __device__ inline int vfar_db(int D) { return 8 * ((D + 7) / 8); }
+// registration (launch_vfar_ref: vfar_pad_refs(N) records of vfar_stride(D)
+// doubles) and leaves per-segment sums in part (vfar_part_doubles(M)
+// doubles); one wrench slot per far row from slot0.
+__host__ __device__ inline int vfar_db(int D) { return 4 * ((D + 3) / 4); }
 __host__ __device__ inline int vfar_stride(int D) { return vfar_db(D) + 6; }
 size_t vfar_part_doubles(int M);
+int vfar_pad_refs(int N);
+void vfar_prepare(int D);  // host queries of the far-row launch, outside stream capture
 hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, const Derived* dv, int* far_idx,
                             hipStream_t st);
 hipError_t launch_vfar_ref(const float* aX, const float* wX, int N, int D, const double* vd, const float4* ref4,
                            double* refd, hipStream_t st);
 hipError_t launch_vfar(const VForceArgs& A, const float* aY, int D, const double* vd, const double* refd,
-                       const int* far_idx, int n_far, double* part, int slot0, bool wu, bool wf, hipStream_t st);
+                       const int* far_idx, int n_far, double* part, int slot0, bool wu, bool wf, int n_cu,
+                       hipStream_t st);
 int vforce_K(int D);
 // Halves per split-f16 row: the contraction [h, h, l] . [h, l, h] of length
 // 3 (D + 2), padded to whole 16x16x32 instructions.

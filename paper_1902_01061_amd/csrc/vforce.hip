@@ -45,6 +45,7 @@
 // is FP64, as in the scalar kernel: per-point forces, the block's wrench
 // partial in wpart[slot] (same layout, consumed by the same update kernel).
 #include <algorithm>
+#include <atomic>
 
 #include "common.h"
 #include "launch.h"
@@ -515,15 +516,19 @@ constexpr int VFAR_BLOCKS = 2048;  // pair blocks aimed at (tiles x segments)
 // Reference record of the far-row evaluation, vfar_stride(D) doubles: c_j
 // zero-padded to vfar_db(D) entries, b_j, x, y, z, |x|^2 of ref4, and a
 // zero (an even stride whose LDS copies of 4 consecutive records start in
-// distinct bank groups).
+// distinct bank groups); vfar_pad_refs(N) records, those past N of zero
+// weight.
 __global__ __launch_bounds__(256) void vfar_ref_kernel(const float* __restrict__ aX, const float* __restrict__ wX,
                                                        int N, int D, const double* __restrict__ vd,
                                                        const float4* __restrict__ ref4, double* __restrict__ refd) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;  // < vfar_pad_refs(N)
   const int DB = vfar_db(D), RS = vfar_stride(D);
-  const double isig = 1.0 / vd[32];
   double* r = refd + (int64_t)j * RS;
+  if (j >= N) {  // padding: zero weight (exp2 of -1e300 in FP32 is 0)
+    for (int c = 0; c < RS; ++c) r[c] = c == DB ? -1e300 : 0.0;
+    return;
+  }
+  const double isig = 1.0 / vd[32];
   double n2 = 0.0;
   for (int c = 0; c < DB; ++c) {
     const double e = c < D ? ((double)aX[(int64_t)j * D + c] - vd[c]) * isig : 0.0;
@@ -539,20 +544,38 @@ __global__ __launch_bounds__(256) void vfar_ref_kernel(const float* __restrict__
   r[DB + 5] = 0.0;
 }
 
-// Segments of the reference: about VFAR_BLOCKS pair blocks in all, whole
-// chunks each; part holds n_seg x 5 x (64 row tiles) sums, at most
-// max(VFAR_BLOCKS, row tiles) x 320 doubles.
+// Segments of the reference: one round of pair blocks (bpc resident blocks
+// per compute unit, from the kernel's register and LDS budget), whole
+// chunks each, so that a block's start-up latency is paid once and its
+// chunks stream through the LDS; at most max(VFAR_BLOCKS, row tiles)
+// blocks, so part holds at most that many x 320 doubles.
 struct VfarGrid {
   int n_rt, n_seg, cps;  // row tiles, segments, chunks per segment
 };
-inline VfarGrid vfar_grid(int n_far, int N) {
+inline VfarGrid vfar_grid(int n_far, int N, int slots) {
   VfarGrid g;
   g.n_rt = (n_far + 63) / 64;
   const int n_ch = std::max(1, (N + VFAR_CH - 1) / VFAR_CH);
-  const int s = std::max(1, std::min(n_ch, VFAR_BLOCKS / g.n_rt));
+  slots = std::max(1, std::min(VFAR_BLOCKS, slots));
+  const int s = std::max(1, std::min(n_ch, slots / g.n_rt));
   g.cps = (n_ch + s - 1) / s;
   g.n_seg = (n_ch + g.cps - 1) / g.cps;
   return g;
+}
+
+// One staged chunk: NG granules of 16 bytes per thread of a block of 256
+// (a clang vector type, which stays in registers).
+typedef double v2d __attribute__((ext_vector_type(2)));
+template <int NG>
+__device__ __forceinline__ void vfar_fetch(v2d (&buf)[NG], const double* __restrict__ refd, int ch) {
+  const v2d* src = reinterpret_cast<const v2d*>(refd + (int64_t)ch * VFAR_CH * (2 * NG));
+#pragma unroll
+  for (int i = 0; i < NG; ++i) buf[i] = src[threadIdx.x + 256 * i];
+}
+template <int NG>
+__device__ __forceinline__ void vfar_store(const v2d (&buf)[NG], double* lds) {
+#pragma unroll
+  for (int i = 0; i < NG; ++i) reinterpret_cast<v2d*>(lds)[threadIdx.x + 256 * i] = buf[i];
 }
 
 // Block (row tile rt, segment sg): 64 far rows 64 rt + g + G rr (row group
@@ -561,69 +584,75 @@ inline VfarGrid vfar_grid(int n_far, int N) {
 // of a row group every Q-th of them.  Sums: over the records of a lane, over
 // q (a butterfly), then over the 4 waves in order, into
 // part[(sg * 5 + e) * 64 n_rt + row].
-template <int DB>
+template <int DB, bool WU, bool PF>
 __global__ __launch_bounds__(256) void vfar_pairs_kernel(const double* __restrict__ refd, int N, int cps,
                                                          const float* __restrict__ aY, int D,
                                                          const double* __restrict__ vd,
                                                          const int* __restrict__ far_idx, int n_far,
                                                          double* __restrict__ part) {
   constexpr int RS = DB + 6, RPL = DB <= 16 ? 4 : 2, G = 64 / RPL, Q = RPL, CW = VFAR_CH / 4;
+  constexpr int NS = WU ? 5 : 4;  // sums: c, c x, c y, c z (and c |x|^2 for the energy)
   static_assert(VFAR_CH == 256, "one staged record per thread");
   static_assert(VFAR_CH * RS >= 4 * 64 * 5, "LDS also holds the wave sums");
-  __shared__ __align__(16) double lds[VFAR_CH * RS];
+  constexpr int NG = RS / 2;  // 16-byte granules of a chunk per thread
+  // PF: two LDS buffers; chunk ch + 1 is requested before chunk ch is used
+  // and lands in registers meanwhile (otherwise it is requested after)
+  __shared__ __align__(16) double lds[(PF ? 2 : 1) * VFAR_CH * RS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane % G, q = lane / G;
   const int64_t nfp = (int64_t)gridDim.x * 64;
+  const int n_ch = (N + VFAR_CH - 1) / VFAR_CH;
+  const int c0 = (int)blockIdx.y * cps, c1 = min(n_ch, c0 + cps);
+  // the far-row indices, then the first chunk, then the rows' descriptors
+  // are requested, so that the staging overlaps the row set-up
+  int ip[RPL];
+#pragma unroll
+  for (int rr = 0; rr < RPL; ++rr) {
+    const int k = (int)blockIdx.x * 64 + g + G * rr;
+    ip[rr] = far_idx[k < n_far ? k : n_far - 1];
+  }
+  v2d b0[NG];
+  if (c0 < c1) vfar_fetch(b0, refd, c0);
   const double isig = 1.0 / vd[32];
   double wi[RPL][DB], ni[RPL];
 #pragma unroll
   for (int rr = 0; rr < RPL; ++rr) {
-    const int k = (int)blockIdx.x * 64 + g + G * rr;
-    const int ip = far_idx[k < n_far ? k : n_far - 1];
     double n2 = 0.0;
 #pragma unroll
     for (int c = 0; c < DB; ++c) {
-      const double e = c < D ? ((double)aY[(int64_t)ip * D + c] - vd[c]) * isig : 0.0;
+      const double e = c < D ? ((double)aY[(int64_t)ip[rr] * D + c] - vd[c]) * isig : 0.0;
       wi[rr][c] = 2.0 * LOG2E * e;
       n2 += e * e;
     }
     ni[rr] = LOG2E * n2;
   }
+  if (c0 < c1) vfar_store(b0, lds);
   double s[RPL][5];
 #pragma unroll
   for (int rr = 0; rr < RPL; ++rr)
 #pragma unroll
     for (int e = 0; e < 5; ++e) s[rr][e] = 0.0;
-  const int n_ch = (N + VFAR_CH - 1) / VFAR_CH;
-  const int c0 = (int)blockIdx.y * cps, c1 = min(n_ch, c0 + cps);
   for (int ch = c0; ch < c1; ++ch) {
-    __syncthreads();  // the previous chunk is consumed
-    const int64_t base = (int64_t)ch * VFAR_CH;
-    const int nrec = (int)min((int64_t)VFAR_CH, (int64_t)N - base);
-    // RS / 2 granules of 16 bytes per thread, all loads issued before the
-    // LDS writes; records past N get zero weight (exp2 of -1e300 in FP32 is 0)
-    const double2* src = reinterpret_cast<const double2*>(refd + base * RS);
-    double2 buf[RS / 2];
-    if (nrec == VFAR_CH) {
-#pragma unroll
-      for (int i = 0; i < RS / 2; ++i) buf[i] = src[threadIdx.x + 256 * i];
+    double* cur = lds + (PF ? ((ch - c0) & 1) * VFAR_CH * RS : 0);
+    v2d b[NG];
+    if constexpr (PF) {
+      __syncthreads();  // chunk ch is staged, the buffer of ch + 1 is free
+      if (ch + 1 < c1) vfar_fetch(b, refd, ch + 1);
     } else {
-#pragma unroll
-      for (int i = 0; i < RS / 2; ++i) {
-        const int e = threadIdx.x + 256 * i;
-        buf[i] = (2 * e) / RS < nrec ? src[e] : make_double2((2 * e) % RS == DB ? -1e300 : 0.0, 0.0);
+      if (ch > c0) {
+        vfar_fetch(b, refd, ch);
+        __syncthreads();  // the previous chunk is consumed
+        vfar_store(b, cur);
       }
+      __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < RS / 2; ++i) reinterpret_cast<double2*>(lds)[threadIdx.x + 256 * i] = buf[i];
-    __syncthreads();
 #pragma unroll 2
     for (int st = 0; st < CW / Q; ++st) {
-      const double2* r = reinterpret_cast<const double2*>(lds + (wave * CW + st * Q + q) * RS);
+      const v2d* r = reinterpret_cast<const v2d*>(cur + (wave * CW + st * Q + q) * RS);
       double v[DB + 6];
 #pragma unroll
       for (int c = 0; c < (DB + 6) / 2; ++c) {
-        const double2 x = r[c];
+        const v2d x = r[c];
         v[2 * c] = x.x;
         v[2 * c + 1] = x.y;
       }
@@ -634,11 +663,12 @@ __global__ __launch_bounds__(256) void vfar_pairs_kernel(const double* __restric
         for (int c = 0; c < DB; ++c) t = fma(wi[rr][c], v[c], t);
         const double cw = (double)__builtin_amdgcn_exp2f((float)t);
         s[rr][0] += cw;
-        s[rr][1] = fma(cw, v[DB + 1], s[rr][1]);
-        s[rr][2] = fma(cw, v[DB + 2], s[rr][2]);
-        s[rr][3] = fma(cw, v[DB + 3], s[rr][3]);
-        s[rr][4] = fma(cw, v[DB + 4], s[rr][4]);
+#pragma unroll
+        for (int e = 1; e < NS; ++e) s[rr][e] = fma(cw, v[DB + e], s[rr][e]);
       }
+    }
+    if constexpr (PF) {
+      if (ch + 1 < c1) vfar_store(b, lds + ((ch + 1 - c0) & 1) * VFAR_CH * RS);
     }
   }
 #pragma unroll
@@ -833,39 +863,86 @@ hipError_t launch_vfar_list(const float* aY, int M, int D, const double* vd, con
 }
 
 size_t vfar_part_doubles(int M) { return (size_t)std::max(VFAR_BLOCKS, (M + 63) / 64) * 64 * 5; }
+int vfar_pad_refs(int N) { return (N + VFAR_CH - 1) / VFAR_CH * VFAR_CH; }
 
 hipError_t launch_vfar_ref(const float* aX, const float* wX, int N, int D, const double* vd, const float4* ref4,
                            double* refd, hipStream_t st) {
-  if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(vfar_ref_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, aX, wX, N, D, vd, ref4,
-                     refd);
+  const int n = vfar_pad_refs(N);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vfar_ref_kernel, dim3((unsigned)(n / 256)), dim3(256), 0, st, aX, wX, N, D, vd, ref4, refd);
   return hipGetLastError();
 }
 
+// Resident blocks per compute unit of a pair kernel (from its register and
+// LDS budget), queried once; vfar_prepare runs the queries outside any
+// stream capture.
+template <int DB, bool WU>
+int vfar_bpc() {
+  constexpr bool PF = DB <= 8;  // register prefetch of the next chunk where the registers allow it
+  static std::atomic<int> bpc{0};
+  int b = bpc.load(std::memory_order_relaxed);
+  if (b == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, vfar_pairs_kernel<DB, WU, PF>, 256, 0) != hipSuccess)
+      b = 0;
+    b = std::max(1, b);
+    bpc.store(b, std::memory_order_relaxed);
+  }
+  return b;
+}
+
+template <int DB, bool WU>
+hipError_t launch_pairs(int n_far, int N, int n_cu, const double* refd, const float* aY, int D, const double* vd,
+                        const int* far_idx, double* part, hipStream_t st, VfarGrid& vg) {
+  constexpr bool PF = DB <= 8;
+  vg = vfar_grid(n_far, N, vfar_bpc<DB, WU>() * n_cu);
+  const dim3 grid((unsigned)vg.n_rt, (unsigned)vg.n_seg);
+  hipLaunchKernelGGL((vfar_pairs_kernel<DB, WU, PF>), grid, dim3(256), 0, st, refd, N, vg.cps, aY, D, vd, far_idx,
+                     n_far, part);
+  return hipGetLastError();
+}
+
+void vfar_prepare(int D) {
+  switch (vfar_db(D)) {
+    case 4: vfar_bpc<4, false>(); vfar_bpc<4, true>(); break;
+    case 8: vfar_bpc<8, false>(); vfar_bpc<8, true>(); break;
+    case 12: vfar_bpc<12, false>(); vfar_bpc<12, true>(); break;
+    case 16: vfar_bpc<16, false>(); vfar_bpc<16, true>(); break;
+    case 20: vfar_bpc<20, false>(); vfar_bpc<20, true>(); break;
+    case 24: vfar_bpc<24, false>(); vfar_bpc<24, true>(); break;
+    case 28: vfar_bpc<28, false>(); vfar_bpc<28, true>(); break;
+    case 32: vfar_bpc<32, false>(); vfar_bpc<32, true>(); break;
+    default: break;
+  }
+}
+
 hipError_t launch_vfar(const VForceArgs& A, const float* aY, int D, const double* vd, const double* refd,
-                       const int* far_idx, int n_far, double* part, int slot0, bool wu, bool wf, hipStream_t st) {
+                       const int* far_idx, int n_far, double* part, int slot0, bool wu, bool wf, int n_cu,
+                       hipStream_t st) {
   if (n_far <= 0) return hipSuccess;
   const int N = A.N;
-  const VfarGrid vg = vfar_grid(n_far, N);
-  const dim3 grid((unsigned)vg.n_rt, (unsigned)vg.n_seg), block(256);
-  switch (vfar_db(D)) {
-    case 8:
-      hipLaunchKernelGGL((vfar_pairs_kernel<8>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far, part);
-      break;
-    case 16:
-      hipLaunchKernelGGL((vfar_pairs_kernel<16>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far,
-                         part);
-      break;
-    case 24:
-      hipLaunchKernelGGL((vfar_pairs_kernel<24>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far,
-                         part);
-      break;
-    case 32:
-      hipLaunchKernelGGL((vfar_pairs_kernel<32>), grid, block, 0, st, refd, N, vg.cps, aY, D, vd, far_idx, n_far,
-                         part);
-      break;
+  VfarGrid vg;
+  hipError_t e = hipSuccess;
+  switch (vfar_db(D) * 2 + (wu ? 1 : 0)) {
+    case 8: e = launch_pairs<4, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 9: e = launch_pairs<4, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 16: e = launch_pairs<8, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 17: e = launch_pairs<8, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 24: e = launch_pairs<12, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 25: e = launch_pairs<12, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 32: e = launch_pairs<16, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 33: e = launch_pairs<16, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 40: e = launch_pairs<20, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 41: e = launch_pairs<20, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 48: e = launch_pairs<24, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 49: e = launch_pairs<24, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 56: e = launch_pairs<28, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 57: e = launch_pairs<28, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 64: e = launch_pairs<32, false>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
+    case 65: e = launch_pairs<32, true>(n_far, N, n_cu, refd, aY, D, vd, far_idx, part, st, vg); break;
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
+  const dim3 block(256);
   const dim3 eg((unsigned)vg.n_rt);
   if (wu && wf)
     hipLaunchKernelGGL((vfar_epi_kernel<true, true>), eg, block, 0, st, A, far_idx, n_far, vg.n_seg, part, slot0);

@@ -261,6 +261,55 @@ def test_step_vec_full_size_sampled(sg, ctx):
     assert e <= F_TOL
 
 
+@pytest.mark.parametrize("D", [3, 5, 20])
+def test_step_vec_many_far_rows_sampled(sg, ctx, D):
+    """24 000 x 24 000 with 40% of the template rows 30 spreads (of the
+    clustered part) from the descriptor mean, in 240 groups around 1% of the
+    reference descriptors: more than 8 spreads after standardisation, so the
+    far-row kernels run on about 150 row tiles with several staged chunks
+    per reference segment and a ragged last segment (register prefetch for
+    D = 3 and 5; descriptors padded to 4, 8 and 20 entries).  Sampled rows, most of them far,
+    meet the per-point bar with the energy sum (wrench asked for) and
+    without it."""
+    M = N = 24000
+    pr = random_pair(M, N, seed=70 + D)
+    rng = np.random.default_rng(70 + D)
+    cen = rng.random((6, D))
+    aX = cen[rng.integers(0, 6, N)] + 0.05 * rng.normal(size=(N, D))
+    aY = cen[rng.integers(0, 6, M)] + 0.05 * rng.normal(size=(M, D))
+    sd0 = np.sqrt(np.mean(np.sum((aX - aX.mean(0)) ** 2, axis=1)))
+    u = rng.normal(size=(240, D))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    hubs = aX.mean(0) + 30.0 * sd0 * u
+    far = rng.choice(M, int(0.4 * M), replace=False)
+    aX[:240] = hubs + 0.1 * sd0 * rng.normal(size=(240, D))
+    aY[far] = hubs[rng.integers(0, 240, len(far))] + 0.3 * sd0 * rng.normal(size=(len(far), D))
+    aX, aY = aX.astype(np.float32), aY.astype(np.float32)
+    mu = aX.astype(np.float64).mean(0)
+    sig = np.sqrt(np.mean(np.sum((aX - mu) ** 2, axis=1)))
+    n_far = int(np.sum(np.sum(((aY - mu) / sig) ** 2, axis=1) > 64.0))
+    assert n_far > 0.35 * M, n_far
+    prm = O.Params(p=1.0, k=16, E=40)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64))
+    pose = O.Pose(1.05, rot_axis_angle([1, -1, 2], 10.0), np.array([0.02, -0.03, 0.01]))
+    Y = pose.apply(pr.tmpl)
+    rows = np.concatenate([rng.choice(far, 200, replace=False),
+                           rng.choice(np.setdiff1d(np.arange(M), far), 56, replace=False)])
+    t = 5
+    G = O.G_schedule(t, prm.E)
+    f_o, _ = O.forces(Y, S, G, rows=rows, block=32)
+    sc = O.force_scale(Y, S, G, rows=rows, block=32)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    gp = sg.Params(p=1.0, k=16, E=40)
+    mt, mr = _dt(_mom(pr.tmpl), torch.float64), _dt(_mom(pr.ref), torch.float64)
+    for want_wrench in (True, False):
+        _, _, f = ctx.step_vec(tm, _dt(aY), rf, _dt(aX), mt, mr, gp, t, sg.pose_from_srt(pose.s, pose.R, pose.t),
+                               want_wrench=want_wrench, want_f=True)
+        e = row_error(f.cpu().numpy().astype(np.float64)[rows], f_o, sc)
+        print(f"many far rows D={D} ({n_far} far) wrench={want_wrench}: sampled force error {e:.1e}")
+        assert e <= F_TOL
+
+
 def test_vec_rejects_bad_arguments(sg, ctx):
     pr = random_pair(100, 120, seed=2)
     tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
