@@ -86,6 +86,33 @@ def test_degenerate_clouds_are_errors(sg, ctx):
     ctx.register(tm, rf, sg.Params(k=8, E=3))
 
 
+def test_empty_clouds_are_rejected(sg, ctx):
+    """A cloud with no points is an argument error (code -1) at every entry
+    point that takes one, before any kernel runs; the context stays
+    usable."""
+    pr = random_pair(40, 50, seed=6)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    empty = sg.Cloud(np.zeros((0, 3), np.float32))
+    prm = sg.Params(k=4, E=3)
+    calls = [
+        ("register, empty template", lambda: ctx.register(empty, rf, prm)),
+        ("register, empty reference", lambda: ctx.register(tm, empty, prm)),
+        ("descriptors", lambda: ctx.descriptors(empty, 4)),
+        ("knn", lambda: ctx.knn(empty, 4)),
+        ("residual", lambda: ctx.residual(empty, rf, sg.pose_identity())),
+        ("batch with an empty member", lambda: ctx.register_batch([tm, empty], [rf, rf], prm)),
+        ("vector registration", lambda: ctx.register_vec(empty, _dt(np.zeros((0, 4))), rf,
+                                                         _dt(np.random.rand(50, 4)), sg.Params(p=1.0, E=3))),
+        ("batched descriptors", lambda: ctx.descriptors_batch([tm, empty], 4)),
+    ]
+    for name, call in calls:
+        with pytest.raises(sg.SgrError) as e:
+            call()
+        assert e.value.code == -1, name
+    pose, _ = ctx.register(tm, rf, prm)
+    assert np.isfinite(pose.cpu().numpy()).all()
+
+
 @pytest.mark.parametrize("flags,tol", [(0, F_TOL), (2, 2e-3)])
 def test_largest_workload_force_along_trajectory(sg, ctx, flags, tol):
     """The depth-frame scene (250 000 x 307 200, g = a a s): the force at the
