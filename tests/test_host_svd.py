@@ -15,14 +15,13 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-@pytest.fixture(scope="module")
-def harness(tmp_path_factory):
+def _build(tmp_path_factory, name, extra):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
-    exe = str(tmp_path_factory.mktemp("svd") / "svd_check")
-    subprocess.run([hipcc, "--offload-arch=gfx950", "-O2", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-                    "-packed-fp32-ops", os.path.join(HERE, "host", "svd_check.hip"), "-o", exe],
+    exe = str(tmp_path_factory.mktemp("svd") / name)
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                    "-packed-fp32-ops"] + extra + [os.path.join(HERE, "host", "svd_check.hip"), "-o", exe],
                    check=True, capture_output=True)
 
     def run(cases):
@@ -32,7 +31,9 @@ def harness(tmp_path_factory):
             v0 = np.zeros(9) if V0 is None else np.asarray(V0, float).ravel()
             lines.append(" ".join([str(int(V0 is not None))] + [repr(float(x)) for x in np.asarray(A).ravel()]
                                   + [repr(float(x)) for x in v0]))
-        out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
+        out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True)
+        assert out.returncode == 0 and "runtime error" not in out.stderr and "Sanitizer" not in out.stderr, \
+            out.stderr[-2000:]
         res = []
         for ln in out.stdout.strip().split("\n"):
             x = np.array([float(t) for t in ln.split()])
@@ -40,6 +41,11 @@ def harness(tmp_path_factory):
                             ok=int(x[30]), lam=x[31:34]))
         return res
     return run
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    return _build(tmp_path_factory, "svd_check", ["-O2"])
 
 
 def _kabsch(C):
@@ -142,3 +148,30 @@ def test_extreme_scales(harness):
         assert r["ok"] == 1
         np.testing.assert_allclose(r["R"], _kabsch(A), atol=1e-11 if tol < 1e-6 else 1e-2)
         assert abs(np.linalg.det(r["R"]) - 1.0) < 1e-12
+
+
+def test_routines_under_host_sanitizers(harness, tmp_path_factory):
+    """The same routines built for the host with AddressSanitizer and
+    UndefinedBehaviorSanitizer (no recovery: any report ends the run with an
+    error), over every case above: warm and cold starts, rank 2, 1 and 0,
+    the identity, PSD eigenvalues and entries from 2^-1060 to 1e300.  No
+    report, and the same results as the optimised build."""
+    san = _build(tmp_path_factory, "svd_check_san",
+                 ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all"])
+    rng = np.random.default_rng(11)
+    mats = _cases(rng, 20)
+    cases = [(A, None) for A in mats]
+    for A in mats[:10]:
+        _, _, Vt = np.linalg.svd(A + 1e-3 * np.linalg.norm(A) * rng.normal(size=(3, 3)))
+        cases.append((A, Vt.T * np.sign(np.linalg.det(Vt))))
+    P, Q = _random_rot(rng), _random_rot(rng)
+    cases += [(P @ np.diag([3.0, 1.0, 0.0]) @ Q.T, None), (P @ np.diag([3.0, 0.0, 0.0]) @ Q.T, None),
+              (np.zeros((3, 3)), None), (np.eye(3), None)]
+    cases += [(A / np.abs(A).max() * sc, None) for A in mats[:3] for sc in (1e-300, 1e300, 2.0 ** -1060)]
+    a, b = san(cases), harness(cases)
+    assert len(a) == len(b) == len(cases)
+    for x, y in zip(a, b):
+        assert x["ok"] == y["ok"]
+        for key in ("sv", "R", "lam"):
+            np.testing.assert_allclose(x[key], y[key], rtol=1e-12, atol=1e-12 * max(1.0, float(np.abs(y[key]).max())))
