@@ -261,19 +261,13 @@ def test_step_vec_full_size_sampled(sg, ctx):
     assert e <= F_TOL
 
 
-@pytest.mark.parametrize("D", [3, 5, 20])
-def test_step_vec_many_far_rows_sampled(sg, ctx, D):
-    """24 000 x 24 000 with 40% of the template rows 30 spreads (of the
-    clustered part) from the descriptor mean, in 240 groups around 1% of the
-    reference descriptors: more than 8 spreads after standardisation, so the
-    far-row kernels run on about 150 row tiles with several staged chunks
-    per reference segment and a ragged last segment (register prefetch for
-    D = 3 and 5; descriptors padded to 4, 8 and 20 entries).  Sampled rows, most of them far,
-    meet the per-point bar with the energy sum (wrench asked for) and
-    without it."""
-    M = N = 24000
-    pr = random_pair(M, N, seed=70 + D)
-    rng = np.random.default_rng(70 + D)
+def _far_case(M, N, D, seed):
+    """Clustered descriptors with 40 % of the template rows 30 spreads (of
+    the clustered part) from the mean, in groups around 1 % of the
+    reference descriptors (at most 240): more than 8 spreads after
+    standardisation."""
+    pr = random_pair(M, N, seed=seed)
+    rng = np.random.default_rng(seed)
     cen = rng.random((6, D))
     aX = cen[rng.integers(0, 6, N)] + 0.05 * rng.normal(size=(N, D))
     aY = cen[rng.integers(0, 6, M)] + 0.05 * rng.normal(size=(M, D))
@@ -282,13 +276,27 @@ def test_step_vec_many_far_rows_sampled(sg, ctx, D):
     u /= np.linalg.norm(u, axis=1, keepdims=True)
     hubs = aX.mean(0) + 30.0 * sd0 * u
     far = rng.choice(M, int(0.4 * M), replace=False)
-    aX[:240] = hubs + 0.1 * sd0 * rng.normal(size=(240, D))
-    aY[far] = hubs[rng.integers(0, 240, len(far))] + 0.3 * sd0 * rng.normal(size=(len(far), D))
+    n_hub = max(1, min(240, N // 100))   # 1 % of the reference, so sigma stays near 3 sd0
+    aX[:n_hub] = hubs[:n_hub] + 0.1 * sd0 * rng.normal(size=(n_hub, D))
+    aY[far] = hubs[rng.integers(0, n_hub, len(far))] + 0.3 * sd0 * rng.normal(size=(len(far), D))
     aX, aY = aX.astype(np.float32), aY.astype(np.float32)
     mu = aX.astype(np.float64).mean(0)
     sig = np.sqrt(np.mean(np.sum((aX - mu) ** 2, axis=1)))
     n_far = int(np.sum(np.sum(((aY - mu) / sig) ** 2, axis=1) > 64.0))
     assert n_far > 0.35 * M, n_far
+    return pr, aX, aY, far, n_far, rng
+
+
+@pytest.mark.parametrize("D", [3, 5, 20])
+def test_step_vec_many_far_rows_sampled(sg, ctx, D):
+    """24 000 x 24 000 with 40% of the template rows far (_far_case): the
+    far-row kernels run on about 150 row tiles with several staged chunks
+    per reference segment and a ragged last segment (register prefetch for
+    D = 3 and 5; descriptors padded to 4, 8 and 20 entries).  Sampled rows,
+    most of them far, meet the per-point bar with the energy sum (wrench
+    asked for) and without it."""
+    M = N = 24000
+    pr, aX, aY, far, n_far, rng = _far_case(M, N, D, 70 + D)
     prm = O.Params(p=1.0, k=16, E=40)
     S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64))
     pose = O.Pose(1.05, rot_axis_angle([1, -1, 2], 10.0), np.array([0.02, -0.03, 0.01]))
@@ -308,6 +316,34 @@ def test_step_vec_many_far_rows_sampled(sg, ctx, D):
         e = row_error(f.cpu().numpy().astype(np.float64)[rows], f_o, sc)
         print(f"many far rows D={D} ({n_far} far) wrench={want_wrench}: sampled force error {e:.1e}")
         assert e <= F_TOL
+
+
+@pytest.mark.parametrize("flags", [0, 4])
+def test_register_vec_far_rows_with_pose_independent_sums(sg, ctx, flags):
+    """A registration whose template has 40 % far rows (_far_case, 3 000 x
+    3 000, D = 5): with the pair sums formed once (flags bit 3; the far rows'
+    sums from the far-row kernels) against the per-iteration kernels and
+    against the oracle's registration, in both product forms."""
+    pr, aX, aY, _, n_far, _ = _far_case(3000, 3000, 5, 90)
+    prm = O.Params(p=1.0, k=16, E=20)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=aX.astype(np.float64), aY=aY.astype(np.float64))
+    po, _, _ = O.register(pr.tmpl, S)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    poses = {}
+    for f in (flags, flags | 8):
+        pose, _ = ctx.register_vec(tm, _dt(aY), rf, _dt(aX), sg.Params(p=1.0, k=16, E=20, flags=f))
+        s, R, t = sg.pose_to_srt(pose)
+        poses[f] = O.Pose(s, R, t)
+    D = O.diameter(pr.ref)
+
+    def rmse(a, b):
+        d = a.apply(pr.tmpl) - b.apply(pr.tmpl)
+        return float(np.sqrt(np.mean(np.sum(d * d, axis=1)))) / D
+    e_o, e_k = rmse(poses[flags | 8], po), rmse(poses[flags | 8], poses[flags])
+    print(f"far rows ({n_far}), flags {flags}: pose-independent sums vs oracle {e_o:.1e} D, "
+          f"vs per-iteration kernels {e_k:.1e} D (per-iteration vs oracle {rmse(poses[flags], po):.1e} D)")
+    assert e_o <= 1e-4 and rmse(poses[flags], po) <= 1e-4
+    assert e_k <= 1e-6
 
 
 def test_vec_rejects_bad_arguments(sg, ctx):
