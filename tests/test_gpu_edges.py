@@ -171,3 +171,39 @@ def test_tiny_clouds_vector_step_matches_oracle(sg, ctx, flags):
         s_, R_, t_ = sg.pose_to_srt(pg)
         d = O.Pose(s_, R_, t_).apply(pr.tmpl) - po.apply(pr.tmpl)
         assert np.sqrt(np.mean(np.sum(d * d, axis=1))) <= 1e-4 * O.diameter(pr.ref), fl
+
+
+@pytest.mark.parametrize("p", [1.0, 2.0])
+def test_step_beyond_32bit_pair_count_sampled(sg, ctx, p):
+    """2 097 159 template x 2 097 161 reference points (4.4e12 pairs per
+    step, past 32-bit pair counts), curvatures from the GPU (k = 16, shared
+    with the oracle): one step's per-point forces on 128 sampled rows meet
+    the per-point bar, and the wrench equals the FP64 sum of the step's own
+    per-point forces (F = sum f, K = sum f (y - ybar)^T) to 1e-5 of the
+    absolute-sum scales."""
+    M, N = (1 << 21) + 7, (1 << 21) + 9
+    pr = random_pair(M, N, seed=31)
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    a_t, mom_t = ctx.descriptors(tm, 16)
+    a_r, mom_r = ctx.descriptors(rf, 16)
+    eps = 0.0 if p == 1.0 else 0.01
+    prm = O.Params(p=p, k=16, E=100, eps=eps)
+    S = O.make_setup(pr.ref, pr.tmpl, prm, aX=a_r.cpu().numpy().astype(np.float64),
+                     aY=a_t.cpu().numpy().astype(np.float64))
+    t = 3
+    _, wr, f = ctx.step(tm, a_t, rf, a_r, mom_t, mom_r, sg.Params(p=p, k=16, E=100, eps=eps), t,
+                        sg.pose_identity(), want_wrench=True, want_f=True)
+    f = f.cpu().numpy().astype(np.float64)
+    wr = wr.cpu().numpy()
+    rows = np.random.default_rng(2).choice(M, 128, replace=False)
+    G = O.G_schedule(t, 100)
+    Y = pr.tmpl.astype(np.float64)
+    f_o, _, sc = O.forces_c(Y, S, G, rows=rows, want_scale=True)   # the C loops: same definition
+    e = row_error(f[rows], f_o, sc)
+    Yc = Y - Y.mean(axis=0)
+    nf = np.linalg.norm(f, axis=1)
+    e_F = np.linalg.norm(wr[0:3] - f.sum(axis=0)) / nf.sum()
+    e_K = np.linalg.norm(wr[3:12].reshape(3, 3) - f.T @ Yc) / np.sum(nf * np.linalg.norm(Yc, axis=1))
+    print(f"p = {p:g}, {M} x {N}: sampled force error {e:.1e}, wrench vs own forces F {e_F:.1e} K {e_K:.1e}")
+    assert e <= F_TOL
+    assert e_F <= 1e-5 and e_K <= 1e-5
