@@ -451,8 +451,10 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
 // the KC best of their union by KC rounds of a wave-wide minimum (keys are
 // unique, so exactly the lanes holding the minimum pop it, and duplicates of
 // a merged entry are popped together), and every lane continues from the
-// merged list.  The stopping test is grid_knn_kernel's on the merged k-th
-// key, so the neighbour list is the same exact one.
+// merged list (a shell in which no lane took a key leaves every list equal
+// to the merged one, and skips the merge).  The stopping test is
+// grid_knn_kernel's on the merged k-th key, so the neighbour list is the
+// same exact one.
 // Wave `wave` of n_waves takes the far queries wave, wave + n_waves, ...
 template <int KC>
 __device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const int* __restrict__ starts,
@@ -472,17 +474,28 @@ __device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const
     uint64_t L[KC];
 #pragma unroll
     for (int s = 0; s < KC; ++s) L[s] = ~0ull;
+    float kth = key_of(~0ull);  // the k-th key of the merged list (NaN: fewer than k yet)
     for (int r = 0; r <= rmax; ++r) {
       const int side = 2 * r + 1;
+      bool took = false;
       for (int row = lane; row < side * side; row += 64) {
         row_spans(starts, G, c, r, row / side - r, row % side - r, [&](int p0, int p1) {
           span_points(spts, p0, p1, buf, [&](const float4& P) {
             const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
             const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
             const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
-            if (d2 < INFINITY && key < L[KC - 1]) insert_key(L, key);
+            if (d2 < INFINITY && key < L[KC - 1]) {
+              insert_key(L, key);
+              took = true;
+            }
           });
         });
+      }
+      // no lane took a key in this shell: every lane's list is still the
+      // merged list of the last shell, which the merge would return again
+      if (__ballot(took) == 0) {
+        if (shell_done(G, c, qv, r, kth)) break;
+        continue;
       }
       // merge the 64 lists: M collects the successive wave minima in order
       uint64_t M[KC];
@@ -505,7 +518,6 @@ __device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const
         for (int s = 0; s < KC - 1; ++s) M[s] = M[s + 1];
         M[KC - 1] = m;
       }
-      float kth = 0.f;
 #pragma unroll
       for (int s = 0; s < KC; ++s) {
         L[s] = M[s];
