@@ -49,6 +49,18 @@ struct Derived {
   double dprev[3];   // the previous iteration's translation (0 at the start)
 };
 
+// A pointer read from a table in device memory (a batch's job or
+// registration descriptors) is a generic pointer to the compiler: its loads
+// become flat loads, which wait on the LDS counter as well as the memory
+// counter and are not moved past LDS stores, so loads meant to be in flight
+// together are issued one at a time.  gptr(p) rebuilds p from its integer
+// value as a global-memory pointer, so that its uses compile to global loads
+// and stores.  Only for pointers to device (global) memory.
+template <class T>
+__device__ inline T* gptr(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 enum : int32_t {
   ST_NONFINITE = 1,   // non-finite wrench or cross-covariance
   ST_SINGULAR = 2,    // cross-covariance of rank < 2

@@ -148,7 +148,7 @@ __global__ __launch_bounds__(1024) void prepare_batch_kernel(const PrepDesc* __r
   __shared__ double lds[16 * 3];
   __shared__ double red_max[16];
   __shared__ double abar_s;
-  const PrepDesc& g = d[blockIdx.x];
+  const PrepDesc g = prep_at(d, blockIdx.x);
   prepare_body(g.aX, g.wX, g.N, g.aY, g.mY, g.M, g.mom_t, g.mom_r, P, outs + blockIdx.x, lds, red_max, &abar_s);
 }
 
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void pack_tmpl_kernel(const float* __restrict_
 
 __global__ __launch_bounds__(256) void pack_tmpl_batch_kernel(const RegDesc* __restrict__ regs,
                                                               const Derived* __restrict__ dvs) {
-  const RegDesc& g = regs[blockIdx.y];
+  const RegDesc g = reg_at(regs, blockIdx.y);
   for (int ip = blockIdx.x * 256 + threadIdx.x; ip < g.M; ip += gridDim.x * 256)
     pack_tmpl_body(g.y0x, g.y0y, g.y0z, g.aY, g.mY, g.M, g.perm, dvs[blockIdx.y], g.tm4, g.tmx, ip);
 }
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void pack_batch_kernel(const PrepDesc* __restr
                                                          const Derived* __restrict__ dvs, float4* __restrict__ ref4,
                                                          float* __restrict__ lw) {
   const int r = blk2reg[blockIdx.x];
-  const PrepDesc& g = d[r];
+  const PrepDesc g = prep_at(d, r);
   pack_ref_body(g.xx, g.xy, g.xz, g.aX, g.wX, g.N, dvs + r, ref4 + g.ref_off, lw + g.ref_off,
                 (int64_t)(blockIdx.x - g.blk0) * 256 + threadIdx.x);
 }
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(F_BT) void force_batch_kernel(BatchArgs B) {
   __shared__ float s_y[PM == 1 ? 3 * R * F_BT : 1];
   for (int it = blockIdx.x; it < B.n_items; it += gridDim.x) {
     const int4 item = B.items[it];  // (registration, template block, chunk, output slot)
-    const RegDesc& g = B.regs[item.x];
+    const RegDesc g = reg_at(B.regs, item.x);
     ForceArgs A{g.y0x, g.y0y, g.y0z, g.aY, g.mY, B.ref4 + g.ref_off, B.reflw + g.ref_off,
                 B.poses + (int64_t)13 * item.x, B.dvs + item.x, g.M, g.N, B.chunk_len, 0, B.t, 0.0, B.wpart, nullptr,
                 g.perm, g.tm4, g.tmx};

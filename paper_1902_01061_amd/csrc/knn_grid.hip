@@ -15,6 +15,8 @@
 //    of cell assignment and of the key), so no closer point can be missed.
 #include <vector>
 
+#include <utility>
+
 #include "common.h"
 #include "launch.h"
 
@@ -267,18 +269,22 @@ __device__ inline void row_bounds(const int* __restrict__ starts, const GridInfo
   const int cz = c[2] + dz, cy = c[1] + dy;
   if (cz < 0 || cz >= G.dims[2] || cy < 0 || cy >= G.dims[1]) return;
   const int row = (cz * G.dims[1] + cy) * G.dims[0];
-  if (r == 0 || abs(dz) == r || abs(dy) == r) {
-    a0 = starts[row + max(0, c[0] - r)];
-    a1 = starts[row + min(G.dims[0] - 1, c[0] + r) + 1];
-  } else {
-    if (c[0] - r >= 0) {
-      a0 = starts[row + c[0] - r];
-      a1 = starts[row + c[0] - r + 1];
-    }
-    if (c[0] + r < G.dims[0]) {
-      b0 = starts[row + c[0] + r];
-      b1 = starts[row + c[0] + r + 1];
-    }
+  const bool full = r == 0 || abs(dz) == r || abs(dy) == r;
+  // first span: cells [c - r, c + r] of a boundary row (clipped to the
+  // grid), or the cell c - r of an interior row; second span: the cell
+  // c + r of an interior row.  (Each bound is loaded under one condition:
+  // assignments of loaded values to a0..b1 on several paths made the
+  // compiler keep them in scratch memory.)
+  const int xa0 = max(0, c[0] - r);
+  const int xa1 = full ? min(G.dims[0] - 1, c[0] + r) : c[0] - r;
+  if (xa1 >= xa0) {
+    a0 = starts[row + xa0];
+    a1 = starts[row + xa1 + 1];
+  }
+  const int xb = c[0] + r;
+  if (!full && xb < G.dims[0]) {
+    b0 = starts[row + xb];
+    b1 = starts[row + xb + 1];
   }
 }
 
@@ -340,6 +346,109 @@ __device__ inline void insert_key(uint64_t (&L)[KC], uint64_t key) {
   }
 }
 
+// Compare-exchange of two keys into ascending order.
+__device__ inline void cmp_swap(uint64_t& a, uint64_t& b) {
+  const bool sw = b < a;
+  const uint64_t lo = sw ? b : a, hi = sw ? a : b;
+  a = lo;
+  b = hi;
+}
+
+// f(integral_constant<int, I>) for I = 0 .. N-1, expanded at compile time (the
+// networks below index register arrays, which must never be indexed at run
+// time).
+template <class F, int... I>
+__device__ inline void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ inline void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// Sorts a bitonic sequence (ascending, then descending) into ascending order
+// (Batcher's bitonic merger: half-cleaners of width N/2, N/4, ..., 1).
+template <int N, int J = N / 2>
+__device__ inline void bitonic_merge(uint64_t (&v)[N]) {
+  if constexpr (J > 0) {
+    static_for<N>([&](auto i) {
+      if constexpr ((i & J) == 0) cmp_swap(v[i], v[i | J]);
+    });
+    bitonic_merge<N, J / 2>(v);
+  }
+}
+
+// Sorts 8 keys ascending (bitonic sort: merges of width 2, 4, 8 with
+// alternating directions).
+template <int W = 2, int J = 1>
+__device__ inline void bitonic_sort8(uint64_t (&v)[8]) {
+  if constexpr (W <= 8) {
+    static_for<8>([&](auto i) {
+      if constexpr ((i & J) == 0) {
+        if constexpr ((i & W) == 0)
+          cmp_swap(v[i], v[i | J]);
+        else
+          cmp_swap(v[i | J], v[i]);
+      }
+    });
+    if constexpr (J > 1)
+      bitonic_sort8<W, J / 2>(v);
+    else
+      bitonic_sort8<W * 2, W>(v);
+  }
+}
+
+// Merges up to 8 keys cand[0 .. cnt) (the lane's LDS column) into the sorted
+// list L, keeping its KC smallest.  A flush runs in every lane of the wave
+// at once, and with one sorted insertion per key it would cost the largest
+// cnt of the wave times 7 KC operations; the keys instead go through one
+// network: the buffer, padded with all-ones keys, is sorted; with L and the
+// buffer both ascending and padded to a power of two P >= KC, the
+// element-wise minimum of L and the reversed buffer is a bitonic sequence
+// that holds the P smallest keys of the two, and a bitonic merger sorts it.
+// Keys are (key bits, index) words, so the result is the same list as that
+// of the insertions.
+template <int KC>
+__device__ inline void flush_keys(uint64_t (&L)[KC], const uint64_t* cand, int cnt) {
+  uint64_t B[8];
+  static_for<8>([&](auto u) { B[u] = u < cnt ? cand[u * GQ_BT] : ~0ull; });
+  bitonic_sort8(B);
+  if constexpr ((KC & (KC - 1)) == 0) {
+    // P = KC: only the last 8 slots meet a buffered key; merged in place
+    static_for<8>([&](auto u) {
+      const uint64_t b = B[u];
+      L[KC - 1 - u] = b < L[KC - 1 - u] ? b : L[KC - 1 - u];
+    });
+    bitonic_merge<KC>(L);
+  } else {
+    // KC = 24, P = 32: L's padding is all ones, so the sequence is L
+    // followed by the reversed buffer
+    static_assert(KC == 24, "list sizes are 8, 16, 24 or 32");
+    uint64_t D[32];
+    static_for<24>([&](auto i) { D[i] = L[i]; });
+    static_for<8>([&](auto u) { D[24 + u] = B[7 - u]; });
+    bitonic_merge<32>(D);
+    static_for<24>([&](auto i) { L[i] = D[i]; });
+  }
+}
+
+// Order in which a lane visits the rows (dz, dy) of shell r: the rows
+// nearest the query's cell first (by |dz| + |dy|, then max(|dz|, |dy|)), so
+// that the k-th key falls early and fewer later candidates are buffered.  Any
+// order visits the same points before the stopping test.
+__device__ inline void shell_row(int r, int ri, int& dz, int& dy) {
+  if (r == 1) {
+    // (0,0) (0,-1) (0,1) (-1,0) (1,0) (-1,-1) (-1,1) (1,-1) (1,1), as
+    // 2-bit fields of dz + 1 and dy + 1 (no table in memory)
+    dz = ((0x28215 >> (2 * ri)) & 3) - 1;
+    dy = ((0x22161 >> (2 * ri)) & 3) - 1;
+    return;
+  }
+  const int w = 2 * r + 1;
+  dz = ri / w - r;
+  dy = ri % w - r;
+}
+
 // Writes the k neighbour indices of every point (row = original index,
 // sorted by key; -1 where fewer than k finite points exist).  With a far
 // list, a query whose search is not finished after shell rcap (an outlier in
@@ -354,6 +463,7 @@ __device__ inline void insert_key(uint64_t (&L)[KC], uint64_t key) {
 // some lane accepts a candidate at almost every step, and inserting at once
 // would make the wave run the 5 KC-operation insertion at almost every step.
 constexpr int KNN_CB = 8;
+static_assert(KNN_CB == 8, "flush_keys sorts a buffer of 8 keys");
 
 // Query t (a position in the cell-sorted array); buf and cand are the lane's
 // LDS columns (stride GQ_BT).  No barriers.
@@ -389,7 +499,11 @@ __device__ inline void grid_knn_query(const float4* __restrict__ spts, const int
     for (int ri = 0; ri <= nrow; ++ri) {
       const bool end = ri == nrow;
       int a0 = 0, a1 = 1, b0 = 0, b1 = 0;
-      if (!end) row_bounds(starts, G, c, r, ri / w - r, ri % w - r, a0, a1, b0, b1);
+      if (!end) {
+        int dz, dy;
+        shell_row(r, ri, dz, dy);
+        row_bounds(starts, G, c, r, dz, dy, a0, a1, b0, b1);
+      }
 #pragma unroll 1
       for (int h = 0; h < 2; ++h) {
         const int q0 = h ? b0 : a0, q1 = h ? b1 : a1;
@@ -413,8 +527,7 @@ __device__ inline void grid_knn_query(const float4* __restrict__ spts, const int
               }
             }
             if (__any(cnt == KNN_CB || (end && cnt > 0))) {
-#pragma unroll 1
-              for (int e = 0; e < cnt; ++e) insert_key(L, cand[e * GQ_BT]);
+              flush_keys<KC>(L, cand, cnt);
               cnt = 0;
             }
           }
@@ -454,84 +567,89 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
 // merged list (a shell in which no lane took a key leaves every list equal
 // to the merged one, and skips the merge).  The stopping test is
 // grid_knn_kernel's on the merged k-th key, so the neighbour list is the
-// same exact one.
+// same exact one.  This is far query t (a position in the cell-sorted
+// array) of the grid G, searched by the calling wave.
+template <int KC>
+__device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const int* __restrict__ starts,
+                                          const GridInfo& G, int k, int t, int32_t* __restrict__ idx_out,
+                                          float4* buf) {
+  const int lane = threadIdx.x & 63;
+  const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
+  const float4 q = spts[t];
+  const int qi = __float_as_int(q.w);
+  const float qv[3] = {q.x, q.y, q.z};
+  int c[3];
+  for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
+  uint64_t L[KC];
+#pragma unroll
+  for (int s = 0; s < KC; ++s) L[s] = ~0ull;
+  float kth = key_of(~0ull);  // the k-th key of the merged list (NaN: fewer than k yet)
+  for (int r = 0; r <= rmax; ++r) {
+    const int side = 2 * r + 1;
+    bool took = false;
+    for (int row = lane; row < side * side; row += 64) {
+      row_spans(starts, G, c, r, row / side - r, row % side - r, [&](int p0, int p1) {
+        span_points(spts, p0, p1, buf, [&](const float4& P) {
+          const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
+          const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+          const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
+          if (d2 < INFINITY && key < L[KC - 1]) {
+            insert_key(L, key);
+            took = true;
+          }
+        });
+      });
+    }
+    // no lane took a key in this shell: every lane's list is still the
+    // merged list of the last shell, which the merge would return again
+    if (__ballot(took) == 0) {
+      if (shell_done(G, c, qv, r, kth)) break;
+      continue;
+    }
+    // merge the 64 lists: M collects the successive wave minima in order
+    uint64_t M[KC];
+#pragma unroll
+    for (int s = 0; s < KC; ++s) M[s] = ~0ull;
+#pragma unroll 1
+    for (int round = 0; round < KC; ++round) {
+      const uint64_t h = L[0];
+      uint64_t m = h;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(m, off, 64);
+        m = o < m ? o : m;
+      }
+      const bool pop = h == m;
+#pragma unroll
+      for (int s = 0; s < KC - 1; ++s) L[s] = pop ? L[s + 1] : L[s];
+      L[KC - 1] = pop ? ~0ull : L[KC - 1];
+#pragma unroll
+      for (int s = 0; s < KC - 1; ++s) M[s] = M[s + 1];
+      M[KC - 1] = m;
+    }
+#pragma unroll
+    for (int s = 0; s < KC; ++s) {
+      L[s] = M[s];
+      if (s == k - 1) kth = key_of(M[s]);
+    }
+    if (shell_done(G, c, qv, r, kth)) break;
+  }
+  if (lane == 0) {
+    const int64_t o = (int64_t)qi * k;
+#pragma unroll
+    for (int s = 0; s < KC; ++s)
+      if (s < k) idx_out[o + s] = (int32_t)(uint32_t)L[s];
+  }
+}
+
 // Wave `wave` of n_waves takes the far queries wave, wave + n_waves, ...
 template <int KC>
 __device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const int* __restrict__ starts,
                                           const GridInfo* __restrict__ gi, int k, const int* __restrict__ far,
                                           int32_t* __restrict__ idx_out, int wave, int n_waves, float4* buf) {
-  const int lane = threadIdx.x & 63;
   const int cnt = far[0];
   const GridInfo G = *gi;
-  const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
-  for (int f = wave; f < cnt; f += n_waves) {
-    const int t = far[1 + f];
-    const float4 q = spts[t];
-    const int qi = __float_as_int(q.w);
-    const float qv[3] = {q.x, q.y, q.z};
-    int c[3];
-    for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
-    uint64_t L[KC];
-#pragma unroll
-    for (int s = 0; s < KC; ++s) L[s] = ~0ull;
-    float kth = key_of(~0ull);  // the k-th key of the merged list (NaN: fewer than k yet)
-    for (int r = 0; r <= rmax; ++r) {
-      const int side = 2 * r + 1;
-      bool took = false;
-      for (int row = lane; row < side * side; row += 64) {
-        row_spans(starts, G, c, r, row / side - r, row % side - r, [&](int p0, int p1) {
-          span_points(spts, p0, p1, buf, [&](const float4& P) {
-            const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
-            const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
-            const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(P.w);
-            if (d2 < INFINITY && key < L[KC - 1]) {
-              insert_key(L, key);
-              took = true;
-            }
-          });
-        });
-      }
-      // no lane took a key in this shell: every lane's list is still the
-      // merged list of the last shell, which the merge would return again
-      if (__ballot(took) == 0) {
-        if (shell_done(G, c, qv, r, kth)) break;
-        continue;
-      }
-      // merge the 64 lists: M collects the successive wave minima in order
-      uint64_t M[KC];
-#pragma unroll
-      for (int s = 0; s < KC; ++s) M[s] = ~0ull;
-#pragma unroll 1
-      for (int round = 0; round < KC; ++round) {
-        const uint64_t h = L[0];
-        uint64_t m = h;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const uint64_t o = __shfl_xor(m, off, 64);
-          m = o < m ? o : m;
-        }
-        const bool pop = h == m;
-#pragma unroll
-        for (int s = 0; s < KC - 1; ++s) L[s] = pop ? L[s + 1] : L[s];
-        L[KC - 1] = pop ? ~0ull : L[KC - 1];
-#pragma unroll
-        for (int s = 0; s < KC - 1; ++s) M[s] = M[s + 1];
-        M[KC - 1] = m;
-      }
-#pragma unroll
-      for (int s = 0; s < KC; ++s) {
-        L[s] = M[s];
-        if (s == k - 1) kth = key_of(M[s]);
-      }
-      if (shell_done(G, c, qv, r, kth)) break;
-    }
-    if (lane == 0) {
-      const int64_t o = (int64_t)qi * k;
-#pragma unroll
-      for (int s = 0; s < KC; ++s)
-        if (s < k) idx_out[o + s] = (int32_t)(uint32_t)L[s];
-    }
-  }
+  for (int f = wave; f < cnt; f += n_waves) grid_knn_far_query<KC>(spts, starts, G, k, far[1 + f], idx_out, buf);
 }
 
 template <int KC>
@@ -546,24 +664,52 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_far_kernel(const float4* __res
                          (gridDim.x * GQ_BT) >> 6, s_buf + threadIdx.x);
 }
 
-// Curvature from the neighbour lists (FP64 covariance, 1/k, centred).
+// Curvature from the neighbour lists (FP64 covariance, 1/k, centred).  The
+// neighbours are read in groups of CURV_G: the group's indices, then its
+// coordinates, each requested before the first is used, so a pass over k
+// neighbours waits for memory 2 ceil(k / CURV_G) times rather than twice per
+// neighbour.  The sums run over the neighbours in list order.
+constexpr int CURV_G = 8;
+
+template <class F>
+__device__ inline void curv_groups(const float* __restrict__ X, const float* __restrict__ Y,
+                                   const float* __restrict__ Zc, int k, const int32_t* __restrict__ nb, F&& f) {
+#pragma unroll 1
+  for (int s0 = 0; s0 < k; s0 += CURV_G) {
+    int id[CURV_G];
+#pragma unroll
+    for (int u = 0; u < CURV_G; ++u) id[u] = s0 + u < k ? nb[s0 + u] : 0;
+    float px[CURV_G], py[CURV_G], pz[CURV_G];
+#pragma unroll
+    for (int u = 0; u < CURV_G; ++u) {
+      const int j = max(id[u], 0);
+      px[u] = X[j];
+      py[u] = Y[j];
+      pz[u] = Zc[j];
+    }
+#pragma unroll
+    for (int u = 0; u < CURV_G; ++u)
+      if (s0 + u < k) f(id[u], px[u], py[u], pz[u]);
+  }
+}
+
+// Thread t takes the point at position t of the cell-sorted array, so the
+// 64 points of a wave are neighbours in space and mostly share their
+// neighbours, whose coordinates then come from the caches.
 __device__ inline void curvature_point(const float* __restrict__ X, const float* __restrict__ Y,
-                                       const float* __restrict__ Zc, int n, int k, const int32_t* __restrict__ idx,
-                                       float* __restrict__ a_out, int q) {
-  if (q >= n) return;
+                                       const float* __restrict__ Zc, const float4* __restrict__ spts, int n, int k,
+                                       const int32_t* __restrict__ idx, float* __restrict__ a_out, int t) {
+  if (t >= n) return;
+  const int q = __float_as_int(spts[t].w);
   const int32_t* nb = idx + (int64_t)q * k;
   bool missing = false;
   double m[3] = {0, 0, 0};
-  for (int s = 0; s < k; ++s) {
-    const int id = nb[s];
-    if (id < 0) {
-      missing = true;
-      continue;
-    }
-    m[0] += (double)X[id];
-    m[1] += (double)Y[id];
-    m[2] += (double)Zc[id];
-  }
+  curv_groups(X, Y, Zc, k, nb, [&](int id, float x, float y, float z) {
+    missing |= id < 0;
+    m[0] += (double)x;
+    m[1] += (double)y;
+    m[2] += (double)z;
+  });
   if (missing) {
     a_out[q] = NAN;
     return;
@@ -571,16 +717,15 @@ __device__ inline void curvature_point(const float* __restrict__ X, const float*
   const double invk = 1.0 / (double)k;
   for (int a = 0; a < 3; ++a) m[a] *= invk;
   double C[6] = {0, 0, 0, 0, 0, 0};
-  for (int s = 0; s < k; ++s) {
-    const int id = nb[s];
-    const double ex = (double)X[id] - m[0], ey = (double)Y[id] - m[1], ez = (double)Zc[id] - m[2];
+  curv_groups(X, Y, Zc, k, nb, [&](int, float x, float y, float z) {
+    const double ex = (double)x - m[0], ey = (double)y - m[1], ez = (double)z - m[2];
     C[0] += ex * ex;
     C[1] += ey * ey;
     C[2] += ez * ez;
     C[3] += ex * ey;
     C[4] += ex * ez;
     C[5] += ey * ez;
-  }
+  });
   for (int c = 0; c < 6; ++c) C[c] *= invk;
   double lam[3];
   eig_psd3(C, lam);
@@ -589,9 +734,10 @@ __device__ inline void curvature_point(const float* __restrict__ X, const float*
 }
 
 __global__ __launch_bounds__(256) void curvature_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                        const float* __restrict__ Zc, int n, int k,
+                                                        const float* __restrict__ Zc,
+                                                        const float4* __restrict__ spts, int n, int k,
                                                         const int32_t* __restrict__ idx, float* __restrict__ a_out) {
-  curvature_point(X, Y, Zc, n, k, idx, a_out, blockIdx.x * 256 + threadIdx.x);
+  curvature_point(X, Y, Zc, spts, n, k, idx, a_out, blockIdx.x * 256 + threadIdx.x);
 }
 
 int grid_max_cells(int n) {
@@ -697,7 +843,7 @@ hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n
     hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
     hipLaunchKernelGGL(grid_knn_far_kernel<32>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
   }
-  if (a_out) hipLaunchKernelGGL(curvature_kernel, gn, b256, 0, st, x, y, z, n, k, lists, a_out);
+  if (a_out) hipLaunchKernelGGL(curvature_kernel, gn, b256, 0, st, x, y, z, B.spts, n, k, lists, a_out);
   return hipGetLastError();
 }
 
@@ -782,19 +928,28 @@ struct GridJob {
   int* far;
 };
 
+// Job c of the table, with its pointers marked as global memory (gptr).
+__device__ inline GridJob job_at(const GridJob* jobs, int c) {
+  GridJob J = jobs[c];
+  J.x = gptr(J.x), J.y = gptr(J.y), J.z = gptr(J.z), J.a_out = gptr(J.a_out), J.gi = gptr(J.gi);
+  J.cell_of = gptr(J.cell_of), J.counts = gptr(J.counts), J.cursor = gptr(J.cursor), J.starts = gptr(J.starts);
+  J.spts = gptr(J.spts), J.nbr = gptr(J.nbr), J.far = gptr(J.far);
+  return J;
+}
+
 __global__ __launch_bounds__(1024) void grid_setup_batch_kernel(const GridJob* __restrict__ jobs) {
-  const GridJob& J = jobs[blockIdx.x];
+  const GridJob J = job_at(jobs, blockIdx.x);
   grid_setup_body(J.x, J.y, J.z, J.n, J.max_cells, J.gi, J.far);
 }
 
 __global__ __launch_bounds__(1024) void grid_refine_batch_kernel(const GridJob* __restrict__ jobs) {
-  const GridJob& J = jobs[blockIdx.x];
+  const GridJob J = job_at(jobs, blockIdx.x);
   grid_refine_body(J.counts, J.n, J.max_cells, J.gi);
 }
 
 // counts (and, with both, cursor) of every cell set to 0; grid (clouds, splits)
 __global__ __launch_bounds__(1024) void grid_clear_batch_kernel(const GridJob* __restrict__ jobs, int both) {
-  const GridJob& J = jobs[blockIdx.x];
+  const GridJob J = job_at(jobs, blockIdx.x);
   for (int c = blockIdx.y * 1024 + threadIdx.x; c < J.max_cells; c += gridDim.y * 1024) {
     J.counts[c] = 0;
     if (both) J.cursor[c] = 0;
@@ -804,7 +959,7 @@ __global__ __launch_bounds__(1024) void grid_clear_batch_kernel(const GridJob* _
 __global__ __launch_bounds__(256) void grid_count_batch_kernel(const GridJob* __restrict__ jobs,
                                                                const int2* __restrict__ bmap) {
   const int2 cb = bmap[blockIdx.x];
-  const GridJob& J = jobs[cb.x];
+  const GridJob J = job_at(jobs, cb.x);
   grid_count_point(J.x, J.y, J.z, J.n, J.gi, J.cell_of, J.counts, cb.y * 256 + threadIdx.x);
 }
 
@@ -814,7 +969,7 @@ __global__ __launch_bounds__(256) void grid_count_batch_kernel(const GridJob* __
 __global__ __launch_bounds__(1024) void grid_scan_batch_kernel(const GridJob* __restrict__ jobs) {
   __shared__ int s_w[16];
   __shared__ int s_carry;
-  const GridJob& J = jobs[blockIdx.x];
+  const GridJob J = job_at(jobs, blockIdx.x);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
@@ -845,7 +1000,7 @@ __global__ __launch_bounds__(1024) void grid_scan_batch_kernel(const GridJob* __
 __global__ __launch_bounds__(256) void grid_scatter_batch_kernel(const GridJob* __restrict__ jobs,
                                                                  const int2* __restrict__ bmap) {
   const int2 cb = bmap[blockIdx.x];
-  const GridJob& J = jobs[cb.x];
+  const GridJob J = job_at(jobs, cb.x);
   grid_scatter_point(J.x, J.y, J.z, J.n, J.cell_of, J.starts, J.cursor, J.spts, cb.y * 256 + threadIdx.x);
 }
 
@@ -855,26 +1010,98 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_batch_kernel(const GridJob* __
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
   __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
   const int2 cb = bmap[blockIdx.x];
-  const GridJob& J = jobs[cb.x];
+  const GridJob J = job_at(jobs, cb.x);
   grid_knn_query<KC>(J.spts, J.starts, J.gi, J.n, k, KNN_RCAP, J.far, J.nbr, cb.y * GQ_BT + threadIdx.x,
                      s_buf + threadIdx.x, s_cand + threadIdx.x);
 }
 
-// grid (clouds, splits): the far queries of cloud blockIdx.x over its
-// splits x 4 waves
+// The far queries of all clouds from one queue: positions [off[c],
+// off[c + 1]) of the queue are cloud c's far list, with off (fq + 2, n_clouds
+// + 1 entries) the exclusive scan of the far counts, and every wave takes
+// the next position from the counter fq[0] until the queue is empty, so the
+// waves stay busy however the far queries fall on the clouds.  One block:
+// the scan, and the counter set to 0.
+__global__ __launch_bounds__(1024) void far_scan_batch_kernel(const GridJob* __restrict__ jobs, int n_clouds,
+                                                              int* __restrict__ fq) {
+  __shared__ int s_w[16];
+  __shared__ int s_carry;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int* off = fq + 2;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n_clouds; base += 1024) {
+    const int c = base + threadIdx.x;
+    const int v = c < n_clouds ? gptr(jobs[c].far)[0] : 0;
+    int x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int o = __shfl_up(x, d, 64);
+      if (lane >= d) x += o;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int before = s_carry;
+    for (int u = 0; u < w; ++u) before += s_w[u];
+    if (c < n_clouds) off[c] = before + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int u = 0; u < 16; ++u) tot += s_w[u];
+      s_carry += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    off[n_clouds] = s_carry;
+    fq[0] = 0;
+  }
+}
+
+// Cloud of queue position g: the last c with off[c] <= g (a cloud without
+// far queries shares its offset with the next one, so the last such c is
+// the one whose range holds g).  Each round probes 64 evenly spaced offsets
+// of the remaining range; two rounds cover 4 096 clouds.
+__device__ inline int far_cloud_of(const int* __restrict__ off, int n_clouds, int g) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, len = n_clouds;  // off[lo] <= g; lo + len == n_clouds or off[lo + len] > g
+  while (len > 1) {
+    const int step = (len + 63) / 64;
+    const bool le = lane * step < len && off[lo + lane * step] <= g;
+    const int cnt = __popcll(__ballot(le));
+    lo += (cnt - 1) * step;
+    len = min(step, len - (cnt - 1) * step);
+  }
+  return lo;
+}
+
 template <int KC>
-__global__ __launch_bounds__(GQ_BT) void grid_knn_far_batch_kernel(const GridJob* __restrict__ jobs, int k) {
+__global__ __launch_bounds__(GQ_BT) void grid_knn_far_queue_kernel(const GridJob* __restrict__ jobs, int n_clouds,
+                                                                   int* __restrict__ fq, int k) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
-  const GridJob& J = jobs[blockIdx.x];
-  grid_knn_far_waves<KC>(J.spts, J.starts, J.gi, k, J.far, J.nbr, (blockIdx.y * GQ_BT + threadIdx.x) >> 6,
-                         (gridDim.y * GQ_BT) >> 6, s_buf + threadIdx.x);
+  const int lane = threadIdx.x & 63;
+  const int* off = fq + 2;
+  const int total = off[n_clouds];
+  for (;;) {
+    // The wave takes one position: every lane adds (lane 0 adds 1, the
+    // others 0) and the first lane's old value, read as a scalar, is the
+    // position.  No branch on the lane inside the loop: a per-lane
+    // condition that does not change between iterations lets the compiler
+    // split the loop into one copy per set of lanes, run one after the other,
+    // and the copy without the atomic would never see the queue advance.
+    int g = atomicAdd(fq, lane == 0 ? 1 : 0);
+    g = __builtin_amdgcn_readfirstlane(g);
+    if (g >= total) break;
+    const int c = far_cloud_of(off, n_clouds, g);
+    const GridJob J = job_at(jobs, c);
+    const GridInfo G = *J.gi;
+    grid_knn_far_query<KC>(J.spts, J.starts, G, k, J.far[1 + (g - off[c])], J.nbr, s_buf + threadIdx.x);
+  }
 }
 
 __global__ __launch_bounds__(256) void curvature_batch_kernel(const GridJob* __restrict__ jobs,
                                                               const int2* __restrict__ bmap, int k) {
   const int2 cb = bmap[blockIdx.x];
-  const GridJob& J = jobs[cb.x];
-  if (J.a_out) curvature_point(J.x, J.y, J.z, J.n, k, J.nbr, J.a_out, cb.y * 256 + threadIdx.x);
+  const GridJob J = job_at(jobs, cb.x);
+  if (J.a_out) curvature_point(J.x, J.y, J.z, J.spts, J.n, k, J.nbr, J.a_out, cb.y * 256 + threadIdx.x);
 }
 
 size_t grid_knn_batch_workspace(const int* n, int n_clouds, int k) {
@@ -885,6 +1112,7 @@ size_t grid_knn_batch_workspace(const int* n, int n_clouds, int k) {
     blocks += (n[c] + 255) / 256;
   }
   b += ((sizeof(GridJob) * (size_t)n_clouds + 255) & ~size_t(255)) + ((sizeof(int2) * (size_t)blocks + 255) & ~size_t(255));
+  b += (sizeof(int) * ((size_t)n_clouds + 3) + 255) & ~size_t(255);  // far queue: counter, pad, offsets
   return b;
 }
 
@@ -906,6 +1134,8 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
   GridJob* d_jobs = (GridJob*)p;
   p += (sizeof(GridJob) * (size_t)n_clouds + 255) & ~size_t(255);
   int2* d_bmap = (int2*)p;
+  p += (sizeof(int2) * bmap.size() + 255) & ~size_t(255);
+  int* d_fq = (int*)p;
   hipError_t e = hipMemcpyAsync(d_jobs, jobs.data(), sizeof(GridJob) * jobs.size(), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(d_bmap, bmap.data(), sizeof(int2) * bmap.size(), hipMemcpyHostToDevice, st);
@@ -922,19 +1152,25 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
   hipLaunchKernelGGL(grid_count_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
   hipLaunchKernelGGL(grid_scan_batch_kernel, gc, dim3(1024), 0, st, d_jobs);
   hipLaunchKernelGGL(grid_scatter_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
-  const dim3 gf((unsigned)n_clouds, 16);
+  // far pass: a persistent grid of waves over the queue of all clouds' far
+  // queries (4 waves per block)
+  const dim3 gf(1024);
   if (k <= 8) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<8>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(grid_knn_far_batch_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
+    hipLaunchKernelGGL(grid_knn_far_queue_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   } else if (k <= 16) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<16>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(grid_knn_far_batch_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
+    hipLaunchKernelGGL(grid_knn_far_queue_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   } else if (k <= 24) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<24>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(grid_knn_far_batch_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
+    hipLaunchKernelGGL(grid_knn_far_queue_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   } else {
     hipLaunchKernelGGL(grid_knn_batch_kernel<32>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(grid_knn_far_batch_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
+    hipLaunchKernelGGL(grid_knn_far_queue_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   }
   hipLaunchKernelGGL(curvature_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap, k);
   return hipGetLastError();

@@ -89,6 +89,22 @@ struct RegDesc {
   float2* tmx;          // [M]
 };
 
+// A batch descriptor read on the device, with its pointers marked as
+// global memory (gptr).
+__device__ inline PrepDesc prep_at(const PrepDesc* d, int r) {
+  PrepDesc g = d[r];
+  g.xx = gptr(g.xx), g.xy = gptr(g.xy), g.xz = gptr(g.xz), g.aX = gptr(g.aX), g.wX = gptr(g.wX);
+  g.aY = gptr(g.aY), g.mY = gptr(g.mY), g.mom_t = gptr(g.mom_t), g.mom_r = gptr(g.mom_r);
+  return g;
+}
+
+__device__ inline RegDesc reg_at(const RegDesc* d, int r) {
+  RegDesc g = d[r];
+  g.y0x = gptr(g.y0x), g.y0y = gptr(g.y0y), g.y0z = gptr(g.y0z), g.aY = gptr(g.aY), g.mY = gptr(g.mY);
+  g.perm = gptr(g.perm), g.tm4 = gptr(g.tm4), g.tmx = gptr(g.tmx);
+  return g;
+}
+
 struct BatchArgs {
   const RegDesc* regs;
   const int4* items;    // (registration, template block, chunk, wrench slot)

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(PS_BT) void psum_batch_kernel(const RegDesc* __rest
   __shared__ float4 s_x[PS_BT];
   __shared__ float s_l[PS_BT], s_q[PS_BT];
   const int2 rb = tblk[blockIdx.x];
-  const RegDesc& g = regs[rb.x];
+  const RegDesc g = reg_at(regs, rb.x);
   const int ip = rb.y * PS_BT + threadIdx.x;
   const float bi = ip < g.M ? g.tm4[ip].w : 0.f;
   double t[PS_NQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(PS_BT) void pinv_batch_kernel(const RegDesc* __rest
                                                            double* __restrict__ wpart) {
   __shared__ double s_red[(PS_BT / 64) * 13];
   const int2 rb = tblk[blockIdx.x];
-  const RegDesc& g = regs[rb.x];
+  const RegDesc g = reg_at(regs, rb.x);
   double w[13];
 #pragma unroll
   for (int e = 0; e < 13; ++e) w[e] = 0.0;

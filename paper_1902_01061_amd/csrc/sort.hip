@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void seg_gather_kernel(const RegDesc* __restri
                                                          int* __restrict__ idx) {
   const int r = blockIdx.y;
   const int M = regs[r].M;
-  const float* __restrict__ a = regs[r].aY;
+  const float* __restrict__ a = gptr(regs[r].aY);
   const int o = off[r];
   for (int i = blockIdx.x * 256 + threadIdx.x; i < M; i += gridDim.x * 256) {
     keys[o + i] = a[i];
