@@ -215,22 +215,26 @@ __global__ __launch_bounds__(SCAN_B) void scan_add_kernel(int* __restrict__ out,
   if (blockIdx.x == 0 && threadIdx.x == 0) out[m] = bsum[nb];
 }
 
+// Also packs the point, in its own order, as p4[i] = (x, y, z, 0): one
+// 16-byte load per neighbour for the curvature instead of three.
 __device__ inline void grid_scatter_point(const float* __restrict__ X, const float* __restrict__ Y,
                                           const float* __restrict__ Zc, int n, const int* __restrict__ cell_of,
                                           const int* __restrict__ starts, int* __restrict__ cursor,
-                                          float4* __restrict__ spts, int i) {
+                                          float4* __restrict__ spts, float4* __restrict__ p4, int i) {
   if (i >= n) return;
   const int c = cell_of[i];
   const int pos = starts[c] + atomicAdd(&cursor[c], 1);
-  spts[pos] = make_float4(X[i], Y[i], Zc[i], __int_as_float(i));
+  const float x = X[i], y = Y[i], z = Zc[i];
+  spts[pos] = make_float4(x, y, z, __int_as_float(i));
+  p4[i] = make_float4(x, y, z, 0.f);
 }
 
 __global__ __launch_bounds__(256) void grid_scatter_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                            const float* __restrict__ Zc, int n,
                                                            const int* __restrict__ cell_of,
                                                            const int* __restrict__ starts, int* __restrict__ cursor,
-                                                           float4* __restrict__ spts) {
-  grid_scatter_point(X, Y, Zc, n, cell_of, starts, cursor, spts, blockIdx.x * 256 + threadIdx.x);
+                                                           float4* __restrict__ spts, float4* __restrict__ p4) {
+  grid_scatter_point(X, Y, Zc, n, cell_of, starts, cursor, spts, p4, blockIdx.x * 256 + threadIdx.x);
 }
 
 __device__ inline bool key_less(float d, int i, float bd, int bi) { return d < bd || (d == bd && i < bi); }
@@ -664,80 +668,106 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_far_kernel(const float4* __res
                          (gridDim.x * GQ_BT) >> 6, s_buf + threadIdx.x);
 }
 
-// Curvature from the neighbour lists (FP64 covariance, 1/k, centred).  The
-// neighbours are read in groups of CURV_G: the group's indices, then its
-// coordinates, each requested before the first is used, so a pass over k
-// neighbours waits for memory 2 ceil(k / CURV_G) times rather than twice per
-// neighbour.  The sums run over the neighbours in list order.
+// Curvature from the neighbour lists (FP64 covariance, 1/k, centred), one
+// block of CURV_BT points.  A point's list is k consecutive indices, so with
+// one point per thread every load instruction of a wave would touch 64
+// different rows; the block's rows (contiguous in memory) are therefore
+// copied into LDS with coalesced loads first, at an odd row stride so that
+// the threads' reads of their own rows meet no bank conflict.  The
+// neighbours' packed coordinates (p4) are then read in groups of CURV_G, each
+// group's loads all requested before the first is used, in one pass: the
+// sums are taken of the offsets from the list's first point (the query
+// itself unless duplicates come first), C = S2 / k - (S1 / k)(S1 / k)^T,
+// which is the centred covariance for any shift and, with a shift inside the
+// neighbourhood, keeps the FP64 cancellation at the rounding of the offsets.
+constexpr int CURV_BT = 256;
 constexpr int CURV_G = 8;
 
-template <class F>
-__device__ inline void curv_groups(const float* __restrict__ X, const float* __restrict__ Y,
-                                   const float* __restrict__ Zc, int k, const int32_t* __restrict__ nb, F&& f) {
+__device__ inline int curv_stride(int k) { return k | 1; }
+
+// Points [b CURV_BT, min(n, (b + 1) CURV_BT)); lds holds CURV_BT rows of
+// curv_stride(k) ints.  Every thread reaches the barrier.
+__device__ inline void curvature_block(const float4* __restrict__ p4, int n, int k, const int32_t* __restrict__ idx,
+                                       float* __restrict__ a_out, int b, int* lds) {
+  const int p0 = b * CURV_BT;
+  const int cnt = min(CURV_BT, n - p0);
+  const int st = curv_stride(k);
+  {
+    // element e = threadIdx.x + CURV_BT i of the block's cnt k indices is
+    // column c of row r; (r, c) advance by (CURV_BT / k, CURV_BT % k)
+    const int32_t* src = idx + (int64_t)p0 * k;
+    const int dr = CURV_BT / k, dc = CURV_BT % k;
+    int r = threadIdx.x / k, c = threadIdx.x % k;
+#pragma unroll 4
+    for (int e = threadIdx.x; e < cnt * k; e += CURV_BT) {
+      lds[r * st + c] = src[e];
+      r += dr;
+      c += dc;
+      if (c >= k) {
+        c -= k;
+        ++r;
+      }
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t >= cnt) return;
+  const int q = p0 + t;
+  const int* nb = lds + t * st;
+  bool missing = false;
+  double sh[3] = {0, 0, 0}, S1[3] = {0, 0, 0}, S2[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll 1
   for (int s0 = 0; s0 < k; s0 += CURV_G) {
     int id[CURV_G];
 #pragma unroll
     for (int u = 0; u < CURV_G; ++u) id[u] = s0 + u < k ? nb[s0 + u] : 0;
-    float px[CURV_G], py[CURV_G], pz[CURV_G];
+    float4 P[CURV_G];
 #pragma unroll
-    for (int u = 0; u < CURV_G; ++u) {
-      const int j = max(id[u], 0);
-      px[u] = X[j];
-      py[u] = Y[j];
-      pz[u] = Zc[j];
+    for (int u = 0; u < CURV_G; ++u) P[u] = p4[max(id[u], 0)];
+    if (s0 == 0) {
+      sh[0] = (double)P[0].x;
+      sh[1] = (double)P[0].y;
+      sh[2] = (double)P[0].z;
     }
 #pragma unroll
-    for (int u = 0; u < CURV_G; ++u)
-      if (s0 + u < k) f(id[u], px[u], py[u], pz[u]);
+    for (int u = 0; u < CURV_G; ++u) {
+      if (s0 + u < k) {
+        missing |= id[u] < 0;
+        const double dx = (double)P[u].x - sh[0], dy = (double)P[u].y - sh[1], dz = (double)P[u].z - sh[2];
+        S1[0] += dx;
+        S1[1] += dy;
+        S1[2] += dz;
+        S2[0] += dx * dx;
+        S2[1] += dy * dy;
+        S2[2] += dz * dz;
+        S2[3] += dx * dy;
+        S2[4] += dx * dz;
+        S2[5] += dy * dz;
+      }
+    }
   }
-}
-
-// Thread t takes the point at position t of the cell-sorted array, so the
-// 64 points of a wave are neighbours in space and mostly share their
-// neighbours, whose coordinates then come from the caches.
-__device__ inline void curvature_point(const float* __restrict__ X, const float* __restrict__ Y,
-                                       const float* __restrict__ Zc, const float4* __restrict__ spts, int n, int k,
-                                       const int32_t* __restrict__ idx, float* __restrict__ a_out, int t) {
-  if (t >= n) return;
-  const int q = __float_as_int(spts[t].w);
-  const int32_t* nb = idx + (int64_t)q * k;
-  bool missing = false;
-  double m[3] = {0, 0, 0};
-  curv_groups(X, Y, Zc, k, nb, [&](int id, float x, float y, float z) {
-    missing |= id < 0;
-    m[0] += (double)x;
-    m[1] += (double)y;
-    m[2] += (double)z;
-  });
   if (missing) {
     a_out[q] = NAN;
     return;
   }
   const double invk = 1.0 / (double)k;
-  for (int a = 0; a < 3; ++a) m[a] *= invk;
-  double C[6] = {0, 0, 0, 0, 0, 0};
-  curv_groups(X, Y, Zc, k, nb, [&](int, float x, float y, float z) {
-    const double ex = (double)x - m[0], ey = (double)y - m[1], ez = (double)z - m[2];
-    C[0] += ex * ex;
-    C[1] += ey * ey;
-    C[2] += ez * ez;
-    C[3] += ex * ey;
-    C[4] += ex * ez;
-    C[5] += ey * ez;
-  });
-  for (int c = 0; c < 6; ++c) C[c] *= invk;
+  const double mx = S1[0] * invk, my = S1[1] * invk, mz = S1[2] * invk;
+  const double C[6] = {S2[0] * invk - mx * mx, S2[1] * invk - my * my, S2[2] * invk - mz * mz,
+                       S2[3] * invk - mx * my, S2[4] * invk - mx * mz, S2[5] * invk - my * mz};
   double lam[3];
   eig_psd3(C, lam);
   const double tr = C[0] + C[1] + C[2];
   a_out[q] = (tr > 0.0) ? (float)(lam[2] / tr) : 0.f;
 }
 
-__global__ __launch_bounds__(256) void curvature_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                        const float* __restrict__ Zc,
-                                                        const float4* __restrict__ spts, int n, int k,
-                                                        const int32_t* __restrict__ idx, float* __restrict__ a_out) {
-  curvature_point(X, Y, Zc, spts, n, k, idx, a_out, blockIdx.x * 256 + threadIdx.x);
+// Dynamic LDS of the curvature kernels: CURV_BT rows of curv_stride(k) ints.
+inline size_t curv_lds_bytes(int k) { return sizeof(int) * (size_t)CURV_BT * (size_t)(k | 1); }
+
+__global__ __launch_bounds__(CURV_BT) void curvature_kernel(const float4* __restrict__ p4, int n, int k,
+                                                            const int32_t* __restrict__ idx,
+                                                            float* __restrict__ a_out) {
+  extern __shared__ int s_nb[];
+  curvature_block(p4, n, k, idx, a_out, blockIdx.x, s_nb);
 }
 
 int grid_max_cells(int n) {
@@ -758,6 +788,7 @@ size_t grid_knn_workspace(int n, int k) {
   add(sizeof(int) * ((size_t)max_cells + 1));  // starts
   add(sizeof(int) * ((size_t)nb + 1));     // block sums
   add(sizeof(float4) * (size_t)n);         // sorted points
+  add(sizeof(float4) * (size_t)n);         // packed points
   add(sizeof(int32_t) * (size_t)n * k);    // neighbour lists
   add(sizeof(int) * ((size_t)n + 1));      // far-query list
   return b;
@@ -773,6 +804,7 @@ struct GridBufs {
   int* starts;
   int* bsum;
   float4* spts;
+  float4* p4;  // the points in their own order, (x, y, z, 0)
   int32_t* nbr;
   int* far;  // [0]: count, [1..n]: sorted positions of the queries left to the wave-per-query pass
 };
@@ -794,6 +826,7 @@ GridBufs carve_grid(void* ws, int n, int k) {
   B.starts = (int*)take(sizeof(int) * ((size_t)max_cells + 1));
   B.bsum = (int*)take(sizeof(int) * ((size_t)nb + 1));
   B.spts = (float4*)take(sizeof(float4) * (size_t)n);
+  B.p4 = (float4*)take(sizeof(float4) * (size_t)n);
   B.nbr = (int32_t*)take(sizeof(int32_t) * (size_t)n * k);
   B.far = (int*)take(sizeof(int) * ((size_t)n + 1));
   return B;
@@ -814,7 +847,8 @@ hipError_t build_grid(const float* x, const float* y, const float* z, int n, con
   hipLaunchKernelGGL(scan_local_kernel, dim3(nb), dim3(SCAN_B), 0, st, B.counts, max_cells, B.starts, B.bsum);
   hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(64), 0, st, B.bsum, nb);
   hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(SCAN_B), 0, st, B.starts, max_cells, B.bsum, nb);
-  hipLaunchKernelGGL(grid_scatter_kernel, gn, b256, 0, st, x, y, z, n, B.cell_of, B.starts, B.cursor, B.spts);
+  hipLaunchKernelGGL(grid_scatter_kernel, gn, b256, 0, st, x, y, z, n, B.cell_of, B.starts, B.cursor, B.spts,
+                     B.p4);
   return hipGetLastError();
 }
 
@@ -843,7 +877,8 @@ hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n
     hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
     hipLaunchKernelGGL(grid_knn_far_kernel<32>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
   }
-  if (a_out) hipLaunchKernelGGL(curvature_kernel, gn, b256, 0, st, x, y, z, B.spts, n, k, lists, a_out);
+  if (a_out)
+    hipLaunchKernelGGL(curvature_kernel, gn, dim3(CURV_BT), curv_lds_bytes(k), st, B.p4, n, k, lists, a_out);
   return hipGetLastError();
 }
 
@@ -924,6 +959,7 @@ struct GridJob {
   int* cursor;
   int* starts;
   float4* spts;
+  float4* p4;
   int32_t* nbr;
   int* far;
 };
@@ -933,7 +969,7 @@ __device__ inline GridJob job_at(const GridJob* jobs, int c) {
   GridJob J = jobs[c];
   J.x = gptr(J.x), J.y = gptr(J.y), J.z = gptr(J.z), J.a_out = gptr(J.a_out), J.gi = gptr(J.gi);
   J.cell_of = gptr(J.cell_of), J.counts = gptr(J.counts), J.cursor = gptr(J.cursor), J.starts = gptr(J.starts);
-  J.spts = gptr(J.spts), J.nbr = gptr(J.nbr), J.far = gptr(J.far);
+  J.spts = gptr(J.spts), J.p4 = gptr(J.p4), J.nbr = gptr(J.nbr), J.far = gptr(J.far);
   return J;
 }
 
@@ -1001,7 +1037,7 @@ __global__ __launch_bounds__(256) void grid_scatter_batch_kernel(const GridJob* 
                                                                  const int2* __restrict__ bmap) {
   const int2 cb = bmap[blockIdx.x];
   const GridJob J = job_at(jobs, cb.x);
-  grid_scatter_point(J.x, J.y, J.z, J.n, J.cell_of, J.starts, J.cursor, J.spts, cb.y * 256 + threadIdx.x);
+  grid_scatter_point(J.x, J.y, J.z, J.n, J.cell_of, J.starts, J.cursor, J.spts, J.p4, cb.y * 256 + threadIdx.x);
 }
 
 template <int KC>
@@ -1097,11 +1133,15 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_far_queue_kernel(const GridJob
   }
 }
 
-__global__ __launch_bounds__(256) void curvature_batch_kernel(const GridJob* __restrict__ jobs,
-                                                              const int2* __restrict__ bmap, int k) {
+// Block (cloud, block) of the list: CURV_BT points of one cloud, as
+// curvature_kernel.
+static_assert(CURV_BT == 256, "the (cloud, block) list counts blocks of 256 points");
+__global__ __launch_bounds__(CURV_BT) void curvature_batch_kernel(const GridJob* __restrict__ jobs,
+                                                                  const int2* __restrict__ bmap, int k) {
+  extern __shared__ int s_nb[];
   const int2 cb = bmap[blockIdx.x];
   const GridJob J = job_at(jobs, cb.x);
-  if (J.a_out) curvature_point(J.x, J.y, J.z, J.spts, J.n, k, J.nbr, J.a_out, cb.y * 256 + threadIdx.x);
+  if (J.a_out) curvature_block(J.p4, J.n, k, J.nbr, J.a_out, cb.y, s_nb);
 }
 
 size_t grid_knn_batch_workspace(const int* n, int n_clouds, int k) {
@@ -1128,7 +1168,7 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
     p += grid_knn_workspace(n[c], k);
     int32_t* lists = (idx_out && idx_out[c]) ? idx_out[c] : B.nbr;
     jobs[c] = GridJob{x[c], y[c], z[c], a_out ? a_out[c] : nullptr, n[c], grid_max_cells(n[c]), B.gi, B.cell_of,
-                      B.counts, B.cursor, B.starts, B.spts, lists, B.far};
+                      B.counts, B.cursor, B.starts, B.spts, B.p4, lists, B.far};
     for (int b = 0; b < (n[c] + 255) / 256; ++b) bmap.push_back(make_int2(c, b));
   }
   GridJob* d_jobs = (GridJob*)p;
@@ -1172,7 +1212,7 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
     hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
     hipLaunchKernelGGL(grid_knn_far_queue_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   }
-  hipLaunchKernelGGL(curvature_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap, k);
+  hipLaunchKernelGGL(curvature_batch_kernel, gb, dim3(CURV_BT), curv_lds_bytes(k), st, d_jobs, d_bmap, k);
   return hipGetLastError();
 }
 
