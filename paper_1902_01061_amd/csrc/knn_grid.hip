@@ -470,11 +470,14 @@ constexpr int KNN_CB = 8;
 static_assert(KNN_CB == 8, "flush_keys sorts a buffer of 8 keys");
 
 // Query t (a position in the cell-sorted array); buf and cand are the lane's
-// LDS columns (stride GQ_BT).  No barriers.
+// LDS columns (stride GQ_BT).  No barriers.  The search starts at shell r0:
+// with r0 > 0 it resumes a query handed over after shell r0 - 1, whose list
+// of the k best of shells 0 .. r0 - 1 is in its output row (see below).
 template <int KC>
-__device__ inline void grid_knn_query(const float4* __restrict__ spts, const int* __restrict__ starts,
-                                      const GridInfo* __restrict__ gi, int n, int k, int rcap, int* __restrict__ far,
-                                      int32_t* __restrict__ idx_out, int t, float4* buf, uint64_t* cand) {
+__device__ inline void grid_knn_query(const float4* __restrict__ spts, const float4* __restrict__ p4,
+                                      const int* __restrict__ starts, const GridInfo* __restrict__ gi, int n, int k,
+                                      int rcap, int* __restrict__ far, int32_t* __restrict__ idx_out, int t,
+                                      float4* buf, uint64_t* cand, int r0) {
   if (t >= n) return;
   const GridInfo G = *gi;
   const float4 q = spts[t];
@@ -492,9 +495,26 @@ __device__ inline void grid_knn_query(const float4* __restrict__ spts, const int
   uint64_t L[KC];
 #pragma unroll
   for (int s = 0; s < KC; ++s) L[s] = (s < KC - k) ? 0ull : ~0ull;
+  if (r0 > 0) {
+    // the row's indices in key order (-1: empty); their keys are rebuilt
+    // from the packed points with the same float32 arithmetic
+    const int64_t o = (int64_t)qi * k;
+#pragma unroll
+    for (int s = 0; s < KC; ++s) {
+      if (s >= KC - k) {
+        const int id = idx_out[o + (s - (KC - k))];
+        if (id >= 0) {
+          const float4 P = p4[id];
+          const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
+          const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+          L[s] = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)id;
+        }
+      }
+    }
+  }
   int cnt = 0;  // buffered candidates of this lane
   const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
-  for (int r = 0; r <= rmax; ++r) {
+  for (int r = r0; r <= rmax; ++r) {
     // the rows of shell r (see row_spans), then one end row that visits no
     // point and empties the buffers through the same insertion code, so that
     // this code exists once
@@ -539,9 +559,11 @@ __device__ inline void grid_knn_query(const float4* __restrict__ spts, const int
       }
     }
     if (shell_done(G, c, qv, r, key_of(L[KC - 1]))) break;
+    // handed to the far pass, which continues from shell rcap + 1 with the
+    // list written below (the k best of the shells searched here)
     if (far && r >= rcap) {
       far[1 + atomicAdd(far, 1)] = t;
-      return;
+      break;
     }
   }
   // static slot indices only (a runtime index would put L in scratch memory)
@@ -557,8 +579,8 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
                                                          int* __restrict__ far, int32_t* __restrict__ idx_out) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
   __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
-  grid_knn_query<KC>(spts, starts, gi, n, k, rcap, far, idx_out, blockIdx.x * GQ_BT + threadIdx.x,
-                     s_buf + threadIdx.x, s_cand + threadIdx.x);
+  grid_knn_query<KC>(spts, nullptr, starts, gi, n, k, rcap, far, idx_out, blockIdx.x * GQ_BT + threadIdx.x,
+                     s_buf + threadIdx.x, s_cand + threadIdx.x, 0);
 }
 
 // The queries grid_knn_kernel left unfinished, one wave per query (a
@@ -574,9 +596,9 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
 // same exact one.  This is far query t (a position in the cell-sorted
 // array) of the grid G, searched by the calling wave.
 template <int KC>
-__device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const int* __restrict__ starts,
-                                          const GridInfo& G, int k, int t, int32_t* __restrict__ idx_out,
-                                          float4* buf) {
+__device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const float4* __restrict__ p4,
+                                          const int* __restrict__ starts, const GridInfo& G, int k, int t,
+                                          int32_t* __restrict__ idx_out, float4* buf) {
   const int lane = threadIdx.x & 63;
   const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
   const float4 q = spts[t];
@@ -584,11 +606,32 @@ __device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const
   const float qv[3] = {q.x, q.y, q.z};
   int c[3];
   for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
+  // The one-lane pass searched shells 0 .. KNN_RCAP and left the k best of
+  // them in the query's output row (index -1 for an empty slot): lane s < k
+  // rebuilds entry s's key from the packed points (the same float32
+  // arithmetic as the key was made with), and every lane starts from that
+  // list, as after a merge.  Slots k .. KC-1 start empty; they never hold
+  // one of the k best.
   uint64_t L[KC];
+  {
+    uint64_t mine = ~0ull;
+    if (lane < k) {
+      const int id = idx_out[(int64_t)qi * k + lane];
+      if (id >= 0) {
+        const float4 P = p4[id];
+        const float ex = __fsub_rn(P.x, q.x), ey = __fsub_rn(P.y, q.y), ez = __fsub_rn(P.z, q.z);
+        const float d2 = __fadd_rn(__fadd_rn(__fmul_rn(ex, ex), __fmul_rn(ey, ey)), __fmul_rn(ez, ez));
+        mine = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)id;
+      }
+    }
 #pragma unroll
-  for (int s = 0; s < KC; ++s) L[s] = ~0ull;
+    for (int s = 0; s < KC; ++s) L[s] = s < k ? __shfl(mine, s, 64) : ~0ull;
+  }
   float kth = key_of(~0ull);  // the k-th key of the merged list (NaN: fewer than k yet)
-  for (int r = 0; r <= rmax; ++r) {
+#pragma unroll
+  for (int s = 0; s < KC; ++s)
+    if (s == k - 1) kth = key_of(L[s]);
+  for (int r = KNN_RCAP + 1; r <= rmax; ++r) {
     const int side = 2 * r + 1;
     bool took = false;
     for (int row = lane; row < side * side; row += 64) {
@@ -648,23 +691,25 @@ __device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const
 
 // Wave `wave` of n_waves takes the far queries wave, wave + n_waves, ...
 template <int KC>
-__device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const int* __restrict__ starts,
+__device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const float4* __restrict__ p4,
+                                          const int* __restrict__ starts,
                                           const GridInfo* __restrict__ gi, int k, const int* __restrict__ far,
                                           int32_t* __restrict__ idx_out, int wave, int n_waves, float4* buf) {
   const int cnt = far[0];
   const GridInfo G = *gi;
-  for (int f = wave; f < cnt; f += n_waves) grid_knn_far_query<KC>(spts, starts, G, k, far[1 + f], idx_out, buf);
+  for (int f = wave; f < cnt; f += n_waves)
+    grid_knn_far_query<KC>(spts, p4, starts, G, k, far[1 + f], idx_out, buf);
 }
 
 template <int KC>
 __global__ __launch_bounds__(GQ_BT) void grid_knn_far_kernel(const float4* __restrict__ spts,
+                                                             const float4* __restrict__ p4,
                                                              const int* __restrict__ starts,
-                                                             const GridInfo* __restrict__ gi, int n, int k,
+                                                             const GridInfo* __restrict__ gi, int k,
                                                              const int* __restrict__ far,
                                                              int32_t* __restrict__ idx_out) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
-  (void)n;
-  grid_knn_far_waves<KC>(spts, starts, gi, k, far, idx_out, (blockIdx.x * GQ_BT + threadIdx.x) >> 6,
+  grid_knn_far_waves<KC>(spts, p4, starts, gi, k, far, idx_out, (blockIdx.x * GQ_BT + threadIdx.x) >> 6,
                          (gridDim.x * GQ_BT) >> 6, s_buf + threadIdx.x);
 }
 
@@ -866,16 +911,16 @@ hipError_t launch_grid_knn(const float* x, const float* y, const float* z, int n
   const dim3 gf(512);
   if (k <= 8) {
     hipLaunchKernelGGL(grid_knn_kernel<8>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
-    hipLaunchKernelGGL(grid_knn_far_kernel<8>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<8>, gf, bq, 0, st, B.spts, B.p4, B.starts, B.gi, k, B.far, lists);
   } else if (k <= 16) {
     hipLaunchKernelGGL(grid_knn_kernel<16>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
-    hipLaunchKernelGGL(grid_knn_far_kernel<16>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<16>, gf, bq, 0, st, B.spts, B.p4, B.starts, B.gi, k, B.far, lists);
   } else if (k <= 24) {
     hipLaunchKernelGGL(grid_knn_kernel<24>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
-    hipLaunchKernelGGL(grid_knn_far_kernel<24>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<24>, gf, bq, 0, st, B.spts, B.p4, B.starts, B.gi, k, B.far, lists);
   } else {
     hipLaunchKernelGGL(grid_knn_kernel<32>, gq, bq, 0, st, B.spts, B.starts, B.gi, n, k, KNN_RCAP, B.far, lists);
-    hipLaunchKernelGGL(grid_knn_far_kernel<32>, gf, bq, 0, st, B.spts, B.starts, B.gi, n, k, B.far, lists);
+    hipLaunchKernelGGL(grid_knn_far_kernel<32>, gf, bq, 0, st, B.spts, B.p4, B.starts, B.gi, k, B.far, lists);
   }
   if (a_out)
     hipLaunchKernelGGL(curvature_kernel, gn, dim3(CURV_BT), curv_lds_bytes(k), st, B.p4, n, k, lists, a_out);
@@ -1047,16 +1092,13 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_batch_kernel(const GridJob* __
   __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
   const int2 cb = bmap[blockIdx.x];
   const GridJob J = job_at(jobs, cb.x);
-  grid_knn_query<KC>(J.spts, J.starts, J.gi, J.n, k, KNN_RCAP, J.far, J.nbr, cb.y * GQ_BT + threadIdx.x,
-                     s_buf + threadIdx.x, s_cand + threadIdx.x);
+  grid_knn_query<KC>(J.spts, nullptr, J.starts, J.gi, J.n, k, KNN_RCAP, J.far, J.nbr, cb.y * GQ_BT + threadIdx.x,
+                     s_buf + threadIdx.x, s_cand + threadIdx.x, 0);
 }
 
-// The far queries of all clouds from one queue: positions [off[c],
-// off[c + 1]) of the queue are cloud c's far list, with off (fq + 2, n_clouds
-// + 1 entries) the exclusive scan of the far counts, and every wave takes
-// the next position from the counter fq[0] until the queue is empty, so the
-// waves stay busy however the far queries fall on the clouds.  One block:
-// the scan, and the counter set to 0.
+// The far queries of all clouds as one list: positions [off[c], off[c + 1])
+// are cloud c's far list, with off (fq + 2, n_clouds + 1 entries) the
+// exclusive scan of the far counts.  One block.
 __global__ __launch_bounds__(1024) void far_scan_batch_kernel(const GridJob* __restrict__ jobs, int n_clouds,
                                                               int* __restrict__ fq) {
   __shared__ int s_w[16];
@@ -1086,50 +1128,42 @@ __global__ __launch_bounds__(1024) void far_scan_batch_kernel(const GridJob* __r
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    off[n_clouds] = s_carry;
-    fq[0] = 0;
-  }
+  if (threadIdx.x == 0) off[n_clouds] = s_carry;
 }
 
-// Cloud of queue position g: the last c with off[c] <= g (a cloud without
+// Cloud of far-list position g: the last c with off[c] <= g (a cloud without
 // far queries shares its offset with the next one, so the last such c is
-// the one whose range holds g).  Each round probes 64 evenly spaced offsets
-// of the remaining range; two rounds cover 4 096 clouds.
+// the one whose range holds g), by bisection (off[n_clouds] = total > g).
 __device__ inline int far_cloud_of(const int* __restrict__ off, int n_clouds, int g) {
-  const int lane = threadIdx.x & 63;
-  int lo = 0, len = n_clouds;  // off[lo] <= g; lo + len == n_clouds or off[lo + len] > g
-  while (len > 1) {
-    const int step = (len + 63) / 64;
-    const bool le = lane * step < len && off[lo + lane * step] <= g;
-    const int cnt = __popcll(__ballot(le));
-    lo += (cnt - 1) * step;
-    len = min(step, len - (cnt - 1) * step);
+  int lo = 0, hi = n_clouds;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
   }
   return lo;
 }
 
+// The far queries of all clouds, one lane each: lane g of the grid takes
+// positions g, g + grid size, ... of the concatenated far lists and resumes
+// the one-lane search from shell KNN_RCAP + 1.  (A lane per query suits the
+// batch's many far queries, whose searches cost about the same; the
+// one-cloud pass keeps a wave per query, which finishes a few of them
+// sooner.)
 template <int KC>
-__global__ __launch_bounds__(GQ_BT) void grid_knn_far_queue_kernel(const GridJob* __restrict__ jobs, int n_clouds,
-                                                                   int* __restrict__ fq, int k) {
+__global__ __launch_bounds__(GQ_BT) void grid_knn_far_lanes_kernel(const GridJob* __restrict__ jobs, int n_clouds,
+                                                                   const int* __restrict__ fq, int k) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
-  const int lane = threadIdx.x & 63;
+  __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
   const int* off = fq + 2;
   const int total = off[n_clouds];
-  for (;;) {
-    // The wave takes one position: every lane adds (lane 0 adds 1, the
-    // others 0) and the first lane's old value, read as a scalar, is the
-    // position.  No branch on the lane inside the loop: a per-lane
-    // condition that does not change between iterations lets the compiler
-    // split the loop into one copy per set of lanes, run one after the other,
-    // and the copy without the atomic would never see the queue advance.
-    int g = atomicAdd(fq, lane == 0 ? 1 : 0);
-    g = __builtin_amdgcn_readfirstlane(g);
-    if (g >= total) break;
+  for (int g = blockIdx.x * GQ_BT + threadIdx.x; g < total; g += gridDim.x * GQ_BT) {
     const int c = far_cloud_of(off, n_clouds, g);
     const GridJob J = job_at(jobs, c);
-    const GridInfo G = *J.gi;
-    grid_knn_far_query<KC>(J.spts, J.starts, G, k, J.far[1 + (g - off[c])], J.nbr, s_buf + threadIdx.x);
+    grid_knn_query<KC>(J.spts, J.p4, J.starts, J.gi, J.n, k, 0, nullptr, J.nbr, J.far[1 + (g - off[c])],
+                       s_buf + threadIdx.x, s_cand + threadIdx.x, KNN_RCAP + 1);
   }
 }
 
@@ -1152,7 +1186,7 @@ size_t grid_knn_batch_workspace(const int* n, int n_clouds, int k) {
     blocks += (n[c] + 255) / 256;
   }
   b += ((sizeof(GridJob) * (size_t)n_clouds + 255) & ~size_t(255)) + ((sizeof(int2) * (size_t)blocks + 255) & ~size_t(255));
-  b += (sizeof(int) * ((size_t)n_clouds + 3) + 255) & ~size_t(255);  // far queue: counter, pad, offsets
+  b += (sizeof(int) * ((size_t)n_clouds + 3) + 255) & ~size_t(255);  // far list offsets (at + 2)
   return b;
 }
 
@@ -1192,25 +1226,24 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
   hipLaunchKernelGGL(grid_count_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
   hipLaunchKernelGGL(grid_scan_batch_kernel, gc, dim3(1024), 0, st, d_jobs);
   hipLaunchKernelGGL(grid_scatter_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
-  // far pass: a persistent grid of waves over the queue of all clouds' far
-  // queries (4 waves per block)
-  const dim3 gf(1024);
+  // far pass: a grid of lanes over the list of all clouds' far queries
+  const dim3 gf(512);
   if (k <= 8) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<8>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
     hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_queue_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   } else if (k <= 16) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<16>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
     hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_queue_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   } else if (k <= 24) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<24>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
     hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_queue_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   } else {
     hipLaunchKernelGGL(grid_knn_batch_kernel<32>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
     hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_queue_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
   }
   hipLaunchKernelGGL(curvature_batch_kernel, gb, dim3(CURV_BT), curv_lds_bytes(k), st, d_jobs, d_bmap, k);
   return hipGetLastError();
