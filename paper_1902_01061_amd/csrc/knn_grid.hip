@@ -49,15 +49,20 @@ __device__ inline void grid_dims(GridInfo& G, double h, int max_cells) {
 }
 
 constexpr int GQ_BT = 256;
-constexpr int KNN_RCAP = 2;  // shells a lane searches alone before handing its query to a wave
+constexpr int KNN_RCAP = 1;  // shells a lane searches alone before handing its query to a wave
 constexpr int SCAN_B = 1024;
 
 // Bodies of the grid kernels, shared by the one-cloud kernels and their
 // batched forms (a table of clouds, one launch per phase for all of them).
 __device__ inline void grid_setup_body(const float* __restrict__ X, const float* __restrict__ Y,
                                        const float* __restrict__ Zc, int n, int max_cells, GridInfo* __restrict__ gi,
-                                       int* __restrict__ far) {
-  if (threadIdx.x == 0) far[0] = 0;  // count of queries handed to the wave-per-query pass
+                                       int* __restrict__ far, int* __restrict__ far2) {
+  // counts of the queries handed over by the one-lane pass (far) and, in a
+  // batch, by the pass that resumes them for one more shell (far2)
+  if (threadIdx.x == 0) {
+    far[0] = 0;
+    if (far2) far2[0] = 0;
+  }
   __shared__ float red[16][6];
   float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
   for (int i = threadIdx.x; i < n; i += 1024) {
@@ -114,7 +119,7 @@ __device__ inline void grid_setup_body(const float* __restrict__ X, const float*
 __global__ __launch_bounds__(1024) void grid_setup_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                           const float* __restrict__ Zc, int n, int max_cells,
                                                           GridInfo* __restrict__ gi, int* __restrict__ far) {
-  grid_setup_body(X, Y, Zc, n, max_cells, gi, far);
+  grid_setup_body(X, Y, Zc, n, max_cells, gi, far, nullptr);
 }
 
 // Second look at the cell size, from the first count: scans are surfaces
@@ -836,6 +841,7 @@ size_t grid_knn_workspace(int n, int k) {
   add(sizeof(float4) * (size_t)n);         // packed points
   add(sizeof(int32_t) * (size_t)n * k);    // neighbour lists
   add(sizeof(int) * ((size_t)n + 1));      // far-query list
+  add(sizeof(int) * ((size_t)n + 1));      // second far-query list (batches)
   return b;
 }
 
@@ -851,7 +857,8 @@ struct GridBufs {
   float4* spts;
   float4* p4;  // the points in their own order, (x, y, z, 0)
   int32_t* nbr;
-  int* far;  // [0]: count, [1..n]: sorted positions of the queries left to the wave-per-query pass
+  int* far;  // [0]: count, [1..n]: sorted positions of the queries left to the far pass
+  int* far2;  // the same for the batch's second hand-over
 };
 
 GridBufs carve_grid(void* ws, int n, int k) {
@@ -874,6 +881,7 @@ GridBufs carve_grid(void* ws, int n, int k) {
   B.p4 = (float4*)take(sizeof(float4) * (size_t)n);
   B.nbr = (int32_t*)take(sizeof(int32_t) * (size_t)n * k);
   B.far = (int*)take(sizeof(int) * ((size_t)n + 1));
+  B.far2 = (int*)take(sizeof(int) * ((size_t)n + 1));
   return B;
 }
 
@@ -1007,6 +1015,7 @@ struct GridJob {
   float4* p4;
   int32_t* nbr;
   int* far;
+  int* far2;
 };
 
 // Job c of the table, with its pointers marked as global memory (gptr).
@@ -1014,13 +1023,13 @@ __device__ inline GridJob job_at(const GridJob* jobs, int c) {
   GridJob J = jobs[c];
   J.x = gptr(J.x), J.y = gptr(J.y), J.z = gptr(J.z), J.a_out = gptr(J.a_out), J.gi = gptr(J.gi);
   J.cell_of = gptr(J.cell_of), J.counts = gptr(J.counts), J.cursor = gptr(J.cursor), J.starts = gptr(J.starts);
-  J.spts = gptr(J.spts), J.p4 = gptr(J.p4), J.nbr = gptr(J.nbr), J.far = gptr(J.far);
+  J.spts = gptr(J.spts), J.p4 = gptr(J.p4), J.nbr = gptr(J.nbr), J.far = gptr(J.far), J.far2 = gptr(J.far2);
   return J;
 }
 
 __global__ __launch_bounds__(1024) void grid_setup_batch_kernel(const GridJob* __restrict__ jobs) {
   const GridJob J = job_at(jobs, blockIdx.x);
-  grid_setup_body(J.x, J.y, J.z, J.n, J.max_cells, J.gi, J.far);
+  grid_setup_body(J.x, J.y, J.z, J.n, J.max_cells, J.gi, J.far, J.far2);
 }
 
 __global__ __launch_bounds__(1024) void grid_refine_batch_kernel(const GridJob* __restrict__ jobs) {
@@ -1097,10 +1106,10 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_batch_kernel(const GridJob* __
 }
 
 // The far queries of all clouds as one list: positions [off[c], off[c + 1])
-// are cloud c's far list, with off (fq + 2, n_clouds + 1 entries) the
-// exclusive scan of the far counts.  One block.
+// are cloud c's far list (far, or far2 with `second`), with off (fq + 2,
+// n_clouds + 1 entries) the exclusive scan of their counts.  One block.
 __global__ __launch_bounds__(1024) void far_scan_batch_kernel(const GridJob* __restrict__ jobs, int n_clouds,
-                                                              int* __restrict__ fq) {
+                                                              int* __restrict__ fq, int second) {
   __shared__ int s_w[16];
   __shared__ int s_carry;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1109,7 +1118,7 @@ __global__ __launch_bounds__(1024) void far_scan_batch_kernel(const GridJob* __r
   __syncthreads();
   for (int base = 0; base < n_clouds; base += 1024) {
     const int c = base + threadIdx.x;
-    const int v = c < n_clouds ? gptr(jobs[c].far)[0] : 0;
+    const int v = c < n_clouds ? gptr(second ? jobs[c].far2 : jobs[c].far)[0] : 0;
     int x = v;
     for (int d = 1; d < 64; d <<= 1) {
       const int o = __shfl_up(x, d, 64);
@@ -1146,15 +1155,18 @@ __device__ inline int far_cloud_of(const int* __restrict__ off, int n_clouds, in
   return lo;
 }
 
-// The far queries of all clouds, one lane each: lane g of the grid takes
-// positions g, g + grid size, ... of the concatenated far lists and resumes
-// the one-lane search from shell KNN_RCAP + 1.  (A lane per query suits the
-// batch's many far queries, whose searches cost about the same; the
-// one-cloud pass keeps a wave per query, which finishes a few of them
-// sooner.)
+// The handed-over queries of all clouds, one lane each: lane g of the grid
+// takes positions g, g + grid size, ... of the concatenated lists (far, or
+// far2 with `second`) and resumes the one-lane search at shell r0.  With
+// `handover` a query not finished after shell r0 is handed over again, to
+// far2, so that the few deep searches do not hold up waves of queries that
+// need one shell more.  (A lane per query suits the batch's many handed-over
+// queries; the one-cloud pass keeps a wave per query, which finishes a few
+// of them sooner.)
 template <int KC>
 __global__ __launch_bounds__(GQ_BT) void grid_knn_far_lanes_kernel(const GridJob* __restrict__ jobs, int n_clouds,
-                                                                   const int* __restrict__ fq, int k) {
+                                                                   const int* __restrict__ fq, int k, int second,
+                                                                   int r0, int handover) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
   __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
   const int* off = fq + 2;
@@ -1162,8 +1174,9 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_far_lanes_kernel(const GridJob
   for (int g = blockIdx.x * GQ_BT + threadIdx.x; g < total; g += gridDim.x * GQ_BT) {
     const int c = far_cloud_of(off, n_clouds, g);
     const GridJob J = job_at(jobs, c);
-    grid_knn_query<KC>(J.spts, J.p4, J.starts, J.gi, J.n, k, 0, nullptr, J.nbr, J.far[1 + (g - off[c])],
-                       s_buf + threadIdx.x, s_cand + threadIdx.x, KNN_RCAP + 1);
+    const int* list = second ? J.far2 : J.far;
+    grid_knn_query<KC>(J.spts, J.p4, J.starts, J.gi, J.n, k, r0, handover ? J.far2 : nullptr, J.nbr,
+                       list[1 + (g - off[c])], s_buf + threadIdx.x, s_cand + threadIdx.x, r0);
   }
 }
 
@@ -1202,7 +1215,7 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
     p += grid_knn_workspace(n[c], k);
     int32_t* lists = (idx_out && idx_out[c]) ? idx_out[c] : B.nbr;
     jobs[c] = GridJob{x[c], y[c], z[c], a_out ? a_out[c] : nullptr, n[c], grid_max_cells(n[c]), B.gi, B.cell_of,
-                      B.counts, B.cursor, B.starts, B.spts, B.p4, lists, B.far};
+                      B.counts, B.cursor, B.starts, B.spts, B.p4, lists, B.far, B.far2};
     for (int b = 0; b < (n[c] + 255) / 256; ++b) bmap.push_back(make_int2(c, b));
   }
   GridJob* d_jobs = (GridJob*)p;
@@ -1226,24 +1239,41 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
   hipLaunchKernelGGL(grid_count_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
   hipLaunchKernelGGL(grid_scan_batch_kernel, gc, dim3(1024), 0, st, d_jobs);
   hipLaunchKernelGGL(grid_scatter_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
-  // far pass: a grid of lanes over the list of all clouds' far queries
+  // the handed-over queries: a grid of lanes over the list of all clouds'
+  // far queries, for shell KNN_RCAP + 1, then over those still open
   const dim3 gf(512);
   if (k <= 8) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<8>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
+                       KNN_RCAP + 1, 1);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
+                       KNN_RCAP + 2, 0);
   } else if (k <= 16) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<16>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
+                       KNN_RCAP + 1, 1);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
+                       KNN_RCAP + 2, 0);
   } else if (k <= 24) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<24>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
+                       KNN_RCAP + 1, 1);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
+                       KNN_RCAP + 2, 0);
   } else {
     hipLaunchKernelGGL(grid_knn_batch_kernel<32>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
+                       KNN_RCAP + 1, 1);
+    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
+    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
+                       KNN_RCAP + 2, 0);
   }
   hipLaunchKernelGGL(curvature_batch_kernel, gb, dim3(CURV_BT), curv_lds_bytes(k), st, d_jobs, d_bmap, k);
   return hipGetLastError();
