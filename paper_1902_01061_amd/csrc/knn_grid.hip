@@ -603,7 +603,7 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_kernel(const float4* __restric
 template <int KC>
 __device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const float4* __restrict__ p4,
                                           const int* __restrict__ starts, const GridInfo& G, int k, int t,
-                                          int32_t* __restrict__ idx_out, float4* buf) {
+                                          int32_t* __restrict__ idx_out, float4* buf, int r0) {
   const int lane = threadIdx.x & 63;
   const int rmax = max(G.dims[0], max(G.dims[1], G.dims[2]));
   const float4 q = spts[t];
@@ -611,7 +611,7 @@ __device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const
   const float qv[3] = {q.x, q.y, q.z};
   int c[3];
   for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);
-  // The one-lane pass searched shells 0 .. KNN_RCAP and left the k best of
+  // The lane passes searched shells 0 .. r0 - 1 and left the k best of
   // them in the query's output row (index -1 for an empty slot): lane s < k
   // rebuilds entry s's key from the packed points (the same float32
   // arithmetic as the key was made with), and every lane starts from that
@@ -636,7 +636,7 @@ __device__ inline void grid_knn_far_query(const float4* __restrict__ spts, const
 #pragma unroll
   for (int s = 0; s < KC; ++s)
     if (s == k - 1) kth = key_of(L[s]);
-  for (int r = KNN_RCAP + 1; r <= rmax; ++r) {
+  for (int r = r0; r <= rmax; ++r) {
     const int side = 2 * r + 1;
     bool took = false;
     for (int row = lane; row < side * side; row += 64) {
@@ -703,7 +703,7 @@ __device__ inline void grid_knn_far_waves(const float4* __restrict__ spts, const
   const int cnt = far[0];
   const GridInfo G = *gi;
   for (int f = wave; f < cnt; f += n_waves)
-    grid_knn_far_query<KC>(spts, p4, starts, G, k, far[1 + f], idx_out, buf);
+    grid_knn_far_query<KC>(spts, p4, starts, G, k, far[1 + f], idx_out, buf, KNN_RCAP + 1);
 }
 
 template <int KC>
@@ -1156,17 +1156,15 @@ __device__ inline int far_cloud_of(const int* __restrict__ off, int n_clouds, in
 }
 
 // The handed-over queries of all clouds, one lane each: lane g of the grid
-// takes positions g, g + grid size, ... of the concatenated lists (far, or
-// far2 with `second`) and resumes the one-lane search at shell r0.  With
-// `handover` a query not finished after shell r0 is handed over again, to
-// far2, so that the few deep searches do not hold up waves of queries that
-// need one shell more.  (A lane per query suits the batch's many handed-over
+// takes positions g, g + grid size, ... of the concatenated lists (far) and
+// resumes the one-lane search at shell r0; a query not finished after shell
+// r0 is handed over again, to far2, so that the few deep searches do not
+// hold up waves of queries that need one shell more.  (A lane per query suits the batch's many handed-over
 // queries; the one-cloud pass keeps a wave per query, which finishes a few
 // of them sooner.)
 template <int KC>
 __global__ __launch_bounds__(GQ_BT) void grid_knn_far_lanes_kernel(const GridJob* __restrict__ jobs, int n_clouds,
-                                                                   const int* __restrict__ fq, int k, int second,
-                                                                   int r0, int handover) {
+                                                                   const int* __restrict__ fq, int k, int r0) {
   __shared__ float4 s_buf[SPAN_U * GQ_BT];
   __shared__ uint64_t s_cand[KNN_CB * GQ_BT];
   const int* off = fq + 2;
@@ -1174,9 +1172,28 @@ __global__ __launch_bounds__(GQ_BT) void grid_knn_far_lanes_kernel(const GridJob
   for (int g = blockIdx.x * GQ_BT + threadIdx.x; g < total; g += gridDim.x * GQ_BT) {
     const int c = far_cloud_of(off, n_clouds, g);
     const GridJob J = job_at(jobs, c);
-    const int* list = second ? J.far2 : J.far;
-    grid_knn_query<KC>(J.spts, J.p4, J.starts, J.gi, J.n, k, r0, handover ? J.far2 : nullptr, J.nbr,
-                       list[1 + (g - off[c])], s_buf + threadIdx.x, s_cand + threadIdx.x, r0);
+    grid_knn_query<KC>(J.spts, J.p4, J.starts, J.gi, J.n, k, r0, J.far2, J.nbr, J.far[1 + (g - off[c])],
+                       s_buf + threadIdx.x, s_cand + threadIdx.x, r0);
+  }
+}
+
+// The queries still open after the lane pass, one wave each (deep searches,
+// which one lane would take long over): wave w of the grid takes positions
+// w, w + number of waves, ... of the concatenated lists (far2), resuming at
+// shell r0.
+template <int KC>
+__global__ __launch_bounds__(GQ_BT) void grid_knn_far_waves_batch_kernel(const GridJob* __restrict__ jobs,
+                                                                         int n_clouds, const int* __restrict__ fq,
+                                                                         int k, int r0) {
+  __shared__ float4 s_buf[SPAN_U * GQ_BT];
+  const int* off = fq + 2;
+  const int total = off[n_clouds];
+  const int n_waves = (gridDim.x * GQ_BT) >> 6;
+  for (int g = (blockIdx.x * GQ_BT + threadIdx.x) >> 6; g < total; g += n_waves) {
+    const int c = far_cloud_of(off, n_clouds, g);
+    const GridJob J = job_at(jobs, c);
+    const GridInfo G = *J.gi;
+    grid_knn_far_query<KC>(J.spts, J.p4, J.starts, G, k, J.far2[1 + (g - off[c])], J.nbr, s_buf + threadIdx.x, r0);
   }
 }
 
@@ -1189,6 +1206,21 @@ __global__ __launch_bounds__(CURV_BT) void curvature_batch_kernel(const GridJob*
   const int2 cb = bmap[blockIdx.x];
   const GridJob J = job_at(jobs, cb.x);
   if (J.a_out) curvature_block(J.p4, J.n, k, J.nbr, J.a_out, cb.y, s_nb);
+}
+
+// The handed-over queries of a batch: shell KNN_RCAP + 1 with a lane per
+// query (far -> far2), then those still open with a wave per query.  The lane
+// pass gets more blocks than fit at once, so that every CU holds as many
+// waves as its LDS allows while the list lasts.  (Measured on the 512 clouds
+// of the batch workload: a wave per query for all of them took 1.5 times as
+// long, a lane per query for the deeper shells as well 1.2 to 2 times.)
+template <class LanesK, class WavesK>
+void far_passes(LanesK lanes, WavesK waves, const GridJob* d_jobs, int n_clouds, int* d_fq, int k, hipStream_t st) {
+  const dim3 gl(2048), gw(1024), bt(GQ_BT);
+  hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
+  hipLaunchKernelGGL(lanes, gl, bt, 0, st, d_jobs, n_clouds, (const int*)d_fq, k, KNN_RCAP + 1);
+  hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
+  hipLaunchKernelGGL(waves, gw, bt, 0, st, d_jobs, n_clouds, (const int*)d_fq, k, KNN_RCAP + 2);
 }
 
 size_t grid_knn_batch_workspace(const int* n, int n_clouds, int k) {
@@ -1239,41 +1271,19 @@ hipError_t launch_grid_knn_batch(const float* const* x, const float* const* y, c
   hipLaunchKernelGGL(grid_count_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
   hipLaunchKernelGGL(grid_scan_batch_kernel, gc, dim3(1024), 0, st, d_jobs);
   hipLaunchKernelGGL(grid_scatter_batch_kernel, gb, dim3(256), 0, st, d_jobs, d_bmap);
-  // the handed-over queries: a grid of lanes over the list of all clouds'
-  // far queries, for shell KNN_RCAP + 1, then over those still open
-  const dim3 gf(512);
+
   if (k <= 8) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<8>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
-                       KNN_RCAP + 1, 1);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<8>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
-                       KNN_RCAP + 2, 0);
+    far_passes(grid_knn_far_lanes_kernel<8>, grid_knn_far_waves_batch_kernel<8>, d_jobs, n_clouds, d_fq, k, st);
   } else if (k <= 16) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<16>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
-                       KNN_RCAP + 1, 1);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<16>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
-                       KNN_RCAP + 2, 0);
+    far_passes(grid_knn_far_lanes_kernel<16>, grid_knn_far_waves_batch_kernel<16>, d_jobs, n_clouds, d_fq, k, st);
   } else if (k <= 24) {
     hipLaunchKernelGGL(grid_knn_batch_kernel<24>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
-                       KNN_RCAP + 1, 1);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<24>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
-                       KNN_RCAP + 2, 0);
+    far_passes(grid_knn_far_lanes_kernel<24>, grid_knn_far_waves_batch_kernel<24>, d_jobs, n_clouds, d_fq, k, st);
   } else {
     hipLaunchKernelGGL(grid_knn_batch_kernel<32>, gb, dim3(GQ_BT), 0, st, d_jobs, d_bmap, k);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 0);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 0,
-                       KNN_RCAP + 1, 1);
-    hipLaunchKernelGGL(far_scan_batch_kernel, dim3(1), dim3(1024), 0, st, d_jobs, n_clouds, d_fq, 1);
-    hipLaunchKernelGGL(grid_knn_far_lanes_kernel<32>, gf, dim3(GQ_BT), 0, st, d_jobs, n_clouds, d_fq, k, 1,
-                       KNN_RCAP + 2, 0);
+    far_passes(grid_knn_far_lanes_kernel<32>, grid_knn_far_waves_batch_kernel<32>, d_jobs, n_clouds, d_fq, k, st);
   }
   hipLaunchKernelGGL(curvature_batch_kernel, gb, dim3(CURV_BT), curv_lds_bytes(k), st, d_jobs, d_bmap, k);
   return hipGetLastError();
