@@ -177,8 +177,11 @@ class Context:
         """Curvatures (and neighbour lists) of many clouds in one call:
         ([a_c float32 [n_c]], [idx_c int32 [n_c, k]] or None)."""
         B = len(clouds)
-        a = [torch.empty(c.n, dtype=torch.float32, device=self.device) for c in clouds]
-        idx = [torch.empty((c.n, k), dtype=torch.int32, device=self.device) for c in clouds] if want_idx else None
+        sizes = [c.n for c in clouds]
+        # one allocation each, handed out as per-cloud views
+        a = list(torch.empty(sum(sizes), dtype=torch.float32, device=self.device).split(sizes))
+        idx = (list(torch.empty((sum(sizes), k), dtype=torch.int32, device=self.device).split(sizes))
+               if want_idx else None)
         cc = (SgrCloud * B)(*[c.c() for c in clouds])
         pa = (ctypes.c_void_p * B)(*[t.data_ptr() for t in a])
         pi = (ctypes.c_void_p * B)(*[t.data_ptr() for t in idx]) if want_idx else None
