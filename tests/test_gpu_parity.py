@@ -391,3 +391,28 @@ def test_knn_adversarial_inputs_match_bruteforce(sg, ctx, k):
         idx = ctx.knn(sg.Cloud(P), k).cpu().numpy()
         ref_idx = O.knn_c(P, k)
         assert (idx == ref_idx).all(), name
+
+
+@pytest.mark.parametrize("k", [8, 24])
+def test_batch_knn_adversarial_inputs_match_bruteforce(sg, ctx, k):
+    """The same clouds in one batched call (sgr_descriptors_batch), with two
+    more that send queries through every hand-over of the batched search:
+    two dense clusters 400 cluster widths apart with a sparse halo (queries
+    open after shell 1, after shell 2, and deep ones), and a cloud with
+    nothing to hand over placed between them in the list.  Lists bit-exact
+    against brute force, curvatures to float32 rounding."""
+    rng = np.random.default_rng(23)
+    clouds = [P for _, P in _adversarial_clouds()]
+    two = np.concatenate([rng.normal(size=(1500, 3)) * 0.01, rng.normal(size=(1500, 3)) * 0.01 + [4.0, 0.0, 0.0],
+                          rng.uniform([-1, -1, -1], [5, 1, 1], size=(300, 3))]).astype(np.float32)
+    clouds.insert(2, two)
+    clouds.insert(3, np.stack(np.meshgrid(np.arange(9), np.arange(9), np.arange(9)), -1).reshape(-1, 3)
+                  .astype(np.float32) * 0.5)
+    a, idx = ctx.descriptors_batch([sg.Cloud(P) for P in clouds], k, want_idx=True)
+    torch.cuda.synchronize()
+    for c, P in enumerate(clouds):
+        ref_idx = O.knn_c(P, k)
+        got = idx[c].cpu().numpy()
+        assert np.array_equal(got, ref_idx), c
+        np.testing.assert_allclose(a[c].cpu().numpy(), O.surface_variation(P, ref_idx).astype(np.float32),
+                                   rtol=2e-6, atol=1e-9, err_msg=str(c))
