@@ -250,8 +250,12 @@ __device__ inline bool key_less(float d, int i, float bd, int bi) { return d < b
 // lane therefore issues SPAN_U independent loads, parks the points in its own
 // LDS column (buf[u * GQ_BT], no other lane touches it, no barrier) and then
 // processes them in a rolled loop, which keeps the per-candidate code (the
-// top-k insertion) in one copy.
-constexpr int SPAN_U = 8;
+// top-k insertion) in one copy.  Six loads: with the 8-key candidate column
+// a 256-thread block then needs 40 KB of LDS, so four blocks (four waves
+// per SIMD, which the registers also allow) fit on a CU; with eight loads
+// only three fit, and the batched search took 16 % longer (measured on the
+// 512 clouds of the batch workload; four loads: 3 % longer).
+constexpr int SPAN_U = 6;
 
 template <class F>
 __device__ inline void span_points(const float4* __restrict__ spts, int p0, int p1, float4* buf, F&& f) {
