@@ -65,8 +65,11 @@ __device__ inline void grid_setup_body(const float* __restrict__ X, const float*
   }
   __shared__ float red[16][6];
   float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  // the bounding box of the finite points (an infinite coordinate would
+  // make the box infinite and the grid one row of cells)
   for (int i = threadIdx.x; i < n; i += 1024) {
     const float p[3] = {X[i], Y[i], Zc[i]};
+    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) continue;
     for (int a = 0; a < 3; ++a) {
       v[a] = fminf(v[a], p[a]);
       v[3 + a] = fmaxf(v[3 + a], p[a]);
@@ -87,8 +90,9 @@ __device__ inline void grid_setup_body(const float* __restrict__ X, const float*
   GridInfo G;
   double e[3];
   for (int a = 0; a < 3; ++a) {
-    G.lo[a] = red[0][a];
-    e[a] = (double)red[0][3 + a] - (double)red[0][a];
+    const bool any = red[0][a] <= red[0][3 + a];  // some finite point
+    G.lo[a] = any ? red[0][a] : 0.f;
+    e[a] = any ? (double)red[0][3 + a] - (double)red[0][a] : 0.0;
   }
   // cell size for about two points per cell of the bounding volume; flat or
   // linear clouds fall back to their non-degenerate extents
@@ -491,6 +495,12 @@ __device__ inline void grid_knn_query(const float4* __restrict__ spts, const flo
   const GridInfo G = *gi;
   const float4 q = spts[t];
   const int qi = __float_as_int(q.w);
+  // a query with a non-finite coordinate has no finite key to any point:
+  // its list is empty (and searching for one would visit every shell)
+  if (!(isfinite(q.x) && isfinite(q.y) && isfinite(q.z))) {
+    for (int s = 0; s < k; ++s) idx_out[(int64_t)qi * k + s] = -1;
+    return;
+  }
   const float qv[3] = {q.x, q.y, q.z};
   int c[3];
   for (int a = 0; a < 3; ++a) c[a] = cell_coord(qv[a], G.lo[a], G.h, G.dims[a]);

@@ -165,3 +165,38 @@ def test_batch_descriptors_match_oracle_and_single_clouds(sg, ctx):
         i1 = ctx.knn(cls[c], 16)
         a1, _ = ctx.descriptors(cls[c], 16)
         assert torch.equal(i1, idx[c]) and torch.equal(a1, a[c]), c
+
+
+def test_batch_descriptors_small_and_nonfinite_clouds_equal_single(sg, ctx):
+    """Clouds of exactly k and k + 1 points, and one with non-finite
+    coordinates (a NaN and an infinite point, which are nobody's neighbour
+    and have no finite neighbour: their lists are -1, their curvature NaN,
+    and they do not enter the grid's box), between ordinary clouds, through
+    the batched grid search: lists and curvatures equal the one-cloud
+    search's, bit for bit (NaN where it gives NaN)."""
+    rng = np.random.default_rng(31)
+    k = 8
+    bad = rng.normal(size=(400, 3)).astype(np.float32)
+    bad[5] = [np.nan, 0.0, 0.0]
+    bad[17] = [0.0, np.inf, 0.0]
+    clouds = [rng.normal(size=(2000, 3)).astype(np.float32), rng.normal(size=(k, 3)).astype(np.float32),
+              rng.normal(size=(k + 1, 3)).astype(np.float32), bad, rng.uniform(-1, 1, size=(3000, 3)).astype(np.float32)]
+    cls = [sg.Cloud(P) for P in clouds]
+    a, idx = ctx.descriptors_batch(cls, k, want_idx=True)
+    torch.cuda.synchronize()
+    for c, cl in enumerate(cls):
+        i1 = ctx.knn(cl, k)
+        a1, _ = ctx.descriptors(cl, k)
+        assert torch.equal(i1, idx[c]), c
+        assert torch.equal(torch.isnan(a1), torch.isnan(a[c])), c
+        ok = ~torch.isnan(a1)
+        assert torch.equal(a1[ok], a[c][ok]), c
+    for c in (1, 2):  # every point's list is the whole cloud, or all but its farthest point
+        assert np.array_equal(idx[c].cpu().numpy(), O.knn_c(clouds[c], k)), c
+    got = idx[3].cpu().numpy()
+    assert (got[5] == -1).all() and (got[17] == -1).all() and torch.isnan(a[3][5]) and torch.isnan(a[3][17])
+    # the finite points' lists are brute force over the finite points
+    # (renumbering by the order-preserving map f keeps the index tie-break)
+    fin = np.isfinite(bad).all(axis=1)
+    f = np.flatnonzero(fin)
+    assert np.array_equal(got[fin], f[O.knn_c(bad[fin], k)])
