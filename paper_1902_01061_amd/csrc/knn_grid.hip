@@ -3,8 +3,9 @@
 // every operation rounded, ties by index), followed by the same FP64
 // neighbourhood covariance and curvature (Sec. III-A).
 //
-// 1. grid_setup: bounding box and a cell size h with about two points per
-//    cell of the bounding volume (fewer cells than the allocated maximum);
+// 1. grid_setup: bounding box of the finite points and a cell size h with
+//    about two points per cell of the bounding volume (fewer cells than the
+//    allocated maximum), shrunk for surfaces after a first count;
 // 2. counting sort of the points by cell (cell counts, exclusive scan,
 //    scatter); the order inside a cell does not matter because candidates
 //    are ranked by the (distance, index) key;
@@ -12,10 +13,12 @@
 //    cells): shells of cells at Chebyshev radius 0, 1, 2, ... are scanned
 //    until the current k-th distance is below the distance from the query to
 //    the unsearched region (with a margin that covers the float32 rounding
-//    of cell assignment and of the key), so no closer point can be missed.
-#include <vector>
-
+//    of cell assignment and of the key), so no closer point can be missed;
+//    a query still open after shell 1 is handed over with its list and
+//    resumed where it stopped (a wave per query; in a batch, a lane per
+//    query for shell 2, then a wave per query).
 #include <utility>
+#include <vector>
 
 #include "common.h"
 #include "launch.h"
@@ -49,7 +52,7 @@ __device__ inline void grid_dims(GridInfo& G, double h, int max_cells) {
 }
 
 constexpr int GQ_BT = 256;
-constexpr int KNN_RCAP = 1;  // shells a lane searches alone before handing its query to a wave
+constexpr int KNN_RCAP = 1;  // last shell the one-lane pass searches before handing a query over
 constexpr int SCAN_B = 1024;
 
 // Bodies of the grid kernels, shared by the one-cloud kernels and their
