@@ -92,9 +92,11 @@ class Cloud:
         return int(self.soa.shape[1])
 
     def c(self) -> SgrCloud:
-        s = self.soa
-        return SgrCloud(s[0].data_ptr(), s[1].data_ptr(), s[2].data_ptr(),
-                        self.m.data_ptr() if self.m is not None else None, self.n)
+        # rows of the contiguous (3, n) array by address arithmetic (indexing
+        # the tensor three times per call costs more than the call itself
+        # when a batch passes hundreds of clouds)
+        base, n = self.soa.data_ptr(), self.n
+        return SgrCloud(base, base + 4 * n, base + 8 * n, self.m.data_ptr() if self.m is not None else None, n)
 
 
 def pose_inverse(pose: torch.Tensor) -> torch.Tensor:
