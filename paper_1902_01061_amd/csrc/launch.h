@@ -46,7 +46,7 @@ struct ForceArgs {
   const float2* tmx = nullptr;
 };
 
-// A cloud for the batched descriptor kernels.
+// A cloud for the batched moments kernel.
 struct CloudDesc {
   const float* x;
   const float* y;
@@ -190,8 +190,6 @@ hipError_t launch_change(const float* yx, const float* yy, const float* yz, cons
                          const float* xy, const float* xz, const float* aX, int N, const double* pose, float tau2,
                          double shape_thr, uint8_t* flags, int32_t* nn, float* key, void* ws, hipStream_t st);
 
-hipError_t launch_knn_desc(const float* x, const float* y, const float* z, int n, int k, float* a_out,
-                           int32_t* idx_out, hipStream_t st);
 hipError_t launch_moments(const float* x, const float* y, const float* z, int64_t n, double* out, hipStream_t st);
 // Force with vector descriptors (p = 1, g = s) on the matrix cores.
 struct VForceArgs {
@@ -301,7 +299,6 @@ hipError_t launch_force(const ForceArgs& A, int R, int pm, bool want_u, bool wan
 // Resident blocks per CU of the force kernel without energy or per-point
 // output (R points per lane, p mode, scalar-load variant).
 int force_blocks_per_cu(int R, int pm, bool sm);
-hipError_t launch_knn_desc_batch(const CloudDesc* clouds, const int2* blocks, int n_blocks, int k, hipStream_t st);
 hipError_t launch_moments_batch(const CloudDesc* clouds, int n_clouds, double* out, hipStream_t st);
 hipError_t launch_prepare_batch(const PrepDesc* d, int B, const PrepParams& P, Derived* outs, hipStream_t st);
 hipError_t launch_pack_batch(const PrepDesc* d, const int* blk2reg, int n_blocks, const Derived* dvs, float4* ref4,
