@@ -153,9 +153,13 @@ hipError_t launch_update(const double* wpart, int nblk, const double* pose_in, d
 // scale c s = sqrt(lambda_X / lambda_Y0) does not depend on the pose, and
 // the Newton-Schulz step Ro = Rn (3I - Rn^T Rn) / 2 is differentiated as
 // written.  Assumes the forward update was applied (status 0).
-__global__ void update_bwd_kernel(const double* __restrict__ pose_in, const double* __restrict__ W,
-                                  const double* __restrict__ gpose_out, const Derived* __restrict__ dv,
-                                  double* __restrict__ gpose_in, double* __restrict__ gW) {
+// One wave (its launch): the bound lets the single thread keep its FP64
+// state in registers (the default bound of 1 024 threads spilled it).
+__global__ __launch_bounds__(64) void update_bwd_kernel(const double* __restrict__ pose_in,
+                                                        const double* __restrict__ W,
+                                                        const double* __restrict__ gpose_out,
+                                                        const Derived* __restrict__ dv, double* __restrict__ gpose_in,
+                                                        double* __restrict__ gW) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const Derived& D = *dv;
   const double s = pose_in[0];
