@@ -1,6 +1,5 @@
 // The rigid update of Sec. III-B (FP64, one thread) and the fixed-order sum
-// of the wrench partials that feeds it; included by the update kernels and
-// by the force kernel's form that runs the update in its last block.
+// of the wrench partials that feeds it; included by the update kernels.
 #pragma once
 #include "common.h"
 
@@ -60,17 +59,15 @@ __device__ inline void sum_partials(const double* __restrict__ wpart, int n, dou
   }
 }
 
-// The update itself (one thread).  Every field of the constant block it
-// reads is loaded into registers first, and the three it changes (status,
-// warm-start vectors, previous translation) are stored at the end: reading
-// them in place would order each later load behind those stores.  pose_in
-// and pose_out may be the same array (the pose is updated in place), so
-// neither is declared __restrict__; the pose is read into registers before
-// anything is stored.
 // Everything the update reads besides the wrench.  The thread that runs
 // the update loads it before the wrench rows are summed (update_load), so
 // that both sets of loads are in flight together, then applies the update
-// (update_apply).
+// (update_apply).  Every field of the constant block it reads is loaded into
+// registers first, and the three it changes (status, warm-start vectors,
+// previous translation) are stored at the end: reading them in place would
+// order each later load behind those stores.  pose_in and pose_out may be
+// the same array (the pose is updated in place), so neither is declared
+// __restrict__; the pose is read into registers before anything is stored.
 struct UpdateIn {
   double G;
   double ybar0[3], SigY0[6], Vw[9], dprev[3];
@@ -100,6 +97,7 @@ __device__ inline void update_load(const Derived* __restrict__ dv, const double*
   u.status = dv->status;
 }
 
+// The update itself (one thread).
 __device__ inline void update_apply(const double W[13], const UpdateIn& u, double* pose_out,
                                     Derived* __restrict__ dv, int do_update, double* __restrict__ wrench_out,
                                     double* __restrict__ stats_row) {
