@@ -1,6 +1,6 @@
-// Exact k nearest neighbours through a uniform grid (same result as the
-// brute-force kernel: float32 squared distance ((dx*dx + dy*dy) + dz*dz),
-// every operation rounded, ties by index), followed by the same FP64
+// Exact k nearest neighbours through a uniform grid (the same lists as a
+// search over all points: float32 squared distance ((dx*dx + dy*dy) + dz*dz),
+// every operation rounded, ties by index), followed by the FP64
 // neighbourhood covariance and curvature (Sec. III-A).
 //
 // 1. grid_setup: bounding box of the finite points and a cell size h with
