@@ -95,8 +95,9 @@ typedef struct {
                     sums over the reference run as a bf16 matrix product on the
                     matrix cores (pair weights FP32, rounded to bf16; coordinates
                     split into bf16 head + tail; FP32 accumulate, FP64 wrench);
-                    the energy U is then reported as 0 except by the FP32 final
-                    iteration of sgr_register; not for batch calls;
+                    the energy U is then reported as 0 except for the last
+                    iteration of sgr_register with stats, which runs the FP32
+                    kernel; not for batch calls;
                     bit 2: vector descriptors (sgr_step_vec, sgr_register_vec)
                     with FP32 matrix products instead of the split-f16 form;
                     bit 3: pose-independent pair sums (sgr_register,

@@ -508,7 +508,7 @@ struct SingleWs {
   char* sws;
   float4* tm4;
   float2* tmx;
-  Tiles T, TM;  // FP32 kernel (and the final energy); kernel of the other iterations
+  Tiles T, TM;  // FP32 kernel; kernel of the mixed-precision iterations
   int nslot;
 };
 
@@ -559,8 +559,10 @@ int setup_single(const sgr_cloud* tmpl, const sgr_cloud* ref, const PrepParams& 
 
 // Iterations [t0, t1) of (force, update) on the pose in place, captured in a
 // graph cached in gc unless FLAG_NO_GRAPH is set or there is one iteration.
-// G follows eq. 12 over prm->E; the last of the E iterations uses the FP32
-// kernel and accumulates the energy.
+// G follows eq. 12 over prm->E.  The energy U is accumulated only where it is
+// read, in the per-iteration stats; with stats, the last of the E
+// iterations of a mixed-precision registration uses the FP32 kernel so that
+// its energy is the FP32 one.
 int run_single_loop(sgr_ctx* ctx, GraphCache& gc, const sgr_cloud* tmpl, const sgr_cloud* ref,
                     const sgr_params* prm, const SingleWs& w, sgr_pose* inout, double* stats, int t0, int t1,
                     hipStream_t st) {
@@ -569,8 +571,8 @@ int run_single_loop(sgr_ctx* ctx, GraphCache& gc, const sgr_cloud* tmpl, const s
   auto loop = [&](hipStream_t s) -> int {
     for (int t = t0; t < t1; ++t) {
       const bool last = t == prm->E - 1;
-      const bool mixed = is_mixed(prm) && !last;   // the final energy comes from the FP32 kernel
-      const bool wu = !mixed && (stats != nullptr || last);
+      const bool mixed = is_mixed(prm) && !(last && stats != nullptr);
+      const bool wu = !mixed && stats != nullptr;
       const Tiles& Tt = mixed ? w.TM : w.T;
       ForceArgs A{tmpl->x, tmpl->y, tmpl->z, w.aY, tmpl->m, w.ref4, w.lw, (const double*)inout, w.dv, M, N,
                   Tt.chunk_len, Tt.n_chunks, t, 0.0, w.wpart, nullptr, w.perm, w.tm4, w.tmx};
@@ -1225,7 +1227,7 @@ int sgr_register_vec(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, cons
   }
   auto loop = [&](hipStream_t s) -> int {
     for (int t = 0; t < prm->E; ++t) {
-      const bool wu = stats != nullptr || t == prm->E - 1;
+      const bool wu = stats != nullptr;  // U is read only from the stats
       int used = w.slots;
       if (pinv) {
         HIPCHK(launch_pinv(w.tm4, w.tmx, w.ps_S, M, (const double*)inout, w.dv, t, wu, w.wpart, s));
