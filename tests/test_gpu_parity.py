@@ -335,6 +335,24 @@ def test_residual_matches_oracle(sg, ctx):
     assert r_nn == pytest.approx(O.residual_nn(pose, pr.tmpl, pr.ref), rel=1e-6)
 
 
+def test_residual_nearest_at_scale_and_outside_the_reference(sg, ctx):
+    """The nearest-neighbour residual on the scan pair, 20 % of its template
+    points outliers: at the generating pose, at the identity, and with the
+    template moved entirely outside the reference's box, against the
+    oracle's FP64 k-d tree."""
+    pr = config2()
+    tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
+    Rt = pr.gt_R.T
+    back = O.Pose(1 / pr.gt_s, Rt, -(Rt @ pr.gt_t) / pr.gt_s)
+    cases = {"generating": back, "identity": O.Pose(1.0, np.eye(3), np.zeros(3)),
+             "outside": O.Pose(back.s, back.R, back.t + np.array([5.0, -3.0, 2.0]))}
+    for name, pose in cases.items():
+        got = ctx.residual(tm, rf, sg.pose_from_srt(pose.s, pose.R, pose.t)).item()
+        want = O.residual_nn(pose, pr.tmpl, pr.ref)
+        print(f"{name}: nearest-neighbour RMSE {got:.9e} (oracle {want:.9e})")
+        assert got == pytest.approx(want, rel=1e-6), name
+
+
 # ------------------------------------------------------------ error paths
 def test_error_codes(sg, ctx):
     pr = random_pair(10, 20, seed=1)
