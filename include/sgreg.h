@@ -354,8 +354,9 @@ int sgr_plan_force(sgr_plan* plan, int t, double G, const sgr_pose* pose, double
 int sgr_set_tiles(sgr_ctx* ctx, int64_t M, int64_t N, double p, int R, int blocks_per_cu, int variant);
 
 /* Autotuner: times the pair-force kernel for every launch shape (R in
- * {1, 2, 4, 8}, LDS or scalar-load variant, one or two waves of resident
- * blocks) on this pair, `reps` launches each, and stores the fastest in the
+ * {1, 2, 4, 8}, LDS or scalar-load variant, 1 to 4 blocks per CU and 1 to 8
+ * waves of resident blocks, at most 64 blocks per CU) on this pair, `reps`
+ * launches each, and stores the fastest in the
  * tile table for the (M, N, p) bucket.  best (host int[3], nullable): R,
  * blocks_per_cu, variant; best_ms (host, nullable): its time per launch.
  * Synchronises the stream. */

@@ -1309,15 +1309,19 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   const auto key = std::make_tuple(log2_bucket(M), log2_bucket(N), pm);
   // Candidates: template points per lane, the reference load variant, and
   // the blocks per CU of the launch: 1 to 4 (long reference chunks, a few
-  // resident blocks), one or two waves of resident blocks (from the
-  // kernel's occupancy).
+  // resident blocks), and 1 to 8 waves of resident blocks (from the kernel's
+  // occupancy, at most 64 blocks per CU).  Several waves of shorter chunks
+  // even out the end of a large launch: the SIMDs serve the oldest wave
+  // first, so the blocks of a CU do not finish together, and a block's fixed
+  // start and end cost little beside a long pair loop.
   const int cand_R[4] = {1, 2, 4, 8};
+  constexpr int kMaxWaves = 8;
   // size the workspace for the largest candidate
   size_t need = 0;
   for (int R : cand_R)
     for (int v : {0, 1}) {
       Tiles T = TileTable::make(M, N, R, 8 * ctx->n_cu, v);
-      T.bpc = 2 * force_blocks_per_cu(R, pm, v != 0);
+      T.bpc = std::min(64, kMaxWaves * force_blocks_per_cu(R, pm, v != 0));
       Carve cv{nullptr};
       cv.take<double>(16);
       cv.take<Derived>(1);
@@ -1353,10 +1357,11 @@ int sgr_autotune(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, const sg
   int bR = 4, bB = 8, bV = 0;
   for (int v : {0, 1})
     for (int R : cand_R)
-      for (int c = 0; c < 6; ++c) {
+      for (int c = 0; c < 4 + kMaxWaves; ++c) {
         const int occ = force_blocks_per_cu(R, pm, v != 0);
         const int bpc = c < 4 ? c + 1 : (c - 3) * occ;
         if (c < 4 && bpc >= occ) continue;  // covered by the occupancy targets
+        if (bpc > 64) continue;
         Tiles T = TileTable::make(M, N, R, 8 * ctx->n_cu, v);
         T.bpc = bpc;
         const FLaunch L = force_shape(ctx, M, N, T, pm);

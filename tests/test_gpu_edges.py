@@ -3,6 +3,8 @@ than one wave and than one block (every tile ragged), a single reference
 tile, degenerate clouds (one point, non-finite coordinates) that must come
 back as errors, and the largest workload (the 250 000 x 307 200 depth-frame
 scene) on sampled rows along a registration's trajectory."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -10,6 +12,9 @@ import torch
 from oracle import ref as O
 from parity_bars import F_TOL, row_error
 from synth import config5, random_pair, rot_axis_angle
+
+TILES = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1902_01061_amd",
+                     "tiles_gfx950.json")
 
 pytestmark = pytest.mark.gpu
 
@@ -113,13 +118,15 @@ def test_empty_clouds_are_rejected(sg, ctx):
     assert np.isfinite(pose.cpu().numpy()).all()
 
 
-@pytest.mark.parametrize("flags,tol", [(0, F_TOL), (2, 2e-3)])
-def test_largest_workload_force_along_trajectory(sg, ctx, flags, tol):
+@pytest.mark.parametrize("p,flags,tol", [(1.0, 0, F_TOL), (1.0, 2, 2e-3), (2.0, 0, F_TOL)])
+def test_largest_workload_force_along_trajectory(sg, ctx, p, flags, tol):
     """The depth-frame scene (250 000 x 307 200, g = a a s): the force at the
     poses the FP32 registration reaches before iterations 0-4, 10, 50 and 99,
-    on 256 sampled rows against the C oracle by the per-point bar, for the
-    FP32 kernel and for the mixed-precision one (whose gate, 2e-3, is derived
-    in test_gpu_mixed.py from the bf16 rounding of the pair weights)."""
+    on 256 sampled rows against the C oracle by the per-point bar, in the
+    launch shapes of the committed tile table (the shapes the bench times):
+    the FP32 kernel at p = 1 and p = 2, and the mixed-precision one (whose
+    gate, 2e-3, is derived in test_gpu_mixed.py from the bf16 rounding of the
+    pair weights)."""
     pr = config5()
     tm, rf = sg.Cloud(pr.tmpl), sg.Cloud(pr.ref)
     E = 100
@@ -127,9 +134,11 @@ def test_largest_workload_force_along_trajectory(sg, ctx, flags, tol):
     traj = st.cpu().numpy()
     a_t, mom_t = ctx.descriptors(tm, 16)
     a_r, mom_r = ctx.descriptors(rf, 16)
-    S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=1.0, g_mode=1, k=16, E=E),
+    S = O.make_setup(pr.ref, pr.tmpl, O.Params(p=p, g_mode=1, k=16, E=E),
                      aX=a_r.cpu().numpy().astype(np.float64), aY=a_t.cpu().numpy().astype(np.float64))
-    plan = sg.Plan(ctx, tm, a_t, rf, a_r, mom_t, mom_r, sg.Params(p=1.0, g_mode=1, k=16, E=E, flags=flags))
+    ctx_t = sg.Context(0)
+    ctx_t.load_tiles(TILES)
+    plan = sg.Plan(ctx_t, tm, a_t, rf, a_r, mom_t, mom_r, sg.Params(p=p, g_mode=1, k=16, E=E, flags=flags))
     rows = np.random.default_rng(5).choice(pr.M, 256, replace=False)
     errs = []
     for t in (0, 1, 2, 3, 4, 10, 50, 99):
@@ -140,7 +149,8 @@ def test_largest_workload_force_along_trajectory(sg, ctx, flags, tol):
         f_o, _, sc = O.forces_c(Yt, S, O.G_schedule(t, E), rows=rows, want_scale=True)
         errs.append(row_error(f, f_o, sc))
     plan.close()
-    print(f"scene force along the trajectory (flags {flags}): " + ", ".join(f"{e:.1e}" for e in errs))
+    ctx_t.close()
+    print(f"scene force along the trajectory (p {p:g}, flags {flags}): " + ", ".join(f"{e:.1e}" for e in errs))
     assert max(errs) <= tol
 
 
