@@ -146,8 +146,17 @@ int check_mixed(const sgr_params* p) {
 }
 
 // Tiles for a call: the mixed kernel has a fixed 256-point template block.
+// Its launch targets 8 blocks per CU, and up to 24 while every block keeps
+// at least 4e6 pairs: more rounds of shorter chunks even out the end of a
+// large launch, but on a small pair each block's fixed start and end would
+// dominate (the scene, 7.7e10 pairs: 8.08 ms at 24 blocks per CU against
+// 8.55 at 8; the scan pair, 1.2e9 pairs: 0.145 ms at 8 against 0.164 at 24).
 Tiles tiles_for(const sgr_ctx* ctx, int M, int N, const sgr_params* p) {
-  if (is_mixed(p)) return TileTable::make(M, N, 1, 8 * ctx->n_cu);
+  if (is_mixed(p)) {
+    const int64_t lo = int64_t(8) * ctx->n_cu, hi = int64_t(24) * ctx->n_cu;
+    const int64_t tb = std::min(hi, std::max(lo, (int64_t)M * N / 4000000));
+    return TileTable::make(M, N, 1, (int)tb);
+  }
   return ctx->tiles.pick(M, N, pmode_of(p->p));
 }
 
