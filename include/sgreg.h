@@ -440,9 +440,9 @@ int sgr_change_detect(sgr_ctx* ctx, const sgr_cloud* tmpl, const float* a_t, con
 
 /* B independent registrations of uneven sizes with shared parameters
  * (tmpls, refs: HOST arrays of B cloud views).  Descriptors of all 2B
- * clouds run in one launch; each iteration is one persistent launch over a
- * work list of (registration, template block, reference chunk) items plus
- * one update launch, captured in a HIP graph.  poses: device [B] (initial
+ * clouds run in one launch; each iteration is one launch over a work list
+ * of (registration, template block, reference chunk) items, one block per
+ * item in decreasing cost, plus one update launch, captured in a HIP graph.  poses: device [B] (initial
  * poses in, final out).  energy_out (device [B], nullable): final energy U
  * of each.  stats (device [B][E][32], nullable) as in sgr_register.
  * Synchronises the stream; SGR_ENUMERIC / SGR_EDEGENERATE if any
