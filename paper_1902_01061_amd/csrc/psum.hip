@@ -11,10 +11,10 @@
 //
 // psum_kernel forms S0, S1, S2 once per registration (scalar descriptors;
 // the vector-descriptor kernel writes the same sums itself), one pass over all
-// pairs: a block of 256 template points (visiting order) against one chunk of
-// the reference, staged through LDS 256 points at a time; every lane sums a
-// tile's 256 terms in FP32 and adds them to FP64 sums, as the force kernel
-// does.  psum_reduce_kernel adds the chunks in a fixed order.  pinv_kernel
+// pairs: a block of 1 024 template points (visiting order, four per lane)
+// against one chunk of the reference, staged through LDS 256 points at a
+// time; every lane sums a tile's 256 terms per point in FP32 and adds them
+// to FP64 sums, as the force kernel does.  psum_reduce_kernel adds the chunks in a fixed order.  pinv_kernel
 // is then the whole per-iteration force: O(M) work that poses the template
 // exactly as the force kernel does (FP64 pose, FP32 posed point), forms the
 // forces in FP64 and writes the same per-block wrench partials for the
@@ -71,22 +71,76 @@ __device__ inline void pair_sums(float bi, const float4* __restrict__ ref4, cons
   }
 }
 
+// One block: PS_R * 256 template points (visiting order), PS_R per lane,
+// against one chunk of the reference; every staged point is read from LDS
+// once for the lane's PS_R points.
+constexpr int PS_R = 4;
+
 __global__ __launch_bounds__(PS_BT) void psum_kernel(const float4* __restrict__ tm4, int M,
                                                      const float4* __restrict__ ref4, const float* __restrict__ lw,
                                                      int N, int chunk_len, double* __restrict__ part) {
   __shared__ float4 s_x[PS_BT];
   __shared__ float s_l[PS_BT], s_q[PS_BT];
-  const int n_iblk = (M + PS_BT - 1) / PS_BT;
+  const int n_iblk = (M + PS_BT * PS_R - 1) / (PS_BT * PS_R);
   const int iblk = blockIdx.x % n_iblk, chunk = blockIdx.x / n_iblk;
-  const int ip = iblk * PS_BT + threadIdx.x;
-  const float bi = ip < M ? tm4[ip].w : 0.f;
-  const int j0 = chunk * chunk_len, j1 = min(N, j0 + chunk_len);
-  double t[PS_NQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  pair_sums(bi, ref4, lw, j0, j1, s_x, s_l, s_q, t);
-  if (ip < M) {
-    double* o = part + ((int64_t)chunk * M + ip) * PS_NQ;
+  const int ip0 = iblk * PS_BT * PS_R + threadIdx.x;
+  float bi[PS_R];
 #pragma unroll
-    for (int q = 0; q < PS_NQ; ++q) o[q] = t[q];
+  for (int r = 0; r < PS_R; ++r) bi[r] = ip0 + r * PS_BT < M ? tm4[ip0 + r * PS_BT].w : 0.f;
+  const int j0 = chunk * chunk_len, j1 = min(N, j0 + chunk_len);
+  double t[PS_R][PS_NQ];
+#pragma unroll
+  for (int r = 0; r < PS_R; ++r)
+#pragma unroll
+    for (int q = 0; q < PS_NQ; ++q) t[r][q] = 0.0;
+  for (int base = j0; base < j1; base += PS_BT) {
+    __syncthreads();
+    {
+      const int j = base + threadIdx.x;
+      float4 X = make_float4(0.f, 0.f, 0.f, 0.f);
+      float l = -INFINITY;  // exp2(-inf) = 0: beyond the range
+      if (j < j1) {
+        X = ref4[j];
+        l = lw[j];
+      }
+      s_x[threadIdx.x] = X;
+      s_l[threadIdx.x] = l;
+      s_q[threadIdx.x] = __builtin_fmaf(X.x, X.x, __builtin_fmaf(X.y, X.y, X.z * X.z));
+    }
+    __syncthreads();
+    const int n = min(PS_BT, j1 - base);
+    float a[PS_R][PS_NQ];
+#pragma unroll
+    for (int r = 0; r < PS_R; ++r)
+#pragma unroll
+      for (int q = 0; q < PS_NQ; ++q) a[r][q] = 0.f;
+    for (int jj = 0; jj < n; ++jj) {
+      const float4 X = s_x[jj];
+      const float l = s_l[jj], xq = s_q[jj];
+#pragma unroll
+      for (int r = 0; r < PS_R; ++r) {
+        const float d = bi[r] - X.w;
+        const float c = __builtin_amdgcn_exp2f(__builtin_fmaf(-d, d, l));
+        a[r][0] += c;
+        a[r][1] = __builtin_fmaf(c, X.x, a[r][1]);
+        a[r][2] = __builtin_fmaf(c, X.y, a[r][2]);
+        a[r][3] = __builtin_fmaf(c, X.z, a[r][3]);
+        a[r][4] = __builtin_fmaf(c, xq, a[r][4]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PS_R; ++r)
+#pragma unroll
+      for (int q = 0; q < PS_NQ; ++q) t[r][q] += (double)a[r][q];
+  }
+#pragma unroll
+  for (int r = 0; r < PS_R; ++r) {
+    const int ip = ip0 + r * PS_BT;
+    if (ip < M) {
+      double* o = part + ((int64_t)chunk * M + ip) * PS_NQ;
+#pragma unroll
+      for (int q = 0; q < PS_NQ; ++q) o[q] = t[r][q];
+    }
   }
 }
 
@@ -228,10 +282,16 @@ __global__ __launch_bounds__(PS_BT) void pinv_batch_kernel(const RegDesc* __rest
 
 }  // namespace
 
+// Reference chunks of psum_kernel: about 4 blocks per CU, and up to 24 while
+// every block keeps at least 4e6 pairs (more rounds of shorter chunks even
+// out the end of a large launch; on a small pair each block's fixed start
+// and end would dominate).
 int pinv_chunks(int M, int N, int n_cu) {
-  const int n_iblk = (M + PS_BT - 1) / PS_BT;
+  const int n_iblk = (M + PS_BT * PS_R - 1) / (PS_BT * PS_R);
   const int n_t = (N + PS_BT - 1) / PS_BT;
-  const int nc = (4 * n_cu + n_iblk - 1) / n_iblk;  // about four blocks per compute unit
+  const int64_t lo = int64_t(4) * n_cu, hi = int64_t(24) * n_cu;
+  const int64_t target = std::min(hi, std::max(lo, (int64_t)M * N / 4000000));
+  const int nc = (int)((target + n_iblk - 1) / n_iblk);
   return std::max(1, std::min(nc, n_t));
 }
 
@@ -243,7 +303,7 @@ hipError_t launch_psum(const float4* tm4, int M, const float4* ref4, const float
   const int n_t = (N + PS_BT - 1) / PS_BT;
   const int chunk_len = (n_t + n_chunks - 1) / n_chunks * PS_BT;  // whole tiles
   const int nc = (N + chunk_len - 1) / chunk_len;                // chunks actually used
-  const int n_iblk = (M + PS_BT - 1) / PS_BT;
+  const int n_iblk = (M + PS_BT * PS_R - 1) / (PS_BT * PS_R);
   hipLaunchKernelGGL(psum_kernel, dim3((unsigned)(n_iblk * nc)), dim3(PS_BT), 0, st, tm4, M, ref4, lw, N, chunk_len,
                      part);
   hipError_t e = hipGetLastError();
