@@ -1,7 +1,8 @@
 """Write the tile table (launch shapes of the all-pairs force kernel) for
 the workloads this library is measured on, with sgr_autotune on one MI355X:
 
-  tiny pair 1 024 x 1 024 (p = 1), scan pair 32 400 x 36 000 (p = 1),
+  tiny pair 1 024 x 1 024 (p = 1), scan pair 32 400 x 36 000 (p = 1 and
+  p = 2, whose entry the other laws of the r-form share),
   differentiation pair 8 192 x 8 192 (p = 2, eps = 0.05 L), the median
   registration of the 256-registration batch (p = 1), the multi-start pair
   22 000 x 20 000 (p = 1), and the depth-frame scene 250 000 x 307 200
@@ -36,6 +37,7 @@ def main() -> int:
     ms_pair, _ = config4_multistart()
     jobs = [("tiny 1024 x 1024, p = 1", config1(), dict(p=1.0), 16),
             ("scan 32400 x 36000, p = 1", config2(), dict(p=1.0), 24),
+            ("scan 32400 x 36000, p = 2", config2(), dict(p=2.0), 24),
             ("differentiation 8192 x 8192, p = 2", config3(), dict(p=2.0, eps_rel=0.05), 16),
             (f"batch median {med.M} x {med.N}, p = 1", med, dict(p=1.0), 16),
             (f"multi-start {ms_pair.M} x {ms_pair.N}, p = 1", ms_pair, dict(p=1.0), 16)]
